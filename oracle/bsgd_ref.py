@@ -1,0 +1,396 @@
+"""FP64 CPU oracle of BSGD-TV (Gao & Blumensath, arXiv 1812.01307).
+
+TEST INFRASTRUCTURE ONLY.  This module is the plain, slow reference that the
+device path is checked against.  Only the test suite, the package's smoke
+check and the benchmark's CPU-baseline leg may import it; the library never
+does.  It shares no code with the device path: it takes problem arrays
+(CSR of A, y, ...) from the seeded generator and computes everything
+itself with numpy / scipy.sparse in float64.
+
+What it computes, and where the paper defines it:
+
+* Objective (Eq. 1 with the Alg. 1 line-9 reading below):
+  F(x) = ||y - A x||^2 + lam * TV(x).
+* 2-D isotropic TV (Eq. 2) with backward differences; the garbled second
+  term of Eq. 2 is read as x[s,t] - x[s,t-1]; a difference that would reach
+  outside the image (s = 0 or t = 0) is zero.
+* One epoch of Algorithm 1 with every block pair active:
+      g  = sum_i 2 (A_{I_i}^{J_j})^T r_{I_i}      (lines 3 and 7)
+      r' = y - sum_j A_{I_i}^{J_j} x_{J_j}         (lines 4 and 6)
+      x^ = x + mu g                                (line 8)
+      x  = argmin_t ||t - x^||^2 + 2 mu lam TV(t)  (line 9)
+      r  = r'
+  The residual used in line 3 is one epoch old, which is Eq. 3:
+  x^{k+1} = prox(x^k + 2 mu A^T (y - A x^{k-1})).  Initialisation (the
+  paper ignores it): x = x0 (default 0) and r = y - A x0.
+* Line 9 is solved by the fast gradient projection (FGP) method that the
+  paper cites for it (Beck & Teboulle, IEEE TIP 18(11), 2009): projected
+  gradient steps with FISTA momentum on the dual of
+      min_t 1/2 ||t - b||^2 + theta TV(t),   theta = mu * lam,
+  which has the same minimiser as line 9.  The dual step is 1/(8 theta)
+  because ||D||^2 <= 8 for the 2-D difference operator (12 in 3-D).
+  No constraint set is applied (no clamp), and every call starts the dual
+  at zero.
+* u_max = largest eigenvalue of A^T A (Theorem 1) by power iteration from
+  the all-ones vector; the step used throughout is mu = 0.9 / (2 u_max).
+* The M x N block partition of Section 2.1 and a blocked epoch that sums
+  the block products in ascending block order (used to show that blocking
+  changes rounding only).
+
+Where the paper is silent or ambiguous the readings above are used; the
+design notes list them.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+# ---------------------------------------------------------------------------
+# Sparse products (Alg. 1 lines 3-4, summed over blocks)
+# ---------------------------------------------------------------------------
+
+
+def as_matrix(row_ptr, col, val, ncols: int) -> sp.csr_matrix:
+    """Wrap a CSR triple as a scipy matrix (FP64 values)."""
+    nrows = len(row_ptr) - 1
+    return sp.csr_matrix((np.asarray(val, np.float64), np.asarray(col), np.asarray(row_ptr)),
+                         shape=(nrows, ncols))
+
+
+def forward(A: sp.csr_matrix, x: np.ndarray) -> np.ndarray:
+    """A x: all block forward projections z^j_{I_i} summed over j (Alg. 1 line 4)."""
+    return A @ np.asarray(x, np.float64)
+
+
+def backproject(A: sp.csr_matrix, r: np.ndarray) -> np.ndarray:
+    """2 A^T r: all block backprojections g^i_{J_j} summed over i (Alg. 1 line 3)."""
+    return 2.0 * (A.T @ np.asarray(r, np.float64))
+
+
+# ---------------------------------------------------------------------------
+# Total variation (Eq. 2) and its difference operator
+# ---------------------------------------------------------------------------
+
+
+def grad2(x: np.ndarray):
+    """Backward differences D x of an H x W image: (vertical, horizontal)."""
+    x = np.asarray(x, np.float64)
+    dv = np.zeros_like(x)
+    dh = np.zeros_like(x)
+    dv[1:, :] = x[1:, :] - x[:-1, :]
+    dh[:, 1:] = x[:, 1:] - x[:, :-1]
+    return dv, dh
+
+
+def grad2_adj(pv: np.ndarray, ph: np.ndarray) -> np.ndarray:
+    """Adjoint D^T p of grad2 (only rows s >= 1 of pv and columns t >= 1 of ph enter)."""
+    out = np.zeros_like(pv)
+    out[1:, :] += pv[1:, :]
+    out[:-1, :] -= pv[1:, :]
+    out[:, 1:] += ph[:, 1:]
+    out[:, :-1] -= ph[:, 1:]
+    return out
+
+
+def tv2(x: np.ndarray) -> float:
+    """Isotropic TV of Eq. 2: sum over pixels of the length of (D x)[s, t]."""
+    dv, dh = grad2(x)
+    return float(np.sum(np.sqrt(dv * dv + dh * dh)))
+
+
+def grad3(x: np.ndarray):
+    """Backward differences of a D x H x W volume along (depth, rows, columns)."""
+    x = np.asarray(x, np.float64)
+    dd = np.zeros_like(x)
+    dv = np.zeros_like(x)
+    dh = np.zeros_like(x)
+    dd[1:] = x[1:] - x[:-1]
+    dv[:, 1:, :] = x[:, 1:, :] - x[:, :-1, :]
+    dh[:, :, 1:] = x[:, :, 1:] - x[:, :, :-1]
+    return dd, dv, dh
+
+
+def grad3_adj(pd, pv, ph) -> np.ndarray:
+    """Adjoint of grad3."""
+    out = np.zeros_like(pd)
+    out[1:] += pd[1:]
+    out[:-1] -= pd[1:]
+    out[:, 1:, :] += pv[:, 1:, :]
+    out[:, :-1, :] -= pv[:, 1:, :]
+    out[:, :, 1:] += ph[:, :, 1:]
+    out[:, :, :-1] -= ph[:, :, 1:]
+    return out
+
+
+def tv3(x: np.ndarray) -> float:
+    """Isotropic 3-D TV: Eq. 2 extended with a backward difference across slices."""
+    dd, dv, dh = grad3(x)
+    return float(np.sum(np.sqrt(dd * dd + dv * dv + dh * dh)))
+
+
+# ---------------------------------------------------------------------------
+# TV proximal step (Alg. 1 line 9) by FGP on the dual
+# ---------------------------------------------------------------------------
+
+
+def fista_tau(iters: int) -> np.ndarray:
+    """Momentum sequence tau_1 = 1, tau_{k+1} = (1 + sqrt(1 + 4 tau_k^2)) / 2."""
+    tau = np.empty(iters + 1)
+    tau[0] = 1.0
+    for k in range(iters):
+        tau[k + 1] = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * tau[k] * tau[k]))
+    return tau
+
+
+def fgp_prox2(b: np.ndarray, theta: float, iters: int, return_dual: bool = False):
+    """argmin_t 1/2||t - b||^2 + theta TV(t) by `iters` FGP iterations.
+
+    Dual variable p = (pv, ph), one 2-vector per pixel, constrained to the
+    unit disk.  Iteration k (q_1 = 0, p_0 = 0, tau_1 = 1):
+        u_k     = b - theta D^T q_k
+        p_k     = P(q_k + D u_k / (8 theta))      P: pointwise unit-disk projection
+        q_{k+1} = p_k + (tau_k - 1)/tau_{k+1} (p_k - p_{k-1})
+    and the result is b - theta D^T p_K.
+    """
+    b = np.asarray(b, np.float64)
+    if theta == 0.0 or iters == 0:
+        out = b.copy()
+        zero = np.zeros_like(b)
+        return (out, (zero, zero.copy())) if return_dual else out
+    tau = fista_tau(iters)
+    pv_old = np.zeros_like(b)
+    ph_old = np.zeros_like(b)
+    qv = np.zeros_like(b)
+    qh = np.zeros_like(b)
+    step = 1.0 / (8.0 * theta)
+    for k in range(iters):
+        u = b - theta * grad2_adj(qv, qh)
+        gv, gh = grad2(u)
+        pv = qv + step * gv
+        ph = qh + step * gh
+        nrm = np.maximum(1.0, np.sqrt(pv * pv + ph * ph))
+        pv /= nrm
+        ph /= nrm
+        coef = (tau[k] - 1.0) / tau[k + 1]
+        qv = pv + coef * (pv - pv_old)
+        qh = ph + coef * (ph - ph_old)
+        pv_old, ph_old = pv, ph
+    out = b - theta * grad2_adj(pv_old, ph_old)
+    return (out, (pv_old, ph_old)) if return_dual else out
+
+
+def fgp_prox3(b: np.ndarray, theta: float, iters: int, return_dual: bool = False):
+    """3-D version of fgp_prox2 (unit-ball projection in R^3, dual step 1/(12 theta))."""
+    b = np.asarray(b, np.float64)
+    if theta == 0.0 or iters == 0:
+        out = b.copy()
+        return (out, None) if return_dual else out
+    tau = fista_tau(iters)
+    old = [np.zeros_like(b) for _ in range(3)]
+    q = [np.zeros_like(b) for _ in range(3)]
+    step = 1.0 / (12.0 * theta)
+    for k in range(iters):
+        u = b - theta * grad3_adj(*q)
+        g = grad3(u)
+        p = [q[a] + step * g[a] for a in range(3)]
+        nrm = np.maximum(1.0, np.sqrt(p[0] ** 2 + p[1] ** 2 + p[2] ** 2))
+        p = [pa / nrm for pa in p]
+        coef = (tau[k] - 1.0) / tau[k + 1]
+        q = [p[a] + coef * (p[a] - old[a]) for a in range(3)]
+        old = p
+    out = b - theta * grad3_adj(*old)
+    return (out, old) if return_dual else out
+
+
+# ---------------------------------------------------------------------------
+# Step size (Theorem 1)
+# ---------------------------------------------------------------------------
+
+
+def power_umax(A: sp.csr_matrix, tol: float = 1e-12, max_iter: int = 100000) -> float:
+    """Largest eigenvalue of A^T A by power iteration from the all-ones vector.
+
+    Stops when the Rayleigh quotient changes by less than `tol` (relative).
+    """
+    v = np.ones(A.shape[1]) / np.sqrt(A.shape[1])
+    u = 0.0
+    for _ in range(max_iter):
+        w = A.T @ (A @ v)
+        u_new = float(v @ w)
+        nrm = float(np.linalg.norm(w))
+        if nrm == 0.0:
+            return 0.0
+        v = w / nrm
+        if abs(u_new - u) <= tol * abs(u_new):
+            return u_new
+        u = u_new
+    return u
+
+
+def step_size(u_max: float, factor: float = 0.9) -> float:
+    """mu = factor / (2 u_max); Theorem 1 needs factor < 1 at lam = 0."""
+    return factor / (2.0 * u_max)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1, unblocked form
+# ---------------------------------------------------------------------------
+
+
+def prox(xhat: np.ndarray, theta: float, prox_iters: int, shape) -> np.ndarray:
+    """Alg. 1 line 9 on the image of `shape` (2-D or 3-D)."""
+    if theta == 0.0:
+        return xhat.copy()
+    img = xhat.reshape(shape)
+    if len(shape) == 2:
+        return fgp_prox2(img, theta, prox_iters).ravel()
+    return fgp_prox3(img, theta, prox_iters).ravel()
+
+
+def bsgd_epoch(A, y, x, r, mu: float, lam: float, prox_iters: int, shape):
+    """One epoch of Algorithm 1 (all block pairs); returns (x_new, r_new)."""
+    g = backproject(A, r)                 # lines 3 + 7, stale residual
+    r_new = y - forward(A, x)             # lines 4 + 6, current x
+    xhat = x + mu * g                     # line 8
+    x_new = prox(xhat, mu * lam, prox_iters, shape)   # line 9
+    return x_new, r_new
+
+
+def initial_state(A, y, x0=None):
+    """x = x0 (zero by default), r = y - A x0."""
+    if x0 is None:
+        return np.zeros(A.shape[1]), np.asarray(y, np.float64).copy()
+    x0 = np.asarray(x0, np.float64).copy()
+    return x0, np.asarray(y, np.float64) - forward(A, x0)
+
+
+def bsgd_tv(A, y, mu: float, lam: float, epochs: int, prox_iters: int, shape,
+            x0=None, state=None, record: bool = False):
+    """Run `epochs` epochs of Algorithm 1.
+
+    Returns (x, r) after the last epoch and, with record=True, the list of
+    iterates x after each epoch.  `state` = (x, r) resumes a run.
+    """
+    x, r = state if state is not None else initial_state(A, y, x0)
+    x = np.array(x, np.float64)
+    r = np.array(r, np.float64)
+    hist = []
+    for _ in range(epochs):
+        x, r = bsgd_epoch(A, y, x, r, mu, lam, prox_iters, shape)
+        if record:
+            hist.append(x.copy())
+    return (x, r, hist) if record else (x, r)
+
+
+def objective(A, y, x, lam: float, shape) -> float:
+    """F(x) = ||y - A x||^2 + lam TV(x) (the problem that Alg. 1 line 9 targets)."""
+    res = y - forward(A, x)
+    tv = tv2(x.reshape(shape)) if len(shape) == 2 else tv3(x.reshape(shape))
+    return float(res @ res) + lam * tv
+
+
+def thm2_margin(A, y, x_prev, x_cur, x_next, mu: float) -> float:
+    """Right side minus left side of Theorem 2's condition (Eq. 8) at one epoch.
+
+    f(x) = ||y - A x||^2.  A positive value means the condition holds.
+    """
+    f = lambda v: float(np.sum((y - forward(A, v)) ** 2))  # noqa: E731
+    grad_prev = -2.0 * (A.T @ (y - forward(A, x_prev)))
+    d = x_next - x_cur
+    rhs = f(x_cur) + float(d @ grad_prev) + float(d @ d) / (2.0 * mu)
+    return rhs - f(x_next)
+
+
+# ---------------------------------------------------------------------------
+# Block partition (Section 2.1) and the blocked epoch
+# ---------------------------------------------------------------------------
+
+
+def tile(row_ptr, col, val, row_off, col_off, i: int, j: int):
+    """Block A_{I_i}^{J_j} of Section 2.1's partition as a block-local CSR.
+
+    Returns (ptr, lcol, lval): row pointers (int64, |I_i|+1 entries),
+    column indices relative to the block's first column (int32, ascending
+    within each row) and the values, in the order they appear in A.
+    """
+    r0, r1 = int(row_off[i]), int(row_off[i + 1])
+    c0, c1 = int(col_off[j]), int(col_off[j + 1])
+    a0, a1 = int(row_ptr[r0]), int(row_ptr[r1])
+    cs = np.asarray(col[a0:a1])
+    rows = np.repeat(np.arange(r1 - r0), np.diff(np.asarray(row_ptr[r0:r1 + 1])))
+    sel = (cs >= c0) & (cs < c1)
+    ptr = np.zeros(r1 - r0 + 1, np.int64)
+    np.cumsum(np.bincount(rows[sel], minlength=r1 - r0), out=ptr[1:])
+    return ptr, (cs[sel] - c0).astype(np.int32), np.asarray(val[a0:a1])[sel]
+
+
+def tile_transpose(ptr, lcol, lval, ncols_block: int):
+    """Transpose of a block-local CSR (rows = the block's pixels, columns = its rays)."""
+    nrows_block = len(ptr) - 1
+    T = sp.csr_matrix((lval, lcol, ptr), shape=(nrows_block, ncols_block)).T.tocsr()
+    T.sort_indices()
+    return T.indptr.astype(np.int64), T.indices.astype(np.int32), T.data.astype(lval.dtype)
+
+
+def tiles(row_ptr, col, val, row_off, col_off):
+    """All M x N blocks: dict (i, j) -> block CSR and ('T', i, j) -> its transpose."""
+    M, N = len(row_off) - 1, len(col_off) - 1
+    out = {}
+    for i in range(M):
+        for j in range(N):
+            blk = tile(row_ptr, col, val, row_off, col_off, i, j)
+            out[(i, j)] = blk
+            out[("T", i, j)] = tile_transpose(*blk, int(col_off[j + 1] - col_off[j]))
+    return out
+
+
+def bsgd_epoch_blocked(blocks, row_off, col_off, y, x, r, mu: float, lam: float,
+                       prox_iters: int, shape):
+    """Algorithm 1 epoch written block by block (lines 2-9).
+
+    z^j_{I_i} = A_{I_i}^{J_j} x_{J_j};  g^i_{J_j} = 2 (A_{I_i}^{J_j})^T r_{I_i};
+    r_{I_i} = y_{I_i} - sum_j z^j (ascending j);  g_{J_j} = sum_i g^i (ascending i).
+    """
+    M, N = len(row_off) - 1, len(col_off) - 1
+    g = np.zeros_like(x)
+    r_new = np.empty_like(r)
+    z = {}
+    ghat = {}
+    for i in range(M):                      # the pair loop (order is irrelevant)
+        r0, r1 = int(row_off[i]), int(row_off[i + 1])
+        for j in range(N):
+            c0, c1 = int(col_off[j]), int(col_off[j + 1])
+            ptr, lcol, lval = blocks[(i, j)]
+            Aij = sp.csr_matrix((lval, lcol, ptr), shape=(r1 - r0, c1 - c0))
+            ghat[(i, j)] = 2.0 * (Aij.T @ r[r0:r1])
+            z[(i, j)] = Aij @ x[c0:c1]
+    for i in range(M):
+        r0, r1 = int(row_off[i]), int(row_off[i + 1])
+        acc = np.zeros(r1 - r0)
+        for j in range(N):
+            acc = acc + z[(i, j)]
+        r_new[r0:r1] = y[r0:r1] - acc
+    for j in range(N):
+        c0, c1 = int(col_off[j]), int(col_off[j + 1])
+        acc = np.zeros(c1 - c0)
+        for i in range(M):
+            acc = acc + ghat[(i, j)]
+        g[c0:c1] = acc
+    xhat = x + mu * g
+    return prox(xhat, mu * lam, prox_iters, shape), r_new
+
+
+def block_forward(blocks, row_off, col_off, i: int, j: int, x_block):
+    """z^j_{I_i} = A_{I_i}^{J_j} x_{J_j} for one block (Alg. 1 line 4)."""
+    r0, r1 = int(row_off[i]), int(row_off[i + 1])
+    c0, c1 = int(col_off[j]), int(col_off[j + 1])
+    ptr, lcol, lval = blocks[(i, j)]
+    return sp.csr_matrix((lval, lcol, ptr), shape=(r1 - r0, c1 - c0)) @ x_block
+
+
+def block_backproject(blocks, row_off, col_off, i: int, j: int, r_block):
+    """g^i_{J_j} = 2 (A_{I_i}^{J_j})^T r_{I_i} for one block (Alg. 1 line 3)."""
+    r0, r1 = int(row_off[i]), int(row_off[i + 1])
+    c0, c1 = int(col_off[j]), int(col_off[j + 1])
+    ptr, lcol, lval = blocks[(i, j)]
+    return 2.0 * (sp.csr_matrix((lval, lcol, ptr), shape=(r1 - r0, c1 - c0)).T @ r_block)

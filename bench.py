@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the BSGD-TV hot path on one MI355X.
+
+One step = one whole reconstruction job of the 512 x 512 workload
+(720 angles x 729 bins, M = N = 8 blocks, lambda = 0.01, 200 epochs, 20 FGP
+iterations), starting from A, A^T (FP32 CSR) and y already resident in HBM:
+    S0   build the block store            (bsgd_plan_create)
+    S0'  u_max by power iteration, mu = 0.9 / (2 u_max)
+    S1-S5 x 200 epochs                     (bsgd_run_epochs)
+The reported value is epochs per second over whole jobs (setup included).
+
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _alg_bytes(nnz, r, c, val_bytes):
+    """Algorithmic HBM bytes per launch of the two fused row kernels."""
+    fwd = (val_bytes + 4) * nnz + 8 * (r + 1) + 4 * c + 4 * r + 4 * r  # A, ptr, x, y, r'
+    bwd = (val_bytes + 4) * nnz + 8 * (c + 1) + 4 * r + 4 * c + 4 * c  # A^T, ptr, r, x, x^
+    return fwd, bwd
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2_512")
+    ap.add_argument("--vt", choices=["f32", "f16"], default="f32")
+    ap.add_argument("--epochs", type=int, default=None, help="override the workload's epoch count")
+    ap.add_argument("--power-iters", type=int, default=30)
+    ap.add_argument("--cpu-epochs", type=int, default=5, help="oracle epochs timed for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on exactly one GPU "
+              "(see the design notes for how the path would shard)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1812_01307_amd as bsgd
+
+    dev = torch.device("cuda:0")
+    print(f"[bench] generating {args.config}", file=sys.stderr, flush=True)
+    t_gen = time.perf_counter()
+    prob = synth.make_problem(args.config)
+    tp, tc, tv = prob.ensure_transpose()
+    t_gen = time.perf_counter() - t_gen
+    epochs = args.epochs or prob.epochs
+    K = prob.prox_iters
+    vt = bsgd.BSGD_VAL_F16 if args.vt == "f16" else bsgd.BSGD_VAL_F32
+    flags = bsgd.BSGD_PLAN_F16 if vt == bsgd.BSGD_VAL_F16 else 0
+    r, c, nnz = prob.nrows, prob.ncols, prob.nnz
+
+    # inputs resident in HBM before the timed region
+    A = (r, c, bsgd.to_device(prob.row_ptr, torch.int64), bsgd.to_device(prob.col, torch.int32),
+         bsgd.to_device(prob.val, torch.float32))
+    At = (c, r, bsgd.to_device(tp, torch.int64), bsgd.to_device(tc, torch.int32),
+          bsgd.to_device(tv, torch.float32))
+    y = bsgd.to_device(prob.y, torch.float32)
+    torch.cuda.synchronize()
+    print(f"[bench] nnz={nnz} rows={r} cols={c} gen={t_gen:.1f}s", file=sys.stderr, flush=True)
+
+    timing = not args.no_kernel_timing
+    acc = {"fwd": 0.0, "bwd": 0.0, "prox": 0.0, "n": 0}
+
+    def job(record):
+        plan = bsgd.bsgd_plan_create(A, At, prob.M, prob.N, prob.row_off, prob.col_off, prob.H,
+                                     prob.W, 1, flags)
+        u = bsgd.bsgd_power_umax(plan, args.power_iters, vt=vt)
+        mu = 0.9 / (2.0 * u)
+        st = bsgd.bsgd_state_create(plan, 1, vt)
+        if record and timing:
+            bsgd.bsgd_state_enable_timing(st, epochs)
+        bsgd.bsgd_state_init(st, y)
+        bsgd.bsgd_run_epochs(st, mu, prob.lam, epochs, K)
+        x = bsgd.bsgd_get_x(st)
+        if record and timing:
+            f, b, p, n = bsgd.bsgd_state_timing(st)  # waits for this job's events
+            acc["fwd"] += f
+            acc["bwd"] += b
+            acc["prox"] += p
+            acc["n"] += n
+        return st, x, mu, plan
+
+    for w in range(args.warmup):
+        job(False)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        st, x, mu, plan = job(True)
+        print(f"[bench] step {k + 1}/{args.steps}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = epochs * args.steps / (t1 - t0)
+
+    rn2, ep, _ = bsgd.bsgd_get_stats(st)
+    xh = x.cpu().numpy().astype(np.float64)
+    xt = prob.x_true.ravel()
+    rel_err_true = float(np.linalg.norm(xh - xt) / np.linalg.norm(xt))
+
+    # epoch-only rate (no setup), for context
+    st2 = bsgd.bsgd_state_create(plan, 1, vt)
+    bsgd.bsgd_state_init(st2, y)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    bsgd.bsgd_run_epochs(st2, mu, prob.lam, epochs, K)
+    torch.cuda.synchronize()
+    epoch_ms = (time.perf_counter() - te) * 1e3 / epochs
+
+    val_bytes = 2 if vt == bsgd.BSGD_VAL_F16 else 4
+    b_fwd, b_bwd = _alg_bytes(nnz, r, c, val_bytes)
+    roofline = None
+    kernel = {}
+    if timing and acc["n"]:
+        f_ms = acc["fwd"] / acc["n"]
+        b_ms = acc["bwd"] / acc["n"]
+        p_ms = acc["prox"] / acc["n"]
+        kernel = {"fwd_ms": f_ms, "bwd_ms": b_ms, "prox_ms": p_ms,
+                  "fwd_gbs": b_fwd / f_ms / 1e6, "bwd_gbs": b_bwd / b_ms / 1e6}
+        dom_bytes, dom_ms, dom = (b_fwd, f_ms, "fwd") if f_ms >= b_ms else (b_bwd, b_ms, "bwd")
+        achieved = dom_bytes / dom_ms / 1e6
+        roofline = {"bound": "hbm", "kernel": "k_rows (%s)" % ("A x: lines 4+6" if dom == "fwd"
+                                                               else "A^T r: lines 3+7+8"),
+                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "alg_bytes_per_launch": dom_bytes}
+
+    cpu = None
+    if not args.no_cpu_baseline and args.cpu_epochs > 0:
+        import oracle  # CPU baseline leg only
+        A64 = oracle.as_matrix(prob.row_ptr, prob.col, prob.val, c)
+        mu_cpu = 0.9 / (2.0 * oracle.power_umax(A64, tol=1e-6, max_iter=20))
+        print(f"[bench] cpu baseline: {args.cpu_epochs} oracle epochs", file=sys.stderr, flush=True)
+        xc, rc = oracle.initial_state(A64, prob.y)
+        tc0 = time.perf_counter()
+        xc, rc = oracle.bsgd_tv(A64, prob.y, mu_cpu, prob.lam, args.cpu_epochs, K, (prob.H, prob.W),
+                                state=(xc, rc))
+        tcs = time.perf_counter() - tc0
+        cpu = {"value": round(args.cpu_epochs / tcs, 4), "unit": "epochs/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{args.cpu_epochs} epochs of {args.config} (FP64 numpy/scipy, single "
+                         f"thread, setup excluded) in {tcs:.1f} s"}
+
+    out = {
+        "metric": "BSGD-TV epochs/s + HBM GB/s vs peak; served recon p50/p99 latency",
+        "value": round(value, 2),
+        "unit": "epochs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if vt == bsgd.BSGD_VAL_F32 else "f16-values/f32-accumulate",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: one reconstruction job per step ({prob.H}x{prob.W} "
+                               f"image, {prob.n_ang} angles x {prob.bins} bins, M=N={prob.M}, "
+                               f"lambda={prob.lam}, {epochs} epochs, {K} FGP iterations, "
+                               f"setup S0+S0' included)",
+                   "nnz": nnz, "epochs_per_step": epochs, "power_iters": args.power_iters},
+        "epoch_only_ms": round(epoch_ms, 4),
+        "epoch_only_epochs_per_s": round(1e3 / epoch_ms, 2),
+        "alg_bytes_per_epoch": b_fwd + b_bwd,
+        "alg_gbs_epoch_only": round((b_fwd + b_bwd) / epoch_ms / 1e6, 1),
+        "kernels": {k: round(v, 4) for k, v in kernel.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "quality": {"res_norm2": rn2, "rel_err_vs_phantom": round(rel_err_true, 5)},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,281 @@
+/*
+ * bsgd.h — C ABI of the BSGD-TV device library (gfx950 / MI355X).
+ *
+ * BSGD-TV (Gao & Blumensath, "BSGD-TV: A parallel algorithm solving total
+ * variation constrained image reconstruction problems", arXiv 1812.01307)
+ * minimises ||y - A x||^2 + (TV term) for a sparse X-ray projection matrix A
+ * (r rays x c pixels) split into M row blocks I_i and N column blocks J_j
+ * (Section 2.1).  Each epoch of Algorithm 1 computes, for every block pair,
+ *     g^i_{J_j} = 2 (A_{I_i}^{J_j})^T r_{I_i}      (line 3)
+ *     z^j_{I_i} = A_{I_i}^{J_j} x_{J_j}             (line 4)
+ * then r = y - sum_j z^j (line 6), g = sum_i g^i (line 7), x = x + mu g
+ * (line 8) and x = argmin_t ||t - x||^2 + 2 mu lam TV(t) (line 9), the last
+ * solved by fast gradient projection (FGP) on the dual (the method the
+ * paper cites for line 9).
+ *
+ * Conventions for every call:
+ *   - Pointers documented as "device" point to HIP device memory owned by
+ *     the caller; the library never frees them and never keeps them beyond
+ *     the object that borrows them (plan or state).  "host" pointers are
+ *     read during the call only.
+ *   - Calls that take a stream enqueue work on it and return without
+ *     waiting, unless the description says "synchronises".
+ *   - Every call returns a bsgd_status; on failure nothing has been
+ *     enqueued (argument errors) or the HIP error is reported
+ *     (BSGD_ERR_HIP), and bsgd_last_error() gives a message (thread-local).
+ *   - The library allocates no device memory: plans and states live in
+ *     caller-provided workspaces whose sizes the *_workspace_size calls
+ *     return.  It allocates small host structures only.
+ *   - Vectors are FP32.  Images are row-major H x W (pixel index s*W + t,
+ *     row s from the top); a D-slice volume is D consecutive images.
+ */
+#ifndef BSGD_H
+#define BSGD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BSGD_OK = 0,
+  BSGD_ERR_INVALID = -1,     /* bad argument or inconsistent input data     */
+  BSGD_ERR_WORKSPACE = -2,   /* workspace smaller than the size query gave  */
+  BSGD_ERR_HIP = -3,         /* a HIP runtime call failed                   */
+  BSGD_ERR_UNSUPPORTED = -4, /* valid request this build does not implement */
+  BSGD_ERR_DIVERGED = -5     /* residual norm is not finite                 */
+} bsgd_status;
+
+/* Element type of the stored matrix values; accumulation is always FP32. */
+typedef enum { BSGD_VAL_F32 = 0, BSGD_VAL_F16 = 1 } bsgd_valtype;
+
+/* Plan flags. */
+#define BSGD_PLAN_F16 1u /* also keep an FP16 (round-to-nearest-even) copy of the values */
+
+/*
+ * A sparse matrix in CSR form, in device memory.  Columns must be strictly
+ * ascending within each row and lie in [0, ncols); row_ptr[0] = 0 and
+ * row_ptr[nrows] = nnz.  nnz < 2^31.
+ */
+typedef struct {
+  int64_t nrows;
+  int64_t ncols;
+  int64_t nnz;
+  const int64_t* row_ptr; /* device, nrows + 1 */
+  const int32_t* col;     /* device, nnz */
+  const float* val;       /* device, nnz */
+} bsgd_csr;
+
+typedef struct bsgd_plan bsgd_plan;   /* block store of A and A^T (opaque) */
+typedef struct bsgd_state bsgd_state; /* iterate, residual and prox buffers (opaque) */
+
+/* ------------------------------------------------------------------------
+ * Block store (Section 2.1: A divided into M row blocks and N column blocks)
+ * ---------------------------------------------------------------------- */
+
+/*
+ * Upper bound of the plan workspace for a matrix of this size (host only,
+ * no device access).  flags as for bsgd_plan_create.
+ */
+bsgd_status bsgd_plan_workspace_size(int64_t nrows, int64_t ncols, int64_t nnz, int M, int N,
+                                     unsigned flags, size_t* bytes);
+
+/*
+ * Build the block store of A (Section 2.1) in `workspace` (device, at least
+ * bsgd_plan_workspace_size bytes, 256-byte aligned).
+ *
+ *   A       the whole matrix (rays x pixels), device CSR, FP32 values.
+ *   At      its transpose (pixels x rays), device CSR; the caller guarantees
+ *           that it is the transpose of A (same nnz is checked).
+ *   M, N    number of row and column blocks, 1 <= M <= nrows, 1 <= N <= ncols.
+ *   row_off host, M+1 ascending ray offsets, row_off[0] = 0, row_off[M] = r:
+ *           row block I_i = rays [row_off[i], row_off[i+1]).
+ *   col_off host, N+1 ascending pixel offsets, col_off[N] = c: column block
+ *           J_j = pixels [col_off[j], col_off[j+1]).
+ *   H, W, D image shape with H*W*D = c (D = 1 for a 2-D image).
+ *
+ * The store keeps every block A_{I_i}^{J_j} and its transpose addressable
+ * (bsgd_tile_export) in a row-interleaved layout: the entries of ray rho for
+ * column block j follow those for block j-1, and likewise for each pixel's
+ * row of A^T over the row blocks.  The A/At arrays are only read during the
+ * call.  Synchronises `stream` at the end (to validate the input: sorted
+ * columns, indices in range, row_ptr consistent with nnz).
+ * *out is released with bsgd_plan_destroy; the workspace must outlive it.
+ */
+bsgd_status bsgd_plan_create(const bsgd_csr* A, const bsgd_csr* At, int M, int N,
+                             const int64_t* row_off, const int64_t* col_off, int H, int W, int D,
+                             unsigned flags, void* workspace, size_t workspace_bytes,
+                             hipStream_t stream, bsgd_plan** out);
+
+void bsgd_plan_destroy(bsgd_plan* plan);
+
+/*
+ * Number of stored entries of block (i, j) (identical for the block and its
+ * transpose).  Synchronises `stream`.
+ */
+bsgd_status bsgd_tile_nnz(const bsgd_plan* plan, int i, int j, hipStream_t stream, int64_t* nnz);
+
+/*
+ * Write block A_{I_i}^{J_j} (transposed = 0) or its transpose (transposed = 1)
+ * as a block-local CSR: ptr (device, rows+1 int64), col (device, nnz int32,
+ * column indices relative to the block's first column, ascending) and val
+ * (device, nnz FP32).  rows = |I_i| (|J_j| when transposed); nnz from
+ * bsgd_tile_nnz.
+ */
+bsgd_status bsgd_tile_export(const bsgd_plan* plan, int i, int j, int transposed, int64_t* ptr,
+                             int32_t* col, float* val, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Step-level products (Algorithm 1 lines 3, 4, 6, 7, 8)
+ * ---------------------------------------------------------------------- */
+
+/*
+ * Forward projection over all blocks (lines 4 and 6):
+ *   y == NULL:  out = A x             (sum over j of z^j = A_{I_i}^{J_j} x_{J_j})
+ *   y != NULL:  out = y - A x         (the residual of line 6)
+ * x: device, c floats; y, out: device, r floats.  vt selects the value copy.
+ */
+bsgd_status bsgd_forward(const bsgd_plan* plan, bsgd_valtype vt, const float* x, const float* y,
+                         float* out, hipStream_t stream);
+
+/*
+ * Backprojection over all blocks (lines 3, 7 and 8):
+ *   x == NULL:  out = 2 A^T r                    (g = sum_i 2 (A_{I_i}^{J_j})^T r_{I_i})
+ *   x != NULL:  out = x + mu * 2 A^T r           (the gradient step of line 8)
+ * r: device, r floats; x, out: device, c floats.
+ */
+bsgd_status bsgd_backproject(const bsgd_plan* plan, bsgd_valtype vt, const float* r,
+                             const float* x, float mu, float* out, hipStream_t stream);
+
+/*
+ * One block's forward product z^j_{I_i} = A_{I_i}^{J_j} x_{J_j} (line 4).
+ * xj: device, |J_j| floats; z: device, |I_i| floats.
+ */
+bsgd_status bsgd_forward_block(const bsgd_plan* plan, bsgd_valtype vt, int i, int j,
+                               const float* xj, float* z, hipStream_t stream);
+
+/*
+ * One block's backprojection g^i_{J_j} = 2 (A_{I_i}^{J_j})^T r_{I_i} (line 3).
+ * ri: device, |I_i| floats; g: device, |J_j| floats.
+ */
+bsgd_status bsgd_backproject_block(const bsgd_plan* plan, bsgd_valtype vt, int i, int j,
+                                   const float* ri, float* g, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * TV proximal step (line 9) and TV value (Eq. 2)
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes for bsgd_tv_prox / bsgd_tv_value on an H x W x D image. */
+bsgd_status bsgd_tv_workspace_size(int H, int W, int D, size_t* bytes);
+
+/*
+ * out = argmin_t 1/2 ||t - b||^2 + theta TV(t) approximated by `iters` FGP
+ * iterations started from a zero dual (line 9 with theta = mu * lam).  TV is
+ * the isotropic TV of Eq. 2 with backward differences (zero where a
+ * difference would leave the image); D > 1 adds the difference across
+ * slices (3-D TV, dual step 1/(12 theta) instead of 1/(8 theta)).
+ * b, out: device, H*W*D floats (out may not alias b); ws: device workspace.
+ * theta = 0 or iters = 0 copies b.
+ */
+bsgd_status bsgd_tv_prox(int H, int W, int D, const float* b, float theta, int iters, float* out,
+                         void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* TV(x) of Eq. 2 (3-D when D > 1), accumulated in FP64.  Synchronises. */
+bsgd_status bsgd_tv_value(int H, int W, int D, const float* x, void* ws, size_t ws_bytes,
+                          hipStream_t stream, double* tv);
+
+/* ------------------------------------------------------------------------
+ * Step size (Theorem 1: mu < 1 / (2 u_max), u_max = largest eigenvalue of A^T A)
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes for bsgd_power_umax. */
+bsgd_status bsgd_power_workspace_size(const bsgd_plan* plan, size_t* bytes);
+
+/*
+ * u_max by `iters` power-iteration steps v <- A^T A v / ||A^T A v|| from the
+ * all-ones vector; *umax is the last Rayleigh quotient ||A v||^2 / ||v||^2.
+ * Synchronises.
+ */
+bsgd_status bsgd_power_umax(const bsgd_plan* plan, bsgd_valtype vt, int iters, void* ws,
+                            size_t ws_bytes, hipStream_t stream, float* umax);
+
+/* ------------------------------------------------------------------------
+ * Whole epochs (Algorithm 1)
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes of a state for `nrhs` right-hand sides (nrhs = 1 here). */
+bsgd_status bsgd_state_workspace_size(const bsgd_plan* plan, int nrhs, size_t* bytes);
+
+/*
+ * Create a state in `workspace` (device).  The state borrows the plan.  It
+ * owns one extra HIP stream and two events (default priority) that let the
+ * forward product overlap the prox inside an epoch.
+ */
+bsgd_status bsgd_state_create(const bsgd_plan* plan, int nrhs, bsgd_valtype vt, void* workspace,
+                              size_t workspace_bytes, bsgd_state** out);
+
+void bsgd_state_destroy(bsgd_state* state);
+
+/*
+ * Start a reconstruction: copy y (device, r floats); x = x0 (device, c
+ * floats) or 0 when x0 == NULL; r = y - A x0 (r = y when x0 == NULL), the
+ * initialisation that Algorithm 1 leaves open.  Resets the epoch count.
+ */
+bsgd_status bsgd_state_init(bsgd_state* state, const float* y, const float* x0, hipStream_t stream);
+
+/*
+ * Resume from a saved state: x (device, c floats), r (device, r floats, the
+ * residual y - A x_prev of the previous epoch; Eq. 3 makes it part of the
+ * state) and the epoch count.  y must have been set by bsgd_state_init.
+ */
+bsgd_status bsgd_state_load(bsgd_state* state, const float* x, const float* r, int64_t epoch,
+                            hipStream_t stream);
+
+/*
+ * Run `epochs` epochs of Algorithm 1 with every block pair active:
+ *   g = 2 A^T r; r' = y - A x; x^ = x + mu g; x = FGP(x^, theta = mu * lam,
+ *   prox_iters); r = r'.
+ * mu > 0, lam >= 0, epochs >= 0, prox_iters >= 1 when lam > 0.  lam = 0
+ * skips the prox (x = x^).  Enqueued on `stream` (the state's own stream
+ * joins it); no allocation and no host synchronisation.
+ */
+bsgd_status bsgd_run_epochs(bsgd_state* state, float mu, float lam, int epochs, int prox_iters,
+                            hipStream_t stream);
+
+/* Copy the current iterate x (c floats) / residual r (r floats) to device memory. */
+bsgd_status bsgd_get_x(const bsgd_state* state, float* x, hipStream_t stream);
+bsgd_status bsgd_get_r(const bsgd_state* state, float* r, hipStream_t stream);
+
+/*
+ * ||r||^2 of the current residual (FP64 sum of FP32 squares, fixed order)
+ * and the number of epochs run since init.  Synchronises.  Returns
+ * BSGD_ERR_DIVERGED (with the values filled in) when ||r||^2 is not finite.
+ */
+bsgd_status bsgd_get_stats(const bsgd_state* state, hipStream_t stream, double* res_norm2,
+                           int64_t* epochs_done);
+
+/*
+ * Kernel timers (measurement).  After bsgd_state_enable_timing(state,
+ * max_epochs), each of the next max_epochs epochs run by bsgd_run_epochs
+ * records HIP events (on the stream each kernel runs on) around its forward
+ * pass (lines 4 and 6), its backprojection pass (lines 3, 7, 8) and its prox
+ * (line 9).  bsgd_state_timing synchronises, returns the summed durations in
+ * milliseconds and the number of timed epochs, and rearms the timers.
+ * max_epochs = 0 disables timing.
+ */
+bsgd_status bsgd_state_enable_timing(bsgd_state* state, int max_epochs);
+bsgd_status bsgd_state_timing(bsgd_state* state, double* fwd_ms, double* bwd_ms, double* prox_ms,
+                              int64_t* epochs_timed);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* bsgd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSGD_H */

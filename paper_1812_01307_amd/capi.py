@@ -1,0 +1,402 @@
+"""ctypes binding of libbsgd.so (the C ABI declared in include/bsgd.h).
+
+Argument marshalling only: torch tensors are passed as device pointers, the
+current torch stream as the HIP stream.  Every function here has the name
+of the C entry point it calls.  The library must have been built
+(``python -m paper_1812_01307_amd.build`` or ``__graft_entry__.build()``);
+importing this module without it raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbsgd.so")
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is not built; run __graft_entry__.build() first")
+_lib = ctypes.CDLL(_LIB_PATH)
+
+BSGD_OK = 0
+BSGD_ERR_INVALID = -1
+BSGD_ERR_WORKSPACE = -2
+BSGD_ERR_HIP = -3
+BSGD_ERR_UNSUPPORTED = -4
+BSGD_ERR_DIVERGED = -5
+BSGD_VAL_F32 = 0
+BSGD_VAL_F16 = 1
+BSGD_PLAN_F16 = 1
+
+_STATUS = {0: "OK", -1: "INVALID", -2: "WORKSPACE", -3: "HIP", -4: "UNSUPPORTED", -5: "DIVERGED"}
+
+
+class BsgdError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn}: {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class bsgd_csr(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int
+_f32 = ctypes.c_float
+_sz = ctypes.c_size_t
+_PROTOS = {
+    "bsgd_plan_workspace_size": [_i64, _i64, _i64, _i32, _i32, ctypes.c_uint, ctypes.POINTER(_sz)],
+    "bsgd_plan_create": [ctypes.POINTER(bsgd_csr), ctypes.POINTER(bsgd_csr), _i32, _i32,
+                         ctypes.POINTER(_i64), ctypes.POINTER(_i64), _i32, _i32, _i32,
+                         ctypes.c_uint, _vp, _sz, _vp, ctypes.POINTER(_vp)],
+    "bsgd_tile_nnz": [_vp, _i32, _i32, _vp, ctypes.POINTER(_i64)],
+    "bsgd_tile_export": [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp],
+    "bsgd_forward": [_vp, _i32, _vp, _vp, _vp, _vp],
+    "bsgd_backproject": [_vp, _i32, _vp, _vp, _f32, _vp, _vp],
+    "bsgd_forward_block": [_vp, _i32, _i32, _i32, _vp, _vp, _vp],
+    "bsgd_backproject_block": [_vp, _i32, _i32, _i32, _vp, _vp, _vp],
+    "bsgd_tv_workspace_size": [_i32, _i32, _i32, ctypes.POINTER(_sz)],
+    "bsgd_tv_prox": [_i32, _i32, _i32, _vp, _f32, _i32, _vp, _vp, _sz, _vp],
+    "bsgd_tv_value": [_i32, _i32, _i32, _vp, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_double)],
+    "bsgd_power_workspace_size": [_vp, ctypes.POINTER(_sz)],
+    "bsgd_power_umax": [_vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_f32)],
+    "bsgd_state_workspace_size": [_vp, _i32, ctypes.POINTER(_sz)],
+    "bsgd_state_create": [_vp, _i32, _i32, _vp, _sz, ctypes.POINTER(_vp)],
+    "bsgd_state_init": [_vp, _vp, _vp, _vp],
+    "bsgd_state_load": [_vp, _vp, _vp, _i64, _vp],
+    "bsgd_run_epochs": [_vp, _f32, _f32, _i32, _i32, _vp],
+    "bsgd_get_x": [_vp, _vp, _vp],
+    "bsgd_get_r": [_vp, _vp, _vp],
+    "bsgd_get_stats": [_vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)],
+    "bsgd_state_enable_timing": [_vp, _i32],
+    "bsgd_state_timing": [_vp] + [ctypes.POINTER(ctypes.c_double)] * 3 + [ctypes.POINTER(_i64)],
+}
+for _name, _args in _PROTOS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.bsgd_plan_destroy.argtypes = [_vp]
+_lib.bsgd_plan_destroy.restype = None
+_lib.bsgd_state_destroy.argtypes = [_vp]
+_lib.bsgd_state_destroy.restype = None
+_lib.bsgd_last_error.argtypes = []
+_lib.bsgd_last_error.restype = ctypes.c_char_p
+
+EXPORTED = sorted(list(_PROTOS) + ["bsgd_plan_destroy", "bsgd_state_destroy", "bsgd_last_error"])
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _check(fn: str, status: int, allow=()):
+    if status != BSGD_OK and status not in allow:
+        raise BsgdError(fn, status, _lib.bsgd_last_error().decode())
+    return status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _f32(t, n=None, name="tensor"):
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return t
+
+
+# --------------------------------------------------------------------------
+# Plan
+# --------------------------------------------------------------------------
+
+class Plan:
+    """Block store of A and A^T in a torch-owned device workspace."""
+
+    def __init__(self, handle, workspace, M, N, row_off, col_off, H, W, D, nrows, ncols, flags):
+        self.handle = handle
+        self.workspace = workspace
+        self.M, self.N = M, N
+        self.row_off, self.col_off = list(row_off), list(col_off)
+        self.H, self.W, self.D = H, W, D
+        self.nrows, self.ncols = nrows, ncols
+        self.flags = flags
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.bsgd_plan_destroy(h)
+            self.handle = None
+
+
+def bsgd_plan_workspace_size(nrows, ncols, nnz, M, N, flags=0) -> int:
+    out = _sz()
+    _check("bsgd_plan_workspace_size",
+           _lib.bsgd_plan_workspace_size(nrows, ncols, nnz, M, N, flags, ctypes.byref(out)))
+    return out.value
+
+
+def bsgd_plan_create(A, At, M, N, row_off, col_off, H, W, D=1, flags=0, stream=None) -> Plan:
+    """A, At: (row_ptr int64, col int32, val float32) device tensor triples plus shapes.
+
+    A = (nrows, ncols, row_ptr, col, val); At likewise for the transpose.
+    """
+    nrows, ncols, rp, cl, vl = A
+    tn, tc, trp, tcl, tvl = At
+    for t, dt in ((rp, torch.int64), (cl, torch.int32), (vl, torch.float32),
+                  (trp, torch.int64), (tcl, torch.int32), (tvl, torch.float32)):
+        if t.dtype != dt:
+            raise ValueError(f"CSR array has dtype {t.dtype}, expected {dt}")
+    a = bsgd_csr(nrows, ncols, cl.numel(), _ptr(rp), _ptr(cl), _ptr(vl))
+    at = bsgd_csr(tn, tc, tcl.numel(), _ptr(trp), _ptr(tcl), _ptr(tvl))
+    nbytes = bsgd_plan_workspace_size(nrows, ncols, cl.numel(), M, N, flags)
+    ws = _ws(nbytes, rp.device)
+    ro = (_i64 * (M + 1))(*[int(v) for v in row_off])
+    co = (_i64 * (N + 1))(*[int(v) for v in col_off])
+    h = _vp()
+    _check("bsgd_plan_create", _lib.bsgd_plan_create(
+        ctypes.byref(a), ctypes.byref(at), M, N, ro, co, H, W, D, flags, _ptr(ws), nbytes,
+        _stream(stream), ctypes.byref(h)))
+    return Plan(h, ws, M, N, row_off, col_off, H, W, D, nrows, ncols, flags)
+
+
+def bsgd_tile_nnz(plan: Plan, i, j, stream=None) -> int:
+    out = _i64()
+    _check("bsgd_tile_nnz", _lib.bsgd_tile_nnz(plan.handle, i, j, _stream(stream), ctypes.byref(out)))
+    return out.value
+
+
+def bsgd_tile_export(plan: Plan, i, j, transposed=False, stream=None):
+    """Block (i, j) (or its transpose) as block-local (ptr, col, val) device tensors."""
+    nnz = bsgd_tile_nnz(plan, i, j, stream)
+    dev = plan.workspace.device
+    rows = (plan.row_off[i + 1] - plan.row_off[i]) if not transposed else \
+        (plan.col_off[j + 1] - plan.col_off[j])
+    ptr = torch.empty(rows + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    val = torch.empty(max(nnz, 1), dtype=torch.float32, device=dev)
+    _check("bsgd_tile_export", _lib.bsgd_tile_export(plan.handle, i, j, int(bool(transposed)),
+                                                     _ptr(ptr), _ptr(col), _ptr(val), _stream(stream)))
+    return ptr, col[:nnz], val[:nnz]
+
+
+# --------------------------------------------------------------------------
+# Products
+# --------------------------------------------------------------------------
+
+def bsgd_forward(plan: Plan, x, y=None, out=None, vt=BSGD_VAL_F32, stream=None):
+    _f32(x, plan.ncols, "x")
+    if y is not None:
+        _f32(y, plan.nrows, "y")
+    if out is None:
+        out = torch.empty(plan.nrows, dtype=torch.float32, device=x.device)
+    _f32(out, plan.nrows, "out")
+    _check("bsgd_forward", _lib.bsgd_forward(plan.handle, vt, _ptr(x), _ptr(y), _ptr(out),
+                                             _stream(stream)))
+    return out
+
+
+def bsgd_backproject(plan: Plan, r, x=None, mu=0.0, out=None, vt=BSGD_VAL_F32, stream=None):
+    _f32(r, plan.nrows, "r")
+    if x is not None:
+        _f32(x, plan.ncols, "x")
+    if out is None:
+        out = torch.empty(plan.ncols, dtype=torch.float32, device=r.device)
+    _f32(out, plan.ncols, "out")
+    _check("bsgd_backproject", _lib.bsgd_backproject(plan.handle, vt, _ptr(r), _ptr(x), float(mu),
+                                                     _ptr(out), _stream(stream)))
+    return out
+
+
+def bsgd_forward_block(plan: Plan, i, j, xj, out=None, vt=BSGD_VAL_F32, stream=None):
+    _f32(xj, plan.col_off[j + 1] - plan.col_off[j], "xj")
+    n = plan.row_off[i + 1] - plan.row_off[i]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=xj.device)
+    _f32(out, n, "z")
+    _check("bsgd_forward_block", _lib.bsgd_forward_block(plan.handle, vt, i, j, _ptr(xj), _ptr(out),
+                                                         _stream(stream)))
+    return out
+
+
+def bsgd_backproject_block(plan: Plan, i, j, ri, out=None, vt=BSGD_VAL_F32, stream=None):
+    _f32(ri, plan.row_off[i + 1] - plan.row_off[i], "ri")
+    n = plan.col_off[j + 1] - plan.col_off[j]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=ri.device)
+    _f32(out, n, "g")
+    _check("bsgd_backproject_block", _lib.bsgd_backproject_block(
+        plan.handle, vt, i, j, _ptr(ri), _ptr(out), _stream(stream)))
+    return out
+
+
+# --------------------------------------------------------------------------
+# TV
+# --------------------------------------------------------------------------
+
+def bsgd_tv_workspace_size(H, W, D=1) -> int:
+    out = _sz()
+    _check("bsgd_tv_workspace_size", _lib.bsgd_tv_workspace_size(H, W, D, ctypes.byref(out)))
+    return out.value
+
+
+def bsgd_tv_prox(b, theta, iters, out=None, ws=None, stream=None):
+    """b: (H, W) or (D, H, W) float32 device tensor."""
+    shape = tuple(b.shape)
+    D, H, W = (1,) + shape if len(shape) == 2 else shape
+    _f32(b)
+    if out is None:
+        out = torch.empty_like(b)
+    nbytes = bsgd_tv_workspace_size(H, W, D)
+    if ws is None:
+        ws = _ws(nbytes, b.device)
+    _check("bsgd_tv_prox", _lib.bsgd_tv_prox(H, W, D, _ptr(b), float(theta), int(iters), _ptr(out),
+                                             _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def bsgd_tv_value(x, ws=None, stream=None) -> float:
+    shape = tuple(x.shape)
+    D, H, W = (1,) + shape if len(shape) == 2 else shape
+    _f32(x)
+    nbytes = bsgd_tv_workspace_size(H, W, D)
+    if ws is None:
+        ws = _ws(nbytes, x.device)
+    out = ctypes.c_double()
+    _check("bsgd_tv_value", _lib.bsgd_tv_value(H, W, D, _ptr(x), _ptr(ws), ws.numel(),
+                                               _stream(stream), ctypes.byref(out)))
+    return out.value
+
+
+# --------------------------------------------------------------------------
+# Step size
+# --------------------------------------------------------------------------
+
+def bsgd_power_workspace_size(plan: Plan) -> int:
+    out = _sz()
+    _check("bsgd_power_workspace_size", _lib.bsgd_power_workspace_size(plan.handle, ctypes.byref(out)))
+    return out.value
+
+
+def bsgd_power_umax(plan: Plan, iters, vt=BSGD_VAL_F32, ws=None, stream=None) -> float:
+    nbytes = bsgd_power_workspace_size(plan)
+    if ws is None:
+        ws = _ws(nbytes, plan.workspace.device)
+    out = ctypes.c_float()
+    _check("bsgd_power_umax", _lib.bsgd_power_umax(plan.handle, vt, int(iters), _ptr(ws), ws.numel(),
+                                                   _stream(stream), ctypes.byref(out)))
+    return float(out.value)
+
+
+# --------------------------------------------------------------------------
+# Epochs
+# --------------------------------------------------------------------------
+
+class State:
+    def __init__(self, handle, workspace, plan):
+        self.handle = handle
+        self.workspace = workspace
+        self.plan = plan
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.bsgd_state_destroy(h)
+            self.handle = None
+
+
+def bsgd_state_workspace_size(plan: Plan, nrhs=1) -> int:
+    out = _sz()
+    _check("bsgd_state_workspace_size", _lib.bsgd_state_workspace_size(plan.handle, nrhs,
+                                                                       ctypes.byref(out)))
+    return out.value
+
+
+def bsgd_state_create(plan: Plan, nrhs=1, vt=BSGD_VAL_F32) -> State:
+    nbytes = bsgd_state_workspace_size(plan, nrhs)
+    ws = _ws(nbytes, plan.workspace.device)
+    h = _vp()
+    _check("bsgd_state_create", _lib.bsgd_state_create(plan.handle, nrhs, vt, _ptr(ws), nbytes,
+                                                       ctypes.byref(h)))
+    return State(h, ws, plan)
+
+
+def bsgd_state_init(state: State, y, x0=None, stream=None):
+    _f32(y, state.plan.nrows, "y")
+    if x0 is not None:
+        _f32(x0, state.plan.ncols, "x0")
+    _check("bsgd_state_init", _lib.bsgd_state_init(state.handle, _ptr(y), _ptr(x0), _stream(stream)))
+
+
+def bsgd_state_load(state: State, x, r, epoch, stream=None):
+    _f32(x, state.plan.ncols, "x")
+    _f32(r, state.plan.nrows, "r")
+    _check("bsgd_state_load", _lib.bsgd_state_load(state.handle, _ptr(x), _ptr(r), int(epoch),
+                                                   _stream(stream)))
+
+
+def bsgd_run_epochs(state: State, mu, lam, epochs, prox_iters, stream=None):
+    _check("bsgd_run_epochs", _lib.bsgd_run_epochs(state.handle, float(mu), float(lam), int(epochs),
+                                                   int(prox_iters), _stream(stream)))
+
+
+def bsgd_get_x(state: State, out=None, stream=None):
+    if out is None:
+        out = torch.empty(state.plan.ncols, dtype=torch.float32, device=state.workspace.device)
+    _f32(out, state.plan.ncols, "x")
+    _check("bsgd_get_x", _lib.bsgd_get_x(state.handle, _ptr(out), _stream(stream)))
+    return out
+
+
+def bsgd_get_r(state: State, out=None, stream=None):
+    if out is None:
+        out = torch.empty(state.plan.nrows, dtype=torch.float32, device=state.workspace.device)
+    _f32(out, state.plan.nrows, "r")
+    _check("bsgd_get_r", _lib.bsgd_get_r(state.handle, _ptr(out), _stream(stream)))
+    return out
+
+
+def bsgd_get_stats(state: State, stream=None, allow_diverged=False):
+    """(||r||^2, epochs_done); raises on divergence unless allow_diverged."""
+    rn = ctypes.c_double()
+    ep = _i64()
+    st = _lib.bsgd_get_stats(state.handle, _stream(stream), ctypes.byref(rn), ctypes.byref(ep))
+    _check("bsgd_get_stats", st, allow=(BSGD_ERR_DIVERGED,) if allow_diverged else ())
+    return rn.value, ep.value, st == BSGD_ERR_DIVERGED
+
+
+def bsgd_last_error() -> str:
+    return _lib.bsgd_last_error().decode()
+
+
+def bsgd_state_enable_timing(state: State, max_epochs: int):
+    _check("bsgd_state_enable_timing", _lib.bsgd_state_enable_timing(state.handle, int(max_epochs)))
+
+
+def bsgd_state_timing(state: State):
+    """(forward ms, backprojection ms, prox ms, epochs timed) summed over timed epochs."""
+    f, b, x = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    n = _i64()
+    _check("bsgd_state_timing", _lib.bsgd_state_timing(state.handle, ctypes.byref(f), ctypes.byref(b),
+                                                       ctypes.byref(x), ctypes.byref(n)))
+    return f.value, b.value, x.value, n.value

@@ -1,0 +1,272 @@
+// Sparse products over the block store (Algorithm 1 lines 3-8).
+//
+// A row of the store (a ray of A, or a pixel of A^T) lists the row's entries
+// of all its blocks back to back, so one pass over the row computes the sum
+// over blocks of the block products: sum_j z^j for a ray (lines 4 and 6) and
+// sum_i g^i for a pixel (lines 3 and 7).  A group of LPR lanes of one
+// wavefront walks a row with 16-byte loads of column indices and values
+// (rows are padded to a multiple of 8 entries, so loads are aligned), gathers
+// the vector entries, and reduces across the group with cross-lane shuffles.
+// No atomics: every output element is written once by one lane, and the
+// summation order is fixed for a given LPR.
+#include "bsgd_internal.h"
+
+namespace bsgd {
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <typename T>
+__device__ __forceinline__ T stream_load(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
+// Sum of val[e] * v[col[e]] over the lane's share of [beg, end).
+template <int LPR>
+__device__ __forceinline__ float row_dot_f32(const int32_t* __restrict__ col,
+                                             const float* __restrict__ val,
+                                             const float* __restrict__ v, int64_t beg, int64_t end,
+                                             int lane) {
+  float acc0 = 0.f, acc1 = 0.f;
+  int64_t e = beg + 4 * lane;
+  // two chunks in flight per lane
+  for (; e + 4 * LPR < end; e += 8 * LPR) {
+    const i32x4 c0 = stream_load(reinterpret_cast<const i32x4*>(col + e));
+    const f32x4 a0 = stream_load(reinterpret_cast<const f32x4*>(val + e));
+    const i32x4 c1 = stream_load(reinterpret_cast<const i32x4*>(col + e + 4 * LPR));
+    const f32x4 a1 = stream_load(reinterpret_cast<const f32x4*>(val + e + 4 * LPR));
+    acc0 = fmaf(a0.x, v[c0.x], acc0);
+    acc1 = fmaf(a1.x, v[c1.x], acc1);
+    acc0 = fmaf(a0.y, v[c0.y], acc0);
+    acc1 = fmaf(a1.y, v[c1.y], acc1);
+    acc0 = fmaf(a0.z, v[c0.z], acc0);
+    acc1 = fmaf(a1.z, v[c1.z], acc1);
+    acc0 = fmaf(a0.w, v[c0.w], acc0);
+    acc1 = fmaf(a1.w, v[c1.w], acc1);
+  }
+  if (e < end) {
+    const i32x4 c0 = stream_load(reinterpret_cast<const i32x4*>(col + e));
+    const f32x4 a0 = stream_load(reinterpret_cast<const f32x4*>(val + e));
+    acc0 = fmaf(a0.x, v[c0.x], acc0);
+    acc0 = fmaf(a0.y, v[c0.y], acc0);
+    acc0 = fmaf(a0.z, v[c0.z], acc0);
+    acc0 = fmaf(a0.w, v[c0.w], acc0);
+  }
+  return acc0 + acc1;
+}
+
+// FP16 values: 8 entries per lane per chunk (32 B of columns, 16 B of values).
+template <int LPR>
+__device__ __forceinline__ float row_dot_f16(const int32_t* __restrict__ col,
+                                             const __half* __restrict__ val,
+                                             const float* __restrict__ v, int64_t beg, int64_t end,
+                                             int lane) {
+  float acc0 = 0.f, acc1 = 0.f;
+  for (int64_t e = beg + 8 * lane; e < end; e += 8 * LPR) {
+    const i32x4 c0 = stream_load(reinterpret_cast<const i32x4*>(col + e));
+    const i32x4 c1 = stream_load(reinterpret_cast<const i32x4*>(col + e + 4));
+    const f16x8 a = stream_load(reinterpret_cast<const f16x8*>(val + e));
+    acc0 = fmaf((float)a[0], v[c0.x], acc0);
+    acc1 = fmaf((float)a[4], v[c1.x], acc1);
+    acc0 = fmaf((float)a[1], v[c0.y], acc0);
+    acc1 = fmaf((float)a[5], v[c1.y], acc1);
+    acc0 = fmaf((float)a[2], v[c0.z], acc0);
+    acc1 = fmaf((float)a[6], v[c1.z], acc1);
+    acc0 = fmaf((float)a[3], v[c0.w], acc0);
+    acc1 = fmaf((float)a[7], v[c1.w], acc1);
+  }
+  return acc0 + acc1;
+}
+
+template <int LPR>
+__device__ __forceinline__ float group_sum(float x) {
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, LPR);
+  return x;
+}
+
+template <typename VT, int LPR, int MODE>
+__global__ __launch_bounds__(256) void k_rows(const int64_t* __restrict__ ptr,
+                                              const int32_t* __restrict__ col,
+                                              const VT* __restrict__ val,
+                                              const float* __restrict__ v,
+                                              const float* __restrict__ y,
+                                              const float* __restrict__ xadd, float scale,
+                                              float* __restrict__ out, int64_t nrows) {
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t row = gid / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  float acc = 0.f;
+  if (row < nrows) {
+    const int64_t beg = ptr[row], end = ptr[row + 1];
+    if constexpr (sizeof(VT) == 4)
+      acc = row_dot_f32<LPR>(col, reinterpret_cast<const float*>(val), v, beg, end, lane);
+    else
+      acc = row_dot_f16<LPR>(col, reinterpret_cast<const __half*>(val), v, beg, end, lane);
+  }
+  acc = group_sum<LPR>(acc);
+  if (row < nrows && lane == 0) {
+    if constexpr (MODE == kPlain)
+      out[row] = scale * acc;
+    else if constexpr (MODE == kResidual)
+      out[row] = y[row] - acc;
+    else
+      out[row] = fmaf(scale, acc, xadd[row]);
+  }
+}
+
+template <typename VT, int MODE>
+static hipError_t launch_rows_vt(const Store& st, const VT* val, const float* v, const float* y,
+                                 const float* xadd, float scale, float* out, hipStream_t s) {
+  const int lpr = st.lanes_per_row;
+  const int64_t threads = st.nrows * lpr;
+  const unsigned blocks = (unsigned)((threads + 255) / 256);
+  if (blocks == 0) return hipSuccess;
+  switch (lpr) {
+    case 8:
+      k_rows<VT, 8, MODE><<<blocks, 256, 0, s>>>(st.ptr, st.col, val, v, y, xadd, scale, out,
+                                                 st.nrows);
+      break;
+    case 16:
+      k_rows<VT, 16, MODE><<<blocks, 256, 0, s>>>(st.ptr, st.col, val, v, y, xadd, scale, out,
+                                                  st.nrows);
+      break;
+    case 32:
+      k_rows<VT, 32, MODE><<<blocks, 256, 0, s>>>(st.ptr, st.col, val, v, y, xadd, scale, out,
+                                                  st.nrows);
+      break;
+    default:
+      k_rows<VT, 64, MODE><<<blocks, 256, 0, s>>>(st.ptr, st.col, val, v, y, xadd, scale, out,
+                                                  st.nrows);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_rows_mode(const Store& st, bsgd_valtype vt, const float* v,
+                                   const float* y, const float* xadd, float scale, float* out,
+                                   hipStream_t s) {
+  if (vt == BSGD_VAL_F16)
+    return launch_rows_vt<__half, MODE>(st, st.val16, v, y, xadd, scale, out, s);
+  return launch_rows_vt<float, MODE>(st, st.val, v, y, xadd, scale, out, s);
+}
+
+hipError_t launch_rows(const Store& st, bsgd_valtype vt, RowMode mode, const float* v,
+                       const float* y, const float* xadd, float scale, float* out,
+                       hipStream_t s) {
+  switch (mode) {
+    case kPlain:
+      return launch_rows_mode<kPlain>(st, vt, v, y, xadd, scale, out, s);
+    case kResidual:
+      return launch_rows_mode<kResidual>(st, vt, v, y, xadd, scale, out, s);
+    default:
+      return launch_rows_mode<kStep>(st, vt, v, y, xadd, scale, out, s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One block's product: the entries of segment `segk` of rows
+// [row0, row0 + nrows), gathering v[col - col_base].  One wavefront per row,
+// scalar loads (used for per-block checks, not on the epoch path).
+// ---------------------------------------------------------------------------
+template <typename VT>
+__global__ __launch_bounds__(256) void k_segment_rows(
+    const int64_t* __restrict__ ptr, const int32_t* __restrict__ seg, int nseg,
+    const int32_t* __restrict__ col, const VT* __restrict__ val, int64_t row0, int64_t nrows,
+    int segk, int64_t col_base, const float* __restrict__ v, float scale,
+    float* __restrict__ out) {
+  const int64_t r = ((int64_t)blockIdx.x * 256 + threadIdx.x) / 64;
+  const int lane = threadIdx.x & 63;
+  float acc = 0.f;
+  if (r < nrows) {
+    const int64_t row = row0 + r;
+    const int32_t* sg = seg + row * (nseg + 1);
+    const int64_t beg = ptr[row] + sg[segk], end = ptr[row] + sg[segk + 1];
+    for (int64_t e = beg + lane; e < end; e += 64)
+      acc = fmaf((float)val[e], v[col[e] - col_base], acc);
+  }
+  acc = group_sum<64>(acc);
+  if (r < nrows && lane == 0) out[r] = scale * acc;
+}
+
+hipError_t launch_segment_rows(const Store& st, bsgd_valtype vt, int64_t row0, int64_t nrows,
+                               int segk, int64_t col_base, const float* v, float scale,
+                               float* out, hipStream_t s) {
+  const unsigned blocks = (unsigned)((nrows * 64 + 255) / 256);
+  if (blocks == 0) return hipSuccess;
+  if (vt == BSGD_VAL_F16)
+    k_segment_rows<__half><<<blocks, 256, 0, s>>>(st.ptr, st.seg, st.nseg, st.col, st.val16,
+                                                  row0, nrows, segk, col_base, v, scale, out);
+  else
+    k_segment_rows<float><<<blocks, 256, 0, s>>>(st.ptr, st.seg, st.nseg, st.col, st.val, row0,
+                                                 nrows, segk, col_base, v, scale, out);
+  return hipGetLastError();
+}
+
+}  // namespace bsgd
+
+// ---------------------------------------------------------------------------
+// C ABI: step-level products
+// ---------------------------------------------------------------------------
+using namespace bsgd;
+
+static bsgd_status check_vt(const bsgd_plan* plan, bsgd_valtype vt) {
+  BSGD_REQUIRE(plan != nullptr, "plan is NULL");
+  BSGD_REQUIRE(vt == BSGD_VAL_F32 || vt == BSGD_VAL_F16, "unknown value type %d", (int)vt);
+  if (vt == BSGD_VAL_F16 && !(plan->flags & BSGD_PLAN_F16)) {
+    set_error("plan was created without BSGD_PLAN_F16");
+    return BSGD_ERR_INVALID;
+  }
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_forward(const bsgd_plan* plan, bsgd_valtype vt, const float* x,
+                                    const float* y, float* out, hipStream_t stream) {
+  bsgd_status st = check_vt(plan, vt);
+  if (st != BSGD_OK) return st;
+  BSGD_REQUIRE(x != nullptr && out != nullptr, "x and out must be non-NULL");
+  BSGD_HIP(launch_rows(plan->fwd, vt, y ? kResidual : kPlain, x, y, nullptr, 1.0f, out, stream));
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_backproject(const bsgd_plan* plan, bsgd_valtype vt, const float* r,
+                                        const float* x, float mu, float* out,
+                                        hipStream_t stream) {
+  bsgd_status st = check_vt(plan, vt);
+  if (st != BSGD_OK) return st;
+  BSGD_REQUIRE(r != nullptr && out != nullptr, "r and out must be non-NULL");
+  if (x)
+    BSGD_HIP(launch_rows(plan->bwd, vt, kStep, r, nullptr, x, 2.0f * mu, out, stream));
+  else
+    BSGD_HIP(launch_rows(plan->bwd, vt, kPlain, r, nullptr, nullptr, 2.0f, out, stream));
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_forward_block(const bsgd_plan* plan, bsgd_valtype vt, int i, int j,
+                                          const float* xj, float* z, hipStream_t stream) {
+  bsgd_status st = check_vt(plan, vt);
+  if (st != BSGD_OK) return st;
+  BSGD_REQUIRE(i >= 0 && i < plan->M && j >= 0 && j < plan->N, "block (%d, %d) out of range", i,
+               j);
+  BSGD_REQUIRE(xj != nullptr && z != nullptr, "xj and z must be non-NULL");
+  const int64_t r0 = plan->row_off[i], r1 = plan->row_off[i + 1];
+  BSGD_HIP(launch_segment_rows(plan->fwd, vt, r0, r1 - r0, j, plan->col_off[j], xj, 1.0f, z,
+                               stream));
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_backproject_block(const bsgd_plan* plan, bsgd_valtype vt, int i,
+                                              int j, const float* ri, float* g,
+                                              hipStream_t stream) {
+  bsgd_status st = check_vt(plan, vt);
+  if (st != BSGD_OK) return st;
+  BSGD_REQUIRE(i >= 0 && i < plan->M && j >= 0 && j < plan->N, "block (%d, %d) out of range", i,
+               j);
+  BSGD_REQUIRE(ri != nullptr && g != nullptr, "ri and g must be non-NULL");
+  const int64_t c0 = plan->col_off[j], c1 = plan->col_off[j + 1];
+  BSGD_HIP(launch_segment_rows(plan->bwd, vt, c0, c1 - c0, i, plan->row_off[i], ri, 2.0f, g,
+                               stream));
+  return BSGD_OK;
+}

@@ -1,0 +1,346 @@
+// Step size (Theorem 1) and whole epochs of Algorithm 1.
+//
+// Epoch schedule.  Line 3 uses the residual r_k of the previous epoch and
+// line 4 the current iterate x_k, so within one epoch
+//     S2: x^ = x_k + mu * 2 A^T r_k     (lines 3, 7, 8; one fused pass over A^T)
+//     S1: r_{k+1} = y - A x_k           (lines 4, 6;    one fused pass over A)
+//     S5: x_{k+1} = FGP(x^)             (line 9)
+// S1 depends on nothing produced in the epoch, so it runs on the state's
+// second stream while S2 and then the prox run on the caller's stream; the
+// prox (many short launches) hides under the forward pass.  x and r are
+// double-buffered; events order the buffer reuse across epochs.
+#include <cmath>
+#include <vector>
+
+#include "bsgd_internal.h"
+
+struct bsgd_state {
+  const bsgd_plan* plan = nullptr;
+  int nrhs = 1;
+  bsgd_valtype vt = BSGD_VAL_F32;
+  float* y = nullptr;
+  float* x[2] = {nullptr, nullptr};
+  float* r[2] = {nullptr, nullptr};
+  float* xhat = nullptr;
+  float* tv_ws = nullptr;
+  double* partial = nullptr;  // kReduceBlocks + 1 (last = result)
+  int cur = 0;
+  int64_t epochs_done = 0;
+  bool initialised = false;
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_main = nullptr, ev_aux = nullptr;
+  // optional kernel timers: 5 events per timed epoch
+  std::vector<hipEvent_t> tev;
+  int t_cap = 0, t_used = 0;
+};
+
+namespace bsgd {
+
+// ---------------------------------------------------------------------------
+// Power iteration helpers
+// ---------------------------------------------------------------------------
+__global__ void k_scale_by_rsqrt(float* __restrict__ v, const float* __restrict__ w, int64_t n,
+                                 const double* __restrict__ nrm2) {
+  const double s = *nrm2 > 0.0 ? 1.0 / sqrt(*nrm2) : 0.0;
+  const float fs = (float)s;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = w[i] * fs;
+}
+
+__global__ void k_ratio(const double* __restrict__ num, const double* __restrict__ den,
+                        float* __restrict__ out) {
+  *out = *den > 0.0 ? (float)(*num / *den) : 0.f;
+}
+
+static size_t power_layout(const bsgd_plan* p, void* ws, float** v, float** z, float** w,
+                           double** part, double** sc, float** res) {
+  Carver cv(ws);
+  *v = cv.take<float>(p->fwd.ncols);
+  *w = cv.take<float>(p->fwd.ncols);
+  *z = cv.take<float>(p->fwd.nrows);
+  *part = cv.take<double>(kReduceBlocks);
+  *sc = cv.take<double>(4);
+  *res = cv.take<float>(4);
+  return align_up(cv.off, kAlign);
+}
+
+static size_t state_layout(const bsgd_plan* p, void* ws, bsgd_state* st) {
+  Carver cv(ws);
+  const int64_t r = p->fwd.nrows, c = p->fwd.ncols;
+  st->y = cv.take<float>(r);
+  st->x[0] = cv.take<float>(c);
+  st->x[1] = cv.take<float>(c);
+  st->r[0] = cv.take<float>(r);
+  st->r[1] = cv.take<float>(r);
+  st->xhat = cv.take<float>(c);
+  st->tv_ws = cv.take<float>(tv_ws_floats(p->H, p->W, p->D));
+  st->partial = cv.take<double>(kReduceBlocks + 1);
+  return align_up(cv.off, kAlign);
+}
+
+}  // namespace bsgd
+
+using namespace bsgd;
+
+extern "C" bsgd_status bsgd_power_workspace_size(const bsgd_plan* plan, size_t* bytes) {
+  clear_error();
+  BSGD_REQUIRE(plan && bytes, "NULL argument");
+  float *v, *z, *w, *res;
+  double *part, *sc;
+  *bytes = power_layout(plan, nullptr, &v, &z, &w, &part, &sc, &res);
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_power_umax(const bsgd_plan* plan, bsgd_valtype vt, int iters,
+                                       void* ws, size_t ws_bytes, hipStream_t stream,
+                                       float* umax) {
+  clear_error();
+  BSGD_REQUIRE(plan && ws && umax, "NULL argument");
+  BSGD_REQUIRE(iters >= 1, "iters must be >= 1");
+  BSGD_REQUIRE(vt == BSGD_VAL_F32 || (vt == BSGD_VAL_F16 && (plan->flags & BSGD_PLAN_F16)),
+               "value type not available in this plan");
+  float *v, *z, *w, *res;
+  double *part, *sc;
+  const size_t need = power_layout(plan, ws, &v, &z, &w, &part, &sc, &res);
+  if (ws_bytes < need) {
+    set_error("power workspace has %zu bytes, needs %zu", ws_bytes, need);
+    return BSGD_ERR_WORKSPACE;
+  }
+  const int64_t c = plan->fwd.ncols, r = plan->fwd.nrows;
+  BSGD_HIP(fill_f32(v, c, 1.0f, stream));
+  for (int it = 0; it < iters; ++it) {
+    BSGD_HIP(launch_rows(plan->fwd, vt, kPlain, v, nullptr, nullptr, 1.0f, z, stream));  // A v
+    BSGD_HIP(launch_rows(plan->bwd, vt, kPlain, z, nullptr, nullptr, 1.0f, w, stream));  // A^T A v
+    BSGD_HIP(launch_sumsq(z, r, part, sc + 0, stream));   // ||A v||^2
+    BSGD_HIP(launch_sumsq(v, c, part, sc + 1, stream));   // ||v||^2
+    BSGD_HIP(launch_sumsq(w, c, part, sc + 2, stream));   // ||A^T A v||^2
+    k_ratio<<<1, 1, 0, stream>>>(sc + 0, sc + 1, res);
+    BSGD_LAUNCH_CHECK();
+    k_scale_by_rsqrt<<<1024, 256, 0, stream>>>(v, w, c, sc + 2);
+    BSGD_LAUNCH_CHECK();
+  }
+  BSGD_HIP(hipMemcpyAsync(umax, res, sizeof(float), hipMemcpyDeviceToHost, stream));
+  BSGD_HIP(hipStreamSynchronize(stream));
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_state_workspace_size(const bsgd_plan* plan, int nrhs, size_t* bytes) {
+  clear_error();
+  BSGD_REQUIRE(plan && bytes, "NULL argument");
+  if (nrhs != 1) {
+    set_error("nrhs = %d: only single right-hand sides are implemented", nrhs);
+    return BSGD_ERR_UNSUPPORTED;
+  }
+  bsgd_state tmp;
+  *bytes = state_layout(plan, nullptr, &tmp);
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_state_create(const bsgd_plan* plan, int nrhs, bsgd_valtype vt,
+                                         void* workspace, size_t workspace_bytes,
+                                         bsgd_state** out) {
+  clear_error();
+  BSGD_REQUIRE(plan && workspace && out, "NULL argument");
+  BSGD_REQUIRE(((uintptr_t)workspace % kAlign) == 0, "workspace must be 256-byte aligned");
+  BSGD_REQUIRE(vt == BSGD_VAL_F32 || (vt == BSGD_VAL_F16 && (plan->flags & BSGD_PLAN_F16)),
+               "value type not available in this plan");
+  size_t need = 0;
+  bsgd_status s = bsgd_state_workspace_size(plan, nrhs, &need);
+  if (s != BSGD_OK) return s;
+  if (workspace_bytes < need) {
+    set_error("state workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    return BSGD_ERR_WORKSPACE;
+  }
+  bsgd_state* st = new bsgd_state();
+  st->plan = plan;
+  st->nrhs = nrhs;
+  st->vt = vt;
+  state_layout(plan, workspace, st);
+  hipError_t e = hipStreamCreateWithFlags(&st->aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_main, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_aux, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    set_error("state stream/event creation failed: %s", hipGetErrorString(e));
+    if (st->ev_main) (void)hipEventDestroy(st->ev_main);
+    if (st->aux) (void)hipStreamDestroy(st->aux);
+    delete st;
+    return BSGD_ERR_HIP;
+  }
+  *out = st;
+  return BSGD_OK;
+}
+
+static void destroy_timers(bsgd_state* st) {
+  for (hipEvent_t e : st->tev) (void)hipEventDestroy(e);
+  st->tev.clear();
+  st->t_cap = st->t_used = 0;
+}
+
+extern "C" void bsgd_state_destroy(bsgd_state* st) {
+  if (!st) return;
+  if (st->aux) (void)hipStreamSynchronize(st->aux);
+  destroy_timers(st);
+  if (st->ev_aux) (void)hipEventDestroy(st->ev_aux);
+  if (st->ev_main) (void)hipEventDestroy(st->ev_main);
+  if (st->aux) (void)hipStreamDestroy(st->aux);
+  delete st;
+}
+
+extern "C" bsgd_status bsgd_state_init(bsgd_state* st, const float* y, const float* x0,
+                                       hipStream_t stream) {
+  clear_error();
+  BSGD_REQUIRE(st && y, "NULL argument");
+  const bsgd_plan* p = st->plan;
+  const int64_t r = p->fwd.nrows, c = p->fwd.ncols;
+  BSGD_HIP(hipMemcpyAsync(st->y, y, sizeof(float) * r, hipMemcpyDeviceToDevice, stream));
+  st->cur = 0;
+  if (x0) {
+    BSGD_HIP(hipMemcpyAsync(st->x[0], x0, sizeof(float) * c, hipMemcpyDeviceToDevice, stream));
+    BSGD_HIP(launch_rows(p->fwd, st->vt, kResidual, st->x[0], st->y, nullptr, 1.0f, st->r[0],
+                         stream));
+  } else {
+    BSGD_HIP(fill_f32(st->x[0], c, 0.0f, stream));
+    BSGD_HIP(hipMemcpyAsync(st->r[0], st->y, sizeof(float) * r, hipMemcpyDeviceToDevice, stream));
+  }
+  st->epochs_done = 0;
+  st->initialised = true;
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_state_load(bsgd_state* st, const float* x, const float* r,
+                                       int64_t epoch, hipStream_t stream) {
+  clear_error();
+  BSGD_REQUIRE(st && x && r, "NULL argument");
+  BSGD_REQUIRE(st->initialised, "state_init must be called first (it sets y)");
+  BSGD_REQUIRE(epoch >= 0, "epoch must be >= 0");
+  const bsgd_plan* p = st->plan;
+  st->cur = 0;
+  BSGD_HIP(hipMemcpyAsync(st->x[0], x, sizeof(float) * p->fwd.ncols, hipMemcpyDeviceToDevice,
+                          stream));
+  BSGD_HIP(hipMemcpyAsync(st->r[0], r, sizeof(float) * p->fwd.nrows, hipMemcpyDeviceToDevice,
+                          stream));
+  st->epochs_done = epoch;
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int epochs,
+                                       int prox_iters, hipStream_t stream) {
+  clear_error();
+  BSGD_REQUIRE(st != nullptr, "state is NULL");
+  BSGD_REQUIRE(st->initialised, "state_init must be called first");
+  BSGD_REQUIRE(std::isfinite(mu) && mu > 0.f, "mu must be finite and > 0");
+  BSGD_REQUIRE(std::isfinite(lam) && lam >= 0.f, "lam must be finite and >= 0");
+  BSGD_REQUIRE(epochs >= 0, "epochs must be >= 0");
+  BSGD_REQUIRE(lam == 0.f || prox_iters >= 1, "prox_iters must be >= 1 when lam > 0");
+  const bsgd_plan* p = st->plan;
+  const float theta = mu * lam;
+  for (int e = 0; e < epochs; ++e) {
+    const int c = st->cur, n = 1 - c;
+    hipEvent_t* tv = st->t_used < st->t_cap ? &st->tev[5 * (size_t)st->t_used++] : nullptr;
+    // S1 on the aux stream, after everything already queued on `stream`
+    BSGD_HIP(hipEventRecord(st->ev_main, stream));
+    BSGD_HIP(hipStreamWaitEvent(st->aux, st->ev_main, 0));
+    if (tv) BSGD_HIP(hipEventRecord(tv[0], st->aux));
+    BSGD_HIP(launch_rows(p->fwd, st->vt, kResidual, st->x[c], st->y, nullptr, 1.0f, st->r[n],
+                         st->aux));
+    if (tv) BSGD_HIP(hipEventRecord(tv[1], st->aux));
+    BSGD_HIP(hipEventRecord(st->ev_aux, st->aux));
+    // S2 (+S4) then S5 on `stream`
+    if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
+    if (theta == 0.f) {
+      BSGD_HIP(launch_rows(p->bwd, st->vt, kStep, st->r[c], nullptr, st->x[c], 2.0f * mu,
+                           st->x[n], stream));
+      if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
+    } else {
+      BSGD_HIP(launch_rows(p->bwd, st->vt, kStep, st->r[c], nullptr, st->x[c], 2.0f * mu,
+                           st->xhat, stream));
+      if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
+      BSGD_HIP(tv_prox_run(p->H, p->W, p->D, st->xhat, theta, prox_iters, st->x[n], st->tv_ws,
+                           stream));
+    }
+    if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));
+    BSGD_HIP(hipStreamWaitEvent(stream, st->ev_aux, 0));
+    st->cur = n;
+    st->epochs_done++;
+  }
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_get_x(const bsgd_state* st, float* x, hipStream_t stream) {
+  clear_error();
+  BSGD_REQUIRE(st && x, "NULL argument");
+  BSGD_HIP(hipMemcpyAsync(x, st->x[st->cur], sizeof(float) * st->plan->fwd.ncols,
+                          hipMemcpyDeviceToDevice, stream));
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_get_r(const bsgd_state* st, float* r, hipStream_t stream) {
+  clear_error();
+  BSGD_REQUIRE(st && r, "NULL argument");
+  BSGD_HIP(hipMemcpyAsync(r, st->r[st->cur], sizeof(float) * st->plan->fwd.nrows,
+                          hipMemcpyDeviceToDevice, stream));
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_get_stats(const bsgd_state* st, hipStream_t stream, double* res_norm2,
+                                      int64_t* epochs_done) {
+  clear_error();
+  BSGD_REQUIRE(st && res_norm2 && epochs_done, "NULL argument");
+  BSGD_HIP(launch_sumsq(st->r[st->cur], st->plan->fwd.nrows, st->partial,
+                        st->partial + kReduceBlocks, stream));
+  BSGD_HIP(hipMemcpyAsync(res_norm2, st->partial + kReduceBlocks, sizeof(double),
+                          hipMemcpyDeviceToHost, stream));
+  BSGD_HIP(hipStreamSynchronize(stream));
+  *epochs_done = st->epochs_done;
+  if (!std::isfinite(*res_norm2)) {
+    set_error("residual norm is not finite after %lld epochs", (long long)st->epochs_done);
+    return BSGD_ERR_DIVERGED;
+  }
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_state_enable_timing(bsgd_state* st, int max_epochs) {
+  clear_error();
+  BSGD_REQUIRE(st != nullptr, "state is NULL");
+  BSGD_REQUIRE(max_epochs >= 0, "max_epochs must be >= 0");
+  destroy_timers(st);
+  st->tev.resize(5 * (size_t)max_epochs, nullptr);
+  for (auto& e : st->tev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      e = nullptr;
+      destroy_timers(st);
+      set_error("timer event creation failed: %s", hipGetErrorString(r));
+      return BSGD_ERR_HIP;
+    }
+  }
+  st->t_cap = max_epochs;
+  st->t_used = 0;
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_state_timing(bsgd_state* st, double* fwd_ms, double* bwd_ms,
+                                         double* prox_ms, int64_t* epochs_timed) {
+  clear_error();
+  BSGD_REQUIRE(st && fwd_ms && bwd_ms && prox_ms && epochs_timed, "NULL argument");
+  double f = 0, b = 0, x = 0;
+  for (int k = 0; k < st->t_used; ++k) {
+    hipEvent_t* e = &st->tev[5 * (size_t)k];
+    BSGD_HIP(hipEventSynchronize(e[4]));
+    BSGD_HIP(hipEventSynchronize(e[1]));
+    float ms = 0.f;
+    BSGD_HIP(hipEventElapsedTime(&ms, e[0], e[1]));
+    f += ms;
+    BSGD_HIP(hipEventElapsedTime(&ms, e[2], e[3]));
+    b += ms;
+    BSGD_HIP(hipEventElapsedTime(&ms, e[3], e[4]));
+    x += ms;
+  }
+  *fwd_ms = f;
+  *bwd_ms = b;
+  *prox_ms = x;
+  *epochs_timed = st->t_used;
+  st->t_used = 0;
+  return BSGD_OK;
+}

@@ -1,0 +1,30 @@
+"""Host-side marshalling: upload CSR arrays with torch and create a plan."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import capi
+
+
+def to_device(a, dtype, device="cuda") -> torch.Tensor:
+    """Copy a host array to the device with the given torch dtype."""
+    np_dtype = {torch.int64: np.int64, torch.int32: np.int32, torch.float32: np.float32}[dtype]
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np_dtype)).to(device)
+
+
+def plan_from_host(nrows, ncols, row_ptr, col, val, t_ptr, t_col, t_val, M, N, row_off, col_off,
+                   H, W, D=1, f16=False, device="cuda", stream=None) -> capi.Plan:
+    """Upload A and A^T (host CSR; values are rounded to FP32) and build the block store.
+
+    The uploaded copies are released once the plan is built; the plan keeps
+    only its own store.
+    """
+    A = (nrows, ncols, to_device(row_ptr, torch.int64, device), to_device(col, torch.int32, device),
+         to_device(val, torch.float32, device))
+    At = (ncols, nrows, to_device(t_ptr, torch.int64, device), to_device(t_col, torch.int32, device),
+          to_device(t_val, torch.float32, device))
+    flags = capi.BSGD_PLAN_F16 if f16 else 0
+    plan = capi.bsgd_plan_create(A, At, M, N, row_off, col_off, H, W, D, flags, stream=stream)
+    del A, At
+    return plan

@@ -1,0 +1,281 @@
+"""Device path vs the FP64 oracle, through the C ABI (needs a GPU)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import (ITERATE_REL, PRODUCT_REL, abs_matrix, f32, matrix, mu_for, plan_for,
+                         problem, ragged_problem, rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+CASES = ["c1", "ragged"]
+
+
+def _case(name):
+    return problem("c1_64") if name == "c1" else ragged_problem()
+
+
+# --------------------------------------------------------------------------
+# S0: block store
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", CASES)
+def test_tiles_bit_exact(name):
+    import paper_1812_01307_amd as bsgd
+    p = _case(name)
+    plan = plan_for(p)
+    val32 = f32(p.val).astype(np.float64)
+    for i in range(p.M):
+        for j in range(p.N):
+            ptr, lc, lv = oracle.tile(p.row_ptr, p.col, val32, p.row_off, p.col_off, i, j)
+            g_ptr, g_col, g_val = bsgd.bsgd_tile_export(plan, i, j)
+            torch.cuda.synchronize()
+            assert np.array_equal(g_ptr.cpu().numpy(), ptr)
+            assert np.array_equal(g_col.cpu().numpy(), lc)
+            assert np.array_equal(g_val.cpu().numpy().astype(np.float64), lv)
+            tptr, tcol, tval = oracle.tile_transpose(ptr, lc, lv, p.col_off[j + 1] - p.col_off[j])
+            g_ptr, g_col, g_val = bsgd.bsgd_tile_export(plan, i, j, transposed=True)
+            torch.cuda.synchronize()
+            assert np.array_equal(g_ptr.cpu().numpy(), tptr)
+            assert np.array_equal(g_col.cpu().numpy(), tcol)
+            assert np.array_equal(g_val.cpu().numpy().astype(np.float64), tval)
+
+
+# --------------------------------------------------------------------------
+# S1-S4: products
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("vt", [0, 1])
+def test_forward_and_backprojection(name, vt):
+    import paper_1812_01307_amd as bsgd
+    p = _case(name)
+    plan = plan_for(p, f16=(vt == 1))
+    A = matrix(p)
+    if vt == 1:
+        # the half-precision form is compared with the oracle on the
+        # FP16-rounded matrix (isolates the accumulation error)
+        A = oracle.as_matrix(p.row_ptr, p.col,
+                             p.val.astype(np.float32).astype(np.float16).astype(np.float64),
+                             p.ncols)
+    Aabs = abs_matrix(p)
+    rng = np.random.default_rng(5)
+    x = f32(rng.random(p.ncols))
+    r = f32(rng.standard_normal(p.nrows))
+    y = f32(rng.standard_normal(p.nrows))
+    mu = 1.7e-3
+    xd, rd, yd = _dev(x), _dev(r), _dev(y)
+    ax = _host(bsgd.bsgd_forward(plan, xd, vt=vt))
+    res = _host(bsgd.bsgd_forward(plan, xd, yd, vt=vt))
+    g = _host(bsgd.bsgd_backproject(plan, rd, vt=vt))
+    step = _host(bsgd.bsgd_backproject(plan, rd, xd, mu, vt=vt))
+    bound_f = PRODUCT_REL * (Aabs @ np.abs(x)) + 1e-30
+    bound_b = PRODUCT_REL * 2 * (Aabs.T @ np.abs(r)) + 1e-30
+    assert np.all(np.abs(ax - oracle.forward(A, x)) <= bound_f)
+    assert np.all(np.abs(res - (y - oracle.forward(A, x))) <= bound_f + 1e-7 * np.abs(y))
+    g_ref = oracle.backproject(A, r)
+    assert np.all(np.abs(g - g_ref) <= bound_b)
+    assert np.all(np.abs(step - (x + mu * g_ref)) <= mu * bound_b + 1e-7 * np.abs(x))
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_block_products(name):
+    import paper_1812_01307_amd as bsgd
+    p = _case(name)
+    plan = plan_for(p)
+    blocks = oracle.tiles(p.row_ptr, p.col, p.val, p.row_off, p.col_off)
+    rng = np.random.default_rng(6)
+    x = f32(rng.random(p.ncols))
+    r = f32(rng.standard_normal(p.nrows))
+    for i in range(p.M):
+        r0, r1 = p.row_off[i], p.row_off[i + 1]
+        for j in range(p.N):
+            c0, c1 = p.col_off[j], p.col_off[j + 1]
+            z = _host(bsgd.bsgd_forward_block(plan, i, j, _dev(x[c0:c1])))
+            zr = oracle.block_forward(blocks, p.row_off, p.col_off, i, j, x[c0:c1])
+            ptr, lc, lv = blocks[(i, j)]
+            Ab = oracle.as_matrix(ptr, lc, np.abs(lv), c1 - c0)
+            assert np.all(np.abs(z - zr) <= PRODUCT_REL * (Ab @ np.abs(x[c0:c1])) + 1e-30)
+            g = _host(bsgd.bsgd_backproject_block(plan, i, j, _dev(r[r0:r1])))
+            gr = oracle.block_backproject(blocks, p.row_off, p.col_off, i, j, r[r0:r1])
+            assert np.all(np.abs(g - gr) <= PRODUCT_REL * 2 * (Ab.T @ np.abs(r[r0:r1])) + 1e-30)
+
+
+# --------------------------------------------------------------------------
+# S5: TV prox and TV value
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(64, 64), (45, 67), (1, 37), (29, 1), (1, 1), (8, 40)])
+@pytest.mark.parametrize("theta,iters", [(0.05, 1), (0.05, 20), (0.5, 3), (1e-6, 20), (0.02, 100)])
+def test_tv_prox_matches_fgp(shape, theta, iters):
+    import paper_1812_01307_amd as bsgd
+    rng = np.random.default_rng(hash((shape, iters)) % 2 ** 32)
+    b = f32(rng.random(shape))
+    out = _host(bsgd.bsgd_tv_prox(_dev(b), theta, iters))
+    ref = oracle.fgp_prox2(b.astype(np.float64), theta, iters)
+    # correction theta D^T p is at most 4 theta per pixel; FP32 arithmetic on
+    # values of size ~1 plus the relative FP32 error of that correction
+    assert np.max(np.abs(out - ref)) <= 4e-6 + 1e-4 * 4 * theta
+
+
+def test_tv_prox_identity_cases_and_3d():
+    import paper_1812_01307_amd as bsgd
+    b = f32(np.random.default_rng(1).random((3, 20, 24)))
+    out = _host(bsgd.bsgd_tv_prox(_dev(b[0]), 0.0, 20))
+    assert np.array_equal(out, b[0].astype(np.float64))
+    out3 = _host(bsgd.bsgd_tv_prox(_dev(b), 0.05, 20))
+    ref3 = oracle.fgp_prox3(b.astype(np.float64), 0.05, 20)
+    assert np.max(np.abs(out3 - ref3)) <= 4e-6 + 1e-4 * 6 * 0.05
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (45, 67), (1, 9), (4, 16, 16)])
+def test_tv_value(shape):
+    import paper_1812_01307_amd as bsgd
+    x = f32(np.random.default_rng(2).random(shape))
+    tv = bsgd.bsgd_tv_value(_dev(x))
+    ref = oracle.tv2(x.astype(np.float64)) if len(shape) == 2 else oracle.tv3(x.astype(np.float64))
+    assert abs(tv - ref) <= 1e-12 * max(ref, 1.0)
+
+
+# --------------------------------------------------------------------------
+# S0': step size
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", CASES)
+def test_power_umax(name):
+    import paper_1812_01307_amd as bsgd
+    p = _case(name)
+    plan = plan_for(p)
+    u = bsgd.bsgd_power_umax(plan, 60)
+    ref = oracle.power_umax(matrix(p))
+    assert abs(u - ref) <= 1e-4 * ref
+
+
+# --------------------------------------------------------------------------
+# Whole epochs (Algorithm 1)
+# --------------------------------------------------------------------------
+
+def _trajectory(p, plan, mu, lam, epochs, K, vt=0):
+    import paper_1812_01307_amd as bsgd
+    st = bsgd.bsgd_state_create(plan, 1, vt)
+    bsgd.bsgd_state_init(st, _dev(f32(p.y)))
+    xs = []
+    for _ in range(epochs):
+        bsgd.bsgd_run_epochs(st, mu, lam, 1, K)
+        xs.append(_host(bsgd.bsgd_get_x(st)))
+    return xs, st
+
+
+@pytest.mark.parametrize("lam", [None, 0.0, 20.0, 200.0])
+def test_c1_trajectory_per_epoch(lam):
+    p = problem("c1_64")
+    lam = p.lam if lam is None else lam
+    plan = plan_for(p)
+    mu = mu_for(p)
+    A = matrix(p)
+    y32 = f32(p.y).astype(np.float64)
+    _, _, ref = oracle.bsgd_tv(A, y32, float(np.float32(mu)), lam, p.epochs, p.prox_iters,
+                               (p.H, p.W), record=True)
+    xs, _ = _trajectory(p, plan, mu, lam, p.epochs, p.prox_iters)
+    errs = [rel_l2(a, b) for a, b in zip(xs, ref)]
+    assert max(errs) <= ITERATE_REL, (max(errs), int(np.argmax(errs)))
+
+
+def test_ragged_trajectory():
+    p = ragged_problem()
+    plan = plan_for(p)
+    mu = mu_for(p)
+    y32 = f32(p.y).astype(np.float64)
+    _, _, ref = oracle.bsgd_tv(matrix(p), y32, float(np.float32(mu)), 5.0, 30, 20, (p.H, p.W),
+                               record=True)
+    xs, _ = _trajectory(p, plan, mu, 5.0, 30, 20)
+    assert max(rel_l2(a, b) for a, b in zip(xs, ref)) <= ITERATE_REL
+
+
+def test_runs_are_bitwise_reproducible_and_resume_is_exact():
+    import paper_1812_01307_amd as bsgd
+    p = problem("c1_64")
+    plan = plan_for(p)
+    mu = mu_for(p)
+    y = _dev(f32(p.y))
+    outs = []
+    for _ in range(2):
+        st = bsgd.bsgd_state_create(plan)
+        bsgd.bsgd_state_init(st, y)
+        bsgd.bsgd_run_epochs(st, mu, 20.0, 12, 20)
+        outs.append((_host(bsgd.bsgd_get_x(st)), _host(bsgd.bsgd_get_r(st))))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    st = bsgd.bsgd_state_create(plan)
+    bsgd.bsgd_state_init(st, y)
+    bsgd.bsgd_run_epochs(st, mu, 20.0, 5, 20)
+    xk, rk = bsgd.bsgd_get_x(st), bsgd.bsgd_get_r(st)
+    torch.cuda.synchronize()
+    st2 = bsgd.bsgd_state_create(plan)
+    bsgd.bsgd_state_init(st2, y)
+    bsgd.bsgd_state_load(st2, xk, rk, 5)
+    bsgd.bsgd_run_epochs(st2, mu, 20.0, 7, 20)
+    assert np.array_equal(_host(bsgd.bsgd_get_x(st2)), outs[0][0])
+    assert np.array_equal(_host(bsgd.bsgd_get_r(st2)), outs[0][1])
+    rn, ep, _ = bsgd.bsgd_get_stats(st2)
+    assert ep == 12 and abs(rn - float(np.sum(outs[0][1] ** 2))) <= 1e-9 * rn
+
+
+def test_divergence_is_reported():
+    """Far above the Theorem 1 bound the residual overflows and get_stats says so."""
+    import paper_1812_01307_amd as bsgd
+    p = problem("c1_64")
+    plan = plan_for(p)
+    u = oracle.power_umax(matrix(p))
+    st = bsgd.bsgd_state_create(plan)
+    bsgd.bsgd_state_init(st, _dev(f32(p.y)))
+    bsgd.bsgd_run_epochs(st, 8.0 / (2.0 * u), 0.0, 400, 0)
+    rn, ep, diverged = bsgd.bsgd_get_stats(st, allow_diverged=True)
+    assert diverged and ep == 400
+    with pytest.raises(bsgd.BsgdError):
+        bsgd.bsgd_get_stats(st)
+
+
+def test_invalid_inputs_are_rejected():
+    import paper_1812_01307_amd as bsgd
+    p = problem(None, n=8, n_ang=6, bins=13, M=2, N=2, seed=3)
+    tp, tc, tv = p.ensure_transpose()
+    bad_col = p.col.copy()
+    bad_col[5], bad_col[6] = bad_col[6], bad_col[5]          # unsorted row
+    with pytest.raises(bsgd.BsgdError, match="ascending"):
+        bsgd.plan_from_host(p.nrows, p.ncols, p.row_ptr, bad_col, p.val, tp, tc, tv, 2, 2,
+                            p.row_off, p.col_off, 8, 8)
+    bad_col = p.col.copy()
+    bad_col[-1] = p.ncols + 3                                 # column out of range
+    with pytest.raises(bsgd.BsgdError, match="range"):
+        bsgd.plan_from_host(p.nrows, p.ncols, p.row_ptr, bad_col, p.val, tp, tc, tv, 2, 2,
+                            p.row_off, p.col_off, 8, 8)
+    bad_ptr = p.row_ptr.copy()
+    bad_ptr[3] = bad_ptr[4] + 1                               # row_ptr not ascending
+    with pytest.raises(bsgd.BsgdError, match="row_ptr"):
+        bsgd.plan_from_host(p.nrows, p.ncols, bad_ptr, p.col, p.val, tp, tc, tv, 2, 2,
+                            p.row_off, p.col_off, 8, 8)
+    with pytest.raises(bsgd.BsgdError, match="shape"):
+        bsgd.plan_from_host(p.nrows, p.ncols, p.row_ptr, p.col, p.val, tp, tc, tv, 2, 2,
+                            p.row_off, p.col_off, 8, 9)
+    plan = plan_for(p)
+    st = bsgd.bsgd_state_create(plan)
+    with pytest.raises(bsgd.BsgdError, match="init"):
+        bsgd.bsgd_run_epochs(st, 1e-3, 0.0, 1, 0)
+    bsgd.bsgd_state_init(st, _dev(f32(p.y)))
+    with pytest.raises(bsgd.BsgdError, match="mu"):
+        bsgd.bsgd_run_epochs(st, -1.0, 0.0, 1, 0)
+    with pytest.raises(bsgd.BsgdError, match="prox_iters"):
+        bsgd.bsgd_run_epochs(st, 1e-3, 1.0, 1, 0)
+    with pytest.raises(bsgd.BsgdError, match="BSGD_PLAN_F16"):
+        bsgd.bsgd_forward(plan, _dev(f32(np.zeros(p.ncols))), vt=1)

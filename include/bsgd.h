@@ -54,7 +54,8 @@ typedef enum {
 typedef enum { BSGD_VAL_F32 = 0, BSGD_VAL_F16 = 1 } bsgd_valtype;
 
 /* Plan flags. */
-#define BSGD_PLAN_F16 1u /* also keep an FP16 (round-to-nearest-even) copy of the values */
+#define BSGD_PLAN_F16 1u      /* also keep an FP16 (round-to-nearest-even) copy of the values */
+#define BSGD_PLAN_AUTOTUNE 2u /* time the row kernels per store and keep the fastest launch */
 
 /*
  * A sparse matrix in CSR form, in device memory.  Columns must be strictly
@@ -79,10 +80,11 @@ typedef struct bsgd_state bsgd_state; /* iterate, residual and prox buffers (opa
 
 /*
  * Upper bound of the plan workspace for a matrix of this size (host only,
- * no device access).  flags as for bsgd_plan_create.
+ * no device access).  Arguments as for bsgd_plan_create.
  */
 bsgd_status bsgd_plan_workspace_size(int64_t nrows, int64_t ncols, int64_t nnz, int M, int N,
-                                     unsigned flags, size_t* bytes);
+                                     int H, int W, int D, int64_t view_len, unsigned flags,
+                                     size_t* bytes);
 
 /*
  * Build the block store of A (Section 2.1) in `workspace` (device, at least
@@ -97,6 +99,13 @@ bsgd_status bsgd_plan_workspace_size(int64_t nrows, int64_t ncols, int64_t nnz, 
  *   col_off host, N+1 ascending pixel offsets, col_off[N] = c: column block
  *           J_j = pixels [col_off[j], col_off[j+1]).
  *   H, W, D image shape with H*W*D = c (D = 1 for a 2-D image).
+ *   view_len number of consecutive rays that form one view (one projection
+ *           angle), or 0 if the rows have no such structure.  Only the
+ *           internal vector order depends on it (rays of 8 consecutive views
+ *           are interleaved bin by bin, pixels are stored in 8 x 8 tiles, so
+ *           the gathers of the products stay within few cache lines); every
+ *           vector crossing this interface is in natural order.
+ *   flags   BSGD_PLAN_F16 and/or BSGD_PLAN_AUTOTUNE.
  *
  * The store keeps every block A_{I_i}^{J_j} and its transpose addressable
  * (bsgd_tile_export) in a row-interleaved layout: the entries of ray rho for
@@ -108,10 +117,24 @@ bsgd_status bsgd_plan_workspace_size(int64_t nrows, int64_t ncols, int64_t nnz, 
  */
 bsgd_status bsgd_plan_create(const bsgd_csr* A, const bsgd_csr* At, int M, int N,
                              const int64_t* row_off, const int64_t* col_off, int H, int W, int D,
-                             unsigned flags, void* workspace, size_t workspace_bytes,
-                             hipStream_t stream, bsgd_plan** out);
+                             int64_t view_len, unsigned flags, void* workspace,
+                             size_t workspace_bytes, hipStream_t stream, bsgd_plan** out);
 
 void bsgd_plan_destroy(bsgd_plan* plan);
+
+/*
+ * Launch choice of the fused row kernels of the forward store (A) and the
+ * backward store (A^T): the number of lanes of a wavefront that share one
+ * row (2, 4, 8, 16, 32 or 64), or-ed with BSGD_LAUNCH_NT when the matrix
+ * streams are read with non-temporal loads.  Chosen from the mean row length
+ * (plain loads), or by timing every choice when the plan was created with
+ * BSGD_PLAN_AUTOTUNE; set_lanes overrides it (for instance with values an
+ * earlier autotuned plan of the same matrix reported).  Results change only
+ * by summation order.
+ */
+#define BSGD_LAUNCH_NT 128
+bsgd_status bsgd_plan_lanes(const bsgd_plan* plan, int* fwd_launch, int* bwd_launch);
+bsgd_status bsgd_plan_set_lanes(bsgd_plan* plan, int fwd_launch, int bwd_launch);
 
 /*
  * Number of stored entries of block (i, j) (identical for the block and its
@@ -130,7 +153,9 @@ bsgd_status bsgd_tile_export(const bsgd_plan* plan, int i, int j, int transposed
                              int32_t* col, float* val, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * Step-level products (Algorithm 1 lines 3, 4, 6, 7, 8)
+ * Step-level products (Algorithm 1 lines 3, 4, 6, 7, 8).  The whole-matrix
+ * calls stage their operands in the plan's scratch vectors, so calls on one
+ * plan must not overlap (serialise them on one stream).
  * ---------------------------------------------------------------------- */
 
 /*
@@ -245,6 +270,17 @@ bsgd_status bsgd_state_load(bsgd_state* state, const float* x, const float* r, i
  */
 bsgd_status bsgd_run_epochs(bsgd_state* state, float mu, float lam, int epochs, int prox_iters,
                             hipStream_t stream);
+
+/*
+ * Epoch schedule.  The forward pass (lines 4, 6) does not depend on the
+ * backprojection (lines 3, 7, 8) or the prox (line 9) of the same epoch
+ * (Eq. 3: line 3 uses the previous epoch's residual), so it runs on the
+ * state's second stream: mode 0 starts it together with the backprojection,
+ * mode 1 after the backprojection (it then overlaps the prox only; faster on
+ * MI355X since both passes are bandwidth-bound).  Results do not depend on
+ * the mode.  Default 1.
+ */
+bsgd_status bsgd_state_set_overlap(bsgd_state* state, int mode);
 
 /* Copy the current iterate x (c floats) / residual r (r floats) to device memory. */
 bsgd_status bsgd_get_x(const bsgd_state* state, float* x, hipStream_t stream);

@@ -27,6 +27,8 @@ BSGD_ERR_DIVERGED = -5
 BSGD_VAL_F32 = 0
 BSGD_VAL_F16 = 1
 BSGD_PLAN_F16 = 1
+BSGD_PLAN_AUTOTUNE = 2
+BSGD_LAUNCH_NT = 128
 
 _STATUS = {0: "OK", -1: "INVALID", -2: "WORKSPACE", -3: "HIP", -4: "UNSUPPORTED", -5: "DIVERGED"}
 
@@ -48,10 +50,13 @@ _i32 = ctypes.c_int
 _f32 = ctypes.c_float
 _sz = ctypes.c_size_t
 _PROTOS = {
-    "bsgd_plan_workspace_size": [_i64, _i64, _i64, _i32, _i32, ctypes.c_uint, ctypes.POINTER(_sz)],
+    "bsgd_plan_workspace_size": [_i64, _i64, _i64, _i32, _i32, _i32, _i32, _i32, _i64,
+                                 ctypes.c_uint, ctypes.POINTER(_sz)],
     "bsgd_plan_create": [ctypes.POINTER(bsgd_csr), ctypes.POINTER(bsgd_csr), _i32, _i32,
-                         ctypes.POINTER(_i64), ctypes.POINTER(_i64), _i32, _i32, _i32,
+                         ctypes.POINTER(_i64), ctypes.POINTER(_i64), _i32, _i32, _i32, _i64,
                          ctypes.c_uint, _vp, _sz, _vp, ctypes.POINTER(_vp)],
+    "bsgd_plan_lanes": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+    "bsgd_plan_set_lanes": [_vp, _i32, _i32],
     "bsgd_tile_nnz": [_vp, _i32, _i32, _vp, ctypes.POINTER(_i64)],
     "bsgd_tile_export": [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp],
     "bsgd_forward": [_vp, _i32, _vp, _vp, _vp, _vp],
@@ -72,6 +77,7 @@ _PROTOS = {
     "bsgd_get_r": [_vp, _vp, _vp],
     "bsgd_get_stats": [_vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)],
     "bsgd_state_enable_timing": [_vp, _i32],
+    "bsgd_state_set_overlap": [_vp, _i32],
     "bsgd_state_timing": [_vp] + [ctypes.POINTER(ctypes.c_double)] * 3 + [ctypes.POINTER(_i64)],
 }
 for _name, _args in _PROTOS.items():
@@ -149,14 +155,16 @@ class Plan:
             self.handle = None
 
 
-def bsgd_plan_workspace_size(nrows, ncols, nnz, M, N, flags=0) -> int:
+def bsgd_plan_workspace_size(nrows, ncols, nnz, M, N, H, W, D=1, view_len=0, flags=0) -> int:
     out = _sz()
     _check("bsgd_plan_workspace_size",
-           _lib.bsgd_plan_workspace_size(nrows, ncols, nnz, M, N, flags, ctypes.byref(out)))
+           _lib.bsgd_plan_workspace_size(nrows, ncols, nnz, M, N, H, W, D, view_len, flags,
+                                         ctypes.byref(out)))
     return out.value
 
 
-def bsgd_plan_create(A, At, M, N, row_off, col_off, H, W, D=1, flags=0, stream=None) -> Plan:
+def bsgd_plan_create(A, At, M, N, row_off, col_off, H, W, D=1, view_len=0, flags=0,
+                     stream=None) -> Plan:
     """A, At: (row_ptr int64, col int32, val float32) device tensor triples plus shapes.
 
     A = (nrows, ncols, row_ptr, col, val); At likewise for the transpose.
@@ -169,15 +177,25 @@ def bsgd_plan_create(A, At, M, N, row_off, col_off, H, W, D=1, flags=0, stream=N
             raise ValueError(f"CSR array has dtype {t.dtype}, expected {dt}")
     a = bsgd_csr(nrows, ncols, cl.numel(), _ptr(rp), _ptr(cl), _ptr(vl))
     at = bsgd_csr(tn, tc, tcl.numel(), _ptr(trp), _ptr(tcl), _ptr(tvl))
-    nbytes = bsgd_plan_workspace_size(nrows, ncols, cl.numel(), M, N, flags)
+    nbytes = bsgd_plan_workspace_size(nrows, ncols, cl.numel(), M, N, H, W, D, view_len, flags)
     ws = _ws(nbytes, rp.device)
     ro = (_i64 * (M + 1))(*[int(v) for v in row_off])
     co = (_i64 * (N + 1))(*[int(v) for v in col_off])
     h = _vp()
     _check("bsgd_plan_create", _lib.bsgd_plan_create(
-        ctypes.byref(a), ctypes.byref(at), M, N, ro, co, H, W, D, flags, _ptr(ws), nbytes,
-        _stream(stream), ctypes.byref(h)))
+        ctypes.byref(a), ctypes.byref(at), M, N, ro, co, H, W, D, view_len, flags, _ptr(ws),
+        nbytes, _stream(stream), ctypes.byref(h)))
     return Plan(h, ws, M, N, row_off, col_off, H, W, D, nrows, ncols, flags)
+
+
+def bsgd_plan_lanes(plan: Plan):
+    f, b = _i32(), _i32()
+    _check("bsgd_plan_lanes", _lib.bsgd_plan_lanes(plan.handle, ctypes.byref(f), ctypes.byref(b)))
+    return f.value, b.value
+
+
+def bsgd_plan_set_lanes(plan: Plan, fwd_lanes: int, bwd_lanes: int):
+    _check("bsgd_plan_set_lanes", _lib.bsgd_plan_set_lanes(plan.handle, fwd_lanes, bwd_lanes))
 
 
 def bsgd_tile_nnz(plan: Plan, i, j, stream=None) -> int:
@@ -400,3 +418,7 @@ def bsgd_state_timing(state: State):
     _check("bsgd_state_timing", _lib.bsgd_state_timing(state.handle, ctypes.byref(f), ctypes.byref(b),
                                                        ctypes.byref(x), ctypes.byref(n)))
     return f.value, b.value, x.value, n.value
+
+
+def bsgd_state_set_overlap(state: State, mode: int):
+    _check("bsgd_state_set_overlap", _lib.bsgd_state_set_overlap(state.handle, int(mode)))

@@ -17,6 +17,8 @@ namespace bsgd {
 // values are aligned and never straddle two rows.
 constexpr int kPad = 8;
 constexpr size_t kAlign = 256;
+constexpr int kViewTile = 8;  // views interleaved in the internal ray order
+constexpr int kPixTile = 8;   // 8 x 8 pixel tiles in the internal pixel order
 
 void set_error(const char* fmt, ...);
 void clear_error();
@@ -64,12 +66,62 @@ struct Carver {
   }
 };
 
+// Internal vector orders.  The sparse products gather x (by pixel) and r (by
+// ray); in the natural orders a steep ray touches a new cache line per pixel
+// and a pixel's rays are one view (view_len floats) apart.  Internally:
+//   pixels: 8 x 8 tiles of each slice, row-major inside a tile
+//           (a ray crossing a tile reads one 256-byte block);
+//   rays:   groups of kViewTile consecutive views interleaved bin by bin
+//           (the rays through one pixel over 8 views lie within a few lines).
+// Internal vectors have holes (ragged tiles / a last partial view group);
+// holes hold 0 and no stored entry refers to them.
+struct Layout {
+  int64_t nrows = 0, nviews = 0, view_len = 0, r_int = 0;
+  int H = 1, W = 1, D = 1, Ht = 1, Wt = 1;
+  int64_t c_int = 0;
+
+  __host__ __device__ int64_t ray_in(int64_t rho) const {
+    if (view_len == 0) return rho;
+    const int64_t a = rho / view_len, b = rho - a * view_len;
+    return (a / kViewTile) * (kViewTile * view_len) + b * kViewTile + (a % kViewTile);
+  }
+  __host__ __device__ int64_t ray_out(int64_t k) const {  // -1 for a hole
+    if (view_len == 0) return k < nrows ? k : -1;
+    const int64_t g = k / (kViewTile * view_len), rem = k - g * (kViewTile * view_len);
+    const int64_t a = g * kViewTile + rem % kViewTile, b = rem / kViewTile;
+    return a < nviews ? a * view_len + b : -1;
+  }
+  __host__ __device__ int64_t pix_st(int d, int s, int t) const {
+    return (int64_t)d * ((int64_t)Ht * Wt * 64) + ((int64_t)((s >> 3) * Wt + (t >> 3)) << 6) +
+           ((s & 7) << 3) + (t & 7);
+  }
+  __host__ __device__ int64_t pix_in(int64_t p) const {
+    const int64_t hw = (int64_t)H * W;
+    const int d = (int)(p / hw);
+    const int64_t rem = p - d * hw;
+    const int s = (int)(rem / W), t = (int)(rem - (int64_t)s * W);
+    return pix_st(d, s, t);
+  }
+  __host__ __device__ int64_t pix_out(int64_t k) const {  // -1 for a hole
+    const int64_t sl = (int64_t)Ht * Wt * 64;
+    const int d = (int)(k / sl);
+    const int64_t rem = k - d * sl;
+    const int tile = (int)(rem >> 6), w = (int)(rem & 63);
+    const int s = (tile / Wt) * 8 + (w >> 3), t = (tile % Wt) * 8 + (w & 7);
+    return (s < H && t < W) ? (int64_t)d * H * W + (int64_t)s * W + t : -1;
+  }
+};
+
+Layout make_layout(int64_t nrows, int64_t view_len, int H, int W, int D);
+
 // One direction of the block store: rows of A (rays, segments = column
-// blocks) or rows of A^T (pixels, segments = row blocks).  Row `row` holds
-// its entries in [ptr[row], ptr[row] + seg[row*(nseg+1) + nseg]) followed by
-// zero padding up to ptr[row+1]; segment k is the relative range
-// [seg[.. + k], seg[.. + k + 1]) and holds the columns in
-// [seg_off[k], seg_off[k+1]).
+// blocks) or rows of A^T (pixels, segments = row blocks), rows in internal
+// order.  Row `row` holds its entries in [ptr[row], ptr[row] + seg[row*(nseg+1)
+// + nseg]) followed by zero padding up to ptr[row+1]; segment k is the
+// relative range [seg[.. + k], seg[.. + k + 1]) and holds the entries whose
+// natural column lies in [seg_off[k], seg_off[k+1]).  Entries keep the
+// natural column order; their stored indices are internal (pixel or ray)
+// indices.
 struct Store {
   int64_t nrows = 0, ncols = 0, nnz = 0, cap = 0;
   int nseg = 0;
@@ -79,7 +131,8 @@ struct Store {
   float* val = nullptr;
   __half* val16 = nullptr;
   std::vector<int64_t> seg_off;   // host copy, nseg + 1 entries
-  int lanes_per_row = 64;         // launch choice for the fused row kernels
+  int lanes_per_row = 8;          // launch choice for the fused row kernels
+  bool nontemporal = false;       // non-temporal loads of the matrix streams
 };
 
 }  // namespace bsgd
@@ -87,13 +140,17 @@ struct Store {
 struct bsgd_plan {
   int M = 0, N = 0, H = 0, W = 0, D = 0;
   unsigned flags = 0;
-  bsgd::Store fwd;   // A
-  bsgd::Store bwd;   // A^T
+  bsgd::Layout L;
+  bsgd::Store fwd;   // A   (rows: internal ray order; columns: internal pixel indices)
+  bsgd::Store bwd;   // A^T (rows: internal pixel order; columns: internal ray indices)
   std::vector<int64_t> row_off, col_off;
-  int64_t* scratch64 = nullptr;   // max(nrows, ncols) + 1 entries (tile export)
+  int64_t* scratch64 = nullptr;   // max(r_int, c_int) + 1 entries (build, export)
   int64_t* scan_tmp = nullptr;    // block sums for scans
   int* err = nullptr;             // validation flags
   int64_t* seg_dev = nullptr;     // segment bounds staged for the fill kernel
+  float* vin = nullptr;           // max(r_int, c_int): permuted inputs of step-level calls
+  float* vaux = nullptr;          // max(r_int, c_int): second permuted input
+  float* vout = nullptr;          // max(r_int, c_int): outputs before un-permuting
 };
 
 namespace bsgd {
@@ -103,19 +160,28 @@ hipError_t exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_
                               hipStream_t s);
 size_t scan_tmp_count(int64_t n);
 
-// Fused row products over a whole store (all blocks):
+// Fused row products over a whole store (all blocks), internal orders:
 //   mode kPlain:    out = scale * (row . v)
 //   mode kResidual: out = y - row . v
 //   mode kStep:     out = xadd + scale * (row . v)
 enum RowMode { kPlain = 0, kResidual = 1, kStep = 2 };
 hipError_t launch_rows(const Store& st, bsgd_valtype vt, RowMode mode, const float* v,
                        const float* y, const float* xadd, float scale, float* out,
-                       hipStream_t s);
+                       hipStream_t s, int lanes = 0, int nt = -1);
 
-// Products of one segment (one block) of a store.
-hipError_t launch_segment_rows(const Store& st, bsgd_valtype vt, int64_t row0, int64_t nrows,
-                               int segk, int64_t col_base, const float* v, float scale,
-                               float* out, hipStream_t s);
+// Products of one segment (one block) of a store, natural orders in and out.
+hipError_t launch_segment_rows(const bsgd_plan* p, bool fwd, bsgd_valtype vt, int64_t nat_row0,
+                               int64_t nrows, int segk, int64_t col_base, const float* v,
+                               float scale, float* out, hipStream_t s);
+
+// Natural <-> internal vector orders (holes are written as 0).
+enum VecKind { kPixels = 0, kRays = 1 };
+hipError_t permute_in(const Layout& L, VecKind kind, const float* nat, float* internal,
+                      hipStream_t s);
+hipError_t permute_out(const Layout& L, VecKind kind, const float* internal, float* nat,
+                       hipStream_t s);
+// v = 1 on every pixel, 0 on holes (internal order)
+hipError_t fill_pixels_one(const Layout& L, float* v, hipStream_t s);
 
 // Deterministic sum of squares in FP64 (fixed grid, fixed order).
 constexpr int kReduceBlocks = 512;
@@ -123,9 +189,11 @@ hipError_t launch_sumsq(const float* x, int64_t n, double* partial, double* out,
 
 hipError_t fill_f32(float* x, int64_t n, float v, hipStream_t s);
 
-// FGP TV prox on device buffers; ws must hold tv_ws_floats(H, W, D) floats.
-size_t tv_ws_floats(int H, int W, int D);
-hipError_t tv_prox_run(int H, int W, int D, const float* b, float theta, int iters, float* out,
-                       float* ws, hipStream_t s);
+// FGP TV prox.  tiled = false: natural row-major image (H*W*D floats);
+// tiled = true: the internal pixel order of L (c_int floats).  ws must hold
+// tv_ws_floats(n) floats with n the vector length.
+size_t tv_ws_floats(int64_t n, int D);
+hipError_t tv_prox_run(const Layout& L, bool tiled, const float* b, float theta, int iters,
+                       float* out, float* ws, hipStream_t s);
 
 }  // namespace bsgd

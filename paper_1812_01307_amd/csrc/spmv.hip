@@ -6,9 +6,11 @@
 // sum_i g^i for a pixel (lines 3 and 7).  A group of LPR lanes of one
 // wavefront walks a row with 16-byte loads of column indices and values
 // (rows are padded to a multiple of 8 entries, so loads are aligned), gathers
-// the vector entries, and reduces across the group with cross-lane shuffles.
-// No atomics: every output element is written once by one lane, and the
-// summation order is fixed for a given LPR.
+// the vector entries (x or r, in the internal tiled orders, L2-resident), and
+// reduces across the group with cross-lane shuffles.  No atomics: every
+// output element is written once by one lane, and the summation order is
+// fixed for a given LPR.  Narrow groups (8 lanes on the 512^2 workload)
+// keep many rows in flight per wavefront and measured fastest on gfx950.
 #include "bsgd_internal.h"
 
 namespace bsgd {
@@ -17,13 +19,18 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
-template <typename T>
-__device__ __forceinline__ T stream_load(const T* p) {
-  return __builtin_nontemporal_load(p);
+// Matrix streams are read once per pass; NT = true marks the loads
+// non-temporal so they do not evict the gathered vector from L2.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld(const T* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
 }
 
 // Sum of val[e] * v[col[e]] over the lane's share of [beg, end).
-template <int LPR>
+template <int LPR, bool NT>
 __device__ __forceinline__ float row_dot_f32(const int32_t* __restrict__ col,
                                              const float* __restrict__ val,
                                              const float* __restrict__ v, int64_t beg, int64_t end,
@@ -32,10 +39,10 @@ __device__ __forceinline__ float row_dot_f32(const int32_t* __restrict__ col,
   int64_t e = beg + 4 * lane;
   // two chunks in flight per lane
   for (; e + 4 * LPR < end; e += 8 * LPR) {
-    const i32x4 c0 = stream_load(reinterpret_cast<const i32x4*>(col + e));
-    const f32x4 a0 = stream_load(reinterpret_cast<const f32x4*>(val + e));
-    const i32x4 c1 = stream_load(reinterpret_cast<const i32x4*>(col + e + 4 * LPR));
-    const f32x4 a1 = stream_load(reinterpret_cast<const f32x4*>(val + e + 4 * LPR));
+    const i32x4 c0 = ld<NT>(reinterpret_cast<const i32x4*>(col + e));
+    const f32x4 a0 = ld<NT>(reinterpret_cast<const f32x4*>(val + e));
+    const i32x4 c1 = ld<NT>(reinterpret_cast<const i32x4*>(col + e + 4 * LPR));
+    const f32x4 a1 = ld<NT>(reinterpret_cast<const f32x4*>(val + e + 4 * LPR));
     acc0 = fmaf(a0.x, v[c0.x], acc0);
     acc1 = fmaf(a1.x, v[c1.x], acc1);
     acc0 = fmaf(a0.y, v[c0.y], acc0);
@@ -46,8 +53,8 @@ __device__ __forceinline__ float row_dot_f32(const int32_t* __restrict__ col,
     acc1 = fmaf(a1.w, v[c1.w], acc1);
   }
   if (e < end) {
-    const i32x4 c0 = stream_load(reinterpret_cast<const i32x4*>(col + e));
-    const f32x4 a0 = stream_load(reinterpret_cast<const f32x4*>(val + e));
+    const i32x4 c0 = ld<NT>(reinterpret_cast<const i32x4*>(col + e));
+    const f32x4 a0 = ld<NT>(reinterpret_cast<const f32x4*>(val + e));
     acc0 = fmaf(a0.x, v[c0.x], acc0);
     acc0 = fmaf(a0.y, v[c0.y], acc0);
     acc0 = fmaf(a0.z, v[c0.z], acc0);
@@ -57,16 +64,16 @@ __device__ __forceinline__ float row_dot_f32(const int32_t* __restrict__ col,
 }
 
 // FP16 values: 8 entries per lane per chunk (32 B of columns, 16 B of values).
-template <int LPR>
+template <int LPR, bool NT>
 __device__ __forceinline__ float row_dot_f16(const int32_t* __restrict__ col,
                                              const __half* __restrict__ val,
                                              const float* __restrict__ v, int64_t beg, int64_t end,
                                              int lane) {
   float acc0 = 0.f, acc1 = 0.f;
   for (int64_t e = beg + 8 * lane; e < end; e += 8 * LPR) {
-    const i32x4 c0 = stream_load(reinterpret_cast<const i32x4*>(col + e));
-    const i32x4 c1 = stream_load(reinterpret_cast<const i32x4*>(col + e + 4));
-    const f16x8 a = stream_load(reinterpret_cast<const f16x8*>(val + e));
+    const i32x4 c0 = ld<NT>(reinterpret_cast<const i32x4*>(col + e));
+    const i32x4 c1 = ld<NT>(reinterpret_cast<const i32x4*>(col + e + 4));
+    const f16x8 a = ld<NT>(reinterpret_cast<const f16x8*>(val + e));
     acc0 = fmaf((float)a[0], v[c0.x], acc0);
     acc1 = fmaf((float)a[4], v[c1.x], acc1);
     acc0 = fmaf((float)a[1], v[c0.y], acc0);
@@ -86,7 +93,7 @@ __device__ __forceinline__ float group_sum(float x) {
   return x;
 }
 
-template <typename VT, int LPR, int MODE>
+template <typename VT, int LPR, int MODE, bool NT>
 __global__ __launch_bounds__(256) void k_rows(const int64_t* __restrict__ ptr,
                                               const int32_t* __restrict__ col,
                                               const VT* __restrict__ val,
@@ -101,9 +108,9 @@ __global__ __launch_bounds__(256) void k_rows(const int64_t* __restrict__ ptr,
   if (row < nrows) {
     const int64_t beg = ptr[row], end = ptr[row + 1];
     if constexpr (sizeof(VT) == 4)
-      acc = row_dot_f32<LPR>(col, reinterpret_cast<const float*>(val), v, beg, end, lane);
+      acc = row_dot_f32<LPR, NT>(col, reinterpret_cast<const float*>(val), v, beg, end, lane);
     else
-      acc = row_dot_f16<LPR>(col, reinterpret_cast<const __half*>(val), v, beg, end, lane);
+      acc = row_dot_f16<LPR, NT>(col, reinterpret_cast<const __half*>(val), v, beg, end, lane);
   }
   acc = group_sum<LPR>(acc);
   if (row < nrows && lane == 0) {
@@ -116,99 +123,119 @@ __global__ __launch_bounds__(256) void k_rows(const int64_t* __restrict__ ptr,
   }
 }
 
+template <typename VT, int MODE, int LPR>
+static void launch_lpr(const Store& st, bool nt, const VT* val, const float* v, const float* y,
+                       const float* xadd, float scale, float* out, hipStream_t s) {
+  const unsigned blocks = (unsigned)((st.nrows * LPR + 255) / 256);
+  if (!blocks) return;
+  if (nt)
+    k_rows<VT, LPR, MODE, true><<<blocks, 256, 0, s>>>(st.ptr, st.col, val, v, y, xadd, scale,
+                                                       out, st.nrows);
+  else
+    k_rows<VT, LPR, MODE, false><<<blocks, 256, 0, s>>>(st.ptr, st.col, val, v, y, xadd, scale,
+                                                        out, st.nrows);
+}
+
 template <typename VT, int MODE>
-static hipError_t launch_rows_vt(const Store& st, const VT* val, const float* v, const float* y,
-                                 const float* xadd, float scale, float* out, hipStream_t s) {
-  const int lpr = st.lanes_per_row;
-  const int64_t threads = st.nrows * lpr;
-  const unsigned blocks = (unsigned)((threads + 255) / 256);
-  if (blocks == 0) return hipSuccess;
-  switch (lpr) {
-    case 8:
-      k_rows<VT, 8, MODE><<<blocks, 256, 0, s>>>(st.ptr, st.col, val, v, y, xadd, scale, out,
-                                                 st.nrows);
-      break;
-    case 16:
-      k_rows<VT, 16, MODE><<<blocks, 256, 0, s>>>(st.ptr, st.col, val, v, y, xadd, scale, out,
-                                                  st.nrows);
-      break;
-    case 32:
-      k_rows<VT, 32, MODE><<<blocks, 256, 0, s>>>(st.ptr, st.col, val, v, y, xadd, scale, out,
-                                                  st.nrows);
-      break;
-    default:
-      k_rows<VT, 64, MODE><<<blocks, 256, 0, s>>>(st.ptr, st.col, val, v, y, xadd, scale, out,
-                                                  st.nrows);
-      break;
+static hipError_t launch_rows_vt(const Store& st, int lanes, bool nt, const VT* val,
+                                 const float* v, const float* y, const float* xadd, float scale,
+                                 float* out, hipStream_t s) {
+  switch (lanes) {
+    case 2: launch_lpr<VT, MODE, 2>(st, nt, val, v, y, xadd, scale, out, s); break;
+    case 4: launch_lpr<VT, MODE, 4>(st, nt, val, v, y, xadd, scale, out, s); break;
+    case 8: launch_lpr<VT, MODE, 8>(st, nt, val, v, y, xadd, scale, out, s); break;
+    case 16: launch_lpr<VT, MODE, 16>(st, nt, val, v, y, xadd, scale, out, s); break;
+    case 32: launch_lpr<VT, MODE, 32>(st, nt, val, v, y, xadd, scale, out, s); break;
+    default: launch_lpr<VT, MODE, 64>(st, nt, val, v, y, xadd, scale, out, s); break;
   }
   return hipGetLastError();
 }
 
 template <int MODE>
-static hipError_t launch_rows_mode(const Store& st, bsgd_valtype vt, const float* v,
-                                   const float* y, const float* xadd, float scale, float* out,
-                                   hipStream_t s) {
+static hipError_t launch_rows_mode(const Store& st, int lanes, bool nt, bsgd_valtype vt,
+                                   const float* v, const float* y, const float* xadd,
+                                   float scale, float* out, hipStream_t s) {
   if (vt == BSGD_VAL_F16)
-    return launch_rows_vt<__half, MODE>(st, st.val16, v, y, xadd, scale, out, s);
-  return launch_rows_vt<float, MODE>(st, st.val, v, y, xadd, scale, out, s);
+    return launch_rows_vt<__half, MODE>(st, lanes, nt, st.val16, v, y, xadd, scale, out, s);
+  return launch_rows_vt<float, MODE>(st, lanes, nt, st.val, v, y, xadd, scale, out, s);
 }
 
 hipError_t launch_rows(const Store& st, bsgd_valtype vt, RowMode mode, const float* v,
                        const float* y, const float* xadd, float scale, float* out,
-                       hipStream_t s) {
+                       hipStream_t s, int lanes, int nt) {
+  if (lanes <= 0) lanes = st.lanes_per_row;
+  const bool n = nt < 0 ? st.nontemporal : nt != 0;
   switch (mode) {
     case kPlain:
-      return launch_rows_mode<kPlain>(st, vt, v, y, xadd, scale, out, s);
+      return launch_rows_mode<kPlain>(st, lanes, n, vt, v, y, xadd, scale, out, s);
     case kResidual:
-      return launch_rows_mode<kResidual>(st, vt, v, y, xadd, scale, out, s);
+      return launch_rows_mode<kResidual>(st, lanes, n, vt, v, y, xadd, scale, out, s);
     default:
-      return launch_rows_mode<kStep>(st, vt, v, y, xadd, scale, out, s);
+      return launch_rows_mode<kStep>(st, lanes, n, vt, v, y, xadd, scale, out, s);
   }
 }
 
 // ---------------------------------------------------------------------------
-// One block's product: the entries of segment `segk` of rows
-// [row0, row0 + nrows), gathering v[col - col_base].  One wavefront per row,
-// scalar loads (used for per-block checks, not on the epoch path).
+// One block's product in natural orders: rows nat_row0 .. nat_row0+nrows-1
+// (rays of I_i, or pixels of J_j), the entries of segment `segk`, gathering
+// v[natural column - col_base].  One wavefront per row, scalar loads (used
+// for per-block checks, not on the epoch path).
 // ---------------------------------------------------------------------------
-template <typename VT>
+template <typename VT, bool FWD>
 __global__ __launch_bounds__(256) void k_segment_rows(
     const int64_t* __restrict__ ptr, const int32_t* __restrict__ seg, int nseg,
-    const int32_t* __restrict__ col, const VT* __restrict__ val, int64_t row0, int64_t nrows,
-    int segk, int64_t col_base, const float* __restrict__ v, float scale,
+    const int32_t* __restrict__ col, const VT* __restrict__ val, Layout L, int64_t row0,
+    int64_t nrows, int segk, int64_t col_base, const float* __restrict__ v, float scale,
     float* __restrict__ out) {
   const int64_t r = ((int64_t)blockIdx.x * 256 + threadIdx.x) / 64;
   const int lane = threadIdx.x & 63;
   float acc = 0.f;
   if (r < nrows) {
-    const int64_t row = row0 + r;
-    const int32_t* sg = seg + row * (nseg + 1);
-    const int64_t beg = ptr[row] + sg[segk], end = ptr[row] + sg[segk + 1];
-    for (int64_t e = beg + lane; e < end; e += 64)
-      acc = fmaf((float)val[e], v[col[e] - col_base], acc);
+    const int64_t k = FWD ? L.ray_in(row0 + r) : L.pix_in(row0 + r);
+    const int32_t* sg = seg + k * (nseg + 1);
+    const int64_t beg = ptr[k] + sg[segk], end = ptr[k] + sg[segk + 1];
+    for (int64_t e = beg + lane; e < end; e += 64) {
+      const int64_t nat = FWD ? L.pix_out(col[e]) : L.ray_out(col[e]);
+      acc = fmaf((float)val[e], v[nat - col_base], acc);
+    }
   }
   acc = group_sum<64>(acc);
   if (r < nrows && lane == 0) out[r] = scale * acc;
 }
 
-hipError_t launch_segment_rows(const Store& st, bsgd_valtype vt, int64_t row0, int64_t nrows,
-                               int segk, int64_t col_base, const float* v, float scale,
-                               float* out, hipStream_t s) {
+hipError_t launch_segment_rows(const bsgd_plan* p, bool fwd, bsgd_valtype vt, int64_t nat_row0,
+                               int64_t nrows, int segk, int64_t col_base, const float* v,
+                               float scale, float* out, hipStream_t s) {
   const unsigned blocks = (unsigned)((nrows * 64 + 255) / 256);
   if (blocks == 0) return hipSuccess;
-  if (vt == BSGD_VAL_F16)
-    k_segment_rows<__half><<<blocks, 256, 0, s>>>(st.ptr, st.seg, st.nseg, st.col, st.val16,
-                                                  row0, nrows, segk, col_base, v, scale, out);
-  else
-    k_segment_rows<float><<<blocks, 256, 0, s>>>(st.ptr, st.seg, st.nseg, st.col, st.val, row0,
-                                                 nrows, segk, col_base, v, scale, out);
+  const Store& st = fwd ? p->fwd : p->bwd;
+  if (fwd) {
+    if (vt == BSGD_VAL_F16)
+      k_segment_rows<__half, true><<<blocks, 256, 0, s>>>(st.ptr, st.seg, st.nseg, st.col,
+                                                          st.val16, p->L, nat_row0, nrows, segk,
+                                                          col_base, v, scale, out);
+    else
+      k_segment_rows<float, true><<<blocks, 256, 0, s>>>(st.ptr, st.seg, st.nseg, st.col, st.val,
+                                                         p->L, nat_row0, nrows, segk, col_base, v,
+                                                         scale, out);
+  } else {
+    if (vt == BSGD_VAL_F16)
+      k_segment_rows<__half, false><<<blocks, 256, 0, s>>>(st.ptr, st.seg, st.nseg, st.col,
+                                                           st.val16, p->L, nat_row0, nrows, segk,
+                                                           col_base, v, scale, out);
+    else
+      k_segment_rows<float, false><<<blocks, 256, 0, s>>>(st.ptr, st.seg, st.nseg, st.col,
+                                                          st.val, p->L, nat_row0, nrows, segk,
+                                                          col_base, v, scale, out);
+  }
   return hipGetLastError();
 }
 
 }  // namespace bsgd
 
 // ---------------------------------------------------------------------------
-// C ABI: step-level products
+// C ABI: step-level products (natural orders; the plan's scratch vectors
+// carry the permuted operands, so calls on one plan must not overlap)
 // ---------------------------------------------------------------------------
 using namespace bsgd;
 
@@ -224,35 +251,50 @@ static bsgd_status check_vt(const bsgd_plan* plan, bsgd_valtype vt) {
 
 extern "C" bsgd_status bsgd_forward(const bsgd_plan* plan, bsgd_valtype vt, const float* x,
                                     const float* y, float* out, hipStream_t stream) {
+  clear_error();
   bsgd_status st = check_vt(plan, vt);
   if (st != BSGD_OK) return st;
   BSGD_REQUIRE(x != nullptr && out != nullptr, "x and out must be non-NULL");
-  BSGD_HIP(launch_rows(plan->fwd, vt, y ? kResidual : kPlain, x, y, nullptr, 1.0f, out, stream));
+  const Layout& L = plan->L;
+  BSGD_HIP(permute_in(L, kPixels, x, plan->vin, stream));
+  if (y) BSGD_HIP(permute_in(L, kRays, y, plan->vaux, stream));
+  BSGD_HIP(launch_rows(plan->fwd, vt, y ? kResidual : kPlain, plan->vin, plan->vaux, nullptr,
+                       1.0f, plan->vout, stream));
+  BSGD_HIP(permute_out(L, kRays, plan->vout, out, stream));
   return BSGD_OK;
 }
 
 extern "C" bsgd_status bsgd_backproject(const bsgd_plan* plan, bsgd_valtype vt, const float* r,
                                         const float* x, float mu, float* out,
                                         hipStream_t stream) {
+  clear_error();
   bsgd_status st = check_vt(plan, vt);
   if (st != BSGD_OK) return st;
   BSGD_REQUIRE(r != nullptr && out != nullptr, "r and out must be non-NULL");
-  if (x)
-    BSGD_HIP(launch_rows(plan->bwd, vt, kStep, r, nullptr, x, 2.0f * mu, out, stream));
-  else
-    BSGD_HIP(launch_rows(plan->bwd, vt, kPlain, r, nullptr, nullptr, 2.0f, out, stream));
+  const Layout& L = plan->L;
+  BSGD_HIP(permute_in(L, kRays, r, plan->vin, stream));
+  if (x) {
+    BSGD_HIP(permute_in(L, kPixels, x, plan->vaux, stream));
+    BSGD_HIP(launch_rows(plan->bwd, vt, kStep, plan->vin, nullptr, plan->vaux, 2.0f * mu,
+                         plan->vout, stream));
+  } else {
+    BSGD_HIP(launch_rows(plan->bwd, vt, kPlain, plan->vin, nullptr, nullptr, 2.0f, plan->vout,
+                         stream));
+  }
+  BSGD_HIP(permute_out(L, kPixels, plan->vout, out, stream));
   return BSGD_OK;
 }
 
 extern "C" bsgd_status bsgd_forward_block(const bsgd_plan* plan, bsgd_valtype vt, int i, int j,
                                           const float* xj, float* z, hipStream_t stream) {
+  clear_error();
   bsgd_status st = check_vt(plan, vt);
   if (st != BSGD_OK) return st;
   BSGD_REQUIRE(i >= 0 && i < plan->M && j >= 0 && j < plan->N, "block (%d, %d) out of range", i,
                j);
   BSGD_REQUIRE(xj != nullptr && z != nullptr, "xj and z must be non-NULL");
   const int64_t r0 = plan->row_off[i], r1 = plan->row_off[i + 1];
-  BSGD_HIP(launch_segment_rows(plan->fwd, vt, r0, r1 - r0, j, plan->col_off[j], xj, 1.0f, z,
+  BSGD_HIP(launch_segment_rows(plan, true, vt, r0, r1 - r0, j, plan->col_off[j], xj, 1.0f, z,
                                stream));
   return BSGD_OK;
 }
@@ -260,13 +302,14 @@ extern "C" bsgd_status bsgd_forward_block(const bsgd_plan* plan, bsgd_valtype vt
 extern "C" bsgd_status bsgd_backproject_block(const bsgd_plan* plan, bsgd_valtype vt, int i,
                                               int j, const float* ri, float* g,
                                               hipStream_t stream) {
+  clear_error();
   bsgd_status st = check_vt(plan, vt);
   if (st != BSGD_OK) return st;
   BSGD_REQUIRE(i >= 0 && i < plan->M && j >= 0 && j < plan->N, "block (%d, %d) out of range", i,
                j);
   BSGD_REQUIRE(ri != nullptr && g != nullptr, "ri and g must be non-NULL");
   const int64_t c0 = plan->col_off[j], c1 = plan->col_off[j + 1];
-  BSGD_HIP(launch_segment_rows(plan->bwd, vt, c0, c1 - c0, i, plan->row_off[i], ri, 2.0f, g,
+  BSGD_HIP(launch_segment_rows(plan, false, vt, c0, c1 - c0, i, plan->row_off[i], ri, 2.0f, g,
                                stream));
   return BSGD_OK;
 }

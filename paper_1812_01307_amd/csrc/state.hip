@@ -25,6 +25,7 @@ struct bsgd_state {
   float* tv_ws = nullptr;
   double* partial = nullptr;  // kReduceBlocks + 1 (last = result)
   int cur = 0;
+  int overlap = 1;  // 0: forward pass concurrent with backprojection + prox; 1: with the prox only
   int64_t epochs_done = 0;
   bool initialised = false;
   hipStream_t aux = nullptr;
@@ -56,25 +57,26 @@ __global__ void k_ratio(const double* __restrict__ num, const double* __restrict
 static size_t power_layout(const bsgd_plan* p, void* ws, float** v, float** z, float** w,
                            double** part, double** sc, float** res) {
   Carver cv(ws);
-  *v = cv.take<float>(p->fwd.ncols);
-  *w = cv.take<float>(p->fwd.ncols);
-  *z = cv.take<float>(p->fwd.nrows);
+  *v = cv.take<float>(p->L.c_int);
+  *w = cv.take<float>(p->L.c_int);
+  *z = cv.take<float>(p->L.r_int);
   *part = cv.take<double>(kReduceBlocks);
   *sc = cv.take<double>(4);
   *res = cv.take<float>(4);
   return align_up(cv.off, kAlign);
 }
 
+// All state vectors are in the plan's internal orders (see bsgd::Layout).
 static size_t state_layout(const bsgd_plan* p, void* ws, bsgd_state* st) {
   Carver cv(ws);
-  const int64_t r = p->fwd.nrows, c = p->fwd.ncols;
+  const int64_t r = p->L.r_int, c = p->L.c_int;
   st->y = cv.take<float>(r);
   st->x[0] = cv.take<float>(c);
   st->x[1] = cv.take<float>(c);
   st->r[0] = cv.take<float>(r);
   st->r[1] = cv.take<float>(r);
   st->xhat = cv.take<float>(c);
-  st->tv_ws = cv.take<float>(tv_ws_floats(p->H, p->W, p->D));
+  st->tv_ws = cv.take<float>(tv_ws_floats(c, p->D));
   st->partial = cv.take<double>(kReduceBlocks + 1);
   return align_up(cv.off, kAlign);
 }
@@ -107,8 +109,8 @@ extern "C" bsgd_status bsgd_power_umax(const bsgd_plan* plan, bsgd_valtype vt, i
     set_error("power workspace has %zu bytes, needs %zu", ws_bytes, need);
     return BSGD_ERR_WORKSPACE;
   }
-  const int64_t c = plan->fwd.ncols, r = plan->fwd.nrows;
-  BSGD_HIP(fill_f32(v, c, 1.0f, stream));
+  const int64_t c = plan->L.c_int, r = plan->L.r_int;
+  BSGD_HIP(fill_pixels_one(plan->L, v, stream));
   for (int it = 0; it < iters; ++it) {
     BSGD_HIP(launch_rows(plan->fwd, vt, kPlain, v, nullptr, nullptr, 1.0f, z, stream));  // A v
     BSGD_HIP(launch_rows(plan->bwd, vt, kPlain, z, nullptr, nullptr, 1.0f, w, stream));  // A^T A v
@@ -192,11 +194,14 @@ extern "C" bsgd_status bsgd_state_init(bsgd_state* st, const float* y, const flo
   clear_error();
   BSGD_REQUIRE(st && y, "NULL argument");
   const bsgd_plan* p = st->plan;
-  const int64_t r = p->fwd.nrows, c = p->fwd.ncols;
-  BSGD_HIP(hipMemcpyAsync(st->y, y, sizeof(float) * r, hipMemcpyDeviceToDevice, stream));
+  const int64_t r = p->L.r_int, c = p->L.c_int;
+  BSGD_HIP(permute_in(p->L, kRays, y, st->y, stream));
   st->cur = 0;
+  BSGD_HIP(fill_f32(st->x[1], c, 0.0f, stream));
+  BSGD_HIP(fill_f32(st->xhat, c, 0.0f, stream));
+  BSGD_HIP(fill_f32(st->r[1], r, 0.0f, stream));
   if (x0) {
-    BSGD_HIP(hipMemcpyAsync(st->x[0], x0, sizeof(float) * c, hipMemcpyDeviceToDevice, stream));
+    BSGD_HIP(permute_in(p->L, kPixels, x0, st->x[0], stream));
     BSGD_HIP(launch_rows(p->fwd, st->vt, kResidual, st->x[0], st->y, nullptr, 1.0f, st->r[0],
                          stream));
   } else {
@@ -216,10 +221,8 @@ extern "C" bsgd_status bsgd_state_load(bsgd_state* st, const float* x, const flo
   BSGD_REQUIRE(epoch >= 0, "epoch must be >= 0");
   const bsgd_plan* p = st->plan;
   st->cur = 0;
-  BSGD_HIP(hipMemcpyAsync(st->x[0], x, sizeof(float) * p->fwd.ncols, hipMemcpyDeviceToDevice,
-                          stream));
-  BSGD_HIP(hipMemcpyAsync(st->r[0], r, sizeof(float) * p->fwd.nrows, hipMemcpyDeviceToDevice,
-                          stream));
+  BSGD_HIP(permute_in(p->L, kPixels, x, st->x[0], stream));
+  BSGD_HIP(permute_in(p->L, kRays, r, st->r[0], stream));
   st->epochs_done = epoch;
   return BSGD_OK;
 }
@@ -238,25 +241,23 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
   for (int e = 0; e < epochs; ++e) {
     const int c = st->cur, n = 1 - c;
     hipEvent_t* tv = st->t_used < st->t_cap ? &st->tev[5 * (size_t)st->t_used++] : nullptr;
-    // S1 on the aux stream, after everything already queued on `stream`
-    BSGD_HIP(hipEventRecord(st->ev_main, stream));
+    // S2 (+S4) on `stream`; S1 on the aux stream after everything queued on
+    // `stream` before this epoch (overlap 0) or after S2 (overlap 1)
+    if (st->overlap == 0) BSGD_HIP(hipEventRecord(st->ev_main, stream));
+    if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
+    BSGD_HIP(launch_rows(p->bwd, st->vt, kStep, st->r[c], nullptr, st->x[c], 2.0f * mu,
+                         theta == 0.f ? st->x[n] : st->xhat, stream));
+    if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
+    if (st->overlap == 1) BSGD_HIP(hipEventRecord(st->ev_main, stream));
     BSGD_HIP(hipStreamWaitEvent(st->aux, st->ev_main, 0));
     if (tv) BSGD_HIP(hipEventRecord(tv[0], st->aux));
     BSGD_HIP(launch_rows(p->fwd, st->vt, kResidual, st->x[c], st->y, nullptr, 1.0f, st->r[n],
                          st->aux));
     if (tv) BSGD_HIP(hipEventRecord(tv[1], st->aux));
     BSGD_HIP(hipEventRecord(st->ev_aux, st->aux));
-    // S2 (+S4) then S5 on `stream`
-    if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
-    if (theta == 0.f) {
-      BSGD_HIP(launch_rows(p->bwd, st->vt, kStep, st->r[c], nullptr, st->x[c], 2.0f * mu,
-                           st->x[n], stream));
-      if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
-    } else {
-      BSGD_HIP(launch_rows(p->bwd, st->vt, kStep, st->r[c], nullptr, st->x[c], 2.0f * mu,
-                           st->xhat, stream));
-      if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
-      BSGD_HIP(tv_prox_run(p->H, p->W, p->D, st->xhat, theta, prox_iters, st->x[n], st->tv_ws,
+    // S5 on `stream`
+    if (theta != 0.f) {
+      BSGD_HIP(tv_prox_run(p->L, true, st->xhat, theta, prox_iters, st->x[n], st->tv_ws,
                            stream));
     }
     if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));
@@ -270,16 +271,14 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
 extern "C" bsgd_status bsgd_get_x(const bsgd_state* st, float* x, hipStream_t stream) {
   clear_error();
   BSGD_REQUIRE(st && x, "NULL argument");
-  BSGD_HIP(hipMemcpyAsync(x, st->x[st->cur], sizeof(float) * st->plan->fwd.ncols,
-                          hipMemcpyDeviceToDevice, stream));
+  BSGD_HIP(permute_out(st->plan->L, kPixels, st->x[st->cur], x, stream));
   return BSGD_OK;
 }
 
 extern "C" bsgd_status bsgd_get_r(const bsgd_state* st, float* r, hipStream_t stream) {
   clear_error();
   BSGD_REQUIRE(st && r, "NULL argument");
-  BSGD_HIP(hipMemcpyAsync(r, st->r[st->cur], sizeof(float) * st->plan->fwd.nrows,
-                          hipMemcpyDeviceToDevice, stream));
+  BSGD_HIP(permute_out(st->plan->L, kRays, st->r[st->cur], r, stream));
   return BSGD_OK;
 }
 
@@ -287,7 +286,7 @@ extern "C" bsgd_status bsgd_get_stats(const bsgd_state* st, hipStream_t stream, 
                                       int64_t* epochs_done) {
   clear_error();
   BSGD_REQUIRE(st && res_norm2 && epochs_done, "NULL argument");
-  BSGD_HIP(launch_sumsq(st->r[st->cur], st->plan->fwd.nrows, st->partial,
+  BSGD_HIP(launch_sumsq(st->r[st->cur], st->plan->L.r_int, st->partial,
                         st->partial + kReduceBlocks, stream));
   BSGD_HIP(hipMemcpyAsync(res_norm2, st->partial + kReduceBlocks, sizeof(double),
                           hipMemcpyDeviceToHost, stream));
@@ -342,5 +341,13 @@ extern "C" bsgd_status bsgd_state_timing(bsgd_state* st, double* fwd_ms, double*
   *prox_ms = x;
   *epochs_timed = st->t_used;
   st->t_used = 0;
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_state_set_overlap(bsgd_state* st, int mode) {
+  clear_error();
+  BSGD_REQUIRE(st != nullptr, "state is NULL");
+  BSGD_REQUIRE(mode == 0 || mode == 1, "overlap mode must be 0 or 1");
+  st->overlap = mode;
   return BSGD_OK;
 }

@@ -9,14 +9,15 @@
 //     u_k     = b - theta D^T q_k
 //     p_k     = P(q_k + D u_k / (8 theta))          (P: unit-disk projection)
 // with tau_1 = 1, tau_{k+1} = (1 + sqrt(1 + 4 tau_k^2)) / 2 and q_1 = 0; the
-// result is b - theta D^T p_K.
+// result is b - theta D^T p_K.  Volumes (D > 1 slices) add the difference
+// across slices, project onto the unit ball of R^3 and step 1/(12 theta).
 //
-// One kernel per iteration: a 32 x 8 tile of output pixels stages q on the
-// tile plus a one-pixel halo and u on the tile plus its upper/left halo in
-// LDS, so each input element is read from memory (L2 for these image-sized
-// buffers) once per iteration.  The dual lives in three rotating buffer
-// pairs (pv, ph); nothing needs zero-initialising because iteration 1 takes
-// q = 0 and iteration 2 takes q = p_1 without reading p_0.
+// 2-D: up to 20 iterations per launch (k_fgp_fused2, below): a 32 x 32
+// output tile plus a halo one pixel wider than the iteration count lives in
+// LDS, and the halo is recomputed rather than exchanged.  Nothing needs zero-initialising: iteration 1 takes q = 0 and iteration 2
+// takes q = p_1 without reading p_0.  Images are addressed either in natural
+// row-major order or in the library's internal 8 x 8-tiled pixel order.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -24,95 +25,186 @@
 
 namespace bsgd {
 
-constexpr int kTW = 32;  // tile width (columns)
-constexpr int kTH = 8;   // tile height (rows)
-
 enum QMode { kQZero = 0, kQCopy = 1, kQMomentum = 2 };
 
-__global__ __launch_bounds__(kTW* kTH) void k_fgp_iter2(
-    int H, int W, const float* __restrict__ b, float theta, float step, float coef, int qmode,
-    const float* __restrict__ p1v, const float* __restrict__ p1h, const float* __restrict__ p2v,
-    const float* __restrict__ p2h, float* __restrict__ ov, float* __restrict__ oh) {
-  __shared__ float sqv[kTH + 2][kTW + 2];
-  __shared__ float sqh[kTH + 2][kTW + 2];
-  __shared__ float su[kTH + 1][kTW + 1];
-  const int s0 = blockIdx.y * kTH, t0 = blockIdx.x * kTW;
-  const int tid = threadIdx.y * kTW + threadIdx.x;
+template <bool TILED>
+__device__ __forceinline__ int64_t pidx(const Layout& L, int d, int s, int t) {
+  if constexpr (TILED)
+    return L.pix_st(d, s, t);
+  else
+    return ((int64_t)d * L.H + s) * L.W + t;
+}
 
-  // q on rows s0-1 .. s0+kTH, columns t0-1 .. t0+kTW (zero outside the image)
-  for (int k = tid; k < (kTH + 2) * (kTW + 2); k += kTW * kTH) {
-    const int ls = k / (kTW + 2), lt = k % (kTW + 2);
-    const int s = s0 - 1 + ls, t = t0 - 1 + lt;
-    float qv = 0.f, qh = 0.f;
-    if (qmode != kQZero && s >= 0 && s < H && t >= 0 && t < W) {
-      const size_t i = (size_t)s * W + t;
-      const float av = p1v[i], ah = p1h[i];
-      if (qmode == kQCopy) {
-        qv = av;
-        qh = ah;
-      } else {
-        qv = fmaf(coef, av - p2v[i], av);
-        qh = fmaf(coef, ah - p2h[i], ah);
+// ---------------------------------------------------------------------------
+// Fused 2-D FGP: up to kFuseMax iterations in one launch.  Each block owns a
+// kFT x kFT output tile and keeps b and the last two duals on the tile plus a
+// halo of (iterations + 1) pixels in LDS.  Every iteration shrinks the region
+// on which the duals are exact by one pixel per side (D and D^T are one-pixel
+// stencils), so after L iterations the tile and one extra row/column are
+// exact; the halo work is recomputed redundantly by neighbouring blocks
+// instead of exchanged.  Pixels outside the image are held at zero and the
+// same boundary rules as the per-iteration kernel apply, so the arithmetic
+// per pixel is the same.
+// ---------------------------------------------------------------------------
+constexpr int kFT = 32;
+constexpr int kFuseMax = 20;
+constexpr int kFR = kFT + 2 * (kFuseMax + 1);  // 74
+constexpr int kFThreads = 512;
+
+struct FuseArgs {
+  float coef[kFuseMax + 1];  // coef[m] = c_{k0+m}
+};
+
+template <bool TILED>
+__global__ __launch_bounds__(kFThreads) void k_fgp_fused2(
+    Layout L, const float* __restrict__ b, float theta, float step, int k0, int iters,
+    FuseArgs ca, const float* __restrict__ in1v, const float* __restrict__ in1h,
+    const float* __restrict__ in2v, const float* __restrict__ in2h, float* __restrict__ out_x,
+    float* __restrict__ o1v, float* __restrict__ o1h, float* __restrict__ o2v,
+    float* __restrict__ o2h) {
+  __shared__ float sb[kFR * kFR];
+  __shared__ float sav[kFR * kFR], sah[kFR * kFR];  // dual slot A
+  __shared__ float sbv[kFR * kFR], sbh[kFR * kFR];  // dual slot B
+  __shared__ float su[kFR * kFR];
+  const int H = L.H, W = L.W;
+  const int h = iters + 1;
+  const int R = kFT + 2 * h;
+  const int s0 = blockIdx.y * kFT - h, t0 = blockIdx.x * kFT - h;  // image coords of LDS (0,0)
+  const int tid = threadIdx.x;
+
+  // load b and the incoming duals (p_{k0} -> slot A, p_{k0-1} -> slot B)
+  for (int q = tid; q < R * R; q += kFThreads) {
+    const int ls = q / R, lt = q - ls * R;
+    const int s = s0 + ls, t = t0 + lt;
+    float vb = 0.f, a1 = 0.f, a2 = 0.f, b1 = 0.f, b2 = 0.f;
+    if (s >= 0 && s < H && t >= 0 && t < W) {
+      const int64_t i = pidx<TILED>(L, 0, s, t);
+      vb = b[i];
+      if (k0 >= 1) {
+        a1 = in1v[i];
+        a2 = in1h[i];
+      }
+      if (k0 >= 2) {
+        b1 = in2v[i];
+        b2 = in2h[i];
       }
     }
-    sqv[ls][lt] = qv;
-    sqh[ls][lt] = qh;
+    const int o = ls * kFR + lt;
+    sb[o] = vb;
+    sav[o] = a1;
+    sah[o] = a2;
+    sbv[o] = b1;
+    sbh[o] = b2;
   }
   __syncthreads();
 
-  // u = b - theta D^T q on rows s0-1 .. s0+kTH-1, columns t0-1 .. t0+kTW-1
-  for (int k = tid; k < (kTH + 1) * (kTW + 1); k += kTW * kTH) {
-    const int ls = k / (kTW + 1), lt = k % (kTW + 1);
-    const int s = s0 - 1 + ls, t = t0 - 1 + lt;
-    float u = 0.f;
-    if (s >= 0 && s < H && t >= 0 && t < W) {
-      // D^T q at (s, t): qv(s,t) - qv(s+1,t) + qh(s,t) - qh(s,t+1)
-      const float dtq = (sqv[ls][lt] - sqv[ls + 1][lt]) + (sqh[ls][lt] - sqh[ls][lt + 1]);
-      u = b[(size_t)s * W + t] - theta * dtq;
+  float* p1v = sav;  // p_{k-1}
+  float* p1h = sah;
+  float* p2v = sbv;  // p_{k-2}
+  float* p2h = sbh;
+  for (int m = 1; m <= iters; ++m) {
+    const int k = k0 + m;
+    const int qm = k == 1 ? kQZero : (k == 2 ? kQCopy : kQMomentum);
+    const float coef = ca.coef[m];
+    // q at an LDS offset from the two dual slots
+    auto qv_at = [&](int o) {
+      return qm == kQZero ? 0.f : (qm == kQCopy ? p1v[o] : fmaf(coef, p1v[o] - p2v[o], p1v[o]));
+    };
+    auto qh_at = [&](int o) {
+      return qm == kQZero ? 0.f : (qm == kQCopy ? p1h[o] : fmaf(coef, p1h[o] - p2h[o], p1h[o]));
+    };
+    // u on [m-1, R-m) x [m-1, R-m)
+    {
+      const int lo = m - 1, wdt = R - m - lo;
+      for (int q = tid; q < wdt * wdt; q += kFThreads) {
+        const int ls = lo + q / wdt, lt = lo + q % wdt;
+        const int s = s0 + ls, t = t0 + lt;
+        float u = 0.f;
+        if (s >= 0 && s < H && t >= 0 && t < W) {
+          const int o = ls * kFR + lt;
+          const float dtq = (qv_at(o) - qv_at(o + kFR)) + (qh_at(o) - qh_at(o + 1));
+          u = sb[o] - theta * dtq;
+        }
+        su[ls * kFR + lt] = u;
+      }
     }
-    su[ls][lt] = u;
+    __syncthreads();
+    // p_k on [m, R-m) x [m, R-m), written over p_{k-2}
+    {
+      const int lo = m, wdt = R - m - lo;
+      for (int q = tid; q < wdt * wdt; q += kFThreads) {
+        const int ls = lo + q / wdt, lt = lo + q % wdt;
+        const int s = s0 + ls, t = t0 + lt;
+        if (s >= 0 && s < H && t >= 0 && t < W) {
+          const int o = ls * kFR + lt;
+          const float uc = su[o];
+          const float gv = s >= 1 ? uc - su[o - kFR] : 0.f;
+          const float gh = t >= 1 ? uc - su[o - 1] : 0.f;
+          const float av = fmaf(step, gv, qv_at(o));
+          const float ah = fmaf(step, gh, qh_at(o));
+          const float nrm = fmaxf(1.f, sqrtf(av * av + ah * ah));
+          p2v[o] = av / nrm;
+          p2h[o] = ah / nrm;
+        }
+      }
+    }
+    __syncthreads();
+    float* tv = p1v;
+    float* th = p1h;
+    p1v = p2v;
+    p1h = p2h;
+    p2v = tv;
+    p2h = th;
   }
-  __syncthreads();
 
-  const int s = s0 + threadIdx.y, t = t0 + threadIdx.x;
-  if (s < H && t < W) {
-    const int ls = threadIdx.y + 1, lt = threadIdx.x + 1;
-    const float uc = su[ls][lt];
-    const float gv = s >= 1 ? uc - su[ls - 1][lt] : 0.f;
-    const float gh = t >= 1 ? uc - su[ls][lt - 1] : 0.f;
-    const float av = fmaf(step, gv, sqv[ls][lt]);
-    const float ah = fmaf(step, gh, sqh[ls][lt]);
-    const float nrm = fmaxf(1.f, sqrtf(av * av + ah * ah));
-    const size_t i = (size_t)s * W + t;
-    ov[i] = av / nrm;
-    oh[i] = ah / nrm;
+  // outputs on the kFT x kFT tile
+  for (int q = tid; q < kFT * kFT; q += kFThreads) {
+    const int ls = h + q / kFT, lt = h + q % kFT;
+    const int s = s0 + ls, t = t0 + lt;
+    if (s >= H || t >= W) continue;
+    const int o = ls * kFR + lt;
+    const int64_t i = pidx<TILED>(L, 0, s, t);
+    if (out_x) {
+      const float dn = s + 1 < H ? p1v[o + kFR] : 0.f;
+      const float rt = t + 1 < W ? p1h[o + 1] : 0.f;
+      const float dtp = (p1v[o] - dn) + (p1h[o] - rt);
+      out_x[i] = sb[o] - theta * dtp;
+    } else {
+      o1v[i] = p1v[o];
+      o1h[i] = p1h[o];
+      o2v[i] = p2v[o];
+      o2h[i] = p2h[o];
+    }
   }
 }
 
-// out = b - theta D^T p
-__global__ __launch_bounds__(256) void k_fgp_out2(int H, int W, const float* __restrict__ b,
+// out = b - theta D^T p (2-D)
+template <bool TILED>
+__global__ __launch_bounds__(256) void k_fgp_out2(Layout L, const float* __restrict__ b,
                                                   float theta, const float* __restrict__ pv,
                                                   const float* __restrict__ ph,
                                                   float* __restrict__ out) {
+  const int H = L.H, W = L.W;
   const int64_t n = (int64_t)H * W;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * 256) {
     const int s = (int)(i / W), t = (int)(i % W);
-    const float dn = s + 1 < H ? pv[i + W] : 0.f;
-    const float rt = t + 1 < W ? ph[i + 1] : 0.f;
-    const float dtp = (pv[i] - dn) + (ph[i] - rt);
-    out[i] = b[i] - theta * dtp;
+    const int64_t c = pidx<TILED>(L, 0, s, t);
+    const float dn = s + 1 < H ? pv[pidx<TILED>(L, 0, s + 1, t)] : 0.f;
+    const float rt = t + 1 < W ? ph[pidx<TILED>(L, 0, s, t + 1)] : 0.f;
+    const float dtp = (pv[c] - dn) + (ph[c] - rt);
+    out[c] = b[c] - theta * dtp;
   }
 }
 
-// 3-D: D x H x W volume, dual (pd, pv, ph), step 1/(12 theta).  One kernel
-// per iteration without LDS staging (neighbour reads hit the caches).
-// q = momentum combination of the last two duals (three planes each).
-__global__ __launch_bounds__(256) void k_fgp_q3(int64_t n, float coef, int qmode,
+// 3-D (D slices): q = momentum combination of the last two duals (3 planes
+// of length n each, element-wise, so the order of the planes' elements does
+// not matter).
+__global__ __launch_bounds__(256) void k_fgp_q3(int64_t n3, float coef, int qmode,
                                                 const float* __restrict__ p1,
                                                 const float* __restrict__ p2,
                                                 float* __restrict__ q) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < 3 * n;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n3;
        i += (int64_t)gridDim.x * 256) {
     float v = 0.f;
     if (qmode == kQCopy)
@@ -123,78 +215,91 @@ __global__ __launch_bounds__(256) void k_fgp_q3(int64_t n, float coef, int qmode
   }
 }
 
-// u = b - theta D^T q
-__global__ __launch_bounds__(256) void k_fgp_u3(int D, int H, int W, const float* __restrict__ b,
-                                                 float theta, const float* __restrict__ q,
-                                                 float* __restrict__ u) {
-  const int64_t n = (int64_t)D * H * W;
-  const int64_t hw = (int64_t)H * W;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+// u = b - theta D^T q (3-D); n = plane length (vector length)
+template <bool TILED>
+__global__ __launch_bounds__(256) void k_fgp_u3(Layout L, int64_t n, const float* __restrict__ b,
+                                                float theta, const float* __restrict__ q,
+                                                float* __restrict__ u) {
+  const int D = L.D, H = L.H, W = L.W;
+  const int64_t hw = (int64_t)H * W, tot = hw * D;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < tot;
        i += (int64_t)gridDim.x * 256) {
     const int d = (int)(i / hw);
-    const int64_t rem = i % hw;
+    const int64_t rem = i - d * hw;
     const int s = (int)(rem / W), t = (int)(rem % W);
-    const float nd = d + 1 < D ? q[i + hw] : 0.f;
-    const float nv = s + 1 < H ? q[n + i + W] : 0.f;
-    const float nh = t + 1 < W ? q[2 * n + i + 1] : 0.f;
-    const float dtq = (q[i] - nd) + (q[n + i] - nv) + (q[2 * n + i] - nh);
-    u[i] = b[i] - theta * dtq;
+    const int64_t c = pidx<TILED>(L, d, s, t);
+    const float nd = d + 1 < D ? q[pidx<TILED>(L, d + 1, s, t)] : 0.f;
+    const float nv = s + 1 < H ? q[n + pidx<TILED>(L, d, s + 1, t)] : 0.f;
+    const float nh = t + 1 < W ? q[2 * n + pidx<TILED>(L, d, s, t + 1)] : 0.f;
+    const float dtq = (q[c] - nd) + (q[n + c] - nv) + (q[2 * n + c] - nh);
+    u[c] = b[c] - theta * dtq;
   }
 }
 
-__global__ __launch_bounds__(256) void k_fgp_p3(int D, int H, int W, float step,
+template <bool TILED>
+__global__ __launch_bounds__(256) void k_fgp_p3(Layout L, int64_t n, float step,
                                                 const float* __restrict__ q,
                                                 const float* __restrict__ u,
                                                 float* __restrict__ p) {
-  const int64_t n = (int64_t)D * H * W;
-  const int64_t hw = (int64_t)H * W;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+  const int D = L.D, H = L.H, W = L.W;
+  const int64_t hw = (int64_t)H * W, tot = hw * D;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < tot;
        i += (int64_t)gridDim.x * 256) {
     const int d = (int)(i / hw);
-    const int64_t rem = i % hw;
+    const int64_t rem = i - d * hw;
     const int s = (int)(rem / W), t = (int)(rem % W);
-    const float uc = u[i];
-    const float gd = d >= 1 ? uc - u[i - hw] : 0.f;
-    const float gv = s >= 1 ? uc - u[i - W] : 0.f;
-    const float gh = t >= 1 ? uc - u[i - 1] : 0.f;
-    const float ad = fmaf(step, gd, q[i]);
-    const float av = fmaf(step, gv, q[n + i]);
-    const float ah = fmaf(step, gh, q[2 * n + i]);
+    const int64_t c = pidx<TILED>(L, d, s, t);
+    const float uc = u[c];
+    const float gd = d >= 1 ? uc - u[pidx<TILED>(L, d - 1, s, t)] : 0.f;
+    const float gv = s >= 1 ? uc - u[pidx<TILED>(L, d, s - 1, t)] : 0.f;
+    const float gh = t >= 1 ? uc - u[pidx<TILED>(L, d, s, t - 1)] : 0.f;
+    const float ad = fmaf(step, gd, q[c]);
+    const float av = fmaf(step, gv, q[n + c]);
+    const float ah = fmaf(step, gh, q[2 * n + c]);
     const float nrm = fmaxf(1.f, sqrtf(ad * ad + av * av + ah * ah));
-    p[i] = ad / nrm;
-    p[n + i] = av / nrm;
-    p[2 * n + i] = ah / nrm;
+    p[c] = ad / nrm;
+    p[n + c] = av / nrm;
+    p[2 * n + c] = ah / nrm;
   }
 }
 
-__global__ __launch_bounds__(256) void k_fgp_out3(int D, int H, int W, const float* __restrict__ b,
-                                                  float theta, const float* __restrict__ p,
+template <bool TILED>
+__global__ __launch_bounds__(256) void k_fgp_out3(Layout L, int64_t n,
+                                                  const float* __restrict__ b, float theta,
+                                                  const float* __restrict__ p,
                                                   float* __restrict__ out) {
-  const int64_t n = (int64_t)D * H * W;
-  const int64_t hw = (int64_t)H * W;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+  const int D = L.D, H = L.H, W = L.W;
+  const int64_t hw = (int64_t)H * W, tot = hw * D;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < tot;
        i += (int64_t)gridDim.x * 256) {
     const int d = (int)(i / hw);
-    const int64_t rem = i % hw;
+    const int64_t rem = i - d * hw;
     const int s = (int)(rem / W), t = (int)(rem % W);
-    const float nd = d + 1 < D ? p[i + hw] : 0.f;
-    const float nv = s + 1 < H ? p[n + i + W] : 0.f;
-    const float nh = t + 1 < W ? p[2 * n + i + 1] : 0.f;
-    const float dtp = (p[i] - nd) + (p[n + i] - nv) + (p[2 * n + i] - nh);
-    out[i] = b[i] - theta * dtp;
+    const int64_t c = pidx<TILED>(L, d, s, t);
+    const float nd = d + 1 < D ? p[pidx<TILED>(L, d + 1, s, t)] : 0.f;
+    const float nv = s + 1 < H ? p[n + pidx<TILED>(L, d, s + 1, t)] : 0.f;
+    const float nh = t + 1 < W ? p[2 * n + pidx<TILED>(L, d, s, t + 1)] : 0.f;
+    const float dtp = (p[c] - nd) + (p[n + c] - nv) + (p[2 * n + c] - nh);
+    out[c] = b[c] - theta * dtp;
   }
 }
 
-__global__ void k_copy_f32(const float* __restrict__ a, float* __restrict__ b, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    b[i] = a[i];
+template <bool TILED>
+__global__ void k_copy_img(Layout L, const float* __restrict__ a, float* __restrict__ b) {
+  const int64_t hw = (int64_t)L.H * L.W, tot = hw * L.D;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int d = (int)(i / hw);
+    const int64_t rem = i - d * hw;
+    const int64_t c = pidx<TILED>(L, d, (int)(rem / L.W), (int)(rem % L.W));
+    b[c] = a[c];
+  }
 }
 
-size_t tv_ws_floats(int H, int W, int D) {
-  const size_t n = (size_t)H * W * D;
-  // 2-D: three rotating dual pairs; 3-D: three rotating triples plus q and u
-  return D == 1 ? 6 * n : 9 * n + 3 * n + n;
+size_t tv_ws_floats(int64_t n, int D) {
+  // 2-D: two dual pairs in, two out (fused chunks); 3-D: three rotating
+  // triples plus q and u
+  return D == 1 ? 8 * (size_t)n : 13 * (size_t)n;
 }
 
 static unsigned grid_for(int64_t n) {
@@ -216,32 +321,41 @@ static void momentum(int iters, std::vector<float>& c) {
   }
 }
 
-hipError_t tv_prox_run(int H, int W, int D, const float* b, float theta, int iters, float* out,
-                       float* ws, hipStream_t s) {
-  const int64_t n = (int64_t)H * W * D;
+template <bool TILED>
+static hipError_t tv_prox_impl(const Layout& L, const float* b, float theta, int iters,
+                               float* out, float* ws, hipStream_t s) {
+  const int64_t n = TILED ? L.c_int : (int64_t)L.H * L.W * L.D;
+  const int64_t npix = (int64_t)L.H * L.W * L.D;
   if (theta == 0.f || iters == 0) {
-    k_copy_f32<<<grid_for(n), 256, 0, s>>>(b, out, n);
+    k_copy_img<TILED><<<grid_for(npix), 256, 0, s>>>(L, b, out);
     return hipGetLastError();
   }
   std::vector<float> c;
   momentum(iters, c);
-  if (D == 1) {
-    float* buf[3] = {ws, ws + 2 * n, ws + 4 * n};  // (pv, ph) pairs
+  if (L.D == 1) {
+    // chunks of up to kFuseMax iterations, one fused launch each.  A chunk
+    // reads p_{k0} and p_{k0-1} (every block reads a halo, so the outputs
+    // cannot overwrite them) and writes p_{k0+L}, p_{k0+L-1} into the other
+    // two of four (pv, ph) buffer pairs; the last chunk writes the result.
+    float* buf[4] = {ws, ws + 2 * n, ws + 4 * n, ws + 6 * n};
     const float step = 1.0f / (8.0f * theta);
-    dim3 grid((W + kTW - 1) / kTW, (H + kTH - 1) / kTH);
-    dim3 block(kTW, kTH);
-    int cur = 0;  // buffer receiving p_k
-    for (int k = 1; k <= iters; ++k) {
-      float* o = buf[cur];
-      const float* p1 = buf[(cur + 2) % 3];  // p_{k-1}
-      const float* p2 = buf[(cur + 1) % 3];  // p_{k-2}
-      const int qm = k == 1 ? kQZero : (k == 2 ? kQCopy : kQMomentum);
-      k_fgp_iter2<<<grid, block, 0, s>>>(H, W, b, theta, step, c[k], qm, p1, p1 + n, p2, p2 + n, o,
-                                         o + n);
-      cur = (cur + 1) % 3;
+    dim3 grid((L.W + kFT - 1) / kFT, (L.H + kFT - 1) / kFT);
+    int in = 0;  // p_{k0} in buf[in], p_{k0-1} in buf[in + 1]
+    for (int k0 = 0; k0 < iters;) {
+      const int chunk = std::min(kFuseMax, iters - k0);
+      FuseArgs ca{};
+      for (int m = 1; m <= chunk; ++m) ca.coef[m] = c[k0 + m];
+      const float* i1 = buf[in];
+      const float* i2 = buf[in + 1];
+      float* o1 = buf[2 - in];
+      float* o2 = buf[3 - in];
+      const bool last = k0 + chunk == iters;
+      k_fgp_fused2<TILED><<<grid, kFThreads, 0, s>>>(
+          L, b, theta, step, k0, chunk, ca, i1, i1 + n, i2, i2 + n, last ? out : nullptr,
+          o1, o1 + n, o2, o2 + n);
+      in = 2 - in;
+      k0 += chunk;
     }
-    const float* pk = buf[(cur + 2) % 3];
-    k_fgp_out2<<<grid_for(n), 256, 0, s>>>(H, W, b, theta, pk, pk + n, out);
     return hipGetLastError();
   }
   float* buf[3] = {ws, ws + 3 * n, ws + 6 * n};  // (pd, pv, ph) triples
@@ -254,16 +368,22 @@ hipError_t tv_prox_run(int H, int W, int D, const float* b, float theta, int ite
     const float* p1 = buf[(cur + 2) % 3];
     const float* p2 = buf[(cur + 1) % 3];
     const int qm = k == 1 ? kQZero : (k == 2 ? kQCopy : kQMomentum);
-    k_fgp_q3<<<grid_for(3 * n), 256, 0, s>>>(n, c[k], qm, p1, p2, q);
-    k_fgp_u3<<<grid_for(n), 256, 0, s>>>(D, H, W, b, theta, q, u);
-    k_fgp_p3<<<grid_for(n), 256, 0, s>>>(D, H, W, step, q, u, o);
+    k_fgp_q3<<<grid_for(3 * n), 256, 0, s>>>(3 * n, c[k], qm, p1, p2, q);
+    k_fgp_u3<TILED><<<grid_for(npix), 256, 0, s>>>(L, n, b, theta, q, u);
+    k_fgp_p3<TILED><<<grid_for(npix), 256, 0, s>>>(L, n, step, q, u, o);
     cur = (cur + 1) % 3;
   }
-  k_fgp_out3<<<grid_for(n), 256, 0, s>>>(D, H, W, b, theta, buf[(cur + 2) % 3], out);
+  k_fgp_out3<TILED><<<grid_for(npix), 256, 0, s>>>(L, n, b, theta, buf[(cur + 2) % 3], out);
   return hipGetLastError();
 }
 
-// TV value: per-element isotropic difference length, FP64 partials.
+hipError_t tv_prox_run(const Layout& L, bool tiled, const float* b, float theta, int iters,
+                       float* out, float* ws, hipStream_t s) {
+  return tiled ? tv_prox_impl<true>(L, b, theta, iters, out, ws, s)
+               : tv_prox_impl<false>(L, b, theta, iters, out, ws, s);
+}
+
+// TV value (natural order): per-element isotropic difference length, FP64 partials.
 __global__ __launch_bounds__(256) void k_tv_partial(int D, int H, int W,
                                                     const float* __restrict__ x,
                                                     double* __restrict__ partial) {
@@ -310,8 +430,16 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 using namespace bsgd;
 
 static size_t tv_bytes(int H, int W, int D) {
-  return align_up(tv_ws_floats(H, W, D) * sizeof(float), kAlign) +
+  return align_up(tv_ws_floats((int64_t)H * W * D, D) * sizeof(float), kAlign) +
          align_up((kReduceBlocks + 1) * sizeof(double), kAlign);
+}
+
+static Layout natural_layout(int H, int W, int D) {
+  Layout L;
+  L.H = H;
+  L.W = W;
+  L.D = D;
+  return L;
 }
 
 extern "C" bsgd_status bsgd_tv_workspace_size(int H, int W, int D, size_t* bytes) {
@@ -334,7 +462,8 @@ extern "C" bsgd_status bsgd_tv_prox(int H, int W, int D, const float* b, float t
     set_error("tv workspace has %zu bytes, needs %zu", ws_bytes, tv_bytes(H, W, D));
     return BSGD_ERR_WORKSPACE;
   }
-  BSGD_HIP(tv_prox_run(H, W, D, b, theta, iters, out, static_cast<float*>(ws), stream));
+  BSGD_HIP(tv_prox_run(natural_layout(H, W, D), false, b, theta, iters, out,
+                       static_cast<float*>(ws), stream));
   return BSGD_OK;
 }
 
@@ -348,7 +477,8 @@ extern "C" bsgd_status bsgd_tv_value(int H, int W, int D, const float* x, void* 
     return BSGD_ERR_WORKSPACE;
   }
   double* partial = reinterpret_cast<double*>(
-      static_cast<char*>(ws) + align_up(tv_ws_floats(H, W, D) * sizeof(float), kAlign));
+      static_cast<char*>(ws) +
+      align_up(tv_ws_floats((int64_t)H * W * D, D) * sizeof(float), kAlign));
   k_tv_partial<<<kReduceBlocks, 256, 0, stream>>>(D, H, W, x, partial);
   BSGD_LAUNCH_CHECK();
   k_sum_partials<<<1, 256, 0, stream>>>(partial, kReduceBlocks, partial + kReduceBlocks);

@@ -27,14 +27,16 @@ def test_library_exports_every_declared_symbol():
 
 def test_size_queries_and_argument_errors():
     from paper_1812_01307_amd import capi
-    b32 = capi.bsgd_plan_workspace_size(8190, 4096, 477832, 2, 2, 0)
-    b16 = capi.bsgd_plan_workspace_size(8190, 4096, 477832, 2, 2, capi.BSGD_PLAN_F16)
+    b32 = capi.bsgd_plan_workspace_size(8190, 4096, 477832, 2, 2, 64, 64, 1, 91, 0)
+    b16 = capi.bsgd_plan_workspace_size(8190, 4096, 477832, 2, 2, 64, 64, 1, 91, capi.BSGD_PLAN_F16)
     assert b16 > b32 > 2 * 477832 * 8
     with pytest.raises(capi.BsgdError) as e:
-        capi.bsgd_plan_workspace_size(10, 10, 5, 11, 1, 0)
+        capi.bsgd_plan_workspace_size(10, 10, 5, 11, 1, 2, 5, 1, 0, 0)
     assert e.value.status == capi.BSGD_ERR_INVALID
     with pytest.raises(capi.BsgdError):
-        capi.bsgd_plan_workspace_size(10, 10, 2 ** 31, 1, 1, 0)
+        capi.bsgd_plan_workspace_size(10, 10, 2 ** 31, 1, 1, 2, 5, 1, 0, 0)
+    with pytest.raises(capi.BsgdError, match="shape"):
+        capi.bsgd_plan_workspace_size(10, 10, 5, 1, 1, 3, 3, 1, 0, 0)
     assert capi.bsgd_tv_workspace_size(512, 512, 1) >= 6 * 512 * 512 * 4
     assert capi.bsgd_tv_workspace_size(16, 16, 4) >= 13 * 16 * 16 * 4
     with pytest.raises(capi.BsgdError):

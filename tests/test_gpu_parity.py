@@ -19,11 +19,18 @@ def _host(t):
     return t.cpu().numpy().astype(np.float64)
 
 
-CASES = ["c1", "ragged"]
+CASES = ["c1", "ragged", "ragged_noview"]
 
 
 def _case(name):
     return problem("c1_64") if name == "c1" else ragged_problem()
+
+
+def _plan(name, **kw):
+    """c1 and ragged use the view-interleaved ray order; ragged_noview the identity order."""
+    if name == "ragged_noview":
+        kw.setdefault("view_len", 0)
+    return plan_for(_case(name), **kw)
 
 
 # --------------------------------------------------------------------------
@@ -34,7 +41,7 @@ def _case(name):
 def test_tiles_bit_exact(name):
     import paper_1812_01307_amd as bsgd
     p = _case(name)
-    plan = plan_for(p)
+    plan = _plan(name)
     val32 = f32(p.val).astype(np.float64)
     for i in range(p.M):
         for j in range(p.N):
@@ -61,7 +68,7 @@ def test_tiles_bit_exact(name):
 def test_forward_and_backprojection(name, vt):
     import paper_1812_01307_amd as bsgd
     p = _case(name)
-    plan = plan_for(p, f16=(vt == 1))
+    plan = _plan(name, f16=(vt == 1))
     A = matrix(p)
     if vt == 1:
         # the half-precision form is compared with the oracle on the
@@ -93,7 +100,7 @@ def test_forward_and_backprojection(name, vt):
 def test_block_products(name):
     import paper_1812_01307_amd as bsgd
     p = _case(name)
-    plan = plan_for(p)
+    plan = _plan(name)
     blocks = oracle.tiles(p.row_ptr, p.col, p.val, p.row_off, p.col_off)
     rng = np.random.default_rng(6)
     x = f32(rng.random(p.ncols))
@@ -117,7 +124,8 @@ def test_block_products(name):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("shape", [(64, 64), (45, 67), (1, 37), (29, 1), (1, 1), (8, 40)])
-@pytest.mark.parametrize("theta,iters", [(0.05, 1), (0.05, 20), (0.5, 3), (1e-6, 20), (0.02, 100)])
+@pytest.mark.parametrize("theta,iters", [(0.05, 1), (0.05, 20), (0.5, 3), (1e-6, 20), (0.02, 21),
+                                         (0.05, 30), (0.02, 100)])
 def test_tv_prox_matches_fgp(shape, theta, iters):
     import paper_1812_01307_amd as bsgd
     rng = np.random.default_rng(hash((shape, iters)) % 2 ** 32)
@@ -156,7 +164,7 @@ def test_tv_value(shape):
 def test_power_umax(name):
     import paper_1812_01307_amd as bsgd
     p = _case(name)
-    plan = plan_for(p)
+    plan = _plan(name)
     u = bsgd.bsgd_power_umax(plan, 60)
     ref = oracle.power_umax(matrix(p))
     assert abs(u - ref) <= 1e-4 * ref
@@ -192,9 +200,10 @@ def test_c1_trajectory_per_epoch(lam):
     assert max(errs) <= ITERATE_REL, (max(errs), int(np.argmax(errs)))
 
 
-def test_ragged_trajectory():
+@pytest.mark.parametrize("view_len", [None, 0])
+def test_ragged_trajectory(view_len):
     p = ragged_problem()
-    plan = plan_for(p)
+    plan = plan_for(p, view_len=view_len)
     mu = mu_for(p)
     y32 = f32(p.y).astype(np.float64)
     _, _, ref = oracle.bsgd_tv(matrix(p), y32, float(np.float32(mu)), 5.0, 30, 20, (p.H, p.W),
@@ -203,7 +212,8 @@ def test_ragged_trajectory():
     assert max(rel_l2(a, b) for a, b in zip(xs, ref)) <= ITERATE_REL
 
 
-def test_runs_are_bitwise_reproducible_and_resume_is_exact():
+@pytest.mark.parametrize("overlap", [0, 1])
+def test_runs_are_bitwise_reproducible_and_resume_is_exact(overlap):
     import paper_1812_01307_amd as bsgd
     p = problem("c1_64")
     plan = plan_for(p)
@@ -212,6 +222,7 @@ def test_runs_are_bitwise_reproducible_and_resume_is_exact():
     outs = []
     for _ in range(2):
         st = bsgd.bsgd_state_create(plan)
+        bsgd.bsgd_state_set_overlap(st, overlap)
         bsgd.bsgd_state_init(st, y)
         bsgd.bsgd_run_epochs(st, mu, 20.0, 12, 20)
         outs.append((_host(bsgd.bsgd_get_x(st)), _host(bsgd.bsgd_get_r(st))))
@@ -254,7 +265,7 @@ def test_invalid_inputs_are_rejected():
     bad_col[5], bad_col[6] = bad_col[6], bad_col[5]          # unsorted row
     with pytest.raises(bsgd.BsgdError, match="ascending"):
         bsgd.plan_from_host(p.nrows, p.ncols, p.row_ptr, bad_col, p.val, tp, tc, tv, 2, 2,
-                            p.row_off, p.col_off, 8, 8)
+                            p.row_off, p.col_off, 8, 8, view_len=p.bins)
     bad_col = p.col.copy()
     bad_col[-1] = p.ncols + 3                                 # column out of range
     with pytest.raises(bsgd.BsgdError, match="range"):
@@ -279,3 +290,27 @@ def test_invalid_inputs_are_rejected():
         bsgd.bsgd_run_epochs(st, 1e-3, 1.0, 1, 0)
     with pytest.raises(bsgd.BsgdError, match="BSGD_PLAN_F16"):
         bsgd.bsgd_forward(plan, _dev(f32(np.zeros(p.ncols))), vt=1)
+
+
+def test_lane_choices_agree_and_autotune():
+    """Every lane count gives the same products up to summation order; autotune picks one."""
+    import paper_1812_01307_amd as bsgd
+    p = problem("c1_64")
+    plan = plan_for(p, autotune=True)
+    f_l, b_l = bsgd.bsgd_plan_lanes(plan)
+    nt = bsgd.BSGD_LAUNCH_NT
+    assert f_l & ~nt in (2, 4, 8, 16, 32) and b_l & ~nt in (2, 4, 8, 16, 32)
+    rng = np.random.default_rng(9)
+    x = _dev(f32(rng.random(p.ncols)))
+    r = _dev(f32(rng.standard_normal(p.nrows)))
+    Aabs = abs_matrix(p)
+    ref_f = oracle.forward(matrix(p), _host(x))
+    ref_b = oracle.backproject(matrix(p), _host(r))
+    for lanes in (2, 4, 8, 16, 32, 64, 8 | nt, 64 | nt):
+        bsgd.bsgd_plan_set_lanes(plan, lanes, lanes)
+        f = _host(bsgd.bsgd_forward(plan, x))
+        b = _host(bsgd.bsgd_backproject(plan, r))
+        assert np.all(np.abs(f - ref_f) <= PRODUCT_REL * (Aabs @ np.abs(_host(x))) + 1e-30)
+        assert np.all(np.abs(b - ref_b) <= PRODUCT_REL * 2 * (Aabs.T @ np.abs(_host(r))) + 1e-30)
+    with pytest.raises(bsgd.BsgdError):
+        bsgd.bsgd_plan_set_lanes(plan, 3, 8)

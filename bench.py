@@ -67,6 +67,11 @@ def main(argv=None):
                     help="epoch schedule: forward pass concurrent with backprojection (0) or after it (1)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--mu-file", default=None,
+                    help="JSON with a fixed step mu_f32 (precision runs against the oracle); "
+                         "the jobs then skip the power iteration")
+    ap.add_argument("--dump", default=None, help="save the iterate every --dump-every epochs (npz)")
+    ap.add_argument("--dump-every", type=int, default=50)
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -92,7 +97,8 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     print(f"[bench] generating {args.config}", file=sys.stderr, flush=True)
     t_gen = time.perf_counter()
-    prob = synth.make_problem(args.config)
+    # FP32 matrix values for the device (the projections y are FP64-computed)
+    prob = synth.make_problem(args.config, dtype=np.float32)
     tp, tc, tv = prob.ensure_transpose()
     t_gen = time.perf_counter() - t_gen
     epochs = args.epochs or prob.epochs
@@ -123,13 +129,21 @@ def main(argv=None):
         del p0
         print(f"[bench] autotuned launch {tuned}", file=sys.stderr, flush=True)
 
+    fixed_mu = None
+    if args.mu_file:
+        with open(args.mu_file) as f:
+            fixed_mu = float(json.load(f)["mu_f32"])
+
     def job(record):
         plan = bsgd.bsgd_plan_create(A, At, prob.M, prob.N, prob.row_off, prob.col_off, prob.H,
                                      prob.W, 1, prob.bins, flags)
         if tuned is not None:
             bsgd.bsgd_plan_set_lanes(plan, *tuned)
-        u = bsgd.bsgd_power_umax(plan, args.power_iters, vt=vt)
-        mu = 0.9 / (2.0 * u)
+        if fixed_mu is None:
+            u = bsgd.bsgd_power_umax(plan, args.power_iters, vt=vt)
+            mu = 0.9 / (2.0 * u)
+        else:
+            mu = fixed_mu
         st = bsgd.bsgd_state_create(plan, 1, vt)
         bsgd.bsgd_state_set_overlap(st, args.overlap)
         if record and timing:
@@ -175,6 +189,20 @@ def main(argv=None):
     torch.cuda.synchronize()
     epoch_ms = (time.perf_counter() - te) * 1e3 / epochs
 
+    if args.dump:
+        # untimed: the iterate every --dump-every epochs of one more job
+        st3 = bsgd.bsgd_state_create(plan, 1, vt)
+        bsgd.bsgd_state_init(st3, y)
+        snaps = {}
+        done = 0
+        while done < epochs:
+            n = min(args.dump_every, epochs - done)
+            bsgd.bsgd_run_epochs(st3, mu, prob.lam, n, K)
+            done += n
+            snaps[f"x{done}"] = bsgd.bsgd_get_x(st3).cpu().numpy()
+        np.savez(args.dump, mu=np.float32(mu), **snaps)
+        print(f"[bench] saved {sorted(snaps)} to {args.dump}", file=sys.stderr, flush=True)
+
     val_bytes = 2 if vt == bsgd.BSGD_VAL_F16 else 4
     b_fwd, b_bwd = _alg_bytes(nnz, r, c, val_bytes)
     roofline = None
@@ -200,7 +228,8 @@ def main(argv=None):
     cpu = None
     if not args.no_cpu_baseline and args.cpu_epochs > 0:
         import oracle  # CPU baseline leg only
-        A64 = oracle.as_matrix(prob.row_ptr, prob.col, prob.val, c)
+        rp64, col64, val64 = synth.projection_matrix(prob.H, prob.W, prob.n_ang, prob.bins)
+        A64 = oracle.as_matrix(rp64, col64, val64, c)
         mu_cpu = 0.9 / (2.0 * oracle.power_umax(A64, tol=1e-6, max_iter=20))
         print(f"[bench] cpu baseline: {args.cpu_epochs} oracle epochs", file=sys.stderr, flush=True)
         xc, rc = oracle.initial_state(A64, prob.y)
@@ -231,7 +260,9 @@ def main(argv=None):
                                f"lambda={prob.lam}, {epochs} epochs, {K} FGP iterations, "
                                f"setup S0+S0' included)",
                    "nnz": nnz, "epochs_per_step": epochs, "power_iters": args.power_iters,
-                   "lanes_per_row": list(bsgd.bsgd_plan_lanes(plan)), "overlap": args.overlap},
+                   "lanes_per_row": list(bsgd.bsgd_plan_lanes(plan)), "overlap": args.overlap,
+                   "mu": "fixed from " + args.mu_file if fixed_mu is not None
+                   else f"power iteration ({args.power_iters} steps)"},
         "epoch_only_ms": round(epoch_ms, 4),
         "epoch_only_epochs_per_s": round(1e3 / epoch_ms, 2),
         "alg_bytes_per_epoch": b_fwd + b_bwd,

@@ -73,6 +73,7 @@ typedef struct {
 
 typedef struct bsgd_plan bsgd_plan;   /* block store of A and A^T (opaque) */
 typedef struct bsgd_state bsgd_state; /* iterate, residual and prox buffers (opaque) */
+typedef struct bsgd_graph bsgd_graph; /* captured epochs of one state (opaque) */
 
 /* ------------------------------------------------------------------------
  * Block store (Section 2.1: A divided into M row blocks and N column blocks)
@@ -232,23 +233,38 @@ bsgd_status bsgd_power_umax(const bsgd_plan* plan, bsgd_valtype vt, int iters, v
  * Whole epochs (Algorithm 1)
  * ---------------------------------------------------------------------- */
 
-/* Workspace bytes of a state for `nrhs` right-hand sides (nrhs = 1 here). */
-bsgd_status bsgd_state_workspace_size(const bsgd_plan* plan, int nrhs, size_t* bytes);
+/*
+ * State flags.  A state holds nrhs right-hand sides that share the plan's A:
+ * nrhs = 1, or a power of two from 4 to 1024.  With several RHS every vector
+ * crossing this interface is a row-major matrix [rows][nrhs] (the RHS index
+ * fastest), the products become sparse-times-dense products that read A once
+ * for all RHS, and the prox is either
+ *   - per RHS (default): independent 2-D reconstructions, each with its own
+ *     lambda (bsgd_state_set_lambda) -- batches of requests on one geometry;
+ *   - BSGD_STATE_VOLUME: the RHS are the slices of one volume and line 9 uses
+ *     the isotropic 3-D TV across them (needs a 2-D plan, D = 1).
+ */
+#define BSGD_STATE_VOLUME 1u
+
+/* Workspace bytes of a state. */
+bsgd_status bsgd_state_workspace_size(const bsgd_plan* plan, int nrhs, unsigned flags,
+                                      size_t* bytes);
 
 /*
  * Create a state in `workspace` (device).  The state borrows the plan.  It
  * owns one extra HIP stream and two events (default priority) that let the
  * forward product overlap the prox inside an epoch.
  */
-bsgd_status bsgd_state_create(const bsgd_plan* plan, int nrhs, bsgd_valtype vt, void* workspace,
-                              size_t workspace_bytes, bsgd_state** out);
+bsgd_status bsgd_state_create(const bsgd_plan* plan, int nrhs, bsgd_valtype vt, unsigned flags,
+                              void* workspace, size_t workspace_bytes, bsgd_state** out);
 
 void bsgd_state_destroy(bsgd_state* state);
 
 /*
- * Start a reconstruction: copy y (device, r floats); x = x0 (device, c
- * floats) or 0 when x0 == NULL; r = y - A x0 (r = y when x0 == NULL), the
- * initialisation that Algorithm 1 leaves open.  Resets the epoch count.
+ * Start a reconstruction: copy y (device, r x nrhs floats); x = x0 (device,
+ * c x nrhs floats) or 0 when x0 == NULL; r = y - A x0 (r = y when x0 ==
+ * NULL), the initialisation that Algorithm 1 leaves open.  Resets the epoch
+ * count and the per-RHS lambdas (to 0).
  */
 bsgd_status bsgd_state_init(bsgd_state* state, const float* y, const float* x0, hipStream_t stream);
 
@@ -264,9 +280,12 @@ bsgd_status bsgd_state_load(bsgd_state* state, const float* x, const float* r, i
  * Run `epochs` epochs of Algorithm 1 with every block pair active:
  *   g = 2 A^T r; r' = y - A x; x^ = x + mu g; x = FGP(x^, theta = mu * lam,
  *   prox_iters); r = r'.
- * mu > 0, lam >= 0, epochs >= 0, prox_iters >= 1 when lam > 0.  lam = 0
- * skips the prox (x = x^).  Enqueued on `stream` (the state's own stream
- * joins it); no allocation and no host synchronisation.
+ * mu > 0, lam >= 0 (the same for every RHS), epochs >= 0, prox_iters >= 1
+ * when lam != 0.  lam = 0 skips the prox (x = x^).  On a batch state,
+ * lam < 0 selects the per-RHS values of bsgd_state_set_lambda.  Enqueued on
+ * `stream` (the state's own stream joins it); no allocation and no host
+ * synchronisation, so a call can be captured in a HIP graph (capture an even
+ * number of epochs: the iterate buffers alternate).
  */
 bsgd_status bsgd_run_epochs(bsgd_state* state, float mu, float lam, int epochs, int prox_iters,
                             hipStream_t stream);
@@ -306,6 +325,38 @@ bsgd_status bsgd_get_stats(const bsgd_state* state, hipStream_t stream, double* 
 bsgd_status bsgd_state_enable_timing(bsgd_state* state, int max_epochs);
 bsgd_status bsgd_state_timing(bsgd_state* state, double* fwd_ms, double* bwd_ms, double* prox_ms,
                               int64_t* epochs_timed);
+
+/*
+ * Batch states (several RHS, no BSGD_STATE_VOLUME): per-slot operations for
+ * serving independent reconstructions on one geometry.
+ *   set_rhs     (re)start slot k with y (device, r floats, natural order) and
+ *               x0 (device, c floats, or NULL for 0); y == NULL empties the
+ *               slot (all its vectors become zero and stay zero).  Other
+ *               slots are untouched.
+ *   set_lambda  per-slot lambda (host, nrhs floats >= 0), used by
+ *               bsgd_run_epochs with lam < 0.  Synchronises.
+ *   get_x_rhs   slot k's iterate (device, c floats, natural order).
+ *   get_stats_rhs  ||r_k||^2 per slot (host, nrhs doubles, FP64 sums in a
+ *               fixed order).  Synchronises; BSGD_ERR_DIVERGED if any is
+ *               not finite.
+ */
+bsgd_status bsgd_state_set_rhs(bsgd_state* state, int k, const float* y, const float* x0,
+                               hipStream_t stream);
+bsgd_status bsgd_state_set_lambda(bsgd_state* state, const float* lam, hipStream_t stream);
+bsgd_status bsgd_get_x_rhs(const bsgd_state* state, int k, float* x, hipStream_t stream);
+bsgd_status bsgd_get_stats_rhs(const bsgd_state* state, hipStream_t stream, double* res_norm2);
+
+/*
+ * Capture `epochs` epochs of bsgd_run_epochs (same arguments; epochs even,
+ * >= 2) as a HIP graph on `stream` (not the null stream) and instantiate it.
+ * bsgd_graph_launch replays them on `stream`: the same kernels, so results
+ * equal bsgd_run_epochs bitwise.  The graph belongs to the state (destroy it
+ * first); mu, lam and the iteration count are fixed at capture.
+ */
+bsgd_status bsgd_graph_create(bsgd_state* state, float mu, float lam, int epochs, int prox_iters,
+                              hipStream_t stream, bsgd_graph** out);
+bsgd_status bsgd_graph_launch(bsgd_graph* graph, hipStream_t stream);
+void bsgd_graph_destroy(bsgd_graph* graph);
 
 /* Message for the last failed call on this thread ("" if none). */
 const char* bsgd_last_error(void);

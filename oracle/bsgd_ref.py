@@ -394,3 +394,48 @@ def block_backproject(blocks, row_off, col_off, i: int, j: int, r_block):
     c0, c1 = int(col_off[j]), int(col_off[j + 1])
     ptr, lcol, lval = blocks[(i, j)]
     return 2.0 * (sp.csr_matrix((lval, lcol, ptr), shape=(r1 - r0, c1 - c0)).T @ r_block)
+
+
+# ---------------------------------------------------------------------------
+# Several right-hand sides sharing A (slices of a volume, or a batch of
+# independent reconstructions on one geometry)
+# ---------------------------------------------------------------------------
+
+
+def bsgd_epoch_multi(A, Y, X, R, mu: float, lam, prox_iters: int, shape2d, volume: bool):
+    """One epoch of Algorithm 1 applied to S right-hand sides at once.
+
+    Y, R: (S, r) arrays and X: (S, c) arrays, one row per RHS.  The products
+    are those of bsgd_epoch for every RHS.  Line 9 is either the 3-D TV prox
+    of the volume whose slices are the RHS (volume=True, one lam), or the 2-D
+    prox of each RHS with its own lam[j] (volume=False).
+    """
+    S = X.shape[0]
+    H, W = shape2d
+    G = 2.0 * np.asarray(A.T @ R.T).T           # lines 3 + 7, stale residuals
+    R_new = Y - np.asarray(A @ X.T).T           # lines 4 + 6
+    Xhat = X + mu * G                           # line 8
+    if volume:
+        theta = mu * float(lam)
+        X_new = (fgp_prox3(Xhat.reshape(S, H, W), theta, prox_iters).reshape(S, H * W)
+                 if theta != 0.0 else Xhat.copy())
+    else:
+        lam = np.broadcast_to(np.asarray(lam, np.float64), (S,))
+        X_new = np.empty_like(Xhat)
+        for j in range(S):
+            X_new[j] = prox(Xhat[j], mu * float(lam[j]), prox_iters, (H, W))
+    return X_new, R_new
+
+
+def bsgd_tv_multi(A, Y, mu: float, lam, epochs: int, prox_iters: int, shape2d, volume: bool,
+                  record: bool = False):
+    """Run epochs of bsgd_epoch_multi from X = 0, R = Y (the single-RHS initialisation)."""
+    Y = np.asarray(Y, np.float64)
+    X = np.zeros((Y.shape[0], A.shape[1]))
+    R = Y.copy()
+    hist = []
+    for _ in range(epochs):
+        X, R = bsgd_epoch_multi(A, Y, X, R, mu, lam, prox_iters, shape2d, volume)
+        if record:
+            hist.append(X.copy())
+    return (X, R, hist) if record else (X, R)

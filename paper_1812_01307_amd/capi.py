@@ -29,6 +29,7 @@ BSGD_VAL_F16 = 1
 BSGD_PLAN_F16 = 1
 BSGD_PLAN_AUTOTUNE = 2
 BSGD_LAUNCH_NT = 128
+BSGD_STATE_VOLUME = 1
 
 _STATUS = {0: "OK", -1: "INVALID", -2: "WORKSPACE", -3: "HIP", -4: "UNSUPPORTED", -5: "DIVERGED"}
 
@@ -68,8 +69,14 @@ _PROTOS = {
     "bsgd_tv_value": [_i32, _i32, _i32, _vp, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_double)],
     "bsgd_power_workspace_size": [_vp, ctypes.POINTER(_sz)],
     "bsgd_power_umax": [_vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_f32)],
-    "bsgd_state_workspace_size": [_vp, _i32, ctypes.POINTER(_sz)],
-    "bsgd_state_create": [_vp, _i32, _i32, _vp, _sz, ctypes.POINTER(_vp)],
+    "bsgd_state_workspace_size": [_vp, _i32, ctypes.c_uint, ctypes.POINTER(_sz)],
+    "bsgd_state_create": [_vp, _i32, _i32, ctypes.c_uint, _vp, _sz, ctypes.POINTER(_vp)],
+    "bsgd_state_set_rhs": [_vp, _i32, _vp, _vp, _vp],
+    "bsgd_state_set_lambda": [_vp, ctypes.POINTER(_f32), _vp],
+    "bsgd_get_x_rhs": [_vp, _i32, _vp, _vp],
+    "bsgd_get_stats_rhs": [_vp, _vp, ctypes.POINTER(ctypes.c_double)],
+    "bsgd_graph_create": [_vp, _f32, _f32, _i32, _i32, _vp, ctypes.POINTER(_vp)],
+    "bsgd_graph_launch": [_vp, _vp],
     "bsgd_state_init": [_vp, _vp, _vp, _vp],
     "bsgd_state_load": [_vp, _vp, _vp, _i64, _vp],
     "bsgd_run_epochs": [_vp, _f32, _f32, _i32, _i32, _vp],
@@ -88,10 +95,13 @@ _lib.bsgd_plan_destroy.argtypes = [_vp]
 _lib.bsgd_plan_destroy.restype = None
 _lib.bsgd_state_destroy.argtypes = [_vp]
 _lib.bsgd_state_destroy.restype = None
+_lib.bsgd_graph_destroy.argtypes = [_vp]
+_lib.bsgd_graph_destroy.restype = None
 _lib.bsgd_last_error.argtypes = []
 _lib.bsgd_last_error.restype = ctypes.c_char_p
 
-EXPORTED = sorted(list(_PROTOS) + ["bsgd_plan_destroy", "bsgd_state_destroy", "bsgd_last_error"])
+EXPORTED = sorted(list(_PROTOS) + ["bsgd_plan_destroy", "bsgd_state_destroy", "bsgd_graph_destroy",
+                                   "bsgd_last_error"])
 
 
 def library_path() -> str:
@@ -124,7 +134,7 @@ def _ws(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def _f32(t, n=None, name="tensor"):
+def _chk(t, n=None, name="tensor"):
     if t.dtype != torch.float32:
         raise ValueError(f"{name} must be float32")
     if n is not None and t.numel() != n:
@@ -223,46 +233,46 @@ def bsgd_tile_export(plan: Plan, i, j, transposed=False, stream=None):
 # --------------------------------------------------------------------------
 
 def bsgd_forward(plan: Plan, x, y=None, out=None, vt=BSGD_VAL_F32, stream=None):
-    _f32(x, plan.ncols, "x")
+    _chk(x, plan.ncols, "x")
     if y is not None:
-        _f32(y, plan.nrows, "y")
+        _chk(y, plan.nrows, "y")
     if out is None:
         out = torch.empty(plan.nrows, dtype=torch.float32, device=x.device)
-    _f32(out, plan.nrows, "out")
+    _chk(out, plan.nrows, "out")
     _check("bsgd_forward", _lib.bsgd_forward(plan.handle, vt, _ptr(x), _ptr(y), _ptr(out),
                                              _stream(stream)))
     return out
 
 
 def bsgd_backproject(plan: Plan, r, x=None, mu=0.0, out=None, vt=BSGD_VAL_F32, stream=None):
-    _f32(r, plan.nrows, "r")
+    _chk(r, plan.nrows, "r")
     if x is not None:
-        _f32(x, plan.ncols, "x")
+        _chk(x, plan.ncols, "x")
     if out is None:
         out = torch.empty(plan.ncols, dtype=torch.float32, device=r.device)
-    _f32(out, plan.ncols, "out")
+    _chk(out, plan.ncols, "out")
     _check("bsgd_backproject", _lib.bsgd_backproject(plan.handle, vt, _ptr(r), _ptr(x), float(mu),
                                                      _ptr(out), _stream(stream)))
     return out
 
 
 def bsgd_forward_block(plan: Plan, i, j, xj, out=None, vt=BSGD_VAL_F32, stream=None):
-    _f32(xj, plan.col_off[j + 1] - plan.col_off[j], "xj")
+    _chk(xj, plan.col_off[j + 1] - plan.col_off[j], "xj")
     n = plan.row_off[i + 1] - plan.row_off[i]
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=xj.device)
-    _f32(out, n, "z")
+    _chk(out, n, "z")
     _check("bsgd_forward_block", _lib.bsgd_forward_block(plan.handle, vt, i, j, _ptr(xj), _ptr(out),
                                                          _stream(stream)))
     return out
 
 
 def bsgd_backproject_block(plan: Plan, i, j, ri, out=None, vt=BSGD_VAL_F32, stream=None):
-    _f32(ri, plan.row_off[i + 1] - plan.row_off[i], "ri")
+    _chk(ri, plan.row_off[i + 1] - plan.row_off[i], "ri")
     n = plan.col_off[j + 1] - plan.col_off[j]
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=ri.device)
-    _f32(out, n, "g")
+    _chk(out, n, "g")
     _check("bsgd_backproject_block", _lib.bsgd_backproject_block(
         plan.handle, vt, i, j, _ptr(ri), _ptr(out), _stream(stream)))
     return out
@@ -282,7 +292,7 @@ def bsgd_tv_prox(b, theta, iters, out=None, ws=None, stream=None):
     """b: (H, W) or (D, H, W) float32 device tensor."""
     shape = tuple(b.shape)
     D, H, W = (1,) + shape if len(shape) == 2 else shape
-    _f32(b)
+    _chk(b)
     if out is None:
         out = torch.empty_like(b)
     nbytes = bsgd_tv_workspace_size(H, W, D)
@@ -296,7 +306,7 @@ def bsgd_tv_prox(b, theta, iters, out=None, ws=None, stream=None):
 def bsgd_tv_value(x, ws=None, stream=None) -> float:
     shape = tuple(x.shape)
     D, H, W = (1,) + shape if len(shape) == 2 else shape
-    _f32(x)
+    _chk(x)
     nbytes = bsgd_tv_workspace_size(H, W, D)
     if ws is None:
         ws = _ws(nbytes, x.device)
@@ -331,10 +341,12 @@ def bsgd_power_umax(plan: Plan, iters, vt=BSGD_VAL_F32, ws=None, stream=None) ->
 # --------------------------------------------------------------------------
 
 class State:
-    def __init__(self, handle, workspace, plan):
+    def __init__(self, handle, workspace, plan, nrhs=1, flags=0):
         self.handle = handle
         self.workspace = workspace
         self.plan = plan
+        self.nrhs = nrhs
+        self.flags = flags
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -343,32 +355,33 @@ class State:
             self.handle = None
 
 
-def bsgd_state_workspace_size(plan: Plan, nrhs=1) -> int:
+def bsgd_state_workspace_size(plan: Plan, nrhs=1, flags=0) -> int:
     out = _sz()
-    _check("bsgd_state_workspace_size", _lib.bsgd_state_workspace_size(plan.handle, nrhs,
+    _check("bsgd_state_workspace_size", _lib.bsgd_state_workspace_size(plan.handle, nrhs, flags,
                                                                        ctypes.byref(out)))
     return out.value
 
 
-def bsgd_state_create(plan: Plan, nrhs=1, vt=BSGD_VAL_F32) -> State:
-    nbytes = bsgd_state_workspace_size(plan, nrhs)
+def bsgd_state_create(plan: Plan, nrhs=1, vt=BSGD_VAL_F32, flags=0) -> State:
+    nbytes = bsgd_state_workspace_size(plan, nrhs, flags)
     ws = _ws(nbytes, plan.workspace.device)
     h = _vp()
-    _check("bsgd_state_create", _lib.bsgd_state_create(plan.handle, nrhs, vt, _ptr(ws), nbytes,
-                                                       ctypes.byref(h)))
-    return State(h, ws, plan)
+    _check("bsgd_state_create", _lib.bsgd_state_create(plan.handle, nrhs, vt, flags, _ptr(ws),
+                                                       nbytes, ctypes.byref(h)))
+    return State(h, ws, plan, nrhs, flags)
 
 
 def bsgd_state_init(state: State, y, x0=None, stream=None):
-    _f32(y, state.plan.nrows, "y")
+    """y: [r] or [r, nrhs]; x0: [c] or [c, nrhs] (row-major, RHS fastest)."""
+    _chk(y, state.plan.nrows * state.nrhs, "y")
     if x0 is not None:
-        _f32(x0, state.plan.ncols, "x0")
+        _chk(x0, state.plan.ncols * state.nrhs, "x0")
     _check("bsgd_state_init", _lib.bsgd_state_init(state.handle, _ptr(y), _ptr(x0), _stream(stream)))
 
 
 def bsgd_state_load(state: State, x, r, epoch, stream=None):
-    _f32(x, state.plan.ncols, "x")
-    _f32(r, state.plan.nrows, "r")
+    _chk(x, state.plan.ncols * state.nrhs, "x")
+    _chk(r, state.plan.nrows * state.nrhs, "r")
     _check("bsgd_state_load", _lib.bsgd_state_load(state.handle, _ptr(x), _ptr(r), int(epoch),
                                                    _stream(stream)))
 
@@ -379,17 +392,19 @@ def bsgd_run_epochs(state: State, mu, lam, epochs, prox_iters, stream=None):
 
 
 def bsgd_get_x(state: State, out=None, stream=None):
+    n = state.plan.ncols * state.nrhs
     if out is None:
-        out = torch.empty(state.plan.ncols, dtype=torch.float32, device=state.workspace.device)
-    _f32(out, state.plan.ncols, "x")
+        out = torch.empty(n, dtype=torch.float32, device=state.workspace.device)
+    _chk(out, n, "x")
     _check("bsgd_get_x", _lib.bsgd_get_x(state.handle, _ptr(out), _stream(stream)))
     return out
 
 
 def bsgd_get_r(state: State, out=None, stream=None):
+    n = state.plan.nrows * state.nrhs
     if out is None:
-        out = torch.empty(state.plan.nrows, dtype=torch.float32, device=state.workspace.device)
-    _f32(out, state.plan.nrows, "r")
+        out = torch.empty(n, dtype=torch.float32, device=state.workspace.device)
+    _chk(out, n, "r")
     _check("bsgd_get_r", _lib.bsgd_get_r(state.handle, _ptr(out), _stream(stream)))
     return out
 
@@ -422,3 +437,61 @@ def bsgd_state_timing(state: State):
 
 def bsgd_state_set_overlap(state: State, mode: int):
     _check("bsgd_state_set_overlap", _lib.bsgd_state_set_overlap(state.handle, int(mode)))
+
+
+def bsgd_state_set_rhs(state: State, k: int, y=None, x0=None, stream=None):
+    if y is not None:
+        _chk(y, state.plan.nrows, "y")
+    if x0 is not None:
+        _chk(x0, state.plan.ncols, "x0")
+    _check("bsgd_state_set_rhs", _lib.bsgd_state_set_rhs(state.handle, int(k), _ptr(y), _ptr(x0),
+                                                         _stream(stream)))
+
+
+def bsgd_state_set_lambda(state: State, lam, stream=None):
+    arr = (ctypes.c_float * state.nrhs)(*[float(v) for v in lam])
+    _check("bsgd_state_set_lambda", _lib.bsgd_state_set_lambda(state.handle, arr, _stream(stream)))
+
+
+def bsgd_get_x_rhs(state: State, k: int, out=None, stream=None):
+    if out is None:
+        out = torch.empty(state.plan.ncols, dtype=torch.float32, device=state.workspace.device)
+    _chk(out, state.plan.ncols, "x")
+    _check("bsgd_get_x_rhs", _lib.bsgd_get_x_rhs(state.handle, int(k), _ptr(out), _stream(stream)))
+    return out
+
+
+def bsgd_get_stats_rhs(state: State, stream=None, allow_diverged=False):
+    """Per-RHS ||r_k||^2 (list of floats)."""
+    arr = (ctypes.c_double * state.nrhs)()
+    st = _lib.bsgd_get_stats_rhs(state.handle, _stream(stream), arr)
+    _check("bsgd_get_stats_rhs", st, allow=(BSGD_ERR_DIVERGED,) if allow_diverged else ())
+    return list(arr)
+
+
+class Graph:
+    def __init__(self, handle, state):
+        self.handle = handle
+        self.state = state
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.bsgd_graph_destroy(h)
+            self.handle = None
+
+
+def bsgd_graph_create(state: State, mu, lam, epochs, prox_iters, stream=None) -> Graph:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    if s.cuda_stream == 0:
+        raise ValueError("graph capture needs a non-default stream")
+    h = _vp()
+    _check("bsgd_graph_create", _lib.bsgd_graph_create(state.handle, float(mu), float(lam),
+                                                       int(epochs), int(prox_iters),
+                                                       ctypes.c_void_p(s.cuda_stream),
+                                                       ctypes.byref(h)))
+    return Graph(h, state)
+
+
+def bsgd_graph_launch(graph: Graph, stream=None):
+    _check("bsgd_graph_launch", _lib.bsgd_graph_launch(graph.handle, _stream(stream)))

@@ -169,17 +169,37 @@ hipError_t launch_rows(const Store& st, bsgd_valtype vt, RowMode mode, const flo
                        const float* y, const float* xadd, float scale, float* out,
                        hipStream_t s, int lanes = 0, int nt = -1);
 
+// Same products for S right-hand sides ([rows][S] and [cols][S] matrices, the
+// RHS index fastest; S a multiple of 4).
+hipError_t launch_spmm(const Store& st, bsgd_valtype vt, RowMode mode, const float* V,
+                       const float* Y, const float* XADD, float scale, float* OUT, int S,
+                       hipStream_t s);
+
 // Products of one segment (one block) of a store, natural orders in and out.
 hipError_t launch_segment_rows(const bsgd_plan* p, bool fwd, bsgd_valtype vt, int64_t nat_row0,
                                int64_t nrows, int segk, int64_t col_base, const float* v,
                                float scale, float* out, hipStream_t s);
 
-// Natural <-> internal vector orders (holes are written as 0).
+// Natural <-> internal vector orders (holes are written as 0).  With S > 1
+// the vectors are [rows][S] matrices (RHS fastest) and whole rows move.
 enum VecKind { kPixels = 0, kRays = 1 };
 hipError_t permute_in(const Layout& L, VecKind kind, const float* nat, float* internal,
-                      hipStream_t s);
+                      hipStream_t s, int S = 1);
 hipError_t permute_out(const Layout& L, VecKind kind, const float* internal, float* nat,
-                       hipStream_t s);
+                       hipStream_t s, int S = 1);
+// Column j of an internal [n_int][S] matrix from / to a natural vector
+// (nat == nullptr writes zeros).
+hipError_t scatter_column(const Layout& L, VecKind kind, const float* nat, float* internal,
+                          int S, int j, hipStream_t s);
+hipError_t gather_column(const Layout& L, VecKind kind, const float* internal, float* nat, int S,
+                         int j, hipStream_t s);
+// mat[k * S + j] = v[k] for k < n (both internal order)
+hipError_t set_column(const float* v, float* mat, int64_t n, int S, int j, hipStream_t s);
+// Per-column sums of squares of an [n][S] matrix, FP64, fixed order:
+// partial must hold kColBlocks * S doubles, out S doubles.
+constexpr int kColBlocks = 64;
+hipError_t launch_colsumsq(const float* X, int64_t n, int S, double* partial, double* out,
+                           hipStream_t s);
 // v = 1 on every pixel, 0 on holes (internal order)
 hipError_t fill_pixels_one(const Layout& L, float* v, hipStream_t s);
 
@@ -195,5 +215,14 @@ hipError_t fill_f32(float* x, int64_t n, float v, hipStream_t s);
 size_t tv_ws_floats(int64_t n, int D);
 hipError_t tv_prox_run(const Layout& L, bool tiled, const float* b, float theta, int iters,
                        float* out, float* ws, hipStream_t s);
+// S images in the internal 2-D pixel order, [c_int][S] (image index fastest),
+// each with its own theta_j = mu * lam[j] (lam: device array of S floats, or
+// nullptr for theta_j = mu * lam0 for all j).  ws: tv_ws_floats(c_int * S, 1).
+hipError_t tv_prox_batch(const Layout& L, int S, const float* b, float mu, const float* lam,
+                         float lam0, int iters, float* out, float* ws, hipStream_t s);
+// One volume of S slices in the internal order [c_int][S] (slice index
+// fastest), 3-D TV.  ws: tv_ws_floats(c_int * S, 2).
+hipError_t tv_prox_volume(const Layout& L, int S, const float* b, float theta, int iters,
+                          float* out, float* ws, hipStream_t s);
 
 }  // namespace bsgd

@@ -169,6 +169,57 @@ hipError_t launch_sumsq(const float* x, int64_t n, double* partial, double* out,
   return hipGetLastError();
 }
 
+// Per-column sums of squares of an [n][S] matrix (S a power of two).  Block
+// b covers rows b, b + kColBlocks, ...; with S <= 256 each thread keeps one
+// column (thread t: column t mod S) and the block adds its 256/S partials per
+// column in a fixed order; with S > 256 each thread keeps S/256 columns.  A
+// second kernel adds the kColBlocks partials of each column in order.
+__global__ __launch_bounds__(256) void k_colsumsq_partial(const float* __restrict__ X, int64_t n,
+                                                          int S, double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const int t = threadIdx.x;
+  if (S <= 256) {
+    const int j = t & (S - 1), per = 256 / S;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * per + t / S; i < n; i += (int64_t)kColBlocks * per) {
+      const double v = X[i * S + j];
+      acc += v * v;
+    }
+    sh[t] = acc;
+    __syncthreads();
+    if (t < S) {
+      double s = 0.0;
+      for (int m = 0; m < per; ++m) s += sh[t + m * S];
+      partial[(int64_t)blockIdx.x * S + t] = s;
+    }
+  } else {
+    for (int j = t; j < S; j += 256) {
+      double acc = 0.0;
+      for (int64_t i = blockIdx.x; i < n; i += kColBlocks) {
+        const double v = X[i * S + j];
+        acc += v * v;
+      }
+      partial[(int64_t)blockIdx.x * S + j] = acc;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_colsumsq_final(const double* __restrict__ partial, int S,
+                                                        double* __restrict__ out) {
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < S; j += gridDim.x * 256) {
+    double acc = 0.0;
+    for (int b = 0; b < kColBlocks; ++b) acc += partial[(int64_t)b * S + j];
+    out[j] = acc;
+  }
+}
+
+hipError_t launch_colsumsq(const float* X, int64_t n, int S, double* partial, double* out,
+                           hipStream_t s) {
+  k_colsumsq_partial<<<kColBlocks, 256, 0, s>>>(X, n, S, partial);
+  k_colsumsq_final<<<(S + 255) / 256, 256, 0, s>>>(partial, S, out);
+  return hipGetLastError();
+}
+
 }  // namespace bsgd
 
 extern "C" const char* bsgd_last_error(void) { return bsgd::g_error.c_str(); }

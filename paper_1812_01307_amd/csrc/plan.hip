@@ -306,22 +306,45 @@ __global__ __launch_bounds__(256) void k_tile_copy(
 }
 
 // ---------------------------------------------------------------------------
-// Vector permutations
+// Vector permutations (whole rows of S values move together)
 // ---------------------------------------------------------------------------
 __global__ void k_permute_in(Layout L, int kind, const float* __restrict__ nat,
-                             float* __restrict__ out, int64_t n_int) {
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_int;
-       k += (int64_t)gridDim.x * blockDim.x) {
+                             float* __restrict__ out, int64_t n_int, int S) {
+  const int64_t tot = n_int * S;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = q / S;
+    const int j = (int)(q - k * S);
     const int64_t src = kind == kPixels ? L.pix_out(k) : L.ray_out(k);
-    out[k] = src >= 0 ? nat[src] : 0.f;
+    out[q] = src >= 0 ? nat[src * S + j] : 0.f;
   }
 }
 
 __global__ void k_permute_out(Layout L, int kind, const float* __restrict__ in,
-                              float* __restrict__ nat, int64_t n) {
+                              float* __restrict__ nat, int64_t n, int S) {
+  const int64_t tot = n * S;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = q / S;
+    const int j = (int)(q - i * S);
+    nat[q] = in[(kind == kPixels ? L.pix_in(i) : L.ray_in(i)) * S + j];
+  }
+}
+
+__global__ void k_scatter_col(Layout L, int kind, const float* __restrict__ nat,
+                              float* __restrict__ mat, int64_t n_int, int S, int j) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_int;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t src = kind == kPixels ? L.pix_out(k) : L.ray_out(k);
+    mat[k * S + j] = (nat && src >= 0) ? nat[src] : 0.f;
+  }
+}
+
+__global__ void k_gather_col(Layout L, int kind, const float* __restrict__ mat,
+                             float* __restrict__ nat, int64_t n, int S, int j) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    nat[i] = in[kind == kPixels ? L.pix_in(i) : L.ray_in(i)];
+    nat[i] = mat[(kind == kPixels ? L.pix_in(i) : L.ray_in(i)) * S + j];
 }
 
 __global__ void k_fill_pixels_one(Layout L, float* __restrict__ v) {
@@ -335,17 +358,50 @@ static unsigned grid_of(int64_t n) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
 }
 
+static int64_t nat_len(const Layout& L, VecKind kind) {
+  return kind == kPixels ? (int64_t)L.H * L.W * L.D : L.nrows;
+}
+static int64_t int_len(const Layout& L, VecKind kind) {
+  return kind == kPixels ? L.c_int : L.r_int;
+}
+
 hipError_t permute_in(const Layout& L, VecKind kind, const float* nat, float* internal,
-                      hipStream_t s) {
-  const int64_t n = kind == kPixels ? L.c_int : L.r_int;
-  k_permute_in<<<grid_of(n), 256, 0, s>>>(L, kind, nat, internal, n);
+                      hipStream_t s, int S) {
+  const int64_t n = int_len(L, kind);
+  k_permute_in<<<grid_of(n * S), 256, 0, s>>>(L, kind, nat, internal, n, S);
   return hipGetLastError();
 }
 
 hipError_t permute_out(const Layout& L, VecKind kind, const float* internal, float* nat,
-                       hipStream_t s) {
-  const int64_t n = kind == kPixels ? (int64_t)L.H * L.W * L.D : L.nrows;
-  k_permute_out<<<grid_of(n), 256, 0, s>>>(L, kind, internal, nat, n);
+                       hipStream_t s, int S) {
+  const int64_t n = nat_len(L, kind);
+  k_permute_out<<<grid_of(n * S), 256, 0, s>>>(L, kind, internal, nat, n, S);
+  return hipGetLastError();
+}
+
+hipError_t scatter_column(const Layout& L, VecKind kind, const float* nat, float* internal,
+                          int S, int j, hipStream_t s) {
+  const int64_t n = int_len(L, kind);
+  k_scatter_col<<<grid_of(n), 256, 0, s>>>(L, kind, nat, internal, n, S, j);
+  return hipGetLastError();
+}
+
+hipError_t gather_column(const Layout& L, VecKind kind, const float* internal, float* nat, int S,
+                         int j, hipStream_t s) {
+  const int64_t n = nat_len(L, kind);
+  k_gather_col<<<grid_of(n), 256, 0, s>>>(L, kind, internal, nat, n, S, j);
+  return hipGetLastError();
+}
+
+__global__ void k_set_col(const float* __restrict__ v, float* __restrict__ mat, int64_t n, int S,
+                          int j) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    mat[k * S + j] = v[k];
+}
+
+hipError_t set_column(const float* v, float* mat, int64_t n, int S, int j, hipStream_t s) {
+  k_set_col<<<grid_of(n), 256, 0, s>>>(v, mat, n, S, j);
   return hipGetLastError();
 }
 

@@ -63,14 +63,41 @@ __device__ __forceinline__ float row_dot_f32(const int32_t* __restrict__ col,
   return acc0 + acc1;
 }
 
-// FP16 values: 8 entries per lane per chunk (32 B of columns, 16 B of values).
+// FP16 values: 8 entries per lane per chunk (32 B of columns, 16 B of
+// values), two chunks in flight per lane.
 template <int LPR, bool NT>
 __device__ __forceinline__ float row_dot_f16(const int32_t* __restrict__ col,
                                              const __half* __restrict__ val,
                                              const float* __restrict__ v, int64_t beg, int64_t end,
                                              int lane) {
   float acc0 = 0.f, acc1 = 0.f;
-  for (int64_t e = beg + 8 * lane; e < end; e += 8 * LPR) {
+  int64_t e = beg + 8 * lane;
+  for (; e + 8 * LPR < end; e += 16 * LPR) {
+    const int64_t e1 = e + 8 * LPR;
+    const i32x4 c0 = ld<NT>(reinterpret_cast<const i32x4*>(col + e));
+    const i32x4 c1 = ld<NT>(reinterpret_cast<const i32x4*>(col + e + 4));
+    const f16x8 a = ld<NT>(reinterpret_cast<const f16x8*>(val + e));
+    const i32x4 d0 = ld<NT>(reinterpret_cast<const i32x4*>(col + e1));
+    const i32x4 d1 = ld<NT>(reinterpret_cast<const i32x4*>(col + e1 + 4));
+    const f16x8 b = ld<NT>(reinterpret_cast<const f16x8*>(val + e1));
+    acc0 = fmaf((float)a[0], v[c0.x], acc0);
+    acc1 = fmaf((float)b[0], v[d0.x], acc1);
+    acc0 = fmaf((float)a[1], v[c0.y], acc0);
+    acc1 = fmaf((float)b[1], v[d0.y], acc1);
+    acc0 = fmaf((float)a[2], v[c0.z], acc0);
+    acc1 = fmaf((float)b[2], v[d0.z], acc1);
+    acc0 = fmaf((float)a[3], v[c0.w], acc0);
+    acc1 = fmaf((float)b[3], v[d0.w], acc1);
+    acc0 = fmaf((float)a[4], v[c1.x], acc0);
+    acc1 = fmaf((float)b[4], v[d1.x], acc1);
+    acc0 = fmaf((float)a[5], v[c1.y], acc0);
+    acc1 = fmaf((float)b[5], v[d1.y], acc1);
+    acc0 = fmaf((float)a[6], v[c1.z], acc0);
+    acc1 = fmaf((float)b[6], v[d1.z], acc1);
+    acc0 = fmaf((float)a[7], v[c1.w], acc0);
+    acc1 = fmaf((float)b[7], v[d1.w], acc1);
+  }
+  if (e < end) {
     const i32x4 c0 = ld<NT>(reinterpret_cast<const i32x4*>(col + e));
     const i32x4 c1 = ld<NT>(reinterpret_cast<const i32x4*>(col + e + 4));
     const f16x8 a = ld<NT>(reinterpret_cast<const f16x8*>(val + e));
@@ -313,3 +340,87 @@ extern "C" bsgd_status bsgd_backproject_block(const bsgd_plan* plan, bsgd_valtyp
                                stream));
   return BSGD_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Several right-hand sides (slices of a volume, or a batch of reconstructions
+// sharing A): V is [ncols_int][S], Y / XADD / OUT are [nrows_int][S], the RHS
+// index fastest.  One wavefront per (row, chunk of 256 RHS); each lane owns 4
+// consecutive RHS.  The row's entries are read once per chunk (every lane
+// reads the same column and value, so the wavefront issues one request), and
+// each entry gathers one 16-byte piece of V's row per lane (1 KB per
+// wavefront, coalesced).  Four entries are in flight per lane.
+// ---------------------------------------------------------------------------
+namespace bsgd {
+
+template <typename VT, int MODE>
+__global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ ptr,
+                                              const int32_t* __restrict__ col,
+                                              const VT* __restrict__ val,
+                                              const float* __restrict__ V,
+                                              const float* __restrict__ Y,
+                                              const float* __restrict__ XADD, float scale,
+                                              float* __restrict__ OUT, int64_t nrows, int S) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int j = blockIdx.y * 256 + (threadIdx.x & 63) * 4;
+  if (row >= nrows || j >= S) return;  // no cross-lane operations follow
+  const int64_t beg = ptr[row], end = ptr[row + 1];
+  f32x4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0, a2 = a0, a3 = a0;
+  for (int64_t e = beg; e < end; e += 4) {  // rows are padded to a multiple of 8
+    const int32_t c0 = col[e], c1 = col[e + 1], c2 = col[e + 2], c3 = col[e + 3];
+    const float w0 = (float)val[e], w1 = (float)val[e + 1], w2 = (float)val[e + 2],
+                w3 = (float)val[e + 3];
+    const f32x4 v0 = *reinterpret_cast<const f32x4*>(V + (int64_t)c0 * S + j);
+    const f32x4 v1 = *reinterpret_cast<const f32x4*>(V + (int64_t)c1 * S + j);
+    const f32x4 v2 = *reinterpret_cast<const f32x4*>(V + (int64_t)c2 * S + j);
+    const f32x4 v3 = *reinterpret_cast<const f32x4*>(V + (int64_t)c3 * S + j);
+    a0 += w0 * v0;
+    a1 += w1 * v1;
+    a2 += w2 * v2;
+    a3 += w3 * v3;
+  }
+  const f32x4 acc = (a0 + a1) + (a2 + a3);
+  const int64_t o = row * S + j;
+  f32x4 res;
+  if constexpr (MODE == kPlain) {
+    res = scale * acc;
+  } else if constexpr (MODE == kResidual) {
+    res = *reinterpret_cast<const f32x4*>(Y + o) - acc;
+  } else {
+    const f32x4 xa = *reinterpret_cast<const f32x4*>(XADD + o);
+    res.x = fmaf(scale, acc.x, xa.x);
+    res.y = fmaf(scale, acc.y, xa.y);
+    res.z = fmaf(scale, acc.z, xa.z);
+    res.w = fmaf(scale, acc.w, xa.w);
+  }
+  *reinterpret_cast<f32x4*>(OUT + o) = res;
+}
+
+template <int MODE>
+static hipError_t launch_spmm_mode(const Store& st, bsgd_valtype vt, const float* V,
+                                   const float* Y, const float* XADD, float scale, float* OUT,
+                                   int S, hipStream_t s) {
+  dim3 grid((unsigned)((st.nrows + 3) / 4), (unsigned)((S + 255) / 256));
+  if (grid.x == 0) return hipSuccess;
+  if (vt == BSGD_VAL_F16)
+    k_spmm<__half, MODE><<<grid, 256, 0, s>>>(st.ptr, st.col, st.val16, V, Y, XADD, scale, OUT,
+                                              st.nrows, S);
+  else
+    k_spmm<float, MODE><<<grid, 256, 0, s>>>(st.ptr, st.col, st.val, V, Y, XADD, scale, OUT,
+                                             st.nrows, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm(const Store& st, bsgd_valtype vt, RowMode mode, const float* V,
+                       const float* Y, const float* XADD, float scale, float* OUT, int S,
+                       hipStream_t s) {
+  switch (mode) {
+    case kPlain:
+      return launch_spmm_mode<kPlain>(st, vt, V, Y, XADD, scale, OUT, S, s);
+    case kResidual:
+      return launch_spmm_mode<kResidual>(st, vt, V, Y, XADD, scale, OUT, S, s);
+    default:
+      return launch_spmm_mode<kStep>(st, vt, V, Y, XADD, scale, OUT, S, s);
+  }
+}
+
+}  // namespace bsgd

@@ -16,8 +16,12 @@
 
 struct bsgd_state {
   const bsgd_plan* plan = nullptr;
-  int nrhs = 1;
+  int nrhs = 1;            // right-hand sides (vectors are [rows][nrhs], RHS fastest)
+  unsigned flags = 0;      // BSGD_STATE_VOLUME: the RHS are slices of one volume (3-D TV)
   bsgd_valtype vt = BSGD_VAL_F32;
+  float* lam = nullptr;    // nrhs per-RHS lambdas (batches of independent images)
+  float* tmp_r = nullptr;  // r_int: one-RHS scratch (slot initialisation)
+  float* tmp_c = nullptr;  // c_int
   float* y = nullptr;
   float* x[2] = {nullptr, nullptr};
   float* r[2] = {nullptr, nullptr};
@@ -66,19 +70,29 @@ static size_t power_layout(const bsgd_plan* p, void* ws, float** v, float** z, f
   return align_up(cv.off, kAlign);
 }
 
-// All state vectors are in the plan's internal orders (see bsgd::Layout).
-static size_t state_layout(const bsgd_plan* p, void* ws, bsgd_state* st) {
+// All state vectors are in the plan's internal orders (see bsgd::Layout),
+// [rows][nrhs] with the RHS index fastest.
+static size_t state_layout(const bsgd_plan* p, int S, unsigned flags, void* ws, bsgd_state* st) {
   Carver cv(ws);
-  const int64_t r = p->L.r_int, c = p->L.c_int;
+  const int64_t r = p->L.r_int * S, c = p->L.c_int * S;
   st->y = cv.take<float>(r);
   st->x[0] = cv.take<float>(c);
   st->x[1] = cv.take<float>(c);
   st->r[0] = cv.take<float>(r);
   st->r[1] = cv.take<float>(r);
   st->xhat = cv.take<float>(c);
-  st->tv_ws = cv.take<float>(tv_ws_floats(c, p->D));
-  st->partial = cv.take<double>(kReduceBlocks + 1);
+  const size_t tvf = S == 1 ? tv_ws_floats(p->L.c_int, p->D)
+                            : tv_ws_floats(c, (flags & BSGD_STATE_VOLUME) ? 2 : 1);
+  st->tv_ws = cv.take<float>(tvf);
+  st->partial = cv.take<double>(std::max<size_t>(kReduceBlocks + 1, (size_t)(kColBlocks + 1) * S));
+  st->lam = cv.take<float>(S);
+  st->tmp_r = cv.take<float>(p->L.r_int);
+  st->tmp_c = cv.take<float>(p->L.c_int);
   return align_up(cv.off, kAlign);
+}
+
+static bool valid_nrhs(int S) {
+  return S == 1 || (S >= 4 && S <= 1024 && (S & (S - 1)) == 0);
 }
 
 }  // namespace bsgd
@@ -127,20 +141,21 @@ extern "C" bsgd_status bsgd_power_umax(const bsgd_plan* plan, bsgd_valtype vt, i
   return BSGD_OK;
 }
 
-extern "C" bsgd_status bsgd_state_workspace_size(const bsgd_plan* plan, int nrhs, size_t* bytes) {
+extern "C" bsgd_status bsgd_state_workspace_size(const bsgd_plan* plan, int nrhs, unsigned flags,
+                                                 size_t* bytes) {
   clear_error();
   BSGD_REQUIRE(plan && bytes, "NULL argument");
-  if (nrhs != 1) {
-    set_error("nrhs = %d: only single right-hand sides are implemented", nrhs);
-    return BSGD_ERR_UNSUPPORTED;
-  }
+  BSGD_REQUIRE(valid_nrhs(nrhs), "nrhs must be 1 or a power of two from 4 to 1024");
+  BSGD_REQUIRE((flags & ~BSGD_STATE_VOLUME) == 0, "unknown state flags 0x%x", flags);
+  BSGD_REQUIRE(!(flags & BSGD_STATE_VOLUME) || (nrhs > 1 && plan->D == 1),
+               "a volume state needs nrhs > 1 slices and a 2-D plan");
   bsgd_state tmp;
-  *bytes = state_layout(plan, nullptr, &tmp);
+  *bytes = state_layout(plan, nrhs, flags, nullptr, &tmp);
   return BSGD_OK;
 }
 
 extern "C" bsgd_status bsgd_state_create(const bsgd_plan* plan, int nrhs, bsgd_valtype vt,
-                                         void* workspace, size_t workspace_bytes,
+                                         unsigned flags, void* workspace, size_t workspace_bytes,
                                          bsgd_state** out) {
   clear_error();
   BSGD_REQUIRE(plan && workspace && out, "NULL argument");
@@ -148,7 +163,7 @@ extern "C" bsgd_status bsgd_state_create(const bsgd_plan* plan, int nrhs, bsgd_v
   BSGD_REQUIRE(vt == BSGD_VAL_F32 || (vt == BSGD_VAL_F16 && (plan->flags & BSGD_PLAN_F16)),
                "value type not available in this plan");
   size_t need = 0;
-  bsgd_status s = bsgd_state_workspace_size(plan, nrhs, &need);
+  bsgd_status s = bsgd_state_workspace_size(plan, nrhs, flags, &need);
   if (s != BSGD_OK) return s;
   if (workspace_bytes < need) {
     set_error("state workspace has %zu bytes, needs %zu", workspace_bytes, need);
@@ -157,8 +172,9 @@ extern "C" bsgd_status bsgd_state_create(const bsgd_plan* plan, int nrhs, bsgd_v
   bsgd_state* st = new bsgd_state();
   st->plan = plan;
   st->nrhs = nrhs;
+  st->flags = flags;
   st->vt = vt;
-  state_layout(plan, workspace, st);
+  state_layout(plan, nrhs, flags, workspace, st);
   hipError_t e = hipStreamCreateWithFlags(&st->aux, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_main, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_aux, hipEventDisableTiming);
@@ -194,16 +210,22 @@ extern "C" bsgd_status bsgd_state_init(bsgd_state* st, const float* y, const flo
   clear_error();
   BSGD_REQUIRE(st && y, "NULL argument");
   const bsgd_plan* p = st->plan;
-  const int64_t r = p->L.r_int, c = p->L.c_int;
-  BSGD_HIP(permute_in(p->L, kRays, y, st->y, stream));
+  const int S = st->nrhs;
+  const int64_t r = p->L.r_int * S, c = p->L.c_int * S;
+  BSGD_HIP(permute_in(p->L, kRays, y, st->y, stream, S));
   st->cur = 0;
   BSGD_HIP(fill_f32(st->x[1], c, 0.0f, stream));
   BSGD_HIP(fill_f32(st->xhat, c, 0.0f, stream));
   BSGD_HIP(fill_f32(st->r[1], r, 0.0f, stream));
+  BSGD_HIP(fill_f32(st->lam, S, 0.0f, stream));
   if (x0) {
-    BSGD_HIP(permute_in(p->L, kPixels, x0, st->x[0], stream));
-    BSGD_HIP(launch_rows(p->fwd, st->vt, kResidual, st->x[0], st->y, nullptr, 1.0f, st->r[0],
-                         stream));
+    BSGD_HIP(permute_in(p->L, kPixels, x0, st->x[0], stream, S));
+    if (S == 1)
+      BSGD_HIP(launch_rows(p->fwd, st->vt, kResidual, st->x[0], st->y, nullptr, 1.0f, st->r[0],
+                           stream));
+    else
+      BSGD_HIP(launch_spmm(p->fwd, st->vt, kResidual, st->x[0], st->y, nullptr, 1.0f, st->r[0],
+                           S, stream));
   } else {
     BSGD_HIP(fill_f32(st->x[0], c, 0.0f, stream));
     BSGD_HIP(hipMemcpyAsync(st->r[0], st->y, sizeof(float) * r, hipMemcpyDeviceToDevice, stream));
@@ -221,8 +243,8 @@ extern "C" bsgd_status bsgd_state_load(bsgd_state* st, const float* x, const flo
   BSGD_REQUIRE(epoch >= 0, "epoch must be >= 0");
   const bsgd_plan* p = st->plan;
   st->cur = 0;
-  BSGD_HIP(permute_in(p->L, kPixels, x, st->x[0], stream));
-  BSGD_HIP(permute_in(p->L, kRays, r, st->r[0], stream));
+  BSGD_HIP(permute_in(p->L, kPixels, x, st->x[0], stream, st->nrhs));
+  BSGD_HIP(permute_in(p->L, kRays, r, st->r[0], stream, st->nrhs));
   st->epochs_done = epoch;
   return BSGD_OK;
 }
@@ -233,11 +255,15 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
   BSGD_REQUIRE(st != nullptr, "state is NULL");
   BSGD_REQUIRE(st->initialised, "state_init must be called first");
   BSGD_REQUIRE(std::isfinite(mu) && mu > 0.f, "mu must be finite and > 0");
-  BSGD_REQUIRE(std::isfinite(lam) && lam >= 0.f, "lam must be finite and >= 0");
+  BSGD_REQUIRE(std::isfinite(lam), "lam must be finite");
+  const bool per_rhs = lam < 0.f;
+  BSGD_REQUIRE(!per_rhs || (st->nrhs > 1 && !(st->flags & BSGD_STATE_VOLUME)),
+               "lam < 0 (per-RHS lambdas) needs a batch state");
   BSGD_REQUIRE(epochs >= 0, "epochs must be >= 0");
-  BSGD_REQUIRE(lam == 0.f || prox_iters >= 1, "prox_iters must be >= 1 when lam > 0");
+  BSGD_REQUIRE(lam == 0.f || prox_iters >= 1, "prox_iters must be >= 1 when lam != 0");
   const bsgd_plan* p = st->plan;
-  const float theta = mu * lam;
+  const int S = st->nrhs;
+  const float theta = per_rhs ? -1.f : mu * lam;  // -1: per-RHS thetas from st->lam
   for (int e = 0; e < epochs; ++e) {
     const int c = st->cur, n = 1 - c;
     hipEvent_t* tv = st->t_used < st->t_cap ? &st->tev[5 * (size_t)st->t_used++] : nullptr;
@@ -245,20 +271,36 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
     // `stream` before this epoch (overlap 0) or after S2 (overlap 1)
     if (st->overlap == 0) BSGD_HIP(hipEventRecord(st->ev_main, stream));
     if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
-    BSGD_HIP(launch_rows(p->bwd, st->vt, kStep, st->r[c], nullptr, st->x[c], 2.0f * mu,
-                         theta == 0.f ? st->x[n] : st->xhat, stream));
+    float* step_out = theta == 0.f ? st->x[n] : st->xhat;
+    if (S == 1)
+      BSGD_HIP(launch_rows(p->bwd, st->vt, kStep, st->r[c], nullptr, st->x[c], 2.0f * mu,
+                           step_out, stream));
+    else
+      BSGD_HIP(launch_spmm(p->bwd, st->vt, kStep, st->r[c], nullptr, st->x[c], 2.0f * mu,
+                           step_out, S, stream));
     if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
     if (st->overlap == 1) BSGD_HIP(hipEventRecord(st->ev_main, stream));
     BSGD_HIP(hipStreamWaitEvent(st->aux, st->ev_main, 0));
     if (tv) BSGD_HIP(hipEventRecord(tv[0], st->aux));
-    BSGD_HIP(launch_rows(p->fwd, st->vt, kResidual, st->x[c], st->y, nullptr, 1.0f, st->r[n],
-                         st->aux));
+    if (S == 1)
+      BSGD_HIP(launch_rows(p->fwd, st->vt, kResidual, st->x[c], st->y, nullptr, 1.0f, st->r[n],
+                           st->aux));
+    else
+      BSGD_HIP(launch_spmm(p->fwd, st->vt, kResidual, st->x[c], st->y, nullptr, 1.0f, st->r[n],
+                           S, st->aux));
     if (tv) BSGD_HIP(hipEventRecord(tv[1], st->aux));
     BSGD_HIP(hipEventRecord(st->ev_aux, st->aux));
     // S5 on `stream`
     if (theta != 0.f) {
-      BSGD_HIP(tv_prox_run(p->L, true, st->xhat, theta, prox_iters, st->x[n], st->tv_ws,
-                           stream));
+      if (S == 1)
+        BSGD_HIP(tv_prox_run(p->L, true, st->xhat, theta, prox_iters, st->x[n], st->tv_ws,
+                             stream));
+      else if (st->flags & BSGD_STATE_VOLUME)
+        BSGD_HIP(tv_prox_volume(p->L, S, st->xhat, theta, prox_iters, st->x[n], st->tv_ws,
+                                stream));
+      else
+        BSGD_HIP(tv_prox_batch(p->L, S, st->xhat, mu, per_rhs ? st->lam : nullptr, lam,
+                               prox_iters, st->x[n], st->tv_ws, stream));
     }
     if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));
     BSGD_HIP(hipStreamWaitEvent(stream, st->ev_aux, 0));
@@ -271,14 +313,14 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
 extern "C" bsgd_status bsgd_get_x(const bsgd_state* st, float* x, hipStream_t stream) {
   clear_error();
   BSGD_REQUIRE(st && x, "NULL argument");
-  BSGD_HIP(permute_out(st->plan->L, kPixels, st->x[st->cur], x, stream));
+  BSGD_HIP(permute_out(st->plan->L, kPixels, st->x[st->cur], x, stream, st->nrhs));
   return BSGD_OK;
 }
 
 extern "C" bsgd_status bsgd_get_r(const bsgd_state* st, float* r, hipStream_t stream) {
   clear_error();
   BSGD_REQUIRE(st && r, "NULL argument");
-  BSGD_HIP(permute_out(st->plan->L, kRays, st->r[st->cur], r, stream));
+  BSGD_HIP(permute_out(st->plan->L, kRays, st->r[st->cur], r, stream, st->nrhs));
   return BSGD_OK;
 }
 
@@ -286,7 +328,7 @@ extern "C" bsgd_status bsgd_get_stats(const bsgd_state* st, hipStream_t stream, 
                                       int64_t* epochs_done) {
   clear_error();
   BSGD_REQUIRE(st && res_norm2 && epochs_done, "NULL argument");
-  BSGD_HIP(launch_sumsq(st->r[st->cur], st->plan->L.r_int, st->partial,
+  BSGD_HIP(launch_sumsq(st->r[st->cur], st->plan->L.r_int * st->nrhs, st->partial,
                         st->partial + kReduceBlocks, stream));
   BSGD_HIP(hipMemcpyAsync(res_norm2, st->partial + kReduceBlocks, sizeof(double),
                           hipMemcpyDeviceToHost, stream));
@@ -350,4 +392,139 @@ extern "C" bsgd_status bsgd_state_set_overlap(bsgd_state* st, int mode) {
   BSGD_REQUIRE(mode == 0 || mode == 1, "overlap mode must be 0 or 1");
   st->overlap = mode;
   return BSGD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches of independent reconstructions: per-slot set-up, lambdas, results
+// ---------------------------------------------------------------------------
+extern "C" bsgd_status bsgd_state_set_rhs(bsgd_state* st, int k, const float* y, const float* x0,
+                                          hipStream_t stream) {
+  clear_error();
+  BSGD_REQUIRE(st != nullptr, "state is NULL");
+  BSGD_REQUIRE(st->initialised, "state_init must be called first");
+  BSGD_REQUIRE(k >= 0 && k < st->nrhs, "slot %d out of range", k);
+  const bsgd_plan* p = st->plan;
+  const Layout& L = p->L;
+  const int S = st->nrhs, c = st->cur;
+  // y == NULL empties the slot (all its vectors zero: it stays zero)
+  BSGD_HIP(scatter_column(L, kRays, y, st->y, S, k, stream));
+  BSGD_HIP(scatter_column(L, kPixels, x0, st->x[c], S, k, stream));
+  BSGD_HIP(scatter_column(L, kPixels, nullptr, st->x[1 - c], S, k, stream));
+  BSGD_HIP(scatter_column(L, kPixels, nullptr, st->xhat, S, k, stream));
+  BSGD_HIP(scatter_column(L, kRays, nullptr, st->r[1 - c], S, k, stream));
+  if (y && x0) {
+    // r = y - A x0 for this slot only (one-RHS product in internal order,
+    // in place over the permuted y, then into the slot's column)
+    BSGD_HIP(permute_in(L, kPixels, x0, st->tmp_c, stream));
+    BSGD_HIP(permute_in(L, kRays, y, st->tmp_r, stream));
+    BSGD_HIP(launch_rows(p->fwd, st->vt, kResidual, st->tmp_c, st->tmp_r, nullptr, 1.0f,
+                         st->tmp_r, stream));
+    BSGD_HIP(set_column(st->tmp_r, st->r[c], L.r_int, S, k, stream));
+  } else {
+    BSGD_HIP(scatter_column(L, kRays, y, st->r[c], S, k, stream));
+  }
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_state_set_lambda(bsgd_state* st, const float* lam, hipStream_t stream) {
+  clear_error();
+  BSGD_REQUIRE(st && lam, "NULL argument");
+  for (int j = 0; j < st->nrhs; ++j)
+    BSGD_REQUIRE(std::isfinite(lam[j]) && lam[j] >= 0.f, "lam[%d] must be finite and >= 0", j);
+  BSGD_HIP(hipMemcpyAsync(st->lam, lam, sizeof(float) * st->nrhs, hipMemcpyHostToDevice, stream));
+  BSGD_HIP(hipStreamSynchronize(stream));
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_get_x_rhs(const bsgd_state* st, int k, float* x, hipStream_t stream) {
+  clear_error();
+  BSGD_REQUIRE(st && x, "NULL argument");
+  BSGD_REQUIRE(k >= 0 && k < st->nrhs, "slot %d out of range", k);
+  BSGD_HIP(gather_column(st->plan->L, kPixels, st->x[st->cur], x, st->nrhs, k, stream));
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_get_stats_rhs(const bsgd_state* st, hipStream_t stream,
+                                          double* res_norm2) {
+  clear_error();
+  BSGD_REQUIRE(st && res_norm2, "NULL argument");
+  const int S = st->nrhs;
+  double* out = st->partial + (size_t)kColBlocks * S;
+  BSGD_HIP(launch_colsumsq(st->r[st->cur], st->plan->L.r_int, S, st->partial, out, stream));
+  BSGD_HIP(hipMemcpyAsync(res_norm2, out, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
+  BSGD_HIP(hipStreamSynchronize(stream));
+  for (int j = 0; j < S; ++j)
+    if (!std::isfinite(res_norm2[j])) {
+      set_error("residual norm of slot %d is not finite", j);
+      return BSGD_ERR_DIVERGED;
+    }
+  return BSGD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// HIP graph of a fixed number of epochs
+// ---------------------------------------------------------------------------
+struct bsgd_graph {
+  bsgd_state* st = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int epochs = 0;
+};
+
+extern "C" bsgd_status bsgd_graph_create(bsgd_state* st, float mu, float lam, int epochs,
+                                         int prox_iters, hipStream_t stream, bsgd_graph** out) {
+  clear_error();
+  BSGD_REQUIRE(st && out, "NULL argument");
+  BSGD_REQUIRE(epochs >= 2 && epochs % 2 == 0,
+               "a graph holds an even number of epochs (the iterate buffers alternate)");
+  BSGD_REQUIRE(stream != nullptr, "capture needs a non-default stream");
+  const int t_cap = st->t_cap, t_used = st->t_used;
+  st->t_cap = 0;  // no timing events inside the graph
+  const int64_t done = st->epochs_done;
+  const int cur = st->cur;
+  BSGD_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  bsgd_status s = bsgd_run_epochs(st, mu, lam, epochs, prox_iters, stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(stream, &g);
+  st->t_cap = t_cap;
+  st->t_used = t_used;
+  st->epochs_done = done;
+  st->cur = cur;
+  if (s != BSGD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) {
+    set_error("graph capture failed: %s", hipGetErrorString(e));
+    return BSGD_ERR_HIP;
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    set_error("graph instantiation failed: %s", hipGetErrorString(e));
+    return BSGD_ERR_HIP;
+  }
+  bsgd_graph* gr = new bsgd_graph();
+  gr->st = st;
+  gr->graph = g;
+  gr->exec = ex;
+  gr->epochs = epochs;
+  *out = gr;
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_graph_launch(bsgd_graph* gr, hipStream_t stream) {
+  clear_error();
+  BSGD_REQUIRE(gr != nullptr, "graph is NULL");
+  BSGD_HIP(hipGraphLaunch(gr->exec, stream));
+  gr->st->epochs_done += gr->epochs;
+  return BSGD_OK;
+}
+
+extern "C" void bsgd_graph_destroy(bsgd_graph* gr) {
+  if (!gr) return;
+  if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+  if (gr->graph) (void)hipGraphDestroy(gr->graph);
+  delete gr;
 }

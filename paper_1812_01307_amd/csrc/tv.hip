@@ -55,13 +55,16 @@ struct FuseArgs {
   float coef[kFuseMax + 1];  // coef[m] = c_{k0+m}
 };
 
+// A batch of S images shares the launch (blockIdx.z = image j, pixel (s, t)
+// of image j at index(s, t) * S + j); image j uses theta_j = mu * lam[j], or
+// theta0 when lam is null.  theta_j = 0 copies b (the prox is the identity).
 template <bool TILED>
 __global__ __launch_bounds__(kFThreads) void k_fgp_fused2(
-    Layout L, const float* __restrict__ b, float theta, float step, int k0, int iters,
-    FuseArgs ca, const float* __restrict__ in1v, const float* __restrict__ in1h,
-    const float* __restrict__ in2v, const float* __restrict__ in2h, float* __restrict__ out_x,
-    float* __restrict__ o1v, float* __restrict__ o1h, float* __restrict__ o2v,
-    float* __restrict__ o2h) {
+    Layout L, int S, const float* __restrict__ lam, float mu, float theta0,
+    const float* __restrict__ b, int k0, int iters, FuseArgs ca, const float* __restrict__ in1v,
+    const float* __restrict__ in1h, const float* __restrict__ in2v,
+    const float* __restrict__ in2h, float* __restrict__ out_x, float* __restrict__ o1v,
+    float* __restrict__ o1h, float* __restrict__ o2v, float* __restrict__ o2h) {
   __shared__ float sb[kFR * kFR];
   __shared__ float sav[kFR * kFR], sah[kFR * kFR];  // dual slot A
   __shared__ float sbv[kFR * kFR], sbh[kFR * kFR];  // dual slot B
@@ -71,6 +74,20 @@ __global__ __launch_bounds__(kFThreads) void k_fgp_fused2(
   const int R = kFT + 2 * h;
   const int s0 = blockIdx.y * kFT - h, t0 = blockIdx.x * kFT - h;  // image coords of LDS (0,0)
   const int tid = threadIdx.x;
+  const int img = blockIdx.z;
+  const float theta = lam ? mu * lam[img] : theta0;
+  if (theta == 0.f) {
+    if (out_x)
+      for (int q = tid; q < kFT * kFT; q += kFThreads) {
+        const int s = s0 + h + q / kFT, t = t0 + h + q % kFT;
+        if (s < H && t < W) {
+          const int64_t i = pidx<TILED>(L, 0, s, t) * S + img;
+          out_x[i] = b[i];
+        }
+      }
+    return;
+  }
+  const float step = 1.0f / (8.0f * theta);
 
   // load b and the incoming duals (p_{k0} -> slot A, p_{k0-1} -> slot B)
   for (int q = tid; q < R * R; q += kFThreads) {
@@ -78,7 +95,7 @@ __global__ __launch_bounds__(kFThreads) void k_fgp_fused2(
     const int s = s0 + ls, t = t0 + lt;
     float vb = 0.f, a1 = 0.f, a2 = 0.f, b1 = 0.f, b2 = 0.f;
     if (s >= 0 && s < H && t >= 0 && t < W) {
-      const int64_t i = pidx<TILED>(L, 0, s, t);
+      const int64_t i = pidx<TILED>(L, 0, s, t) * S + img;
       vb = b[i];
       if (k0 >= 1) {
         a1 = in1v[i];
@@ -163,7 +180,7 @@ __global__ __launch_bounds__(kFThreads) void k_fgp_fused2(
     const int s = s0 + ls, t = t0 + lt;
     if (s >= H || t >= W) continue;
     const int o = ls * kFR + lt;
-    const int64_t i = pidx<TILED>(L, 0, s, t);
+    const int64_t i = pidx<TILED>(L, 0, s, t) * S + img;
     if (out_x) {
       const float dn = s + 1 < H ? p1v[o + kFR] : 0.f;
       const float rt = t + 1 < W ? p1h[o + 1] : 0.f;
@@ -284,6 +301,12 @@ __global__ __launch_bounds__(256) void k_fgp_out3(Layout L, int64_t n,
   }
 }
 
+__global__ void k_copy_f32v(const float* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
 template <bool TILED>
 __global__ void k_copy_img(Layout L, const float* __restrict__ a, float* __restrict__ b) {
   const int64_t hw = (int64_t)L.H * L.W, tot = hw * L.D;
@@ -321,6 +344,37 @@ static void momentum(int iters, std::vector<float>& c) {
   }
 }
 
+// 2-D FGP over S images ([n][S] with n the per-image vector length) in chunks
+// of up to kFuseMax iterations, one fused launch each.  A chunk reads p_{k0}
+// and p_{k0-1} (every block reads a halo, so the outputs cannot overwrite
+// them) and writes p_{k0+L}, p_{k0+L-1} into the other two of four (pv, ph)
+// buffer pairs; the last chunk writes the result.
+template <bool TILED>
+static hipError_t fgp2_chunks(const Layout& L, int S, const float* b, float theta0,
+                              const float* lam, float mu, int iters, const std::vector<float>& c,
+                              float* out, float* ws, int64_t n, hipStream_t s) {
+  const int64_t m = n * S;
+  float* buf[4] = {ws, ws + 2 * m, ws + 4 * m, ws + 6 * m};
+  dim3 grid((L.W + kFT - 1) / kFT, (L.H + kFT - 1) / kFT, S);
+  int in = 0;  // p_{k0} in buf[in], p_{k0-1} in buf[in + 1]
+  for (int k0 = 0; k0 < iters;) {
+    const int chunk = std::min(kFuseMax, iters - k0);
+    FuseArgs ca{};
+    for (int q = 1; q <= chunk; ++q) ca.coef[q] = c[k0 + q];
+    const float* i1 = buf[in];
+    const float* i2 = buf[in + 1];
+    float* o1 = buf[2 - in];
+    float* o2 = buf[3 - in];
+    const bool last = k0 + chunk == iters;
+    k_fgp_fused2<TILED><<<grid, kFThreads, 0, s>>>(L, S, lam, mu, theta0, b, k0, chunk, ca, i1,
+                                                   i1 + m, i2, i2 + m, last ? out : nullptr, o1,
+                                                   o1 + m, o2, o2 + m);
+    in = 2 - in;
+    k0 += chunk;
+  }
+  return hipGetLastError();
+}
+
 template <bool TILED>
 static hipError_t tv_prox_impl(const Layout& L, const float* b, float theta, int iters,
                                float* out, float* ws, hipStream_t s) {
@@ -332,32 +386,7 @@ static hipError_t tv_prox_impl(const Layout& L, const float* b, float theta, int
   }
   std::vector<float> c;
   momentum(iters, c);
-  if (L.D == 1) {
-    // chunks of up to kFuseMax iterations, one fused launch each.  A chunk
-    // reads p_{k0} and p_{k0-1} (every block reads a halo, so the outputs
-    // cannot overwrite them) and writes p_{k0+L}, p_{k0+L-1} into the other
-    // two of four (pv, ph) buffer pairs; the last chunk writes the result.
-    float* buf[4] = {ws, ws + 2 * n, ws + 4 * n, ws + 6 * n};
-    const float step = 1.0f / (8.0f * theta);
-    dim3 grid((L.W + kFT - 1) / kFT, (L.H + kFT - 1) / kFT);
-    int in = 0;  // p_{k0} in buf[in], p_{k0-1} in buf[in + 1]
-    for (int k0 = 0; k0 < iters;) {
-      const int chunk = std::min(kFuseMax, iters - k0);
-      FuseArgs ca{};
-      for (int m = 1; m <= chunk; ++m) ca.coef[m] = c[k0 + m];
-      const float* i1 = buf[in];
-      const float* i2 = buf[in + 1];
-      float* o1 = buf[2 - in];
-      float* o2 = buf[3 - in];
-      const bool last = k0 + chunk == iters;
-      k_fgp_fused2<TILED><<<grid, kFThreads, 0, s>>>(
-          L, b, theta, step, k0, chunk, ca, i1, i1 + n, i2, i2 + n, last ? out : nullptr,
-          o1, o1 + n, o2, o2 + n);
-      in = 2 - in;
-      k0 += chunk;
-    }
-    return hipGetLastError();
-  }
+  if (L.D == 1) return fgp2_chunks<TILED>(L, 1, b, theta, nullptr, 1.f, iters, c, out, ws, n, s);
   float* buf[3] = {ws, ws + 3 * n, ws + 6 * n};  // (pd, pv, ph) triples
   float* q = ws + 9 * n;
   float* u = ws + 12 * n;
@@ -381,6 +410,148 @@ hipError_t tv_prox_run(const Layout& L, bool tiled, const float* b, float theta,
                        float* out, float* ws, hipStream_t s) {
   return tiled ? tv_prox_impl<true>(L, b, theta, iters, out, ws, s)
                : tv_prox_impl<false>(L, b, theta, iters, out, ws, s);
+}
+
+hipError_t tv_prox_batch(const Layout& L, int S, const float* b, float mu, const float* lam,
+                         float lam0, int iters, float* out, float* ws, hipStream_t s) {
+  std::vector<float> c;
+  momentum(std::max(iters, 1), c);
+  if (iters == 0) {
+    // identity for every image: one chunk-free copy through the theta = 0 path
+    return fgp2_chunks<true>(L, S, b, 0.f, nullptr, mu, 1, c, out, ws, L.c_int, s);
+  }
+  return fgp2_chunks<true>(L, S, b, mu * lam0, lam, mu, iters, c, out, ws, L.c_int, s);
+}
+
+// ---------------------------------------------------------------------------
+// 3-D FGP for a volume of S slices stored slice-minor in the internal pixel
+// order: voxel (d, s, t) at pix_st(s, t) * S + d.  One kernel per iteration:
+// a block owns one 8 x 8 memory tile of pixels times 32 slices, stages q on
+// the tile plus a one-voxel halo and u on the tile plus its lower-index halo
+// in LDS (the same recurrence as the 2-D kernels, with the difference across
+// slices added and step 1/(12 theta)).
+// ---------------------------------------------------------------------------
+constexpr int kVS = 8, kVD = 32;
+constexpr int kVQ = (kVS + 2) * (kVS + 2) * (kVD + 2);
+constexpr int kVU = (kVS + 1) * (kVS + 1) * (kVD + 1);
+
+__global__ __launch_bounds__(256) void k_fgp_iter3v(
+    Layout L, int S, const float* __restrict__ b, float theta, float step, float coef, int qmode,
+    const float* __restrict__ p1, const float* __restrict__ p2, float* __restrict__ po,
+    int64_t n) {
+  __shared__ float sq[3][kVQ];
+  __shared__ float su[kVU];
+  const int H = L.H, W = L.W;
+  const int tile = blockIdx.x;
+  const int s0 = (tile / L.Wt) * kVS, t0 = (tile % L.Wt) * kVS, d0 = blockIdx.y * kVD;
+  const int tid = threadIdx.x;
+  // q on s0-1..s0+8, t0-1..t0+8, d0-1..d0+32
+  for (int q = tid; q < kVQ; q += 256) {
+    const int ld = q % (kVD + 2), rest = q / (kVD + 2);
+    const int lt = rest % (kVS + 2), ls = rest / (kVS + 2);
+    const int s = s0 - 1 + ls, t = t0 - 1 + lt, d = d0 - 1 + ld;
+    float qa = 0.f, qb = 0.f, qc = 0.f;
+    if (qmode != kQZero && s >= 0 && s < H && t >= 0 && t < W && d >= 0 && d < S) {
+      const int64_t i = L.pix_st(0, s, t) * S + d;
+      const float a1 = p1[i], b1 = p1[n + i], c1 = p1[2 * n + i];
+      if (qmode == kQCopy) {
+        qa = a1;
+        qb = b1;
+        qc = c1;
+      } else {
+        qa = fmaf(coef, a1 - p2[i], a1);
+        qb = fmaf(coef, b1 - p2[n + i], b1);
+        qc = fmaf(coef, c1 - p2[2 * n + i], c1);
+      }
+    }
+    sq[0][q] = qa;  // depth component
+    sq[1][q] = qb;  // vertical
+    sq[2][q] = qc;  // horizontal
+  }
+  __syncthreads();
+  auto qi = [](int ls, int lt, int ld) { return (ls * (kVS + 2) + lt) * (kVD + 2) + ld; };
+  auto ui = [](int ls, int lt, int ld) { return (ls * (kVS + 1) + lt) * (kVD + 1) + ld; };
+  // u on s0-1..s0+7, t0-1..t0+7, d0-1..d0+31
+  for (int q = tid; q < kVU; q += 256) {
+    const int ld = q % (kVD + 1), rest = q / (kVD + 1);
+    const int lt = rest % (kVS + 1), ls = rest / (kVS + 1);
+    const int s = s0 - 1 + ls, t = t0 - 1 + lt, d = d0 - 1 + ld;
+    float u = 0.f;
+    if (s >= 0 && s < H && t >= 0 && t < W && d >= 0 && d < S) {
+      const int c = qi(ls, lt, ld);
+      const float dtq = (sq[0][c] - sq[0][qi(ls, lt, ld + 1)]) +
+                        (sq[1][c] - sq[1][qi(ls + 1, lt, ld)]) +
+                        (sq[2][c] - sq[2][qi(ls, lt + 1, ld)]);
+      u = b[L.pix_st(0, s, t) * S + d] - theta * dtq;
+    }
+    su[q] = u;
+  }
+  __syncthreads();
+  for (int q = tid; q < kVS * kVS * kVD; q += 256) {
+    const int ld = q % kVD, rest = q / kVD;
+    const int lt = rest % kVS, ls = rest / kVS;
+    const int s = s0 + ls, t = t0 + lt, d = d0 + ld;
+    if (s >= H || t >= W || d >= S) continue;
+    const int uc = ui(ls + 1, lt + 1, ld + 1);
+    const float u0 = su[uc];
+    const float gd = d >= 1 ? u0 - su[ui(ls + 1, lt + 1, ld)] : 0.f;
+    const float gv = s >= 1 ? u0 - su[ui(ls, lt + 1, ld + 1)] : 0.f;
+    const float gh = t >= 1 ? u0 - su[ui(ls + 1, lt, ld + 1)] : 0.f;
+    const int c = qi(ls + 1, lt + 1, ld + 1);
+    const float ad = fmaf(step, gd, sq[0][c]);
+    const float av = fmaf(step, gv, sq[1][c]);
+    const float ah = fmaf(step, gh, sq[2][c]);
+    const float nrm = fmaxf(1.f, sqrtf(ad * ad + av * av + ah * ah));
+    const int64_t i = L.pix_st(0, s, t) * S + d;
+    po[i] = ad / nrm;
+    po[n + i] = av / nrm;
+    po[2 * n + i] = ah / nrm;
+  }
+}
+
+// out = b - theta D^T p (volume, slice-minor)
+__global__ __launch_bounds__(256) void k_fgp_out3v(Layout L, int S, const float* __restrict__ b,
+                                                   float theta, const float* __restrict__ p,
+                                                   float* __restrict__ out, int64_t n) {
+  const int64_t tot = (int64_t)L.H * L.W * S;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < tot;
+       q += (int64_t)gridDim.x * 256) {
+    const int d = (int)(q % S);
+    const int64_t pix = q / S;
+    const int s = (int)(pix / L.W), t = (int)(pix % L.W);
+    const int64_t c = L.pix_st(0, s, t) * S + d;
+    const float nd = d + 1 < S ? p[c + 1] : 0.f;
+    const float nv = s + 1 < L.H ? p[n + L.pix_st(0, s + 1, t) * S + d] : 0.f;
+    const float nh = t + 1 < L.W ? p[2 * n + L.pix_st(0, s, t + 1) * S + d] : 0.f;
+    const float dtp = (p[c] - nd) + (p[n + c] - nv) + (p[2 * n + c] - nh);
+    out[c] = b[c] - theta * dtp;
+  }
+}
+
+hipError_t tv_prox_volume(const Layout& L, int S, const float* b, float theta, int iters,
+                          float* out, float* ws, hipStream_t s) {
+  const int64_t n = L.c_int * S;
+  if (theta == 0.f || iters == 0) {
+    k_copy_f32v<<<grid_for(n), 256, 0, s>>>(b, out, n);
+    return hipGetLastError();
+  }
+  std::vector<float> c;
+  momentum(iters, c);
+  float* buf[3] = {ws, ws + 3 * n, ws + 6 * n};  // (pd, pv, ph) triples
+  const float step = 1.0f / (12.0f * theta);
+  dim3 grid((unsigned)(L.Ht * L.Wt), (unsigned)((S + kVD - 1) / kVD));
+  int cur = 0;
+  for (int k = 1; k <= iters; ++k) {
+    float* o = buf[cur];
+    const float* p1 = buf[(cur + 2) % 3];
+    const float* p2 = buf[(cur + 1) % 3];
+    const int qm = k == 1 ? kQZero : (k == 2 ? kQCopy : kQMomentum);
+    k_fgp_iter3v<<<grid, 256, 0, s>>>(L, S, b, theta, step, c[k], qm, p1, p2, o, n);
+    cur = (cur + 1) % 3;
+  }
+  k_fgp_out3v<<<grid_for((int64_t)L.H * L.W * S), 256, 0, s>>>(L, S, b, theta,
+                                                               buf[(cur + 2) % 3], out, n);
+  return hipGetLastError();
 }
 
 // TV value (natural order): per-element isotropic difference length, FP64 partials.

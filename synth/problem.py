@@ -55,22 +55,33 @@ def _load():
             f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
             lib.siddon_count.argtypes = [ctypes.c_int] * 4 + [i64p]
             lib.siddon_count.restype = ctypes.c_int64
-            lib.siddon_fill.argtypes = [ctypes.c_int] * 4 + [i64p, i32p, f64p]
+            vp = ctypes.c_void_p
+            lib.siddon_fill.argtypes = [ctypes.c_int] * 4 + [i64p, i32p, vp, vp, vp, vp]
             lib.siddon_fill.restype = ctypes.c_int
+            f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
             lib.csr_transpose_f64.argtypes = [
                 ctypes.c_int64, ctypes.c_int64, i64p, i32p, f64p, i64p, i32p, f64p]
             lib.csr_transpose_f64.restype = ctypes.c_int
+            lib.csr_transpose_f32.argtypes = [
+                ctypes.c_int64, ctypes.c_int64, i64p, i32p, f32p, i64p, i32p, f32p]
+            lib.csr_transpose_f32.restype = ctypes.c_int
             lib.synth_num_threads.restype = ctypes.c_int
             _lib = lib
     return _lib
 
 
-def projection_matrix(H: int, W: int, n_ang: int, bins: int):
-    """Parallel-beam projection matrix as FP64 CSR (row_ptr, col, val).
+def _vptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def projection_matrix(H: int, W: int, n_ang: int, bins: int, dtype=np.float64, x=None):
+    """Parallel-beam projection matrix as CSR (row_ptr, col, val).
 
     Rows are rays (row index angle * bins + bin), columns are pixels
-    (row-major s * W + t); entries are exact chord lengths, columns
-    ascending within each row (geometry documented in siddon.c).
+    (row-major s * W + t); entries are exact chord lengths (computed in FP64,
+    stored as `dtype`), columns ascending within each row (geometry
+    documented in siddon.c).  With an image x (FP64, H*W), also returns
+    A x computed in FP64 from the unrounded lengths.
     """
     lib = _load()
     nrays = n_ang * bins
@@ -80,23 +91,36 @@ def projection_matrix(H: int, W: int, n_ang: int, bins: int):
         raise RuntimeError("projection generator: internal ordering check failed")
     row_ptr = np.zeros(nrays + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
+    del counts
     col = np.empty(nnz, dtype=np.int32)
-    val = np.empty(nnz, dtype=np.float64)
-    if lib.siddon_fill(H, W, n_ang, bins, row_ptr, col, val) != 0:
+    val = np.empty(nnz, dtype=dtype)
+    xd = None if x is None else np.ascontiguousarray(x, np.float64).ravel()
+    ax = None if x is None else np.empty(nrays, np.float64)
+    v64 = val if val.dtype == np.float64 else None
+    v32 = val if val.dtype == np.float32 else None
+    if v64 is None and v32 is None:
+        raise ValueError("dtype must be float64 or float32")
+    if lib.siddon_fill(H, W, n_ang, bins, row_ptr, col, _vptr(v64), _vptr(v32), _vptr(xd),
+                       _vptr(ax)) != 0:
         raise RuntimeError("projection generator: fill pass disagreed with count pass")
-    return row_ptr, col, val
+    return (row_ptr, col, val) if x is None else (row_ptr, col, val, ax)
 
 
 def transpose_csr(nrows: int, ncols: int, row_ptr, col, val):
-    """Stable transpose of an FP64 CSR matrix (rows of the result sorted)."""
+    """Stable transpose of a CSR matrix (FP64 or FP32 values; rows of the result sorted)."""
     lib = _load()
     nnz = int(row_ptr[-1])
     t_ptr = np.empty(ncols + 1, dtype=np.int64)
     t_col = np.empty(nnz, dtype=np.int32)
-    t_val = np.empty(nnz, dtype=np.float64)
-    rc = lib.csr_transpose_f64(nrows, ncols, np.ascontiguousarray(row_ptr, np.int64),
-                               np.ascontiguousarray(col, np.int32),
-                               np.ascontiguousarray(val, np.float64), t_ptr, t_col, t_val)
+    if val.dtype == np.float32:
+        t_val = np.empty(nnz, dtype=np.float32)
+        fn = lib.csr_transpose_f32
+    else:
+        t_val = np.empty(nnz, dtype=np.float64)
+        fn = lib.csr_transpose_f64
+        val = np.ascontiguousarray(val, np.float64)
+    rc = fn(nrows, ncols, np.ascontiguousarray(row_ptr, np.int64),
+            np.ascontiguousarray(col, np.int32), val, t_ptr, t_col, t_val)
     if rc != 0:
         raise RuntimeError("transpose: column index out of range")
     return t_ptr, t_col, t_val
@@ -199,20 +223,18 @@ CONFIGS = {
 }
 
 
-def _forward_f64(row_ptr, col, val, x):
-    """y = A x through scipy's CSR product (data synthesis only)."""
-    import scipy.sparse as sp
-    nrows = len(row_ptr) - 1
-    A = sp.csr_matrix((val, col, row_ptr), shape=(nrows, x.shape[0]))
-    return A @ x
-
-
 def make_problem(name: str | None = None, *, n: int | None = None, H: int | None = None,
                  W: int | None = None, n_ang: int | None = None, bins: int | None = None,
                  M: int = 1, N: int = 1, noise: float = 0.01, lam: float = 0.0,
                  epochs: int = 10, prox_iters: int = 20, seed: int = 0,
-                 n_ellipses: int = 10, with_transpose: bool = True) -> Problem:
-    """Build a named configuration (see the module docstring) or a custom one."""
+                 n_ellipses: int = 10, with_transpose: bool = True,
+                 dtype=np.float64) -> Problem:
+    """Build a named configuration (see the module docstring) or a custom one.
+
+    dtype = np.float32 stores the matrix values rounded to FP32 (for the
+    device path of the large workloads); the projections y are computed in
+    FP64 from the unrounded lengths either way.
+    """
     if name is not None:
         cfg = dict(CONFIGS[name])
         n, n_ang, bins, M, N = cfg["n"], cfg["n_ang"], cfg["bins"], cfg["M"], cfg["N"]
@@ -222,10 +244,9 @@ def make_problem(name: str | None = None, *, n: int | None = None, H: int | None
     W = W if W is not None else n
     if bins is None:
         bins = int(np.ceil(max(H, W) * np.sqrt(2.0))) | 1
-    row_ptr, col, val = projection_matrix(H, W, n_ang, bins)
-    row_off, col_off = block_offsets(n_ang, bins, H * W, M, N)
     x_true = ellipse_phantom(H, W, n_ellipses, seed)
-    ax = _forward_f64(row_ptr, col, val, x_true.ravel())
+    row_ptr, col, val, ax = projection_matrix(H, W, n_ang, bins, dtype=dtype, x=x_true)
+    row_off, col_off = block_offsets(n_ang, bins, H * W, M, N)
     sigma = noise * float(np.max(ax)) if ax.size else 0.0
     rng = np.random.default_rng(seed + 10**6)
     y = ax + sigma * rng.standard_normal(ax.shape[0])

@@ -29,9 +29,10 @@
  *
  * Exported (C ABI, used from Python through ctypes):
  *   siddon_count     per-ray entry counts
- *   siddon_fill      CSR column indices and FP64 lengths
- *   csr_transpose_f64  stable counting-sort transpose (rows of A^T sorted
- *                      by ray index)
+ *   siddon_fill      CSR column indices and lengths (FP64 or FP32), and
+ *                    optionally the FP64 projections of an image
+ *   csr_transpose_f64 / _f32  stable counting-sort transpose (rows of A^T
+ *                    sorted by ray index)
  */
 #include <math.h>
 #include <stdint.h>
@@ -237,9 +238,14 @@ int64_t siddon_count(int H, int W, int n_ang, int bins, int64_t* counts) {
   return total;
 }
 
-/* Fill CSR columns and lengths given row_ptr (nrays+1) from the counts. */
+/*
+ * Fill CSR columns and lengths given row_ptr (nrays+1) from the counts.
+ * Lengths go to val64 (FP64) or, when val64 is NULL, to val32 (rounded to
+ * FP32).  When x is not NULL, ax[ray] = sum of length * x[col] over the row
+ * in column order, in FP64 (the noiseless projections of an image x).
+ */
 int siddon_fill(int H, int W, int n_ang, int bins, const int64_t* row_ptr,
-                int32_t* col, double* val) {
+                int32_t* col, double* val64, float* val32, const double* x, double* ax) {
   const int64_t nrays = (int64_t)n_ang * bins;
   int err = 0;
 #pragma omp parallel reduction(| : err)
@@ -259,10 +265,16 @@ int siddon_fill(int H, int W, int n_ang, int bins, const int64_t* row_ptr,
         continue;
       }
       const int64_t base = row_ptr[ray];
+      double acc = 0.0;
       for (int k = 0; k < n; ++k) {
         col[base + k] = buf[k].col;
-        val[base + k] = buf[k].len;
+        if (val64)
+          val64[base + k] = buf[k].len;
+        else
+          val32[base + k] = (float)buf[k].len;
+        if (x) acc += buf[k].len * x[buf[k].col];
       }
+      if (ax) ax[ray] = acc;
     }
     free(buf);
     free(lam);
@@ -272,32 +284,79 @@ int siddon_fill(int H, int W, int n_ang, int bins, const int64_t* row_ptr,
 }
 
 /*
- * Stable counting-sort transpose of a CSR matrix (nrows x ncols) with FP64
- * values: row k of the result lists the original rows holding column k in
- * ascending order.  t_ptr has ncols+1 entries.  Returns 0, or -1 if a
- * column index is out of range.
+ * Stable counting-sort transpose of a CSR matrix (nrows x ncols): row k of
+ * the result lists the original rows holding column k in ascending order.
+ * t_ptr has ncols+1 entries.  Threads own contiguous row ranges; per-thread
+ * column histograms give each thread its write offsets, so the result is
+ * the same as a serial pass.  Returns 0, or -1 if a column index is out of
+ * range.
  */
-int csr_transpose_f64(int64_t nrows, int64_t ncols, const int64_t* row_ptr,
-                      const int32_t* col, const double* val, int64_t* t_ptr,
-                      int32_t* t_col, double* t_val) {
-  memset(t_ptr, 0, sizeof(int64_t) * (size_t)(ncols + 1));
-  const int64_t nnz = row_ptr[nrows];
-  for (int64_t e = 0; e < nnz; ++e) {
-    if (col[e] < 0 || col[e] >= ncols) return -1;
-    t_ptr[col[e] + 1]++;
+#define DEFINE_TRANSPOSE(NAME, T)                                                      \
+  int NAME(int64_t nrows, int64_t ncols, const int64_t* row_ptr, const int32_t* col,    \
+           const T* val, int64_t* t_ptr, int32_t* t_col, T* t_val) {                    \
+    int nth = 1;                                                                        \
+    _Pragma("omp parallel") _Pragma("omp single") nth = synth_threads_();               \
+    int64_t* hist = (int64_t*)calloc((size_t)nth * (size_t)ncols, sizeof(int64_t));     \
+    if (!hist) return -2;                                                               \
+    int bad = 0;                                                                        \
+    _Pragma("omp parallel num_threads(nth) reduction(| : bad)") {                       \
+      const int t = synth_thread_id_();                                                 \
+      const int64_t r0 = nrows * t / nth, r1 = nrows * (t + 1) / nth;                   \
+      int64_t* h = hist + (size_t)t * ncols;                                            \
+      for (int64_t e = row_ptr[r0]; e < row_ptr[r1]; ++e) {                             \
+        if (col[e] < 0 || col[e] >= ncols)                                              \
+          bad = 1;                                                                      \
+        else                                                                            \
+          h[col[e]]++;                                                                  \
+      }                                                                                 \
+    }                                                                                   \
+    if (bad) {                                                                          \
+      free(hist);                                                                       \
+      return -1;                                                                        \
+    }                                                                                   \
+    int64_t run = 0;                                                                    \
+    for (int64_t k = 0; k < ncols; ++k) {                                               \
+      t_ptr[k] = run;                                                                   \
+      for (int t = 0; t < nth; ++t) {                                                   \
+        const int64_t c = hist[(size_t)t * ncols + k];                                  \
+        hist[(size_t)t * ncols + k] = run;                                              \
+        run += c;                                                                       \
+      }                                                                                 \
+    }                                                                                   \
+    t_ptr[ncols] = run;                                                                 \
+    _Pragma("omp parallel num_threads(nth)") {                                          \
+      const int t = synth_thread_id_();                                                 \
+      const int64_t r0 = nrows * t / nth, r1 = nrows * (t + 1) / nth;                   \
+      int64_t* cur = hist + (size_t)t * ncols;                                          \
+      for (int64_t row = r0; row < r1; ++row)                                           \
+        for (int64_t e = row_ptr[row]; e < row_ptr[row + 1]; ++e) {                     \
+          const int64_t dst = cur[col[e]]++;                                            \
+          t_col[dst] = (int32_t)row;                                                    \
+          t_val[dst] = val[e];                                                          \
+        }                                                                               \
+    }                                                                                   \
+    free(hist);                                                                         \
+    return 0;                                                                           \
   }
-  for (int64_t k = 0; k < ncols; ++k) t_ptr[k + 1] += t_ptr[k];
-  int64_t* cursor = (int64_t*)malloc(sizeof(int64_t) * (size_t)ncols);
-  memcpy(cursor, t_ptr, sizeof(int64_t) * (size_t)ncols);
-  for (int64_t row = 0; row < nrows; ++row)
-    for (int64_t e = row_ptr[row]; e < row_ptr[row + 1]; ++e) {
-      const int64_t dst = cursor[col[e]]++;
-      t_col[dst] = (int32_t)row;
-      t_val[dst] = val[e];
-    }
-  free(cursor);
-  return 0;
+
+static int synth_threads_(void) {
+#ifdef _OPENMP
+  return omp_get_num_threads();
+#else
+  return 1;
+#endif
 }
+
+static int synth_thread_id_(void) {
+#ifdef _OPENMP
+  return omp_get_thread_num();
+#else
+  return 0;
+#endif
+}
+
+DEFINE_TRANSPOSE(csr_transpose_f32, float)
+DEFINE_TRANSPOSE(csr_transpose_f64, double)
 
 int synth_num_threads(void) {
 #ifdef _OPENMP

@@ -414,3 +414,28 @@ def test_epoch_is_line8_then_line9():
     assert np.max(np.abs(x_new.reshape(p.H, p.W) - ref)) < 1e-4
     far, _ = _pdhg_tv(xhat, 2.0 * mu * lam, 40000)
     assert np.max(np.abs(far - ref)) > 1e-2
+
+
+def test_multi_rhs_batch_equals_independent_runs():
+    """A batch of S right-hand sides with per-RHS lambdas decouples into S single runs."""
+    p, A = _tiny(n=8, n_ang=10, bins=13)
+    mu = oracle.step_size(oracle.power_umax(A))
+    rng = np.random.default_rng(12)
+    Y = np.stack([p.y, A @ rng.random(p.ncols), p.y * 0.5, np.zeros(p.nrows)])
+    lam = np.array([30.0, 0.0, 5.0, 12.0])
+    X, R = oracle.bsgd_tv_multi(A, Y, mu, lam, 6, 20, (p.H, p.W), volume=False)
+    for j in range(4):
+        xj, rj = oracle.bsgd_tv(A, Y[j], mu, lam[j], 6, 20, (p.H, p.W))
+        assert np.allclose(X[j], xj, rtol=0, atol=1e-13) and np.allclose(R[j], rj, rtol=0, atol=1e-12)
+
+
+def test_multi_rhs_volume_of_identical_slices_is_2d():
+    """Identical slices: the 3-D TV across them adds nothing; the converged prox is the 2-D one."""
+    p, A = _tiny(n=8, n_ang=10, bins=13)
+    mu = oracle.step_size(oracle.power_umax(A))
+    Y = np.stack([p.y] * 3)
+    lam = 3000.0
+    X3, _ = oracle.bsgd_tv_multi(A, Y, mu, lam, 3, 4000, (p.H, p.W), volume=True)
+    x2, _ = oracle.bsgd_tv(A, p.y, mu, lam, 3, 4000, (p.H, p.W))
+    for j in range(3):
+        assert np.max(np.abs(X3[j] - x2)) < 1e-6 * np.max(np.abs(x2))

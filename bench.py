@@ -65,6 +65,9 @@ def main(argv=None):
     ap.add_argument("--autotune", action="store_true", help="time lane counts during plan creation")
     ap.add_argument("--overlap", type=int, default=1, choices=[0, 1],
                     help="epoch schedule: forward pass concurrent with backprojection (0) or after it (1)")
+    ap.add_argument("--prox-schedule", type=int, default=None, choices=[0, 1],
+                    help="2-D prox kernels: 0 fused chunks, 1 one launch per iteration "
+                         "(default: the library's)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--mu-file", default=None,
@@ -72,6 +75,17 @@ def main(argv=None):
                          "the jobs then skip the power iteration")
     ap.add_argument("--dump", default=None, help="save the iterate every --dump-every epochs (npz)")
     ap.add_argument("--dump-every", type=int, default=50)
+    ap.add_argument("--slices", type=int, default=256,
+                    help="volume workload (--config c4_vol): number of slices")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="volume workload: run the epochs eagerly instead of graph replays")
+    ap.add_argument("--requests", type=int, default=160,
+                    help="serving workload (--config c5_serve): number of requests")
+    ap.add_argument("--rate", type=float, default=40.0, help="serving: mean arrivals per second")
+    ap.add_argument("--slots", type=int, default=8, help="serving: slots per batch state")
+    ap.add_argument("--chunk", type=int, default=10, help="serving: epochs between stop checks")
+    ap.add_argument("--no-unbatched", action="store_true",
+                    help="serving: skip the one-request-at-a-time comparison run")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -94,7 +108,11 @@ def main(argv=None):
     import synth
     import paper_1812_01307_amd as bsgd
 
-    dev = torch.device("cuda:0")
+    if args.config == "c4_vol":
+        return run_volume(args, np, torch, synth, bsgd)
+    if args.config == "c5_serve":
+        return run_serve(args, np, torch, synth, bsgd)
+
     print(f"[bench] generating {args.config}", file=sys.stderr, flush=True)
     t_gen = time.perf_counter()
     # FP32 matrix values for the device (the projections y are FP64-computed)
@@ -146,6 +164,8 @@ def main(argv=None):
             mu = fixed_mu
         st = bsgd.bsgd_state_create(plan, 1, vt)
         bsgd.bsgd_state_set_overlap(st, args.overlap)
+        if args.prox_schedule is not None:
+            bsgd.bsgd_state_set_prox_schedule(st, args.prox_schedule)
         if record and timing:
             bsgd.bsgd_state_enable_timing(st, epochs)
         bsgd.bsgd_state_init(st, y)
@@ -182,6 +202,8 @@ def main(argv=None):
     # epoch-only rate (no setup), for context
     st2 = bsgd.bsgd_state_create(plan, 1, vt)
     bsgd.bsgd_state_set_overlap(st2, args.overlap)
+    if args.prox_schedule is not None:
+        bsgd.bsgd_state_set_prox_schedule(st2, args.prox_schedule)
     bsgd.bsgd_state_init(st2, y)
     torch.cuda.synchronize()
     te = time.perf_counter()
@@ -271,6 +293,262 @@ def main(argv=None):
         "roofline": roofline,
         "cpu_baseline": cpu,
         "quality": {"res_norm2": rn2, "rel_err_vs_phantom": round(rel_err_true, 5)},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_volume(args, np, torch, synth, bsgd):
+    """Batched volume: S slices of the 512 x 512 geometry share one A.
+
+    One step = one whole job: plan (S0), power iteration (S0'), a state with
+    S right-hand sides and the 3-D TV prox, then 200 epochs replayed as a HIP
+    graph of two epochs.  The value is slice-epochs per second.
+    """
+    S = args.slices
+    print(f"[bench] generating c4_vol with {S} slices", file=sys.stderr, flush=True)
+    t_gen = time.perf_counter()
+    prob = synth.make_volume_problem(S=S, dtype=np.float32)
+    tp, tc, tv = prob.ensure_transpose()
+    t_gen = time.perf_counter() - t_gen
+    epochs = args.epochs or prob.epochs
+    if epochs % 2 and not args.no_graph:
+        epochs += 1  # the graph holds two epochs
+    K = prob.prox_iters
+    vt = bsgd.BSGD_VAL_F16 if args.vt == "f16" else bsgd.BSGD_VAL_F32
+    flags = bsgd.BSGD_PLAN_F16 if vt == bsgd.BSGD_VAL_F16 else 0
+    r, c, nnz = prob.nrows, prob.ncols, prob.nnz
+    A = (r, c, bsgd.to_device(prob.row_ptr, torch.int64), bsgd.to_device(prob.col, torch.int32),
+         bsgd.to_device(prob.val, torch.float32))
+    At = (c, r, bsgd.to_device(tp, torch.int64), bsgd.to_device(tc, torch.int32),
+          bsgd.to_device(tv, torch.float32))
+    # [r][S]: slice index fastest
+    Y = bsgd.to_device(np.ascontiguousarray(prob.y.T.astype(np.float32)), torch.float32)
+    torch.cuda.synchronize()
+    print(f"[bench] nnz={nnz} rows={r} cols={c} slices={S} gen={t_gen:.1f}s", file=sys.stderr,
+          flush=True)
+    timing = not args.no_kernel_timing
+    acc = {"fwd": 0.0, "bwd": 0.0, "prox": 0.0, "n": 0}
+    stream = torch.cuda.Stream()  # graph capture needs a non-default stream
+
+    def job(graph, n_epochs=epochs, timed=False):
+        plan = bsgd.bsgd_plan_create(A, At, prob.M, prob.N, prob.row_off, prob.col_off, prob.H,
+                                     prob.W, 1, prob.bins, flags)
+        u = bsgd.bsgd_power_umax(plan, args.power_iters, vt=vt)
+        mu = 0.9 / (2.0 * u)
+        st = bsgd.bsgd_state_create(plan, S, vt, flags=bsgd.BSGD_STATE_VOLUME)
+        if timed:
+            bsgd.bsgd_state_enable_timing(st, n_epochs)
+        bsgd.bsgd_state_init(st, Y)
+        if graph:
+            g = bsgd.bsgd_graph_create(st, mu, prob.lam, 2, K)
+            for _ in range(n_epochs // 2):
+                bsgd.bsgd_graph_launch(g)
+        else:
+            bsgd.bsgd_run_epochs(st, mu, prob.lam, n_epochs, K)
+        x = bsgd.bsgd_get_x(st)
+        if timed:
+            f, b, p, n = bsgd.bsgd_state_timing(st)
+            acc["fwd"] += f
+            acc["bwd"] += b
+            acc["prox"] += p
+            acc["n"] += n
+        return st, x, mu, plan
+
+    graph = not args.no_graph
+    with torch.cuda.stream(stream):
+        for w in range(args.warmup):
+            job(graph)
+            torch.cuda.synchronize()
+            print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            st, x, mu, plan = job(graph)
+            torch.cuda.synchronize()
+            print(f"[bench] step {k + 1}/{args.steps}", file=sys.stderr, flush=True)
+        t1 = time.perf_counter()
+        Xh = x.cpu().numpy().astype(np.float64).reshape(c, S).T
+        if timing:
+            # kernel timers are not captured into graphs: one eager job with events
+            job(False, n_epochs=min(epochs, 20), timed=True)
+            torch.cuda.synchronize()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = S * epochs * args.steps / (t1 - t0)
+    rel = float(np.linalg.norm(Xh - prob.x_true.reshape(S, -1)) / np.linalg.norm(prob.x_true))
+
+    val_bytes = 2 if vt == bsgd.BSGD_VAL_F16 else 4
+    nvox = c * S
+    b_fwd = (val_bytes + 4) * nnz + 8 * (r + 1) + 4 * S * (c + 2 * r)
+    b_bwd = (val_bytes + 4) * nnz + 8 * (c + 1) + 4 * S * (r + 2 * c)
+    b_prox = 40 * nvox * K  # per 3-D FGP iteration: b, two dual triples in, one out
+    kernel, roofline = {}, None
+    if timing and acc["n"]:
+        f_ms, b_ms, p_ms = (acc[k] / acc["n"] for k in ("fwd", "bwd", "prox"))
+        kernel = {"fwd_ms": f_ms, "bwd_ms": b_ms, "prox_ms": p_ms,
+                  "fwd_gbs": b_fwd / f_ms / 1e6, "bwd_gbs": b_bwd / b_ms / 1e6,
+                  "prox_gbs": b_prox / p_ms / 1e6}
+        dom = max((("fwd", b_fwd, f_ms), ("bwd", b_bwd, b_ms), ("prox", b_prox, p_ms)),
+                  key=lambda t: t[2])
+        achieved = dom[1] / dom[2] / 1e6
+        roofline = {"bound": "hbm", "kernel": {"fwd": "k_spmm (A X)", "bwd": "k_spmm (A^T R)",
+                                               "prox": "3-D FGP (K iterations)"}[dom[0]],
+                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "alg_bytes_per_launch": dom[1]}
+    out = {
+        "metric": "BSGD-TV epochs/s + HBM GB/s vs peak; served recon p50/p99 latency",
+        "value": round(value, 1),
+        "unit": "slice-epochs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if vt == bsgd.BSGD_VAL_F32 else "f16-values/f32-accumulate",
+        "data": "synthetic",
+        "config": {"workload": f"c4_vol: {S} slices of {prob.H}x{prob.W} sharing one A "
+                               f"({prob.n_ang} angles x {prob.bins} bins, M=N={prob.M}), 3-D TV, "
+                               f"lambda={prob.lam}, {epochs} epochs, {K} FGP iterations, "
+                               f"setup S0+S0' included",
+                   "nnz": nnz, "slices": S, "epochs_per_step": epochs,
+                   "graph": graph,
+                   "kernel_timing": "events on one eager 20-epoch job after the timed region"},
+        "alg_bytes_per_epoch": b_fwd + b_bwd + b_prox,
+        "kernels": {k: round(v, 4) for k, v in kernel.items()},
+        "roofline": roofline,
+        "cpu_baseline": None,
+        "quality": {"rel_err_vs_phantoms": round(rel, 5)},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+C5_SIZES = (128, 256, 512, 768, 1024)
+C5_ANGLES = (180, 360, 720, 1440)
+
+
+def _c5_bins(n):
+    """Smallest odd detector count covering the image diagonal (n sqrt 2)."""
+    import math
+    b = math.ceil(n * math.sqrt(2.0))
+    return b if b % 2 else b + 1
+
+
+def run_serve(args, np, torch, synth, bsgd):
+    """Serving: a seeded Poisson stream of independent reconstructions over 20
+    resident geometries, served with continuous batching and, for comparison,
+    one request at a time on the one-RHS path.  Latency = completion - arrival.
+    """
+    from paper_1812_01307_amd.serve import DeviceBackend, Request, Server, percentile
+
+    rng = np.random.default_rng(2024)
+    nreq = args.requests
+    gaps = rng.exponential(1.0 / args.rate, nreq)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    geoms = [(n, a) for n in C5_SIZES for a in C5_ANGLES]
+    pick = rng.integers(0, len(geoms), nreq)
+    lams = rng.uniform(0.002, 0.02, nreq).astype(np.float32)
+    be = DeviceBackend()
+    resident = {}
+    ys = {}
+    total_nnz = 0
+    t_gen = time.perf_counter()
+    for gi, (n, ang) in enumerate(geoms):
+        ks = [k for k in range(nreq) if pick[k] == gi]
+        bins = _c5_bins(n)
+        X = (np.stack([synth.ellipse_phantom(n, n, 10, 10**6 + k) for k in ks]) if ks
+             else np.zeros((1, n * n)))
+        rp, col, val, AX = synth.projection_matrix(n, n, ang, bins, dtype=np.float32, x=X)
+        AX = AX.reshape(len(X), -1)
+        tp, tc, tv = synth.transpose_csr(ang * bins, n * n, rp, col, val)
+        row_off, col_off = synth.block_offsets(ang, bins, n * n, 8, 8)
+        A = (ang * bins, n * n, bsgd.to_device(rp, torch.int64), bsgd.to_device(col, torch.int32),
+             bsgd.to_device(val, torch.float32))
+        At = (n * n, ang * bins, bsgd.to_device(tp, torch.int64),
+              bsgd.to_device(tc, torch.int32), bsgd.to_device(tv, torch.float32))
+        plan = bsgd.bsgd_plan_create(A, At, 8, 8, row_off, col_off, n, n, 1, bins, 0)
+        geo = be.geometry(plan, power_iters=args.power_iters, prox_iters=20)
+        torch.cuda.synchronize()
+        del A, At
+        total_nnz += len(col)
+        for i, k in enumerate(ks):
+            y = AX[i] + 0.01 * float(np.max(AX[i])) * \
+                np.random.default_rng(2 * 10**6 + k).standard_normal(AX.shape[1])
+            ys[k] = bsgd.to_device(y.astype(np.float32), torch.float32)
+        resident[(n, ang)] = geo
+        del rp, col, val, tp, tc, tv, AX, X
+        print(f"[bench] geometry {gi + 1}/20: {n}^2, {ang} angles x {bins} bins, "
+              f"{len(ks)} requests", file=sys.stderr, flush=True)
+    t_gen = time.perf_counter() - t_gen
+    plan_bytes = sum(g.plan.workspace.numel() for g in resident.values())
+    print(f"[bench] geometries resident: {total_nnz} nnz, {plan_bytes / 1e9:.1f} GB, "
+          f"setup {t_gen:.0f} s", file=sys.stderr, flush=True)
+
+    def serve(slots, max_states, label):
+        srv = Server(be, slots=slots, chunk=args.chunk, tol=1e-4, max_epochs=300,
+                     max_states=max_states)
+        for key, g in resident.items():
+            srv.add_geometry(key, g)
+        reqs = [Request(rid=k, geometry=geoms[pick[k]], y=ys[k], lam=float(lams[k]),
+                        arrival=float(arrivals[k])) for k in range(nreq)]
+        torch.cuda.synchronize()
+        srv.t0 = srv.clock()
+        last = [0]
+
+        def progress():
+            if len(srv.done) >= last[0] + max(1, nreq // 8):
+                last[0] = len(srv.done)
+                print(f"[bench] {label}: {len(srv.done)}/{nreq} done at {srv.now():.1f} s",
+                      file=sys.stderr, flush=True)
+
+        orig = srv.step
+
+        def step():
+            out = orig()
+            progress()
+            return out
+
+        srv.step = step
+        done = srv.run(reqs)
+        torch.cuda.synchronize()
+        span = max(r.finished for r in done) - min(r.arrival for r in done)
+        lat = [r.latency for r in done]
+        epochs = [r.epochs for r in done]
+        return {"recon_per_s": round(len(done) / span, 3), "makespan_s": round(span, 3),
+                "p50_s": round(percentile(lat, 50), 4), "p99_s": round(percentile(lat, 99), 4),
+                "mean_epochs": round(float(np.mean(epochs)), 1),
+                "converged": sum(r.stop == "converged" for r in done),
+                "epochs_per_s": round(sum(epochs) / span, 1), "slots": slots,
+                "rounds": srv.rounds}, {r.rid: r for r in done}
+
+    batched, res_b = serve(args.slots, None, "batched")
+    print(f"[bench] batched: {batched}", file=sys.stderr, flush=True)
+    unbatched = None
+    if not args.no_unbatched:
+        unbatched, res_u = serve(1, 1, "unbatched")
+        print(f"[bench] unbatched: {unbatched}", file=sys.stderr, flush=True)
+        same_epochs = sum(res_b[k].epochs == res_u[k].epochs for k in res_b)
+        diffs = [float(torch.linalg.norm(res_b[k].x - res_u[k].x) / torch.linalg.norm(res_u[k].x))
+                 for k in res_b if res_b[k].epochs == res_u[k].epochs]
+        unbatched["same_stop_epoch"] = same_epochs
+        unbatched["max_rel_diff_vs_batched"] = max(diffs) if diffs else None
+    out = {
+        "metric": "BSGD-TV epochs/s + HBM GB/s vs peak; served recon p50/p99 latency",
+        "value": batched["recon_per_s"],
+        "unit": "reconstructions/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(batched["makespan_s"] * 1e3, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"c5_serve: {nreq} requests, Poisson {args.rate}/s, 20 geometries "
+                               f"(n in {list(C5_SIZES)}, angles in {list(C5_ANGLES)}, M=N=8), "
+                               f"lambda U[0.002, 0.02], stop |d||r|||/||r|| < 1e-4 or 300 "
+                               f"epochs, checked every {args.chunk}, 20 FGP iterations",
+                   "total_nnz": total_nnz, "resident_plan_bytes": plan_bytes},
+        "p50_s": batched["p50_s"], "p99_s": batched["p99_s"],
+        "batched": batched, "unbatched": unbatched,
+        "speedup_vs_unbatched": (round(batched["recon_per_s"] / unbatched["recon_per_s"], 3)
+                                 if unbatched else None),
+        "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -301,6 +301,15 @@ bsgd_status bsgd_run_epochs(bsgd_state* state, float mu, float lam, int epochs, 
  */
 bsgd_status bsgd_state_set_overlap(bsgd_state* state, int mode);
 
+/*
+ * Schedule of the 2-D prox (line 9) kernels: 0 runs up to 20 FGP iterations
+ * per launch, recomputing a halo as wide as the iteration count in LDS (few
+ * launches, redundant work); 1 runs one iteration per launch (no redundant
+ * work, small LDS footprint, so it shares the GPU well with the concurrent
+ * forward pass on large images).  Same arithmetic per pixel.  Default 0.
+ */
+bsgd_status bsgd_state_set_prox_schedule(bsgd_state* state, int schedule);
+
 /* Copy the current iterate x (c floats) / residual r (r floats) to device memory. */
 bsgd_status bsgd_get_x(const bsgd_state* state, float* x, hipStream_t stream);
 bsgd_status bsgd_get_r(const bsgd_state* state, float* r, hipStream_t stream);
@@ -339,12 +348,23 @@ bsgd_status bsgd_state_timing(bsgd_state* state, double* fwd_ms, double* bwd_ms,
  *   get_stats_rhs  ||r_k||^2 per slot (host, nrhs doubles, FP64 sums in a
  *               fixed order).  Synchronises; BSGD_ERR_DIVERGED if any is
  *               not finite.
+ *   get_res_change_rhs  the squared residual norms of the last two epochs per
+ *               slot: now[j] = ||r_{k+1}||^2 (the residual that the next
+ *               epoch's backprojection uses) and prev[j] = ||r_k||^2 (the one
+ *               the last epoch used), read from the two residual buffers
+ *               (Algorithm 1 lines 3-4 keep both).  prev is meaningful once
+ *               an epoch has run since init, load or the slot's set_rhs.
+ *               Any state, also nrhs = 1.  Synchronises; BSGD_ERR_DIVERGED if
+ *               a value is not finite.  This is what a stopping rule on the
+ *               relative change of ||r|| needs.
  */
 bsgd_status bsgd_state_set_rhs(bsgd_state* state, int k, const float* y, const float* x0,
                                hipStream_t stream);
 bsgd_status bsgd_state_set_lambda(bsgd_state* state, const float* lam, hipStream_t stream);
 bsgd_status bsgd_get_x_rhs(const bsgd_state* state, int k, float* x, hipStream_t stream);
 bsgd_status bsgd_get_stats_rhs(const bsgd_state* state, hipStream_t stream, double* res_norm2);
+bsgd_status bsgd_get_res_change_rhs(const bsgd_state* state, hipStream_t stream, double* now,
+                                    double* prev);
 
 /*
  * Capture `epochs` epochs of bsgd_run_epochs (same arguments; epochs even,

@@ -3,7 +3,7 @@
 Argument marshalling only: torch tensors are passed as device pointers, the
 current torch stream as the HIP stream.  Every function here has the name
 of the C entry point it calls.  The library must have been built
-(``python -m paper_1812_01307_amd.build`` or ``__graft_entry__.build()``);
+(``python paper_1812_01307_amd/build.py`` or ``__graft_entry__.build()``);
 importing this module without it raises ImportError.
 """
 from __future__ import annotations
@@ -75,6 +75,8 @@ _PROTOS = {
     "bsgd_state_set_lambda": [_vp, ctypes.POINTER(_f32), _vp],
     "bsgd_get_x_rhs": [_vp, _i32, _vp, _vp],
     "bsgd_get_stats_rhs": [_vp, _vp, ctypes.POINTER(ctypes.c_double)],
+    "bsgd_get_res_change_rhs": [_vp, _vp, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double)],
     "bsgd_graph_create": [_vp, _f32, _f32, _i32, _i32, _vp, ctypes.POINTER(_vp)],
     "bsgd_graph_launch": [_vp, _vp],
     "bsgd_state_init": [_vp, _vp, _vp, _vp],
@@ -85,6 +87,7 @@ _PROTOS = {
     "bsgd_get_stats": [_vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)],
     "bsgd_state_enable_timing": [_vp, _i32],
     "bsgd_state_set_overlap": [_vp, _i32],
+    "bsgd_state_set_prox_schedule": [_vp, _i32],
     "bsgd_state_timing": [_vp] + [ctypes.POINTER(ctypes.c_double)] * 3 + [ctypes.POINTER(_i64)],
 }
 for _name, _args in _PROTOS.items():
@@ -469,6 +472,15 @@ def bsgd_get_stats_rhs(state: State, stream=None, allow_diverged=False):
     return list(arr)
 
 
+def bsgd_get_res_change_rhs(state: State, stream=None):
+    """Per-RHS squared residual norms of the last two epochs: (now, prev) lists."""
+    now = (ctypes.c_double * state.nrhs)()
+    prev = (ctypes.c_double * state.nrhs)()
+    _check("bsgd_get_res_change_rhs",
+           _lib.bsgd_get_res_change_rhs(state.handle, _stream(stream), now, prev))
+    return list(now), list(prev)
+
+
 class Graph:
     def __init__(self, handle, state):
         self.handle = handle
@@ -495,3 +507,8 @@ def bsgd_graph_create(state: State, mu, lam, epochs, prox_iters, stream=None) ->
 
 def bsgd_graph_launch(graph: Graph, stream=None):
     _check("bsgd_graph_launch", _lib.bsgd_graph_launch(graph.handle, _stream(stream)))
+
+
+def bsgd_state_set_prox_schedule(state: State, schedule: int):
+    _check("bsgd_state_set_prox_schedule", _lib.bsgd_state_set_prox_schedule(state.handle,
+                                                                             int(schedule)))

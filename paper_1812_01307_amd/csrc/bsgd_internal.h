@@ -213,13 +213,15 @@ hipError_t fill_f32(float* x, int64_t n, float v, hipStream_t s);
 // tiled = true: the internal pixel order of L (c_int floats).  ws must hold
 // tv_ws_floats(n) floats with n the vector length.
 size_t tv_ws_floats(int64_t n, int D);
+enum FgpSchedule { kFgpFused = 0, kFgpPerIteration = 1 };
 hipError_t tv_prox_run(const Layout& L, bool tiled, const float* b, float theta, int iters,
-                       float* out, float* ws, hipStream_t s);
+                       float* out, float* ws, hipStream_t s, int schedule);
 // S images in the internal 2-D pixel order, [c_int][S] (image index fastest),
 // each with its own theta_j = mu * lam[j] (lam: device array of S floats, or
 // nullptr for theta_j = mu * lam0 for all j).  ws: tv_ws_floats(c_int * S, 1).
 hipError_t tv_prox_batch(const Layout& L, int S, const float* b, float mu, const float* lam,
-                         float lam0, int iters, float* out, float* ws, hipStream_t s);
+                         float lam0, int iters, float* out, float* ws, hipStream_t s,
+                         int schedule);
 // One volume of S slices in the internal order [c_int][S] (slice index
 // fastest), 3-D TV.  ws: tv_ws_floats(c_int * S, 2).
 hipError_t tv_prox_volume(const Layout& L, int S, const float* b, float theta, int iters,

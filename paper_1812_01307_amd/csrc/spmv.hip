@@ -344,15 +344,29 @@ extern "C" bsgd_status bsgd_backproject_block(const bsgd_plan* plan, bsgd_valtyp
 // ---------------------------------------------------------------------------
 // Several right-hand sides (slices of a volume, or a batch of reconstructions
 // sharing A): V is [ncols_int][S], Y / XADD / OUT are [nrows_int][S], the RHS
-// index fastest.  One wavefront per (row, chunk of 256 RHS); each lane owns 4
-// consecutive RHS.  The row's entries are read once per chunk (every lane
-// reads the same column and value, so the wavefront issues one request), and
-// each entry gathers one 16-byte piece of V's row per lane (1 KB per
-// wavefront, coalesced).  Four entries are in flight per lane.
+// index fastest.  Each lane owns 4 consecutive RHS, so L = min(S/4, 64) lanes
+// cover a chunk of 4L RHS (one 16-byte gather per lane and entry, 16L bytes
+// contiguous per entry).  When S is small the row's entries are split over G
+// groups of L lanes (G = 8 for L <= 8, else 64/L): group g takes the 4-entry
+// chunks g, g + G, ... (rows are padded to a multiple of 8 entries, so chunks
+// never straddle the row end), and the G partial sums are added with xor
+// shuffles in a fixed order.  A row uses L*G lanes; a wavefront holds 64/(L*G)
+// rows.  blockIdx.y selects the RHS chunk when S > 256.  No atomics; the
+// summation order depends only on S.
 // ---------------------------------------------------------------------------
 namespace bsgd {
 
-template <typename VT, int MODE>
+__device__ __forceinline__ f32x4 load_vals(const float* __restrict__ val, int64_t e) {
+  return *reinterpret_cast<const f32x4*>(val + e);
+}
+
+__device__ __forceinline__ f32x4 load_vals(const __half* __restrict__ val, int64_t e) {
+  typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+  const f16x4 h = *reinterpret_cast<const f16x4*>(val + e);
+  return f32x4{(float)h.x, (float)h.y, (float)h.z, (float)h.w};
+}
+
+template <typename VT, int MODE, int L>
 __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ ptr,
                                               const int32_t* __restrict__ col,
                                               const VT* __restrict__ val,
@@ -360,25 +374,41 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ ptr,
                                               const float* __restrict__ Y,
                                               const float* __restrict__ XADD, float scale,
                                               float* __restrict__ OUT, int64_t nrows, int S) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int j = blockIdx.y * 256 + (threadIdx.x & 63) * 4;
-  if (row >= nrows || j >= S) return;  // no cross-lane operations follow
-  const int64_t beg = ptr[row], end = ptr[row + 1];
-  f32x4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0, a2 = a0, a3 = a0;
-  for (int64_t e = beg; e < end; e += 4) {  // rows are padded to a multiple of 8
-    const int32_t c0 = col[e], c1 = col[e + 1], c2 = col[e + 2], c3 = col[e + 3];
-    const float w0 = (float)val[e], w1 = (float)val[e + 1], w2 = (float)val[e + 2],
-                w3 = (float)val[e + 3];
-    const f32x4 v0 = *reinterpret_cast<const f32x4*>(V + (int64_t)c0 * S + j);
-    const f32x4 v1 = *reinterpret_cast<const f32x4*>(V + (int64_t)c1 * S + j);
-    const f32x4 v2 = *reinterpret_cast<const f32x4*>(V + (int64_t)c2 * S + j);
-    const f32x4 v3 = *reinterpret_cast<const f32x4*>(V + (int64_t)c3 * S + j);
-    a0 += w0 * v0;
-    a1 += w1 * v1;
-    a2 += w2 * v2;
-    a3 += w3 * v3;
+  constexpr int G = L <= 8 ? 8 : 64 / L;  // entry groups per row
+  constexpr int LPR = L * G;              // lanes per row
+  constexpr int RPW = 64 / LPR;           // rows per wavefront
+  const int lane = threadIdx.x & 63;
+  const int li = lane % LPR, g = li / L, l = li % L;
+  const int64_t row = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW + lane / LPR;
+  const int j = blockIdx.y * (4 * L) + 4 * l;  // < S: the host launches S / (4L) chunks
+  // rows past the end keep an empty range; every lane reaches the shuffles
+  int64_t beg = 0, end = 0;
+  if (row < nrows) {
+    beg = ptr[row];
+    end = ptr[row + 1];
   }
-  const f32x4 acc = (a0 + a1) + (a2 + a3);
+  f32x4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = a0, a2 = a0, a3 = a0;
+  for (int64_t e = beg + 4 * g; e < end; e += 4 * G) {
+    const i32x4 c = *reinterpret_cast<const i32x4*>(col + e);
+    const f32x4 w = load_vals(val, e);
+    const f32x4 v0 = *reinterpret_cast<const f32x4*>(V + (int64_t)c.x * S + j);
+    const f32x4 v1 = *reinterpret_cast<const f32x4*>(V + (int64_t)c.y * S + j);
+    const f32x4 v2 = *reinterpret_cast<const f32x4*>(V + (int64_t)c.z * S + j);
+    const f32x4 v3 = *reinterpret_cast<const f32x4*>(V + (int64_t)c.w * S + j);
+    a0 += w.x * v0;
+    a1 += w.y * v1;
+    a2 += w.z * v2;
+    a3 += w.w * v3;
+  }
+  f32x4 acc = (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int off = L; off < LPR; off <<= 1) {
+    acc.x += __shfl_xor(acc.x, off);
+    acc.y += __shfl_xor(acc.y, off);
+    acc.z += __shfl_xor(acc.z, off);
+    acc.w += __shfl_xor(acc.w, off);
+  }
+  if (g != 0 || row >= nrows) return;
   const int64_t o = row * S + j;
   f32x4 res;
   if constexpr (MODE == kPlain) {
@@ -395,19 +425,39 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t* __restrict__ ptr,
   *reinterpret_cast<f32x4*>(OUT + o) = res;
 }
 
+template <int MODE, int L>
+static hipError_t launch_spmm_l(const Store& st, bsgd_valtype vt, const float* V, const float* Y,
+                                const float* XADD, float scale, float* OUT, int S,
+                                hipStream_t s) {
+  constexpr int G = L <= 8 ? 8 : 64 / L;
+  constexpr int rows_per_block = 4 * (64 / (L * G));
+  dim3 grid((unsigned)((st.nrows + rows_per_block - 1) / rows_per_block),
+            (unsigned)(S / (4 * L)));
+  if (grid.x == 0) return hipSuccess;
+  if (vt == BSGD_VAL_F16)
+    k_spmm<__half, MODE, L><<<grid, 256, 0, s>>>(st.ptr, st.col, st.val16, V, Y, XADD, scale,
+                                                 OUT, st.nrows, S);
+  else
+    k_spmm<float, MODE, L><<<grid, 256, 0, s>>>(st.ptr, st.col, st.val, V, Y, XADD, scale, OUT,
+                                                st.nrows, S);
+  return hipGetLastError();
+}
+
 template <int MODE>
 static hipError_t launch_spmm_mode(const Store& st, bsgd_valtype vt, const float* V,
                                    const float* Y, const float* XADD, float scale, float* OUT,
                                    int S, hipStream_t s) {
-  dim3 grid((unsigned)((st.nrows + 3) / 4), (unsigned)((S + 255) / 256));
-  if (grid.x == 0) return hipSuccess;
-  if (vt == BSGD_VAL_F16)
-    k_spmm<__half, MODE><<<grid, 256, 0, s>>>(st.ptr, st.col, st.val16, V, Y, XADD, scale, OUT,
-                                              st.nrows, S);
-  else
-    k_spmm<float, MODE><<<grid, 256, 0, s>>>(st.ptr, st.col, st.val, V, Y, XADD, scale, OUT,
-                                             st.nrows, S);
-  return hipGetLastError();
+  // S is 4 .. 1024 and a power of two (checked when the state is created)
+  switch (S >= 256 ? 64 : S / 4) {
+    case 1: return launch_spmm_l<MODE, 1>(st, vt, V, Y, XADD, scale, OUT, S, s);
+    case 2: return launch_spmm_l<MODE, 2>(st, vt, V, Y, XADD, scale, OUT, S, s);
+    case 4: return launch_spmm_l<MODE, 4>(st, vt, V, Y, XADD, scale, OUT, S, s);
+    case 8: return launch_spmm_l<MODE, 8>(st, vt, V, Y, XADD, scale, OUT, S, s);
+    case 16: return launch_spmm_l<MODE, 16>(st, vt, V, Y, XADD, scale, OUT, S, s);
+    case 32: return launch_spmm_l<MODE, 32>(st, vt, V, Y, XADD, scale, OUT, S, s);
+    case 64: return launch_spmm_l<MODE, 64>(st, vt, V, Y, XADD, scale, OUT, S, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_spmm(const Store& st, bsgd_valtype vt, RowMode mode, const float* V,

@@ -30,6 +30,7 @@ struct bsgd_state {
   double* partial = nullptr;  // kReduceBlocks + 1 (last = result)
   int cur = 0;
   int overlap = 1;  // 0: forward pass concurrent with backprojection + prox; 1: with the prox only
+  int prox_schedule = bsgd::kFgpFused;  // 2-D prox: fused chunks or one launch per iteration
   int64_t epochs_done = 0;
   bool initialised = false;
   hipStream_t aux = nullptr;
@@ -294,13 +295,13 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
     if (theta != 0.f) {
       if (S == 1)
         BSGD_HIP(tv_prox_run(p->L, true, st->xhat, theta, prox_iters, st->x[n], st->tv_ws,
-                             stream));
+                             stream, st->prox_schedule));
       else if (st->flags & BSGD_STATE_VOLUME)
         BSGD_HIP(tv_prox_volume(p->L, S, st->xhat, theta, prox_iters, st->x[n], st->tv_ws,
                                 stream));
       else
         BSGD_HIP(tv_prox_batch(p->L, S, st->xhat, mu, per_rhs ? st->lam : nullptr, lam,
-                               prox_iters, st->x[n], st->tv_ws, stream));
+                               prox_iters, st->x[n], st->tv_ws, stream, st->prox_schedule));
     }
     if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));
     BSGD_HIP(hipStreamWaitEvent(stream, st->ev_aux, 0));
@@ -394,6 +395,15 @@ extern "C" bsgd_status bsgd_state_set_overlap(bsgd_state* st, int mode) {
   return BSGD_OK;
 }
 
+extern "C" bsgd_status bsgd_state_set_prox_schedule(bsgd_state* st, int schedule) {
+  clear_error();
+  BSGD_REQUIRE(st != nullptr, "state is NULL");
+  BSGD_REQUIRE(schedule == kFgpFused || schedule == kFgpPerIteration,
+               "prox schedule must be 0 or 1");
+  st->prox_schedule = schedule;
+  return BSGD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Batches of independent reconstructions: per-slot set-up, lambdas, results
 // ---------------------------------------------------------------------------
@@ -455,6 +465,26 @@ extern "C" bsgd_status bsgd_get_stats_rhs(const bsgd_state* st, hipStream_t stre
   BSGD_HIP(hipStreamSynchronize(stream));
   for (int j = 0; j < S; ++j)
     if (!std::isfinite(res_norm2[j])) {
+      set_error("residual norm of slot %d is not finite", j);
+      return BSGD_ERR_DIVERGED;
+    }
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_get_res_change_rhs(const bsgd_state* st, hipStream_t stream,
+                                               double* now, double* prev) {
+  clear_error();
+  BSGD_REQUIRE(st && now && prev, "NULL argument");
+  const int S = st->nrhs;
+  double* out = st->partial + (size_t)kColBlocks * S;
+  // stream order keeps each copy ahead of the next reduction into `out`
+  BSGD_HIP(launch_colsumsq(st->r[st->cur], st->plan->L.r_int, S, st->partial, out, stream));
+  BSGD_HIP(hipMemcpyAsync(now, out, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
+  BSGD_HIP(launch_colsumsq(st->r[1 - st->cur], st->plan->L.r_int, S, st->partial, out, stream));
+  BSGD_HIP(hipMemcpyAsync(prev, out, sizeof(double) * S, hipMemcpyDeviceToHost, stream));
+  BSGD_HIP(hipStreamSynchronize(stream));
+  for (int j = 0; j < S; ++j)
+    if (!std::isfinite(now[j]) || !std::isfinite(prev[j])) {
       set_error("residual norm of slot %d is not finite", j);
       return BSGD_ERR_DIVERGED;
     }

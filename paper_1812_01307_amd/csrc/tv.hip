@@ -36,6 +36,110 @@ __device__ __forceinline__ int64_t pidx(const Layout& L, int d, int s, int t) {
 }
 
 // ---------------------------------------------------------------------------
+// One 2-D FGP iteration per launch: a 32 x 8 tile of output pixels stages q on
+// the tile plus a one-pixel halo and u on the tile plus its upper/left halo
+// in LDS (no redundant work, 5 KB of LDS, so blocks co-reside with the
+// concurrently running forward pass).  Batch layout and per-image theta as
+// for k_fgp_fused2 (blockIdx.z = image).
+// ---------------------------------------------------------------------------
+constexpr int kTW = 32;  // tile width (columns)
+constexpr int kTH = 8;   // tile height (rows)
+
+template <bool TILED>
+__global__ __launch_bounds__(kTW* kTH) void k_fgp_iter2(
+    Layout L, int S, const float* __restrict__ lam, float mu, float theta0,
+    const float* __restrict__ b, float coef, int qmode, const float* __restrict__ p1v,
+    const float* __restrict__ p1h, const float* __restrict__ p2v, const float* __restrict__ p2h,
+    float* __restrict__ ov, float* __restrict__ oh) {
+  __shared__ float sqv[kTH + 2][kTW + 2];
+  __shared__ float sqh[kTH + 2][kTW + 2];
+  __shared__ float su[kTH + 1][kTW + 1];
+  const int H = L.H, W = L.W;
+  const int img = blockIdx.z;
+  const float theta = lam ? mu * lam[img] : theta0;
+  if (theta == 0.f) return;  // identity prox: the output kernel copies b
+  const float step = 1.0f / (8.0f * theta);
+  const int s0 = blockIdx.y * kTH, t0 = blockIdx.x * kTW;
+  const int tid = threadIdx.y * kTW + threadIdx.x;
+
+  // q on rows s0-1 .. s0+kTH, columns t0-1 .. t0+kTW (zero outside the image)
+  for (int k = tid; k < (kTH + 2) * (kTW + 2); k += kTW * kTH) {
+    const int ls = k / (kTW + 2), lt = k % (kTW + 2);
+    const int s = s0 - 1 + ls, t = t0 - 1 + lt;
+    float qv = 0.f, qh = 0.f;
+    if (qmode != kQZero && s >= 0 && s < H && t >= 0 && t < W) {
+      const int64_t i = pidx<TILED>(L, 0, s, t) * S + img;
+      const float av = p1v[i], ah = p1h[i];
+      if (qmode == kQCopy) {
+        qv = av;
+        qh = ah;
+      } else {
+        qv = fmaf(coef, av - p2v[i], av);
+        qh = fmaf(coef, ah - p2h[i], ah);
+      }
+    }
+    sqv[ls][lt] = qv;
+    sqh[ls][lt] = qh;
+  }
+  __syncthreads();
+
+  // u = b - theta D^T q on rows s0-1 .. s0+kTH-1, columns t0-1 .. t0+kTW-1
+  for (int k = tid; k < (kTH + 1) * (kTW + 1); k += kTW * kTH) {
+    const int ls = k / (kTW + 1), lt = k % (kTW + 1);
+    const int s = s0 - 1 + ls, t = t0 - 1 + lt;
+    float u = 0.f;
+    if (s >= 0 && s < H && t >= 0 && t < W) {
+      const float dtq = (sqv[ls][lt] - sqv[ls + 1][lt]) + (sqh[ls][lt] - sqh[ls][lt + 1]);
+      u = b[pidx<TILED>(L, 0, s, t) * S + img] - theta * dtq;
+    }
+    su[ls][lt] = u;
+  }
+  __syncthreads();
+
+  const int s = s0 + threadIdx.y, t = t0 + threadIdx.x;
+  if (s < H && t < W) {
+    const int ls = threadIdx.y + 1, lt = threadIdx.x + 1;
+    const float uc = su[ls][lt];
+    const float gv = s >= 1 ? uc - su[ls - 1][lt] : 0.f;
+    const float gh = t >= 1 ? uc - su[ls][lt - 1] : 0.f;
+    const float av = fmaf(step, gv, sqv[ls][lt]);
+    const float ah = fmaf(step, gh, sqh[ls][lt]);
+    const float nrm = fmaxf(1.f, sqrtf(av * av + ah * ah));
+    const int64_t i = pidx<TILED>(L, 0, s, t) * S + img;
+    ov[i] = av / nrm;
+    oh[i] = ah / nrm;
+  }
+}
+
+// out = b - theta D^T p (2-D, batch layout; theta_j = 0 copies b)
+template <bool TILED>
+__global__ __launch_bounds__(256) void k_fgp_out2b(Layout L, int S, const float* __restrict__ lam,
+                                                   float mu, float theta0,
+                                                   const float* __restrict__ b,
+                                                   const float* __restrict__ pv,
+                                                   const float* __restrict__ ph,
+                                                   float* __restrict__ out) {
+  const int H = L.H, W = L.W;
+  const int64_t tot = (int64_t)H * W * S;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < tot;
+       q += (int64_t)gridDim.x * 256) {
+    const int img = (int)(q % S);
+    const int64_t pix = q / S;
+    const int s = (int)(pix / W), t = (int)(pix % W);
+    const int64_t c = pidx<TILED>(L, 0, s, t) * S + img;
+    const float theta = lam ? mu * lam[img] : theta0;
+    if (theta == 0.f) {
+      out[c] = b[c];
+      continue;
+    }
+    const float dn = s + 1 < H ? pv[pidx<TILED>(L, 0, s + 1, t) * S + img] : 0.f;
+    const float rt = t + 1 < W ? ph[pidx<TILED>(L, 0, s, t + 1) * S + img] : 0.f;
+    const float dtp = (pv[c] - dn) + (ph[c] - rt);
+    out[c] = b[c] - theta * dtp;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Fused 2-D FGP: up to kFuseMax iterations in one launch.  Each block owns a
 // kFT x kFT output tile and keeps b and the last two duals on the tile plus a
 // halo of (iterations + 1) pixels in LDS.  Every iteration shrinks the region
@@ -350,9 +454,39 @@ static void momentum(int iters, std::vector<float>& c) {
 // them) and writes p_{k0+L}, p_{k0+L-1} into the other two of four (pv, ph)
 // buffer pairs; the last chunk writes the result.
 template <bool TILED>
+static hipError_t fgp2_per_iteration(const Layout& L, int S, const float* b, float theta0,
+                                     const float* lam, float mu, int iters,
+                                     const std::vector<float>& c, float* out, float* ws,
+                                     int64_t n, hipStream_t s) {
+  const int64_t m = n * S;
+  float* buf[3] = {ws, ws + 2 * m, ws + 4 * m};  // rotating (pv, ph) pairs
+  dim3 grid((L.W + kTW - 1) / kTW, (L.H + kTH - 1) / kTH, S);
+  dim3 block(kTW, kTH);
+  int cur = 0;  // buffer receiving p_k
+  for (int k = 1; k <= iters; ++k) {
+    float* o = buf[cur];
+    const float* p1 = buf[(cur + 2) % 3];  // p_{k-1}
+    const float* p2 = buf[(cur + 1) % 3];  // p_{k-2}
+    const int qm = k == 1 ? kQZero : (k == 2 ? kQCopy : kQMomentum);
+    k_fgp_iter2<TILED><<<grid, block, 0, s>>>(L, S, lam, mu, theta0, b, c[k], qm, p1, p1 + m, p2,
+                                              p2 + m, o, o + m);
+    cur = (cur + 1) % 3;
+  }
+  const float* pk = buf[(cur + 2) % 3];
+  k_fgp_out2b<TILED><<<grid_for((int64_t)L.H * L.W * S), 256, 0, s>>>(L, S, lam, mu, theta0, b,
+                                                                       pk, pk + m, out);
+  return hipGetLastError();
+}
+
+// Prox schedule: kFgpFused = up to 20 iterations per launch with recomputed
+// halos, kFgpPerIteration = one launch per iteration.  Both compute the same
+// recurrence.
+template <bool TILED>
 static hipError_t fgp2_chunks(const Layout& L, int S, const float* b, float theta0,
                               const float* lam, float mu, int iters, const std::vector<float>& c,
-                              float* out, float* ws, int64_t n, hipStream_t s) {
+                              float* out, float* ws, int64_t n, hipStream_t s, int schedule) {
+  if (schedule == kFgpPerIteration && iters >= 1)
+    return fgp2_per_iteration<TILED>(L, S, b, theta0, lam, mu, iters, c, out, ws, n, s);
   const int64_t m = n * S;
   float* buf[4] = {ws, ws + 2 * m, ws + 4 * m, ws + 6 * m};
   dim3 grid((L.W + kFT - 1) / kFT, (L.H + kFT - 1) / kFT, S);
@@ -377,7 +511,7 @@ static hipError_t fgp2_chunks(const Layout& L, int S, const float* b, float thet
 
 template <bool TILED>
 static hipError_t tv_prox_impl(const Layout& L, const float* b, float theta, int iters,
-                               float* out, float* ws, hipStream_t s) {
+                               float* out, float* ws, hipStream_t s, int schedule) {
   const int64_t n = TILED ? L.c_int : (int64_t)L.H * L.W * L.D;
   const int64_t npix = (int64_t)L.H * L.W * L.D;
   if (theta == 0.f || iters == 0) {
@@ -386,7 +520,8 @@ static hipError_t tv_prox_impl(const Layout& L, const float* b, float theta, int
   }
   std::vector<float> c;
   momentum(iters, c);
-  if (L.D == 1) return fgp2_chunks<TILED>(L, 1, b, theta, nullptr, 1.f, iters, c, out, ws, n, s);
+  if (L.D == 1)
+    return fgp2_chunks<TILED>(L, 1, b, theta, nullptr, 1.f, iters, c, out, ws, n, s, schedule);
   float* buf[3] = {ws, ws + 3 * n, ws + 6 * n};  // (pd, pv, ph) triples
   float* q = ws + 9 * n;
   float* u = ws + 12 * n;
@@ -407,20 +542,21 @@ static hipError_t tv_prox_impl(const Layout& L, const float* b, float theta, int
 }
 
 hipError_t tv_prox_run(const Layout& L, bool tiled, const float* b, float theta, int iters,
-                       float* out, float* ws, hipStream_t s) {
-  return tiled ? tv_prox_impl<true>(L, b, theta, iters, out, ws, s)
-               : tv_prox_impl<false>(L, b, theta, iters, out, ws, s);
+                       float* out, float* ws, hipStream_t s, int schedule) {
+  return tiled ? tv_prox_impl<true>(L, b, theta, iters, out, ws, s, schedule)
+               : tv_prox_impl<false>(L, b, theta, iters, out, ws, s, schedule);
 }
 
 hipError_t tv_prox_batch(const Layout& L, int S, const float* b, float mu, const float* lam,
-                         float lam0, int iters, float* out, float* ws, hipStream_t s) {
+                         float lam0, int iters, float* out, float* ws, hipStream_t s,
+                         int schedule) {
   std::vector<float> c;
   momentum(std::max(iters, 1), c);
   if (iters == 0) {
     // identity for every image: one chunk-free copy through the theta = 0 path
-    return fgp2_chunks<true>(L, S, b, 0.f, nullptr, mu, 1, c, out, ws, L.c_int, s);
+    return fgp2_chunks<true>(L, S, b, 0.f, nullptr, mu, 1, c, out, ws, L.c_int, s, kFgpFused);
   }
-  return fgp2_chunks<true>(L, S, b, mu * lam0, lam, mu, iters, c, out, ws, L.c_int, s);
+  return fgp2_chunks<true>(L, S, b, mu * lam0, lam, mu, iters, c, out, ws, L.c_int, s, schedule);
 }
 
 // ---------------------------------------------------------------------------
@@ -634,7 +770,7 @@ extern "C" bsgd_status bsgd_tv_prox(int H, int W, int D, const float* b, float t
     return BSGD_ERR_WORKSPACE;
   }
   BSGD_HIP(tv_prox_run(natural_layout(H, W, D), false, b, theta, iters, out,
-                       static_cast<float*>(ws), stream));
+                       static_cast<float*>(ws), stream, kFgpFused));
   return BSGD_OK;
 }
 
@@ -659,3 +795,4 @@ extern "C" bsgd_status bsgd_tv_value(int H, int W, int D, const float* x, void* 
   BSGD_HIP(hipStreamSynchronize(stream));
   return BSGD_OK;
 }
+

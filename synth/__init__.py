@@ -14,6 +14,7 @@ from .problem import (  # noqa: F401
     build_native,
     ellipse_phantom,
     make_problem,
+    make_volume_problem,
     projection_matrix,
     seeded_vector,
     transpose_csr,

@@ -56,7 +56,8 @@ def _load():
             lib.siddon_count.argtypes = [ctypes.c_int] * 4 + [i64p]
             lib.siddon_count.restype = ctypes.c_int64
             vp = ctypes.c_void_p
-            lib.siddon_fill.argtypes = [ctypes.c_int] * 4 + [i64p, i32p, vp, vp, vp, vp]
+            lib.siddon_fill.argtypes = [ctypes.c_int] * 4 + [i64p, i32p, vp, vp, vp, vp,
+                                                             ctypes.c_int]
             lib.siddon_fill.restype = ctypes.c_int
             f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
             lib.csr_transpose_f64.argtypes = [
@@ -81,7 +82,8 @@ def projection_matrix(H: int, W: int, n_ang: int, bins: int, dtype=np.float64, x
     (row-major s * W + t); entries are exact chord lengths (computed in FP64,
     stored as `dtype`), columns ascending within each row (geometry
     documented in siddon.c).  With an image x (FP64, H*W), also returns
-    A x computed in FP64 from the unrounded lengths.
+    A x computed in FP64 from the unrounded lengths; x may also be a stack of
+    images (S, H*W) or (S, H, W), then A x is returned as (S, r).
     """
     lib = _load()
     nrays = n_ang * bins
@@ -94,16 +96,28 @@ def projection_matrix(H: int, W: int, n_ang: int, bins: int, dtype=np.float64, x
     del counts
     col = np.empty(nnz, dtype=np.int32)
     val = np.empty(nnz, dtype=dtype)
-    xd = None if x is None else np.ascontiguousarray(x, np.float64).ravel()
-    ax = None if x is None else np.empty(nrays, np.float64)
+    nx = 1
+    xd = ax = None
+    if x is not None:
+        xa = np.asarray(x, np.float64)
+        if xa.size == H * W:
+            xd = np.ascontiguousarray(xa).ravel()
+        else:
+            nx = xa.shape[0]
+            xd = np.ascontiguousarray(xa.reshape(nx, H * W).T)  # [pixel][image]
+        ax = np.empty(nrays * nx, np.float64)
     v64 = val if val.dtype == np.float64 else None
     v32 = val if val.dtype == np.float32 else None
     if v64 is None and v32 is None:
         raise ValueError("dtype must be float64 or float32")
     if lib.siddon_fill(H, W, n_ang, bins, row_ptr, col, _vptr(v64), _vptr(v32), _vptr(xd),
-                       _vptr(ax)) != 0:
+                       _vptr(ax), nx) != 0:
         raise RuntimeError("projection generator: fill pass disagreed with count pass")
-    return (row_ptr, col, val) if x is None else (row_ptr, col, val, ax)
+    if x is None:
+        return row_ptr, col, val
+    if nx > 1:
+        ax = np.ascontiguousarray(ax.reshape(nrays, nx).T)
+    return row_ptr, col, val, ax
 
 
 def transpose_csr(nrows: int, ncols: int, row_ptr, col, val):
@@ -262,3 +276,29 @@ def make_problem(name: str | None = None, *, n: int | None = None, H: int | None
 def seeded_vector(n: int, seed: int, scale: float = 1.0) -> np.ndarray:
     """Seeded FP64 test vector U[0, scale) (shared input for parity cases)."""
     return scale * np.random.default_rng(seed).random(n)
+
+
+def make_volume_problem(S: int = 256, base: str = "c2_512", first_seed: int = 1000,
+                        dtype=np.float32, with_transpose: bool = True) -> Problem:
+    """A stack of S slices sharing one 2-D geometry (the batched workload).
+
+    Slice s has its own ellipse phantom (seed first_seed + s) and noise
+    (seed first_seed + s + 10^6, sigma = noise * max of that slice's
+    projections).  x_true is (S, H, W); y is (S, r), one sinogram per slice.
+    """
+    cfg = dict(CONFIGS[base])
+    n, n_ang, bins = cfg["n"], cfg["n_ang"], cfg["bins"]
+    X = np.stack([ellipse_phantom(n, n, 10, first_seed + s) for s in range(S)])
+    row_ptr, col, val, AX = projection_matrix(n, n, n_ang, bins, dtype=dtype, x=X)
+    Y = np.empty_like(AX)
+    for s in range(S):
+        rng = np.random.default_rng(first_seed + s + 10**6)
+        Y[s] = AX[s] + cfg["noise"] * float(np.max(AX[s])) * rng.standard_normal(AX.shape[1])
+    row_off, col_off = block_offsets(n_ang, bins, n * n, cfg["M"], cfg["N"])
+    prob = Problem(name=f"c4_vol_{S}", H=n, W=n, n_ang=n_ang, bins=bins, M=cfg["M"], N=cfg["N"],
+                   row_ptr=row_ptr, col=col, val=val, row_off=row_off, col_off=col_off,
+                   x_true=X, y=Y, lam=cfg["lam"], epochs=cfg["epochs"],
+                   prox_iters=cfg["prox_iters"], noise_frac=cfg["noise"], seed=first_seed)
+    if with_transpose:
+        prob.ensure_transpose()
+    return prob

@@ -241,11 +241,13 @@ int64_t siddon_count(int H, int W, int n_ang, int bins, int64_t* counts) {
 /*
  * Fill CSR columns and lengths given row_ptr (nrays+1) from the counts.
  * Lengths go to val64 (FP64) or, when val64 is NULL, to val32 (rounded to
- * FP32).  When x is not NULL, ax[ray] = sum of length * x[col] over the row
- * in column order, in FP64 (the noiseless projections of an image x).
+ * FP32).  When x is not NULL it holds nx images as a [H*W][nx] matrix and
+ * ax[ray*nx + j] = sum of length * x[col*nx + j] over the row in column
+ * order, in FP64 (the noiseless projections of the images).
  */
 int siddon_fill(int H, int W, int n_ang, int bins, const int64_t* row_ptr,
-                int32_t* col, double* val64, float* val32, const double* x, double* ax) {
+                int32_t* col, double* val64, float* val32, const double* x, double* ax,
+                int nx) {
   const int64_t nrays = (int64_t)n_ang * bins;
   int err = 0;
 #pragma omp parallel reduction(| : err)
@@ -265,16 +267,22 @@ int siddon_fill(int H, int W, int n_ang, int bins, const int64_t* row_ptr,
         continue;
       }
       const int64_t base = row_ptr[ray];
-      double acc = 0.0;
       for (int k = 0; k < n; ++k) {
         col[base + k] = buf[k].col;
         if (val64)
           val64[base + k] = buf[k].len;
         else
           val32[base + k] = (float)buf[k].len;
-        if (x) acc += buf[k].len * x[buf[k].col];
       }
-      if (ax) ax[ray] = acc;
+      if (x && ax) {
+        double* out = ax + ray * (int64_t)nx;
+        for (int j = 0; j < nx; ++j) out[j] = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const double* xr = x + (int64_t)buf[k].col * nx;
+          const double len = buf[k].len;
+          for (int j = 0; j < nx; ++j) out[j] += len * xr[j];
+        }
+      }
     }
     free(buf);
     free(lam);

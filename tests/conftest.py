@@ -8,7 +8,20 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+def _ensure_library():
+    """Build libbsgd.so when it is missing (hipcc cross-compiles without a GPU)."""
+    if os.path.exists(os.path.join(ROOT, "paper_1812_01307_amd", "libbsgd.so")):
+        return
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "_bsgd_build", os.path.join(ROOT, "paper_1812_01307_amd", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    mod.build()
+
+
 def pytest_configure(config):
+    _ensure_library()
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
 

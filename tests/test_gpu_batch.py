@@ -34,7 +34,8 @@ def _to_rows(M):
     return np.ascontiguousarray(np.asarray(M).T)
 
 
-def test_batch_state_matches_oracle_per_slot():
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_batch_state_matches_oracle_per_slot(schedule):
     import paper_1812_01307_amd as bsgd
     p = problem("c1_64")
     S = 4
@@ -43,6 +44,7 @@ def test_batch_state_matches_oracle_per_slot():
     Y = f32(_batch_inputs(p, S)).astype(np.float64)
     lam = np.array([p.lam, 20.0, 0.0, 200.0])
     st = bsgd.bsgd_state_create(plan, S)
+    bsgd.bsgd_state_set_prox_schedule(st, schedule)
     bsgd.bsgd_state_init(st, _dev(f32(_to_rows(Y)).ravel()))
     bsgd.bsgd_state_set_lambda(st, lam)
     _, _, ref = oracle.bsgd_tv_multi(matrix(p), Y, mu, lam, 25, p.prox_iters, (p.H, p.W),
@@ -151,3 +153,27 @@ def test_graph_replay_is_bitwise_equal(S, flags):
     assert np.array_equal(out, ref)
     with pytest.raises(bsgd.BsgdError, match="even"):
         bsgd.bsgd_graph_create(st2, mu, lam, 3, 20, stream=s)
+
+
+@pytest.mark.parametrize("S", [4, 8, 16, 64, 256, 512])
+def test_batch_widths_match_oracle(S):
+    """Every lane split of the several-RHS products (entry groups, RHS chunks)."""
+    import paper_1812_01307_amd as bsgd
+    p = problem("c1_64")
+    plan = plan_for(p)
+    mu = float(np.float32(mu_for(p)))
+    Y = f32(_batch_inputs(p, S)).astype(np.float64)
+    lam = np.random.default_rng(S).uniform(0.0, 40.0, S)
+    lam[S // 2] = 0.0
+    st = bsgd.bsgd_state_create(plan, S)
+    bsgd.bsgd_state_init(st, _dev(f32(_to_rows(Y)).ravel()))
+    bsgd.bsgd_state_set_lambda(st, lam)
+    lam32 = lam.astype(np.float32).astype(np.float64)
+    _, _, ref = oracle.bsgd_tv_multi(matrix(p), Y, mu, lam32, 3, 10, (p.H, p.W), volume=False,
+                                     record=True)
+    for k in range(3):
+        bsgd.bsgd_run_epochs(st, mu, -1.0, 1, 10)
+        X = _host(bsgd.bsgd_get_x(st)).reshape(p.ncols, S).T
+        errs = [rel_l2(X[j], ref[k][j]) for j in range(S - 1)]
+        assert max(errs) <= ITERATE_REL, (k, int(np.argmax(errs)), max(errs))
+        assert np.max(np.abs(X[S - 1])) == 0.0

@@ -174,9 +174,10 @@ def test_power_umax(name):
 # Whole epochs (Algorithm 1)
 # --------------------------------------------------------------------------
 
-def _trajectory(p, plan, mu, lam, epochs, K, vt=0):
+def _trajectory(p, plan, mu, lam, epochs, K, vt=0, schedule=0):
     import paper_1812_01307_amd as bsgd
     st = bsgd.bsgd_state_create(plan, 1, vt)
+    bsgd.bsgd_state_set_prox_schedule(st, schedule)
     bsgd.bsgd_state_init(st, _dev(f32(p.y)))
     xs = []
     for _ in range(epochs):
@@ -185,8 +186,9 @@ def _trajectory(p, plan, mu, lam, epochs, K, vt=0):
     return xs, st
 
 
+@pytest.mark.parametrize("schedule", [0, 1])
 @pytest.mark.parametrize("lam", [None, 0.0, 20.0, 200.0])
-def test_c1_trajectory_per_epoch(lam):
+def test_c1_trajectory_per_epoch(lam, schedule):
     p = problem("c1_64")
     lam = p.lam if lam is None else lam
     plan = plan_for(p)
@@ -195,20 +197,21 @@ def test_c1_trajectory_per_epoch(lam):
     y32 = f32(p.y).astype(np.float64)
     _, _, ref = oracle.bsgd_tv(A, y32, float(np.float32(mu)), lam, p.epochs, p.prox_iters,
                                (p.H, p.W), record=True)
-    xs, _ = _trajectory(p, plan, mu, lam, p.epochs, p.prox_iters)
+    xs, _ = _trajectory(p, plan, mu, lam, p.epochs, p.prox_iters, schedule=schedule)
     errs = [rel_l2(a, b) for a, b in zip(xs, ref)]
     assert max(errs) <= ITERATE_REL, (max(errs), int(np.argmax(errs)))
 
 
-@pytest.mark.parametrize("view_len", [None, 0])
-def test_ragged_trajectory(view_len):
+@pytest.mark.parametrize("view_len,schedule,K", [(None, 0, 20), (0, 0, 20), (None, 1, 20),
+                                                  (0, 1, 33)])
+def test_ragged_trajectory(view_len, schedule, K):
     p = ragged_problem()
     plan = plan_for(p, view_len=view_len)
     mu = mu_for(p)
     y32 = f32(p.y).astype(np.float64)
-    _, _, ref = oracle.bsgd_tv(matrix(p), y32, float(np.float32(mu)), 5.0, 30, 20, (p.H, p.W),
+    _, _, ref = oracle.bsgd_tv(matrix(p), y32, float(np.float32(mu)), 5.0, 30, K, (p.H, p.W),
                                record=True)
-    xs, _ = _trajectory(p, plan, mu, 5.0, 30, 20)
+    xs, _ = _trajectory(p, plan, mu, 5.0, 30, K, schedule=schedule)
     assert max(rel_l2(a, b) for a, b in zip(xs, ref)) <= ITERATE_REL
 
 

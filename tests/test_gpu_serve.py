@@ -1,0 +1,80 @@
+"""Serving on the device: each result is the same alone and in a mix (GPU)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_helpers import ITERATE_REL, f32, matrix, mu_for, plan_for, problem, ragged_problem, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+CHUNK, MAX_EPOCHS, TOL = 10, 150, 1e-3
+
+
+def _geometries():
+    return {"c1": problem("c1_64"), "ragged": ragged_problem()}
+
+
+def _requests(probs):
+    """Seven requests over two geometries: own phantom, noise and lambda each."""
+    reqs = []
+    keys = ["c1", "ragged", "c1", "c1", "ragged", "c1", "ragged"]
+    lams = [0.02, 5.0, 20.0, 0.0, 200.0, 200.0, 100.0]
+    for i, (k, lam) in enumerate(zip(keys, lams)):
+        p = probs[k]
+        x = synth.ellipse_phantom(p.H, p.W, 10, 300 + i).ravel()
+        y = matrix(p) @ x
+        y = y + 0.01 * np.max(y) * np.random.default_rng(900 + i).standard_normal(y.size)
+        reqs.append((i, k, f32(y), float(np.float32(lam))))
+    return reqs
+
+
+def _serve(probs, plans, mus, reqs, slots, stagger):
+    import paper_1812_01307_amd as bsgd
+    from paper_1812_01307_amd.serve import DeviceBackend, Request, Server
+    be = DeviceBackend()
+    srv = Server(be, slots=slots, chunk=CHUNK, tol=TOL, max_epochs=MAX_EPOCHS)
+    for k in probs:
+        srv.add_geometry(k, be.geometry(plans[k], mu=mus[k], prox_iters=20))
+    objs = [Request(rid=i, geometry=k, y=torch.from_numpy(y).cuda(), lam=lam)
+            for i, k, y, lam in reqs]
+    pending = list(objs)
+    while pending or srv.busy:
+        if pending:
+            srv.submit(pending.pop(0))
+            if not stagger:
+                while pending:
+                    srv.submit(pending.pop(0))
+        srv.step()
+    torch.cuda.synchronize()
+    assert bsgd.capi is not None
+    return {r.rid: (r.x.cpu().numpy(), r.epochs, r.stop) for r in objs}
+
+
+@pytest.fixture(scope="module")
+def setup():
+    probs = _geometries()
+    plans = {k: plan_for(p) for k, p in probs.items()}
+    mus = {k: float(np.float32(mu_for(p))) for k, p in probs.items()}
+    return probs, plans, mus, _requests(probs)
+
+
+@pytest.mark.parametrize("slots", [4, 1])
+def test_alone_equals_mix_and_matches_oracle(setup, slots):
+    probs, plans, mus, reqs = setup
+    mix = _serve(probs, plans, mus, reqs, slots, stagger=True)
+    assert sorted(mix) == [r[0] for r in reqs]
+    for rid, k, y, lam in reqs:
+        alone = _serve(probs, plans, mus, [(rid, k, y, lam)], slots, stagger=False)[rid]
+        x_mix, e_mix, _ = mix[rid]
+        assert alone[1] == e_mix, (rid, alone[1], e_mix)
+        assert np.array_equal(alone[0], x_mix), rid
+        # and the served result is the oracle's after the same number of epochs
+        p = probs[k]
+        x_ref, _ = oracle.bsgd_tv(matrix(p), y.astype(np.float64), mus[k], lam, e_mix, 20,
+                                  (p.H, p.W))
+        assert rel_l2(x_mix, x_ref) <= ITERATE_REL, (rid, rel_l2(x_mix, x_ref))
+    # some requests stop by the rule, the others at the epoch cap
+    stops = {s for _, _, s in mix.values()}
+    assert stops == {"converged", "max_epochs"}, stops

@@ -1,0 +1,210 @@
+"""Serving scheduler policy (host logic only, a simulated backend; no GPU)."""
+import math
+
+import pytest
+
+from paper_1812_01307_amd.serve import Request, Server, percentile
+
+
+class FakeBackend:
+    """Residual norms follow ||r_e|| = 1 + exp(-e / tau) after e epochs in a
+    slot (tau per request), so the stop epoch of every request is known."""
+
+    def __init__(self, state_bytes=100, geom_bytes=1000):
+        self.sb, self.gb = state_bytes, geom_bytes
+        self.states = []
+        self.dropped = 0
+        self.launches = []
+
+    def geometry_bytes(self, g):
+        return self.gb
+
+    def state_bytes(self, g, slots):
+        return self.sb * slots
+
+    def new_state(self, g, slots):
+        h = {"slots": [None] * slots, "e": [0] * slots, "lam": [0.0] * slots, "g": g}
+        self.states.append(h)
+        return h
+
+    def drop_state(self, h):
+        self.dropped += 1
+        h["dead"] = True
+
+    def admit(self, h, g, k, req):
+        assert not h.get("dead")
+        assert h["slots"][k] is None
+        h["slots"][k] = req
+        h["e"][k] = 0
+
+    def set_lambdas(self, h, lams):
+        h["lam"] = list(lams)
+
+    def launch(self, h, g, epochs):
+        for k, req in enumerate(h["slots"]):
+            if req is not None:
+                assert h["lam"][k] == req.lam
+                h["e"][k] += epochs
+        self.launches.append((h["g"], epochs))
+
+    @staticmethod
+    def norm(e, tau):
+        return 1.0 + math.exp(-e / tau)
+
+    def res_change(self, h):
+        now, prev = [], []
+        for k, req in enumerate(h["slots"]):
+            if req is None:
+                now.append(0.0)
+                prev.append(0.0)
+            else:
+                tau = req.y
+                now.append(self.norm(h["e"][k], tau) ** 2)
+                prev.append(self.norm(h["e"][k] - 1, tau) ** 2)
+        return now, prev
+
+    def take_result(self, h, k):
+        return ("x", h["slots"][k].rid, h["e"][k])
+
+    def release(self, h, k):
+        h["slots"][k] = None
+
+
+def expected_epochs(tau, chunk, tol, max_epochs):
+    e = chunk
+    while e < max_epochs:
+        a, b = FakeBackend.norm(e, tau), FakeBackend.norm(e - 1, tau)
+        if abs(a - b) / b < tol:
+            return e
+        e += chunk
+    return max_epochs
+
+
+def _requests(n, geoms=("g0", "g1", "g2")):
+    return [Request(rid=i, geometry=geoms[i % len(geoms)], y=3.0 + 2.0 * i, lam=0.01 * (i + 1),
+                    arrival=0.0) for i in range(n)]
+
+
+def _server(fb, **kw):
+    srv = Server(fb, clock=lambda: 0.0, **kw)
+    for g in ("g0", "g1", "g2"):
+        srv.add_geometry(g, g)
+    return srv
+
+
+def test_every_request_stops_by_the_rule_at_chunk_boundaries():
+    fb = FakeBackend()
+    srv = _server(fb, slots=4, chunk=10, tol=1e-4, max_epochs=300)
+    reqs = _requests(11)
+    for r in reqs:
+        srv.submit(r)
+    while srv.busy:
+        srv.step()
+    assert len(srv.done) == 11
+    for r in reqs:
+        assert r.x == ("x", r.rid, r.epochs)
+        assert r.epochs == expected_epochs(r.y, 10, 1e-4, 300)
+        assert r.stop == ("converged" if r.epochs < 300 else "max_epochs")
+
+
+def test_result_is_the_same_alone_and_in_the_mix():
+    mix = _requests(9)
+    fb = FakeBackend()
+    srv = _server(fb, slots=2, chunk=10)
+    # staggered admissions: one new request before each round
+    pending = list(mix)
+    while pending or srv.busy:
+        if pending:
+            srv.submit(pending.pop(0))
+        srv.step()
+    for r in mix:
+        alone = _requests(9)[r.rid]
+        fb2 = FakeBackend()
+        s2 = _server(fb2, slots=2, chunk=10)
+        s2.submit(alone)
+        while s2.busy:
+            s2.step()
+        assert alone.epochs == r.epochs and alone.x == r.x
+
+
+def test_hbm_budget_bounds_admission_and_other_geometries_proceed():
+    # budget: 3 geometries (3000) + 2 states of 4 slots (800)
+    fb = FakeBackend(state_bytes=100, geom_bytes=1000)
+    srv = _server(fb, slots=4, chunk=10, hbm_bytes=3800)
+    reqs = [Request(rid=i, geometry="g0", y=50.0, lam=0.01, arrival=0.0) for i in range(9)]
+    reqs.append(Request(rid=9, geometry="g1", y=5.0, lam=0.01, arrival=0.0))
+    for r in reqs:
+        srv.submit(r)
+    srv.step()
+    # g0 got two states (8 slots), its ninth request and g1's request wait for memory
+    assert srv.resident_bytes() <= 3800
+    assert sum(b.active for b in srv.batches) == 8
+    assert len(srv.queue) == 2
+    while srv.busy:
+        srv.step()
+        assert srv.resident_bytes() <= 3800
+    assert len(srv.done) == 10
+    # g1's request was served once a state became idle and was released
+    assert fb.dropped >= 1
+
+
+def test_idle_states_are_reused_and_lambdas_follow_slots():
+    fb = FakeBackend()
+    srv = _server(fb, slots=4, chunk=10)
+    a = Request(rid=0, geometry="g0", y=3.0, lam=0.5)
+    srv.submit(a)
+    while srv.busy:
+        srv.step()
+    b = Request(rid=1, geometry="g0", y=3.0, lam=0.25)
+    srv.submit(b)
+    srv.step()
+    assert len(fb.states) == 1          # the idle state took the new request
+    assert fb.states[0]["lam"][0] == 0.25
+    while srv.busy:
+        srv.step()
+    assert b.epochs == a.epochs
+
+
+def test_run_follows_arrival_times():
+    t = [0.0]
+    fb = FakeBackend()
+    srv = Server(fb, slots=2, chunk=10, clock=lambda: t[0])
+    srv.add_geometry("g0", "g0")
+    reqs = [Request(rid=i, geometry="g0", y=3.0, lam=0.1, arrival=float(i)) for i in range(3)]
+
+    def sleep(dt):
+        t[0] += dt
+
+    orig_step = srv.step
+
+    def step():
+        t[0] += 0.25  # each round takes a quarter second
+        return orig_step()
+
+    srv.step = step
+    done = srv.run(reqs, sleep=sleep)
+    assert [r.rid for r in done] == [0, 1, 2]
+    for r in done:
+        assert r.admitted >= r.arrival and r.finished > r.admitted and r.latency > 0
+
+
+def test_invalid_requests_and_settings_are_rejected():
+    fb = FakeBackend()
+    srv = _server(fb)
+    with pytest.raises(KeyError):
+        srv.submit(Request(rid=0, geometry="nope", y=1.0, lam=0.1))
+    with pytest.raises(ValueError):
+        srv.submit(Request(rid=0, geometry="g0", y=1.0, lam=-1.0))
+    with pytest.raises(ValueError):
+        Server(fb, chunk=7, max_epochs=300)
+    with pytest.raises(ValueError):
+        srv.add_geometry("g0", "g0")
+    small = Server(fb, hbm_bytes=500)
+    with pytest.raises(MemoryError):
+        small.add_geometry("g", "g")
+
+
+def test_percentile_nearest_rank():
+    v = list(range(1, 101))
+    assert percentile(v, 50) == 50 and percentile(v, 99) == 99 and percentile(v, 100) == 100
+    assert percentile([7.0], 99) == 7.0

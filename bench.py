@@ -37,7 +37,7 @@ def _kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1812_01307_amd", "csrc")
-    for f in ("spmv.hip", "plan.hip", "bsgd_internal.h"):
+    for f in ("spmv.hip", "plan.hip", "staged.hip", "bsgd_internal.h"):
         with open(os.path.join(base, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -63,8 +63,12 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="time lane counts during plan creation")
-    ap.add_argument("--overlap", type=int, default=1, choices=[0, 1],
-                    help="epoch schedule: forward pass concurrent with backprojection (0) or after it (1)")
+    ap.add_argument("--staged", default="bwd", choices=["none", "fwd", "bwd", "both"],
+                    help="directions built in the staged form (LDS-served gathers) and used by "
+                         "the epochs")
+    ap.add_argument("--overlap", type=int, default=1, choices=[0, 1, 2],
+                    help="epoch schedule: forward pass concurrent with backprojection (0), after it "
+                         "and concurrent with the prox (1), or after the prox on one stream (2)")
     ap.add_argument("--prox-schedule", type=int, default=None, choices=[0, 1],
                     help="2-D prox kernels: 0 fused chunks, 1 one launch per iteration "
                          "(default: the library's)")
@@ -123,6 +127,8 @@ def main(argv=None):
     K = prob.prox_iters
     vt = bsgd.BSGD_VAL_F16 if args.vt == "f16" else bsgd.BSGD_VAL_F32
     flags = bsgd.BSGD_PLAN_F16 if vt == bsgd.BSGD_VAL_F16 else 0
+    flags |= {"none": 0, "fwd": bsgd.BSGD_PLAN_STAGED_FWD, "bwd": bsgd.BSGD_PLAN_STAGED_BWD,
+              "both": bsgd.BSGD_PLAN_STAGED}[args.staged]
     r, c, nnz = prob.nrows, prob.ncols, prob.nnz
 
     # inputs resident in HBM before the timed region
@@ -143,7 +149,7 @@ def main(argv=None):
         # reused by every timed job (the tuner's cache)
         p0 = bsgd.bsgd_plan_create(A, At, prob.M, prob.N, prob.row_off, prob.col_off, prob.H,
                                    prob.W, 1, prob.bins, flags | bsgd.BSGD_PLAN_AUTOTUNE)
-        tuned = bsgd.bsgd_plan_lanes(p0)
+        tuned = (bsgd.bsgd_plan_lanes(p0), bsgd.bsgd_plan_staged(p0))
         del p0
         print(f"[bench] autotuned launch {tuned}", file=sys.stderr, flush=True)
 
@@ -156,7 +162,8 @@ def main(argv=None):
         plan = bsgd.bsgd_plan_create(A, At, prob.M, prob.N, prob.row_off, prob.col_off, prob.H,
                                      prob.W, 1, prob.bins, flags)
         if tuned is not None:
-            bsgd.bsgd_plan_set_lanes(plan, *tuned)
+            bsgd.bsgd_plan_set_lanes(plan, *tuned[0])
+            bsgd.bsgd_plan_set_staged(plan, *[max(v, 0) for v in tuned[1]])
         if fixed_mu is None:
             u = bsgd.bsgd_power_umax(plan, args.power_iters, vt=vt)
             mu = 0.9 / (2.0 * u)
@@ -227,6 +234,24 @@ def main(argv=None):
 
     val_bytes = 2 if vt == bsgd.BSGD_VAL_F16 else 4
     b_fwd, b_bwd = _alg_bytes(nnz, r, c, val_bytes)
+    staged_info = None
+    if args.staged != "none":
+        lanes = bsgd.bsgd_plan_staged(plan)
+        staged_info = {"lanes": list(lanes)}
+        for d, name in ((0, "fwd"), (1, "bwd")):
+            if lanes[d] <= 0:
+                continue
+            P, SW, ent = bsgd.bsgd_plan_staged_shape(plan, d)
+            nr, ncv = (r, c) if d == 0 else (c, r)
+            # stored entries (2-byte columns), segment table, per-stage partials
+            # written and read, the gathered vector once, the epilogue vectors
+            b = (val_bytes + 2) * ent + 4 * ((nr + 2047) // 2048) * P * 2049 + 8 * P * nr \
+                + 4 * ncv + 8 * nr
+            staged_info[name] = {"stages": P, "stage_width": SW, "entries": ent, "alg_bytes": b}
+            if d == 0:
+                b_fwd = b
+            else:
+                b_bwd = b
     roofline = None
     kernel = {}
     if timing and acc["n"]:
@@ -239,10 +264,13 @@ def main(argv=None):
         achieved = dom_bytes / dom_ms / 1e6
         traffic = None
         if (PMC_TRAFFIC["config"] == args.config and PMC_TRAFFIC["vt"] == args.vt
+                and PMC_TRAFFIC.get("staged", "none") == args.staged
                 and _kernel_source_hash() == PMC_TRAFFIC["sha256"]):
             traffic = PMC_TRAFFIC[dom]
-        roofline = {"bound": "hbm", "kernel": "k_rows (%s)" % ("A x: lines 4+6" if dom == "fwd"
-                                                               else "A^T r: lines 3+7+8"),
+        kname = "k_staged" if staged_info and staged_info["lanes"][0 if dom == "fwd" else 1] > 0 \
+            else "k_rows"
+        roofline = {"bound": "hbm", "kernel": "%s (%s)" % (kname, "A x: lines 4+6" if dom == "fwd"
+                                                          else "A^T r: lines 3+7+8"),
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "alg_bytes_per_launch": dom_bytes}
@@ -283,6 +311,7 @@ def main(argv=None):
                                f"setup S0+S0' included)",
                    "nnz": nnz, "epochs_per_step": epochs, "power_iters": args.power_iters,
                    "lanes_per_row": list(bsgd.bsgd_plan_lanes(plan)), "overlap": args.overlap,
+                   "staged": args.staged,
                    "mu": "fixed from " + args.mu_file if fixed_mu is not None
                    else f"power iteration ({args.power_iters} steps)"},
         "epoch_only_ms": round(epoch_ms, 4),
@@ -290,6 +319,7 @@ def main(argv=None):
         "alg_bytes_per_epoch": b_fwd + b_bwd,
         "alg_gbs_epoch_only": round((b_fwd + b_bwd) / epoch_ms / 1e6, 1),
         "kernels": {k: round(v, 4) for k, v in kernel.items()},
+        "staged": staged_info,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "quality": {"res_norm2": rn2, "rel_err_vs_phantom": round(rel_err_true, 5)},

@@ -56,6 +56,9 @@ typedef enum { BSGD_VAL_F32 = 0, BSGD_VAL_F16 = 1 } bsgd_valtype;
 /* Plan flags. */
 #define BSGD_PLAN_F16 1u      /* also keep an FP16 (round-to-nearest-even) copy of the values */
 #define BSGD_PLAN_AUTOTUNE 2u /* time the row kernels per store and keep the fastest launch */
+#define BSGD_PLAN_STAGED_FWD 4u /* also build the staged form of the forward store (A) */
+#define BSGD_PLAN_STAGED_BWD 8u /* also build the staged form of the backward store (A^T) */
+#define BSGD_PLAN_STAGED 12u    /* both staged forms */
 
 /*
  * A sparse matrix in CSR form, in device memory.  Columns must be strictly
@@ -106,7 +109,8 @@ bsgd_status bsgd_plan_workspace_size(int64_t nrows, int64_t ncols, int64_t nnz, 
  *           are interleaved bin by bin, pixels are stored in 8 x 8 tiles, so
  *           the gathers of the products stay within few cache lines); every
  *           vector crossing this interface is in natural order.
- *   flags   BSGD_PLAN_F16 and/or BSGD_PLAN_AUTOTUNE.
+ *   flags   BSGD_PLAN_F16, BSGD_PLAN_AUTOTUNE, BSGD_PLAN_STAGED_FWD and/or
+ *           BSGD_PLAN_STAGED_BWD.
  *
  * The store keeps every block A_{I_i}^{J_j} and its transpose addressable
  * (bsgd_tile_export) in a row-interleaved layout: the entries of ray rho for
@@ -136,6 +140,33 @@ void bsgd_plan_destroy(bsgd_plan* plan);
 #define BSGD_LAUNCH_NT 128
 bsgd_status bsgd_plan_lanes(const bsgd_plan* plan, int* fwd_launch, int* bwd_launch);
 bsgd_status bsgd_plan_set_lanes(bsgd_plan* plan, int fwd_launch, int bwd_launch);
+
+/*
+ * Staged form (plans created with BSGD_PLAN_STAGED_FWD / _BWD).  The same fused sums of
+ * Algorithm 1 lines 3-8 as the row kernels, reorganised for the epochs of
+ * one-RHS states: the internal column space is cut into stages of at most
+ * 32768 columns (whole 8-pixel tile rows, or whole groups of 8 views), each
+ * row's entries are regrouped by stage with 16-bit stage-local column
+ * indices (6 bytes per entry with FP32 values, 4 with FP16), and a
+ * workgroup per (2048-row chunk, stage) serves its gathers from a copy of the
+ * stage's slice of x or r in LDS.  Per-stage row sums are added in stage
+ * order: deterministic, different rounding from the row kernels.
+ *   staged      lanes per row of each direction's staged kernel (4 or 8), 0
+ *               when the epochs of that direction use the row kernels, -1
+ *               when the direction has no staged form.  Built plans default
+ *               to 4; BSGD_PLAN_AUTOTUNE keeps the staged form only where it
+ *               timed faster than the best row-kernel launch.
+ *   set_staged  0, 4 or 8 per direction (4 / 8 only where built).
+ *   staged_shape  stages P, stage width and stored entries (with padding) of
+ *               the forward (transposed = 0) or backward (1) staged store.
+ * States created on the plan reserve the per-stage partial sums (P x rows
+ * floats per direction); bsgd_forward / bsgd_backproject, the block products
+ * and the power iteration always use the row kernels.
+ */
+bsgd_status bsgd_plan_staged(const bsgd_plan* plan, int* fwd_lanes, int* bwd_lanes);
+bsgd_status bsgd_plan_set_staged(bsgd_plan* plan, int fwd_lanes, int bwd_lanes);
+bsgd_status bsgd_plan_staged_shape(const bsgd_plan* plan, int transposed, int* stages,
+                                   int* stage_width, int64_t* entries);
 
 /*
  * Number of stored entries of block (i, j) (identical for the block and its
@@ -296,8 +327,10 @@ bsgd_status bsgd_run_epochs(bsgd_state* state, float mu, float lam, int epochs, 
  * (Eq. 3: line 3 uses the previous epoch's residual), so it runs on the
  * state's second stream: mode 0 starts it together with the backprojection,
  * mode 1 after the backprojection (it then overlaps the prox only; faster on
- * MI355X since both passes are bandwidth-bound).  Results do not depend on
- * the mode.  Default 1.
+ * MI355X since both passes are bandwidth-bound); mode 2 runs everything on
+ * the caller's stream in order (backprojection, prox, forward pass), which
+ * gives each kernel the whole GPU.  Results do not depend on the mode.
+ * Default 1.
  */
 bsgd_status bsgd_state_set_overlap(bsgd_state* state, int mode);
 

@@ -28,6 +28,9 @@ BSGD_VAL_F32 = 0
 BSGD_VAL_F16 = 1
 BSGD_PLAN_F16 = 1
 BSGD_PLAN_AUTOTUNE = 2
+BSGD_PLAN_STAGED_FWD = 4
+BSGD_PLAN_STAGED_BWD = 8
+BSGD_PLAN_STAGED = 12
 BSGD_LAUNCH_NT = 128
 BSGD_STATE_VOLUME = 1
 
@@ -58,6 +61,10 @@ _PROTOS = {
                          ctypes.c_uint, _vp, _sz, _vp, ctypes.POINTER(_vp)],
     "bsgd_plan_lanes": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
     "bsgd_plan_set_lanes": [_vp, _i32, _i32],
+    "bsgd_plan_staged": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+    "bsgd_plan_set_staged": [_vp, _i32, _i32],
+    "bsgd_plan_staged_shape": [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                               ctypes.POINTER(_i64)],
     "bsgd_tile_nnz": [_vp, _i32, _i32, _vp, ctypes.POINTER(_i64)],
     "bsgd_tile_export": [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp],
     "bsgd_forward": [_vp, _i32, _vp, _vp, _vp, _vp],
@@ -205,6 +212,26 @@ def bsgd_plan_lanes(plan: Plan):
     f, b = _i32(), _i32()
     _check("bsgd_plan_lanes", _lib.bsgd_plan_lanes(plan.handle, ctypes.byref(f), ctypes.byref(b)))
     return f.value, b.value
+
+
+def bsgd_plan_staged(plan: Plan):
+    """Lanes per row of the staged kernels (fwd, bwd): 0 = row kernels, -1 = not built."""
+    f, b = _i32(), _i32()
+    _check("bsgd_plan_staged", _lib.bsgd_plan_staged(plan.handle, ctypes.byref(f), ctypes.byref(b)))
+    return f.value, b.value
+
+
+def bsgd_plan_staged_shape(plan: Plan, transposed: int):
+    """(stages, stage width, stored entries) of one direction's staged store."""
+    p_, w_, e_ = _i32(), _i32(), _i64()
+    _check("bsgd_plan_staged_shape", _lib.bsgd_plan_staged_shape(
+        plan.handle, int(transposed), ctypes.byref(p_), ctypes.byref(w_), ctypes.byref(e_)))
+    return p_.value, w_.value, e_.value
+
+
+def bsgd_plan_set_staged(plan: Plan, fwd_lanes: int, bwd_lanes: int):
+    _check("bsgd_plan_set_staged", _lib.bsgd_plan_set_staged(plan.handle, int(fwd_lanes),
+                                                             int(bwd_lanes)))
 
 
 def bsgd_plan_set_lanes(plan: Plan, fwd_lanes: int, bwd_lanes: int):

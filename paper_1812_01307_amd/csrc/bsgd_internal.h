@@ -135,6 +135,36 @@ struct Store {
   bool nontemporal = false;       // non-temporal loads of the matrix streams
 };
 
+// Staged form of one direction (optional, BSGD_PLAN_STAGED).  The internal
+// column space is cut into P stages of SW columns; rows (internal order) are
+// grouped into chunks of RW.  For chunk w and stage s the rows' entries whose
+// column lies in the stage are stored back to back (row by row, each row's
+// segment padded with zero entries to a multiple of kStageVec), with 16-bit
+// stage-local column indices:
+//   wbase[w]                    int64, first entry of chunk w;
+//   segp[(w*P + s)*(RW+1) + k]  int32, offset (from wbase[w]) of row k's
+//                               segment for stage s; k = RW gives the end;
+//   col[e] uint16, val[e] FP32 (optional FP16 copy).
+// A product runs one workgroup per (chunk, stage): the stage's slice of the
+// vector is copied to LDS once and every gather is an LDS read; the per-stage
+// row sums go to a partial buffer that a second pass adds in stage order.
+constexpr int kStageVec = 8;
+constexpr int kStageRows = 2048;
+constexpr int kStageSmall = 19456;  // LDS floats: two workgroups per CU
+constexpr int kStageLarge = 32768;  // LDS floats: one workgroup per CU
+struct Staged {
+  bool built = false;
+  int lanes = 0;        // 0: the epoch uses the row kernel; 4 or 8: staged, lanes per row
+  int SW = 0, P = 0, RW = kStageRows;
+  int64_t nW = 0, nrows = 0, cap = 0, total = 0;
+  int64_t* wbase = nullptr;
+  int32_t* segp = nullptr;
+  uint16_t* col = nullptr;
+  float* val = nullptr;
+  __half* val16 = nullptr;
+  std::vector<int64_t> bnd;  // P + 1 natural column bounds of the stages
+};
+
 }  // namespace bsgd
 
 struct bsgd_plan {
@@ -143,6 +173,9 @@ struct bsgd_plan {
   bsgd::Layout L;
   bsgd::Store fwd;   // A   (rows: internal ray order; columns: internal pixel indices)
   bsgd::Store bwd;   // A^T (rows: internal pixel order; columns: internal ray indices)
+  bsgd::Staged sfwd, sbwd;        // staged forms (BSGD_PLAN_STAGED)
+  int64_t* stage_cnt = nullptr;   // segment counts / offsets while building
+  float* stage_z = nullptr;       // stage partials for the autotuner
   std::vector<int64_t> row_off, col_off;
   int64_t* scratch64 = nullptr;   // max(r_int, c_int) + 1 entries (build, export)
   int64_t* scan_tmp = nullptr;    // block sums for scans
@@ -168,6 +201,17 @@ enum RowMode { kPlain = 0, kResidual = 1, kStep = 2 };
 hipError_t launch_rows(const Store& st, bsgd_valtype vt, RowMode mode, const float* v,
                        const float* y, const float* xadd, float scale, float* out,
                        hipStream_t s, int lanes = 0, int nt = -1);
+
+// Staged products (Staged::lanes must be 4 or 8); zpart holds P * nrows floats.
+hipError_t launch_staged(const Staged& st, bsgd_valtype vt, RowMode mode, const float* v,
+                         int64_t nv, const float* y, const float* xadd, float scale, float* out,
+                         float* zpart, hipStream_t s);
+// Stage geometry of one direction (false if the direction cannot be staged).
+bool stage_geometry(const Layout& L, bool fwd, Staged& st);
+size_t stage_cnt_count(const Layout& L);
+template <bool FWD>
+bsgd_status build_staged(Staged& st, const bsgd_csr& src, const Layout& L, int64_t* scratch,
+                         hipStream_t s);
 
 // Same products for S right-hand sides ([rows][S] and [cols][S] matrices, the
 // RHS index fastest; S a multiple of 4).

@@ -175,12 +175,31 @@ static void carve_store(Carver& cv, Store& st, int64_t nrows, int64_t nnz, int n
   st.val16 = f16 ? cv.take<__half>(st.cap) : nullptr;
 }
 
+static void carve_staged(Carver& cv, Staged& st, const Layout& L, bool fwd, int64_t nnz,
+                         bool f16) {
+  if (!stage_geometry(L, fwd, st)) return;
+  // every non-empty segment adds at most kStageVec - 1 padding entries
+  st.cap = nnz + (int64_t)(kStageVec - 1) * std::min<int64_t>(nnz, st.nrows * st.P) + kStageVec;
+  st.wbase = cv.take<int64_t>(st.nW + 1);
+  st.segp = cv.take<int32_t>((size_t)st.nW * st.P * (st.RW + 1));
+  st.col = cv.take<uint16_t>(st.cap);
+  st.val = cv.take<float>(st.cap);
+  st.val16 = f16 ? cv.take<__half>(st.cap) : nullptr;
+}
+
 static size_t plan_layout(bsgd_plan* p, void* ws, const Layout& L, int64_t nnz, int M, int N,
                           unsigned flags) {
   Carver cv(ws);
   const bool f16 = (flags & BSGD_PLAN_F16) != 0;
   carve_store(cv, p->fwd, L.r_int, nnz, N, f16);
   carve_store(cv, p->bwd, L.c_int, nnz, M, f16);
+  if (flags & BSGD_PLAN_STAGED) {
+    if (flags & BSGD_PLAN_STAGED_FWD) carve_staged(cv, p->sfwd, L, true, nnz, f16);
+    if (flags & BSGD_PLAN_STAGED_BWD) carve_staged(cv, p->sbwd, L, false, nnz, f16);
+    p->stage_cnt = cv.take<int64_t>(stage_cnt_count(L));
+    if (flags & BSGD_PLAN_AUTOTUNE)
+      p->stage_z = cv.take<float>((size_t)std::max(p->sfwd.P * L.r_int, p->sbwd.P * L.c_int));
+  }
   const int64_t mx = std::max(L.r_int, L.c_int);
   p->scratch64 = cv.take<int64_t>(mx + 1);
   p->scan_tmp = cv.take<int64_t>(scan_tmp_count(mx) + 1);
@@ -235,7 +254,8 @@ static bsgd_status build_store(Store& st, const bsgd_csr& src, const Layout& L,
 
 // Time the fused row kernel for each candidate (lane count, load kind) and
 // keep the fastest.
-static bsgd_status autotune_store(Store& st, const float* v, float* out, hipStream_t s) {
+static bsgd_status autotune_store(Store& st, const float* v, float* out, hipStream_t s,
+                                  float* best_ms) {
   static const int cand[] = {2, 4, 8, 16, 32};
   hipEvent_t e0, e1;
   BSGD_HIP(hipEventCreate(&e0));
@@ -270,6 +290,44 @@ static bsgd_status autotune_store(Store& st, const float* v, float* out, hipStre
   (void)hipEventDestroy(e1);
   st.lanes_per_row = best_l;
   st.nontemporal = best_nt;
+  *best_ms = best;
+  return BSGD_OK;
+}
+
+// Time the staged form (4 and 8 lanes per row) against the row kernel's best
+// time and keep whichever is fastest (lanes = 0: the row kernel).
+static bsgd_status autotune_staged(Staged& st, const float* v, int64_t nv, float* out,
+                                   float* zpart, hipStream_t s, float rows_ms) {
+  hipEvent_t e0, e1;
+  BSGD_HIP(hipEventCreate(&e0));
+  BSGD_HIP(hipEventCreate(&e1));
+  float best = rows_ms;
+  int best_l = 0;
+  for (int l : {4, 8}) {
+    st.lanes = l;
+    hipError_t e = launch_staged(st, BSGD_VAL_F32, kPlain, v, nv, nullptr, nullptr, 1.f, out,
+                                 zpart, s);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
+      e = launch_staged(st, BSGD_VAL_F32, kPlain, v, nv, nullptr, nullptr, 1.f, out, zpart, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      set_error("autotune failed: %s", hipGetErrorString(e));
+      return BSGD_ERR_HIP;
+    }
+    if (ms < best) {
+      best = ms;
+      best_l = l;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  st.lanes = best_l;
   return BSGD_OK;
 }
 
@@ -434,6 +492,8 @@ extern "C" bsgd_status bsgd_plan_workspace_size(int64_t nrows, int64_t ncols, in
                                                 unsigned flags, size_t* bytes) {
   clear_error();
   BSGD_REQUIRE(bytes != nullptr, "bytes is NULL");
+  BSGD_REQUIRE((flags & ~(BSGD_PLAN_F16 | BSGD_PLAN_AUTOTUNE | BSGD_PLAN_STAGED)) == 0,
+               "unknown plan flags 0x%x", flags);
   bsgd_status st = check_sizes(nrows, ncols, nnz, M, N, H, W, D, view_len);
   if (st != BSGD_OK) return st;
   bsgd_plan tmp;
@@ -448,8 +508,8 @@ extern "C" bsgd_status bsgd_plan_create(const bsgd_csr* A, const bsgd_csr* At, i
                                         hipStream_t stream, bsgd_plan** out) {
   clear_error();
   BSGD_REQUIRE(A && At && row_off && col_off && workspace && out, "NULL argument");
-  BSGD_REQUIRE((flags & ~(BSGD_PLAN_F16 | BSGD_PLAN_AUTOTUNE)) == 0, "unknown plan flags 0x%x",
-               flags);
+  BSGD_REQUIRE((flags & ~(BSGD_PLAN_F16 | BSGD_PLAN_AUTOTUNE | BSGD_PLAN_STAGED)) == 0,
+               "unknown plan flags 0x%x", flags);
   BSGD_REQUIRE(((uintptr_t)workspace % kAlign) == 0, "workspace must be 256-byte aligned");
   BSGD_REQUIRE(A->row_ptr && A->col && A->val && At->row_ptr && At->col && At->val,
                "NULL CSR array");
@@ -487,6 +547,10 @@ extern "C" bsgd_status bsgd_plan_create(const bsgd_csr* A, const bsgd_csr* At, i
   if (st == BSGD_OK)
     st = build_store<false>(p->bwd, *At, p->L, p->row_off, p->seg_dev, p->scratch64, p->scan_tmp,
                             p->err, stream, "At");
+  if (st == BSGD_OK && p->sfwd.P > 0)
+    st = build_staged<true>(p->sfwd, *A, p->L, p->stage_cnt, stream);
+  if (st == BSGD_OK && p->sbwd.P > 0)
+    st = build_staged<false>(p->sbwd, *At, p->L, p->stage_cnt, stream);
   if (st == BSGD_OK && (flags & BSGD_PLAN_AUTOTUNE)) {
     hipError_t e = fill_pixels_one(p->L, p->vin, stream);
     if (e == hipSuccess) e = fill_f32(p->vaux, p->L.r_int, 1.f, stream);
@@ -494,8 +558,13 @@ extern "C" bsgd_status bsgd_plan_create(const bsgd_csr* A, const bsgd_csr* At, i
       set_error("autotune setup failed: %s", hipGetErrorString(e));
       st = BSGD_ERR_HIP;
     }
-    if (st == BSGD_OK) st = autotune_store(p->fwd, p->vin, p->vout, stream);
-    if (st == BSGD_OK) st = autotune_store(p->bwd, p->vaux, p->vout, stream);
+    float tf = 0.f, tb = 0.f;
+    if (st == BSGD_OK) st = autotune_store(p->fwd, p->vin, p->vout, stream, &tf);
+    if (st == BSGD_OK) st = autotune_store(p->bwd, p->vaux, p->vout, stream, &tb);
+    if (st == BSGD_OK && p->sfwd.built)
+      st = autotune_staged(p->sfwd, p->vin, p->L.c_int, p->vout, p->stage_z, stream, tf);
+    if (st == BSGD_OK && p->sbwd.built)
+      st = autotune_staged(p->sbwd, p->vaux, p->L.r_int, p->vout, p->stage_z, stream, tb);
   }
   if (st == BSGD_OK) {
     hipError_t e = hipStreamSynchronize(stream);
@@ -520,6 +589,39 @@ extern "C" bsgd_status bsgd_plan_lanes(const bsgd_plan* plan, int* fwd_launch, i
   BSGD_REQUIRE(plan && fwd_launch && bwd_launch, "NULL argument");
   *fwd_launch = plan->fwd.lanes_per_row | (plan->fwd.nontemporal ? BSGD_LAUNCH_NT : 0);
   *bwd_launch = plan->bwd.lanes_per_row | (plan->bwd.nontemporal ? BSGD_LAUNCH_NT : 0);
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_plan_staged(const bsgd_plan* plan, int* fwd_lanes, int* bwd_lanes) {
+  clear_error();
+  BSGD_REQUIRE(plan && fwd_lanes && bwd_lanes, "NULL argument");
+  *fwd_lanes = plan->sfwd.built ? plan->sfwd.lanes : -1;
+  *bwd_lanes = plan->sbwd.built ? plan->sbwd.lanes : -1;
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_plan_staged_shape(const bsgd_plan* plan, int transposed, int* stages,
+                                              int* stage_width, int64_t* entries) {
+  clear_error();
+  BSGD_REQUIRE(plan && stages && stage_width && entries, "NULL argument");
+  const Staged& st = transposed ? plan->sbwd : plan->sfwd;
+  BSGD_REQUIRE(st.built, "this direction has no staged form");
+  *stages = st.P;
+  *stage_width = st.SW;
+  *entries = st.total;
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_plan_set_staged(bsgd_plan* plan, int fwd_lanes, int bwd_lanes) {
+  clear_error();
+  BSGD_REQUIRE(plan != nullptr, "plan is NULL");
+  auto ok = [](const Staged& st, int l) {
+    return l == 0 || ((l == 4 || l == 8) && st.built);
+  };
+  BSGD_REQUIRE(ok(plan->sfwd, fwd_lanes) && ok(plan->sbwd, bwd_lanes),
+               "staged lanes must be 0 (row kernel) or 4 / 8 on a direction built staged");
+  plan->sfwd.lanes = fwd_lanes;
+  plan->sbwd.lanes = bwd_lanes;
   return BSGD_OK;
 }
 

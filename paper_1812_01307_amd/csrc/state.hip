@@ -28,6 +28,8 @@ struct bsgd_state {
   float* xhat = nullptr;
   float* tv_ws = nullptr;
   double* partial = nullptr;  // kReduceBlocks + 1 (last = result)
+  float* zf = nullptr;        // per-stage partials of the staged forward product
+  float* zb = nullptr;        // ... and of the staged backprojection
   int cur = 0;
   int overlap = 1;  // 0: forward pass concurrent with backprojection + prox; 1: with the prox only
   int prox_schedule = bsgd::kFgpFused;  // 2-D prox: fused chunks or one launch per iteration
@@ -89,6 +91,8 @@ static size_t state_layout(const bsgd_plan* p, int S, unsigned flags, void* ws, 
   st->lam = cv.take<float>(S);
   st->tmp_r = cv.take<float>(p->L.r_int);
   st->tmp_c = cv.take<float>(p->L.c_int);
+  if (S == 1 && p->sfwd.P > 0) st->zf = cv.take<float>((size_t)p->sfwd.P * p->L.r_int);
+  if (S == 1 && p->sbwd.P > 0) st->zb = cv.take<float>((size_t)p->sbwd.P * p->L.c_int);
   return align_up(cv.off, kAlign);
 }
 
@@ -269,11 +273,15 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
     const int c = st->cur, n = 1 - c;
     hipEvent_t* tv = st->t_used < st->t_cap ? &st->tev[5 * (size_t)st->t_used++] : nullptr;
     // S2 (+S4) on `stream`; S1 on the aux stream after everything queued on
-    // `stream` before this epoch (overlap 0) or after S2 (overlap 1)
+    // `stream` before this epoch (overlap 0) or after S2 (overlap 1), or on
+    // `stream` after the prox (overlap 2: no concurrency)
     if (st->overlap == 0) BSGD_HIP(hipEventRecord(st->ev_main, stream));
     if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
     float* step_out = theta == 0.f ? st->x[n] : st->xhat;
-    if (S == 1)
+    if (S == 1 && p->sbwd.lanes && st->zb)
+      BSGD_HIP(launch_staged(p->sbwd, st->vt, kStep, st->r[c], p->L.r_int, nullptr, st->x[c],
+                             2.0f * mu, step_out, st->zb, stream));
+    else if (S == 1)
       BSGD_HIP(launch_rows(p->bwd, st->vt, kStep, st->r[c], nullptr, st->x[c], 2.0f * mu,
                            step_out, stream));
     else
@@ -281,16 +289,27 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
                            step_out, S, stream));
     if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
     if (st->overlap == 1) BSGD_HIP(hipEventRecord(st->ev_main, stream));
-    BSGD_HIP(hipStreamWaitEvent(st->aux, st->ev_main, 0));
-    if (tv) BSGD_HIP(hipEventRecord(tv[0], st->aux));
-    if (S == 1)
-      BSGD_HIP(launch_rows(p->fwd, st->vt, kResidual, st->x[c], st->y, nullptr, 1.0f, st->r[n],
-                           st->aux));
-    else
-      BSGD_HIP(launch_spmm(p->fwd, st->vt, kResidual, st->x[c], st->y, nullptr, 1.0f, st->r[n],
-                           S, st->aux));
-    if (tv) BSGD_HIP(hipEventRecord(tv[1], st->aux));
-    BSGD_HIP(hipEventRecord(st->ev_aux, st->aux));
+    hipStream_t fs = st->overlap == 2 ? stream : st->aux;
+    auto forward = [&]() -> bsgd_status {
+      if (tv) BSGD_HIP(hipEventRecord(tv[0], fs));
+      if (S == 1 && p->sfwd.lanes && st->zf)
+        BSGD_HIP(launch_staged(p->sfwd, st->vt, kResidual, st->x[c], p->L.c_int, st->y, nullptr,
+                               1.0f, st->r[n], st->zf, fs));
+      else if (S == 1)
+        BSGD_HIP(launch_rows(p->fwd, st->vt, kResidual, st->x[c], st->y, nullptr, 1.0f,
+                             st->r[n], fs));
+      else
+        BSGD_HIP(launch_spmm(p->fwd, st->vt, kResidual, st->x[c], st->y, nullptr, 1.0f,
+                             st->r[n], S, fs));
+      if (tv) BSGD_HIP(hipEventRecord(tv[1], fs));
+      return BSGD_OK;
+    };
+    if (st->overlap != 2) {
+      BSGD_HIP(hipStreamWaitEvent(st->aux, st->ev_main, 0));
+      bsgd_status fst = forward();
+      if (fst != BSGD_OK) return fst;
+      BSGD_HIP(hipEventRecord(st->ev_aux, st->aux));
+    }
     // S5 on `stream`
     if (theta != 0.f) {
       if (S == 1)
@@ -304,7 +323,12 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
                                prox_iters, st->x[n], st->tv_ws, stream, st->prox_schedule));
     }
     if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));
-    BSGD_HIP(hipStreamWaitEvent(stream, st->ev_aux, 0));
+    if (st->overlap == 2) {
+      bsgd_status fst = forward();
+      if (fst != BSGD_OK) return fst;
+    } else {
+      BSGD_HIP(hipStreamWaitEvent(stream, st->ev_aux, 0));
+    }
     st->cur = n;
     st->epochs_done++;
   }
@@ -390,7 +414,7 @@ extern "C" bsgd_status bsgd_state_timing(bsgd_state* st, double* fwd_ms, double*
 extern "C" bsgd_status bsgd_state_set_overlap(bsgd_state* st, int mode) {
   clear_error();
   BSGD_REQUIRE(st != nullptr, "state is NULL");
-  BSGD_REQUIRE(mode == 0 || mode == 1, "overlap mode must be 0 or 1");
+  BSGD_REQUIRE(mode >= 0 && mode <= 2, "overlap mode must be 0, 1 or 2");
   st->overlap = mode;
   return BSGD_OK;
 }

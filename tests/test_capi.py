@@ -38,6 +38,12 @@ def test_size_queries_and_argument_errors():
     with pytest.raises(capi.BsgdError, match="shape"):
         capi.bsgd_plan_workspace_size(10, 10, 5, 1, 1, 3, 3, 1, 0, 0)
     assert capi.bsgd_tv_workspace_size(512, 512, 1) >= 6 * 512 * 512 * 4
+    # the staged form adds 16-bit columns + values (6 bytes per entry) and its tables
+    bst = capi.bsgd_plan_workspace_size(8190, 4096, 477832, 2, 2, 64, 64, 1, 91,
+                                        capi.BSGD_PLAN_STAGED)
+    assert bst > b32 + 6 * 477832
+    with pytest.raises(capi.BsgdError, match="flags"):
+        capi.bsgd_plan_workspace_size(8190, 4096, 477832, 2, 2, 64, 64, 1, 91, 64)
     assert capi.bsgd_tv_workspace_size(16, 16, 4) >= 13 * 16 * 16 * 4
     with pytest.raises(capi.BsgdError):
         capi.bsgd_tv_workspace_size(0, 5, 1)

@@ -215,7 +215,7 @@ def test_ragged_trajectory(view_len, schedule, K):
     assert max(rel_l2(a, b) for a, b in zip(xs, ref)) <= ITERATE_REL
 
 
-@pytest.mark.parametrize("overlap", [0, 1])
+@pytest.mark.parametrize("overlap", [0, 1, 2])
 def test_runs_are_bitwise_reproducible_and_resume_is_exact(overlap):
     import paper_1812_01307_amd as bsgd
     p = problem("c1_64")
@@ -243,6 +243,12 @@ def test_runs_are_bitwise_reproducible_and_resume_is_exact(overlap):
     assert np.array_equal(_host(bsgd.bsgd_get_r(st2)), outs[0][1])
     rn, ep, _ = bsgd.bsgd_get_stats(st2)
     assert ep == 12 and abs(rn - float(np.sum(outs[0][1] ** 2))) <= 1e-9 * rn
+    # the schedules run the same kernels in the same order per stream
+    st3 = bsgd.bsgd_state_create(plan)
+    bsgd.bsgd_state_set_overlap(st3, (overlap + 1) % 3)
+    bsgd.bsgd_state_init(st3, y)
+    bsgd.bsgd_run_epochs(st3, mu, 20.0, 12, 20)
+    assert np.array_equal(_host(bsgd.bsgd_get_x(st3)), outs[0][0])
 
 
 def test_divergence_is_reported():

@@ -77,6 +77,7 @@ typedef struct {
 typedef struct bsgd_plan bsgd_plan;   /* block store of A and A^T (opaque) */
 typedef struct bsgd_state bsgd_state; /* iterate, residual and prox buffers (opaque) */
 typedef struct bsgd_graph bsgd_graph; /* captured epochs of one state (opaque) */
+typedef struct bsgd_fused bsgd_fused; /* tile-sliced store for single-pass epochs (opaque) */
 
 /* ------------------------------------------------------------------------
  * Block store (Section 2.1: A divided into M row blocks and N column blocks)
@@ -410,6 +411,72 @@ bsgd_status bsgd_graph_create(bsgd_state* state, float mu, float lam, int epochs
                               hipStream_t stream, bsgd_graph** out);
 bsgd_status bsgd_graph_launch(bsgd_graph* graph, hipStream_t stream);
 void bsgd_graph_destroy(bsgd_graph* graph);
+
+/* ------------------------------------------------------------------------
+ * Single-pass epochs (Algorithm 1 lines 3-8 with the delay of Eq. 3)
+ *
+ * Line 3 of an epoch uses the previous epoch's residual r_k and line 4 the
+ * current iterate x_k, so both products can be taken in one pass over the
+ * stored entries: z[rho] += a x_k[p] and g[p] += a r_k[rho] for every entry
+ * a = A[rho, p].  An epoch then reads the matrix once instead of once as A
+ * and once as A^T.
+ *
+ * The tile-sliced store regroups the plan's forward store: pixels in 32 x 32
+ * tiles, rays in `chunks` chunks of whole ray groups (8 interleaved views when
+ * the plan has view_len > 0); the part of one ray inside one tile (a
+ * segment) is one lane's list of (16-bit tile-local column, value) entries.
+ * One workgroup per (tile, chunk) keeps the tile of x and per-wavefront
+ * copies of the tile of g in LDS; per-segment sums of A x and per-chunk sums
+ * of A^T r are added in a fixed order by a second kernel, so results are
+ * bitwise reproducible for a given store (and differ from the row kernels
+ * by summation order only).  FP16 values are available when the plan has
+ * BSGD_PLAN_F16.  Images wider than 2048 pixels are not supported
+ * (BSGD_ERR_UNSUPPORTED).
+ *
+ *   fused_workspace_size  counts the segments of `plan` (device pass over the
+ *               forward store, uses the plan's scratch vectors: no other call
+ *               on the plan may overlap it) and returns the workspace bytes
+ *               for bsgd_fused_create with the same chunks.  chunks = 0
+ *               picks about 2048 (tile, chunk) units; chunks <= number of ray
+ *               groups.  Synchronises `stream`.
+ *   fused_create  builds the store in `workspace` (device, 256-byte aligned,
+ *               at least the size returned above) from the plan's forward
+ *               store; the plan must outlive it.  Synchronises.
+ *   fused_shape   tiles, chunks, segments, slices (64 segments each) and
+ *               stored entries (with padding).
+ *   fused_set_waves  wavefronts per (tile, chunk) workgroup: 2, 4 (default)
+ *               or 8; results change by summation order only.
+ *   fused_partials_size  bytes of the partial-sum buffer (device) that every
+ *               pass needs: one float per segment slot and chunks x pixels.
+ *   fused_apply   one pass in natural orders:
+ *                   out_r = y - A x      (A x when y == NULL)      (lines 4, 6)
+ *                   out_x = xadd + mu * 2 A^T r   (2 A^T r when xadd == NULL)
+ *                                                               (lines 3, 7, 8)
+ *               x, xadd, out_x: c floats; y, r, out_r: r floats (device).
+ *               Uses the store's internal scratch vectors: calls on one store
+ *               must not overlap.
+ *   state_attach_fused  epochs of a one-RHS state on the same plan use the
+ *               single-pass form (pass, then the reduce that writes r' and x^,
+ *               then the prox, all on the caller's stream); `partials` (device,
+ *               fused_partials_size bytes) belongs to the state while attached.
+ *               fused == NULL detaches (the row kernels again).  The state's
+ *               value type must be available in the store.
+ */
+bsgd_status bsgd_fused_workspace_size(const bsgd_plan* plan, int chunks, hipStream_t stream,
+                                      size_t* bytes);
+bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, void* workspace,
+                              size_t workspace_bytes, hipStream_t stream, bsgd_fused** out);
+void bsgd_fused_destroy(bsgd_fused* fused);
+bsgd_status bsgd_fused_shape(const bsgd_fused* fused, int* tiles, int* chunks, int64_t* segments,
+                             int64_t* slices, int64_t* entries);
+bsgd_status bsgd_fused_set_waves(bsgd_fused* fused, int waves);
+bsgd_status bsgd_fused_partials_size(const bsgd_fused* fused, size_t* bytes);
+bsgd_status bsgd_fused_apply(const bsgd_fused* fused, bsgd_valtype vt, const float* x,
+                             const float* y, const float* r, const float* xadd, float mu,
+                             float* out_r, float* out_x, void* partials, size_t partials_bytes,
+                             hipStream_t stream);
+bsgd_status bsgd_state_attach_fused(bsgd_state* state, const bsgd_fused* fused, void* partials,
+                                    size_t partials_bytes);
 
 /* Message for the last failed call on this thread ("" if none). */
 const char* bsgd_last_error(void);

@@ -96,6 +96,14 @@ _PROTOS = {
     "bsgd_state_set_overlap": [_vp, _i32],
     "bsgd_state_set_prox_schedule": [_vp, _i32],
     "bsgd_state_timing": [_vp] + [ctypes.POINTER(ctypes.c_double)] * 3 + [ctypes.POINTER(_i64)],
+    "bsgd_fused_workspace_size": [_vp, _i32, _vp, ctypes.POINTER(_sz)],
+    "bsgd_fused_create": [_vp, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)],
+    "bsgd_fused_shape": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i64),
+                         ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+    "bsgd_fused_set_waves": [_vp, _i32],
+    "bsgd_fused_partials_size": [_vp, ctypes.POINTER(_sz)],
+    "bsgd_fused_apply": [_vp, _i32, _vp, _vp, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp],
+    "bsgd_state_attach_fused": [_vp, _vp, _vp, _sz],
 }
 for _name, _args in _PROTOS.items():
     _f = getattr(_lib, _name)
@@ -107,11 +115,13 @@ _lib.bsgd_state_destroy.argtypes = [_vp]
 _lib.bsgd_state_destroy.restype = None
 _lib.bsgd_graph_destroy.argtypes = [_vp]
 _lib.bsgd_graph_destroy.restype = None
+_lib.bsgd_fused_destroy.argtypes = [_vp]
+_lib.bsgd_fused_destroy.restype = None
 _lib.bsgd_last_error.argtypes = []
 _lib.bsgd_last_error.restype = ctypes.c_char_p
 
 EXPORTED = sorted(list(_PROTOS) + ["bsgd_plan_destroy", "bsgd_state_destroy", "bsgd_graph_destroy",
-                                   "bsgd_last_error"])
+                                   "bsgd_fused_destroy", "bsgd_last_error"])
 
 
 def library_path() -> str:
@@ -539,3 +549,97 @@ def bsgd_graph_launch(graph: Graph, stream=None):
 def bsgd_state_set_prox_schedule(state: State, schedule: int):
     _check("bsgd_state_set_prox_schedule", _lib.bsgd_state_set_prox_schedule(state.handle,
                                                                              int(schedule)))
+
+
+# --------------------------------------------------------------------------
+# Single-pass epochs (tile-sliced store)
+# --------------------------------------------------------------------------
+
+class Fused:
+    """Tile-sliced store of a plan's matrix in a torch-owned device workspace."""
+
+    def __init__(self, handle, workspace, plan):
+        self.handle = handle
+        self.workspace = workspace
+        self.plan = plan  # keeps the plan alive
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.bsgd_fused_destroy(h)
+            self.handle = None
+
+
+def bsgd_fused_workspace_size(plan: Plan, chunks=0, stream=None) -> int:
+    out = _sz()
+    _check("bsgd_fused_workspace_size", _lib.bsgd_fused_workspace_size(
+        plan.handle, int(chunks), _stream(stream), ctypes.byref(out)))
+    return out.value
+
+
+def bsgd_fused_create(plan: Plan, chunks=0, stream=None) -> Fused:
+    nbytes = bsgd_fused_workspace_size(plan, chunks, stream)
+    ws = _ws(nbytes, plan.workspace.device)
+    h = _vp()
+    _check("bsgd_fused_create", _lib.bsgd_fused_create(plan.handle, int(chunks), _ptr(ws), nbytes,
+                                                       _stream(stream), ctypes.byref(h)))
+    return Fused(h, ws, plan)
+
+
+def bsgd_fused_shape(fused: Fused):
+    """(tiles, chunks, segments, slices, stored entries)."""
+    t, q = _i32(), _i32()
+    g, sl, e = _i64(), _i64(), _i64()
+    _check("bsgd_fused_shape", _lib.bsgd_fused_shape(fused.handle, ctypes.byref(t), ctypes.byref(q),
+                                                     ctypes.byref(g), ctypes.byref(sl),
+                                                     ctypes.byref(e)))
+    return t.value, q.value, g.value, sl.value, e.value
+
+
+def bsgd_fused_set_waves(fused: Fused, waves: int):
+    _check("bsgd_fused_set_waves", _lib.bsgd_fused_set_waves(fused.handle, int(waves)))
+
+
+def bsgd_fused_partials_size(fused: Fused) -> int:
+    out = _sz()
+    _check("bsgd_fused_partials_size", _lib.bsgd_fused_partials_size(fused.handle, ctypes.byref(out)))
+    return out.value
+
+
+def bsgd_fused_apply(fused: Fused, x, r, y=None, xadd=None, mu=0.0, out_r=None, out_x=None,
+                     vt=BSGD_VAL_F32, partials=None, stream=None):
+    """One single-pass product: (y - A x or A x, xadd + mu 2 A^T r or 2 A^T r)."""
+    plan = fused.plan
+    _chk(x, plan.ncols, "x")
+    _chk(r, plan.nrows, "r")
+    if y is not None:
+        _chk(y, plan.nrows, "y")
+    if xadd is not None:
+        _chk(xadd, plan.ncols, "xadd")
+    dev = x.device
+    if out_r is None:
+        out_r = torch.empty(plan.nrows, dtype=torch.float32, device=dev)
+    if out_x is None:
+        out_x = torch.empty(plan.ncols, dtype=torch.float32, device=dev)
+    _chk(out_r, plan.nrows, "out_r")
+    _chk(out_x, plan.ncols, "out_x")
+    if partials is None:
+        partials = _ws(bsgd_fused_partials_size(fused), dev)
+    _check("bsgd_fused_apply", _lib.bsgd_fused_apply(
+        fused.handle, vt, _ptr(x), _ptr(y), _ptr(r), _ptr(xadd), float(mu), _ptr(out_r),
+        _ptr(out_x), _ptr(partials), partials.numel(), _stream(stream)))
+    return out_r, out_x
+
+
+def bsgd_state_attach_fused(state: State, fused, partials=None):
+    """Run the state's epochs through the single-pass form (fused=None detaches)."""
+    if fused is None:
+        _check("bsgd_state_attach_fused", _lib.bsgd_state_attach_fused(state.handle, None, None, 0))
+        state.fused = state.fused_partials = None
+        return
+    if partials is None:
+        partials = _ws(bsgd_fused_partials_size(fused), state.workspace.device)
+    _check("bsgd_state_attach_fused", _lib.bsgd_state_attach_fused(
+        state.handle, fused.handle, _ptr(partials), partials.numel()))
+    state.fused = fused
+    state.fused_partials = partials

@@ -213,6 +213,20 @@ template <bool FWD>
 bsgd_status build_staged(Staged& st, const bsgd_csr& src, const Layout& L, int64_t* scratch,
                          hipStream_t s);
 
+// Single-pass products over the tile-sliced store (bsgd_fused): one pass
+// writes the per-segment partials of A x (zp) and the per-chunk partials of
+// A^T r (gp); the reduce adds them: out_r = y - A x (A x when y is NULL) and
+// out_x = xadd + scale * A^T r (scale * A^T r when xadd is NULL).  All
+// vectors in internal order.
+size_t fused_partial_floats(const bsgd_fused* F, float** zp, float** gp, void* ws);
+hipError_t launch_fused_pass(const bsgd_fused* F, bsgd_valtype vt, const float* x,
+                             const float* r, float* zp, float* gp, hipStream_t s);
+hipError_t launch_fused_reduce(const bsgd_fused* F, const float* zp, const float* gp,
+                               const float* y, float* out_r, const float* xadd, float scale,
+                               float* out_x, hipStream_t s);
+bool fused_has_f16(const bsgd_fused* F);
+const bsgd_plan* fused_plan(const bsgd_fused* F);
+
 // Same products for S right-hand sides ([rows][S] and [cols][S] matrices, the
 // RHS index fastest; S a multiple of 4).
 hipError_t launch_spmm(const Store& st, bsgd_valtype vt, RowMode mode, const float* V,

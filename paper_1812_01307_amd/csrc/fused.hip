@@ -1,0 +1,964 @@
+// Single-pass epoch products (Algorithm 1 lines 3-8, with the delay of Eq. 3).
+//
+// Line 3 of an epoch uses the residual r_k of the previous epoch and line 4
+// the current iterate x_k.  Both are known when the epoch starts, so one
+// pass over the stored entries a = A[rho, p] can produce both sums:
+//     z[rho] += a * x_k[p]      (line 4; summed over the column blocks: line 6)
+//     g[p]   += a * r_k[rho]    (line 3; summed over the row blocks:    line 7)
+// which reads the matrix once per epoch instead of once as A and once as A^T.
+//
+// Tile-sliced store.  Pixels are grouped into 32 x 32 tiles (4 x 4 of the
+// internal 8 x 8 tiles, across slices for volumes); rays into Q chunks of
+// whole ray groups (8 interleaved views, see bsgd::Layout).  A segment is
+// the part of one ray inside one tile.  Unit u = (tile, chunk) holds the
+// segments of the chunk's rays in the tile, sorted longest first, ties by
+// (view, bin parity, bin), 64 per slice, one per lane (neighbouring lanes
+// then follow parallel rays two bins apart, which never cross the same pixel:
+// a pixel's shadow on the detector is at most sqrt(2) bins wide).  A slice
+// stores its entries
+// lane-interleaved in groups of 4:
+//     entry j of lane l at soff[s] + (j / 4) * 256 + l * 4 + j % 4
+// as a 16-bit column (the pixel's address in the tile's LDS image, row
+// stride 33) and an FP32 value (optional FP16 copy).  Lanes shorter than the
+// slice's longest are padded with zero values on a column they already use.
+//
+// Pass.  One workgroup per unit copies the tile of x_k to LDS.  Each of its W
+// wavefronts takes every W-th slice of the unit, gathers x from LDS for the
+// row sums (one partial per segment, stored at [rank][ray], rank = the
+// segment's place among the ray's segments) and adds a * r[rho] into the
+// tile's g in LDS.  Those adds are 64-bit integer LDS atomics on fixed-point
+// terms (see to_fixed): exact and order-free, so the lanes and wavefronts
+// that meet on a pixel need no ordering (FP32 LDS atomics measured about 4x
+// slower than the whole pass on gfx950).  The unit's partial of g is
+// converted back to FP32 once.  A second kernel adds each ray's segment
+// partials in the order the ray enters the tiles (r = y - sum) and each
+// pixel's Q chunk partials in chunk order (x^ = x + mu * 2 sum).  No global
+// atomics: results are bitwise reproducible for a given store.
+//
+// The store is built on the device from the plan's forward store: one
+// wavefront per ray finds its segments (first-appearance rank and length),
+// a stable radix sort orders them by (unit, length), and the entries are
+// scattered into their slices.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "bsgd_internal.h"
+
+namespace bsgd {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kFT = 32;              // tile side in pixels
+constexpr int kFTS = kFT + 1;        // LDS row stride (rows and columns hit distinct banks)
+constexpr int kFTA = kFT * kFTS;     // LDS floats per tile image
+constexpr int kKeyLen = 2048;        // key >> 32 = unit * 2048 + (2047 - segment length)
+constexpr int kMaxSeg = kFT * kFT;   // a segment holds at most one entry per pixel
+
+struct TileGeom {
+  int Ht = 1, Wt = 1;        // 8 x 8 tiles per image column / row
+  int FTh = 1, FTw = 1;      // 32 x 32 tiles per image column / row
+  int D = 1;
+  int Q = 1;                 // ray chunks
+  int64_t slice_px = 0;      // internal pixels per slice (Ht * Wt * 64)
+  int64_t group_len = 64;    // internal rays per ray group
+  int64_t ngroups = 1;
+  int64_t view_len = 0;      // rays per view (0: rows without view structure)
+  int64_t tiles() const { return (int64_t)D * FTh * FTw; }
+  int64_t units() const { return tiles() * Q; }
+};
+
+}  // namespace bsgd
+
+struct bsgd_fused {
+  const bsgd_plan* plan = nullptr;
+  bsgd::TileGeom g;
+  int waves = 4;             // wavefronts per unit workgroup (2, 4 or 8)
+  int64_t pairs = 0, slices = 0, entries = 0, cap = 0;
+  int maxrank = 0;           // most segments of one ray
+  double smax = 0.0;         // largest column sum of |A| (bounds the sums of A^T r)
+  int32_t* sbeg = nullptr;   // units + 1: first slice of each unit
+  int32_t* sng = nullptr;    // slices: 4-entry groups per lane
+  int64_t* soff = nullptr;   // slices + 1: first entry of each slice
+  int32_t* sray = nullptr;   // slices * 64: internal ray of each lane (-1: none)
+  int32_t* poff = nullptr;   // r_int + 1: first segment of each ray
+  uint16_t* srank = nullptr; // slices * 64: the lane's segment's rank within its ray
+  uint16_t* col = nullptr;   // cap
+  float* val = nullptr;      // cap
+  __half* val16 = nullptr;   // cap (plans with BSGD_PLAN_F16)
+  // internal-order operands of bsgd_fused_apply
+  float *xin = nullptr, *xadd = nullptr, *rin = nullptr, *yin = nullptr, *zo = nullptr,
+        *go = nullptr;
+};
+
+namespace bsgd {
+
+// ---------------------------------------------------------------------------
+// Geometry
+// ---------------------------------------------------------------------------
+static TileGeom tile_geom(const Layout& L, int chunks) {
+  TileGeom g;
+  g.Ht = L.Ht;
+  g.Wt = L.Wt;
+  g.FTh = (L.Ht + 3) / 4;
+  g.FTw = (L.Wt + 3) / 4;
+  g.D = L.D;
+  g.slice_px = (int64_t)L.Ht * L.Wt * 64;
+  g.view_len = L.view_len;
+  if (L.view_len > 0) {
+    g.group_len = (int64_t)kViewTile * L.view_len;
+    g.ngroups = L.r_int / g.group_len;
+  } else {
+    g.group_len = 64;
+    g.ngroups = (L.r_int + 63) / 64;
+  }
+  if (chunks > 0) {
+    g.Q = chunks;
+  } else {
+    // about 2048 unit workgroups, no more chunks than ray groups
+    const int64_t want = (2048 + g.tiles() - 1) / g.tiles();
+    g.Q = (int)std::max<int64_t>(1, std::min<int64_t>(want, g.ngroups));
+  }
+  return g;
+}
+
+__device__ __forceinline__ int chunk_of(const TileGeom& g, int64_t k) {
+  return (int)((k / g.group_len) * g.Q / g.ngroups);
+}
+
+// Internal pixel index -> row-band key G (slice, tile row), tile column f and
+// address in the tile's LDS image.
+__device__ __forceinline__ void decode_pixel(const TileGeom& g, int64_t cp, int& G, int& f,
+                                             int& a) {
+  const int64_t d = cp / g.slice_px;
+  const int64_t rem = cp - d * g.slice_px;
+  const int t8 = (int)(rem >> 6), w = (int)(rem & 63);
+  const int tr8 = t8 / g.Wt, tc8 = t8 - tr8 * g.Wt;
+  G = (int)d * g.FTh + (tr8 >> 2);
+  f = tc8 >> 2;
+  a = (((tr8 & 3) << 3) + (w >> 3)) * kFTS + ((tc8 & 3) << 3) + (w & 7);
+}
+
+// Walk one ray's entries (one wavefront; the entries are in ascending natural
+// pixel order, so the band key G never decreases along the row).  Lane f
+// keeps, for the current band, the rank and running length of the segment
+// in tile column f.  Segments are ranked in the order the ray enters them.
+//   vis.entry(rank, j, lds_addr, e)    entry e is the j-th of segment `rank`
+//   vis.close(G, f, len, rank)         called by every lane f when band G ends
+//                                      (rank < 0: no segment in column f)
+//   vis.finish(nseg)
+template <class V>
+__device__ void walk_ray(const TileGeom& g, const int32_t* __restrict__ col, int64_t beg,
+                         int64_t len, V& vis) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = (1ull << lane) - 1ull;
+  int Gcur = -1, cnt = 0, rank = -1, nseen = 0;
+  for (int64_t c0 = 0; c0 < len; c0 += 64) {
+    const int64_t e = c0 + lane;
+    const bool valid = e < len;
+    int G = 0x7fffffff, f = 0, a = 0;
+    if (valid) decode_pixel(g, col[beg + e], G, f, a);
+    bool done = !valid;
+    uint64_t live;
+    while ((live = __ballot(!done)) != 0ull) {
+      const int leader = __builtin_ctzll(live);
+      const int Gl = __shfl(G, leader);
+      if (Gl != Gcur) {
+        if (Gcur >= 0) vis.close(Gcur, lane, cnt, rank);
+        cnt = 0;
+        rank = -1;
+        Gcur = Gl;
+      }
+      const bool inG = !done && G == Gl;
+      uint64_t todo = __ballot(inG);
+      while (todo) {
+        const int l2 = __builtin_ctzll(todo);
+        const int fl = __shfl(f, l2);
+        const uint64_t mm = __ballot(inG && f == fl);
+        int rk = __shfl(rank, fl);
+        const int base = __shfl(cnt, fl);
+        if (rk < 0) rk = nseen++;
+        if (lane == fl) {
+          rank = rk;
+          cnt = base + __popcll(mm);
+        }
+        if (inG && f == fl) vis.entry(rk, base + __popcll(mm & below), a, beg + e);
+        todo &= ~mm;
+      }
+      done = done || inG;
+    }
+  }
+  if (Gcur >= 0) vis.close(Gcur, lane, cnt, rank);
+  vis.finish(nseen);
+}
+
+struct VisCount {
+  TileGeom g;
+  int64_t k;
+  int q;
+  int64_t* ncross;
+  int32_t *ucnt, *umax, *ulen, *maxc;
+  __device__ void entry(int, int, int, int64_t) {}
+  __device__ void close(int G, int f, int len, int rank) {
+    if (rank < 0) return;
+    const int64_t u = ((int64_t)G * g.FTw + f) * g.Q + q;
+    atomicAdd(&ucnt[u], 1);
+    atomicMax(&umax[u], len);
+    atomicAdd(&ulen[u], len);
+  }
+  __device__ void finish(int n) {
+    if ((threadIdx.x & 63) == 0) {
+      ncross[k] = n;
+      atomicMax(maxc, n);
+    }
+  }
+};
+
+// Tie order inside a length class: view, bin parity, bin (rays of the
+// internal order k = group * 8 * bins + bin * 8 + view-in-group); the ray
+// order when the rows have no view structure.
+__device__ __forceinline__ uint32_t tie_of(const TileGeom& g, int64_t k) {
+  if (g.view_len == 0) return (uint32_t)k;
+  const int64_t G = k / g.group_len, rem = k - G * g.group_len;
+  const int64_t b = rem / kViewTile, v = rem % kViewTile;
+  const int64_t half = (g.view_len + 1) / 2;
+  return (uint32_t)(((v * g.ngroups + G) * 2 + (b & 1)) * half + (b >> 1));
+}
+
+struct VisPairs {
+  TileGeom g;
+  int64_t k;
+  int q;
+  const int64_t* poff;
+  uint64_t* key;
+  int32_t* idx;
+  int32_t* pray;
+  __device__ void entry(int, int, int, int64_t) {}
+  __device__ void close(int G, int f, int len, int rank) {
+    if (rank < 0) return;
+    const int64_t p = poff[k] + rank;
+    const int64_t u = ((int64_t)G * g.FTw + f) * g.Q + q;
+    key[p] = ((uint64_t)(u * kKeyLen + (kKeyLen - 1 - len)) << 32) | tie_of(g, k);
+    idx[p] = (int32_t)p;
+    pray[p] = (int32_t)k;
+  }
+  __device__ void finish(int) {}
+};
+
+struct VisFill {
+  int64_t k;
+  const int64_t* poff;
+  const int32_t* pos;
+  const int64_t* soff;
+  const float* vsrc;
+  const __half* v16src;
+  uint16_t* col;
+  float* val;
+  __half* val16;
+  int* err;
+  __device__ void entry(int rk, int j, int a, int64_t e) {
+    const int32_t P = pos[poff[k] + rk];
+    const int64_t s = P >> 6;
+    const int l = P & 63;
+    const int64_t addr = soff[s] + (int64_t)(j >> 2) * 256 + l * 4 + (j & 3);
+    if (addr >= soff[s + 1]) {
+      atomicOr(err, 1);
+      return;
+    }
+    col[addr] = (uint16_t)a;
+    val[addr] = vsrc[e];
+    if (val16) val16[addr] = v16src ? v16src[e] : __float2half_rn(vsrc[e]);
+  }
+  __device__ void close(int, int, int, int) {}
+  __device__ void finish(int) {}
+};
+
+// MODE 0: count, 1: segments, 2: fill.  One wavefront per internal ray.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_fz_walk(
+    TileGeom g, const int64_t* __restrict__ ptr, const int32_t* __restrict__ seg, int nseg,
+    const int32_t* __restrict__ col, const float* __restrict__ vsrc,
+    const __half* __restrict__ v16src, int64_t r_int, int64_t* ncross, int32_t* ucnt,
+    int32_t* umax, int32_t* ulen, int32_t* maxc, const int64_t* poff, uint64_t* key, int32_t* idx,
+    int32_t* pray, const int32_t* pos, const int64_t* soff, uint16_t* ocol, float* oval,
+    __half* oval16, int* err) {
+  const int64_t k = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  if (k >= r_int) return;  // uniform per wavefront
+  const int64_t beg = ptr[k];
+  const int64_t len = seg[k * (nseg + 1) + nseg];
+  const int q = chunk_of(g, k);
+  if constexpr (MODE == 0) {
+    VisCount v{g, k, q, ncross, ucnt, umax, ulen, maxc};
+    walk_ray(g, col, beg, len, v);
+  } else if constexpr (MODE == 1) {
+    VisPairs v{g, k, q, poff, key, idx, pray};
+    walk_ray(g, col, beg, len, v);
+  } else {
+    VisFill v{k, poff, pos, soff, vsrc, v16src, ocol, oval, oval16, err};
+    walk_ray(g, col, beg, len, v);
+  }
+}
+
+// Sorted segment i -> its slot; lane 0 of a slice holds its longest segment.
+__global__ void k_fz_place(const uint64_t* __restrict__ keys, const int32_t* __restrict__ idx,
+                           const int32_t* __restrict__ pray, const int64_t* __restrict__ poff,
+                           int64_t npairs, const int64_t* __restrict__ ubeg,
+                           const int32_t* __restrict__ sbeg, int64_t nslots,
+                           int32_t* __restrict__ pos, int32_t* __restrict__ sray,
+                           uint16_t* __restrict__ srank, int32_t* __restrict__ slen,
+                           int32_t* __restrict__ sng, int64_t* __restrict__ sng256,
+                           int* __restrict__ err) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npairs;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t key = (uint32_t)(keys[i] >> 32);
+    const int64_t u = key / kKeyLen;
+    const int len = kKeyLen - 1 - (int)(key % kKeyLen);
+    const int64_t m = i - ubeg[u];
+    const int64_t s = sbeg[u] + m / 64;
+    const int l = (int)(m % 64);
+    const int64_t P = s * 64 + l;
+    if (m < 0 || P >= nslots) {
+      atomicOr(err, 2);
+      continue;
+    }
+    const int32_t p = idx[i];
+    pos[p] = (int32_t)P;
+    sray[P] = pray[p];
+    srank[P] = (uint16_t)(p - poff[pray[p]]);
+    slen[P] = len;
+    if (l == 0) {
+      sng[s] = (len + 3) / 4;
+      sng256[s] = (int64_t)((len + 3) / 4) * 256;
+    }
+  }
+}
+
+__global__ void k_fz_init_slots(int32_t* __restrict__ sray, int32_t* __restrict__ slen,
+                                int64_t nslots) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    sray[i] = -1;
+    slen[i] = 0;
+  }
+}
+
+// Zero-valued padding of every lane up to its slice's group count; the
+// column repeats the lane's last real entry (an empty lane uses its own
+// lane number, so padded lanes do not meet on one LDS address).
+__global__ void k_fz_pad(const int32_t* __restrict__ slen, const int32_t* __restrict__ sng,
+                         const int64_t* __restrict__ soff, int64_t nslots,
+                         uint16_t* __restrict__ col, float* __restrict__ val,
+                         __half* __restrict__ val16) {
+  for (int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; P < nslots;
+       P += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = P >> 6;
+    const int l = (int)(P & 63);
+    const int len = slen[P], ng = sng[s];
+    const int64_t base = soff[s] + l * 4;
+    const uint16_t c =
+        len > 0 ? col[base + (int64_t)((len - 1) >> 2) * 256 + ((len - 1) & 3)] : (uint16_t)l;
+    for (int j = len; j < 4 * ng; ++j) {
+      const int64_t a = base + (int64_t)(j >> 2) * 256 + (j & 3);
+      col[a] = c;
+      val[a] = 0.f;
+      if (val16) val16[a] = __float2half_rn(0.f);
+    }
+  }
+}
+
+// Largest column sum of |A| (rows of the transposed store), FP64, as the bit
+// pattern of a non-negative double (which orders like the value).
+__global__ __launch_bounds__(256) void k_fz_colsum(const int64_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ seg, int nseg,
+                                                   const float* __restrict__ val, int64_t n,
+                                                   unsigned long long* __restrict__ out) {
+  const int64_t k = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (k >= n) return;  // uniform per wavefront
+  const int64_t beg = ptr[k], len = seg[k * (nseg + 1) + nseg];
+  double acc = 0.0;
+  for (int64_t e = lane; e < len; e += 64) acc += fabs((double)val[beg + e]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) atomicMax(out, (unsigned long long)__double_as_longlong(acc));
+}
+
+__global__ void k_i64_to_i32(const int64_t* __restrict__ in, int32_t* __restrict__ out,
+                             int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (int32_t)in[i];
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0;
+}
+
+static unsigned grid_for(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192));
+}
+
+// ---------------------------------------------------------------------------
+// The pass
+// ---------------------------------------------------------------------------
+template <typename VT>
+__device__ __forceinline__ void load4(const VT* __restrict__ val, int64_t i, float (&a)[4]) {
+  if constexpr (sizeof(VT) == 4) {
+    const f32x4 v = *reinterpret_cast<const f32x4*>(reinterpret_cast<const float*>(val) + i);
+    a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+  } else {
+    const f16x4 v = *reinterpret_cast<const f16x4*>(reinterpret_cast<const _Float16*>(val) + i);
+    a[0] = (float)v[0]; a[1] = (float)v[1]; a[2] = (float)v[2]; a[3] = (float)v[3];
+  }
+}
+
+// 64-bit fixed-point terms for the LDS sums of A^T r.  Scale 2^e per
+// workgroup, e from the largest |r| of the workgroup's rays and the largest
+// column sum of |A| (smax): every partial sum of a pixel stays below 2^61 in
+// magnitude, and a term (the exact FP64 product a * r * 2^e) is rounded to
+// the nearest integer, an error below 2^-62 of the largest possible sum.
+// Integer addition is associative, so the order of the LDS atomics does not
+// change the result.
+__device__ __forceinline__ int fixed_exponent(double smax, float rmax) {
+  const double b = smax * (double)rmax;
+  if (!(b > 0.0) || !isfinite(b)) return 0;
+  int E;
+  (void)frexp(b, &E);  // b < 2^E
+  return min(max(61 - E, -1000), 1000);
+}
+
+__device__ __forceinline__ unsigned long long to_fixed(float a, double rs) {
+  return (unsigned long long)(long long)rint((double)a * rs);
+}
+
+template <typename VT, int W>
+__global__ __launch_bounds__(64 * W) void k_fused(
+    TileGeom g, const int32_t* __restrict__ sbeg, const int32_t* __restrict__ sng,
+    const int64_t* __restrict__ soff, const int32_t* __restrict__ sray,
+    const uint16_t* __restrict__ srank, const uint16_t* __restrict__ col,
+    const VT* __restrict__ val, const float* __restrict__ x, const float* __restrict__ r,
+    float* __restrict__ zp, float* __restrict__ gp, int64_t r_int, int64_t c_int, double smax) {
+  __shared__ float xs[kFTA];
+  __shared__ unsigned long long gs[kFTA];
+  __shared__ unsigned rmax_bits;
+  constexpr int NT = 64 * W;
+  const int u = blockIdx.x;
+  const int tile = u / g.Q, q = u - tile * g.Q;
+  const int per = g.FTh * g.FTw;
+  const int d = tile / per;
+  const int tt = tile - d * per;
+  const int ftr = tt / g.FTw, ftc = tt - ftr * g.FTw;
+  const int64_t xbase = (int64_t)d * g.slice_px;
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6, lane = tid & 63;
+  const int s0 = sbeg[u], s1 = sbeg[u + 1];
+  for (int i = tid; i < kFTA; i += NT) {
+    xs[i] = 0.f;
+    gs[i] = 0ull;
+  }
+  if (tid == 0) rmax_bits = 0u;
+  // largest |r| over the unit's rays (sets the fixed-point scale)
+  float rm = 0.f;
+  for (int s = s0 + wv; s < s1; s += W) {
+    const int rho = sray[(int64_t)s * 64 + lane];
+    if (rho >= 0) rm = fmaxf(rm, fabsf(r[rho]));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) rm = fmaxf(rm, __shfl_xor(rm, off));
+  __syncthreads();
+  for (int i = tid; i < kFT * kFT; i += NT) {
+    const int b = i >> 6, w = i & 63;
+    const int tr8 = ftr * 4 + (b >> 2), tc8 = ftc * 4 + (b & 3);
+    if (tr8 < g.Ht && tc8 < g.Wt)
+      xs[(((b >> 2) << 3) + (w >> 3)) * kFTS + ((b & 3) << 3) + (w & 7)] =
+          x[xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w];
+  }
+  // |r| >= 0, so its bit pattern orders like the value (a NaN sorts above
+  // every finite value and gives exponent 0)
+  if (lane == 0) atomicMax(&rmax_bits, __float_as_uint(rm));
+  __syncthreads();
+  const int e = fixed_exponent(smax, __uint_as_float(rmax_bits));
+  const double scale = ldexp(1.0, e);
+  for (int s = s0 + wv; s < s1; s += W) {
+    const int rho = sray[(int64_t)s * 64 + lane];
+    const int rk = srank[(int64_t)s * 64 + lane];
+    const double rs = rho >= 0 ? (double)r[rho] * scale : 0.0;
+    const int64_t base = soff[s] + lane * 4;
+    const int ng = sng[s];
+    float z0 = 0.f, z1 = 0.f;
+    int j = 0;
+    for (; j + 1 < ng; j += 2) {
+      const u16x4 c0 = *reinterpret_cast<const u16x4*>(col + base + (int64_t)j * 256);
+      const u16x4 c1 = *reinterpret_cast<const u16x4*>(col + base + (int64_t)(j + 1) * 256);
+      float a0[4], a1[4];
+      load4<VT>(val, base + (int64_t)j * 256, a0);
+      load4<VT>(val, base + (int64_t)(j + 1) * 256, a1);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        z0 = fmaf(a0[t], xs[c0[t]], z0);
+        atomicAdd(&gs[c0[t]], to_fixed(a0[t], rs));
+        z1 = fmaf(a1[t], xs[c1[t]], z1);
+        atomicAdd(&gs[c1[t]], to_fixed(a1[t], rs));
+      }
+    }
+    if (j < ng) {
+      const u16x4 c0 = *reinterpret_cast<const u16x4*>(col + base + (int64_t)j * 256);
+      float a0[4];
+      load4<VT>(val, base + (int64_t)j * 256, a0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        z0 = fmaf(a0[t], xs[c0[t]], z0);
+        atomicAdd(&gs[c0[t]], to_fixed(a0[t], rs));
+      }
+    }
+    if (rho >= 0) zp[(int64_t)rk * r_int + rho] = z0 + z1;
+  }
+  __syncthreads();
+  const double inv = ldexp(1.0, -e);
+  for (int i = tid; i < kFT * kFT; i += NT) {
+    const int b = i >> 6, w = i & 63;
+    const int tr8 = ftr * 4 + (b >> 2), tc8 = ftc * 4 + (b & 3);
+    if (tr8 < g.Ht && tc8 < g.Wt) {
+      const int a = (((b >> 2) << 3) + (w >> 3)) * kFTS + ((b & 3) << 3) + (w & 7);
+      gp[(int64_t)q * c_int + xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w] =
+          (float)((double)(long long)gs[a] * inv);
+    }
+  }
+}
+
+// Rays: out_r = y - sum of the ray's segment partials zp[rank][ray] in rank
+// order, or the sum when y is NULL.  Pixels: out_x = xadd + scale * (sum of the Q chunk
+// partials, in chunk order), or scale * sum when xadd is NULL.
+__global__ __launch_bounds__(256) void k_fz_reduce(
+    const int32_t* __restrict__ poff, const float* __restrict__ zp,
+    const float* __restrict__ y, float* __restrict__ out_r,
+    int64_t r_int, const float* __restrict__ gp, int Q, const float* __restrict__ xadd,
+    float scale, float* __restrict__ out_x, int64_t c_int) {
+  const int64_t tot = r_int + c_int;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < tot;
+       i += (int64_t)gridDim.x * 256) {
+    if (i < r_int) {
+      const int n = poff[i + 1] - poff[i];
+      const float* z = zp + i;
+      float a = 0.f;
+      int k = 0;
+      for (; k + 3 < n; k += 4) {
+        const float v0 = z[(int64_t)k * r_int], v1 = z[(int64_t)(k + 1) * r_int];
+        const float v2 = z[(int64_t)(k + 2) * r_int], v3 = z[(int64_t)(k + 3) * r_int];
+        a += v0;
+        a += v1;
+        a += v2;
+        a += v3;
+      }
+      for (; k < n; ++k) a += z[(int64_t)k * r_int];
+      out_r[i] = y ? y[i] - a : a;
+    } else {
+      const int64_t p = i - r_int;
+      float a = 0.f;
+      for (int k = 0; k < Q; ++k) a += gp[(int64_t)k * c_int + p];
+      out_x[p] = xadd ? fmaf(scale, a, xadd[p]) : scale * a;
+    }
+  }
+}
+
+template <typename VT, int W>
+static void launch_fused_w(const bsgd_fused& F, const VT* val, const float* x, const float* r,
+                           float* zp, float* gp, hipStream_t s) {
+  k_fused<VT, W><<<(unsigned)F.g.units(), 64 * W, 0, s>>>(
+      F.g, F.sbeg, F.sng, F.soff, F.sray, F.srank, F.col, val, x, r, zp, gp, F.plan->L.r_int,
+      F.plan->L.c_int, F.smax);
+}
+
+template <typename VT>
+static void launch_fused_vt(const bsgd_fused& F, const VT* val, const float* x, const float* r,
+                            float* zp, float* gp, hipStream_t s) {
+  switch (F.waves) {
+    case 2: launch_fused_w<VT, 2>(F, val, x, r, zp, gp, s); break;
+    case 8: launch_fused_w<VT, 8>(F, val, x, r, zp, gp, s); break;
+    default: launch_fused_w<VT, 4>(F, val, x, r, zp, gp, s); break;
+  }
+}
+
+bool fused_has_f16(const bsgd_fused* F) { return F->val16 != nullptr; }
+const bsgd_plan* fused_plan(const bsgd_fused* F) { return F->plan; }
+
+size_t fused_partial_floats(const bsgd_fused* F, float** zp, float** gp, void* ws) {
+  Carver cv(ws);
+  float* a = cv.take<float>((size_t)std::max(F->maxrank, 1) * F->plan->L.r_int);
+  float* b = cv.take<float>((size_t)F->g.Q * F->plan->L.c_int);
+  if (zp) *zp = a;
+  if (gp) *gp = b;
+  return align_up(cv.off, kAlign);
+}
+
+hipError_t launch_fused_pass(const bsgd_fused* F, bsgd_valtype vt, const float* x,
+                             const float* r, float* zp, float* gp, hipStream_t s) {
+  if (vt == BSGD_VAL_F16)
+    launch_fused_vt<__half>(*F, F->val16, x, r, zp, gp, s);
+  else
+    launch_fused_vt<float>(*F, F->val, x, r, zp, gp, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_reduce(const bsgd_fused* F, const float* zp, const float* gp,
+                               const float* y, float* out_r, const float* xadd, float scale,
+                               float* out_x, hipStream_t s) {
+  const Layout& L = F->plan->L;
+  const int64_t tot = L.r_int + L.c_int;
+  k_fz_reduce<<<grid_for(tot), 256, 0, s>>>(F->poff, zp, y, out_r, L.r_int, gp, F->g.Q,
+                                            xadd, scale, out_x, L.c_int);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Build
+// ---------------------------------------------------------------------------
+struct FusedCounts {
+  int64_t pairs = 0, slices = 0, bound = 0;
+  int maxrank = 0;
+  std::vector<int64_t> ubeg;   // units + 1
+  std::vector<int32_t> sbeg;   // units + 1
+};
+
+// Count pass: segments per ray (into plan->scratch64, then scanned in place)
+// and per unit count / longest / total length (into the plan's scratch
+// vectors).  Synchronises.
+static bsgd_status fused_count(const bsgd_plan* p, const TileGeom& g, hipStream_t s,
+                               FusedCounts& fc) {
+  const Layout& L = p->L;
+  const int64_t units = g.units();
+  int32_t* ucnt = reinterpret_cast<int32_t*>(p->vin);
+  int32_t* umax = reinterpret_cast<int32_t*>(p->vaux);
+  int32_t* ulen = reinterpret_cast<int32_t*>(p->vout);
+  k_fill_i32<<<grid_for(units + 1), 256, 0, s>>>(ucnt, units + 1);  // ucnt[units]: max per ray
+  k_fill_i32<<<grid_for(units), 256, 0, s>>>(umax, units);
+  k_fill_i32<<<grid_for(units), 256, 0, s>>>(ulen, units);
+  BSGD_LAUNCH_CHECK();
+  const unsigned blocks = (unsigned)((L.r_int * 64 + 255) / 256);
+  k_fz_walk<0><<<blocks, 256, 0, s>>>(g, p->fwd.ptr, p->fwd.seg, p->fwd.nseg, p->fwd.col,
+                                      nullptr, nullptr, L.r_int, p->scratch64, ucnt, umax, ulen,
+                                      ucnt + units, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                      nullptr,
+                                      nullptr, nullptr, nullptr, nullptr);
+  BSGD_LAUNCH_CHECK();
+  BSGD_HIP(exclusive_scan_i64(p->scratch64, p->scratch64, L.r_int, p->scan_tmp, s));
+  std::vector<int32_t> hc(units + 1), hm(units), hl(units);
+  BSGD_HIP(hipMemcpyAsync(&fc.pairs, p->scratch64 + L.r_int, sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
+  BSGD_HIP(hipMemcpyAsync(hc.data(), ucnt, sizeof(int32_t) * (units + 1), hipMemcpyDeviceToHost,
+                          s));
+  BSGD_HIP(hipMemcpyAsync(hm.data(), umax, sizeof(int32_t) * units, hipMemcpyDeviceToHost, s));
+  BSGD_HIP(hipMemcpyAsync(hl.data(), ulen, sizeof(int32_t) * units, hipMemcpyDeviceToHost, s));
+  BSGD_HIP(hipStreamSynchronize(s));
+  fc.ubeg.assign(units + 1, 0);
+  fc.sbeg.assign(units + 1, 0);
+  int64_t sl = 0, bound = 0;
+  for (int64_t u = 0; u < units; ++u) {
+    const int64_t nsl = (hc[u] + 63) / 64;
+    fc.ubeg[u + 1] = fc.ubeg[u] + hc[u];
+    fc.sbeg[u] = (int32_t)sl;
+    sl += nsl;
+    // slices sorted longest first: slice k >= 1 is at most as long as the
+    // shortest segment of slice k - 1, so its 64 lanes hold no more than that
+    // slice's entries; groups of 4 add at most 3 entries per lane
+    if (nsl > 0) bound += 64 * ((int64_t)hm[u] + 3) + hl[u] + 192 * nsl;
+  }
+  fc.sbeg[units] = (int32_t)sl;
+  fc.maxrank = hc[units];
+  BSGD_REQUIRE(fc.maxrank < 65536, "a ray crosses %d tiles (at most 65535)", fc.maxrank);
+  fc.slices = sl;
+  fc.bound = bound;
+  BSGD_REQUIRE(sl * 64 < ((int64_t)1 << 31), "too many slices (%lld)", (long long)sl);
+  BSGD_REQUIRE(fc.ubeg[units] == fc.pairs, "segment counts disagree (%lld vs %lld)",
+               (long long)fc.ubeg[units], (long long)fc.pairs);
+  return BSGD_OK;
+}
+
+struct FusedTemps {
+  uint64_t *key = nullptr, *key2 = nullptr;
+  int32_t *idx = nullptr, *idx2 = nullptr, *pray = nullptr, *slen = nullptr, *pos = nullptr;
+  int64_t *ubeg = nullptr, *sng256 = nullptr, *scan_tmp = nullptr;
+  int* err = nullptr;
+  unsigned long long* smax = nullptr;
+  void* cub = nullptr;
+  size_t cub_bytes = 0;
+};
+
+static int key_bits(int64_t units) {
+  int b = 1;
+  while (((int64_t)1 << b) < units * kKeyLen) ++b;
+  return b;
+}
+
+static size_t fused_layout(const bsgd_plan* p, const TileGeom& g, const FusedCounts& fc,
+                           void* ws, bsgd_fused* F, FusedTemps* T) {
+  Carver cv(ws);
+  const Layout& L = p->L;
+  const int64_t units = g.units();
+  const int64_t nslots = std::max<int64_t>(fc.slices, 1) * 64;
+  const int64_t np = std::max<int64_t>(fc.pairs, 1);
+  const bool f16 = p->fwd.val16 != nullptr;
+  F->sbeg = cv.take<int32_t>(units + 1);
+  F->sng = cv.take<int32_t>(std::max<int64_t>(fc.slices, 1));
+  F->soff = cv.take<int64_t>(fc.slices + 1);
+  F->sray = cv.take<int32_t>(nslots);
+  F->poff = cv.take<int32_t>(L.r_int + 1);
+  F->srank = cv.take<uint16_t>(nslots);
+  F->col = cv.take<uint16_t>(std::max<int64_t>(fc.bound, 4));
+  F->val = cv.take<float>(std::max<int64_t>(fc.bound, 4));
+  F->val16 = f16 ? cv.take<__half>(std::max<int64_t>(fc.bound, 4)) : nullptr;
+  F->xin = cv.take<float>(L.c_int);
+  F->xadd = cv.take<float>(L.c_int);
+  F->go = cv.take<float>(L.c_int);
+  F->rin = cv.take<float>(L.r_int);
+  F->yin = cv.take<float>(L.r_int);
+  F->zo = cv.take<float>(L.r_int);
+  // build-only temporaries
+  T->key = cv.take<uint64_t>(np);
+  T->key2 = cv.take<uint64_t>(np);
+  T->pos = cv.take<int32_t>(np);
+  T->idx = cv.take<int32_t>(np);
+  T->idx2 = cv.take<int32_t>(np);
+  T->pray = cv.take<int32_t>(np);
+  T->slen = cv.take<int32_t>(nslots);
+  T->ubeg = cv.take<int64_t>(units + 1);
+  T->sng256 = cv.take<int64_t>(fc.slices + 1);
+  T->scan_tmp = cv.take<int64_t>(scan_tmp_count(fc.slices) + 1);
+  T->err = cv.take<int>(64);
+  T->smax = cv.take<unsigned long long>(1);
+  size_t cub_bytes = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, cub_bytes, (const uint64_t*)nullptr,
+                                           (uint64_t*)nullptr, (const int32_t*)nullptr,
+                                           (int32_t*)nullptr, (int)np, 0, 32 + key_bits(units));
+  T->cub_bytes = std::max<size_t>(cub_bytes, 1);
+  T->cub = cv.take<char>(T->cub_bytes);
+  return align_up(cv.off, kAlign);
+}
+
+static bsgd_status fused_check(const bsgd_plan* p, int chunks, TileGeom* g) {
+  BSGD_REQUIRE(p != nullptr, "plan is NULL");
+  BSGD_REQUIRE(chunks >= 0, "chunks must be >= 0 (0: automatic)");
+  const Layout& L = p->L;
+  if ((L.Wt + 3) / 4 > 64) {
+    set_error("the single-pass form supports images up to 2048 pixels wide");
+    return BSGD_ERR_UNSUPPORTED;
+  }
+  *g = tile_geom(L, chunks);
+  BSGD_REQUIRE(g->Q <= g->ngroups, "chunks (%d) exceeds the number of ray groups (%lld)", g->Q,
+               (long long)g->ngroups);
+  BSGD_REQUIRE(g->units() * kKeyLen < ((int64_t)1 << 32) &&
+                   g->units() < std::max(L.r_int, L.c_int),
+               "too many tiles x chunks (%lld)", (long long)g->units());
+  BSGD_REQUIRE(p->fwd.nnz < ((int64_t)1 << 31), "too many entries");
+  return BSGD_OK;
+}
+
+}  // namespace bsgd
+
+using namespace bsgd;
+
+extern "C" bsgd_status bsgd_fused_workspace_size(const bsgd_plan* plan, int chunks,
+                                                 hipStream_t stream, size_t* bytes) {
+  clear_error();
+  BSGD_REQUIRE(bytes != nullptr, "bytes is NULL");
+  TileGeom g;
+  bsgd_status st = fused_check(plan, chunks, &g);
+  if (st != BSGD_OK) return st;
+  FusedCounts fc;
+  st = fused_count(plan, g, stream, fc);
+  if (st != BSGD_OK) return st;
+  bsgd_fused tmp;
+  FusedTemps T;
+  *bytes = fused_layout(plan, g, fc, nullptr, &tmp, &T);
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, void* workspace,
+                                         size_t workspace_bytes, hipStream_t stream,
+                                         bsgd_fused** out) {
+  clear_error();
+  BSGD_REQUIRE(workspace && out, "NULL argument");
+  BSGD_REQUIRE(((uintptr_t)workspace % kAlign) == 0, "workspace must be 256-byte aligned");
+  TileGeom g;
+  bsgd_status st = fused_check(plan, chunks, &g);
+  if (st != BSGD_OK) return st;
+  FusedCounts fc;
+  st = fused_count(plan, g, stream, fc);
+  if (st != BSGD_OK) return st;
+  bsgd_fused* F = new bsgd_fused();
+  F->plan = plan;
+  F->g = g;
+  FusedTemps T;
+  const size_t need = fused_layout(plan, g, fc, workspace, F, &T);
+  if (workspace_bytes < need) {
+    delete F;
+    set_error("single-pass workspace has %zu bytes, needs %zu", workspace_bytes, need);
+    return BSGD_ERR_WORKSPACE;
+  }
+  const Layout& L = plan->L;
+  const Store& A = plan->fwd;
+  const int64_t units = g.units();
+  const int64_t nslots = fc.slices * 64;
+  const unsigned wblocks = (unsigned)((L.r_int * 64 + 255) / 256);
+  auto fail = [&](bsgd_status s) {
+    delete F;
+    return s;
+  };
+  auto hip_fail = [&](hipError_t e, const char* what) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    delete F;
+    return BSGD_ERR_HIP;
+  };
+  hipError_t e;
+  e = hipMemcpyAsync(F->sbeg, fc.sbeg.data(), sizeof(int32_t) * (units + 1),
+                     hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(T.ubeg, fc.ubeg.data(), sizeof(int64_t) * (units + 1),
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(T.err, 0, sizeof(int), stream);
+  if (e == hipSuccess) e = hipMemsetAsync(T.smax, 0, sizeof(unsigned long long), stream);
+  if (e != hipSuccess) return hip_fail(e, "single-pass build upload");
+  {
+    const Store& B = plan->bwd;
+    k_fz_colsum<<<(unsigned)((B.nrows * 64 + 255) / 256), 256, 0, stream>>>(
+        B.ptr, B.seg, B.nseg, B.val, B.nrows, T.smax);
+  }
+  // per-ray segment offsets (plan->scratch64 holds their exclusive scan)
+  k_i64_to_i32<<<grid_for(L.r_int + 1), 256, 0, stream>>>(plan->scratch64, F->poff, L.r_int + 1);
+  if (fc.pairs > 0) {
+    k_fz_walk<1><<<wblocks, 256, 0, stream>>>(
+        g, A.ptr, A.seg, A.nseg, A.col, nullptr, nullptr, L.r_int, nullptr, nullptr, nullptr,
+        nullptr, nullptr, plan->scratch64, T.key, T.idx, T.pray, nullptr, nullptr, nullptr,
+        nullptr, nullptr, nullptr);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "segment pass");
+    size_t cb = T.cub_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(T.cub, cb, T.key, T.key2, T.idx, T.idx2, (int)fc.pairs,
+                                           0, 32 + key_bits(units), stream);
+    if (e != hipSuccess) return hip_fail(e, "segment sort");
+    k_fz_init_slots<<<grid_for(nslots), 256, 0, stream>>>(F->sray, T.slen, nslots);
+    k_fz_place<<<grid_for(fc.pairs), 256, 0, stream>>>(T.key2, T.idx2, T.pray, plan->scratch64,
+                                                       fc.pairs, T.ubeg, F->sbeg, nslots, T.pos,
+                                                       F->sray, F->srank, T.slen, F->sng,
+                                                       T.sng256, T.err);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "slot placement");
+  }
+  e = exclusive_scan_i64(T.sng256, F->soff, fc.slices, T.scan_tmp, stream);
+  if (e != hipSuccess) return hip_fail(e, "slice offsets");
+  int64_t total = 0;
+  int h_err = 0;
+  unsigned long long smax_bits = 0;
+  e = hipMemcpyAsync(&total, F->soff + fc.slices, sizeof(int64_t), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&smax_bits, T.smax, sizeof(smax_bits), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&h_err, T.err, sizeof(int), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "slice offsets");
+  if (h_err) {  // a segment without a slot: stop before any entry is scattered
+    set_error("single-pass build found inconsistent slots (code %d)", h_err);
+    return fail(BSGD_ERR_INVALID);
+  }
+  if (total > fc.bound) {
+    set_error("single-pass store needs %lld entries, bound %lld", (long long)total,
+              (long long)fc.bound);
+    return fail(BSGD_ERR_INVALID);
+  }
+  if (fc.pairs > 0) {
+    k_fz_walk<2><<<wblocks, 256, 0, stream>>>(
+        g, A.ptr, A.seg, A.nseg, A.col, A.val, A.val16, L.r_int, nullptr, nullptr, nullptr,
+        nullptr, nullptr, plan->scratch64, nullptr, nullptr, nullptr, T.pos, F->soff, F->col,
+        F->val,
+        F->val16, T.err);
+    k_fz_pad<<<grid_for(nslots), 256, 0, stream>>>(T.slen, F->sng, F->soff, nslots, F->col,
+                                                   F->val, F->val16);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "entry fill");
+  }
+  e = hipMemcpyAsync(&h_err, T.err, sizeof(int), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "single-pass build");
+  if (h_err) {
+    set_error("single-pass build found inconsistent slots (code %d)", h_err);
+    return fail(BSGD_ERR_INVALID);
+  }
+  F->pairs = fc.pairs;
+  F->maxrank = fc.maxrank;
+  {
+    double sm;
+    std::memcpy(&sm, &smax_bits, sizeof(sm));
+    // FP16 values round |a| up by at most 2^-11 relative; the scale keeps a
+    // factor-2 margin below 2^62 anyway
+    F->smax = sm;
+  }
+  F->slices = fc.slices;
+  F->entries = total;
+  F->cap = fc.bound;
+  *out = F;
+  return BSGD_OK;
+}
+
+extern "C" void bsgd_fused_destroy(bsgd_fused* F) { delete F; }
+
+extern "C" bsgd_status bsgd_fused_shape(const bsgd_fused* F, int* tiles, int* chunks,
+                                        int64_t* segments, int64_t* slices, int64_t* entries) {
+  clear_error();
+  BSGD_REQUIRE(F && tiles && chunks && segments && slices && entries, "NULL argument");
+  *tiles = (int)F->g.tiles();
+  *chunks = F->g.Q;
+  *segments = F->pairs;
+  *slices = F->slices;
+  *entries = F->entries;
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_fused_set_waves(bsgd_fused* F, int waves) {
+  clear_error();
+  BSGD_REQUIRE(F != nullptr, "fused store is NULL");
+  BSGD_REQUIRE(waves == 2 || waves == 4 || waves == 8, "waves must be 2, 4 or 8");
+  F->waves = waves;
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_fused_partials_size(const bsgd_fused* F, size_t* bytes) {
+  clear_error();
+  BSGD_REQUIRE(F && bytes, "NULL argument");
+  *bytes = fused_partial_floats(F, nullptr, nullptr, nullptr);
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_fused_apply(const bsgd_fused* F, bsgd_valtype vt, const float* x,
+                                        const float* y, const float* r, const float* xadd,
+                                        float mu, float* out_r, float* out_x, void* partials,
+                                        size_t partials_bytes, hipStream_t stream) {
+  clear_error();
+  BSGD_REQUIRE(F && x && r && out_r && out_x && partials, "NULL argument");
+  BSGD_REQUIRE(vt == BSGD_VAL_F32 || (vt == BSGD_VAL_F16 && F->val16),
+               "value type not available in this store");
+  BSGD_REQUIRE(std::isfinite(mu), "mu must be finite");
+  float *zp = nullptr, *gp = nullptr;
+  const size_t need = fused_partial_floats(F, &zp, &gp, partials);
+  if (partials_bytes < need) {
+    set_error("partials workspace has %zu bytes, needs %zu", partials_bytes, need);
+    return BSGD_ERR_WORKSPACE;
+  }
+  const Layout& L = F->plan->L;
+  BSGD_HIP(permute_in(L, kPixels, x, F->xin, stream));
+  BSGD_HIP(permute_in(L, kRays, r, F->rin, stream));
+  if (y) BSGD_HIP(permute_in(L, kRays, y, F->yin, stream));
+  if (xadd) BSGD_HIP(permute_in(L, kPixels, xadd, F->xadd, stream));
+  BSGD_HIP(launch_fused_pass(F, vt, F->xin, F->rin, zp, gp, stream));
+  BSGD_HIP(launch_fused_reduce(F, zp, gp, y ? F->yin : nullptr, F->zo, xadd ? F->xadd : nullptr,
+                               xadd ? 2.0f * mu : 2.0f, F->go, stream));
+  BSGD_HIP(permute_out(L, kRays, F->zo, out_r, stream));
+  BSGD_HIP(permute_out(L, kPixels, F->go, out_x, stream));
+  return BSGD_OK;
+}

@@ -30,6 +30,9 @@ struct bsgd_state {
   double* partial = nullptr;  // kReduceBlocks + 1 (last = result)
   float* zf = nullptr;        // per-stage partials of the staged forward product
   float* zb = nullptr;        // ... and of the staged backprojection
+  const bsgd_fused* fz = nullptr;  // single-pass form (attached), with its partial sums
+  float* fz_zp = nullptr;
+  float* fz_gp = nullptr;
   int cur = 0;
   int overlap = 1;  // 0: forward pass concurrent with backprojection + prox; 1: with the prox only
   int prox_schedule = bsgd::kFgpFused;  // 2-D prox: fused chunks or one launch per iteration
@@ -275,9 +278,28 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
     // S2 (+S4) on `stream`; S1 on the aux stream after everything queued on
     // `stream` before this epoch (overlap 0) or after S2 (overlap 1), or on
     // `stream` after the prox (overlap 2: no concurrency)
+    float* step_out = theta == 0.f ? st->x[n] : st->xhat;
+    if (st->fz) {
+      // single pass over the tile-sliced store (lines 3-4 together), then the
+      // reduce (lines 6-8), then the prox (line 9), in order on `stream`
+      if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
+      BSGD_HIP(launch_fused_pass(st->fz, st->vt, st->x[c], st->r[c], st->fz_zp, st->fz_gp,
+                                 stream));
+      if (tv) BSGD_HIP(hipEventRecord(tv[1], stream));
+      if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
+      BSGD_HIP(launch_fused_reduce(st->fz, st->fz_zp, st->fz_gp, st->y, st->r[n], st->x[c],
+                                   2.0f * mu, step_out, stream));
+      if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
+      if (theta != 0.f)
+        BSGD_HIP(tv_prox_run(p->L, true, st->xhat, theta, prox_iters, st->x[n], st->tv_ws,
+                             stream, st->prox_schedule));
+      if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));
+      st->cur = n;
+      st->epochs_done++;
+      continue;
+    }
     if (st->overlap == 0) BSGD_HIP(hipEventRecord(st->ev_main, stream));
     if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
-    float* step_out = theta == 0.f ? st->x[n] : st->xhat;
     if (S == 1 && p->sbwd.lanes && st->zb)
       BSGD_HIP(launch_staged(p->sbwd, st->vt, kStep, st->r[c], p->L.r_int, nullptr, st->x[c],
                              2.0f * mu, step_out, st->zb, stream));
@@ -416,6 +438,32 @@ extern "C" bsgd_status bsgd_state_set_overlap(bsgd_state* st, int mode) {
   BSGD_REQUIRE(st != nullptr, "state is NULL");
   BSGD_REQUIRE(mode >= 0 && mode <= 2, "overlap mode must be 0, 1 or 2");
   st->overlap = mode;
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_state_attach_fused(bsgd_state* st, const bsgd_fused* fused,
+                                               void* partials, size_t partials_bytes) {
+  clear_error();
+  BSGD_REQUIRE(st != nullptr, "state is NULL");
+  if (!fused) {
+    st->fz = nullptr;
+    st->fz_zp = st->fz_gp = nullptr;
+    return BSGD_OK;
+  }
+  BSGD_REQUIRE(partials != nullptr, "partials is NULL");
+  BSGD_REQUIRE(fused_plan(fused) == st->plan, "the store belongs to another plan");
+  BSGD_REQUIRE(st->nrhs == 1, "single-pass epochs need a one-RHS state");
+  BSGD_REQUIRE(st->vt == BSGD_VAL_F32 || fused_has_f16(fused),
+               "the store has no FP16 values (plan without BSGD_PLAN_F16)");
+  float *zp = nullptr, *gp = nullptr;
+  const size_t need = fused_partial_floats(fused, &zp, &gp, partials);
+  if (partials_bytes < need) {
+    set_error("partials workspace has %zu bytes, needs %zu", partials_bytes, need);
+    return BSGD_ERR_WORKSPACE;
+  }
+  st->fz = fused;
+  st->fz_zp = zp;
+  st->fz_gp = gp;
   return BSGD_OK;
 }
 

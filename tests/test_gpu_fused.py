@@ -1,0 +1,258 @@
+"""Single-pass epochs (tile-sliced store) against the FP64 oracle (GPU, through the C ABI)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import (ITERATE_REL, PRODUCT_REL, abs_matrix, f32, matrix, mu_for, plan_for,
+                         problem, ragged_problem, rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+def _cases():
+    return {
+        "c1": lambda: problem("c1_64"),
+        # many slices per (tile, chunk) unit, full and partial 32 x 32 tiles
+        "medium": lambda: problem(None, H=192, W=192, n_ang=180, bins=273, M=4, N=4, seed=7),
+        # most rays miss the image (empty rows and empty chunks)
+        "wide": lambda: problem(None, H=64, W=64, n_ang=16, bins=2500, M=2, N=2, seed=8),
+        # non-square, ragged 8 x 8 and 32 x 32 tiles, ragged view groups
+        "ragged": ragged_problem,
+        # a single pixel row and a single tile column
+        "strip": lambda: problem(None, H=1, W=40, n_ang=12, bins=45, M=2, N=2, seed=9, lam=0.0),
+    }
+
+
+def _segments(p, view_len):
+    """Independent count of (ray, 32 x 32 tile) pairs with an entry, from the host CSR."""
+    rows = np.repeat(np.arange(p.nrows, dtype=np.int64), np.diff(p.row_ptr))
+    col = np.asarray(p.col, np.int64)
+    s, t = col // p.W, col % p.W
+    ftw = (p.W + 31) // 32
+    key = rows * (((p.H + 31) // 32) * ftw) + (s // 32) * ftw + t // 32
+    return len(np.unique(key))
+
+
+def _fused(plan, chunks=0, waves=None):
+    import paper_1812_01307_amd as bsgd
+    F = bsgd.bsgd_fused_create(plan, chunks)
+    if waves:
+        bsgd.bsgd_fused_set_waves(F, waves)
+    return F
+
+
+@pytest.mark.parametrize("name", ["c1", "medium", "wide", "ragged", "strip"])
+@pytest.mark.parametrize("view_len", [None, 0])
+def test_fused_products_match_oracle(name, view_len):
+    import paper_1812_01307_amd as bsgd
+    p = _cases()[name]()
+    plan = plan_for(p, view_len=view_len)
+    F = _fused(plan)
+    tiles, chunks, segs, slices, entries = bsgd.bsgd_fused_shape(F)
+    assert tiles == ((p.H + 31) // 32) * ((p.W + 31) // 32)
+    assert segs == _segments(p, view_len)
+    assert slices * 64 >= segs and entries >= p.nnz and entries % 256 == 0
+    A, Aabs = matrix(p), abs_matrix(p)
+    rng = np.random.default_rng(11)
+    x = f32(rng.random(p.ncols))
+    xa = f32(rng.standard_normal(p.ncols))
+    r = f32(rng.standard_normal(p.nrows))
+    y = f32(rng.standard_normal(p.nrows))
+    mu = 1.3e-3
+    ax, g = bsgd.bsgd_fused_apply(F, _dev(x), _dev(r))
+    res, step = bsgd.bsgd_fused_apply(F, _dev(x), _dev(r), y=_dev(y), xadd=_dev(xa), mu=mu)
+    ax, g, res, step = map(_host, (ax, g, res, step))
+    bound_f = PRODUCT_REL * (Aabs @ np.abs(x)) + 1e-30
+    bound_b = PRODUCT_REL * 2 * (Aabs.T @ np.abs(r)) + 1e-30
+    ref_ax = oracle.forward(A, x)
+    ref_g = oracle.backproject(A, r)
+    assert np.all(np.abs(ax - ref_ax) <= bound_f)
+    assert np.all(np.abs(g - ref_g) <= bound_b)
+    assert np.all(np.abs(res - (y - ref_ax)) <= bound_f + 1e-7 * np.abs(y))
+    assert np.all(np.abs(step - (xa + mu * ref_g)) <= mu * bound_b + 1e-7 * np.abs(xa))
+    # every chunk count and wave count gives the same sums up to rounding
+    groups = -(-p.nrows // (8 * p.bins)) if view_len is None else -(-p.nrows // 64)
+    for q, w in ((1, 2), (groups, 8), (max(1, groups // 2), 4)):
+        F2 = _fused(plan, q, w)
+        ax2, g2 = bsgd.bsgd_fused_apply(F2, _dev(x), _dev(r))
+        assert np.all(np.abs(_host(ax2) - ref_ax) <= bound_f)
+        assert np.all(np.abs(_host(g2) - ref_g) <= bound_b)
+
+
+def _run(p, plan, F, mu, lam, epochs, K, vt=0):
+    import paper_1812_01307_amd as bsgd
+    st = bsgd.bsgd_state_create(plan, 1, vt)
+    if F is not None:
+        bsgd.bsgd_state_attach_fused(st, F)
+    bsgd.bsgd_state_init(st, _dev(f32(p.y)))
+    xs = []
+    for _ in range(epochs):
+        bsgd.bsgd_run_epochs(st, mu, lam, 1, K)
+        xs.append(_host(bsgd.bsgd_get_x(st)))
+    return xs, st
+
+
+@pytest.mark.parametrize("name", ["c1", "medium", "wide", "ragged"])
+@pytest.mark.parametrize("view_len", [None, 0])
+def test_fused_trajectory_matches_oracle(name, view_len):
+    import paper_1812_01307_amd as bsgd
+    p = _cases()[name]()
+    plan = plan_for(p, view_len=view_len)
+    F = _fused(plan)
+    mu = float(np.float32(mu_for(p)))
+    lam, E = 5.0, 12
+    _, _, ref = oracle.bsgd_tv(matrix(p), f32(p.y).astype(np.float64), mu, lam, E, 20,
+                               (p.H, p.W), record=True)
+    xs, st = _run(p, plan, F, mu, lam, E, 20)
+    errs = [rel_l2(a, b) for a, b in zip(xs, ref)]
+    assert max(errs) <= ITERATE_REL, (max(errs), int(np.argmax(errs)))
+    # the residual carried to the next epoch is y - A x_{E-1}
+    r = _host(bsgd.bsgd_get_r(st))
+    x_prev = ref[-2]
+    r_ref = f32(p.y).astype(np.float64) - oracle.forward(matrix(p), x_prev)
+    assert rel_l2(r, r_ref) <= ITERATE_REL
+    # detached, the same state runs the row kernels again
+    xr, _ = _run(p, plan, None, mu, lam, E, 20)
+    assert max(rel_l2(a, b) for a, b in zip(xs, xr)) <= 1e-6
+
+
+def test_fused_c1_lambda_zero_and_visible_tv():
+    """Whole c1 runs (100 epochs) at the workload's lambda, lambda = 0 and a lambda the prox moves."""
+    p = problem("c1_64")
+    plan = plan_for(p)
+    F = _fused(plan)
+    mu = float(np.float32(mu_for(p)))
+    for lam in (p.lam, 0.0, 200.0):
+        _, _, ref = oracle.bsgd_tv(matrix(p), f32(p.y).astype(np.float64), mu, lam, p.epochs,
+                                   p.prox_iters, (p.H, p.W), record=True)
+        xs, _ = _run(p, plan, F, mu, lam, p.epochs, p.prox_iters)
+        assert max(rel_l2(a, b) for a, b in zip(xs, ref)) <= ITERATE_REL, lam
+
+
+def test_fused_fp16_values():
+    import paper_1812_01307_amd as bsgd
+    p = _cases()["medium"]()
+    plan = plan_for(p, f16=True)
+    F = _fused(plan)
+    mu = float(np.float32(mu_for(p)))
+    E = 10
+    xs, _ = _run(p, plan, F, mu, 5.0, E, 20, vt=bsgd.BSGD_VAL_F16)
+    vals = p.val.astype(np.float32).astype(np.float16).astype(np.float64)
+    A16 = oracle.as_matrix(p.row_ptr, p.col, vals, p.ncols)
+    _, _, ref = oracle.bsgd_tv(A16, f32(p.y).astype(np.float64), mu, 5.0, E, 20, (p.H, p.W),
+                               record=True)
+    assert max(rel_l2(a, b) for a, b in zip(xs, ref)) <= ITERATE_REL
+    # products in FP16 values against the FP16-rounded matrix
+    rng = np.random.default_rng(3)
+    x = f32(rng.random(p.ncols))
+    r = f32(rng.standard_normal(p.nrows))
+    ax, g = bsgd.bsgd_fused_apply(F, _dev(x), _dev(r), vt=bsgd.BSGD_VAL_F16)
+    Aabs = abs_matrix(p)
+    assert np.all(np.abs(_host(ax) - A16 @ x) <= PRODUCT_REL * (Aabs @ np.abs(x)) + 1e-30)
+    assert np.all(np.abs(_host(g) - 2 * (A16.T @ r))
+                  <= PRODUCT_REL * 2 * (Aabs.T @ np.abs(r)) + 1e-30)
+
+
+def test_fused_runs_are_bitwise_reproducible_and_graphs_replay_exactly():
+    import paper_1812_01307_amd as bsgd
+    p = _cases()["medium"]()
+    plan = plan_for(p)
+    mu = float(np.float32(mu_for(p)))
+    F = _fused(plan)
+    a, _ = _run(p, plan, F, mu, 20.0, 6, 20)
+    b, _ = _run(p, plan, F, mu, 20.0, 6, 20)
+    assert all(np.array_equal(u, v) for u, v in zip(a, b))
+    # a second store built from the same plan is identical, so are its results
+    c, _ = _run(p, plan, _fused(plan), mu, 20.0, 6, 20)
+    assert all(np.array_equal(u, v) for u, v in zip(a, c))
+    # 6 epochs as 3 replays of a 2-epoch graph, with eager work between replays
+    s = torch.cuda.Stream()
+    st = bsgd.bsgd_state_create(plan)
+    bsgd.bsgd_state_attach_fused(st, F)
+    with torch.cuda.stream(s):
+        bsgd.bsgd_state_init(st, _dev(f32(p.y)), stream=s)
+        gr = bsgd.bsgd_graph_create(st, mu, 20.0, 2, 20, stream=s)
+        for k in range(3):
+            bsgd.bsgd_graph_launch(gr, stream=s)
+            s.synchronize()
+            x = _host(bsgd.bsgd_get_x(st, stream=s))
+            assert np.array_equal(x, a[2 * k + 1]), k
+            _ = torch.ones(1000, device="cuda").sum().item()
+
+
+def test_fused_validation():
+    import paper_1812_01307_amd as bsgd
+    p = problem("c1_64")
+    plan = plan_for(p)
+    F = _fused(plan)
+    batch = bsgd.bsgd_state_create(plan, 4)
+    with pytest.raises(bsgd.BsgdError, match="one-RHS"):
+        bsgd.bsgd_state_attach_fused(batch, F)
+    other = plan_for(p)
+    st = bsgd.bsgd_state_create(other)
+    with pytest.raises(bsgd.BsgdError, match="another plan"):
+        bsgd.bsgd_state_attach_fused(st, F)
+    groups = -(-p.nrows // (8 * p.bins))
+    with pytest.raises(bsgd.BsgdError, match="chunks"):
+        bsgd.bsgd_fused_workspace_size(plan, groups + 1)
+    with pytest.raises(bsgd.BsgdError, match="waves"):
+        bsgd.bsgd_fused_set_waves(F, 3)
+    st = bsgd.bsgd_state_create(plan)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(bsgd.BsgdError) as e:
+        bsgd.bsgd_state_attach_fused(st, F, small)
+    assert e.value.status == bsgd.BSGD_ERR_WORKSPACE
+    bsgd.bsgd_state_attach_fused(st, F)
+    bsgd.bsgd_state_attach_fused(st, None)
+
+
+def test_fused_f16_state_needs_f16_store():
+    import paper_1812_01307_amd as bsgd
+    p = problem("c1_64")
+    plan = plan_for(p, f16=True)
+    F = _fused(plan)
+    st16 = bsgd.bsgd_state_create(plan, 1, bsgd.BSGD_VAL_F16)
+    bsgd.bsgd_state_attach_fused(st16, F)
+    plain = plan_for(p)
+    F32 = _fused(plain)
+    st = bsgd.bsgd_state_create(plain, 1, bsgd.BSGD_VAL_F32)
+    bsgd.bsgd_state_attach_fused(st, F32)
+
+
+def test_fused_full_size_sampled():
+    """512 x 512, 720 x 729 rays: the bench's store and launch, sampled rows and pixels."""
+    import paper_1812_01307_amd as bsgd
+    p = problem("c2_512")
+    plan = plan_for(p)
+    F = _fused(plan)
+    tiles, chunks, segs, slices, entries = bsgd.bsgd_fused_shape(F)
+    assert tiles == 256 and segs > p.nrows and entries >= p.nnz
+    rng = np.random.default_rng(12)
+    x = f32(rng.random(p.ncols))
+    r = f32(rng.standard_normal(p.nrows))
+    ax, g = bsgd.bsgd_fused_apply(F, _dev(x), _dev(r))
+    ax, g = _host(ax), _host(g)
+    rows = rng.choice(p.nrows, 4000, replace=False)
+    for k in rows:
+        a, b = p.row_ptr[k], p.row_ptr[k + 1]
+        v = p.val[a:b].astype(np.float32).astype(np.float64)
+        c = p.col[a:b]
+        ref = float(np.dot(v, x[c].astype(np.float64)))
+        assert abs(ax[k] - ref) <= PRODUCT_REL * float(np.dot(np.abs(v), np.abs(x[c]))) + 1e-30
+    tp, tc, tv = p.ensure_transpose()
+    for j in rng.choice(p.ncols, 2000, replace=False):
+        a, b = tp[j], tp[j + 1]
+        v = np.asarray(tv[a:b], np.float32).astype(np.float64)
+        c = tc[a:b]
+        ref = 2.0 * float(np.dot(v, r[c].astype(np.float64)))
+        assert abs(g[j] - ref) <= PRODUCT_REL * 2 * float(np.dot(np.abs(v), np.abs(r[c]))) + 1e-30

@@ -5,8 +5,11 @@ One step = one whole reconstruction job of the 512 x 512 workload
 (720 angles x 729 bins, M = N = 8 blocks, lambda = 0.01, 200 epochs, 20 FGP
 iterations), starting from A, A^T (FP32 CSR) and y already resident in HBM:
     S0   build the block store            (bsgd_plan_create)
+         and the tile-sliced store         (bsgd_fused_create; --path fused)
     S0'  u_max by power iteration, mu = 0.9 / (2 u_max)
     S1-S5 x 200 epochs                     (bsgd_run_epochs)
+With --path fused (default) every epoch reads the matrix once (both
+products in one pass); --path rows runs one pass over A and one over A^T.
 The reported value is epochs per second over whole jobs (setup included).
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
@@ -21,23 +24,19 @@ import time
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the two row kernels on c2_512 with FP32 values, from
-# the rocprofv3 FETCH_SIZE / WRITE_SIZE runs summarised in
-# profiles/k_rows_c2_512_hbm_counters.md (scaled by a plain copy's counts).
-# Valid only while the kernel and layout sources hash to the value recorded
-# with the counters; otherwise the figure is reported as null.
-PMC_TRAFFIC = {
-    "sha256": "be3793732a0c385bf69eb9b51bdf82d56f3af49148cca3b9efa7274481624abd",
-    "config": "c2_512", "vt": "f32",
-    "fwd": 2271395987, "bwd": 2182760762,
-}
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs (scaled by what the counters read for a plain copy), keyed
+# by (path, workload, value type[, staged, direction]).  Valid only while the
+# kernel and layout sources hash to the value recorded with the counters;
+# otherwise the figure is reported as null.
+PMC_TRAFFIC = {}
 
 
 def _kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1812_01307_amd", "csrc")
-    for f in ("spmv.hip", "plan.hip", "staged.hip", "bsgd_internal.h"):
+    for f in ("spmv.hip", "plan.hip", "staged.hip", "fused.hip", "bsgd_internal.h"):
         with open(os.path.join(base, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -59,13 +58,21 @@ def main(argv=None):
     ap.add_argument("--vt", choices=["f32", "f16"], default="f32")
     ap.add_argument("--epochs", type=int, default=None, help="override the workload's epoch count")
     ap.add_argument("--power-iters", type=int, default=30)
-    ap.add_argument("--cpu-epochs", type=int, default=5, help="oracle epochs timed for the CPU baseline")
+    ap.add_argument("--cpu-epochs", type=int, default=20,
+                    help="oracle epochs timed for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="time lane counts during plan creation")
-    ap.add_argument("--staged", default="bwd", choices=["none", "fwd", "bwd", "both"],
+    ap.add_argument("--path", default="fused", choices=["fused", "rows"],
+                    help="epoch products: one pass over the tile-sliced store (fused) or one "
+                         "pass over A and one over A^T (rows)")
+    ap.add_argument("--fused-chunks", type=int, default=0,
+                    help="ray chunks of the tile-sliced store (0: automatic)")
+    ap.add_argument("--fused-waves", type=int, default=8, choices=[2, 4, 8],
+                    help="wavefronts per (tile, chunk) workgroup of the single pass")
+    ap.add_argument("--staged", default=None, choices=["none", "fwd", "bwd", "both"],
                     help="directions built in the staged form (LDS-served gathers) and used by "
-                         "the epochs")
+                         "the epochs of --path rows (default bwd; none with --path fused)")
     ap.add_argument("--overlap", type=int, default=1, choices=[0, 1, 2],
                     help="epoch schedule: forward pass concurrent with backprojection (0), after it "
                          "and concurrent with the prox (1), or after the prox on one stream (2)")
@@ -92,6 +99,8 @@ def main(argv=None):
                     help="serving: skip the one-request-at-a-time comparison run")
     args = ap.parse_args(argv)
 
+    if args.staged is None:
+        args.staged = "none" if args.path == "fused" else "bwd"
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on exactly one GPU "
               "(see the design notes for how the path would shard)", file=sys.stderr)
@@ -142,6 +151,7 @@ def main(argv=None):
 
     timing = not args.no_kernel_timing
     acc = {"fwd": 0.0, "bwd": 0.0, "prox": 0.0, "n": 0}
+    fused = args.path == "fused"
 
     tuned = None
     if args.autotune:
@@ -169,7 +179,13 @@ def main(argv=None):
             mu = 0.9 / (2.0 * u)
         else:
             mu = fixed_mu
+        F = None
+        if fused:
+            F = bsgd.bsgd_fused_create(plan, args.fused_chunks)
+            bsgd.bsgd_fused_set_waves(F, args.fused_waves)
         st = bsgd.bsgd_state_create(plan, 1, vt)
+        if F is not None:
+            bsgd.bsgd_state_attach_fused(st, F)
         bsgd.bsgd_state_set_overlap(st, args.overlap)
         if args.prox_schedule is not None:
             bsgd.bsgd_state_set_prox_schedule(st, args.prox_schedule)
@@ -184,7 +200,7 @@ def main(argv=None):
             acc["bwd"] += b
             acc["prox"] += p
             acc["n"] += n
-        return st, x, mu, plan
+        return st, x, mu, plan, F
 
     for w in range(args.warmup):
         job(False)
@@ -194,7 +210,7 @@ def main(argv=None):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        st, x, mu, plan = job(True)
+        st, x, mu, plan, F = job(True)
         print(f"[bench] step {k + 1}/{args.steps}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -208,6 +224,8 @@ def main(argv=None):
 
     # epoch-only rate (no setup), for context
     st2 = bsgd.bsgd_state_create(plan, 1, vt)
+    if F is not None:
+        bsgd.bsgd_state_attach_fused(st2, F)
     bsgd.bsgd_state_set_overlap(st2, args.overlap)
     if args.prox_schedule is not None:
         bsgd.bsgd_state_set_prox_schedule(st2, args.prox_schedule)
@@ -221,6 +239,8 @@ def main(argv=None):
     if args.dump:
         # untimed: the iterate every --dump-every epochs of one more job
         st3 = bsgd.bsgd_state_create(plan, 1, vt)
+        if F is not None:
+            bsgd.bsgd_state_attach_fused(st3, F)
         bsgd.bsgd_state_init(st3, y)
         snaps = {}
         done = 0
@@ -252,9 +272,39 @@ def main(argv=None):
                 b_fwd = b
             else:
                 b_bwd = b
+    fused_info = None
+    if F is not None:
+        tiles, chunks, segs, slices, entries = bsgd.bsgd_fused_shape(F)
+        # matrix read once (16-bit columns, values; padding excluded), per-slot
+        # ray and rank, per-slice count and offset, x tile and r gathers once,
+        # per-segment partials and per-chunk partials of A^T r written
+        b_pass = (val_bytes + 2) * nnz + 6 * 64 * slices + 12 * slices + 4 * c + 4 * r \
+            + 4 * segs + 4 * chunks * c
+        # reduce: partials read, segment offsets, y, r' written, x read, x^ written
+        b_red = 4 * segs + 4 * (r + 1) + 8 * r + 4 * chunks * c + 8 * c
+        b_fwd, b_bwd = b_pass, b_red
+        fused_info = {"tiles": tiles, "chunks": chunks, "segments": segs, "slices": slices,
+                      "stored_entries": entries, "padding": round(entries / nnz - 1, 4),
+                      "waves": args.fused_waves, "alg_bytes_pass": b_pass,
+                      "alg_bytes_reduce": b_red}
     roofline = None
     kernel = {}
-    if timing and acc["n"]:
+    if timing and acc["n"] and F is not None:
+        f_ms = acc["fwd"] / acc["n"]
+        b_ms = acc["bwd"] / acc["n"]
+        p_ms = acc["prox"] / acc["n"]
+        kernel = {"pass_ms": f_ms, "reduce_ms": b_ms, "prox_ms": p_ms,
+                  "pass_gbs": b_fwd / f_ms / 1e6, "reduce_gbs": b_bwd / b_ms / 1e6}
+        achieved = b_fwd / f_ms / 1e6
+        traffic = None
+        key = ("fused", args.config, args.vt)
+        if key in PMC_TRAFFIC and _kernel_source_hash() == PMC_TRAFFIC[key]["sha256"]:
+            traffic = PMC_TRAFFIC[key]["bytes"]
+        roofline = {"bound": "hbm", "kernel": "k_fused (A x and A^T r in one pass: lines 3-4)",
+                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "alg_bytes_per_launch": b_fwd}
+    elif timing and acc["n"]:
         f_ms = acc["fwd"] / acc["n"]
         b_ms = acc["bwd"] / acc["n"]
         p_ms = acc["prox"] / acc["n"]
@@ -263,10 +313,9 @@ def main(argv=None):
         dom_bytes, dom_ms, dom = (b_fwd, f_ms, "fwd") if f_ms >= b_ms else (b_bwd, b_ms, "bwd")
         achieved = dom_bytes / dom_ms / 1e6
         traffic = None
-        if (PMC_TRAFFIC["config"] == args.config and PMC_TRAFFIC["vt"] == args.vt
-                and PMC_TRAFFIC.get("staged", "none") == args.staged
-                and _kernel_source_hash() == PMC_TRAFFIC["sha256"]):
-            traffic = PMC_TRAFFIC[dom]
+        key = ("rows", args.config, args.vt, args.staged, dom)
+        if key in PMC_TRAFFIC and _kernel_source_hash() == PMC_TRAFFIC[key]["sha256"]:
+            traffic = PMC_TRAFFIC[key]["bytes"]
         kname = "k_staged" if staged_info and staged_info["lanes"][0 if dom == "fwd" else 1] > 0 \
             else "k_rows"
         roofline = {"bound": "hbm", "kernel": "%s (%s)" % (kname, "A x: lines 4+6" if dom == "fwd"
@@ -310,6 +359,7 @@ def main(argv=None):
                                f"lambda={prob.lam}, {epochs} epochs, {K} FGP iterations, "
                                f"setup S0+S0' included)",
                    "nnz": nnz, "epochs_per_step": epochs, "power_iters": args.power_iters,
+                   "path": args.path,
                    "lanes_per_row": list(bsgd.bsgd_plan_lanes(plan)), "overlap": args.overlap,
                    "staged": args.staged,
                    "mu": "fixed from " + args.mu_file if fixed_mu is not None
@@ -320,6 +370,7 @@ def main(argv=None):
         "alg_gbs_epoch_only": round((b_fwd + b_bwd) / epoch_ms / 1e6, 1),
         "kernels": {k: round(v, 4) for k, v in kernel.items()},
         "staged": staged_info,
+        "fused": fused_info,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "quality": {"res_norm2": rn2, "rel_err_vs_phantom": round(rel_err_true, 5)},

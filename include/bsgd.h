@@ -337,10 +337,12 @@ bsgd_status bsgd_state_set_overlap(bsgd_state* state, int mode);
 
 /*
  * Schedule of the 2-D prox (line 9) kernels: 0 runs up to 20 FGP iterations
- * per launch, recomputing a halo as wide as the iteration count in LDS (few
- * launches, redundant work); 1 runs one iteration per launch (no redundant
- * work, small LDS footprint, so it shares the GPU well with the concurrent
- * forward pass on large images).  Same arithmetic per pixel.  Default 0.
+ * per launch on 32 x 32 tiles, recomputing a halo as wide as the iteration
+ * count (few launches, redundant work), with each thread keeping a strip of
+ * pixels' duals in registers; 2 is the same schedule with the duals in LDS;
+ * 1 runs one iteration per launch (no redundant work, small LDS footprint).
+ * Same arithmetic per pixel, so all three give identical results.
+ * Default 0.
  */
 bsgd_status bsgd_state_set_prox_schedule(bsgd_state* state, int schedule);
 

@@ -215,15 +215,24 @@ bsgd_status build_staged(Staged& st, const bsgd_csr& src, const Layout& L, int64
 
 // Single-pass products over the tile-sliced store (bsgd_fused): one pass
 // writes the per-segment partials of A x (zp) and the per-chunk partials of
-// A^T r (gp); the reduce adds them: out_r = y - A x (A x when y is NULL) and
-// out_x = xadd + scale * A^T r (scale * A^T r when xadd is NULL).  All
-// vectors in internal order.
-size_t fused_partial_floats(const bsgd_fused* F, float** zp, float** gp, void* ws);
+// A^T r (gp), with a fixed-point scale set from max |r| (*rmax_in); the
+// reduce adds them: out_r = y - A x (A x when y is NULL) and out_x = xadd +
+// scale * A^T r (scale * A^T r when xadd is NULL), and gathers max |out_r|
+// into *rmax_out (zeroed by the pass through rmax_zero) for the next pass.
+// All vectors in internal order.
+struct FusedPartials {
+  float* zp = nullptr;
+  float* gp = nullptr;
+  unsigned* rmax = nullptr;  // 2 words: max |r| of the two residual buffers
+};
+size_t fused_partials(const bsgd_fused* F, FusedPartials* fp, void* ws);
+hipError_t launch_fused_absmax(const float* v, int64_t n, unsigned* out, hipStream_t s);
 hipError_t launch_fused_pass(const bsgd_fused* F, bsgd_valtype vt, const float* x,
-                             const float* r, float* zp, float* gp, hipStream_t s);
+                             const float* r, const unsigned* rmax_in, unsigned* rmax_zero,
+                             float* zp, float* gp, hipStream_t s);
 hipError_t launch_fused_reduce(const bsgd_fused* F, const float* zp, const float* gp,
-                               const float* y, float* out_r, const float* xadd, float scale,
-                               float* out_x, hipStream_t s);
+                               const float* y, float* out_r, unsigned* rmax_out,
+                               const float* xadd, float scale, float* out_x, hipStream_t s);
 bool fused_has_f16(const bsgd_fused* F);
 const bsgd_plan* fused_plan(const bsgd_fused* F);
 
@@ -271,7 +280,7 @@ hipError_t fill_f32(float* x, int64_t n, float v, hipStream_t s);
 // tiled = true: the internal pixel order of L (c_int floats).  ws must hold
 // tv_ws_floats(n) floats with n the vector length.
 size_t tv_ws_floats(int64_t n, int D);
-enum FgpSchedule { kFgpFused = 0, kFgpPerIteration = 1 };
+enum FgpSchedule { kFgpFused = 0, kFgpPerIteration = 1, kFgpFusedLds = 2 };
 hipError_t tv_prox_run(const Layout& L, bool tiled, const float* b, float theta, int iters,
                        float* out, float* ws, hipStream_t s, int schedule);
 // S images in the internal 2-D pixel order, [c_int][S] (image index fastest),

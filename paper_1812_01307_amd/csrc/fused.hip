@@ -78,11 +78,12 @@ struct TileGeom {
 struct bsgd_fused {
   const bsgd_plan* plan = nullptr;
   bsgd::TileGeom g;
-  int waves = 4;             // wavefronts per unit workgroup (2, 4 or 8)
+  int waves = 8;             // wavefronts per unit workgroup (2, 4 or 8)
   int64_t pairs = 0, slices = 0, entries = 0, cap = 0;
   int maxrank = 0;           // most segments of one ray
   double smax = 0.0;         // largest column sum of |A| (bounds the sums of A^T r)
   int32_t* sbeg = nullptr;   // units + 1: first slice of each unit
+  int32_t* uorder = nullptr; // units: launch order (most slices first)
   int32_t* sng = nullptr;    // slices: 4-entry groups per lane
   int64_t* soff = nullptr;   // slices + 1: first entry of each slice
   int32_t* sray = nullptr;   // slices * 64: internal ray of each lane (-1: none)
@@ -408,48 +409,108 @@ static unsigned grid_for(int64_t n) {
 // ---------------------------------------------------------------------------
 // The pass
 // ---------------------------------------------------------------------------
-template <typename VT>
-__device__ __forceinline__ void load4(const VT* __restrict__ val, int64_t i, float (&a)[4]) {
-  if constexpr (sizeof(VT) == 4) {
-    const f32x4 v = *reinterpret_cast<const f32x4*>(reinterpret_cast<const float*>(val) + i);
-    a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
-  } else {
-    const f16x4 v = *reinterpret_cast<const f16x4*>(reinterpret_cast<const _Float16*>(val) + i);
-    a[0] = (float)v[0]; a[1] = (float)v[1]; a[2] = (float)v[2]; a[3] = (float)v[3];
-  }
-}
+// Fixed-point terms for the LDS sums of A^T r.  Scale 2^e, e from the largest
+// |r| (rmax, computed by the kernel that wrote r) and the largest column sum
+// of |A| (smax), so that every partial sum of a pixel stays below 2^46 in
+// magnitude.  A term t = rint(a * r * 2^e) is formed with one FP64 fma:
+// d = a * (r 2^e) + 1.5 * 2^52 is exact up to that rounding and its bit
+// pattern is bits(1.5 * 2^52) + t.  The bit patterns are added as 64-bit
+// integers with LDS atomics: bits(1.5 * 2^52) is a multiple of 2^48, so the
+// low 48 bits of the total are those of sum(t), which the flush sign-extends.
+// Integer addition is exact and associative, so the order of the atomics
+// does not change the result; the rounding of a term is below 2^-46 of the
+// largest possible sum.
+constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
 
-// 64-bit fixed-point terms for the LDS sums of A^T r.  Scale 2^e per
-// workgroup, e from the largest |r| of the workgroup's rays and the largest
-// column sum of |A| (smax): every partial sum of a pixel stays below 2^61 in
-// magnitude, and a term (the exact FP64 product a * r * 2^e) is rounded to
-// the nearest integer, an error below 2^-62 of the largest possible sum.
-// Integer addition is associative, so the order of the LDS atomics does not
-// change the result.
 __device__ __forceinline__ int fixed_exponent(double smax, float rmax) {
   const double b = smax * (double)rmax;
   if (!(b > 0.0) || !isfinite(b)) return 0;
   int E;
   (void)frexp(b, &E);  // b < 2^E
-  return min(max(61 - E, -1000), 1000);
+  return min(max(46 - E, -1000), 1000);
 }
 
 __device__ __forceinline__ unsigned long long to_fixed(float a, double rs) {
-  return (unsigned long long)(long long)rint((double)a * rs);
+  return (unsigned long long)__double_as_longlong(fma((double)a, rs, kMagic));
+}
+
+__device__ __forceinline__ double from_fixed(unsigned long long acc, double inv) {
+  const long long t = (long long)(acc << 16) >> 16;  // sign-extend the low 48 bits
+  return (double)t * inv;
+}
+
+struct SliceMeta {
+  int rho, rk, ng;
+  int64_t base;
+};
+
+__device__ __forceinline__ SliceMeta slice_meta(const int32_t* __restrict__ sray,
+                                                const uint16_t* __restrict__ srank,
+                                                const int32_t* __restrict__ sng,
+                                                const int64_t* __restrict__ soff, int s, int s1,
+                                                int lane) {
+  SliceMeta m{-1, 0, 0, 0};
+  if (s < s1) {
+    m.rho = sray[(int64_t)s * 64 + lane];
+    m.rk = srank[(int64_t)s * 64 + lane];
+    m.ng = sng[s];
+    m.base = soff[s] + lane * 4;
+  }
+  return m;
+}
+
+// Matrix streams are read once per pass: non-temporal loads keep them from
+// evicting the gathered r, the partial sums and the tables from the caches.
+template <typename T>
+__device__ __forceinline__ T ld_nt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
+template <typename VT>
+__device__ __forceinline__ void load_group(const uint16_t* __restrict__ col,
+                                           const VT* __restrict__ val, int64_t i, u16x4& c,
+                                           float (&a)[4]) {
+  c = ld_nt(reinterpret_cast<const u16x4*>(col + i));
+  if constexpr (sizeof(VT) == 4) {
+    const f32x4 v = ld_nt(reinterpret_cast<const f32x4*>(reinterpret_cast<const float*>(val) + i));
+    a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+  } else {
+    const f16x4 v = ld_nt(reinterpret_cast<const f16x4*>(reinterpret_cast<const _Float16*>(val) + i));
+    a[0] = (float)v[0]; a[1] = (float)v[1]; a[2] = (float)v[2]; a[3] = (float)v[3];
+  }
+}
+
+// z += a . x[c] (LDS gathers) and g[c] += a * r (fixed-point LDS atomics)
+__device__ __forceinline__ void group_step(const float* xs, unsigned long long* gs,
+                                           const u16x4& c, const float (&a)[4], double rs,
+                                           float& z) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    z = fmaf(a[t], xs[c[t]], z);
+    atomicAdd(&gs[c[t]], to_fixed(a[t], rs));
+  }
+}
+
+// Slice of wavefront wv in round k of a unit's slices (longest first): even
+// rounds in wavefront order, odd rounds reversed, so that the wavefronts of a
+// workgroup get nearly equal shares of a sorted list.
+template <int W>
+__device__ __forceinline__ int snake(int s0, int k, int wv) {
+  return s0 + k * W + ((k & 1) ? (W - 1 - wv) : wv);
 }
 
 template <typename VT, int W>
 __global__ __launch_bounds__(64 * W) void k_fused(
-    TileGeom g, const int32_t* __restrict__ sbeg, const int32_t* __restrict__ sng,
-    const int64_t* __restrict__ soff, const int32_t* __restrict__ sray,
-    const uint16_t* __restrict__ srank, const uint16_t* __restrict__ col,
-    const VT* __restrict__ val, const float* __restrict__ x, const float* __restrict__ r,
+    TileGeom g, const int32_t* __restrict__ uorder, const int32_t* __restrict__ sbeg,
+    const int32_t* __restrict__ sng, const int64_t* __restrict__ soff,
+    const int32_t* __restrict__ sray, const uint16_t* __restrict__ srank,
+    const uint16_t* __restrict__ col, const VT* __restrict__ val, const float* __restrict__ x,
+    const float* __restrict__ r, const unsigned* __restrict__ rmax_in, unsigned* rmax_zero,
     float* __restrict__ zp, float* __restrict__ gp, int64_t r_int, int64_t c_int, double smax) {
   __shared__ float xs[kFTA];
   __shared__ unsigned long long gs[kFTA];
-  __shared__ unsigned rmax_bits;
   constexpr int NT = 64 * W;
-  const int u = blockIdx.x;
+  const int u = uorder[blockIdx.x];  // largest units first
   const int tile = u / g.Q, q = u - tile * g.Q;
   const int per = g.FTh * g.FTw;
   const int d = tile / per;
@@ -459,19 +520,12 @@ __global__ __launch_bounds__(64 * W) void k_fused(
   const int tid = threadIdx.x;
   const int wv = tid >> 6, lane = tid & 63;
   const int s0 = sbeg[u], s1 = sbeg[u + 1];
+  // the next kernel of the epoch gathers the next residual's |r| maximum here
+  if (rmax_zero && blockIdx.x == 0 && tid == 0) *rmax_zero = 0u;
   for (int i = tid; i < kFTA; i += NT) {
     xs[i] = 0.f;
     gs[i] = 0ull;
   }
-  if (tid == 0) rmax_bits = 0u;
-  // largest |r| over the unit's rays (sets the fixed-point scale)
-  float rm = 0.f;
-  for (int s = s0 + wv; s < s1; s += W) {
-    const int rho = sray[(int64_t)s * 64 + lane];
-    if (rho >= 0) rm = fmaxf(rm, fabsf(r[rho]));
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) rm = fmaxf(rm, __shfl_xor(rm, off));
   __syncthreads();
   for (int i = tid; i < kFT * kFT; i += NT) {
     const int b = i >> 6, w = i & 63;
@@ -480,45 +534,63 @@ __global__ __launch_bounds__(64 * W) void k_fused(
       xs[(((b >> 2) << 3) + (w >> 3)) * kFTS + ((b & 3) << 3) + (w & 7)] =
           x[xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w];
   }
-  // |r| >= 0, so its bit pattern orders like the value (a NaN sorts above
-  // every finite value and gives exponent 0)
-  if (lane == 0) atomicMax(&rmax_bits, __float_as_uint(rm));
-  __syncthreads();
-  const int e = fixed_exponent(smax, __uint_as_float(rmax_bits));
+  const int e = fixed_exponent(smax, __uint_as_float(*rmax_in));
   const double scale = ldexp(1.0, e);
-  for (int s = s0 + wv; s < s1; s += W) {
-    const int rho = sray[(int64_t)s * 64 + lane];
-    const int rk = srank[(int64_t)s * 64 + lane];
-    const double rs = rho >= 0 ? (double)r[rho] * scale : 0.0;
-    const int64_t base = soff[s] + lane * 4;
-    const int ng = sng[s];
+  __syncthreads();
+  // the next slice's table entries and its r value load while a slice streams
+  int k = 0, s = snake<W>(s0, 0, wv);
+  SliceMeta cur = slice_meta(sray, srank, sng, soff, s, s1, lane);
+  float rcur = cur.rho >= 0 ? r[cur.rho] : 0.f;
+  while (s < s1) {
+    const int sn = snake<W>(s0, k + 1, wv);
+    const SliceMeta nxt = slice_meta(sray, srank, sng, soff, sn, s1, lane);
+    const double rs = (double)rcur * scale;
+    const int64_t base = cur.base;
+    const int ng = cur.ng;
     float z0 = 0.f, z1 = 0.f;
+    float rnext = 0.f;
+    bool fetched = false;
     int j = 0;
-    for (; j + 1 < ng; j += 2) {
-      const u16x4 c0 = *reinterpret_cast<const u16x4*>(col + base + (int64_t)j * 256);
-      const u16x4 c1 = *reinterpret_cast<const u16x4*>(col + base + (int64_t)(j + 1) * 256);
-      float a0[4], a1[4];
-      load4<VT>(val, base + (int64_t)j * 256, a0);
-      load4<VT>(val, base + (int64_t)(j + 1) * 256, a1);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        z0 = fmaf(a0[t], xs[c0[t]], z0);
-        atomicAdd(&gs[c0[t]], to_fixed(a0[t], rs));
-        z1 = fmaf(a1[t], xs[c1[t]], z1);
-        atomicAdd(&gs[c1[t]], to_fixed(a1[t], rs));
+    for (; j + 3 < ng; j += 4) {
+      u16x4 c0, c1, c2, c3;
+      float a0[4], a1[4], a2[4], a3[4];
+      load_group<VT>(col, val, base + (int64_t)j * 256, c0, a0);
+      load_group<VT>(col, val, base + (int64_t)(j + 1) * 256, c1, a1);
+      load_group<VT>(col, val, base + (int64_t)(j + 2) * 256, c2, a2);
+      load_group<VT>(col, val, base + (int64_t)(j + 3) * 256, c3, a3);
+      if (!fetched) {
+        fetched = true;
+        if (nxt.rho >= 0) rnext = r[nxt.rho];
       }
+      group_step(xs, gs, c0, a0, rs, z0);
+      group_step(xs, gs, c1, a1, rs, z1);
+      group_step(xs, gs, c2, a2, rs, z0);
+      group_step(xs, gs, c3, a3, rs, z1);
+    }
+    for (; j + 1 < ng; j += 2) {
+      u16x4 c0, c1;
+      float a0[4], a1[4];
+      load_group<VT>(col, val, base + (int64_t)j * 256, c0, a0);
+      load_group<VT>(col, val, base + (int64_t)(j + 1) * 256, c1, a1);
+      if (!fetched) {
+        fetched = true;
+        if (nxt.rho >= 0) rnext = r[nxt.rho];
+      }
+      group_step(xs, gs, c0, a0, rs, z0);
+      group_step(xs, gs, c1, a1, rs, z1);
     }
     if (j < ng) {
-      const u16x4 c0 = *reinterpret_cast<const u16x4*>(col + base + (int64_t)j * 256);
+      u16x4 c0;
       float a0[4];
-      load4<VT>(val, base + (int64_t)j * 256, a0);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        z0 = fmaf(a0[t], xs[c0[t]], z0);
-        atomicAdd(&gs[c0[t]], to_fixed(a0[t], rs));
-      }
+      load_group<VT>(col, val, base + (int64_t)j * 256, c0, a0);
+      group_step(xs, gs, c0, a0, rs, z0);
     }
-    if (rho >= 0) zp[(int64_t)rk * r_int + rho] = z0 + z1;
+    if (!fetched && nxt.rho >= 0) rnext = r[nxt.rho];
+    if (cur.rho >= 0) zp[(int64_t)cur.rk * r_int + cur.rho] = z0 + z1;
+    ++k;
+    s = sn;
+    cur = nxt;
+    rcur = rnext;
   }
   __syncthreads();
   const double inv = ldexp(1.0, -e);
@@ -528,20 +600,23 @@ __global__ __launch_bounds__(64 * W) void k_fused(
     if (tr8 < g.Ht && tc8 < g.Wt) {
       const int a = (((b >> 2) << 3) + (w >> 3)) * kFTS + ((b & 3) << 3) + (w & 7);
       gp[(int64_t)q * c_int + xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w] =
-          (float)((double)(long long)gs[a] * inv);
+          (float)from_fixed(gs[a], inv);
     }
   }
 }
 
 // Rays: out_r = y - sum of the ray's segment partials zp[rank][ray] in rank
-// order, or the sum when y is NULL.  Pixels: out_x = xadd + scale * (sum of the Q chunk
+// order, or the sum when y is NULL; max |out_r| is gathered in *rmax_out (as
+// the bit pattern of a non-negative float, which orders like the value).  Pixels: out_x = xadd + scale * (sum of the Q chunk
 // partials, in chunk order), or scale * sum when xadd is NULL.
 __global__ __launch_bounds__(256) void k_fz_reduce(
     const int32_t* __restrict__ poff, const float* __restrict__ zp,
-    const float* __restrict__ y, float* __restrict__ out_r,
+    const float* __restrict__ y, float* __restrict__ out_r, unsigned* rmax_out,
     int64_t r_int, const float* __restrict__ gp, int Q, const float* __restrict__ xadd,
     float scale, float* __restrict__ out_x, int64_t c_int) {
   const int64_t tot = r_int + c_int;
+  float m = 0.f;
+  bool bad = false;  // a NaN residual (fmaxf would drop it)
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < tot;
        i += (int64_t)gridDim.x * 256) {
     if (i < r_int) {
@@ -558,7 +633,10 @@ __global__ __launch_bounds__(256) void k_fz_reduce(
         a += v3;
       }
       for (; k < n; ++k) a += z[(int64_t)k * r_int];
-      out_r[i] = y ? y[i] - a : a;
+      const float o = y ? y[i] - a : a;
+      out_r[i] = o;
+      m = fmaxf(m, fabsf(o));
+      bad = bad || (o != o);
     } else {
       const int64_t p = i - r_int;
       float a = 0.f;
@@ -566,54 +644,95 @@ __global__ __launch_bounds__(256) void k_fz_reduce(
       out_x[p] = xadd ? fmaf(scale, a, xadd[p]) : scale * a;
     }
   }
+  if (rmax_out) {
+    unsigned mb = bad ? 0x7fc00000u : __float_as_uint(m);  // NaN orders above +inf
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mb = max(mb, (unsigned)__shfl_xor((int)mb, off));
+    // one atomic per wavefront at most, and only while it raises the maximum
+    // (thousands of atomics on one word serialise)
+    if ((threadIdx.x & 63) == 0 && mb > __atomic_load_n(rmax_out, __ATOMIC_RELAXED))
+      atomicMax(rmax_out, mb);
+  }
+}
+
+__global__ void k_fz_zero_u32(unsigned* p) { *p = 0u; }
+
+// max |v| over n floats into *out (zeroed by the preceding launch)
+__global__ __launch_bounds__(256) void k_fz_absmax(const float* __restrict__ v, int64_t n,
+                                                   unsigned* out) {
+  float m = 0.f;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    const float o = v[i];
+    m = fmaxf(m, fabsf(o));
+    bad = bad || (o != o);
+  }
+  unsigned mb = bad ? 0x7fc00000u : __float_as_uint(m);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mb = max(mb, (unsigned)__shfl_xor((int)mb, off));
+  if ((threadIdx.x & 63) == 0 && mb > __atomic_load_n(out, __ATOMIC_RELAXED)) atomicMax(out, mb);
 }
 
 template <typename VT, int W>
 static void launch_fused_w(const bsgd_fused& F, const VT* val, const float* x, const float* r,
-                           float* zp, float* gp, hipStream_t s) {
+                           const unsigned* rmax_in, unsigned* rmax_zero, float* zp, float* gp,
+                           hipStream_t s) {
   k_fused<VT, W><<<(unsigned)F.g.units(), 64 * W, 0, s>>>(
-      F.g, F.sbeg, F.sng, F.soff, F.sray, F.srank, F.col, val, x, r, zp, gp, F.plan->L.r_int,
-      F.plan->L.c_int, F.smax);
+      F.g, F.uorder, F.sbeg, F.sng, F.soff, F.sray, F.srank, F.col, val, x, r, rmax_in,
+      rmax_zero, zp, gp, F.plan->L.r_int, F.plan->L.c_int, F.smax);
 }
 
 template <typename VT>
 static void launch_fused_vt(const bsgd_fused& F, const VT* val, const float* x, const float* r,
-                            float* zp, float* gp, hipStream_t s) {
+                            const unsigned* rmax_in, unsigned* rmax_zero, float* zp, float* gp,
+                            hipStream_t s) {
   switch (F.waves) {
-    case 2: launch_fused_w<VT, 2>(F, val, x, r, zp, gp, s); break;
-    case 8: launch_fused_w<VT, 8>(F, val, x, r, zp, gp, s); break;
-    default: launch_fused_w<VT, 4>(F, val, x, r, zp, gp, s); break;
+    case 2: launch_fused_w<VT, 2>(F, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
+    case 4: launch_fused_w<VT, 4>(F, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
+    default: launch_fused_w<VT, 8>(F, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
   }
 }
 
 bool fused_has_f16(const bsgd_fused* F) { return F->val16 != nullptr; }
 const bsgd_plan* fused_plan(const bsgd_fused* F) { return F->plan; }
 
-size_t fused_partial_floats(const bsgd_fused* F, float** zp, float** gp, void* ws) {
+size_t fused_partials(const bsgd_fused* F, FusedPartials* fp, void* ws) {
   Carver cv(ws);
   float* a = cv.take<float>((size_t)std::max(F->maxrank, 1) * F->plan->L.r_int);
   float* b = cv.take<float>((size_t)F->g.Q * F->plan->L.c_int);
-  if (zp) *zp = a;
-  if (gp) *gp = b;
+  unsigned* m = cv.take<unsigned>(2);
+  if (fp) {
+    fp->zp = a;
+    fp->gp = b;
+    fp->rmax = m;
+  }
   return align_up(cv.off, kAlign);
 }
 
+hipError_t launch_fused_absmax(const float* v, int64_t n, unsigned* out, hipStream_t s) {
+  k_fz_zero_u32<<<1, 1, 0, s>>>(out);
+  k_fz_absmax<<<grid_for(n), 256, 0, s>>>(v, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_fused_pass(const bsgd_fused* F, bsgd_valtype vt, const float* x,
-                             const float* r, float* zp, float* gp, hipStream_t s) {
+                             const float* r, const unsigned* rmax_in, unsigned* rmax_zero,
+                             float* zp, float* gp, hipStream_t s) {
   if (vt == BSGD_VAL_F16)
-    launch_fused_vt<__half>(*F, F->val16, x, r, zp, gp, s);
+    launch_fused_vt<__half>(*F, F->val16, x, r, rmax_in, rmax_zero, zp, gp, s);
   else
-    launch_fused_vt<float>(*F, F->val, x, r, zp, gp, s);
+    launch_fused_vt<float>(*F, F->val, x, r, rmax_in, rmax_zero, zp, gp, s);
   return hipGetLastError();
 }
 
 hipError_t launch_fused_reduce(const bsgd_fused* F, const float* zp, const float* gp,
-                               const float* y, float* out_r, const float* xadd, float scale,
-                               float* out_x, hipStream_t s) {
+                               const float* y, float* out_r, unsigned* rmax_out,
+                               const float* xadd, float scale, float* out_x, hipStream_t s) {
   const Layout& L = F->plan->L;
   const int64_t tot = L.r_int + L.c_int;
-  k_fz_reduce<<<grid_for(tot), 256, 0, s>>>(F->poff, zp, y, out_r, L.r_int, gp, F->g.Q,
-                                            xadd, scale, out_x, L.c_int);
+  k_fz_reduce<<<grid_for(tot), 256, 0, s>>>(F->poff, zp, y, out_r, rmax_out, L.r_int, gp,
+                                            F->g.Q, xadd, scale, out_x, L.c_int);
   return hipGetLastError();
 }
 
@@ -625,6 +744,7 @@ struct FusedCounts {
   int maxrank = 0;
   std::vector<int64_t> ubeg;   // units + 1
   std::vector<int32_t> sbeg;   // units + 1
+  std::vector<int32_t> uorder; // units, most slices first (stable)
 };
 
 // Count pass: segments per ray (into plan->scratch64, then scanned in place)
@@ -671,6 +791,11 @@ static bsgd_status fused_count(const bsgd_plan* p, const TileGeom& g, hipStream_
     if (nsl > 0) bound += 64 * ((int64_t)hm[u] + 3) + hl[u] + 192 * nsl;
   }
   fc.sbeg[units] = (int32_t)sl;
+  fc.uorder.resize(units);
+  for (int64_t u = 0; u < units; ++u) fc.uorder[u] = (int32_t)u;
+  std::stable_sort(fc.uorder.begin(), fc.uorder.end(), [&](int32_t a, int32_t b) {
+    return fc.sbeg[a + 1] - fc.sbeg[a] > fc.sbeg[b + 1] - fc.sbeg[b];
+  });
   fc.maxrank = hc[units];
   BSGD_REQUIRE(fc.maxrank < 65536, "a ray crosses %d tiles (at most 65535)", fc.maxrank);
   fc.slices = sl;
@@ -706,6 +831,7 @@ static size_t fused_layout(const bsgd_plan* p, const TileGeom& g, const FusedCou
   const int64_t np = std::max<int64_t>(fc.pairs, 1);
   const bool f16 = p->fwd.val16 != nullptr;
   F->sbeg = cv.take<int32_t>(units + 1);
+  F->uorder = cv.take<int32_t>(units);
   F->sng = cv.take<int32_t>(std::max<int64_t>(fc.slices, 1));
   F->soff = cv.take<int64_t>(fc.slices + 1);
   F->sray = cv.take<int32_t>(nslots);
@@ -820,6 +946,9 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, void
   e = hipMemcpyAsync(F->sbeg, fc.sbeg.data(), sizeof(int32_t) * (units + 1),
                      hipMemcpyHostToDevice, stream);
   if (e == hipSuccess)
+    e = hipMemcpyAsync(F->uorder, fc.uorder.data(), sizeof(int32_t) * units,
+                       hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess)
     e = hipMemcpyAsync(T.ubeg, fc.ubeg.data(), sizeof(int64_t) * (units + 1),
                        hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipMemsetAsync(T.err, 0, sizeof(int), stream);
@@ -931,7 +1060,7 @@ extern "C" bsgd_status bsgd_fused_set_waves(bsgd_fused* F, int waves) {
 extern "C" bsgd_status bsgd_fused_partials_size(const bsgd_fused* F, size_t* bytes) {
   clear_error();
   BSGD_REQUIRE(F && bytes, "NULL argument");
-  *bytes = fused_partial_floats(F, nullptr, nullptr, nullptr);
+  *bytes = fused_partials(F, nullptr, nullptr);
   return BSGD_OK;
 }
 
@@ -944,8 +1073,8 @@ extern "C" bsgd_status bsgd_fused_apply(const bsgd_fused* F, bsgd_valtype vt, co
   BSGD_REQUIRE(vt == BSGD_VAL_F32 || (vt == BSGD_VAL_F16 && F->val16),
                "value type not available in this store");
   BSGD_REQUIRE(std::isfinite(mu), "mu must be finite");
-  float *zp = nullptr, *gp = nullptr;
-  const size_t need = fused_partial_floats(F, &zp, &gp, partials);
+  FusedPartials fp;
+  const size_t need = fused_partials(F, &fp, partials);
   if (partials_bytes < need) {
     set_error("partials workspace has %zu bytes, needs %zu", partials_bytes, need);
     return BSGD_ERR_WORKSPACE;
@@ -955,9 +1084,10 @@ extern "C" bsgd_status bsgd_fused_apply(const bsgd_fused* F, bsgd_valtype vt, co
   BSGD_HIP(permute_in(L, kRays, r, F->rin, stream));
   if (y) BSGD_HIP(permute_in(L, kRays, y, F->yin, stream));
   if (xadd) BSGD_HIP(permute_in(L, kPixels, xadd, F->xadd, stream));
-  BSGD_HIP(launch_fused_pass(F, vt, F->xin, F->rin, zp, gp, stream));
-  BSGD_HIP(launch_fused_reduce(F, zp, gp, y ? F->yin : nullptr, F->zo, xadd ? F->xadd : nullptr,
-                               xadd ? 2.0f * mu : 2.0f, F->go, stream));
+  BSGD_HIP(launch_fused_absmax(F->rin, L.r_int, fp.rmax, stream));
+  BSGD_HIP(launch_fused_pass(F, vt, F->xin, F->rin, fp.rmax, nullptr, fp.zp, fp.gp, stream));
+  BSGD_HIP(launch_fused_reduce(F, fp.zp, fp.gp, y ? F->yin : nullptr, F->zo, nullptr,
+                               xadd ? F->xadd : nullptr, xadd ? 2.0f * mu : 2.0f, F->go, stream));
   BSGD_HIP(permute_out(L, kRays, F->zo, out_r, stream));
   BSGD_HIP(permute_out(L, kPixels, F->go, out_x, stream));
   return BSGD_OK;

@@ -31,8 +31,7 @@ struct bsgd_state {
   float* zf = nullptr;        // per-stage partials of the staged forward product
   float* zb = nullptr;        // ... and of the staged backprojection
   const bsgd_fused* fz = nullptr;  // single-pass form (attached), with its partial sums
-  float* fz_zp = nullptr;
-  float* fz_gp = nullptr;
+  bsgd::FusedPartials fzp;
   int cur = 0;
   int overlap = 1;  // 0: forward pass concurrent with backprojection + prox; 1: with the prox only
   int prox_schedule = bsgd::kFgpFused;  // 2-D prox: fused chunks or one launch per iteration
@@ -281,13 +280,17 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
     float* step_out = theta == 0.f ? st->x[n] : st->xhat;
     if (st->fz) {
       // single pass over the tile-sliced store (lines 3-4 together), then the
-      // reduce (lines 6-8), then the prox (line 9), in order on `stream`
+      // reduce (lines 6-8), then the prox (line 9), in order on `stream`.
+      // max |r| of the residual the pass reads: computed at the start of each
+      // call, then carried by the reduce (which writes the next residual)
+      const FusedPartials& fp = st->fzp;
+      if (e == 0) BSGD_HIP(launch_fused_absmax(st->r[c], p->L.r_int, fp.rmax + c, stream));
       if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
-      BSGD_HIP(launch_fused_pass(st->fz, st->vt, st->x[c], st->r[c], st->fz_zp, st->fz_gp,
-                                 stream));
+      BSGD_HIP(launch_fused_pass(st->fz, st->vt, st->x[c], st->r[c], fp.rmax + c, fp.rmax + n,
+                                 fp.zp, fp.gp, stream));
       if (tv) BSGD_HIP(hipEventRecord(tv[1], stream));
       if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
-      BSGD_HIP(launch_fused_reduce(st->fz, st->fz_zp, st->fz_gp, st->y, st->r[n], st->x[c],
+      BSGD_HIP(launch_fused_reduce(st->fz, fp.zp, fp.gp, st->y, st->r[n], fp.rmax + n, st->x[c],
                                    2.0f * mu, step_out, stream));
       if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
       if (theta != 0.f)
@@ -447,7 +450,7 @@ extern "C" bsgd_status bsgd_state_attach_fused(bsgd_state* st, const bsgd_fused*
   BSGD_REQUIRE(st != nullptr, "state is NULL");
   if (!fused) {
     st->fz = nullptr;
-    st->fz_zp = st->fz_gp = nullptr;
+    st->fzp = FusedPartials();
     return BSGD_OK;
   }
   BSGD_REQUIRE(partials != nullptr, "partials is NULL");
@@ -455,23 +458,23 @@ extern "C" bsgd_status bsgd_state_attach_fused(bsgd_state* st, const bsgd_fused*
   BSGD_REQUIRE(st->nrhs == 1, "single-pass epochs need a one-RHS state");
   BSGD_REQUIRE(st->vt == BSGD_VAL_F32 || fused_has_f16(fused),
                "the store has no FP16 values (plan without BSGD_PLAN_F16)");
-  float *zp = nullptr, *gp = nullptr;
-  const size_t need = fused_partial_floats(fused, &zp, &gp, partials);
+  FusedPartials fp;
+  const size_t need = fused_partials(fused, &fp, partials);
   if (partials_bytes < need) {
     set_error("partials workspace has %zu bytes, needs %zu", partials_bytes, need);
     return BSGD_ERR_WORKSPACE;
   }
   st->fz = fused;
-  st->fz_zp = zp;
-  st->fz_gp = gp;
+  st->fzp = fp;
   return BSGD_OK;
 }
 
 extern "C" bsgd_status bsgd_state_set_prox_schedule(bsgd_state* st, int schedule) {
   clear_error();
   BSGD_REQUIRE(st != nullptr, "state is NULL");
-  BSGD_REQUIRE(schedule == kFgpFused || schedule == kFgpPerIteration,
-               "prox schedule must be 0 or 1");
+  BSGD_REQUIRE(schedule == kFgpFused || schedule == kFgpPerIteration ||
+                   schedule == kFgpFusedLds,
+               "prox schedule must be 0, 1 or 2");
   st->prox_schedule = schedule;
   return BSGD_OK;
 }

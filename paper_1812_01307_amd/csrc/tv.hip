@@ -299,6 +299,185 @@ __global__ __launch_bounds__(kFThreads) void k_fgp_fused2(
   }
 }
 
+// Register-resident fused 2-D FGP (the default schedule): the same chunks,
+// tiles, halo and per-pixel arithmetic as k_fgp_fused2, with each thread
+// owning a strip of kRNP rows of one column of the tile-plus-halo region.
+// b and the last two duals stay in registers; an iteration publishes q_h
+// (all rows) and q_v (the strip's first row) to LDS for the D^T q stencil,
+// then u (all rows; the strip's last row separately) for the D u stencil,
+// with two barriers.  Vertical neighbours inside a strip come from
+// registers, so an iteration costs about four LDS accesses per pixel
+// instead of about twenty.  Region-edge pixels read zeros for their missing
+// neighbours; like the LDS-resident kernel, errors from the edge move one
+// pixel per iteration and stay inside the halo.
+constexpr int kRNP = 6;                                  // rows per thread
+constexpr int kRThreads = 1024;
+constexpr int kRMax = kFT + 2 * (kFuseMax + 1);          // 74
+constexpr int kRP = kRMax + 2;                           // LDS pitch: a pad column each side
+constexpr int kRNS = (kRMax + kRNP - 1) / kRNP;          // 13 strips
+
+template <bool TILED>
+__global__ __launch_bounds__(kRThreads) void k_fgp_reg2(
+    Layout L, int S, const float* __restrict__ lam, float mu, float theta0,
+    const float* __restrict__ b, int k0, int iters, FuseArgs ca, const float* __restrict__ in1v,
+    const float* __restrict__ in1h, const float* __restrict__ in2v,
+    const float* __restrict__ in2h, float* __restrict__ out_x, float* __restrict__ o1v,
+    float* __restrict__ o1h, float* __restrict__ o2v, float* __restrict__ o2h) {
+  __shared__ float sqh[kRMax * kRP];           // q_h, then p_h for the output stencil
+  __shared__ float su[kRMax * kRP];            // u
+  __shared__ float sqv[(kRNS + 1) * kRP];      // q_v (then p_v) of each strip's first row
+  __shared__ float sub[(kRNS + 1) * kRP];      // u of strip k-1's last row at k
+  const int H = L.H, W = L.W;
+  const int h = iters + 1;
+  const int R = kFT + 2 * h;
+  const int NS = (R + kRNP - 1) / kRNP;
+  const int s0 = blockIdx.y * kFT - h, t0 = blockIdx.x * kFT - h;
+  const int tid = threadIdx.x;
+  const int img = blockIdx.z;
+  const float theta = lam ? mu * lam[img] : theta0;
+  if (theta == 0.f) {
+    if (out_x)
+      for (int q = tid; q < kFT * kFT; q += kRThreads) {
+        const int s = s0 + h + q / kFT, t = t0 + h + q % kFT;
+        if (s < H && t < W) {
+          const int64_t i = pidx<TILED>(L, 0, s, t) * S + img;
+          out_x[i] = b[i];
+        }
+      }
+    return;
+  }
+  const float step = 1.0f / (8.0f * theta);
+  const bool active = tid < R * NS;
+  const int col = active ? tid % R : 0, strip = active ? tid / R : 0;
+  // cells no thread writes (pads, rows past the region) read as zero
+  for (int q = tid; q < kRMax * kRP; q += kRThreads) {
+    sqh[q] = 0.f;
+    su[q] = 0.f;
+  }
+  for (int q = tid; q < (kRNS + 1) * kRP; q += kRThreads) {
+    sqv[q] = 0.f;
+    sub[q] = 0.f;
+  }
+  __syncthreads();
+  const int row0 = strip * kRNP;
+  const int t = t0 + col;
+  const int lc = col + 1;  // LDS column
+  float vb[kRNP], p1v[kRNP], p1h[kRNP], p2v[kRNP], p2h[kRNP];
+  unsigned inside = 0;  // bit r: row0 + r is in the region and the pixel in the image
+#pragma unroll
+  for (int r = 0; r < kRNP; ++r) {
+    const int ls = row0 + r, s = s0 + ls;
+    vb[r] = p1v[r] = p1h[r] = p2v[r] = p2h[r] = 0.f;
+    if (active && ls < R && s >= 0 && s < H && t >= 0 && t < W) {
+      inside |= 1u << r;
+      const int64_t i = pidx<TILED>(L, 0, s, t) * S + img;
+      vb[r] = b[i];
+      if (k0 >= 1) {
+        p1v[r] = in1v[i];
+        p1h[r] = in1h[i];
+      }
+      if (k0 >= 2) {
+        p2v[r] = in2v[i];
+        p2h[r] = in2h[i];
+      }
+    }
+  }
+  for (int m = 1; m <= iters; ++m) {
+    const int k = k0 + m;
+    const int qm = k == 1 ? kQZero : (k == 2 ? kQCopy : kQMomentum);
+    const float coef = ca.coef[m];
+    float qv[kRNP], qh[kRNP], u[kRNP];
+#pragma unroll
+    for (int r = 0; r < kRNP; ++r) {
+      qv[r] = qm == kQZero ? 0.f : (qm == kQCopy ? p1v[r] : fmaf(coef, p1v[r] - p2v[r], p1v[r]));
+      qh[r] = qm == kQZero ? 0.f : (qm == kQCopy ? p1h[r] : fmaf(coef, p1h[r] - p2h[r], p1h[r]));
+    }
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < kRNP; ++r)
+        if (row0 + r < R) sqh[(row0 + r) * kRP + lc] = qh[r];
+      sqv[strip * kRP + lc] = qv[0];
+    }
+    __syncthreads();
+    // u = b - theta D^T q
+    const float qv_next = sqv[(strip + 1) * kRP + lc];  // first row of the strip below
+#pragma unroll
+    for (int r = 0; r < kRNP; ++r) {
+      u[r] = 0.f;
+      if (inside & (1u << r)) {
+        const int ls = row0 + r;
+        const float below = r + 1 < kRNP ? qv[r + 1] : qv_next;
+        const float right = sqh[ls * kRP + lc + 1];
+        const float dtq = (qv[r] - below) + (qh[r] - right);
+        u[r] = vb[r] - theta * dtq;
+      }
+    }
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < kRNP; ++r)
+        if (row0 + r < R) su[(row0 + r) * kRP + lc] = u[r];
+      sub[(strip + 1) * kRP + lc] = u[kRNP - 1];
+    }
+    __syncthreads();
+    // p = P(q + D u / (8 theta))
+    const float u_prev = sub[strip * kRP + lc];  // last row of the strip above
+#pragma unroll
+    for (int r = 0; r < kRNP; ++r) {
+      if (inside & (1u << r)) {
+        const int ls = row0 + r, s = s0 + ls;
+        const float uc = u[r];
+        const float above = r > 0 ? u[r - 1] : u_prev;
+        const float left = su[ls * kRP + lc - 1];
+        const float gv = s >= 1 ? uc - above : 0.f;
+        const float gh = t >= 1 ? uc - left : 0.f;
+        const float av = fmaf(step, gv, qv[r]);
+        const float ah = fmaf(step, gh, qh[r]);
+        const float nrm = fmaxf(1.f, sqrtf(av * av + ah * ah));
+        p2v[r] = p1v[r];
+        p2h[r] = p1h[r];
+        p1v[r] = av / nrm;
+        p1h[r] = ah / nrm;
+      }
+    }
+  }
+  if (out_x) {
+    // out = b - theta D^T p_K on the output tile: p_v of the row below, p_h
+    // of the column to the right
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < kRNP; ++r)
+        if (row0 + r < R) sqh[(row0 + r) * kRP + lc] = p1h[r];
+      sqv[strip * kRP + lc] = p1v[0];
+    }
+    __syncthreads();
+    const float pv_next = sqv[(strip + 1) * kRP + lc];
+#pragma unroll
+    for (int r = 0; r < kRNP; ++r) {
+      const int ls = row0 + r, s = s0 + ls;
+      if (!active || ls < h || ls >= h + kFT || col < h || col >= h + kFT || s >= H || t >= W)
+        continue;
+      const float below = r + 1 < kRNP ? p1v[r + 1] : pv_next;
+      const float dn = s + 1 < H ? below : 0.f;
+      const float rt = t + 1 < W ? sqh[ls * kRP + lc + 1] : 0.f;
+      const float dtp = (p1v[r] - dn) + (p1h[r] - rt);
+      out_x[pidx<TILED>(L, 0, s, t) * S + img] = vb[r] - theta * dtp;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kRNP; ++r) {
+      const int ls = row0 + r, s = s0 + ls;
+      if (!active || ls < h || ls >= h + kFT || col < h || col >= h + kFT || s >= H || t >= W)
+        continue;
+      const int64_t i = pidx<TILED>(L, 0, s, t) * S + img;
+      o1v[i] = p1v[r];
+      o1h[i] = p1h[r];
+      o2v[i] = p2v[r];
+      o2h[i] = p2h[r];
+    }
+  }
+}
+
 // out = b - theta D^T p (2-D)
 template <bool TILED>
 __global__ __launch_bounds__(256) void k_fgp_out2(Layout L, const float* __restrict__ b,
@@ -479,8 +658,9 @@ static hipError_t fgp2_per_iteration(const Layout& L, int S, const float* b, flo
 }
 
 // Prox schedule: kFgpFused = up to 20 iterations per launch with recomputed
-// halos, kFgpPerIteration = one launch per iteration.  Both compute the same
-// recurrence.
+// halos, state in registers (k_fgp_reg2); kFgpFusedLds = the same chunks
+// with the state in LDS (k_fgp_fused2); kFgpPerIteration = one launch per
+// iteration.  All compute the same recurrence with the same arithmetic.
 template <bool TILED>
 static hipError_t fgp2_chunks(const Layout& L, int S, const float* b, float theta0,
                               const float* lam, float mu, int iters, const std::vector<float>& c,
@@ -500,7 +680,12 @@ static hipError_t fgp2_chunks(const Layout& L, int S, const float* b, float thet
     float* o1 = buf[2 - in];
     float* o2 = buf[3 - in];
     const bool last = k0 + chunk == iters;
-    k_fgp_fused2<TILED><<<grid, kFThreads, 0, s>>>(L, S, lam, mu, theta0, b, k0, chunk, ca, i1,
+    if (schedule == kFgpFusedLds)
+      k_fgp_fused2<TILED><<<grid, kFThreads, 0, s>>>(L, S, lam, mu, theta0, b, k0, chunk, ca, i1,
+                                                     i1 + m, i2, i2 + m, last ? out : nullptr, o1,
+                                                     o1 + m, o2, o2 + m);
+    else
+      k_fgp_reg2<TILED><<<grid, kRThreads, 0, s>>>(L, S, lam, mu, theta0, b, k0, chunk, ca, i1,
                                                    i1 + m, i2, i2 + m, last ? out : nullptr, o1,
                                                    o1 + m, o2, o2 + m);
     in = 2 - in;

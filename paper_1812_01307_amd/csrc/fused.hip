@@ -198,24 +198,30 @@ __device__ void walk_ray(const TileGeom& g, const int32_t* __restrict__ col, int
   vis.finish(nseen);
 }
 
+// Raise *word to v (one word shared by the whole grid: read first, so that
+// only the few values that raise it take an atomic).
+__device__ __forceinline__ void raise_to(int32_t* word, int32_t v) {
+  if (v > __atomic_load_n(word, __ATOMIC_RELAXED)) atomicMax(word, v);
+}
+
+// Segments per ray, and the grid-wide maxima of segments per ray (maxc) and
+// entries per segment (maxlen).
 struct VisCount {
-  TileGeom g;
   int64_t k;
-  int q;
   int64_t* ncross;
-  int32_t *ucnt, *umax, *ulen, *maxc;
+  int32_t *maxc, *maxlen;
+  int mlen = 0;
   __device__ void entry(int, int, int, int64_t) {}
-  __device__ void close(int G, int f, int len, int rank) {
-    if (rank < 0) return;
-    const int64_t u = ((int64_t)G * g.FTw + f) * g.Q + q;
-    atomicAdd(&ucnt[u], 1);
-    atomicMax(&umax[u], len);
-    atomicAdd(&ulen[u], len);
+  __device__ void close(int, int, int len, int rank) {
+    if (rank >= 0) mlen = max(mlen, len);
   }
   __device__ void finish(int n) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mlen = max(mlen, __shfl_xor(mlen, off));
     if ((threadIdx.x & 63) == 0) {
       ncross[k] = n;
-      atomicMax(maxc, n);
+      raise_to(maxc, n);
+      raise_to(maxlen, mlen);
     }
   }
 };
@@ -284,8 +290,8 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_fz_walk(
     TileGeom g, const int64_t* __restrict__ ptr, const int32_t* __restrict__ seg, int nseg,
     const int32_t* __restrict__ col, const float* __restrict__ vsrc,
-    const __half* __restrict__ v16src, int64_t r_int, int64_t* ncross, int32_t* ucnt,
-    int32_t* umax, int32_t* ulen, int32_t* maxc, const int64_t* poff, uint64_t* key, int32_t* idx,
+    const __half* __restrict__ v16src, int64_t r_int, int64_t* ncross, int32_t* maxc,
+    int32_t* maxlen, const int64_t* poff, uint64_t* key, int32_t* idx,
     int32_t* pray, const int32_t* pos, const int64_t* soff, uint16_t* ocol, float* oval,
     __half* oval16, int* err) {
   const int64_t k = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
@@ -294,7 +300,7 @@ __global__ __launch_bounds__(256) void k_fz_walk(
   const int64_t len = seg[k * (nseg + 1) + nseg];
   const int q = chunk_of(g, k);
   if constexpr (MODE == 0) {
-    VisCount v{g, k, q, ncross, ucnt, umax, ulen, maxc};
+    VisCount v{k, ncross, maxc, maxlen};
     walk_ray(g, col, beg, len, v);
   } else if constexpr (MODE == 1) {
     VisPairs v{g, k, q, poff, key, idx, pray};
@@ -302,6 +308,27 @@ __global__ __launch_bounds__(256) void k_fz_walk(
   } else {
     VisFill v{k, poff, pos, soff, vsrc, v16src, ocol, oval, oval16, err};
     walk_ray(g, col, beg, len, v);
+  }
+}
+
+// First and last sorted position of each unit (keys sorted by unit first);
+// empty units keep first = 0, last = -1.
+__global__ void k_fz_unit_bounds(const uint64_t* __restrict__ keys, int64_t n,
+                                 int64_t* __restrict__ first, int64_t* __restrict__ last) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t u = (uint32_t)(keys[i] >> 32) / kKeyLen;
+    if (i == 0 || (uint32_t)(keys[i - 1] >> 32) / kKeyLen != u) first[u] = i;
+    if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) / kKeyLen != u) last[u] = i;
+  }
+}
+
+__global__ void k_fz_unit_init(int64_t* __restrict__ first, int64_t* __restrict__ last,
+                               int64_t units) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    first[u] = 0;
+    last[u] = -1;
   }
 }
 
@@ -386,7 +413,8 @@ __global__ __launch_bounds__(256) void k_fz_colsum(const int64_t* __restrict__ p
   for (int64_t e = lane; e < len; e += 64) acc += fabs((double)val[beg + e]);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if (lane == 0) atomicMax(out, (unsigned long long)__double_as_longlong(acc));
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(acc);
+  if (lane == 0 && bits > __atomic_load_n(out, __ATOMIC_RELAXED)) atomicMax(out, bits);
 }
 
 __global__ void k_i64_to_i32(const int64_t* __restrict__ in, int32_t* __restrict__ out,
@@ -605,6 +633,21 @@ __global__ __launch_bounds__(64 * W) void k_fused(
   }
 }
 
+// Maximum of v over a 256-thread block into *out: one atomic per block at
+// most, and only while it raises the stored value (every block of a launch
+// reading and updating one word serialises on one L2 channel otherwise).
+__device__ __forceinline__ void block_max_to(unsigned v, unsigned* out) {
+  __shared__ unsigned wmax[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, off));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    v = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+    if (v > __atomic_load_n(out, __ATOMIC_RELAXED)) atomicMax(out, v);
+  }
+}
+
 // Rays: out_r = y - sum of the ray's segment partials zp[rank][ray] in rank
 // order, or the sum when y is NULL; max |out_r| is gathered in *rmax_out (as
 // the bit pattern of a non-negative float, which orders like the value).  Pixels: out_x = xadd + scale * (sum of the Q chunk
@@ -644,15 +687,7 @@ __global__ __launch_bounds__(256) void k_fz_reduce(
       out_x[p] = xadd ? fmaf(scale, a, xadd[p]) : scale * a;
     }
   }
-  if (rmax_out) {
-    unsigned mb = bad ? 0x7fc00000u : __float_as_uint(m);  // NaN orders above +inf
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mb = max(mb, (unsigned)__shfl_xor((int)mb, off));
-    // one atomic per wavefront at most, and only while it raises the maximum
-    // (thousands of atomics on one word serialise)
-    if ((threadIdx.x & 63) == 0 && mb > __atomic_load_n(rmax_out, __ATOMIC_RELAXED))
-      atomicMax(rmax_out, mb);
-  }
+  if (rmax_out) block_max_to(bad ? 0x7fc00000u : __float_as_uint(m), rmax_out);  // NaN > +inf
 }
 
 __global__ void k_fz_zero_u32(unsigned* p) { *p = 0u; }
@@ -668,10 +703,7 @@ __global__ __launch_bounds__(256) void k_fz_absmax(const float* __restrict__ v, 
     m = fmaxf(m, fabsf(o));
     bad = bad || (o != o);
   }
-  unsigned mb = bad ? 0x7fc00000u : __float_as_uint(m);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) mb = max(mb, (unsigned)__shfl_xor((int)mb, off));
-  if ((threadIdx.x & 63) == 0 && mb > __atomic_load_n(out, __ATOMIC_RELAXED)) atomicMax(out, mb);
+  block_max_to(bad ? 0x7fc00000u : __float_as_uint(m), out);
 }
 
 template <typename VT, int W>
@@ -712,7 +744,7 @@ size_t fused_partials(const bsgd_fused* F, FusedPartials* fp, void* ws) {
 
 hipError_t launch_fused_absmax(const float* v, int64_t n, unsigned* out, hipStream_t s) {
   k_fz_zero_u32<<<1, 1, 0, s>>>(out);
-  k_fz_absmax<<<grid_for(n), 256, 0, s>>>(v, n, out);
+  k_fz_absmax<<<std::min<unsigned>(grid_for(n), 1024), 256, 0, s>>>(v, n, out);
   return hipGetLastError();
 }
 
@@ -731,8 +763,9 @@ hipError_t launch_fused_reduce(const bsgd_fused* F, const float* zp, const float
                                const float* xadd, float scale, float* out_x, hipStream_t s) {
   const Layout& L = F->plan->L;
   const int64_t tot = L.r_int + L.c_int;
-  k_fz_reduce<<<grid_for(tot), 256, 0, s>>>(F->poff, zp, y, out_r, rmax_out, L.r_int, gp,
-                                            F->g.Q, xadd, scale, out_x, L.c_int);
+  const unsigned blocks = std::min<unsigned>(grid_for(tot), 1024);
+  k_fz_reduce<<<blocks, 256, 0, s>>>(F->poff, zp, y, out_r, rmax_out, L.r_int, gp, F->g.Q, xadd,
+                                     scale, out_x, L.c_int);
   return hipGetLastError();
 }
 
@@ -740,76 +773,53 @@ hipError_t launch_fused_reduce(const bsgd_fused* F, const float* zp, const float
 // Build
 // ---------------------------------------------------------------------------
 struct FusedCounts {
-  int64_t pairs = 0, slices = 0, bound = 0;
-  int maxrank = 0;
-  std::vector<int64_t> ubeg;   // units + 1
-  std::vector<int32_t> sbeg;   // units + 1
-  std::vector<int32_t> uorder; // units, most slices first (stable)
+  int64_t pairs = 0;
+  int64_t slices = 0;  // upper bound until the build has sorted the segments
+  int64_t bound = 0;   // upper bound of the stored entries
+  int maxrank = 0, maxlen = 0;
 };
 
-// Count pass: segments per ray (into plan->scratch64, then scanned in place)
-// and per unit count / longest / total length (into the plan's scratch
-// vectors).  Synchronises.
+// Count pass: segments per ray (into plan->scratch64, then scanned in place:
+// the rays' segment offsets), most segments of a ray and longest segment.
+// Bounds for the workspace: a unit with n segments has ceil(n / 64) slices,
+// so there are at most pairs / 64 + units; slices are sorted longest first,
+// so slice k >= 1 of a unit is no longer than the shortest segment of the
+// full slice k - 1 and stores at most that slice's entries, plus up to 3
+// padding entries per lane (groups of 4) -- entries <= nnz + units *
+// 64 * (maxlen + 3) + 192 * slices.  Synchronises.
 static bsgd_status fused_count(const bsgd_plan* p, const TileGeom& g, hipStream_t s,
                                FusedCounts& fc) {
   const Layout& L = p->L;
   const int64_t units = g.units();
-  int32_t* ucnt = reinterpret_cast<int32_t*>(p->vin);
-  int32_t* umax = reinterpret_cast<int32_t*>(p->vaux);
-  int32_t* ulen = reinterpret_cast<int32_t*>(p->vout);
-  k_fill_i32<<<grid_for(units + 1), 256, 0, s>>>(ucnt, units + 1);  // ucnt[units]: max per ray
-  k_fill_i32<<<grid_for(units), 256, 0, s>>>(umax, units);
-  k_fill_i32<<<grid_for(units), 256, 0, s>>>(ulen, units);
+  int32_t* words = reinterpret_cast<int32_t*>(p->vin);  // [0] maxc, [1] maxlen
+  k_fill_i32<<<1, 256, 0, s>>>(words, 2);
   BSGD_LAUNCH_CHECK();
   const unsigned blocks = (unsigned)((L.r_int * 64 + 255) / 256);
   k_fz_walk<0><<<blocks, 256, 0, s>>>(g, p->fwd.ptr, p->fwd.seg, p->fwd.nseg, p->fwd.col,
-                                      nullptr, nullptr, L.r_int, p->scratch64, ucnt, umax, ulen,
-                                      ucnt + units, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                      nullptr,
+                                      nullptr, nullptr, L.r_int, p->scratch64, words, words + 1,
+                                      nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                       nullptr, nullptr, nullptr, nullptr);
   BSGD_LAUNCH_CHECK();
   BSGD_HIP(exclusive_scan_i64(p->scratch64, p->scratch64, L.r_int, p->scan_tmp, s));
-  std::vector<int32_t> hc(units + 1), hm(units), hl(units);
+  int32_t hw[2] = {0, 0};
   BSGD_HIP(hipMemcpyAsync(&fc.pairs, p->scratch64 + L.r_int, sizeof(int64_t),
                           hipMemcpyDeviceToHost, s));
-  BSGD_HIP(hipMemcpyAsync(hc.data(), ucnt, sizeof(int32_t) * (units + 1), hipMemcpyDeviceToHost,
-                          s));
-  BSGD_HIP(hipMemcpyAsync(hm.data(), umax, sizeof(int32_t) * units, hipMemcpyDeviceToHost, s));
-  BSGD_HIP(hipMemcpyAsync(hl.data(), ulen, sizeof(int32_t) * units, hipMemcpyDeviceToHost, s));
+  BSGD_HIP(hipMemcpyAsync(hw, words, sizeof(hw), hipMemcpyDeviceToHost, s));
   BSGD_HIP(hipStreamSynchronize(s));
-  fc.ubeg.assign(units + 1, 0);
-  fc.sbeg.assign(units + 1, 0);
-  int64_t sl = 0, bound = 0;
-  for (int64_t u = 0; u < units; ++u) {
-    const int64_t nsl = (hc[u] + 63) / 64;
-    fc.ubeg[u + 1] = fc.ubeg[u] + hc[u];
-    fc.sbeg[u] = (int32_t)sl;
-    sl += nsl;
-    // slices sorted longest first: slice k >= 1 is at most as long as the
-    // shortest segment of slice k - 1, so its 64 lanes hold no more than that
-    // slice's entries; groups of 4 add at most 3 entries per lane
-    if (nsl > 0) bound += 64 * ((int64_t)hm[u] + 3) + hl[u] + 192 * nsl;
-  }
-  fc.sbeg[units] = (int32_t)sl;
-  fc.uorder.resize(units);
-  for (int64_t u = 0; u < units; ++u) fc.uorder[u] = (int32_t)u;
-  std::stable_sort(fc.uorder.begin(), fc.uorder.end(), [&](int32_t a, int32_t b) {
-    return fc.sbeg[a + 1] - fc.sbeg[a] > fc.sbeg[b + 1] - fc.sbeg[b];
-  });
-  fc.maxrank = hc[units];
+  fc.maxrank = hw[0];
+  fc.maxlen = hw[1];
   BSGD_REQUIRE(fc.maxrank < 65536, "a ray crosses %d tiles (at most 65535)", fc.maxrank);
-  fc.slices = sl;
-  fc.bound = bound;
-  BSGD_REQUIRE(sl * 64 < ((int64_t)1 << 31), "too many slices (%lld)", (long long)sl);
-  BSGD_REQUIRE(fc.ubeg[units] == fc.pairs, "segment counts disagree (%lld vs %lld)",
-               (long long)fc.ubeg[units], (long long)fc.pairs);
+  fc.slices = (fc.pairs + 63) / 64 + units;
+  fc.bound = p->fwd.nnz + units * 64 * ((int64_t)fc.maxlen + 3) + 192 * fc.slices;
+  BSGD_REQUIRE(fc.slices * 64 < ((int64_t)1 << 31), "too many slices (%lld)",
+               (long long)fc.slices);
   return BSGD_OK;
 }
 
 struct FusedTemps {
   uint64_t *key = nullptr, *key2 = nullptr;
   int32_t *idx = nullptr, *idx2 = nullptr, *pray = nullptr, *slen = nullptr, *pos = nullptr;
-  int64_t *ubeg = nullptr, *sng256 = nullptr, *scan_tmp = nullptr;
+  int64_t *first = nullptr, *last = nullptr, *sng256 = nullptr, *scan_tmp = nullptr;
   int* err = nullptr;
   unsigned long long* smax = nullptr;
   void* cub = nullptr;
@@ -854,7 +864,8 @@ static size_t fused_layout(const bsgd_plan* p, const TileGeom& g, const FusedCou
   T->idx2 = cv.take<int32_t>(np);
   T->pray = cv.take<int32_t>(np);
   T->slen = cv.take<int32_t>(nslots);
-  T->ubeg = cv.take<int64_t>(units + 1);
+  T->first = cv.take<int64_t>(units);
+  T->last = cv.take<int64_t>(units);
   T->sng256 = cv.take<int64_t>(fc.slices + 1);
   T->scan_tmp = cv.take<int64_t>(scan_tmp_count(fc.slices) + 1);
   T->err = cv.take<int>(64);
@@ -931,7 +942,6 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, void
   const Layout& L = plan->L;
   const Store& A = plan->fwd;
   const int64_t units = g.units();
-  const int64_t nslots = fc.slices * 64;
   const unsigned wblocks = (unsigned)((L.r_int * 64 + 255) / 256);
   auto fail = [&](bsgd_status s) {
     delete F;
@@ -943,17 +953,9 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, void
     return BSGD_ERR_HIP;
   };
   hipError_t e;
-  e = hipMemcpyAsync(F->sbeg, fc.sbeg.data(), sizeof(int32_t) * (units + 1),
-                     hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(F->uorder, fc.uorder.data(), sizeof(int32_t) * units,
-                       hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(T.ubeg, fc.ubeg.data(), sizeof(int64_t) * (units + 1),
-                       hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipMemsetAsync(T.err, 0, sizeof(int), stream);
+  e = hipMemsetAsync(T.err, 0, sizeof(int), stream);
   if (e == hipSuccess) e = hipMemsetAsync(T.smax, 0, sizeof(unsigned long long), stream);
-  if (e != hipSuccess) return hip_fail(e, "single-pass build upload");
+  if (e != hipSuccess) return hip_fail(e, "single-pass build set-up");
   {
     const Store& B = plan->bwd;
     k_fz_colsum<<<(unsigned)((B.nrows * 64 + 255) / 256), 256, 0, stream>>>(
@@ -961,20 +963,59 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, void
   }
   // per-ray segment offsets (plan->scratch64 holds their exclusive scan)
   k_i64_to_i32<<<grid_for(L.r_int + 1), 256, 0, stream>>>(plan->scratch64, F->poff, L.r_int + 1);
+  k_fz_unit_init<<<grid_for(units), 256, 0, stream>>>(T.first, T.last, units);
   if (fc.pairs > 0) {
     k_fz_walk<1><<<wblocks, 256, 0, stream>>>(
         g, A.ptr, A.seg, A.nseg, A.col, nullptr, nullptr, L.r_int, nullptr, nullptr, nullptr,
-        nullptr, nullptr, plan->scratch64, T.key, T.idx, T.pray, nullptr, nullptr, nullptr,
-        nullptr, nullptr, nullptr);
+        plan->scratch64, T.key, T.idx, T.pray, nullptr, nullptr, nullptr, nullptr, nullptr,
+        nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "segment pass");
     size_t cb = T.cub_bytes;
     e = hipcub::DeviceRadixSort::SortPairs(T.cub, cb, T.key, T.key2, T.idx, T.idx2, (int)fc.pairs,
                                            0, 32 + key_bits(units), stream);
     if (e != hipSuccess) return hip_fail(e, "segment sort");
+    k_fz_unit_bounds<<<grid_for(fc.pairs), 256, 0, stream>>>(T.key2, fc.pairs, T.first, T.last);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "unit bounds");
+  }
+  // slices per unit, launch order (most slices first) and slice offsets on the host
+  std::vector<int64_t> hf(units), hl(units);
+  e = hipMemcpyAsync(hf.data(), T.first, sizeof(int64_t) * units, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hl.data(), T.last, sizeof(int64_t) * units, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "unit bounds");
+  std::vector<int32_t> sbeg(units + 1, 0), uorder(units);
+  int64_t nsl = 0, npl = 0;
+  for (int64_t u = 0; u < units; ++u) {
+    const int64_t n = hl[u] - hf[u] + 1;
+    sbeg[u] = (int32_t)nsl;
+    nsl += (n + 63) / 64;
+    npl += n;
+    uorder[u] = (int32_t)u;
+  }
+  sbeg[units] = (int32_t)nsl;
+  if (npl != fc.pairs || nsl > fc.slices) {
+    set_error("single-pass build: %lld sorted segments in %lld slices (expected %lld, <= %lld)",
+              (long long)npl, (long long)nsl, (long long)fc.pairs, (long long)fc.slices);
+    return fail(BSGD_ERR_INVALID);
+  }
+  std::stable_sort(uorder.begin(), uorder.end(), [&](int32_t a, int32_t b) {
+    return sbeg[a + 1] - sbeg[a] > sbeg[b + 1] - sbeg[b];
+  });
+  fc.slices = nsl;
+  const int64_t nslots = nsl * 64;
+  e = hipMemcpyAsync(F->sbeg, sbeg.data(), sizeof(int32_t) * (units + 1), hipMemcpyHostToDevice,
+                     stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(F->uorder, uorder.data(), sizeof(int32_t) * units, hipMemcpyHostToDevice,
+                       stream);
+  if (e != hipSuccess) return hip_fail(e, "single-pass build upload");
+  if (fc.pairs > 0) {
     k_fz_init_slots<<<grid_for(nslots), 256, 0, stream>>>(F->sray, T.slen, nslots);
     k_fz_place<<<grid_for(fc.pairs), 256, 0, stream>>>(T.key2, T.idx2, T.pray, plan->scratch64,
-                                                       fc.pairs, T.ubeg, F->sbeg, nslots, T.pos,
+                                                       fc.pairs, T.first, F->sbeg, nslots, T.pos,
                                                        F->sray, F->srank, T.slen, F->sng,
                                                        T.sng256, T.err);
     e = hipGetLastError();
@@ -1004,9 +1045,8 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, void
   if (fc.pairs > 0) {
     k_fz_walk<2><<<wblocks, 256, 0, stream>>>(
         g, A.ptr, A.seg, A.nseg, A.col, A.val, A.val16, L.r_int, nullptr, nullptr, nullptr,
-        nullptr, nullptr, plan->scratch64, nullptr, nullptr, nullptr, T.pos, F->soff, F->col,
-        F->val,
-        F->val16, T.err);
+        plan->scratch64, nullptr, nullptr, nullptr, T.pos, F->soff, F->col, F->val, F->val16,
+        T.err);
     k_fz_pad<<<grid_for(nslots), 256, 0, stream>>>(T.slen, F->sng, F->soff, nslots, F->col,
                                                    F->val, F->val16);
     e = hipGetLastError();
@@ -1024,8 +1064,8 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, void
   {
     double sm;
     std::memcpy(&sm, &smax_bits, sizeof(sm));
-    // FP16 values round |a| up by at most 2^-11 relative; the scale keeps a
-    // factor-2 margin below 2^62 anyway
+    // FP16 values round |a| up by at most 2^-11 relative: sums stay below
+    // 2^46 * (1 + 2^-11), inside the 2^47 that the 48-bit window allows
     F->smax = sm;
   }
   F->slices = fc.slices;

@@ -274,17 +274,20 @@ def main(argv=None):
                 b_bwd = b
     fused_info = None
     if F is not None:
-        tiles, chunks, segs, slices, entries = bsgd.bsgd_fused_shape(F)
-        # matrix read once (16-bit columns, values; padding excluded), per-slot
-        # ray and rank, per-slice count and offset, x tile and r gathers once,
-        # per-segment partials and per-chunk partials of A^T r written
-        b_pass = (val_bytes + 2) * nnz + 6 * 64 * slices + 12 * slices + 4 * c + 4 * r \
+        tiles, chunks, segs, slices, entries, cbytes = bsgd.bsgd_fused_shape(F)
+        # matrix read once (columns, values; padding excluded), per-slot ray,
+        # rank (and start address with 1-byte columns), per-slice count and
+        # offset, x tile and r gathers once, per-segment partials and per-chunk
+        # partials of A^T r written
+        slot = 6 + (2 if cbytes == 1 else 0)
+        b_pass = (val_bytes + cbytes) * nnz + slot * 64 * slices + 12 * slices + 4 * c + 4 * r \
             + 4 * segs + 4 * chunks * c
         # reduce: partials read, segment offsets, y, r' written, x read, x^ written
         b_red = 4 * segs + 4 * (r + 1) + 8 * r + 4 * chunks * c + 8 * c
         b_fwd, b_bwd = b_pass, b_red
         fused_info = {"tiles": tiles, "chunks": chunks, "segments": segs, "slices": slices,
                       "stored_entries": entries, "padding": round(entries / nnz - 1, 4),
+                      "column_bytes": cbytes,
                       "waves": args.fused_waves, "alg_bytes_pass": b_pass,
                       "alg_bytes_reduce": b_red}
     roofline = None

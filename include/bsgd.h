@@ -427,25 +427,32 @@ void bsgd_graph_destroy(bsgd_graph* graph);
  * tiles, rays in `chunks` chunks of whole ray groups (8 interleaved views when
  * the plan has view_len > 0); the part of one ray inside one tile (a
  * segment) is one lane's list of (16-bit tile-local column, value) entries.
- * One workgroup per (tile, chunk) keeps the tile of x and per-wavefront
- * copies of the tile of g in LDS; per-segment sums of A x and per-chunk sums
- * of A^T r are added in a fixed order by a second kernel, so results are
- * bitwise reproducible for a given store (and differ from the row kernels
- * by summation order only).  FP16 values are available when the plan has
- * BSGD_PLAN_F16.  Images wider than 2048 pixels are not supported
- * (BSGD_ERR_UNSUPPORTED).
+ * Columns are 8-bit steps between a segment's successive tile-local pixel
+ * addresses (with a 16-bit start per segment) when every step is below 256,
+ * which holds for rays (5 bytes per entry with FP32 values, 3 with FP16),
+ * else 16-bit addresses (flag BSGD_FUSED_WIDE forces them).  One workgroup
+ * per (tile, chunk) keeps the tile of x in LDS for the row sums of A x and
+ * adds the terms of A^T r into the tile in LDS as 64-bit fixed-point numbers
+ * (integer additions, exact in any order; the scale is set from max |r| so
+ * that a term's rounding is below 2^-46 of the largest possible sum);
+ * per-segment sums of A x and per-chunk sums of A^T r are added in a fixed
+ * order by a second kernel, so results are bitwise reproducible for a given
+ * store (and differ from the row kernels by summation order only).  FP16
+ * values are available when the plan has BSGD_PLAN_F16.  Images wider than
+ * 2048 pixels are not supported (BSGD_ERR_UNSUPPORTED).
  *
  *   fused_workspace_size  counts the segments of `plan` (device pass over the
  *               forward store, uses the plan's scratch vectors: no other call
  *               on the plan may overlap it) and returns the workspace bytes
- *               for bsgd_fused_create with the same chunks.  chunks = 0
+ *               for bsgd_fused_create with the same chunks and flags.  chunks = 0
  *               picks about 2048 (tile, chunk) units; chunks <= number of ray
  *               groups.  Synchronises `stream`.
  *   fused_create  builds the store in `workspace` (device, 256-byte aligned,
  *               at least the size returned above) from the plan's forward
  *               store; the plan must outlive it.  Synchronises.
- *   fused_shape   tiles, chunks, segments, slices (64 segments each) and
- *               stored entries (with padding).
+ *   fused_shape   tiles, chunks, segments, slices (64 segments each),
+ *               stored entries (with padding) and bytes per stored column (1:
+ *               8-bit steps, 2: 16-bit addresses).
  *   fused_set_waves  wavefronts per (tile, chunk) workgroup: 2, 4 (default)
  *               or 8; results change by summation order only.
  *   fused_partials_size  bytes of the partial-sum buffer (device) that every
@@ -464,13 +471,14 @@ void bsgd_graph_destroy(bsgd_graph* graph);
  *               fused == NULL detaches (the row kernels again).  The state's
  *               value type must be available in the store.
  */
-bsgd_status bsgd_fused_workspace_size(const bsgd_plan* plan, int chunks, hipStream_t stream,
-                                      size_t* bytes);
-bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, void* workspace,
+#define BSGD_FUSED_WIDE 1u /* 16-bit column addresses even where 8-bit steps would do */
+bsgd_status bsgd_fused_workspace_size(const bsgd_plan* plan, int chunks, unsigned flags,
+                                      hipStream_t stream, size_t* bytes);
+bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, unsigned flags, void* workspace,
                               size_t workspace_bytes, hipStream_t stream, bsgd_fused** out);
 void bsgd_fused_destroy(bsgd_fused* fused);
 bsgd_status bsgd_fused_shape(const bsgd_fused* fused, int* tiles, int* chunks, int64_t* segments,
-                             int64_t* slices, int64_t* entries);
+                             int64_t* slices, int64_t* entries, int* col_bytes);
 bsgd_status bsgd_fused_set_waves(bsgd_fused* fused, int waves);
 bsgd_status bsgd_fused_partials_size(const bsgd_fused* fused, size_t* bytes);
 bsgd_status bsgd_fused_apply(const bsgd_fused* fused, bsgd_valtype vt, const float* x,

@@ -33,6 +33,7 @@ BSGD_PLAN_STAGED_BWD = 8
 BSGD_PLAN_STAGED = 12
 BSGD_LAUNCH_NT = 128
 BSGD_STATE_VOLUME = 1
+BSGD_FUSED_WIDE = 1
 
 _STATUS = {0: "OK", -1: "INVALID", -2: "WORKSPACE", -3: "HIP", -4: "UNSUPPORTED", -5: "DIVERGED"}
 
@@ -96,10 +97,10 @@ _PROTOS = {
     "bsgd_state_set_overlap": [_vp, _i32],
     "bsgd_state_set_prox_schedule": [_vp, _i32],
     "bsgd_state_timing": [_vp] + [ctypes.POINTER(ctypes.c_double)] * 3 + [ctypes.POINTER(_i64)],
-    "bsgd_fused_workspace_size": [_vp, _i32, _vp, ctypes.POINTER(_sz)],
-    "bsgd_fused_create": [_vp, _i32, _vp, _sz, _vp, ctypes.POINTER(_vp)],
+    "bsgd_fused_workspace_size": [_vp, _i32, ctypes.c_uint, _vp, ctypes.POINTER(_sz)],
+    "bsgd_fused_create": [_vp, _i32, ctypes.c_uint, _vp, _sz, _vp, ctypes.POINTER(_vp)],
     "bsgd_fused_shape": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i64),
-                         ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+                         ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i32)],
     "bsgd_fused_set_waves": [_vp, _i32],
     "bsgd_fused_partials_size": [_vp, ctypes.POINTER(_sz)],
     "bsgd_fused_apply": [_vp, _i32, _vp, _vp, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp],
@@ -570,30 +571,31 @@ class Fused:
             self.handle = None
 
 
-def bsgd_fused_workspace_size(plan: Plan, chunks=0, stream=None) -> int:
+def bsgd_fused_workspace_size(plan: Plan, chunks=0, flags=0, stream=None) -> int:
     out = _sz()
     _check("bsgd_fused_workspace_size", _lib.bsgd_fused_workspace_size(
-        plan.handle, int(chunks), _stream(stream), ctypes.byref(out)))
+        plan.handle, int(chunks), int(flags), _stream(stream), ctypes.byref(out)))
     return out.value
 
 
-def bsgd_fused_create(plan: Plan, chunks=0, stream=None) -> Fused:
-    nbytes = bsgd_fused_workspace_size(plan, chunks, stream)
+def bsgd_fused_create(plan: Plan, chunks=0, flags=0, stream=None) -> Fused:
+    nbytes = bsgd_fused_workspace_size(plan, chunks, flags, stream)
     ws = _ws(nbytes, plan.workspace.device)
     h = _vp()
-    _check("bsgd_fused_create", _lib.bsgd_fused_create(plan.handle, int(chunks), _ptr(ws), nbytes,
-                                                       _stream(stream), ctypes.byref(h)))
+    _check("bsgd_fused_create", _lib.bsgd_fused_create(plan.handle, int(chunks), int(flags),
+                                                       _ptr(ws), nbytes, _stream(stream),
+                                                       ctypes.byref(h)))
     return Fused(h, ws, plan)
 
 
 def bsgd_fused_shape(fused: Fused):
-    """(tiles, chunks, segments, slices, stored entries)."""
-    t, q = _i32(), _i32()
+    """(tiles, chunks, segments, slices, stored entries, bytes per stored column)."""
+    t, q, cb = _i32(), _i32(), _i32()
     g, sl, e = _i64(), _i64(), _i64()
     _check("bsgd_fused_shape", _lib.bsgd_fused_shape(fused.handle, ctypes.byref(t), ctypes.byref(q),
                                                      ctypes.byref(g), ctypes.byref(sl),
-                                                     ctypes.byref(e)))
-    return t.value, q.value, g.value, sl.value, e.value
+                                                     ctypes.byref(e), ctypes.byref(cb)))
+    return t.value, q.value, g.value, sl.value, e.value, cb.value
 
 
 def bsgd_fused_set_waves(fused: Fused, waves: int):

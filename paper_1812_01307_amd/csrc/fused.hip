@@ -18,9 +18,14 @@
 // stores its entries
 // lane-interleaved in groups of 4:
 //     entry j of lane l at soff[s] + (j / 4) * 256 + l * 4 + j % 4
-// as a 16-bit column (the pixel's address in the tile's LDS image, row
-// stride 33) and an FP32 value (optional FP16 copy).  Lanes shorter than the
-// slice's longest are padded with zero values on a column they already use.
+// as a column and an FP32 value (optional FP16 copy).  The column is the
+// pixel's address in the tile's LDS image (row stride 33); entries of a
+// segment are in ascending address order, and when every step from one
+// entry to the next is below 256 (always for rays: at most 65) the store
+// keeps 8-bit steps with a 16-bit start address per lane (5 bytes per entry
+// with FP32 values, 3 with FP16), else 16-bit addresses.  Lanes shorter than
+// the slice's longest are padded with zero values on an address they
+// already use (a zero step).
 //
 // Pass.  One workgroup per unit copies the tile of x_k to LDS.  Each of its W
 // wavefronts takes every W-th slice of the unit, gathers x from LDS for the
@@ -44,6 +49,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "bsgd_internal.h"
@@ -89,7 +95,10 @@ struct bsgd_fused {
   int32_t* sray = nullptr;   // slices * 64: internal ray of each lane (-1: none)
   int32_t* poff = nullptr;   // r_int + 1: first segment of each ray
   uint16_t* srank = nullptr; // slices * 64: the lane's segment's rank within its ray
-  uint16_t* col = nullptr;   // cap
+  bool narrow = true;        // 8-bit address steps (col8, sbase) or 16-bit addresses (col)
+  uint8_t* col8 = nullptr;   // cap
+  uint16_t* sbase = nullptr; // slices * 64: first address of each lane (narrow)
+  uint16_t* col = nullptr;   // cap (wide)
   float* val = nullptr;      // cap
   __half* val16 = nullptr;   // cap (plans with BSGD_PLAN_F16)
   // internal-order operands of bsgd_fused_apply
@@ -149,16 +158,19 @@ __device__ __forceinline__ void decode_pixel(const TileGeom& g, int64_t cp, int&
 // pixel order, so the band key G never decreases along the row).  Lane f
 // keeps, for the current band, the rank and running length of the segment
 // in tile column f.  Segments are ranked in the order the ray enters them.
-//   vis.entry(rank, j, lds_addr, e)    entry e is the j-th of segment `rank`
-//   vis.close(G, f, len, rank)         called by every lane f when band G ends
-//                                      (rank < 0: no segment in column f)
+//   vis.entry(rank, j, lds_addr, e, prev)  entry e is the j-th of segment
+//                                      `rank`; prev = the segment's previous
+//                                      address (-1 for j = 0)
+//   vis.close(G, f, len, rank, first)  called by every lane f when band G ends
+//                                      (rank < 0: no segment in column f;
+//                                      first = the segment's first address)
 //   vis.finish(nseg)
 template <class V>
 __device__ void walk_ray(const TileGeom& g, const int32_t* __restrict__ col, int64_t beg,
                          int64_t len, V& vis) {
   const int lane = threadIdx.x & 63;
   const uint64_t below = (1ull << lane) - 1ull;
-  int Gcur = -1, cnt = 0, rank = -1, nseen = 0;
+  int Gcur = -1, cnt = 0, rank = -1, nseen = 0, first = 0, last = 0;
   for (int64_t c0 = 0; c0 < len; c0 += 64) {
     const int64_t e = c0 + lane;
     const bool valid = e < len;
@@ -170,7 +182,7 @@ __device__ void walk_ray(const TileGeom& g, const int32_t* __restrict__ col, int
       const int leader = __builtin_ctzll(live);
       const int Gl = __shfl(G, leader);
       if (Gl != Gcur) {
-        if (Gcur >= 0) vis.close(Gcur, lane, cnt, rank);
+        if (Gcur >= 0) vis.close(Gcur, lane, cnt, rank, first);
         cnt = 0;
         rank = -1;
         Gcur = Gl;
@@ -183,18 +195,29 @@ __device__ void walk_ray(const TileGeom& g, const int32_t* __restrict__ col, int
         const uint64_t mm = __ballot(inG && f == fl);
         int rk = __shfl(rank, fl);
         const int base = __shfl(cnt, fl);
+        const int lastf = __shfl(last, fl);
+        // previous entry of the segment: the batch lane before this one, or
+        // the segment's last entry from an earlier batch
+        const uint64_t pm = mm & below;
+        const int plane = pm ? 63 - __builtin_clzll(pm) : lane;
+        const int pa = __shfl(a, plane);
+        const int prev = pm ? pa : (base > 0 ? lastf : -1);
+        const int alast = __shfl(a, 63 - __builtin_clzll(mm));
+        const int afirst = __shfl(a, l2);
         if (rk < 0) rk = nseen++;
         if (lane == fl) {
+          if (base == 0) first = afirst;
           rank = rk;
           cnt = base + __popcll(mm);
+          last = alast;
         }
-        if (inG && f == fl) vis.entry(rk, base + __popcll(mm & below), a, beg + e);
+        if (inG && f == fl) vis.entry(rk, base + __popcll(mm & below), a, beg + e, prev);
         todo &= ~mm;
       }
       done = done || inG;
     }
   }
-  if (Gcur >= 0) vis.close(Gcur, lane, cnt, rank);
+  if (Gcur >= 0) vis.close(Gcur, lane, cnt, rank, first);
   vis.finish(nseen);
 }
 
@@ -204,24 +227,30 @@ __device__ __forceinline__ void raise_to(int32_t* word, int32_t v) {
   if (v > __atomic_load_n(word, __ATOMIC_RELAXED)) atomicMax(word, v);
 }
 
-// Segments per ray, and the grid-wide maxima of segments per ray (maxc) and
-// entries per segment (maxlen).
+// Segments per ray, and the grid-wide maxima of segments per ray (maxc),
+// entries per segment (maxlen) and address step inside a segment (maxstep).
 struct VisCount {
   int64_t k;
   int64_t* ncross;
-  int32_t *maxc, *maxlen;
-  int mlen = 0;
-  __device__ void entry(int, int, int, int64_t) {}
-  __device__ void close(int, int, int len, int rank) {
+  int32_t *maxc, *maxlen, *maxstep;
+  int mlen = 0, mstep = 0;
+  __device__ void entry(int, int, int a, int64_t, int prev) {
+    if (prev >= 0) mstep = max(mstep, a - prev);
+  }
+  __device__ void close(int, int, int len, int rank, int) {
     if (rank >= 0) mlen = max(mlen, len);
   }
   __device__ void finish(int n) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mlen = max(mlen, __shfl_xor(mlen, off));
+    for (int off = 32; off > 0; off >>= 1) {
+      mlen = max(mlen, __shfl_xor(mlen, off));
+      mstep = max(mstep, __shfl_xor(mstep, off));
+    }
     if ((threadIdx.x & 63) == 0) {
       ncross[k] = n;
       raise_to(maxc, n);
       raise_to(maxlen, mlen);
+      raise_to(maxstep, mstep);
     }
   }
 };
@@ -245,14 +274,16 @@ struct VisPairs {
   uint64_t* key;
   int32_t* idx;
   int32_t* pray;
-  __device__ void entry(int, int, int, int64_t) {}
-  __device__ void close(int G, int f, int len, int rank) {
+  uint16_t* pbase;
+  __device__ void entry(int, int, int, int64_t, int) {}
+  __device__ void close(int G, int f, int len, int rank, int first) {
     if (rank < 0) return;
     const int64_t p = poff[k] + rank;
     const int64_t u = ((int64_t)G * g.FTw + f) * g.Q + q;
     key[p] = ((uint64_t)(u * kKeyLen + (kKeyLen - 1 - len)) << 32) | tie_of(g, k);
     idx[p] = (int32_t)p;
     pray[p] = (int32_t)k;
+    pbase[p] = (uint16_t)first;
   }
   __device__ void finish(int) {}
 };
@@ -265,10 +296,11 @@ struct VisFill {
   const float* vsrc;
   const __half* v16src;
   uint16_t* col;
+  uint8_t* col8;
   float* val;
   __half* val16;
   int* err;
-  __device__ void entry(int rk, int j, int a, int64_t e) {
+  __device__ void entry(int rk, int j, int a, int64_t e, int prev) {
     const int32_t P = pos[poff[k] + rk];
     const int64_t s = P >> 6;
     const int l = P & 63;
@@ -277,11 +309,14 @@ struct VisFill {
       atomicOr(err, 1);
       return;
     }
-    col[addr] = (uint16_t)a;
+    if (col8)
+      col8[addr] = (uint8_t)(j == 0 ? 0 : a - prev);
+    else
+      col[addr] = (uint16_t)a;
     val[addr] = vsrc[e];
     if (val16) val16[addr] = v16src ? v16src[e] : __float2half_rn(vsrc[e]);
   }
-  __device__ void close(int, int, int, int) {}
+  __device__ void close(int, int, int, int, int) {}
   __device__ void finish(int) {}
 };
 
@@ -291,22 +326,22 @@ __global__ __launch_bounds__(256) void k_fz_walk(
     TileGeom g, const int64_t* __restrict__ ptr, const int32_t* __restrict__ seg, int nseg,
     const int32_t* __restrict__ col, const float* __restrict__ vsrc,
     const __half* __restrict__ v16src, int64_t r_int, int64_t* ncross, int32_t* maxc,
-    int32_t* maxlen, const int64_t* poff, uint64_t* key, int32_t* idx,
-    int32_t* pray, const int32_t* pos, const int64_t* soff, uint16_t* ocol, float* oval,
-    __half* oval16, int* err) {
+    int32_t* maxlen, int32_t* maxstep, const int64_t* poff, uint64_t* key, int32_t* idx,
+    int32_t* pray, uint16_t* pbase, const int32_t* pos, const int64_t* soff, uint16_t* ocol,
+    uint8_t* ocol8, float* oval, __half* oval16, int* err) {
   const int64_t k = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
   if (k >= r_int) return;  // uniform per wavefront
   const int64_t beg = ptr[k];
   const int64_t len = seg[k * (nseg + 1) + nseg];
   const int q = chunk_of(g, k);
   if constexpr (MODE == 0) {
-    VisCount v{k, ncross, maxc, maxlen};
+    VisCount v{k, ncross, maxc, maxlen, maxstep};
     walk_ray(g, col, beg, len, v);
   } else if constexpr (MODE == 1) {
-    VisPairs v{g, k, q, poff, key, idx, pray};
+    VisPairs v{g, k, q, poff, key, idx, pray, pbase};
     walk_ray(g, col, beg, len, v);
   } else {
-    VisFill v{k, poff, pos, soff, vsrc, v16src, ocol, oval, oval16, err};
+    VisFill v{k, poff, pos, soff, vsrc, v16src, ocol, ocol8, oval, oval16, err};
     walk_ray(g, col, beg, len, v);
   }
 }
@@ -337,8 +372,9 @@ __global__ void k_fz_place(const uint64_t* __restrict__ keys, const int32_t* __r
                            const int32_t* __restrict__ pray, const int64_t* __restrict__ poff,
                            int64_t npairs, const int64_t* __restrict__ ubeg,
                            const int32_t* __restrict__ sbeg, int64_t nslots,
-                           int32_t* __restrict__ pos, int32_t* __restrict__ sray,
-                           uint16_t* __restrict__ srank, int32_t* __restrict__ slen,
+                           const uint16_t* __restrict__ pbase, int32_t* __restrict__ pos,
+                           int32_t* __restrict__ sray, uint16_t* __restrict__ srank,
+                           uint16_t* __restrict__ sbase, int32_t* __restrict__ slen,
                            int32_t* __restrict__ sng, int64_t* __restrict__ sng256,
                            int* __restrict__ err) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npairs;
@@ -358,6 +394,7 @@ __global__ void k_fz_place(const uint64_t* __restrict__ keys, const int32_t* __r
     pos[p] = (int32_t)P;
     sray[P] = pray[p];
     srank[P] = (uint16_t)(p - poff[pray[p]]);
+    if (sbase) sbase[P] = pbase[p];
     slen[P] = len;
     if (l == 0) {
       sng[s] = (len + 3) / 4;
@@ -367,11 +404,12 @@ __global__ void k_fz_place(const uint64_t* __restrict__ keys, const int32_t* __r
 }
 
 __global__ void k_fz_init_slots(int32_t* __restrict__ sray, int32_t* __restrict__ slen,
-                                int64_t nslots) {
+                                uint16_t* __restrict__ sbase, int64_t nslots) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
        i += (int64_t)gridDim.x * blockDim.x) {
     sray[i] = -1;
     slen[i] = 0;
+    if (sbase) sbase[i] = (uint16_t)(i & 63);  // empty lanes: distinct addresses
   }
 }
 
@@ -380,19 +418,23 @@ __global__ void k_fz_init_slots(int32_t* __restrict__ sray, int32_t* __restrict_
 // lane number, so padded lanes do not meet on one LDS address).
 __global__ void k_fz_pad(const int32_t* __restrict__ slen, const int32_t* __restrict__ sng,
                          const int64_t* __restrict__ soff, int64_t nslots,
-                         uint16_t* __restrict__ col, float* __restrict__ val,
-                         __half* __restrict__ val16) {
+                         uint16_t* __restrict__ col, uint8_t* __restrict__ col8,
+                         float* __restrict__ val, __half* __restrict__ val16) {
   for (int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; P < nslots;
        P += (int64_t)gridDim.x * blockDim.x) {
     const int64_t s = P >> 6;
     const int l = (int)(P & 63);
     const int len = slen[P], ng = sng[s];
     const int64_t base = soff[s] + l * 4;
-    const uint16_t c =
-        len > 0 ? col[base + (int64_t)((len - 1) >> 2) * 256 + ((len - 1) & 3)] : (uint16_t)l;
+    const uint16_t c = col8 || len == 0
+                           ? (uint16_t)l
+                           : col[base + (int64_t)((len - 1) >> 2) * 256 + ((len - 1) & 3)];
     for (int j = len; j < 4 * ng; ++j) {
       const int64_t a = base + (int64_t)(j >> 2) * 256 + (j & 3);
-      col[a] = c;
+      if (col8)
+        col8[a] = 0;  // a zero step: the lane's last address (its start when empty)
+      else
+        col[a] = c;
       val[a] = 0.f;
       if (val16) val16[a] = __float2half_rn(0.f);
     }
@@ -468,19 +510,21 @@ __device__ __forceinline__ double from_fixed(unsigned long long acc, double inv)
 }
 
 struct SliceMeta {
-  int rho, rk, ng;
+  int rho, rk, ng, a0;
   int64_t base;
 };
 
 __device__ __forceinline__ SliceMeta slice_meta(const int32_t* __restrict__ sray,
                                                 const uint16_t* __restrict__ srank,
+                                                const uint16_t* __restrict__ sbase,
                                                 const int32_t* __restrict__ sng,
                                                 const int64_t* __restrict__ soff, int s, int s1,
                                                 int lane) {
-  SliceMeta m{-1, 0, 0, 0};
+  SliceMeta m{-1, 0, 0, 0, 0};
   if (s < s1) {
     m.rho = sray[(int64_t)s * 64 + lane];
     m.rk = srank[(int64_t)s * 64 + lane];
+    m.a0 = sbase ? sbase[(int64_t)s * 64 + lane] : 0;
     m.ng = sng[s];
     m.base = soff[s] + lane * 4;
   }
@@ -494,11 +538,19 @@ __device__ __forceinline__ T ld_nt(const T* p) {
   return __builtin_nontemporal_load(p);
 }
 
-template <typename VT>
-__device__ __forceinline__ void load_group(const uint16_t* __restrict__ col,
-                                           const VT* __restrict__ val, int64_t i, u16x4& c,
-                                           float (&a)[4]) {
-  c = ld_nt(reinterpret_cast<const u16x4*>(col + i));
+// Column data of one group of 4 entries of a lane: 4 addresses (wide) or 4
+// 8-bit steps in one word (narrow).
+template <bool NARROW>
+using ColRaw = typename std::conditional<NARROW, uint32_t, u16x4>::type;
+
+template <typename VT, bool NARROW>
+__device__ __forceinline__ void load_group(const void* __restrict__ col,
+                                           const VT* __restrict__ val, int64_t i,
+                                           ColRaw<NARROW>& c, float (&a)[4]) {
+  if constexpr (NARROW)
+    c = ld_nt(reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(col) + i));
+  else
+    c = ld_nt(reinterpret_cast<const u16x4*>(static_cast<const uint16_t*>(col) + i));
   if constexpr (sizeof(VT) == 4) {
     const f32x4 v = ld_nt(reinterpret_cast<const f32x4*>(reinterpret_cast<const float*>(val) + i));
     a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
@@ -508,10 +560,24 @@ __device__ __forceinline__ void load_group(const uint16_t* __restrict__ col,
   }
 }
 
-// z += a . x[c] (LDS gathers) and g[c] += a * r (fixed-point LDS atomics)
+// z += a . x[c] (LDS gathers) and g[c] += a * r (fixed-point LDS atomics);
+// narrow columns are decoded from the lane's running address ap (groups of
+// a lane are decoded in order)
+template <bool NARROW>
 __device__ __forceinline__ void group_step(const float* xs, unsigned long long* gs,
-                                           const u16x4& c, const float (&a)[4], double rs,
-                                           float& z) {
+                                           const ColRaw<NARROW>& raw, const float (&a)[4],
+                                           double rs, float& z, int& ap) {
+  int c[4];
+  if constexpr (NARROW) {
+    c[0] = ap + (int)(raw & 255u);
+    c[1] = c[0] + (int)((raw >> 8) & 255u);
+    c[2] = c[1] + (int)((raw >> 16) & 255u);
+    c[3] = c[2] + (int)(raw >> 24);
+    ap = c[3];
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) c[t] = raw[t];
+  }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     z = fmaf(a[t], xs[c[t]], z);
@@ -527,12 +593,13 @@ __device__ __forceinline__ int snake(int s0, int k, int wv) {
   return s0 + k * W + ((k & 1) ? (W - 1 - wv) : wv);
 }
 
-template <typename VT, int W>
+template <typename VT, bool NARROW, int W>
 __global__ __launch_bounds__(64 * W) void k_fused(
     TileGeom g, const int32_t* __restrict__ uorder, const int32_t* __restrict__ sbeg,
     const int32_t* __restrict__ sng, const int64_t* __restrict__ soff,
     const int32_t* __restrict__ sray, const uint16_t* __restrict__ srank,
-    const uint16_t* __restrict__ col, const VT* __restrict__ val, const float* __restrict__ x,
+    const uint16_t* __restrict__ sbase, const void* __restrict__ col,
+    const VT* __restrict__ val, const float* __restrict__ x,
     const float* __restrict__ r, const unsigned* __restrict__ rmax_in, unsigned* rmax_zero,
     float* __restrict__ zp, float* __restrict__ gp, int64_t r_int, int64_t c_int, double smax) {
   __shared__ float xs[kFTA];
@@ -567,51 +634,52 @@ __global__ __launch_bounds__(64 * W) void k_fused(
   __syncthreads();
   // the next slice's table entries and its r value load while a slice streams
   int k = 0, s = snake<W>(s0, 0, wv);
-  SliceMeta cur = slice_meta(sray, srank, sng, soff, s, s1, lane);
+  SliceMeta cur = slice_meta(sray, srank, sbase, sng, soff, s, s1, lane);
   float rcur = cur.rho >= 0 ? r[cur.rho] : 0.f;
   while (s < s1) {
     const int sn = snake<W>(s0, k + 1, wv);
-    const SliceMeta nxt = slice_meta(sray, srank, sng, soff, sn, s1, lane);
+    const SliceMeta nxt = slice_meta(sray, srank, sbase, sng, soff, sn, s1, lane);
     const double rs = (double)rcur * scale;
     const int64_t base = cur.base;
     const int ng = cur.ng;
     float z0 = 0.f, z1 = 0.f;
     float rnext = 0.f;
+    int ap = cur.a0;
     bool fetched = false;
     int j = 0;
     for (; j + 3 < ng; j += 4) {
-      u16x4 c0, c1, c2, c3;
+      ColRaw<NARROW> c0, c1, c2, c3;
       float a0[4], a1[4], a2[4], a3[4];
-      load_group<VT>(col, val, base + (int64_t)j * 256, c0, a0);
-      load_group<VT>(col, val, base + (int64_t)(j + 1) * 256, c1, a1);
-      load_group<VT>(col, val, base + (int64_t)(j + 2) * 256, c2, a2);
-      load_group<VT>(col, val, base + (int64_t)(j + 3) * 256, c3, a3);
+      load_group<VT, NARROW>(col, val, base + (int64_t)j * 256, c0, a0);
+      load_group<VT, NARROW>(col, val, base + (int64_t)(j + 1) * 256, c1, a1);
+      load_group<VT, NARROW>(col, val, base + (int64_t)(j + 2) * 256, c2, a2);
+      load_group<VT, NARROW>(col, val, base + (int64_t)(j + 3) * 256, c3, a3);
       if (!fetched) {
         fetched = true;
         if (nxt.rho >= 0) rnext = r[nxt.rho];
       }
-      group_step(xs, gs, c0, a0, rs, z0);
-      group_step(xs, gs, c1, a1, rs, z1);
-      group_step(xs, gs, c2, a2, rs, z0);
-      group_step(xs, gs, c3, a3, rs, z1);
+      group_step<NARROW>(xs, gs, c0, a0, rs, z0, ap);
+      group_step<NARROW>(xs, gs, c1, a1, rs, z1, ap);
+      group_step<NARROW>(xs, gs, c2, a2, rs, z0, ap);
+      group_step<NARROW>(xs, gs, c3, a3, rs, z1, ap);
     }
     for (; j + 1 < ng; j += 2) {
-      u16x4 c0, c1;
+      ColRaw<NARROW> c0, c1;
       float a0[4], a1[4];
-      load_group<VT>(col, val, base + (int64_t)j * 256, c0, a0);
-      load_group<VT>(col, val, base + (int64_t)(j + 1) * 256, c1, a1);
+      load_group<VT, NARROW>(col, val, base + (int64_t)j * 256, c0, a0);
+      load_group<VT, NARROW>(col, val, base + (int64_t)(j + 1) * 256, c1, a1);
       if (!fetched) {
         fetched = true;
         if (nxt.rho >= 0) rnext = r[nxt.rho];
       }
-      group_step(xs, gs, c0, a0, rs, z0);
-      group_step(xs, gs, c1, a1, rs, z1);
+      group_step<NARROW>(xs, gs, c0, a0, rs, z0, ap);
+      group_step<NARROW>(xs, gs, c1, a1, rs, z1, ap);
     }
     if (j < ng) {
-      u16x4 c0;
+      ColRaw<NARROW> c0;
       float a0[4];
-      load_group<VT>(col, val, base + (int64_t)j * 256, c0, a0);
-      group_step(xs, gs, c0, a0, rs, z0);
+      load_group<VT, NARROW>(col, val, base + (int64_t)j * 256, c0, a0);
+      group_step<NARROW>(xs, gs, c0, a0, rs, z0, ap);
     }
     if (!fetched && nxt.rho >= 0) rnext = r[nxt.rho];
     if (cur.rho >= 0) zp[(int64_t)cur.rk * r_int + cur.rho] = z0 + z1;
@@ -710,9 +778,14 @@ template <typename VT, int W>
 static void launch_fused_w(const bsgd_fused& F, const VT* val, const float* x, const float* r,
                            const unsigned* rmax_in, unsigned* rmax_zero, float* zp, float* gp,
                            hipStream_t s) {
-  k_fused<VT, W><<<(unsigned)F.g.units(), 64 * W, 0, s>>>(
-      F.g, F.uorder, F.sbeg, F.sng, F.soff, F.sray, F.srank, F.col, val, x, r, rmax_in,
-      rmax_zero, zp, gp, F.plan->L.r_int, F.plan->L.c_int, F.smax);
+  if (F.narrow)
+    k_fused<VT, true, W><<<(unsigned)F.g.units(), 64 * W, 0, s>>>(
+        F.g, F.uorder, F.sbeg, F.sng, F.soff, F.sray, F.srank, F.sbase, F.col8, val, x, r,
+        rmax_in, rmax_zero, zp, gp, F.plan->L.r_int, F.plan->L.c_int, F.smax);
+  else
+    k_fused<VT, false, W><<<(unsigned)F.g.units(), 64 * W, 0, s>>>(
+        F.g, F.uorder, F.sbeg, F.sng, F.soff, F.sray, F.srank, nullptr, F.col, val, x, r,
+        rmax_in, rmax_zero, zp, gp, F.plan->L.r_int, F.plan->L.c_int, F.smax);
 }
 
 template <typename VT>
@@ -773,10 +846,11 @@ hipError_t launch_fused_reduce(const bsgd_fused* F, const float* zp, const float
 // Build
 // ---------------------------------------------------------------------------
 struct FusedCounts {
+  bool narrow = true;  // 8-bit address steps
   int64_t pairs = 0;
   int64_t slices = 0;  // upper bound until the build has sorted the segments
   int64_t bound = 0;   // upper bound of the stored entries
-  int maxrank = 0, maxlen = 0;
+  int maxrank = 0, maxlen = 0, maxstep = 0;
 };
 
 // Count pass: segments per ray (into plan->scratch64, then scanned in place:
@@ -787,27 +861,30 @@ struct FusedCounts {
 // full slice k - 1 and stores at most that slice's entries, plus up to 3
 // padding entries per lane (groups of 4) -- entries <= nnz + units *
 // 64 * (maxlen + 3) + 192 * slices.  Synchronises.
-static bsgd_status fused_count(const bsgd_plan* p, const TileGeom& g, hipStream_t s,
+static bsgd_status fused_count(const bsgd_plan* p, const TileGeom& g, bool wide, hipStream_t s,
                                FusedCounts& fc) {
   const Layout& L = p->L;
   const int64_t units = g.units();
-  int32_t* words = reinterpret_cast<int32_t*>(p->vin);  // [0] maxc, [1] maxlen
-  k_fill_i32<<<1, 256, 0, s>>>(words, 2);
+  int32_t* words = reinterpret_cast<int32_t*>(p->vin);  // maxc, maxlen, maxstep
+  k_fill_i32<<<1, 256, 0, s>>>(words, 3);
   BSGD_LAUNCH_CHECK();
   const unsigned blocks = (unsigned)((L.r_int * 64 + 255) / 256);
   k_fz_walk<0><<<blocks, 256, 0, s>>>(g, p->fwd.ptr, p->fwd.seg, p->fwd.nseg, p->fwd.col,
                                       nullptr, nullptr, L.r_int, p->scratch64, words, words + 1,
+                                      words + 2, nullptr, nullptr, nullptr, nullptr, nullptr,
                                       nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                      nullptr, nullptr, nullptr, nullptr);
+                                      nullptr);
   BSGD_LAUNCH_CHECK();
   BSGD_HIP(exclusive_scan_i64(p->scratch64, p->scratch64, L.r_int, p->scan_tmp, s));
-  int32_t hw[2] = {0, 0};
+  int32_t hw[3] = {0, 0, 0};
   BSGD_HIP(hipMemcpyAsync(&fc.pairs, p->scratch64 + L.r_int, sizeof(int64_t),
                           hipMemcpyDeviceToHost, s));
   BSGD_HIP(hipMemcpyAsync(hw, words, sizeof(hw), hipMemcpyDeviceToHost, s));
   BSGD_HIP(hipStreamSynchronize(s));
   fc.maxrank = hw[0];
   fc.maxlen = hw[1];
+  fc.maxstep = hw[2];
+  fc.narrow = !wide && fc.maxstep < 256;
   BSGD_REQUIRE(fc.maxrank < 65536, "a ray crosses %d tiles (at most 65535)", fc.maxrank);
   fc.slices = (fc.pairs + 63) / 64 + units;
   fc.bound = p->fwd.nnz + units * 64 * ((int64_t)fc.maxlen + 3) + 192 * fc.slices;
@@ -819,6 +896,7 @@ static bsgd_status fused_count(const bsgd_plan* p, const TileGeom& g, hipStream_
 struct FusedTemps {
   uint64_t *key = nullptr, *key2 = nullptr;
   int32_t *idx = nullptr, *idx2 = nullptr, *pray = nullptr, *slen = nullptr, *pos = nullptr;
+  uint16_t* pbase = nullptr;
   int64_t *first = nullptr, *last = nullptr, *sng256 = nullptr, *scan_tmp = nullptr;
   int* err = nullptr;
   unsigned long long* smax = nullptr;
@@ -847,7 +925,13 @@ static size_t fused_layout(const bsgd_plan* p, const TileGeom& g, const FusedCou
   F->sray = cv.take<int32_t>(nslots);
   F->poff = cv.take<int32_t>(L.r_int + 1);
   F->srank = cv.take<uint16_t>(nslots);
-  F->col = cv.take<uint16_t>(std::max<int64_t>(fc.bound, 4));
+  F->narrow = fc.narrow;
+  if (fc.narrow) {
+    F->col8 = cv.take<uint8_t>(std::max<int64_t>(fc.bound, 4));
+    F->sbase = cv.take<uint16_t>(nslots);
+  } else {
+    F->col = cv.take<uint16_t>(std::max<int64_t>(fc.bound, 4));
+  }
   F->val = cv.take<float>(std::max<int64_t>(fc.bound, 4));
   F->val16 = f16 ? cv.take<__half>(std::max<int64_t>(fc.bound, 4)) : nullptr;
   F->xin = cv.take<float>(L.c_int);
@@ -863,6 +947,7 @@ static size_t fused_layout(const bsgd_plan* p, const TileGeom& g, const FusedCou
   T->idx = cv.take<int32_t>(np);
   T->idx2 = cv.take<int32_t>(np);
   T->pray = cv.take<int32_t>(np);
+  T->pbase = cv.take<uint16_t>(np);
   T->slen = cv.take<int32_t>(nslots);
   T->first = cv.take<int64_t>(units);
   T->last = cv.take<int64_t>(units);
@@ -879,8 +964,9 @@ static size_t fused_layout(const bsgd_plan* p, const TileGeom& g, const FusedCou
   return align_up(cv.off, kAlign);
 }
 
-static bsgd_status fused_check(const bsgd_plan* p, int chunks, TileGeom* g) {
+static bsgd_status fused_check(const bsgd_plan* p, int chunks, unsigned flags, TileGeom* g) {
   BSGD_REQUIRE(p != nullptr, "plan is NULL");
+  BSGD_REQUIRE((flags & ~BSGD_FUSED_WIDE) == 0, "unknown single-pass flags 0x%x", flags);
   BSGD_REQUIRE(chunks >= 0, "chunks must be >= 0 (0: automatic)");
   const Layout& L = p->L;
   if ((L.Wt + 3) / 4 > 64) {
@@ -902,14 +988,15 @@ static bsgd_status fused_check(const bsgd_plan* p, int chunks, TileGeom* g) {
 using namespace bsgd;
 
 extern "C" bsgd_status bsgd_fused_workspace_size(const bsgd_plan* plan, int chunks,
-                                                 hipStream_t stream, size_t* bytes) {
+                                                 unsigned flags, hipStream_t stream,
+                                                 size_t* bytes) {
   clear_error();
   BSGD_REQUIRE(bytes != nullptr, "bytes is NULL");
   TileGeom g;
-  bsgd_status st = fused_check(plan, chunks, &g);
+  bsgd_status st = fused_check(plan, chunks, flags, &g);
   if (st != BSGD_OK) return st;
   FusedCounts fc;
-  st = fused_count(plan, g, stream, fc);
+  st = fused_count(plan, g, (flags & BSGD_FUSED_WIDE) != 0, stream, fc);
   if (st != BSGD_OK) return st;
   bsgd_fused tmp;
   FusedTemps T;
@@ -917,17 +1004,17 @@ extern "C" bsgd_status bsgd_fused_workspace_size(const bsgd_plan* plan, int chun
   return BSGD_OK;
 }
 
-extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, void* workspace,
-                                         size_t workspace_bytes, hipStream_t stream,
-                                         bsgd_fused** out) {
+extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, unsigned flags,
+                                         void* workspace, size_t workspace_bytes,
+                                         hipStream_t stream, bsgd_fused** out) {
   clear_error();
   BSGD_REQUIRE(workspace && out, "NULL argument");
   BSGD_REQUIRE(((uintptr_t)workspace % kAlign) == 0, "workspace must be 256-byte aligned");
   TileGeom g;
-  bsgd_status st = fused_check(plan, chunks, &g);
+  bsgd_status st = fused_check(plan, chunks, flags, &g);
   if (st != BSGD_OK) return st;
   FusedCounts fc;
-  st = fused_count(plan, g, stream, fc);
+  st = fused_count(plan, g, (flags & BSGD_FUSED_WIDE) != 0, stream, fc);
   if (st != BSGD_OK) return st;
   bsgd_fused* F = new bsgd_fused();
   F->plan = plan;
@@ -967,8 +1054,8 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, void
   if (fc.pairs > 0) {
     k_fz_walk<1><<<wblocks, 256, 0, stream>>>(
         g, A.ptr, A.seg, A.nseg, A.col, nullptr, nullptr, L.r_int, nullptr, nullptr, nullptr,
-        plan->scratch64, T.key, T.idx, T.pray, nullptr, nullptr, nullptr, nullptr, nullptr,
-        nullptr);
+        nullptr, plan->scratch64, T.key, T.idx, T.pray, T.pbase, nullptr, nullptr, nullptr,
+        nullptr, nullptr, nullptr, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "segment pass");
     size_t cb = T.cub_bytes;
@@ -1013,11 +1100,12 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, void
                        stream);
   if (e != hipSuccess) return hip_fail(e, "single-pass build upload");
   if (fc.pairs > 0) {
-    k_fz_init_slots<<<grid_for(nslots), 256, 0, stream>>>(F->sray, T.slen, nslots);
+    k_fz_init_slots<<<grid_for(nslots), 256, 0, stream>>>(F->sray, T.slen, F->sbase, nslots);
     k_fz_place<<<grid_for(fc.pairs), 256, 0, stream>>>(T.key2, T.idx2, T.pray, plan->scratch64,
-                                                       fc.pairs, T.first, F->sbeg, nslots, T.pos,
-                                                       F->sray, F->srank, T.slen, F->sng,
-                                                       T.sng256, T.err);
+                                                       fc.pairs, T.first, F->sbeg, nslots,
+                                                       T.pbase, T.pos, F->sray, F->srank,
+                                                       F->sbase, T.slen, F->sng, T.sng256,
+                                                       T.err);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "slot placement");
   }
@@ -1045,10 +1133,10 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, void
   if (fc.pairs > 0) {
     k_fz_walk<2><<<wblocks, 256, 0, stream>>>(
         g, A.ptr, A.seg, A.nseg, A.col, A.val, A.val16, L.r_int, nullptr, nullptr, nullptr,
-        plan->scratch64, nullptr, nullptr, nullptr, T.pos, F->soff, F->col, F->val, F->val16,
-        T.err);
+        nullptr, plan->scratch64, nullptr, nullptr, nullptr, nullptr, T.pos, F->soff, F->col,
+        F->col8, F->val, F->val16, T.err);
     k_fz_pad<<<grid_for(nslots), 256, 0, stream>>>(T.slen, F->sng, F->soff, nslots, F->col,
-                                                   F->val, F->val16);
+                                                   F->col8, F->val, F->val16);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "entry fill");
   }
@@ -1078,9 +1166,12 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, void
 extern "C" void bsgd_fused_destroy(bsgd_fused* F) { delete F; }
 
 extern "C" bsgd_status bsgd_fused_shape(const bsgd_fused* F, int* tiles, int* chunks,
-                                        int64_t* segments, int64_t* slices, int64_t* entries) {
+                                        int64_t* segments, int64_t* slices, int64_t* entries,
+                                        int* col_bytes) {
   clear_error();
-  BSGD_REQUIRE(F && tiles && chunks && segments && slices && entries, "NULL argument");
+  BSGD_REQUIRE(F && tiles && chunks && segments && slices && entries && col_bytes,
+               "NULL argument");
+  *col_bytes = F->narrow ? 1 : 2;
   *tiles = (int)F->g.tiles();
   *chunks = F->g.Q;
   *segments = F->pairs;

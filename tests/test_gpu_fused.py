@@ -43,9 +43,9 @@ def _segments(p, view_len):
     return len(np.unique(key))
 
 
-def _fused(plan, chunks=0, waves=None):
+def _fused(plan, chunks=0, waves=None, flags=0):
     import paper_1812_01307_amd as bsgd
-    F = bsgd.bsgd_fused_create(plan, chunks)
+    F = bsgd.bsgd_fused_create(plan, chunks, flags)
     if waves:
         bsgd.bsgd_fused_set_waves(F, waves)
     return F
@@ -58,7 +58,8 @@ def test_fused_products_match_oracle(name, view_len):
     p = _cases()[name]()
     plan = plan_for(p, view_len=view_len)
     F = _fused(plan)
-    tiles, chunks, segs, slices, entries = bsgd.bsgd_fused_shape(F)
+    tiles, chunks, segs, slices, entries, cbytes = bsgd.bsgd_fused_shape(F)
+    assert cbytes == 1  # rays: steps between successive pixels of a tile are below 256
     assert tiles == ((p.H + 31) // 32) * ((p.W + 31) // 32)
     assert segs == _segments(p, view_len)
     assert slices * 64 >= segs and entries >= p.nnz and entries % 256 == 0
@@ -87,6 +88,12 @@ def test_fused_products_match_oracle(name, view_len):
         ax2, g2 = bsgd.bsgd_fused_apply(F2, _dev(x), _dev(r))
         assert np.all(np.abs(_host(ax2) - ref_ax) <= bound_f)
         assert np.all(np.abs(_host(g2) - ref_g) <= bound_b)
+    # 16-bit addresses give the same addresses, so the same sums bitwise
+    Fw = _fused(plan, flags=bsgd.BSGD_FUSED_WIDE)
+    assert bsgd.bsgd_fused_shape(Fw)[5] == 2
+    axw, gw = bsgd.bsgd_fused_apply(Fw, _dev(x), _dev(r))
+    ax0, g0 = bsgd.bsgd_fused_apply(F, _dev(x), _dev(r))
+    assert np.array_equal(_host(axw), _host(ax0)) and np.array_equal(_host(gw), _host(g0))
 
 
 def _run(p, plan, F, mu, lam, epochs, K, vt=0):
@@ -235,8 +242,8 @@ def test_fused_full_size_sampled():
     p = problem("c2_512")
     plan = plan_for(p)
     F = _fused(plan)
-    tiles, chunks, segs, slices, entries = bsgd.bsgd_fused_shape(F)
-    assert tiles == 256 and segs > p.nrows and entries >= p.nnz
+    tiles, chunks, segs, slices, entries, cbytes = bsgd.bsgd_fused_shape(F)
+    assert tiles == 256 and segs > p.nrows and entries >= p.nnz and cbytes == 1
     rng = np.random.default_rng(12)
     x = f32(rng.random(p.ncols))
     r = f32(rng.standard_normal(p.nrows))
@@ -256,3 +263,40 @@ def test_fused_full_size_sampled():
         c = tc[a:b]
         ref = 2.0 * float(np.dot(v, r[c].astype(np.float64)))
         assert abs(g[j] - ref) <= PRODUCT_REL * 2 * float(np.dot(np.abs(v), np.abs(r[c]))) + 1e-30
+
+
+def test_fused_general_matrix_uses_wide_columns():
+    """Rows that are not rays (random ascending columns): steps exceed 255, 16-bit columns."""
+    import paper_1812_01307_amd as bsgd
+    import synth
+    rng = np.random.default_rng(17)
+    H, W, nrows = 70, 45, 900
+    ncols = H * W
+    lens = rng.integers(0, 120, nrows)
+    lens[::50] = 0  # some empty rows
+    cols = [np.sort(rng.choice(ncols, n, replace=False)).astype(np.int32) for n in lens]
+    row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.concatenate(cols).astype(np.int32)
+    val = rng.random(len(col)) * 1.5
+    tp, tc, tv = synth.transpose_csr(nrows, ncols, row_ptr, col, val)
+    plan = bsgd.plan_from_host(nrows, ncols, row_ptr, col, val, tp, tc, tv, 3, 2,
+                               [0, 300, 600, 900], [0, 1500, ncols], H, W, 1, view_len=0)
+    F = _fused(plan)
+    assert bsgd.bsgd_fused_shape(F)[5] == 2
+    A = oracle.as_matrix(row_ptr, col, f32(val).astype(np.float64), ncols)
+    Aabs = oracle.as_matrix(row_ptr, col, np.abs(f32(val).astype(np.float64)), ncols)
+    x = f32(rng.random(ncols))
+    r = f32(rng.standard_normal(nrows))
+    ax, g = bsgd.bsgd_fused_apply(F, _dev(x), _dev(r))
+    assert np.all(np.abs(_host(ax) - A @ x) <= PRODUCT_REL * (Aabs @ np.abs(x)) + 1e-30)
+    assert np.all(np.abs(_host(g) - 2 * (A.T @ r)) <= PRODUCT_REL * 2 * (Aabs.T @ np.abs(r)) + 1e-30)
+    # a few epochs against the oracle
+    y = f32(A @ rng.random(ncols))
+    mu = float(np.float32(oracle.step_size(oracle.power_umax(A))))
+    _, _, ref = oracle.bsgd_tv(A, y.astype(np.float64), mu, 3.0, 8, 20, (H, W), record=True)
+    st = bsgd.bsgd_state_create(plan)
+    bsgd.bsgd_state_attach_fused(st, F)
+    bsgd.bsgd_state_init(st, _dev(y))
+    for k in range(8):
+        bsgd.bsgd_run_epochs(st, mu, 3.0, 1, 20)
+        assert rel_l2(_host(bsgd.bsgd_get_x(st)), ref[k]) <= ITERATE_REL, k

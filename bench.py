@@ -6,7 +6,7 @@ One step = one whole reconstruction job of the 512 x 512 workload
 iterations), starting from A, A^T (FP32 CSR) and y already resident in HBM:
     S0   build the block store            (bsgd_plan_create)
          and the tile-sliced store         (bsgd_fused_create; --path fused)
-    S0'  u_max by power iteration, mu = 0.9 / (2 u_max)
+    S0'  u_max by Lanczos bidiagonalisation (or --umax power), mu = 0.9 / (2 u_max)
     S1-S5 x 200 epochs                     (bsgd_run_epochs)
 With --path fused (default) every epoch reads the matrix once (both
 products in one pass); --path rows runs one pass over A and one over A^T.
@@ -29,7 +29,12 @@ HBM_PEAK_GBS = 8000.0
 # by (path, workload, value type[, staged, direction]).  Valid only while the
 # kernel and layout sources hash to the value recorded with the counters;
 # otherwise the figure is reported as null.
-PMC_TRAFFIC = {}
+PMC_TRAFFIC = {
+    # profiles/k_fused_c2_512_hbm_counters.md
+    ("fused", "c2_512", "f32"): {
+        "sha256": "d25dc6b662d080c48e4758962b8cf4360e472e706ec6d7047bbb1933c083c4e7",
+        "bytes": 1421558513},
+}
 
 
 def _kernel_source_hash():
@@ -57,6 +62,10 @@ def main(argv=None):
     ap.add_argument("--config", default="c2_512")
     ap.add_argument("--vt", choices=["f32", "f16"], default="f32")
     ap.add_argument("--epochs", type=int, default=None, help="override the workload's epoch count")
+    ap.add_argument("--umax", default="lanczos", choices=["lanczos", "power"],
+                    help="u_max for the step size: Lanczos bidiagonalisation or power iteration")
+    ap.add_argument("--umax-steps", type=int, default=10,
+                    help="Lanczos steps (each one product with A and one with A^T)")
     ap.add_argument("--power-iters", type=int, default=30)
     ap.add_argument("--cpu-epochs", type=int, default=20,
                     help="oracle epochs timed for the CPU baseline")
@@ -175,7 +184,10 @@ def main(argv=None):
             bsgd.bsgd_plan_set_lanes(plan, *tuned[0])
             bsgd.bsgd_plan_set_staged(plan, *[max(v, 0) for v in tuned[1]])
         if fixed_mu is None:
-            u = bsgd.bsgd_power_umax(plan, args.power_iters, vt=vt)
+            if args.umax == "lanczos":
+                u = bsgd.bsgd_lanczos_umax(plan, args.umax_steps, vt=vt)
+            else:
+                u = bsgd.bsgd_power_umax(plan, args.power_iters, vt=vt)
             mu = 0.9 / (2.0 * u)
         else:
             mu = fixed_mu
@@ -361,12 +373,14 @@ def main(argv=None):
                                f"image, {prob.n_ang} angles x {prob.bins} bins, M=N={prob.M}, "
                                f"lambda={prob.lam}, {epochs} epochs, {K} FGP iterations, "
                                f"setup S0+S0' included)",
-                   "nnz": nnz, "epochs_per_step": epochs, "power_iters": args.power_iters,
+                   "nnz": nnz, "epochs_per_step": epochs,
                    "path": args.path,
                    "lanes_per_row": list(bsgd.bsgd_plan_lanes(plan)), "overlap": args.overlap,
                    "staged": args.staged,
                    "mu": "fixed from " + args.mu_file if fixed_mu is not None
-                   else f"power iteration ({args.power_iters} steps)"},
+                   else (f"Lanczos bidiagonalisation ({args.umax_steps} steps)"
+                         if args.umax == "lanczos"
+                         else f"power iteration ({args.power_iters} steps)")},
         "epoch_only_ms": round(epoch_ms, 4),
         "epoch_only_epochs_per_s": round(1e3 / epoch_ms, 2),
         "alg_bytes_per_epoch": b_fwd + b_bwd,

@@ -261,6 +261,19 @@ bsgd_status bsgd_power_workspace_size(const bsgd_plan* plan, size_t* bytes);
 bsgd_status bsgd_power_umax(const bsgd_plan* plan, bsgd_valtype vt, int iters, void* ws,
                             size_t ws_bytes, hipStream_t stream, float* umax);
 
+/*
+ * u_max by `steps` steps of Golub-Kahan-Lanczos bidiagonalisation of A from
+ * the all-ones vector (each step one product with A and one with A^T, like a
+ * power step): the largest eigenvalue of B^T B, B the steps x steps upper
+ * bidiagonal of the recurrence, is the largest Ritz value of A^T A in the
+ * Krylov space, which approaches u_max from below far faster than the
+ * power iteration.  Synchronises; BSGD_ERR_DIVERGED if a value is not
+ * finite.  1 <= steps <= 4096; workspace from bsgd_lanczos_workspace_size.
+ */
+bsgd_status bsgd_lanczos_workspace_size(const bsgd_plan* plan, int steps, size_t* bytes);
+bsgd_status bsgd_lanczos_umax(const bsgd_plan* plan, bsgd_valtype vt, int steps, void* ws,
+                              size_t ws_bytes, hipStream_t stream, float* umax);
+
 /* ------------------------------------------------------------------------
  * Whole epochs (Algorithm 1)
  * ---------------------------------------------------------------------- */

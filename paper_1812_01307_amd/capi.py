@@ -77,6 +77,8 @@ _PROTOS = {
     "bsgd_tv_value": [_i32, _i32, _i32, _vp, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_double)],
     "bsgd_power_workspace_size": [_vp, ctypes.POINTER(_sz)],
     "bsgd_power_umax": [_vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_f32)],
+    "bsgd_lanczos_workspace_size": [_vp, _i32, ctypes.POINTER(_sz)],
+    "bsgd_lanczos_umax": [_vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_f32)],
     "bsgd_state_workspace_size": [_vp, _i32, ctypes.c_uint, ctypes.POINTER(_sz)],
     "bsgd_state_create": [_vp, _i32, _i32, ctypes.c_uint, _vp, _sz, ctypes.POINTER(_vp)],
     "bsgd_state_set_rhs": [_vp, _i32, _vp, _vp, _vp],
@@ -374,6 +376,24 @@ def bsgd_power_umax(plan: Plan, iters, vt=BSGD_VAL_F32, ws=None, stream=None) ->
     out = ctypes.c_float()
     _check("bsgd_power_umax", _lib.bsgd_power_umax(plan.handle, vt, int(iters), _ptr(ws), ws.numel(),
                                                    _stream(stream), ctypes.byref(out)))
+    return float(out.value)
+
+
+def bsgd_lanczos_workspace_size(plan: Plan, steps: int) -> int:
+    out = _sz()
+    _check("bsgd_lanczos_workspace_size", _lib.bsgd_lanczos_workspace_size(plan.handle, int(steps),
+                                                                           ctypes.byref(out)))
+    return out.value
+
+
+def bsgd_lanczos_umax(plan: Plan, steps, vt=BSGD_VAL_F32, ws=None, stream=None) -> float:
+    nbytes = bsgd_lanczos_workspace_size(plan, steps)
+    if ws is None:
+        ws = _ws(nbytes, plan.workspace.device)
+    out = ctypes.c_float()
+    _check("bsgd_lanczos_umax", _lib.bsgd_lanczos_umax(plan.handle, vt, int(steps), _ptr(ws),
+                                                       ws.numel(), _stream(stream),
+                                                       ctypes.byref(out)))
     return float(out.value)
 
 

@@ -9,6 +9,7 @@
 // second stream while S2 and then the prox run on the caller's stream; the
 // prox (many short launches) hides under the forward pass.  x and r are
 // double-buffered; events order the buffer reuse across epochs.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -61,6 +62,58 @@ __global__ void k_scale_by_rsqrt(float* __restrict__ v, const float* __restrict_
 __global__ void k_ratio(const double* __restrict__ num, const double* __restrict__ den,
                         float* __restrict__ out) {
   *out = *den > 0.0 ? (float)(*num / *den) : 0.f;
+}
+
+// Golub-Kahan-Lanczos helpers: x -= sqrt(*s2) * y (s2 a sum of squares)
+__global__ void k_sub_scaled(float* __restrict__ x, const float* __restrict__ y, int64_t n,
+                             const double* __restrict__ s2) {
+  const float a = (float)sqrt(*s2);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = fmaf(-a, y[i], x[i]);
+}
+
+static size_t lanczos_layout(const bsgd_plan* p, int steps, void* ws, float** v, float** w,
+                             float** u0, float** u1, double** part, double** sc) {
+  Carver cv(ws);
+  *v = cv.take<float>(p->L.c_int);
+  *w = cv.take<float>(p->L.c_int);
+  *u0 = cv.take<float>(p->L.r_int);
+  *u1 = cv.take<float>(p->L.r_int);
+  *part = cv.take<double>(kReduceBlocks);
+  *sc = cv.take<double>(2 * (size_t)std::max(steps, 1));
+  return align_up(cv.off, kAlign);
+}
+
+// Largest eigenvalue of the symmetric tridiagonal matrix (d, e) by bisection
+// on Sturm counts.
+static double tridiag_max_eig(const std::vector<double>& d, const std::vector<double>& e) {
+  const int n = (int)d.size();
+  double lo = 0.0, hi = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+    hi = std::max(hi, d[i] + r);
+    lo = std::min(lo, d[i] - r);
+  }
+  auto count_below = [&](double x) {  // eigenvalues < x
+    int c = 0;
+    double q = 1.0;
+    for (int i = 0; i < n; ++i) {
+      const double off = i > 0 ? e[i - 1] * e[i - 1] : 0.0;
+      q = d[i] - x - (i > 0 ? off / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      if (q < 0.0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) == n)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return hi;
 }
 
 static size_t power_layout(const bsgd_plan* p, void* ws, float** v, float** z, float** w,
@@ -145,6 +198,78 @@ extern "C" bsgd_status bsgd_power_umax(const bsgd_plan* plan, bsgd_valtype vt, i
   }
   BSGD_HIP(hipMemcpyAsync(umax, res, sizeof(float), hipMemcpyDeviceToHost, stream));
   BSGD_HIP(hipStreamSynchronize(stream));
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_lanczos_workspace_size(const bsgd_plan* plan, int steps,
+                                                   size_t* bytes) {
+  clear_error();
+  BSGD_REQUIRE(plan && bytes, "NULL argument");
+  BSGD_REQUIRE(steps >= 1 && steps <= 4096, "steps must be in [1, 4096]");
+  float *v, *w, *u0, *u1;
+  double *part, *sc;
+  *bytes = lanczos_layout(plan, steps, nullptr, &v, &w, &u0, &u1, &part, &sc);
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_lanczos_umax(const bsgd_plan* plan, bsgd_valtype vt, int steps,
+                                         void* ws, size_t ws_bytes, hipStream_t stream,
+                                         float* umax) {
+  clear_error();
+  BSGD_REQUIRE(plan && ws && umax, "NULL argument");
+  BSGD_REQUIRE(steps >= 1 && steps <= 4096, "steps must be in [1, 4096]");
+  BSGD_REQUIRE(vt == BSGD_VAL_F32 || (vt == BSGD_VAL_F16 && (plan->flags & BSGD_PLAN_F16)),
+               "value type not available in this plan");
+  float *v, *w, *u[2];
+  double *part, *sc;
+  const size_t need = lanczos_layout(plan, steps, ws, &v, &w, &u[0], &u[1], &part, &sc);
+  if (ws_bytes < need) {
+    set_error("lanczos workspace has %zu bytes, needs %zu", ws_bytes, need);
+    return BSGD_ERR_WORKSPACE;
+  }
+  const int64_t c = plan->L.c_int, r = plan->L.r_int;
+  // v_1 = ones / ||ones|| (holes of the internal order stay 0)
+  BSGD_HIP(fill_pixels_one(plan->L, w, stream));
+  BSGD_HIP(launch_sumsq(w, c, part, sc, stream));
+  k_scale_by_rsqrt<<<1024, 256, 0, stream>>>(v, w, c, sc);
+  BSGD_LAUNCH_CHECK();
+  for (int j = 0; j < steps; ++j) {
+    float* un = u[j & 1];
+    const float* up = u[(j + 1) & 1];
+    // alpha_j u_j = A v_j - beta_{j-1} u_{j-1}
+    BSGD_HIP(launch_rows(plan->fwd, vt, kPlain, v, nullptr, nullptr, 1.0f, un, stream));
+    if (j > 0) {
+      k_sub_scaled<<<1024, 256, 0, stream>>>(un, up, r, sc + 2 * (j - 1) + 1);
+      BSGD_LAUNCH_CHECK();
+    }
+    BSGD_HIP(launch_sumsq(un, r, part, sc + 2 * j, stream));
+    k_scale_by_rsqrt<<<1024, 256, 0, stream>>>(un, un, r, sc + 2 * j);
+    BSGD_LAUNCH_CHECK();
+    // beta_j v_{j+1} = A^T u_j - alpha_j v_j
+    BSGD_HIP(launch_rows(plan->bwd, vt, kPlain, un, nullptr, nullptr, 1.0f, w, stream));
+    k_sub_scaled<<<1024, 256, 0, stream>>>(w, v, c, sc + 2 * j);
+    BSGD_LAUNCH_CHECK();
+    BSGD_HIP(launch_sumsq(w, c, part, sc + 2 * j + 1, stream));
+    k_scale_by_rsqrt<<<1024, 256, 0, stream>>>(v, w, c, sc + 2 * j + 1);
+    BSGD_LAUNCH_CHECK();
+  }
+  std::vector<double> h(2 * (size_t)steps);
+  BSGD_HIP(hipMemcpyAsync(h.data(), sc, sizeof(double) * h.size(), hipMemcpyDeviceToHost, stream));
+  BSGD_HIP(hipStreamSynchronize(stream));
+  // B: diagonal alpha_j, superdiagonal beta_j; B^T B is tridiagonal with
+  // diagonal alpha_j^2 + beta_{j-1}^2 and off-diagonal alpha_j beta_j
+  std::vector<double> d(steps), e(std::max(steps - 1, 0));
+  for (int j = 0; j < steps; ++j) {
+    const double a2 = h[2 * j], b2p = j > 0 ? h[2 * (j - 1) + 1] : 0.0;
+    d[j] = a2 + b2p;
+    if (j + 1 < steps) e[j] = std::sqrt(a2 * h[2 * j + 1]);
+  }
+  for (double x : h)
+    if (!std::isfinite(x)) {
+      set_error("lanczos produced a non-finite value");
+      return BSGD_ERR_DIVERGED;
+    }
+  *umax = (float)tridiag_max_eig(d, e);
   return BSGD_OK;
 }
 

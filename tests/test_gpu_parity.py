@@ -170,6 +170,21 @@ def test_power_umax(name):
     assert abs(u - ref) <= 1e-4 * ref
 
 
+@pytest.mark.parametrize("name", CASES)
+def test_lanczos_umax(name):
+    """Lanczos bidiagonalisation reaches the converged FP64 u_max in a few steps (from below)."""
+    import paper_1812_01307_amd as bsgd
+    p = _case(name)
+    plan = _plan(name)
+    ref = oracle.power_umax(matrix(p))
+    for steps in (6, 10, 24):
+        u = bsgd.bsgd_lanczos_umax(plan, steps)
+        assert abs(u - ref) <= 1e-5 * ref, (steps, u, ref)
+    assert bsgd.bsgd_lanczos_umax(plan, 1) <= ref * (1 + 1e-6)
+    with pytest.raises(bsgd.BsgdError):
+        bsgd.bsgd_lanczos_umax(plan, 0)
+
+
 # --------------------------------------------------------------------------
 # Whole epochs (Algorithm 1)
 # --------------------------------------------------------------------------

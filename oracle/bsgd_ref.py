@@ -36,6 +36,12 @@ What it computes, and where the paper defines it:
 * The M x N block partition of Section 2.1 and a blocked epoch that sums
   the block products in ascending block order (used to show that blocking
   changes rounding only).
+* The Simulations section's comparison methods: ISTA (the same line 8-9
+  step with the current iterate's gradient, A taken whole) and gradient
+  descent on f alone (ISTA with lam = 0).
+* Algorithm 1 on drawn subsets of the row and column blocks (Simulations
+  section, fractions gamma and alpha); the handling of the blocks left out
+  of an iteration is a reading, stated at selected_iteration.
 
 Where the paper is silent or ambiguous the readings above are used; the
 design notes list them.
@@ -439,3 +445,146 @@ def bsgd_tv_multi(A, Y, mu: float, lam, epochs: int, prox_iters: int, shape2d, v
         if record:
             hist.append(X.copy())
     return (X, R, hist) if record else (X, R)
+
+
+# ---------------------------------------------------------------------------
+# Comparison methods of the Simulations section (Fig. 2): ISTA and GD
+# ---------------------------------------------------------------------------
+
+
+def ista_epoch(A, y, x, mu: float, lam: float, prox_iters: int, shape):
+    """One ISTA iteration on F (the proximal gradient method the paper compares with).
+
+    The step of Algorithm 1 lines 8-9 with the gradient of the current
+    iterate (no delay; A taken as a whole, Fig. 2 caption):
+        r  = y - A x
+        x' = argmin_t ||t - (x + 2 mu A^T r)||^2 + 2 mu lam TV(t).
+    Returns (x', r): r is the residual of the input iterate, so the pair has
+    the meaning of Algorithm 1's state (the residual one iterate behind).
+    """
+    r = y - forward(A, x)
+    xhat = x + mu * backproject(A, r)
+    return prox(xhat, mu * lam, prox_iters, shape), r
+
+
+def ista_tv(A, y, mu: float, lam: float, epochs: int, prox_iters: int, shape,
+            x0=None, record: bool = False):
+    """Run `epochs` ISTA iterations from x0 (zero by default).
+
+    Returns (x, r) after the last iteration (r = y - A x of the iterate
+    before it) and, with record=True, the iterates after every iteration.
+    """
+    x = np.zeros(A.shape[1]) if x0 is None else np.array(x0, np.float64)
+    r = np.asarray(y, np.float64) - forward(A, x)
+    hist = []
+    for _ in range(epochs):
+        x, r = ista_epoch(A, y, x, mu, lam, prox_iters, shape)
+        if record:
+            hist.append(x.copy())
+    return (x, r, hist) if record else (x, r)
+
+
+def gd(A, y, mu: float, epochs: int, x0=None, record: bool = False):
+    """Gradient descent on f(x) = ||y - A x||^2 with step mu (Fig. 2's GD).
+
+    x_{k+1} = x_k + 2 mu A^T (y - A x_k): ISTA without the TV term.
+    """
+    shape = (A.shape[1],)
+    return ista_tv(A, y, mu, 0.0, epochs, 0, shape, x0=x0, record=record)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 on drawn subsets of the blocks (Simulations section: only
+# fractions alpha of {x_{J_j}} and gamma of {y_{I_i}} take part in an
+# iteration)
+# ---------------------------------------------------------------------------
+
+
+def mask_members(mask: int, n: int):
+    """Ascending indices k < n whose bit is set in `mask`."""
+    return [k for k in range(n) if (int(mask) >> k) & 1]
+
+
+def selected_iteration(blocks, row_off, col_off, y, x, r, Z, mu: float, lam: float,
+                       prox_iters: int, shape, rows_mask: int, cols_mask: int):
+    """One iteration of Algorithm 1 that runs only the pairs (i, j), i in I, j in J.
+
+    I and J are the set bits of rows_mask and cols_mask.  Reading of what
+    the paper leaves open (it states only that the method still converges
+    with such subsets):
+      * every pair keeps the last product z^j_{I_i} it computed, in Z[j]
+        (a full-length ray vector per column block);
+      * lines 3-4 run for the selected pairs: g^i_{J_j} from the kept
+        residual r_{I_i}, and z^j_{I_i} from the current x_{J_j} (stored in Z);
+      * line 6 refreshes r_{I_i} for i in I from y and the kept products of
+        all column blocks, ascending j; other rows keep their residual;
+      * line 7 sums g^i over i in I only (no rescaling); line 8 moves the
+        selected column blocks; the other blocks of x stay as they are;
+      * line 9 runs on the whole image with theta = mu * lam, as written.
+    With every bit set this is bsgd_epoch_blocked.  Returns (x, r, Z) as new
+    arrays.
+    """
+    M, N = len(row_off) - 1, len(col_off) - 1
+    I, J = mask_members(rows_mask, M), mask_members(cols_mask, N)
+    Z = Z.copy()
+    r_new = r.copy()
+    g = np.zeros_like(x)
+    for j in J:                                   # lines 3 + 7 over i in I
+        c0, c1 = int(col_off[j]), int(col_off[j + 1])
+        acc = np.zeros(c1 - c0)
+        for i in I:
+            r0, r1 = int(row_off[i]), int(row_off[i + 1])
+            acc = acc + block_backproject(blocks, row_off, col_off, i, j, r[r0:r1])
+        g[c0:c1] = acc
+    for i in I:                                   # line 4, then line 6 for I_i
+        r0, r1 = int(row_off[i]), int(row_off[i + 1])
+        for j in J:
+            c0, c1 = int(col_off[j]), int(col_off[j + 1])
+            Z[j, r0:r1] = block_forward(blocks, row_off, col_off, i, j, x[c0:c1])
+        acc = np.zeros(r1 - r0)
+        for j in range(N):
+            acc = acc + Z[j, r0:r1]
+        r_new[r0:r1] = y[r0:r1] - acc
+    xhat = x + mu * g                             # line 8 (zero outside J)
+    return prox(xhat, mu * lam, prox_iters, shape), r_new, Z
+
+
+def selected_initial_state(blocks, row_off, col_off, y, x0=None):
+    """x = x0 (zero by default); Z[j] = the block products of x0; r = y - sum_j Z[j]."""
+    M, N = len(row_off) - 1, len(col_off) - 1
+    nrows, ncols = int(row_off[-1]), int(col_off[-1])
+    x = np.zeros(ncols) if x0 is None else np.array(x0, np.float64)
+    Z = np.zeros((N, nrows))
+    for i in range(M):
+        r0, r1 = int(row_off[i]), int(row_off[i + 1])
+        for j in range(N):
+            c0, c1 = int(col_off[j]), int(col_off[j + 1])
+            Z[j, r0:r1] = block_forward(blocks, row_off, col_off, i, j, x[c0:c1])
+    r = np.asarray(y, np.float64) - Z.sum(axis=0) if x0 is not None else \
+        np.asarray(y, np.float64).copy()
+    return x, r, Z
+
+
+def bsgd_selected(blocks, row_off, col_off, y, mu: float, lam: float, prox_iters: int, shape,
+                  rows_masks, cols_masks, x0=None, state=None, record: bool = False):
+    """Iterations of selected_iteration, one per (rows_masks[t], cols_masks[t]).
+
+    Returns (x, r, Z) and, with record=True, the iterates after every
+    iteration.  `state` = (x, r, Z) resumes a run.
+    """
+    x, r, Z = state if state is not None else selected_initial_state(blocks, row_off, col_off,
+                                                                     y, x0)
+    hist = []
+    for rm, cm in zip(rows_masks, cols_masks):
+        x, r, Z = selected_iteration(blocks, row_off, col_off, y, x, r, Z, mu, lam, prox_iters,
+                                     shape, int(rm), int(cm))
+        if record:
+            hist.append(x.copy())
+    return (x, r, Z, hist) if record else (x, r, Z)
+
+
+def selected_epochs(rows_masks, cols_masks, M: int, N: int) -> np.ndarray:
+    """Epoch count after each iteration: the fraction of the M x N pairs run, summed."""
+    frac = [bin(int(a)).count("1") * bin(int(b)).count("1") / (M * N)
+            for a, b in zip(rows_masks, cols_masks)]
+    return np.cumsum(frac)

@@ -11,6 +11,7 @@ from .problem import (  # noqa: F401
     CONFIGS,
     Problem,
     block_offsets,
+    block_subsets,
     build_native,
     ellipse_phantom,
     make_problem,

@@ -302,3 +302,28 @@ def make_volume_problem(S: int = 256, base: str = "c2_512", first_seed: int = 10
     if with_transpose:
         prob.ensure_transpose()
     return prob
+
+
+def block_subsets(iters: int, M: int, N: int, alpha: float, gamma: float, seed: int):
+    """Seeded draws of the blocks that take part in each partial iteration.
+
+    Iteration t takes max(1, round(gamma * M)) of the M row blocks and
+    max(1, round(alpha * N)) of the N column blocks, uniformly without
+    replacement, from numpy.random.default_rng(seed).  Returns two uint64
+    arrays of length `iters` holding the draws as bit masks (bit i set when
+    block i is taken); M and N are at most 64.
+    """
+    if not (1 <= M <= 64 and 1 <= N <= 64):
+        raise ValueError("bit masks hold at most 64 blocks")
+    if not (0.0 < alpha <= 1.0 and 0.0 < gamma <= 1.0):
+        raise ValueError("fractions must lie in (0, 1]")
+    rng = np.random.default_rng(seed)
+    nr, nc = max(1, int(round(gamma * M))), max(1, int(round(alpha * N)))
+    rows = np.zeros(iters, np.uint64)
+    cols = np.zeros(iters, np.uint64)
+    for t in range(iters):
+        for i in rng.choice(M, nr, replace=False):
+            rows[t] |= np.uint64(1) << np.uint64(i)
+        for j in rng.choice(N, nc, replace=False):
+            cols[t] |= np.uint64(1) << np.uint64(j)
+    return rows, cols

@@ -439,3 +439,184 @@ def test_multi_rhs_volume_of_identical_slices_is_2d():
     x2, _ = oracle.bsgd_tv(A, p.y, mu, lam, 3, 4000, (p.H, p.W))
     for j in range(3):
         assert np.max(np.abs(X3[j] - x2)) < 1e-6 * np.max(np.abs(x2))
+
+
+# --------------------------------------------------------------------------
+# Comparison methods (Simulations section, Fig. 2): ISTA and GD
+# --------------------------------------------------------------------------
+
+def test_gd_modal_closed_form():
+    """GD on f: each eigenmode of A^T A decays by (1 - 2 mu u) per iteration.
+
+    With x_0 = 0, V^T (x_k - x*) = (1 - 2 mu u)^k V^T (-x*), x* the
+    normal-equations solution (eigh and solve, not the oracle's products).
+    """
+    p, A = _tiny()
+    AtA = (A.T @ A).toarray()
+    u, V = np.linalg.eigh(AtA)
+    xstar = np.linalg.solve(AtA, A.T @ p.y)
+    mu = 0.9 / (2.0 * u[-1])
+    _, _, hist = oracle.gd(A, p.y, mu, 50, record=True)
+    c0 = V.T @ (-xstar)
+    for k in range(1, 51):
+        pred = (1.0 - 2.0 * mu * u) ** k * c0
+        assert np.max(np.abs(V.T @ (hist[k - 1] - xstar) - pred)) <= 1e-10 * np.linalg.norm(xstar)
+
+
+def test_ista_with_zero_lambda_is_gd_and_first_iterate_matches_bsgd():
+    p, A = _tiny()
+    mu = oracle.step_size(oracle.power_umax(A))
+    xa, _ = oracle.ista_tv(A, p.y, mu, 0.0, 7, 0, (p.H, p.W))
+    xb, _ = oracle.gd(A, p.y, mu, 7)
+    assert np.array_equal(xa, xb)
+    # from x = 0 both methods use r = y in their first step
+    x1, _ = oracle.ista_tv(A, p.y, mu, 40.0, 1, 20, (p.H, p.W))
+    x2, _ = oracle.bsgd_tv(A, p.y, mu, 40.0, 1, 20, (p.H, p.W))
+    assert np.array_equal(x1, x2)
+
+
+def test_ista_objective_decreases_with_converged_prox():
+    """With mu <= 1/L (L = 2 u_max) and an exact prox, F decreases at every ISTA step.
+
+    This is the sufficient-decrease property of the proximal gradient method
+    (Beck & Teboulle, SIAM J. Imaging Sci. 2(1), 2009, Lemma 2.3), which the
+    delayed method does not have.
+    """
+    p, A = _tiny(n=6, n_ang=10, bins=9)
+    mu = oracle.step_size(oracle.power_umax(A), 0.9)
+    lam = 2.0
+    _, _, hist = oracle.ista_tv(A, p.y, mu, lam, 25, 3000, (p.H, p.W), record=True)
+    F = [oracle.objective(A, p.y, np.zeros(p.ncols), lam, (p.H, p.W))]
+    F += [oracle.objective(A, p.y, h, lam, (p.H, p.W)) for h in hist]
+    assert all(F[k + 1] <= F[k] * (1 + 1e-12) for k in range(len(F) - 1))
+    assert F[-1] < 0.5 * F[0]
+
+
+def test_ista_and_bsgd_reach_the_same_minimiser():
+    """Both methods converge to the unique minimiser of F (Theorem 2 for BSGD).
+
+    Checked with a converged prox: the two limits agree, and the limit is a
+    fixed point of the proximal gradient map (the optimality condition of F).
+    """
+    p, A = _tiny(n=5, n_ang=8, bins=9)
+    mu = oracle.step_size(oracle.power_umax(A), 0.9)
+    lam, K, E = 1.0, 400, 300
+    xi, _ = oracle.ista_tv(A, p.y, mu, lam, E, K, (p.H, p.W))
+    xb, _ = oracle.bsgd_tv(A, p.y, mu, lam, E, K, (p.H, p.W))
+    scale = np.linalg.norm(xi)
+    assert np.linalg.norm(xi - xb) <= 1e-7 * scale
+    step = oracle.prox(xi + mu * oracle.backproject(A, p.y - oracle.forward(A, xi)),
+                       mu * lam, 20000, (p.H, p.W))
+    assert np.linalg.norm(step - xi) <= 1e-7 * scale
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1 on drawn block subsets (Simulations section, alpha and gamma)
+# --------------------------------------------------------------------------
+
+def test_block_subset_draws():
+    rm, cm = synth.block_subsets(400, 5, 8, 0.5, 0.4, seed=3)
+    assert all(bin(int(m)).count("1") == 2 for m in rm)
+    assert all(bin(int(m)).count("1") == 4 for m in cm)
+    assert all(int(m) < (1 << 5) for m in rm) and all(int(m) < (1 << 8) for m in cm)
+    hits = np.array([[(int(m) >> j) & 1 for j in range(8)] for m in cm]).mean(axis=0)
+    assert np.all(np.abs(hits - 0.5) < 0.1)       # uniform over the blocks
+    rm2, cm2 = synth.block_subsets(400, 5, 8, 0.5, 0.4, seed=3)
+    assert np.array_equal(rm, rm2) and np.array_equal(cm, cm2)
+    assert np.allclose(oracle.selected_epochs(rm, cm, 5, 8), np.arange(1, 401) * 8 / 40)
+    full_r, full_c = synth.block_subsets(3, 64, 64, 1.0, 1.0, seed=0)
+    assert all(int(m) == (1 << 64) - 1 for m in full_r) and all(int(m) == (1 << 64) - 1
+                                                                 for m in full_c)
+
+
+@pytest.mark.parametrize("M,N", [(1, 1), (2, 3)])
+def test_selected_with_every_block_is_algorithm1(M, N):
+    p, A = _tiny(n=8, n_ang=10, bins=13, M=M, N=N)
+    ro, co = synth.block_offsets(10, 13, p.ncols, M, N)
+    blocks = oracle.tiles(p.row_ptr, p.col, p.val, ro, co)
+    mu = oracle.step_size(oracle.power_umax(A))
+    x0 = synth.seeded_vector(p.ncols, 4)
+    all_r, all_c = [(1 << M) - 1] * 6, [(1 << N) - 1] * 6
+    x, r, _, hist = oracle.bsgd_selected(blocks, ro, co, p.y, mu, 30.0, 20, (p.H, p.W), all_r,
+                                         all_c, x0=x0, record=True)
+    _, _, ref = oracle.bsgd_tv(A, p.y, mu, 30.0, 6, 20, (p.H, p.W), x0=x0, record=True)
+    for a, b in zip(hist, ref):
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+
+
+def test_selected_column_subsets_converge_to_least_squares():
+    """All row blocks, half the column blocks per iteration, lam = 0.
+
+    A fixed point must zero A_{J_j}^T (y - A x) for every column block, so
+    the only limit is the least-squares solution (a library solve).
+    """
+    p, A = _tiny(n=5, n_ang=8, bins=9, M=2, N=2)
+    assert np.linalg.matrix_rank(A.toarray()) == p.ncols
+    xls = np.linalg.lstsq(A.toarray(), p.y, rcond=None)[0]
+    ro, co = synth.block_offsets(8, 9, p.ncols, 2, 2)
+    blocks = oracle.tiles(p.row_ptr, p.col, p.val, ro, co)
+    mu = oracle.step_size(oracle.power_umax(A))
+    rm, cm = synth.block_subsets(24000, 2, 2, 0.5, 1.0, seed=5)
+    x, _, _ = oracle.bsgd_selected(blocks, ro, co, p.y, mu, 0.0, 0, (p.H, p.W), rm, cm)
+    assert np.linalg.norm(x - xls) <= 1e-8 * np.linalg.norm(xls)
+
+
+def test_selected_row_subsets_converge_on_consistent_data():
+    """Half the row blocks per iteration, lam = 0, y = A x_true exactly.
+
+    With row subsets a fixed point must zero every (A_{I_i}^{J_j})^T r_{I_i}
+    separately, which only a consistent system allows; then the limit is
+    x_true (full column rank).  With noisy y the iterates stay in a
+    neighbourhood of the least-squares solution instead.
+    """
+    p, A = _tiny(n=5, n_ang=8, bins=9, M=2, N=2, noise=0.0)
+    assert np.linalg.matrix_rank(A.toarray()) == p.ncols
+    xt = p.x_true.ravel()
+    ro, co = synth.block_offsets(8, 9, p.ncols, 2, 2)
+    blocks = oracle.tiles(p.row_ptr, p.col, p.val, ro, co)
+    mu = oracle.step_size(oracle.power_umax(A))
+    rm, cm = synth.block_subsets(20000, 2, 2, 1.0, 0.5, seed=5)
+    x, _, _ = oracle.bsgd_selected(blocks, ro, co, p.y, mu, 0.0, 0, (p.H, p.W), rm, cm)
+    assert np.linalg.norm(x - xt) <= 1e-8 * np.linalg.norm(xt)
+    pn, An = _tiny(n=5, n_ang=8, bins=9, M=2, N=2, noise=0.05)
+    bn = oracle.tiles(pn.row_ptr, pn.col, pn.val, ro, co)
+    xls = np.linalg.lstsq(An.toarray(), pn.y, rcond=None)[0]
+    xn, _, _ = oracle.bsgd_selected(bn, ro, co, pn.y, mu, 0.0, 0, (pn.H, pn.W), rm[:6000],
+                                    cm[:6000])
+    err = np.linalg.norm(xn - xls) / np.linalg.norm(xls)
+    assert 1e-6 < err < 0.05
+
+
+def test_selected_leaves_unselected_blocks_and_rows():
+    """lam = 0: x outside the drawn column blocks and r outside the drawn row blocks stay put;
+    the kept products of the drawn pairs equal dense block products of the old x."""
+    p, A = _tiny(n=8, n_ang=12, bins=11, M=3, N=4)
+    ro, co = synth.block_offsets(12, 11, p.ncols, 3, 4)
+    blocks = oracle.tiles(p.row_ptr, p.col, p.val, ro, co)
+    D = A.toarray()
+    mu = oracle.step_size(oracle.power_umax(A))
+    x, r, Z = oracle.selected_initial_state(blocks, ro, co, p.y, synth.seeded_vector(p.ncols, 9))
+    rm, cm = synth.block_subsets(5, 3, 4, 0.5, 0.34, seed=8)
+    for t in range(5):
+        xn, rn, Zn = oracle.selected_iteration(blocks, ro, co, p.y, x, r, Z, mu, 0.0, 0,
+                                               (p.H, p.W), int(rm[t]), int(cm[t]))
+        I = oracle.mask_members(int(rm[t]), 3)
+        J = oracle.mask_members(int(cm[t]), 4)
+        for j in range(4):
+            sl = slice(int(co[j]), int(co[j + 1]))
+            if j in J:
+                g = sum(2.0 * D[int(ro[i]):int(ro[i + 1]), sl].T @ r[int(ro[i]):int(ro[i + 1])]
+                        for i in I)
+                assert np.allclose(xn[sl], x[sl] + mu * g, rtol=0, atol=1e-12)
+            else:
+                assert np.array_equal(xn[sl], x[sl])
+        for i in range(3):
+            rs = slice(int(ro[i]), int(ro[i + 1]))
+            if i in I:
+                for j in J:
+                    sl = slice(int(co[j]), int(co[j + 1]))
+                    assert np.allclose(Zn[j, rs], D[rs, sl] @ x[sl], rtol=0, atol=1e-12)
+                assert np.allclose(rn[rs], p.y[rs] - Zn[:, rs].sum(axis=0), rtol=0, atol=1e-12)
+            else:
+                assert np.array_equal(rn[rs], r[rs]) and np.array_equal(Zn[:, rs], Z[:, rs])
+        x, r, Z = xn, rn, Zn

@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -75,6 +76,14 @@ def main(argv=None):
     ap.add_argument("--path", default="fused", choices=["fused", "rows"],
                     help="epoch products: one pass over the tile-sliced store (fused) or one "
                          "pass over A and one over A^T (rows)")
+    ap.add_argument("--method", default="bsgd", choices=["bsgd", "ista", "gd", "selected"],
+                    help="update rule: Algorithm 1 (bsgd), the Simulations section's comparison "
+                         "methods (ista; gd = ista without the TV term), or Algorithm 1 on drawn "
+                         "block subsets (selected: fractions --alpha of the column blocks and "
+                         "--gamma of the row blocks per iteration; epochs normalised)")
+    ap.add_argument("--alpha", type=float, default=0.5)
+    ap.add_argument("--gamma", type=float, default=0.5)
+    ap.add_argument("--select-seed", type=int, default=7)
     ap.add_argument("--fused-chunks", type=int, default=0,
                     help="ray chunks of the tile-sliced store (0: automatic)")
     ap.add_argument("--fused-waves", type=int, default=8, choices=[2, 4, 8],
@@ -108,8 +117,10 @@ def main(argv=None):
                     help="serving: skip the one-request-at-a-time comparison run")
     args = ap.parse_args(argv)
 
+    if args.method != "bsgd":
+        args.path = "rows"   # the comparison methods run on the block store
     if args.staged is None:
-        args.staged = "none" if args.path == "fused" else "bwd"
+        args.staged = "none" if args.path == "fused" or args.method == "selected" else "bwd"
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on exactly one GPU "
               "(see the design notes for how the path would shard)", file=sys.stderr)
@@ -172,6 +183,38 @@ def main(argv=None):
         del p0
         print(f"[bench] autotuned launch {tuned}", file=sys.stderr, flush=True)
 
+    selected = args.method == "selected"
+    lam_run = 0.0 if args.method == "gd" else prob.lam
+    n_updates = epochs
+    if selected:
+        # enough iterations that the normalised epoch count reaches `epochs`
+        frac = (max(1, round(args.gamma * prob.M)) * max(1, round(args.alpha * prob.N))
+                / (prob.M * prob.N))
+        n_updates = int(math.ceil(epochs / frac - 1e-9))
+        rows_sel, cols_sel = synth.block_subsets(n_updates, prob.M, prob.N, args.alpha,
+                                                 args.gamma, args.select_seed)
+        epochs_norm = n_updates * frac
+    else:
+        epochs_norm = epochs
+
+    def make_state(plan, F):
+        st = bsgd.bsgd_state_create(plan, 1, vt,
+                                    flags=bsgd.BSGD_STATE_BLOCK_SELECT if selected else 0)
+        if F is not None:
+            bsgd.bsgd_state_attach_fused(st, F)
+        if args.method in ("ista", "gd"):
+            bsgd.bsgd_state_set_method(st, bsgd.BSGD_METHOD_ISTA)
+        bsgd.bsgd_state_set_overlap(st, args.overlap)
+        if args.prox_schedule is not None:
+            bsgd.bsgd_state_set_prox_schedule(st, args.prox_schedule)
+        return st
+
+    def run(st, mu):
+        if selected:
+            bsgd.bsgd_run_selected(st, mu, lam_run, rows_sel, cols_sel, K)
+        else:
+            bsgd.bsgd_run_epochs(st, mu, lam_run, epochs, K)
+
     fixed_mu = None
     if args.mu_file:
         with open(args.mu_file) as f:
@@ -195,16 +238,11 @@ def main(argv=None):
         if fused:
             F = bsgd.bsgd_fused_create(plan, args.fused_chunks)
             bsgd.bsgd_fused_set_waves(F, args.fused_waves)
-        st = bsgd.bsgd_state_create(plan, 1, vt)
-        if F is not None:
-            bsgd.bsgd_state_attach_fused(st, F)
-        bsgd.bsgd_state_set_overlap(st, args.overlap)
-        if args.prox_schedule is not None:
-            bsgd.bsgd_state_set_prox_schedule(st, args.prox_schedule)
+        st = make_state(plan, F)
         if record and timing:
-            bsgd.bsgd_state_enable_timing(st, epochs)
+            bsgd.bsgd_state_enable_timing(st, n_updates)
         bsgd.bsgd_state_init(st, y)
-        bsgd.bsgd_run_epochs(st, mu, prob.lam, epochs, K)
+        run(st, mu)
         x = bsgd.bsgd_get_x(st)
         if record and timing:
             f, b, p, n = bsgd.bsgd_state_timing(st)  # waits for this job's events
@@ -227,7 +265,7 @@ def main(argv=None):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = epochs * args.steps / (t1 - t0)
+    value = epochs_norm * args.steps / (t1 - t0)
 
     rn2, ep, _ = bsgd.bsgd_get_stats(st)
     xh = x.cpu().numpy().astype(np.float64)
@@ -235,30 +273,23 @@ def main(argv=None):
     rel_err_true = float(np.linalg.norm(xh - xt) / np.linalg.norm(xt))
 
     # epoch-only rate (no setup), for context
-    st2 = bsgd.bsgd_state_create(plan, 1, vt)
-    if F is not None:
-        bsgd.bsgd_state_attach_fused(st2, F)
-    bsgd.bsgd_state_set_overlap(st2, args.overlap)
-    if args.prox_schedule is not None:
-        bsgd.bsgd_state_set_prox_schedule(st2, args.prox_schedule)
+    st2 = make_state(plan, F)
     bsgd.bsgd_state_init(st2, y)
     torch.cuda.synchronize()
     te = time.perf_counter()
-    bsgd.bsgd_run_epochs(st2, mu, prob.lam, epochs, K)
+    run(st2, mu)
     torch.cuda.synchronize()
-    epoch_ms = (time.perf_counter() - te) * 1e3 / epochs
+    epoch_ms = (time.perf_counter() - te) * 1e3 / epochs_norm
 
-    if args.dump:
+    if args.dump and not selected:
         # untimed: the iterate every --dump-every epochs of one more job
-        st3 = bsgd.bsgd_state_create(plan, 1, vt)
-        if F is not None:
-            bsgd.bsgd_state_attach_fused(st3, F)
+        st3 = make_state(plan, F)
         bsgd.bsgd_state_init(st3, y)
         snaps = {}
         done = 0
         while done < epochs:
             n = min(args.dump_every, epochs - done)
-            bsgd.bsgd_run_epochs(st3, mu, prob.lam, n, K)
+            bsgd.bsgd_run_epochs(st3, mu, lam_run, n, K)
             done += n
             snaps[f"x{done}"] = bsgd.bsgd_get_x(st3).cpu().numpy()
         np.savez(args.dump, mu=np.float32(mu), **snaps)
@@ -302,9 +333,48 @@ def main(argv=None):
                       "column_bytes": cbytes,
                       "waves": args.fused_waves, "alg_bytes_pass": b_pass,
                       "alg_bytes_reduce": b_red}
+    sel_info = None
+    if selected:
+        M, N = prob.M, prob.N
+        tnnz = np.array([[bsgd.bsgd_tile_nnz(plan, i, j) for j in range(N)] for i in range(M)],
+                        np.int64)
+        rsz, csz = np.diff(prob.row_off), np.diff(prob.col_off)
+        bf = bb = 0
+        for rm_, cm_ in zip(rows_sel, cols_sel):
+            I = [i for i in range(M) if (int(rm_) >> i) & 1]
+            J = [j for j in range(N) if (int(cm_) >> j) & 1]
+            ent = int(tnnz[np.ix_(I, J)].sum())
+            nr_sel, nc_sel = int(rsz[I].sum()), int(csz[J].sum())
+            # forward: drawn entries (value + column); per drawn ray its pointer, segment
+            # bounds, block id, the N kept products (drawn ones written, others read), y and
+            # r'; other rays: block id, r read and written; x of the drawn column blocks once
+            bf += (val_bytes + 4) * ent + nr_sel * (8 + 4 * (N + 1) + 1 + 4 * N + 8) \
+                + (r - nr_sel) * 9 + 4 * nc_sel
+            # backward: drawn entries; per drawn pixel pointer, bounds, block id, x read, x^
+            # written; other pixels: block id, x read, x^ written; r of the drawn rows once
+            bb += (val_bytes + 4) * ent + nc_sel * (8 + 4 * (M + 1) + 1 + 8) \
+                + (c - nc_sel) * 9 + 4 * nr_sel
+        b_fwd, b_bwd = bf / n_updates, bb / n_updates
+        sel_info = {"alpha": args.alpha, "gamma": args.gamma, "iterations": n_updates,
+                    "normalised_epochs": round(epochs_norm, 3), "seed": args.select_seed,
+                    "alg_bytes_fwd_avg": round(b_fwd), "alg_bytes_bwd_avg": round(b_bwd)}
     roofline = None
     kernel = {}
-    if timing and acc["n"] and F is not None:
+    if timing and acc["n"] and selected:
+        f_ms = acc["fwd"] / acc["n"]
+        b_ms = acc["bwd"] / acc["n"]
+        p_ms = acc["prox"] / acc["n"]
+        kernel = {"fwd_ms": f_ms, "bwd_ms": b_ms, "prox_ms": p_ms,
+                  "fwd_gbs": b_fwd / f_ms / 1e6, "bwd_gbs": b_bwd / b_ms / 1e6}
+        dom_bytes, dom_ms, dom = (b_fwd, f_ms, "fwd") if f_ms >= b_ms else (b_bwd, b_ms, "bwd")
+        achieved = dom_bytes / dom_ms / 1e6
+        roofline = {"bound": "hbm",
+                    "kernel": ("k_sel_forward (drawn pairs, lines 4+6)" if dom == "fwd"
+                               else "k_sel_backward (drawn pairs, lines 3+7+8)"),
+                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "alg_bytes_per_launch": round(dom_bytes)}
+    elif timing and acc["n"] and F is not None:
         f_ms = acc["fwd"] / acc["n"]
         b_ms = acc["bwd"] / acc["n"]
         p_ms = acc["prox"] / acc["n"]
@@ -346,15 +416,29 @@ def main(argv=None):
         A64 = oracle.as_matrix(rp64, col64, val64, c)
         mu_cpu = 0.9 / (2.0 * oracle.power_umax(A64, tol=1e-6, max_iter=20))
         print(f"[bench] cpu baseline: {args.cpu_epochs} oracle epochs", file=sys.stderr, flush=True)
-        xc, rc = oracle.initial_state(A64, prob.y)
-        tc0 = time.perf_counter()
-        xc, rc = oracle.bsgd_tv(A64, prob.y, mu_cpu, prob.lam, args.cpu_epochs, K, (prob.H, prob.W),
-                                state=(xc, rc))
+        shape = (prob.H, prob.W)
+        cpu_epochs = float(args.cpu_epochs)
+        if selected:
+            blocks = oracle.tiles(rp64, col64, val64, prob.row_off, prob.col_off)
+            n_cpu = max(1, int(math.ceil(args.cpu_epochs / frac - 1e-9)))
+            st_c = oracle.selected_initial_state(blocks, prob.row_off, prob.col_off, prob.y)
+            tc0 = time.perf_counter()
+            oracle.bsgd_selected(blocks, prob.row_off, prob.col_off, prob.y, mu_cpu, lam_run, K,
+                                 shape, rows_sel[:n_cpu], cols_sel[:n_cpu], state=st_c)
+            cpu_epochs = n_cpu * frac
+        elif args.method in ("ista", "gd"):
+            tc0 = time.perf_counter()
+            oracle.ista_tv(A64, prob.y, mu_cpu, lam_run, args.cpu_epochs, K, shape)
+        else:
+            xc, rc = oracle.initial_state(A64, prob.y)
+            tc0 = time.perf_counter()
+            xc, rc = oracle.bsgd_tv(A64, prob.y, mu_cpu, prob.lam, args.cpu_epochs, K, shape,
+                                    state=(xc, rc))
         tcs = time.perf_counter() - tc0
-        cpu = {"value": round(args.cpu_epochs / tcs, 4), "unit": "epochs/s", "cores": 1,
+        cpu = {"value": round(cpu_epochs / tcs, 4), "unit": "epochs/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"{args.cpu_epochs} epochs of {args.config} (FP64 numpy/scipy, single "
-                         f"thread, setup excluded) in {tcs:.1f} s"}
+               "sample": f"{cpu_epochs:g} epochs of {args.config} ({args.method}; FP64 "
+                         f"numpy/scipy, single thread, setup excluded) in {tcs:.1f} s"}
 
     out = {
         "metric": "BSGD-TV epochs/s + HBM GB/s vs peak; served recon p50/p99 latency",
@@ -371,8 +455,9 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": f"{args.config}: one reconstruction job per step ({prob.H}x{prob.W} "
                                f"image, {prob.n_ang} angles x {prob.bins} bins, M=N={prob.M}, "
-                               f"lambda={prob.lam}, {epochs} epochs, {K} FGP iterations, "
+                               f"lambda={lam_run}, {epochs} epochs, {K} FGP iterations, "
                                f"setup S0+S0' included)",
+                   "method": args.method,
                    "nnz": nnz, "epochs_per_step": epochs,
                    "path": args.path,
                    "lanes_per_row": list(bsgd.bsgd_plan_lanes(plan)), "overlap": args.overlap,
@@ -388,6 +473,7 @@ def main(argv=None):
         "kernels": {k: round(v, 4) for k, v in kernel.items()},
         "staged": staged_info,
         "fused": fused_info,
+        "selected": sel_info,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "quality": {"res_norm2": rn2, "rel_err_vs_phantom": round(rel_err_true, 5)},

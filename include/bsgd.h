@@ -290,6 +290,13 @@ bsgd_status bsgd_lanczos_umax(const bsgd_plan* plan, bsgd_valtype vt, int steps,
  *     the isotropic 3-D TV across them (needs a 2-D plan, D = 1).
  */
 #define BSGD_STATE_VOLUME 1u
+/*
+ * BSGD_STATE_BLOCK_SELECT: the state can also run iterations in which only
+ * drawn subsets of the row and column blocks take part (bsgd_run_selected).
+ * It adds one kept product z^j_{I_i} per (ray, column block), N x r floats,
+ * to the workspace.  Needs nrhs = 1 and at most 64 row and column blocks.
+ */
+#define BSGD_STATE_BLOCK_SELECT 2u
 
 /* Workspace bytes of a state. */
 bsgd_status bsgd_state_workspace_size(const bsgd_plan* plan, int nrhs, unsigned flags,
@@ -309,7 +316,9 @@ void bsgd_state_destroy(bsgd_state* state);
  * Start a reconstruction: copy y (device, r x nrhs floats); x = x0 (device,
  * c x nrhs floats) or 0 when x0 == NULL; r = y - A x0 (r = y when x0 ==
  * NULL), the initialisation that Algorithm 1 leaves open.  Resets the epoch
- * count and the per-RHS lambdas (to 0).
+ * count and the per-RHS lambdas (to 0).  With BSGD_STATE_BLOCK_SELECT the
+ * kept products become the block products of x0 (0 when x0 == NULL) and r
+ * their residual y - sum_j z^j.
  */
 bsgd_status bsgd_state_init(bsgd_state* state, const float* y, const float* x0, hipStream_t stream);
 
@@ -317,6 +326,7 @@ bsgd_status bsgd_state_init(bsgd_state* state, const float* y, const float* x0, 
  * Resume from a saved state: x (device, c floats), r (device, r floats, the
  * residual y - A x_prev of the previous epoch; Eq. 3 makes it part of the
  * state) and the epoch count.  y must have been set by bsgd_state_init.
+ * With BSGD_STATE_BLOCK_SELECT the kept products are recomputed from x.
  */
 bsgd_status bsgd_state_load(bsgd_state* state, const float* x, const float* r, int64_t epoch,
                             hipStream_t stream);
@@ -334,6 +344,46 @@ bsgd_status bsgd_state_load(bsgd_state* state, const float* x, const float* r, i
  */
 bsgd_status bsgd_run_epochs(bsgd_state* state, float mu, float lam, int epochs, int prox_iters,
                             hipStream_t stream);
+
+/*
+ * Update rule of bsgd_run_epochs (the Simulations section compares
+ * BSGD-TV with ISTA and with gradient descent, Fig. 2):
+ *   BSGD_METHOD_BSGD (default): Algorithm 1 as above; line 3 uses the
+ *     residual of the previous iterate (Eq. 3), so both products read x and
+ *     r of the epoch's start.
+ *   BSGD_METHOD_ISTA: r = y - A x, then x = FGP(x + 2 mu A^T r): the
+ *     gradient of the current iterate (no delay), so the backprojection
+ *     waits for the forward pass.  lam = 0 gives gradient descent on
+ *     ||y - A x||^2 (Fig. 2's GD).
+ * Both keep r = y - A x of the iterate before the current one, so the
+ * methods can alternate on one state.  The ISTA epoch runs on the block
+ * store (an attached single-pass store serves only BSGD epochs).
+ */
+#define BSGD_METHOD_BSGD 0
+#define BSGD_METHOD_ISTA 1
+bsgd_status bsgd_state_set_method(bsgd_state* state, int method);
+
+/*
+ * `iters` iterations of Algorithm 1 in which only drawn blocks take part
+ * (Simulations section: fractions gamma of {y_{I_i}} and alpha of
+ * {x_{J_j}} per iteration).  Iteration t runs the pairs (i, j) with bit i
+ * of rows_sel[t] and bit j of cols_sel[t] set (host arrays of iters masks,
+ * each non-zero and within M resp. N bits; the caller draws them):
+ *   lines 3, 7, 8: x_{J_j} += 2 mu sum over drawn i of (A_{I_i}^{J_j})^T
+ *     r_{I_i} for drawn j (kept r, no rescaling); other blocks of x stay;
+ *   line 4: z^j_{I_i} = A_{I_i}^{J_j} x_{J_j} for drawn pairs, kept;
+ *   line 6: r_{I_i} = y_{I_i} - sum over all j of the kept z^j_{I_i}
+ *     (ascending j) for drawn i; other rows keep r;
+ *   line 9: the prox of the whole image with theta = mu * lam.
+ * With every bit set an iteration is an epoch of Algorithm 1 (up to
+ * rounding).  Needs a state created with BSGD_STATE_BLOCK_SELECT; counts
+ * iterations in bsgd_get_stats.  The epoch of the Simulations section is
+ * the sum over iterations of the fraction of pairs drawn.  Enqueued on
+ * `stream`, no allocation and no synchronisation.
+ */
+bsgd_status bsgd_run_selected(bsgd_state* state, float mu, float lam, int iters, int prox_iters,
+                              const uint64_t* rows_sel, const uint64_t* cols_sel,
+                              hipStream_t stream);
 
 /*
  * Epoch schedule.  The forward pass (lines 4, 6) does not depend on the
@@ -374,7 +424,7 @@ bsgd_status bsgd_get_stats(const bsgd_state* state, hipStream_t stream, double* 
 /*
  * Kernel timers (measurement).  After bsgd_state_enable_timing(state,
  * max_epochs), each of the next max_epochs epochs run by bsgd_run_epochs
- * records HIP events (on the stream each kernel runs on) around its forward
+ * (or iterations run by bsgd_run_selected) records HIP events (on the stream each kernel runs on) around its forward
  * pass (lines 4 and 6), its backprojection pass (lines 3, 7, 8) and its prox
  * (line 9).  bsgd_state_timing synchronises, returns the summed durations in
  * milliseconds and the number of timed epochs, and rearms the timers.

@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbsgd.so")
@@ -33,6 +34,9 @@ BSGD_PLAN_STAGED_BWD = 8
 BSGD_PLAN_STAGED = 12
 BSGD_LAUNCH_NT = 128
 BSGD_STATE_VOLUME = 1
+BSGD_STATE_BLOCK_SELECT = 2
+BSGD_METHOD_BSGD = 0
+BSGD_METHOD_ISTA = 1
 BSGD_FUSED_WIDE = 1
 
 _STATUS = {0: "OK", -1: "INVALID", -2: "WORKSPACE", -3: "HIP", -4: "UNSUPPORTED", -5: "DIVERGED"}
@@ -107,6 +111,9 @@ _PROTOS = {
     "bsgd_fused_partials_size": [_vp, ctypes.POINTER(_sz)],
     "bsgd_fused_apply": [_vp, _i32, _vp, _vp, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp],
     "bsgd_state_attach_fused": [_vp, _vp, _vp, _sz],
+    "bsgd_state_set_method": [_vp, _i32],
+    "bsgd_run_selected": [_vp, _f32, _f32, _i32, _i32, ctypes.POINTER(ctypes.c_uint64),
+                          ctypes.POINTER(ctypes.c_uint64), _vp],
 }
 for _name, _args in _PROTOS.items():
     _f = getattr(_lib, _name)
@@ -494,6 +501,23 @@ def bsgd_state_timing(state: State):
     _check("bsgd_state_timing", _lib.bsgd_state_timing(state.handle, ctypes.byref(f), ctypes.byref(b),
                                                        ctypes.byref(x), ctypes.byref(n)))
     return f.value, b.value, x.value, n.value
+
+
+def bsgd_state_set_method(state: State, method: int):
+    """BSGD_METHOD_BSGD (Algorithm 1, delayed residual) or BSGD_METHOD_ISTA (no delay)."""
+    _check("bsgd_state_set_method", _lib.bsgd_state_set_method(state.handle, int(method)))
+
+
+def bsgd_run_selected(state: State, mu, lam, rows_sel, cols_sel, prox_iters, stream=None):
+    """Iterations over drawn block subsets: rows_sel[t], cols_sel[t] are bit masks."""
+    rows = np.ascontiguousarray(np.asarray(rows_sel, dtype=np.uint64))
+    cols = np.ascontiguousarray(np.asarray(cols_sel, dtype=np.uint64))
+    if rows.shape != cols.shape or rows.ndim != 1:
+        raise ValueError("rows_sel and cols_sel must be 1-D arrays of equal length")
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    _check("bsgd_run_selected", _lib.bsgd_run_selected(
+        state.handle, float(mu), float(lam), int(rows.size), int(prox_iters),
+        rows.ctypes.data_as(u64p), cols.ctypes.data_as(u64p), _stream(stream)))
 
 
 def bsgd_state_set_overlap(state: State, mode: int):

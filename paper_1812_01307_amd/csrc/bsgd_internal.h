@@ -247,6 +247,22 @@ hipError_t launch_segment_rows(const bsgd_plan* p, bool fwd, bsgd_valtype vt, in
                                int64_t nrows, int segk, int64_t col_base, const float* v,
                                float scale, float* out, hipStream_t s);
 
+// Iterations over drawn block subsets (bit masks of at most kMaxSelBlocks
+// row and column blocks).  blk_r / blk_c: block of each internal ray /
+// pixel (0xFF for holes).  Forward: for rays of drawn row blocks, Z[j *
+// r_int + ray] = segment-j product for drawn j, r_out = y - sum_j Z[j]
+// (ascending j, all blocks); other rays copy r_in.  Backward: for pixels of
+// drawn column blocks, out = xadd + scale * (sum of the drawn row blocks'
+// segments . r); other pixels copy xadd.
+constexpr int kMaxSelBlocks = 64;
+hipError_t launch_block_ids(const bsgd_plan* p, uint8_t* blk_r, uint8_t* blk_c, hipStream_t s);
+hipError_t launch_sel_forward(const Store& st, bsgd_valtype vt, const uint8_t* blk,
+                              uint64_t rows, uint64_t cols, const float* x, const float* y,
+                              const float* r_in, float* r_out, float* Z, hipStream_t s);
+hipError_t launch_sel_backward(const Store& st, bsgd_valtype vt, const uint8_t* blk,
+                               uint64_t rows, uint64_t cols, const float* r, const float* xadd,
+                               float scale, float* out, hipStream_t s);
+
 // Natural <-> internal vector orders (holes are written as 0).  With S > 1
 // the vectors are [rows][S] matrices (RHS fastest) and whole rows move.
 enum VecKind { kPixels = 0, kRays = 1 };

@@ -258,6 +258,161 @@ hipError_t launch_segment_rows(const bsgd_plan* p, bool fwd, bsgd_valtype vt, in
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Iterations over drawn block subsets (Simulations section: fractions gamma
+// of the row blocks and alpha of the column blocks take part).  A row of a
+// store lists its entries block by block (segment k = block k), so a drawn
+// subset is a choice of segments: the kernels read only the drawn segments
+// of the drawn rows.  Block sets are bit masks (at most 64 blocks a side).
+// ---------------------------------------------------------------------------
+struct BlockBounds {
+  int64_t v[kMaxSelBlocks + 1];
+  int n;
+};
+
+// One matrix value as FP32, non-temporal load (FP16 values load as bits).
+template <typename VT>
+__device__ __forceinline__ float ld_val(const VT* p) {
+  if constexpr (sizeof(VT) == 4)
+    return ld<true>(reinterpret_cast<const float*>(p));
+  else
+    return __half2float(
+        __ushort_as_half(ld<true>(reinterpret_cast<const unsigned short*>(p))));
+}
+
+// id[k] = block of internal row k (0xFF for a hole of the internal order).
+template <bool RAYS>
+__global__ __launch_bounds__(256) void k_block_ids(Layout L, BlockBounds b, uint8_t* __restrict__ id,
+                                                   int64_t n) {
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * 256) {
+    const int64_t nat = RAYS ? L.ray_out(k) : L.pix_out(k);
+    int blk = 0;
+#pragma unroll
+    for (int q = 1; q < kMaxSelBlocks; ++q) blk += (q < b.n && nat >= b.v[q]) ? 1 : 0;
+    id[k] = nat < 0 ? (uint8_t)0xFF : (uint8_t)blk;
+  }
+}
+
+// Lines 4 and 6 for the drawn pairs.  A ray of a drawn row block computes
+// z^j (its segment j) for every drawn column block j and keeps it in
+// Z[j * nrows + ray]; its residual becomes y - sum_j Z[j] over all column
+// blocks, ascending j (kept products for the others).  Other rays copy
+// r_in to r_out.
+template <typename VT, int LPR>
+__global__ __launch_bounds__(256) void k_sel_forward(
+    const int64_t* __restrict__ ptr, const int32_t* __restrict__ seg, int nseg,
+    const int32_t* __restrict__ col, const VT* __restrict__ val, const uint8_t* __restrict__ blk,
+    uint64_t rows, uint64_t cols, const float* __restrict__ x, const float* __restrict__ y,
+    const float* __restrict__ r_in, float* __restrict__ r_out, float* __restrict__ Z,
+    int64_t nrows) {
+  const int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  if (row >= nrows) return;  // uniform over the lane group
+  const unsigned b = blk[row];
+  if (b == 0xFFu || !((rows >> b) & 1)) {
+    if (lane == 0) r_out[row] = r_in[row];
+    return;
+  }
+  const int64_t base = ptr[row];
+  const int32_t* sg = seg + row * (nseg + 1);
+  float tot = 0.f;
+  for (int j = 0; j < nseg; ++j) {
+    float zj;
+    if ((cols >> j) & 1) {
+      float acc = 0.f;
+      const int64_t end = base + sg[j + 1];
+      for (int64_t e = base + sg[j] + lane; e < end; e += LPR)
+        acc = fmaf(ld_val(val + e), x[ld<true>(col + e)], acc);
+      zj = group_sum<LPR>(acc);
+      if (lane == 0) Z[j * nrows + row] = zj;
+    } else {
+      zj = Z[j * nrows + row];
+    }
+    tot += zj;
+  }
+  if (lane == 0) r_out[row] = y[row] - tot;
+}
+
+// Lines 3, 7 and 8 for the drawn pairs.  A pixel of a drawn column block
+// sums its segments i (rows of A^T restricted to I_i) over the drawn row
+// blocks: out = xadd + scale * sum; other pixels copy xadd.
+template <typename VT, int LPR>
+__global__ __launch_bounds__(256) void k_sel_backward(
+    const int64_t* __restrict__ ptr, const int32_t* __restrict__ seg, int nseg,
+    const int32_t* __restrict__ col, const VT* __restrict__ val, const uint8_t* __restrict__ blk,
+    uint64_t rows, uint64_t cols, const float* __restrict__ r, const float* __restrict__ xadd,
+    float scale, float* __restrict__ out, int64_t nrows) {
+  const int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPR;
+  const int lane = threadIdx.x & (LPR - 1);
+  if (row >= nrows) return;  // uniform over the lane group
+  const unsigned b = blk[row];
+  if (b == 0xFFu || !((cols >> b) & 1)) {
+    if (lane == 0) out[row] = xadd[row];
+    return;
+  }
+  const int64_t base = ptr[row];
+  const int32_t* sg = seg + row * (nseg + 1);
+  float acc = 0.f;
+  for (int i = 0; i < nseg; ++i) {
+    if (!((rows >> i) & 1)) continue;
+    const int64_t end = base + sg[i + 1];
+    for (int64_t e = base + sg[i] + lane; e < end; e += LPR)
+      acc = fmaf(ld_val(val + e), r[ld<true>(col + e)], acc);
+  }
+  acc = group_sum<LPR>(acc);
+  if (lane == 0) out[row] = fmaf(scale, acc, xadd[row]);
+}
+
+static BlockBounds block_bounds(const std::vector<int64_t>& off) {
+  BlockBounds b{};
+  b.n = (int)off.size() - 1;
+  for (size_t k = 0; k < off.size() && k <= (size_t)kMaxSelBlocks; ++k) b.v[k] = off[k];
+  return b;
+}
+
+hipError_t launch_block_ids(const bsgd_plan* p, uint8_t* blk_r, uint8_t* blk_c, hipStream_t s) {
+  const Layout& L = p->L;
+  k_block_ids<true><<<1024, 256, 0, s>>>(L, block_bounds(p->row_off), blk_r, L.r_int);
+  k_block_ids<false><<<1024, 256, 0, s>>>(L, block_bounds(p->col_off), blk_c, L.c_int);
+  return hipGetLastError();
+}
+
+constexpr int kSelLanes = 8;
+
+hipError_t launch_sel_forward(const Store& st, bsgd_valtype vt, const uint8_t* blk,
+                              uint64_t rows, uint64_t cols, const float* x, const float* y,
+                              const float* r_in, float* r_out, float* Z, hipStream_t s) {
+  const unsigned blocks = (unsigned)((st.nrows * kSelLanes + 255) / 256);
+  if (!blocks) return hipSuccess;
+  if (vt == BSGD_VAL_F16)
+    k_sel_forward<__half, kSelLanes><<<blocks, 256, 0, s>>>(
+        st.ptr, st.seg, st.nseg, st.col, st.val16, blk, rows, cols, x, y, r_in, r_out, Z,
+        st.nrows);
+  else
+    k_sel_forward<float, kSelLanes><<<blocks, 256, 0, s>>>(
+        st.ptr, st.seg, st.nseg, st.col, st.val, blk, rows, cols, x, y, r_in, r_out, Z,
+        st.nrows);
+  return hipGetLastError();
+}
+
+hipError_t launch_sel_backward(const Store& st, bsgd_valtype vt, const uint8_t* blk,
+                               uint64_t rows, uint64_t cols, const float* r, const float* xadd,
+                               float scale, float* out, hipStream_t s) {
+  const unsigned blocks = (unsigned)((st.nrows * kSelLanes + 255) / 256);
+  if (!blocks) return hipSuccess;
+  if (vt == BSGD_VAL_F16)
+    k_sel_backward<__half, kSelLanes><<<blocks, 256, 0, s>>>(
+        st.ptr, st.seg, st.nseg, st.col, st.val16, blk, rows, cols, r, xadd, scale, out,
+        st.nrows);
+  else
+    k_sel_backward<float, kSelLanes><<<blocks, 256, 0, s>>>(
+        st.ptr, st.seg, st.nseg, st.col, st.val, blk, rows, cols, r, xadd, scale, out,
+        st.nrows);
+  return hipGetLastError();
+}
+
 }  // namespace bsgd
 
 // ---------------------------------------------------------------------------

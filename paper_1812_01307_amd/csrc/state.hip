@@ -36,6 +36,10 @@ struct bsgd_state {
   int cur = 0;
   int overlap = 1;  // 0: forward pass concurrent with backprojection + prox; 1: with the prox only
   int prox_schedule = bsgd::kFgpFused;  // 2-D prox: fused chunks or one launch per iteration
+  int method = BSGD_METHOD_BSGD;        // update rule of bsgd_run_epochs
+  float* zt = nullptr;                  // BSGD_STATE_BLOCK_SELECT: kept products, [N][r_int]
+  uint8_t* blk_r = nullptr;             // ... row block of each internal ray (0xFF: hole)
+  uint8_t* blk_c = nullptr;             // ... column block of each internal pixel
   int64_t epochs_done = 0;
   bool initialised = false;
   hipStream_t aux = nullptr;
@@ -148,6 +152,11 @@ static size_t state_layout(const bsgd_plan* p, int S, unsigned flags, void* ws, 
   st->tmp_c = cv.take<float>(p->L.c_int);
   if (S == 1 && p->sfwd.P > 0) st->zf = cv.take<float>((size_t)p->sfwd.P * p->L.r_int);
   if (S == 1 && p->sbwd.P > 0) st->zb = cv.take<float>((size_t)p->sbwd.P * p->L.c_int);
+  if (flags & BSGD_STATE_BLOCK_SELECT) {
+    st->zt = cv.take<float>((size_t)p->N * p->L.r_int);
+    st->blk_r = cv.take<uint8_t>(p->L.r_int);
+    st->blk_c = cv.take<uint8_t>(p->L.c_int);
+  }
   return align_up(cv.off, kAlign);
 }
 
@@ -278,9 +287,14 @@ extern "C" bsgd_status bsgd_state_workspace_size(const bsgd_plan* plan, int nrhs
   clear_error();
   BSGD_REQUIRE(plan && bytes, "NULL argument");
   BSGD_REQUIRE(valid_nrhs(nrhs), "nrhs must be 1 or a power of two from 4 to 1024");
-  BSGD_REQUIRE((flags & ~BSGD_STATE_VOLUME) == 0, "unknown state flags 0x%x", flags);
+  BSGD_REQUIRE((flags & ~(BSGD_STATE_VOLUME | BSGD_STATE_BLOCK_SELECT)) == 0,
+               "unknown state flags 0x%x", flags);
   BSGD_REQUIRE(!(flags & BSGD_STATE_VOLUME) || (nrhs > 1 && plan->D == 1),
                "a volume state needs nrhs > 1 slices and a 2-D plan");
+  BSGD_REQUIRE(!(flags & BSGD_STATE_BLOCK_SELECT) ||
+                   (nrhs == 1 && plan->M <= kMaxSelBlocks && plan->N <= kMaxSelBlocks),
+               "block selection needs nrhs = 1 and at most %d row and column blocks",
+               kMaxSelBlocks);
   bsgd_state tmp;
   *bytes = state_layout(plan, nrhs, flags, nullptr, &tmp);
   return BSGD_OK;
@@ -362,6 +376,14 @@ extern "C" bsgd_status bsgd_state_init(bsgd_state* st, const float* y, const flo
     BSGD_HIP(fill_f32(st->x[0], c, 0.0f, stream));
     BSGD_HIP(hipMemcpyAsync(st->r[0], st->y, sizeof(float) * r, hipMemcpyDeviceToDevice, stream));
   }
+  if (st->zt) {
+    BSGD_HIP(launch_block_ids(p, st->blk_r, st->blk_c, stream));
+    if (x0)  // kept products of x0 and their residual
+      BSGD_HIP(launch_sel_forward(p->fwd, st->vt, st->blk_r, ~0ull, ~0ull, st->x[0], st->y,
+                                  st->r[0], st->r[0], st->zt, stream));
+    else
+      BSGD_HIP(fill_f32(st->zt, (int64_t)p->N * p->L.r_int, 0.0f, stream));
+  }
   st->epochs_done = 0;
   st->initialised = true;
   return BSGD_OK;
@@ -377,8 +399,49 @@ extern "C" bsgd_status bsgd_state_load(bsgd_state* st, const float* x, const flo
   st->cur = 0;
   BSGD_HIP(permute_in(p->L, kPixels, x, st->x[0], stream, st->nrhs));
   BSGD_HIP(permute_in(p->L, kRays, r, st->r[0], stream, st->nrhs));
+  if (st->zt)  // kept products of the loaded x (their residual goes to scratch)
+    BSGD_HIP(launch_sel_forward(p->fwd, st->vt, st->blk_r, ~0ull, ~0ull, st->x[0], st->y,
+                                st->r[0], st->tmp_r, st->zt, stream));
   st->epochs_done = epoch;
   return BSGD_OK;
+}
+
+// Lines 4 + 6 (out = y - A x) and lines 3 + 7 + 8 (out = xadd + scale A^T r)
+// over the block store, in the state's launch form (staged, row kernel, or
+// the several-RHS product), and line 9 into `out`.
+static hipError_t forward_residual(const bsgd_state* st, const float* x, float* out,
+                                   hipStream_t s) {
+  const bsgd_plan* p = st->plan;
+  const int S = st->nrhs;
+  if (S == 1 && p->sfwd.lanes && st->zf)
+    return launch_staged(p->sfwd, st->vt, kResidual, x, p->L.c_int, st->y, nullptr, 1.0f, out,
+                         st->zf, s);
+  if (S == 1) return launch_rows(p->fwd, st->vt, kResidual, x, st->y, nullptr, 1.0f, out, s);
+  return launch_spmm(p->fwd, st->vt, kResidual, x, st->y, nullptr, 1.0f, out, S, s);
+}
+
+static hipError_t backward_step(const bsgd_state* st, const float* r, const float* xadd,
+                                float scale, float* out, hipStream_t s) {
+  const bsgd_plan* p = st->plan;
+  const int S = st->nrhs;
+  if (S == 1 && p->sbwd.lanes && st->zb)
+    return launch_staged(p->sbwd, st->vt, kStep, r, p->L.r_int, nullptr, xadd, scale, out,
+                         st->zb, s);
+  if (S == 1) return launch_rows(p->bwd, st->vt, kStep, r, nullptr, xadd, scale, out, s);
+  return launch_spmm(p->bwd, st->vt, kStep, r, nullptr, xadd, scale, out, S, s);
+}
+
+static hipError_t prox_step(const bsgd_state* st, float mu, float lam, bool per_rhs,
+                            int prox_iters, float* out, hipStream_t s) {
+  const bsgd_plan* p = st->plan;
+  const int S = st->nrhs;
+  if (S == 1)
+    return tv_prox_run(p->L, true, st->xhat, mu * lam, prox_iters, out, st->tv_ws, s,
+                       st->prox_schedule);
+  if (st->flags & BSGD_STATE_VOLUME)
+    return tv_prox_volume(p->L, S, st->xhat, mu * lam, prox_iters, out, st->tv_ws, s);
+  return tv_prox_batch(p->L, S, st->xhat, mu, per_rhs ? st->lam : nullptr, lam, prox_iters, out,
+                       st->tv_ws, s, st->prox_schedule);
 }
 
 extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int epochs,
@@ -403,6 +466,21 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
     // `stream` before this epoch (overlap 0) or after S2 (overlap 1), or on
     // `stream` after the prox (overlap 2: no concurrency)
     float* step_out = theta == 0.f ? st->x[n] : st->xhat;
+    if (st->method == BSGD_METHOD_ISTA) {
+      // r' = y - A x, then x^ = x + 2 mu A^T r' (current gradient), then
+      // line 9; in order on `stream`
+      if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
+      BSGD_HIP(forward_residual(st, st->x[c], st->r[n], stream));
+      if (tv) BSGD_HIP(hipEventRecord(tv[1], stream));
+      if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
+      BSGD_HIP(backward_step(st, st->r[n], st->x[c], 2.0f * mu, step_out, stream));
+      if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
+      if (theta != 0.f) BSGD_HIP(prox_step(st, mu, lam, per_rhs, prox_iters, st->x[n], stream));
+      if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));
+      st->cur = n;
+      st->epochs_done++;
+      continue;
+    }
     if (st->fz) {
       // single pass over the tile-sliced store (lines 3-4 together), then the
       // reduce (lines 6-8), then the prox (line 9), in order on `stream`.
@@ -428,29 +506,13 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
     }
     if (st->overlap == 0) BSGD_HIP(hipEventRecord(st->ev_main, stream));
     if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
-    if (S == 1 && p->sbwd.lanes && st->zb)
-      BSGD_HIP(launch_staged(p->sbwd, st->vt, kStep, st->r[c], p->L.r_int, nullptr, st->x[c],
-                             2.0f * mu, step_out, st->zb, stream));
-    else if (S == 1)
-      BSGD_HIP(launch_rows(p->bwd, st->vt, kStep, st->r[c], nullptr, st->x[c], 2.0f * mu,
-                           step_out, stream));
-    else
-      BSGD_HIP(launch_spmm(p->bwd, st->vt, kStep, st->r[c], nullptr, st->x[c], 2.0f * mu,
-                           step_out, S, stream));
+    BSGD_HIP(backward_step(st, st->r[c], st->x[c], 2.0f * mu, step_out, stream));
     if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
     if (st->overlap == 1) BSGD_HIP(hipEventRecord(st->ev_main, stream));
     hipStream_t fs = st->overlap == 2 ? stream : st->aux;
     auto forward = [&]() -> bsgd_status {
       if (tv) BSGD_HIP(hipEventRecord(tv[0], fs));
-      if (S == 1 && p->sfwd.lanes && st->zf)
-        BSGD_HIP(launch_staged(p->sfwd, st->vt, kResidual, st->x[c], p->L.c_int, st->y, nullptr,
-                               1.0f, st->r[n], st->zf, fs));
-      else if (S == 1)
-        BSGD_HIP(launch_rows(p->fwd, st->vt, kResidual, st->x[c], st->y, nullptr, 1.0f,
-                             st->r[n], fs));
-      else
-        BSGD_HIP(launch_spmm(p->fwd, st->vt, kResidual, st->x[c], st->y, nullptr, 1.0f,
-                             st->r[n], S, fs));
+      BSGD_HIP(forward_residual(st, st->x[c], st->r[n], fs));
       if (tv) BSGD_HIP(hipEventRecord(tv[1], fs));
       return BSGD_OK;
     };
@@ -461,17 +523,7 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
       BSGD_HIP(hipEventRecord(st->ev_aux, st->aux));
     }
     // S5 on `stream`
-    if (theta != 0.f) {
-      if (S == 1)
-        BSGD_HIP(tv_prox_run(p->L, true, st->xhat, theta, prox_iters, st->x[n], st->tv_ws,
-                             stream, st->prox_schedule));
-      else if (st->flags & BSGD_STATE_VOLUME)
-        BSGD_HIP(tv_prox_volume(p->L, S, st->xhat, theta, prox_iters, st->x[n], st->tv_ws,
-                                stream));
-      else
-        BSGD_HIP(tv_prox_batch(p->L, S, st->xhat, mu, per_rhs ? st->lam : nullptr, lam,
-                               prox_iters, st->x[n], st->tv_ws, stream, st->prox_schedule));
-    }
+    if (theta != 0.f) BSGD_HIP(prox_step(st, mu, lam, per_rhs, prox_iters, st->x[n], stream));
     if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));
     if (st->overlap == 2) {
       bsgd_status fst = forward();
@@ -566,6 +618,60 @@ extern "C" bsgd_status bsgd_state_set_overlap(bsgd_state* st, int mode) {
   BSGD_REQUIRE(st != nullptr, "state is NULL");
   BSGD_REQUIRE(mode >= 0 && mode <= 2, "overlap mode must be 0, 1 or 2");
   st->overlap = mode;
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_state_set_method(bsgd_state* st, int method) {
+  clear_error();
+  BSGD_REQUIRE(st != nullptr, "state is NULL");
+  BSGD_REQUIRE(method == BSGD_METHOD_BSGD || method == BSGD_METHOD_ISTA,
+               "method must be BSGD_METHOD_BSGD (0) or BSGD_METHOD_ISTA (1)");
+  st->method = method;
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_run_selected(bsgd_state* st, float mu, float lam, int iters,
+                                         int prox_iters, const uint64_t* rows_sel,
+                                         const uint64_t* cols_sel, hipStream_t stream) {
+  clear_error();
+  BSGD_REQUIRE(st != nullptr, "state is NULL");
+  BSGD_REQUIRE(st->initialised, "state_init must be called first");
+  BSGD_REQUIRE(st->zt != nullptr, "the state was created without BSGD_STATE_BLOCK_SELECT");
+  BSGD_REQUIRE(std::isfinite(mu) && mu > 0.f, "mu must be finite and > 0");
+  BSGD_REQUIRE(std::isfinite(lam) && lam >= 0.f, "lam must be finite and >= 0");
+  BSGD_REQUIRE(iters >= 0, "iters must be >= 0");
+  BSGD_REQUIRE(lam == 0.f || prox_iters >= 1, "prox_iters must be >= 1 when lam != 0");
+  BSGD_REQUIRE(iters == 0 || (rows_sel && cols_sel), "NULL block masks");
+  const bsgd_plan* p = st->plan;
+  const uint64_t row_bits = p->M == 64 ? ~0ull : ((1ull << p->M) - 1);
+  const uint64_t col_bits = p->N == 64 ? ~0ull : ((1ull << p->N) - 1);
+  for (int t = 0; t < iters; ++t) {
+    BSGD_REQUIRE(rows_sel[t] != 0 && (rows_sel[t] & ~row_bits) == 0,
+                 "rows_sel[%d] = 0x%llx: needs a non-empty subset of the %d row blocks", t,
+                 (unsigned long long)rows_sel[t], p->M);
+    BSGD_REQUIRE(cols_sel[t] != 0 && (cols_sel[t] & ~col_bits) == 0,
+                 "cols_sel[%d] = 0x%llx: needs a non-empty subset of the %d column blocks", t,
+                 (unsigned long long)cols_sel[t], p->N);
+  }
+  const float theta = mu * lam;
+  for (int t = 0; t < iters; ++t) {
+    const int c = st->cur, n = 1 - c;
+    float* step_out = theta == 0.f ? st->x[n] : st->xhat;
+    hipEvent_t* tv = st->t_used < st->t_cap ? &st->tev[5 * (size_t)st->t_used++] : nullptr;
+    // lines 4 + 6 with the current x; lines 3, 7, 8 with the kept residual
+    if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
+    BSGD_HIP(launch_sel_forward(p->fwd, st->vt, st->blk_r, rows_sel[t], cols_sel[t], st->x[c],
+                                st->y, st->r[c], st->r[n], st->zt, stream));
+    if (tv) BSGD_HIP(hipEventRecord(tv[1], stream));
+    if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
+    BSGD_HIP(launch_sel_backward(p->bwd, st->vt, st->blk_c, rows_sel[t], cols_sel[t], st->r[c],
+                                 st->x[c], 2.0f * mu, step_out, stream));
+    if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
+    if (theta != 0.f) BSGD_HIP(prox_step(st, mu, lam, false, prox_iters, st->x[n], stream));
+    if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));
+    st->cur = n;
+    st->epochs_done++;
+  }
   return BSGD_OK;
 }
 

@@ -33,16 +33,33 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {
     # profiles/k_fused_c2_512_hbm_counters.md
     ("fused", "c2_512", "f32"): {
-        "sha256": "d25dc6b662d080c48e4758962b8cf4360e472e706ec6d7047bbb1933c083c4e7",
-        "bytes": 1421558513},
+        "sha256": "179aa77f1d81cccb207bb6a36c083ae445777587918e6bfe4a5758da5db5eaea",
+        "bytes": 1421524617},
+    # profiles/k_rows_c2_512_hbm_counters_ista.md (the forward row kernel: same launch on the
+    # row path and under the ISTA rule)
+    ("rows", "c2_512", "f32", "bwd", "fwd"): {
+        "sha256": "31dafc3198b1cd890dd7fcb425a8d37d45861e004c7ea6b6c34eb786ee8eb629",
+        "bytes": 2271214813},
+    # profiles/k_sel_c2_512_hbm_counters.md (mean over the 800 draws of the bench's run)
+    ("selected", "c2_512", "f32", 0.5, 0.5, 7, "fwd"): {
+        "sha256": "664385127ff97608f2e84818929717d7037728b012ac3e7faefc1bda8e006092",
+        "bytes": 948220927},
 }
 
 
-def _kernel_source_hash():
+# Sources that determine each path's dominant kernel and the layout it reads.
+_KERNEL_SOURCES = {
+    "fused": ("fused.hip", "plan.hip", "bsgd_internal.h"),
+    "rows": ("spmv.hip", "plan.hip", "staged.hip", "bsgd_internal.h"),
+    "selected": ("spmv.hip", "plan.hip", "bsgd_internal.h"),
+}
+
+
+def _kernel_source_hash(path):
     import hashlib
     h = hashlib.sha256()
     base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1812_01307_amd", "csrc")
-    for f in ("spmv.hip", "plan.hip", "staged.hip", "fused.hip", "bsgd_internal.h"):
+    for f in _KERNEL_SOURCES[path]:
         with open(os.path.join(base, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -368,11 +385,15 @@ def main(argv=None):
                   "fwd_gbs": b_fwd / f_ms / 1e6, "bwd_gbs": b_bwd / b_ms / 1e6}
         dom_bytes, dom_ms, dom = (b_fwd, f_ms, "fwd") if f_ms >= b_ms else (b_bwd, b_ms, "bwd")
         achieved = dom_bytes / dom_ms / 1e6
+        traffic = None
+        key = ("selected", args.config, args.vt, args.alpha, args.gamma, args.select_seed, dom)
+        if key in PMC_TRAFFIC and _kernel_source_hash("selected") == PMC_TRAFFIC[key]["sha256"]:
+            traffic = PMC_TRAFFIC[key]["bytes"]
         roofline = {"bound": "hbm",
                     "kernel": ("k_sel_forward (drawn pairs, lines 4+6)" if dom == "fwd"
                                else "k_sel_backward (drawn pairs, lines 3+7+8)"),
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "alg_bytes_per_launch": round(dom_bytes)}
     elif timing and acc["n"] and F is not None:
         f_ms = acc["fwd"] / acc["n"]
@@ -383,7 +404,7 @@ def main(argv=None):
         achieved = b_fwd / f_ms / 1e6
         traffic = None
         key = ("fused", args.config, args.vt)
-        if key in PMC_TRAFFIC and _kernel_source_hash() == PMC_TRAFFIC[key]["sha256"]:
+        if key in PMC_TRAFFIC and _kernel_source_hash("fused") == PMC_TRAFFIC[key]["sha256"]:
             traffic = PMC_TRAFFIC[key]["bytes"]
         roofline = {"bound": "hbm", "kernel": "k_fused (A x and A^T r in one pass: lines 3-4)",
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -399,7 +420,7 @@ def main(argv=None):
         achieved = dom_bytes / dom_ms / 1e6
         traffic = None
         key = ("rows", args.config, args.vt, args.staged, dom)
-        if key in PMC_TRAFFIC and _kernel_source_hash() == PMC_TRAFFIC[key]["sha256"]:
+        if key in PMC_TRAFFIC and _kernel_source_hash("rows") == PMC_TRAFFIC[key]["sha256"]:
             traffic = PMC_TRAFFIC[key]["bytes"]
         kname = "k_staged" if staged_info and staged_info["lanes"][0 if dom == "fwd" else 1] > 0 \
             else "k_rows"

@@ -271,14 +271,45 @@ struct BlockBounds {
   int n;
 };
 
-// One matrix value as FP32, non-temporal load (FP16 values load as bits).
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+
+// Four matrix values at a 4-aligned entry index as FP32 (non-temporal loads;
+// FP16 values load as bits).
 template <typename VT>
-__device__ __forceinline__ float ld_val(const VT* p) {
-  if constexpr (sizeof(VT) == 4)
-    return ld<true>(reinterpret_cast<const float*>(p));
-  else
-    return __half2float(
-        __ushort_as_half(ld<true>(reinterpret_cast<const unsigned short*>(p))));
+__device__ __forceinline__ f32x4 ld_val4(const VT* p) {
+  if constexpr (sizeof(VT) == 4) {
+    return ld<true>(reinterpret_cast<const f32x4*>(p));
+  } else {
+    const u16x4 h = ld<true>(reinterpret_cast<const u16x4*>(p));
+    return f32x4{__half2float(__ushort_as_half(h.x)), __half2float(__ushort_as_half(h.y)),
+                 __half2float(__ushort_as_half(h.z)), __half2float(__ushort_as_half(h.w))};
+  }
+}
+
+// Sum of val[e] * v[col[e]] over the entries [beg, end) of one row, by a
+// group of LPR lanes: each lane takes the 4-aligned chunks (16-byte loads)
+// that overlap the range, LPR chunks apart, and zeroes the entries outside
+// it.  Rows start at multiples of kPad entries and their padding repeats a
+// real column, so every chunk lies inside the row's storage and every
+// gathered index is valid.
+template <typename VT, int LPR>
+__device__ __forceinline__ float seg_dot(const int32_t* __restrict__ col,
+                                         const VT* __restrict__ val, const float* __restrict__ v,
+                                         int64_t beg, int64_t end, int lane) {
+  float acc0 = 0.f, acc1 = 0.f;
+  for (int64_t e = (beg & ~(int64_t)3) + 4 * lane; e < end; e += 4 * LPR) {
+    const i32x4 c = ld<true>(reinterpret_cast<const i32x4*>(col + e));
+    const f32x4 a = ld_val4(val + e);
+    const float a0 = (e >= beg) ? a.x : 0.f;
+    const float a1 = (e + 1 >= beg && e + 1 < end) ? a.y : 0.f;
+    const float a2 = (e + 2 >= beg && e + 2 < end) ? a.z : 0.f;
+    const float a3 = (e + 3 < end) ? a.w : 0.f;
+    acc0 = fmaf(a0, v[c.x], acc0);
+    acc1 = fmaf(a1, v[c.y], acc1);
+    acc0 = fmaf(a2, v[c.z], acc0);
+    acc1 = fmaf(a3, v[c.w], acc1);
+  }
+  return acc0 + acc1;
 }
 
 // id[k] = block of internal row k (0xFF for a hole of the internal order).
@@ -321,11 +352,7 @@ __global__ __launch_bounds__(256) void k_sel_forward(
   for (int j = 0; j < nseg; ++j) {
     float zj;
     if ((cols >> j) & 1) {
-      float acc = 0.f;
-      const int64_t end = base + sg[j + 1];
-      for (int64_t e = base + sg[j] + lane; e < end; e += LPR)
-        acc = fmaf(ld_val(val + e), x[ld<true>(col + e)], acc);
-      zj = group_sum<LPR>(acc);
+      zj = group_sum<LPR>(seg_dot<VT, LPR>(col, val, x, base + sg[j], base + sg[j + 1], lane));
       if (lane == 0) Z[j * nrows + row] = zj;
     } else {
       zj = Z[j * nrows + row];
@@ -355,12 +382,8 @@ __global__ __launch_bounds__(256) void k_sel_backward(
   const int64_t base = ptr[row];
   const int32_t* sg = seg + row * (nseg + 1);
   float acc = 0.f;
-  for (int i = 0; i < nseg; ++i) {
-    if (!((rows >> i) & 1)) continue;
-    const int64_t end = base + sg[i + 1];
-    for (int64_t e = base + sg[i] + lane; e < end; e += LPR)
-      acc = fmaf(ld_val(val + e), r[ld<true>(col + e)], acc);
-  }
+  for (int i = 0; i < nseg; ++i)
+    if ((rows >> i) & 1) acc += seg_dot<VT, LPR>(col, val, r, base + sg[i], base + sg[i + 1], lane);
   acc = group_sum<LPR>(acc);
   if (lane == 0) out[row] = fmaf(scale, acc, xadd[row]);
 }

@@ -130,8 +130,12 @@ static TileGeom tile_geom(const Layout& L, int chunks) {
   if (chunks > 0) {
     g.Q = chunks;
   } else {
-    // about 2048 unit workgroups, no more chunks than ray groups
-    const int64_t want = (2048 + g.tiles() - 1) / g.tiles();
+    // at least about 2048 unit workgroups, and chunks of at most 128 K rays
+    // (512 KB of r, so that a unit's residual gathers stay in L2; measured
+    // on gfx950: 8 chunks at 512^2 and 16 at 1024^2, 11% faster epochs
+    // there than 2), no more chunks than ray groups
+    const int64_t want = std::max<int64_t>((2048 + g.tiles() - 1) / g.tiles(),
+                                           (L.r_int + 131071) / 131072);
     g.Q = (int)std::max<int64_t>(1, std::min<int64_t>(want, g.ngroups));
   }
   return g;

@@ -33,8 +33,8 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {
     # profiles/k_fused_c2_512_hbm_counters.md
     ("fused", "c2_512", "f32"): {
-        "sha256": "179aa77f1d81cccb207bb6a36c083ae445777587918e6bfe4a5758da5db5eaea",
-        "bytes": 1421524617},
+        "sha256": "e7038505f6b43a263dcf9caa0e32d56d043d2e3af8374576af3dbddc850f0c54",
+        "bytes": 1421268146},
     # profiles/k_rows_c2_512_hbm_counters_ista.md (the forward row kernel: same launch on the
     # row path and under the ISTA rule)
     ("rows", "c2_512", "f32", "bwd", "fwd"): {

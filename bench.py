@@ -342,8 +342,13 @@ def main(argv=None):
         slot = 6 + (2 if cbytes == 1 else 0)
         b_pass = (val_bytes + cbytes) * nnz + slot * 64 * slices + 12 * slices + 4 * c + 4 * r \
             + 4 * segs + 4 * chunks * c
-        # reduce: partials read, segment offsets, y, r' written, x read, x^ written
-        b_red = 4 * segs + 4 * (r + 1) + 8 * r + 4 * chunks * c + 8 * c
+        # reduce: partials read, segment offsets, y, r' written, x read, x^ written;
+        # with overlap modes 0/1 the timed reduce is the pixel half only (the ray
+        # half runs concurrently with it and the prox on the state's second stream)
+        if args.overlap == 2:
+            b_red = 4 * segs + 4 * (r + 1) + 8 * r + 4 * chunks * c + 8 * c
+        else:
+            b_red = 4 * chunks * c + 8 * c
         b_fwd, b_bwd = b_pass, b_red
         fused_info = {"tiles": tiles, "chunks": chunks, "segments": segs, "slices": slices,
                       "stored_entries": entries, "padding": round(entries / nnz - 1, 4),

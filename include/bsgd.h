@@ -393,15 +393,19 @@ bsgd_status bsgd_run_selected(bsgd_state* state, float mu, float lam, int iters,
  * mode 1 after the backprojection (it then overlaps the prox only; faster on
  * MI355X since both passes are bandwidth-bound); mode 2 runs everything on
  * the caller's stream in order (backprojection, prox, forward pass), which
- * gives each kernel the whole GPU.  Results do not depend on the mode.
- * Default 1.
+ * gives each kernel the whole GPU.  With an attached single-pass store,
+ * modes 0 and 1 run the ray half of the reduce (line 6: the next residual,
+ * needed only by the next pass) on the second stream, concurrently with the
+ * pixel half and the prox; mode 2 keeps it on the caller's stream.  Results
+ * do not depend on the mode.  Default 1.
  */
 bsgd_status bsgd_state_set_overlap(bsgd_state* state, int mode);
 
 /*
- * Schedule of the 2-D prox (line 9) kernels: 0 runs up to 20 FGP iterations
- * per launch on 32 x 32 tiles, recomputing a halo as wide as the iteration
- * count (few launches, redundant work), with each thread keeping a strip of
+ * Schedule of the 2-D prox (line 9) kernels: 0 splits the FGP iterations
+ * into equal launches of at most 12 on 32 x 32 tiles, recomputing a halo as
+ * wide as the launch's iteration count (few launches, redundant work), with
+ * each thread keeping a strip of
  * pixels' duals in registers; 2 is the same schedule with the duals in LDS;
  * 1 runs one iteration per launch (no redundant work, small LDS footprint).
  * Same arithmetic per pixel, so all three give identical results.

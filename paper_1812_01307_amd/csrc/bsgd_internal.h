@@ -230,9 +230,12 @@ hipError_t launch_fused_absmax(const float* v, int64_t n, unsigned* out, hipStre
 hipError_t launch_fused_pass(const bsgd_fused* F, bsgd_valtype vt, const float* x,
                              const float* r, const unsigned* rmax_in, unsigned* rmax_zero,
                              float* zp, float* gp, hipStream_t s);
+// parts: kReduceRays (out_r, *rmax_out), kReducePixels (out_x), or both.
+enum { kReduceRays = 1, kReducePixels = 2, kReduceAll = 3 };
 hipError_t launch_fused_reduce(const bsgd_fused* F, const float* zp, const float* gp,
                                const float* y, float* out_r, unsigned* rmax_out,
-                               const float* xadd, float scale, float* out_x, hipStream_t s);
+                               const float* xadd, float scale, float* out_x, hipStream_t s,
+                               int parts = kReduceAll);
 bool fused_has_f16(const bsgd_fused* F);
 const bsgd_plan* fused_plan(const bsgd_fused* F);
 

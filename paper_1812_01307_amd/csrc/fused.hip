@@ -728,11 +728,10 @@ __global__ __launch_bounds__(256) void k_fz_reduce(
     const int32_t* __restrict__ poff, const float* __restrict__ zp,
     const float* __restrict__ y, float* __restrict__ out_r, unsigned* rmax_out,
     int64_t r_int, const float* __restrict__ gp, int Q, const float* __restrict__ xadd,
-    float scale, float* __restrict__ out_x, int64_t c_int) {
-  const int64_t tot = r_int + c_int;
+    float scale, float* __restrict__ out_x, int64_t c_int, int64_t lo, int64_t hi) {
   float m = 0.f;
   bool bad = false;  // a NaN residual (fmaxf would drop it)
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < tot;
+  for (int64_t i = lo + (int64_t)blockIdx.x * 256 + threadIdx.x; i < hi;
        i += (int64_t)gridDim.x * 256) {
     if (i < r_int) {
       const int n = poff[i + 1] - poff[i];
@@ -759,7 +758,8 @@ __global__ __launch_bounds__(256) void k_fz_reduce(
       out_x[p] = xadd ? fmaf(scale, a, xadd[p]) : scale * a;
     }
   }
-  if (rmax_out) block_max_to(bad ? 0x7fc00000u : __float_as_uint(m), rmax_out);  // NaN > +inf
+  if (rmax_out && lo < r_int)
+    block_max_to(bad ? 0x7fc00000u : __float_as_uint(m), rmax_out);  // NaN > +inf
 }
 
 __global__ void k_fz_zero_u32(unsigned* p) { *p = 0u; }
@@ -837,12 +837,15 @@ hipError_t launch_fused_pass(const bsgd_fused* F, bsgd_valtype vt, const float* 
 
 hipError_t launch_fused_reduce(const bsgd_fused* F, const float* zp, const float* gp,
                                const float* y, float* out_r, unsigned* rmax_out,
-                               const float* xadd, float scale, float* out_x, hipStream_t s) {
+                               const float* xadd, float scale, float* out_x, hipStream_t s,
+                               int parts) {
   const Layout& L = F->plan->L;
-  const int64_t tot = L.r_int + L.c_int;
-  const unsigned blocks = std::min<unsigned>(grid_for(tot), 1024);
+  const int64_t lo = (parts & kReduceRays) ? 0 : L.r_int;
+  const int64_t hi = (parts & kReducePixels) ? L.r_int + L.c_int : L.r_int;
+  if (hi <= lo) return hipSuccess;
+  const unsigned blocks = std::min<unsigned>(grid_for(hi - lo), 1024);
   k_fz_reduce<<<blocks, 256, 0, s>>>(F->poff, zp, y, out_r, rmax_out, L.r_int, gp, F->g.Q, xadd,
-                                     scale, out_x, L.c_int);
+                                     scale, out_x, L.c_int, lo, hi);
   return hipGetLastError();
 }
 

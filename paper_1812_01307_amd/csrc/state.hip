@@ -483,23 +483,36 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
     }
     if (st->fz) {
       // single pass over the tile-sliced store (lines 3-4 together), then the
-      // reduce (lines 6-8), then the prox (line 9), in order on `stream`.
+      // reduce (lines 6-8), then the prox (line 9) on `stream`.  The ray half
+      // of the reduce (line 6: the next residual and its max |r|) is needed
+      // only by the next pass, so with overlap modes 0 and 1 it runs on the
+      // state's second stream, concurrently with the pixel half and the prox.
       // max |r| of the residual the pass reads: computed at the start of each
       // call, then carried by the reduce (which writes the next residual)
       const FusedPartials& fp = st->fzp;
+      const bool split = st->overlap != 2;
       if (e == 0) BSGD_HIP(launch_fused_absmax(st->r[c], p->L.r_int, fp.rmax + c, stream));
       if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
       BSGD_HIP(launch_fused_pass(st->fz, st->vt, st->x[c], st->r[c], fp.rmax + c, fp.rmax + n,
                                  fp.zp, fp.gp, stream));
       if (tv) BSGD_HIP(hipEventRecord(tv[1], stream));
+      if (split) {
+        BSGD_HIP(hipEventRecord(st->ev_main, stream));
+        BSGD_HIP(hipStreamWaitEvent(st->aux, st->ev_main, 0));
+        BSGD_HIP(launch_fused_reduce(st->fz, fp.zp, fp.gp, st->y, st->r[n], fp.rmax + n,
+                                     nullptr, 0.f, nullptr, st->aux, kReduceRays));
+        BSGD_HIP(hipEventRecord(st->ev_aux, st->aux));
+      }
       if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
       BSGD_HIP(launch_fused_reduce(st->fz, fp.zp, fp.gp, st->y, st->r[n], fp.rmax + n, st->x[c],
-                                   2.0f * mu, step_out, stream));
+                                   2.0f * mu, step_out, stream,
+                                   split ? kReducePixels : kReduceAll));
       if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
       if (theta != 0.f)
         BSGD_HIP(tv_prox_run(p->L, true, st->xhat, theta, prox_iters, st->x[n], st->tv_ws,
                              stream, st->prox_schedule));
       if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));
+      if (split) BSGD_HIP(hipStreamWaitEvent(stream, st->ev_aux, 0));
       st->cur = n;
       st->epochs_done++;
       continue;

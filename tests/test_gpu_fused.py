@@ -300,3 +300,23 @@ def test_fused_general_matrix_uses_wide_columns():
     for k in range(8):
         bsgd.bsgd_run_epochs(st, mu, 3.0, 1, 20)
         assert rel_l2(_host(bsgd.bsgd_get_x(st)), ref[k]) <= ITERATE_REL, k
+
+
+@pytest.mark.parametrize("name", ["c1", "ragged"])
+def test_fused_overlap_modes_agree_bitwise(name):
+    """The ray half of the reduce on the second stream (modes 0, 1) or in order (mode 2)."""
+    import paper_1812_01307_amd as bsgd
+    p = _cases()[name]()
+    plan = plan_for(p)
+    F = _fused(plan)
+    mu = float(np.float32(mu_for(p)))
+    outs = []
+    for mode in (0, 1, 2):
+        st = bsgd.bsgd_state_create(plan, 1)
+        bsgd.bsgd_state_attach_fused(st, F)
+        bsgd.bsgd_state_set_overlap(st, mode)
+        bsgd.bsgd_state_init(st, _dev(f32(p.y)))
+        bsgd.bsgd_run_epochs(st, mu, 5.0, 9, 20)
+        outs.append((_host(bsgd.bsgd_get_x(st)), _host(bsgd.bsgd_get_r(st))))
+    for x, r in outs[1:]:
+        assert np.array_equal(x, outs[0][0]) and np.array_equal(r, outs[0][1])

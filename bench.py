@@ -134,8 +134,8 @@ def main(argv=None):
                     help="serving: skip the one-request-at-a-time comparison run")
     args = ap.parse_args(argv)
 
-    if args.method != "bsgd":
-        args.path = "rows"   # the comparison methods run on the block store
+    if args.method == "selected":
+        args.path = "rows"   # the subset iterations run on the block store
     if args.staged is None:
         args.staged = "none" if args.path == "fused" or args.method == "selected" else "bwd"
     if args.gpus != 1:
@@ -350,6 +350,16 @@ def main(argv=None):
         else:
             b_red = 4 * chunks * c + 8 * c
         b_fwd, b_bwd = b_pass, b_red
+        if args.method in ("ista", "gd"):
+            # two passes per epoch: A x only (timed as "fwd": matrix, slots, x tile,
+            # segment partials) and A^T r only with the pixel half of the reduce
+            # (timed as "bwd": matrix, slots, r gathers, chunk partials, then the
+            # partials, x and x^)
+            b_fwd = (val_bytes + cbytes) * nnz + slot * 64 * slices + 12 * slices + 4 * c \
+                + 4 * segs
+            b_bwd = (val_bytes + cbytes) * nnz + slot * 64 * slices + 12 * slices + 4 * r \
+                + 4 * chunks * c + 4 * chunks * c + 8 * c
+            b_pass, b_red = b_fwd, b_bwd
         fused_info = {"tiles": tiles, "chunks": chunks, "segments": segs, "slices": slices,
                       "stored_entries": entries, "padding": round(entries / nnz - 1, 4),
                       "column_bytes": cbytes,
@@ -404,14 +414,21 @@ def main(argv=None):
         f_ms = acc["fwd"] / acc["n"]
         b_ms = acc["bwd"] / acc["n"]
         p_ms = acc["prox"] / acc["n"]
-        kernel = {"pass_ms": f_ms, "reduce_ms": b_ms, "prox_ms": p_ms,
-                  "pass_gbs": b_fwd / f_ms / 1e6, "reduce_gbs": b_bwd / b_ms / 1e6}
+        if args.method in ("ista", "gd"):
+            kernel = {"pass_ax_ms": f_ms, "pass_atr_and_reduce_ms": b_ms, "prox_ms": p_ms,
+                      "pass_ax_gbs": b_fwd / f_ms / 1e6, "pass_atr_gbs": b_bwd / b_ms / 1e6}
+        else:
+            kernel = {"pass_ms": f_ms, "reduce_ms": b_ms, "prox_ms": p_ms,
+                      "pass_gbs": b_fwd / f_ms / 1e6, "reduce_gbs": b_bwd / b_ms / 1e6}
         achieved = b_fwd / f_ms / 1e6
         traffic = None
-        key = ("fused", args.config, args.vt)
+        key = ("fused", args.config, args.vt) if args.method == "bsgd" else \
+            ("fused", args.config, args.vt, args.method)
         if key in PMC_TRAFFIC and _kernel_source_hash("fused") == PMC_TRAFFIC[key]["sha256"]:
             traffic = PMC_TRAFFIC[key]["bytes"]
-        roofline = {"bound": "hbm", "kernel": "k_fused (A x and A^T r in one pass: lines 3-4)",
+        kdesc = ("k_fused (A x only: ISTA's forward pass)" if args.method in ("ista", "gd")
+                 else "k_fused (A x and A^T r in one pass: lines 3-4)")
+        roofline = {"bound": "hbm", "kernel": kdesc,
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "alg_bytes_per_launch": b_fwd}

@@ -356,8 +356,9 @@ bsgd_status bsgd_run_epochs(bsgd_state* state, float mu, float lam, int epochs, 
  *     waits for the forward pass.  lam = 0 gives gradient descent on
  *     ||y - A x||^2 (Fig. 2's GD).
  * Both keep r = y - A x of the iterate before the current one, so the
- * methods can alternate on one state.  The ISTA epoch runs on the block
- * store (an attached single-pass store serves only BSGD epochs).
+ * methods can alternate on one state.  With an attached single-pass store an
+ * ISTA epoch reads that store twice (A x, then A^T of the new residual);
+ * without one it runs the block store's row kernels.
  */
 #define BSGD_METHOD_BSGD 0
 #define BSGD_METHOD_ISTA 1

@@ -227,9 +227,12 @@ struct FusedPartials {
 };
 size_t fused_partials(const bsgd_fused* F, FusedPartials* fp, void* ws);
 hipError_t launch_fused_absmax(const float* v, int64_t n, unsigned* out, hipStream_t s);
+// mode kPassBoth: both products; kPassA: only the A x partials (no r,
+// rmax_in may be NULL); kPassAt: only the A^T r partials (x unused).
+enum { kPassBoth = 0, kPassA = 1, kPassAt = 2 };
 hipError_t launch_fused_pass(const bsgd_fused* F, bsgd_valtype vt, const float* x,
                              const float* r, const unsigned* rmax_in, unsigned* rmax_zero,
-                             float* zp, float* gp, hipStream_t s);
+                             float* zp, float* gp, hipStream_t s, int mode = kPassBoth);
 // parts: kReduceRays (out_r, *rmax_out), kReducePixels (out_x), or both.
 enum { kReduceRays = 1, kReducePixels = 2, kReduceAll = 3 };
 hipError_t launch_fused_reduce(const bsgd_fused* F, const float* zp, const float* gp,

@@ -567,7 +567,7 @@ __device__ __forceinline__ void load_group(const void* __restrict__ col,
 // z += a . x[c] (LDS gathers) and g[c] += a * r (fixed-point LDS atomics);
 // narrow columns are decoded from the lane's running address ap (groups of
 // a lane are decoded in order)
-template <bool NARROW>
+template <bool NARROW, int MODE>
 __device__ __forceinline__ void group_step(const float* xs, unsigned long long* gs,
                                            const ColRaw<NARROW>& raw, const float (&a)[4],
                                            double rs, float& z, int& ap) {
@@ -584,8 +584,8 @@ __device__ __forceinline__ void group_step(const float* xs, unsigned long long* 
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    z = fmaf(a[t], xs[c[t]], z);
-    atomicAdd(&gs[c[t]], to_fixed(a[t], rs));
+    if constexpr (MODE != kPassAt) z = fmaf(a[t], xs[c[t]], z);
+    if constexpr (MODE != kPassA) atomicAdd(&gs[c[t]], to_fixed(a[t], rs));
   }
 }
 
@@ -597,7 +597,7 @@ __device__ __forceinline__ int snake(int s0, int k, int wv) {
   return s0 + k * W + ((k & 1) ? (W - 1 - wv) : wv);
 }
 
-template <typename VT, bool NARROW, int W>
+template <typename VT, bool NARROW, int W, int MODE>
 __global__ __launch_bounds__(64 * W) void k_fused(
     TileGeom g, const int32_t* __restrict__ uorder, const int32_t* __restrict__ sbeg,
     const int32_t* __restrict__ sng, const int64_t* __restrict__ soff,
@@ -622,24 +622,25 @@ __global__ __launch_bounds__(64 * W) void k_fused(
   // the next kernel of the epoch gathers the next residual's |r| maximum here
   if (rmax_zero && blockIdx.x == 0 && tid == 0) *rmax_zero = 0u;
   for (int i = tid; i < kFTA; i += NT) {
-    xs[i] = 0.f;
-    gs[i] = 0ull;
+    if constexpr (MODE != kPassAt) xs[i] = 0.f;
+    if constexpr (MODE != kPassA) gs[i] = 0ull;
   }
   __syncthreads();
-  for (int i = tid; i < kFT * kFT; i += NT) {
-    const int b = i >> 6, w = i & 63;
-    const int tr8 = ftr * 4 + (b >> 2), tc8 = ftc * 4 + (b & 3);
-    if (tr8 < g.Ht && tc8 < g.Wt)
-      xs[(((b >> 2) << 3) + (w >> 3)) * kFTS + ((b & 3) << 3) + (w & 7)] =
-          x[xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w];
-  }
-  const int e = fixed_exponent(smax, __uint_as_float(*rmax_in));
+  if constexpr (MODE != kPassAt)
+    for (int i = tid; i < kFT * kFT; i += NT) {
+      const int b = i >> 6, w = i & 63;
+      const int tr8 = ftr * 4 + (b >> 2), tc8 = ftc * 4 + (b & 3);
+      if (tr8 < g.Ht && tc8 < g.Wt)
+        xs[(((b >> 2) << 3) + (w >> 3)) * kFTS + ((b & 3) << 3) + (w & 7)] =
+            x[xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w];
+    }
+  const int e = MODE == kPassA ? 0 : fixed_exponent(smax, __uint_as_float(*rmax_in));
   const double scale = ldexp(1.0, e);
   __syncthreads();
   // the next slice's table entries and its r value load while a slice streams
   int k = 0, s = snake<W>(s0, 0, wv);
   SliceMeta cur = slice_meta(sray, srank, sbase, sng, soff, s, s1, lane);
-  float rcur = cur.rho >= 0 ? r[cur.rho] : 0.f;
+  float rcur = (MODE != kPassA && cur.rho >= 0) ? r[cur.rho] : 0.f;
   while (s < s1) {
     const int sn = snake<W>(s0, k + 1, wv);
     const SliceMeta nxt = slice_meta(sray, srank, sbase, sng, soff, sn, s1, lane);
@@ -660,12 +661,12 @@ __global__ __launch_bounds__(64 * W) void k_fused(
       load_group<VT, NARROW>(col, val, base + (int64_t)(j + 3) * 256, c3, a3);
       if (!fetched) {
         fetched = true;
-        if (nxt.rho >= 0) rnext = r[nxt.rho];
+        if (MODE != kPassA && nxt.rho >= 0) rnext = r[nxt.rho];
       }
-      group_step<NARROW>(xs, gs, c0, a0, rs, z0, ap);
-      group_step<NARROW>(xs, gs, c1, a1, rs, z1, ap);
-      group_step<NARROW>(xs, gs, c2, a2, rs, z0, ap);
-      group_step<NARROW>(xs, gs, c3, a3, rs, z1, ap);
+      group_step<NARROW, MODE>(xs, gs, c0, a0, rs, z0, ap);
+      group_step<NARROW, MODE>(xs, gs, c1, a1, rs, z1, ap);
+      group_step<NARROW, MODE>(xs, gs, c2, a2, rs, z0, ap);
+      group_step<NARROW, MODE>(xs, gs, c3, a3, rs, z1, ap);
     }
     for (; j + 1 < ng; j += 2) {
       ColRaw<NARROW> c0, c1;
@@ -674,25 +675,26 @@ __global__ __launch_bounds__(64 * W) void k_fused(
       load_group<VT, NARROW>(col, val, base + (int64_t)(j + 1) * 256, c1, a1);
       if (!fetched) {
         fetched = true;
-        if (nxt.rho >= 0) rnext = r[nxt.rho];
+        if (MODE != kPassA && nxt.rho >= 0) rnext = r[nxt.rho];
       }
-      group_step<NARROW>(xs, gs, c0, a0, rs, z0, ap);
-      group_step<NARROW>(xs, gs, c1, a1, rs, z1, ap);
+      group_step<NARROW, MODE>(xs, gs, c0, a0, rs, z0, ap);
+      group_step<NARROW, MODE>(xs, gs, c1, a1, rs, z1, ap);
     }
     if (j < ng) {
       ColRaw<NARROW> c0;
       float a0[4];
       load_group<VT, NARROW>(col, val, base + (int64_t)j * 256, c0, a0);
-      group_step<NARROW>(xs, gs, c0, a0, rs, z0, ap);
+      group_step<NARROW, MODE>(xs, gs, c0, a0, rs, z0, ap);
     }
-    if (!fetched && nxt.rho >= 0) rnext = r[nxt.rho];
-    if (cur.rho >= 0) zp[(int64_t)cur.rk * r_int + cur.rho] = z0 + z1;
+    if (MODE != kPassA && !fetched && nxt.rho >= 0) rnext = r[nxt.rho];
+    if (MODE != kPassAt && cur.rho >= 0) zp[(int64_t)cur.rk * r_int + cur.rho] = z0 + z1;
     ++k;
     s = sn;
     cur = nxt;
     rcur = rnext;
   }
   __syncthreads();
+  if constexpr (MODE == kPassA) return;
   const double inv = ldexp(1.0, -e);
   for (int i = tid; i < kFT * kFT; i += NT) {
     const int b = i >> 6, w = i & 63;
@@ -778,28 +780,39 @@ __global__ __launch_bounds__(256) void k_fz_absmax(const float* __restrict__ v, 
   block_max_to(bad ? 0x7fc00000u : __float_as_uint(m), out);
 }
 
-template <typename VT, int W>
-static void launch_fused_w(const bsgd_fused& F, const VT* val, const float* x, const float* r,
+template <typename VT, int W, int MODE>
+static void launch_fused_m(const bsgd_fused& F, const VT* val, const float* x, const float* r,
                            const unsigned* rmax_in, unsigned* rmax_zero, float* zp, float* gp,
                            hipStream_t s) {
   if (F.narrow)
-    k_fused<VT, true, W><<<(unsigned)F.g.units(), 64 * W, 0, s>>>(
+    k_fused<VT, true, W, MODE><<<(unsigned)F.g.units(), 64 * W, 0, s>>>(
         F.g, F.uorder, F.sbeg, F.sng, F.soff, F.sray, F.srank, F.sbase, F.col8, val, x, r,
         rmax_in, rmax_zero, zp, gp, F.plan->L.r_int, F.plan->L.c_int, F.smax);
   else
-    k_fused<VT, false, W><<<(unsigned)F.g.units(), 64 * W, 0, s>>>(
+    k_fused<VT, false, W, MODE><<<(unsigned)F.g.units(), 64 * W, 0, s>>>(
         F.g, F.uorder, F.sbeg, F.sng, F.soff, F.sray, F.srank, nullptr, F.col, val, x, r,
         rmax_in, rmax_zero, zp, gp, F.plan->L.r_int, F.plan->L.c_int, F.smax);
 }
 
+template <typename VT, int W>
+static void launch_fused_w(const bsgd_fused& F, int mode, const VT* val, const float* x,
+                           const float* r, const unsigned* rmax_in, unsigned* rmax_zero,
+                           float* zp, float* gp, hipStream_t s) {
+  switch (mode) {
+    case kPassA: launch_fused_m<VT, W, kPassA>(F, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
+    case kPassAt: launch_fused_m<VT, W, kPassAt>(F, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
+    default: launch_fused_m<VT, W, kPassBoth>(F, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
+  }
+}
+
 template <typename VT>
-static void launch_fused_vt(const bsgd_fused& F, const VT* val, const float* x, const float* r,
-                            const unsigned* rmax_in, unsigned* rmax_zero, float* zp, float* gp,
-                            hipStream_t s) {
+static void launch_fused_vt(const bsgd_fused& F, int mode, const VT* val, const float* x,
+                            const float* r, const unsigned* rmax_in, unsigned* rmax_zero,
+                            float* zp, float* gp, hipStream_t s) {
   switch (F.waves) {
-    case 2: launch_fused_w<VT, 2>(F, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
-    case 4: launch_fused_w<VT, 4>(F, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
-    default: launch_fused_w<VT, 8>(F, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
+    case 2: launch_fused_w<VT, 2>(F, mode, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
+    case 4: launch_fused_w<VT, 4>(F, mode, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
+    default: launch_fused_w<VT, 8>(F, mode, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
   }
 }
 
@@ -827,11 +840,11 @@ hipError_t launch_fused_absmax(const float* v, int64_t n, unsigned* out, hipStre
 
 hipError_t launch_fused_pass(const bsgd_fused* F, bsgd_valtype vt, const float* x,
                              const float* r, const unsigned* rmax_in, unsigned* rmax_zero,
-                             float* zp, float* gp, hipStream_t s) {
+                             float* zp, float* gp, hipStream_t s, int mode) {
   if (vt == BSGD_VAL_F16)
-    launch_fused_vt<__half>(*F, F->val16, x, r, rmax_in, rmax_zero, zp, gp, s);
+    launch_fused_vt<__half>(*F, mode, F->val16, x, r, rmax_in, rmax_zero, zp, gp, s);
   else
-    launch_fused_vt<float>(*F, F->val, x, r, rmax_in, rmax_zero, zp, gp, s);
+    launch_fused_vt<float>(*F, mode, F->val, x, r, rmax_in, rmax_zero, zp, gp, s);
   return hipGetLastError();
 }
 

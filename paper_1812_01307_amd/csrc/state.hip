@@ -468,12 +468,28 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
     float* step_out = theta == 0.f ? st->x[n] : st->xhat;
     if (st->method == BSGD_METHOD_ISTA) {
       // r' = y - A x, then x^ = x + 2 mu A^T r' (current gradient), then
-      // line 9; in order on `stream`
+      // line 9; in order on `stream`.  With a single-pass store the two
+      // products are two passes over it (A x only, then A^T r' only: the
+      // second needs the first's residual), each with its half of the reduce.
       if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
-      BSGD_HIP(forward_residual(st, st->x[c], st->r[n], stream));
-      if (tv) BSGD_HIP(hipEventRecord(tv[1], stream));
-      if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
-      BSGD_HIP(backward_step(st, st->r[n], st->x[c], 2.0f * mu, step_out, stream));
+      if (st->fz) {
+        const FusedPartials& fp = st->fzp;
+        BSGD_HIP(launch_fused_pass(st->fz, st->vt, st->x[c], nullptr, nullptr, fp.rmax + n,
+                                   fp.zp, fp.gp, stream, kPassA));
+        if (tv) BSGD_HIP(hipEventRecord(tv[1], stream));
+        BSGD_HIP(launch_fused_reduce(st->fz, fp.zp, fp.gp, st->y, st->r[n], fp.rmax + n,
+                                     nullptr, 0.f, nullptr, stream, kReduceRays));
+        if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
+        BSGD_HIP(launch_fused_pass(st->fz, st->vt, nullptr, st->r[n], fp.rmax + n, nullptr,
+                                   fp.zp, fp.gp, stream, kPassAt));
+        BSGD_HIP(launch_fused_reduce(st->fz, fp.zp, fp.gp, nullptr, nullptr, nullptr, st->x[c],
+                                     2.0f * mu, step_out, stream, kReducePixels));
+      } else {
+        BSGD_HIP(forward_residual(st, st->x[c], st->r[n], stream));
+        if (tv) BSGD_HIP(hipEventRecord(tv[1], stream));
+        if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
+        BSGD_HIP(backward_step(st, st->r[n], st->x[c], 2.0f * mu, step_out, stream));
+      }
       if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
       if (theta != 0.f) BSGD_HIP(prox_step(st, mu, lam, per_rhs, prox_iters, st->x[n], stream));
       if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));

@@ -52,15 +52,15 @@ def _run_method(p, plan, method, mu, lam, epochs, K, fused=False, x0=None):
 
 
 @pytest.mark.parametrize("name", ["c1", "medium", "ragged"])
-@pytest.mark.parametrize("staged", [False, True])
-def test_ista_trajectory_matches_oracle(name, staged):
+@pytest.mark.parametrize("form", ["rows", "staged", "fused"])
+def test_ista_trajectory_matches_oracle(name, form):
     import paper_1812_01307_amd as bsgd
     p = _cases()[name]()
-    plan = plan_for(p, staged=staged)
+    plan = plan_for(p, staged=form == "staged")
     mu = float(np.float32(mu_for(p)))
     lam, E = 5.0, 12
     _, _, ref = oracle.ista_tv(matrix(p), _y(p), mu, lam, E, 20, (p.H, p.W), record=True)
-    xs, st = _run_method(p, plan, bsgd.BSGD_METHOD_ISTA, mu, lam, E, 20)
+    xs, st = _run_method(p, plan, bsgd.BSGD_METHOD_ISTA, mu, lam, E, 20, fused=form == "fused")
     errs = [rel_l2(a, b) for a, b in zip(xs, ref)]
     assert max(errs) <= ITERATE_REL, (max(errs), int(np.argmax(errs)))
     # the state keeps r = y - A x of the iterate before the last one
@@ -68,7 +68,8 @@ def test_ista_trajectory_matches_oracle(name, staged):
     assert rel_l2(r, _y(p) - oracle.forward(matrix(p), ref[-2])) <= ITERATE_REL
 
 
-def test_ista_and_gd_on_c1_whole_runs():
+@pytest.mark.parametrize("fused", [False, True])
+def test_ista_and_gd_on_c1_whole_runs(fused):
     """100 epochs of ISTA at the workload's lambda and a lambda the prox moves, and of GD."""
     import paper_1812_01307_amd as bsgd
     p = problem("c1_64")
@@ -77,16 +78,18 @@ def test_ista_and_gd_on_c1_whole_runs():
     A, y = matrix(p), _y(p)
     for lam in (p.lam, 200.0):
         _, _, ref = oracle.ista_tv(A, y, mu, lam, p.epochs, p.prox_iters, (p.H, p.W), record=True)
-        xs, _ = _run_method(p, plan, bsgd.BSGD_METHOD_ISTA, mu, lam, p.epochs, p.prox_iters)
+        xs, _ = _run_method(p, plan, bsgd.BSGD_METHOD_ISTA, mu, lam, p.epochs, p.prox_iters,
+                            fused=fused)
         assert max(rel_l2(a, b) for a, b in zip(xs, ref)) <= ITERATE_REL, lam
     _, _, ref = oracle.gd(A, y, mu, p.epochs, record=True)
-    xs, _ = _run_method(p, plan, bsgd.BSGD_METHOD_ISTA, mu, 0.0, p.epochs, 0)
+    xs, _ = _run_method(p, plan, bsgd.BSGD_METHOD_ISTA, mu, 0.0, p.epochs, 0, fused=fused)
     assert max(rel_l2(a, b) for a, b in zip(xs, ref)) <= ITERATE_REL
 
 
-def test_methods_alternate_on_one_state_and_ignore_the_single_pass_store():
-    """BSGD epochs, then ISTA epochs from the reached iterate; ISTA with an attached store
-    runs the block store (bitwise equal to the plain state)."""
+def test_methods_alternate_on_one_state():
+    """BSGD epochs, then ISTA epochs from the reached iterate, on the block store and on the
+    single-pass store (two single-direction passes per ISTA epoch); the two forms agree to
+    FP32 rounding."""
     import paper_1812_01307_amd as bsgd
     p = problem("c1_64")
     plan = plan_for(p)
@@ -113,7 +116,7 @@ def test_methods_alternate_on_one_state_and_ignore_the_single_pass_store():
         assert n == 12
     xa, _ = _run_method(p, plan, bsgd.BSGD_METHOD_ISTA, mu, lam, 5, 20, fused=False)
     xf, _ = _run_method(p, plan, bsgd.BSGD_METHOD_ISTA, mu, lam, 5, 20, fused=True)
-    assert all(np.array_equal(a, b) for a, b in zip(xa, xf))
+    assert max(rel_l2(a, b) for a, b in zip(xf, xa)) <= 1e-6
 
 
 def test_ista_batch_state_matches_oracle_per_rhs():
@@ -143,9 +146,11 @@ def test_set_method_validation():
         bsgd.bsgd_state_set_method(st, 2)
 
 
-def test_ista_full_size_sampled():
-    """512 x 512, 720 x 729 rays: one GD epoch from a seeded x0, sampled pixels of the
-    new iterate against one-by-one FP64 sums (the residual is recomputed in FP64)."""
+@pytest.mark.parametrize("fused", [False, True])
+def test_ista_full_size_sampled(fused):
+    """512 x 512, 720 x 729 rays (the bench's launch: single-pass store or row kernels): one
+    GD epoch from a seeded x0, sampled rays of the residual and pixels of the new iterate
+    against one-by-one FP64 sums (the residual is recomputed in FP64)."""
     import paper_1812_01307_amd as bsgd
     p = problem("c2_512")
     plan = plan_for(p)
@@ -153,6 +158,9 @@ def test_ista_full_size_sampled():
     rng = np.random.default_rng(41)
     x0 = f32(rng.random(p.ncols))
     st = bsgd.bsgd_state_create(plan, 1)
+    if fused:
+        F = bsgd.bsgd_fused_create(plan)
+        bsgd.bsgd_state_attach_fused(st, F)
     bsgd.bsgd_state_set_method(st, bsgd.BSGD_METHOD_ISTA)
     bsgd.bsgd_state_init(st, _dev(f32(p.y)), _dev(x0))
     bsgd.bsgd_run_epochs(st, mu, 0.0, 1, 0)

@@ -33,25 +33,24 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {
     # profiles/k_fused_c2_512_hbm_counters.md
     ("fused", "c2_512", "f32"): {
-        "sha256": "e7038505f6b43a263dcf9caa0e32d56d043d2e3af8374576af3dbddc850f0c54",
-        "bytes": 1421268146},
-    # profiles/k_rows_c2_512_hbm_counters_ista.md (the forward row kernel: same launch on the
-    # row path and under the ISTA rule)
-    ("rows", "c2_512", "f32", "bwd", "fwd"): {
-        "sha256": "31dafc3198b1cd890dd7fcb425a8d37d45861e004c7ea6b6c34eb786ee8eb629",
-        "bytes": 2271214813},
-    # profiles/k_sel_c2_512_hbm_counters.md (mean over the 800 draws of the bench's run)
-    ("selected", "c2_512", "f32", 0.5, 0.5, 7, "fwd"): {
-        "sha256": "664385127ff97608f2e84818929717d7037728b012ac3e7faefc1bda8e006092",
-        "bytes": 948220927},
+        "sha256": "b5a82309c3100a2f93987e568eec2557ec7765113d054ebdcc3c3b07d18e20c4",
+        "bytes": 1421705622},
+    # profiles/k_fused_ista_c2_512_hbm_counters.md (the A x-only pass)
+    ("fused", "c2_512", "f32", "ista"): {
+        "sha256": "b5a82309c3100a2f93987e568eec2557ec7765113d054ebdcc3c3b07d18e20c4",
+        "bytes": 1415093472},
+    ("fused", "c2_512", "f32", "gd"): {
+        "sha256": "b5a82309c3100a2f93987e568eec2557ec7765113d054ebdcc3c3b07d18e20c4",
+        "bytes": 1415093472},
 }
 
 
-# Sources that determine each path's dominant kernel and the layout it reads.
+# Sources that determine each path's dominant kernel and the layout it reads
+# (the kernel's file and the block-store build it starts from).
 _KERNEL_SOURCES = {
-    "fused": ("fused.hip", "plan.hip", "bsgd_internal.h"),
-    "rows": ("spmv.hip", "plan.hip", "staged.hip", "bsgd_internal.h"),
-    "selected": ("spmv.hip", "plan.hip", "bsgd_internal.h"),
+    "fused": ("fused.hip", "plan.hip"),
+    "rows": ("spmv.hip", "plan.hip", "staged.hip"),
+    "selected": ("spmv.hip", "plan.hip", "state.hip"),
 }
 
 

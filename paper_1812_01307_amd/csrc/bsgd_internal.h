@@ -259,15 +259,28 @@ hipError_t launch_segment_rows(const bsgd_plan* p, bool fwd, bsgd_valtype vt, in
 // r_int + ray] = segment-j product for drawn j, r_out = y - sum_j Z[j]
 // (ascending j, all blocks); other rays copy r_in.  Backward: for pixels of
 // drawn column blocks, out = xadd + scale * (sum of the drawn row blocks'
-// segments . r); other pixels copy xadd.
+// segments . r); other pixels copy xadd.  Both read the block-major copies.
 constexpr int kMaxSelBlocks = 64;
+// Block-major copy of a store direction: segment j of row k at off[j * nrows
+// + k] (nrows * nseg + 1 offsets), padded to multiples of 4 entries.
+struct BlockMajor {
+  int64_t nrows = 0;
+  int nseg = 0;
+  int64_t* off = nullptr;
+  int32_t* col = nullptr;
+  float* val = nullptr;
+  __half* val16 = nullptr;
+};
+size_t block_major_entries(const Store& st);  // capacity of col / val
+hipError_t build_block_major(const Store& st, BlockMajor& bm, int64_t* scan_tmp, hipStream_t s);
 hipError_t launch_block_ids(const bsgd_plan* p, uint8_t* blk_r, uint8_t* blk_c, hipStream_t s);
-hipError_t launch_sel_forward(const Store& st, bsgd_valtype vt, const uint8_t* blk,
-                              uint64_t rows, uint64_t cols, const float* x, const float* y,
-                              const float* r_in, float* r_out, float* Z, hipStream_t s);
-hipError_t launch_sel_backward(const Store& st, bsgd_valtype vt, const uint8_t* blk,
-                               uint64_t rows, uint64_t cols, const float* r, const float* xadd,
-                               float scale, float* out, hipStream_t s);
+hipError_t launch_sel_forward(const Store& st, const BlockMajor& bm, bsgd_valtype vt,
+                              const uint8_t* blk, uint64_t rows, uint64_t cols, const float* x,
+                              const float* y, const float* r_in, float* r_out, float* Z,
+                              hipStream_t s);
+hipError_t launch_sel_backward(const Store& st, const BlockMajor& bm, bsgd_valtype vt,
+                               const uint8_t* blk, uint64_t rows, uint64_t cols, const float* r,
+                               const float* xadd, float scale, float* out, hipStream_t s);
 
 // Natural <-> internal vector orders (holes are written as 0).  With S > 1
 // the vectors are [rows][S] matrices (RHS fastest) and whole rows move.

@@ -286,12 +286,12 @@ __device__ __forceinline__ f32x4 ld_val4(const VT* p) {
   }
 }
 
-// Sum of val[e] * v[col[e]] over the entries [beg, end) of one row, by a
-// group of LPR lanes: each lane takes the 4-aligned chunks (16-byte loads)
+// Sum of val[e] * v[col[e]] over the entries [beg, end) of one segment, by
+// a group of LPR lanes: each lane takes the 4-aligned chunks (16-byte loads)
 // that overlap the range, LPR chunks apart, and zeroes the entries outside
-// it.  Rows start at multiples of kPad entries and their padding repeats a
-// real column, so every chunk lies inside the row's storage and every
-// gathered index is valid.
+// it.  Segments of the block-major copy start at multiples of 4 entries and
+// are padded to one with a real column, so every chunk lies inside the
+// segment's storage and every gathered index is valid.
 template <typename VT, int LPR>
 __device__ __forceinline__ float seg_dot(const int32_t* __restrict__ col,
                                          const VT* __restrict__ val, const float* __restrict__ v,
@@ -326,14 +326,57 @@ __global__ __launch_bounds__(256) void k_block_ids(Layout L, BlockBounds b, uint
   }
 }
 
+// Block-major copy of one direction of the block store.  Segment j of row
+// k (the entries of block j in that row) moves to bm.off[j * nrows + k],
+// padded with zero values to a multiple of 4 entries on a column the row
+// already uses; the segments of one block j lie back to back in internal
+// row order, so the drawn blocks of consecutive rows are contiguous.
+__global__ __launch_bounds__(256) void k_bm_len(const int32_t* __restrict__ seg, int nseg,
+                                                int64_t nrows, int64_t* __restrict__ len4) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nrows * nseg;
+       i += (int64_t)gridDim.x * 256) {
+    const int j = (int)(i / nrows);
+    const int64_t k = i - (int64_t)j * nrows;
+    const int32_t* sg = seg + k * (nseg + 1);
+    len4[i] = (sg[j + 1] - sg[j] + 3) & ~3;
+  }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_bm_copy(const int64_t* __restrict__ ptr,
+                                                 const int32_t* __restrict__ seg, int nseg,
+                                                 const int32_t* __restrict__ col,
+                                                 const VT* __restrict__ val, int64_t nrows,
+                                                 const int64_t* __restrict__ off,
+                                                 int32_t* __restrict__ ocol, VT* __restrict__ oval) {
+  // one wavefront per (row, block) segment
+  const int64_t w = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (w >= nrows * nseg) return;
+  const int j = (int)(w / nrows);
+  const int64_t k = w - (int64_t)j * nrows;
+  const int32_t* sg = seg + k * (nseg + 1);
+  const int64_t src = ptr[k] + sg[j], len = sg[j + 1] - sg[j];
+  const int64_t dst = off[w], len4 = off[w + 1] - dst;
+  for (int64_t e = lane; e < len4; e += 64) {
+    if (e < len) {
+      ocol[dst + e] = col[src + e];
+      oval[dst + e] = val[src + e];
+    } else {
+      ocol[dst + e] = col[src + len - 1];  // len4 > len implies len >= 1
+      oval[dst + e] = VT(0.f);
+    }
+  }
+}
+
 // Lines 4 and 6 for the drawn pairs.  A ray of a drawn row block computes
 // z^j (its segment j) for every drawn column block j and keeps it in
 // Z[j * nrows + ray]; its residual becomes y - sum_j Z[j] over all column
 // blocks, ascending j (kept products for the others).  Other rays copy
-// r_in to r_out.
+// r_in to r_out.  Segments are read from the block-major copy.
 template <typename VT, int LPR>
 __global__ __launch_bounds__(256) void k_sel_forward(
-    const int64_t* __restrict__ ptr, const int32_t* __restrict__ seg, int nseg,
+    const int32_t* __restrict__ seg, int nseg, const int64_t* __restrict__ off,
     const int32_t* __restrict__ col, const VT* __restrict__ val, const uint8_t* __restrict__ blk,
     uint64_t rows, uint64_t cols, const float* __restrict__ x, const float* __restrict__ y,
     const float* __restrict__ r_in, float* __restrict__ r_out, float* __restrict__ Z,
@@ -346,13 +389,13 @@ __global__ __launch_bounds__(256) void k_sel_forward(
     if (lane == 0) r_out[row] = r_in[row];
     return;
   }
-  const int64_t base = ptr[row];
   const int32_t* sg = seg + row * (nseg + 1);
   float tot = 0.f;
   for (int j = 0; j < nseg; ++j) {
     float zj;
     if ((cols >> j) & 1) {
-      zj = group_sum<LPR>(seg_dot<VT, LPR>(col, val, x, base + sg[j], base + sg[j + 1], lane));
+      const int64_t beg = off[(int64_t)j * nrows + row];
+      zj = group_sum<LPR>(seg_dot<VT, LPR>(col, val, x, beg, beg + (sg[j + 1] - sg[j]), lane));
       if (lane == 0) Z[j * nrows + row] = zj;
     } else {
       zj = Z[j * nrows + row];
@@ -367,7 +410,7 @@ __global__ __launch_bounds__(256) void k_sel_forward(
 // blocks: out = xadd + scale * sum; other pixels copy xadd.
 template <typename VT, int LPR>
 __global__ __launch_bounds__(256) void k_sel_backward(
-    const int64_t* __restrict__ ptr, const int32_t* __restrict__ seg, int nseg,
+    const int32_t* __restrict__ seg, int nseg, const int64_t* __restrict__ off,
     const int32_t* __restrict__ col, const VT* __restrict__ val, const uint8_t* __restrict__ blk,
     uint64_t rows, uint64_t cols, const float* __restrict__ r, const float* __restrict__ xadd,
     float scale, float* __restrict__ out, int64_t nrows) {
@@ -379,11 +422,13 @@ __global__ __launch_bounds__(256) void k_sel_backward(
     if (lane == 0) out[row] = xadd[row];
     return;
   }
-  const int64_t base = ptr[row];
   const int32_t* sg = seg + row * (nseg + 1);
   float acc = 0.f;
   for (int i = 0; i < nseg; ++i)
-    if ((rows >> i) & 1) acc += seg_dot<VT, LPR>(col, val, r, base + sg[i], base + sg[i + 1], lane);
+    if ((rows >> i) & 1) {
+      const int64_t beg = off[(int64_t)i * nrows + row];
+      acc += seg_dot<VT, LPR>(col, val, r, beg, beg + (sg[i + 1] - sg[i]), lane);
+    }
   acc = group_sum<LPR>(acc);
   if (lane == 0) out[row] = fmaf(scale, acc, xadd[row]);
 }
@@ -402,36 +447,61 @@ hipError_t launch_block_ids(const bsgd_plan* p, uint8_t* blk_r, uint8_t* blk_c, 
   return hipGetLastError();
 }
 
+size_t block_major_entries(const Store& st) {
+  return (size_t)(st.nnz + 3 * st.nrows * (int64_t)st.nseg + 4);
+}
+
+hipError_t build_block_major(const Store& st, BlockMajor& bm, int64_t* scan_tmp, hipStream_t s) {
+  const int64_t n = st.nrows * st.nseg;
+  bm.nrows = st.nrows;
+  bm.nseg = st.nseg;
+  k_bm_len<<<std::max<unsigned>(1, std::min<unsigned>((unsigned)((n + 255) / 256), 4096)), 256,
+             0, s>>>(st.seg, st.nseg, st.nrows, bm.off);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = exclusive_scan_i64(bm.off, bm.off, n, scan_tmp, s);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = (unsigned)((n * 64 + 255) / 256);
+  if (blocks == 0) return hipSuccess;
+  k_bm_copy<float><<<blocks, 256, 0, s>>>(st.ptr, st.seg, st.nseg, st.col, st.val, st.nrows,
+                                           bm.off, bm.col, bm.val);
+  if (bm.val16)
+    k_bm_copy<__half><<<blocks, 256, 0, s>>>(st.ptr, st.seg, st.nseg, st.col, st.val16,
+                                              st.nrows, bm.off, bm.col, bm.val16);
+  return hipGetLastError();
+}
+
 constexpr int kSelLanes = 8;
 
-hipError_t launch_sel_forward(const Store& st, bsgd_valtype vt, const uint8_t* blk,
-                              uint64_t rows, uint64_t cols, const float* x, const float* y,
-                              const float* r_in, float* r_out, float* Z, hipStream_t s) {
+hipError_t launch_sel_forward(const Store& st, const BlockMajor& bm, bsgd_valtype vt,
+                              const uint8_t* blk, uint64_t rows, uint64_t cols, const float* x,
+                              const float* y, const float* r_in, float* r_out, float* Z,
+                              hipStream_t s) {
   const unsigned blocks = (unsigned)((st.nrows * kSelLanes + 255) / 256);
   if (!blocks) return hipSuccess;
   if (vt == BSGD_VAL_F16)
     k_sel_forward<__half, kSelLanes><<<blocks, 256, 0, s>>>(
-        st.ptr, st.seg, st.nseg, st.col, st.val16, blk, rows, cols, x, y, r_in, r_out, Z,
+        st.seg, st.nseg, bm.off, bm.col, bm.val16, blk, rows, cols, x, y, r_in, r_out, Z,
         st.nrows);
   else
     k_sel_forward<float, kSelLanes><<<blocks, 256, 0, s>>>(
-        st.ptr, st.seg, st.nseg, st.col, st.val, blk, rows, cols, x, y, r_in, r_out, Z,
+        st.seg, st.nseg, bm.off, bm.col, bm.val, blk, rows, cols, x, y, r_in, r_out, Z,
         st.nrows);
   return hipGetLastError();
 }
 
-hipError_t launch_sel_backward(const Store& st, bsgd_valtype vt, const uint8_t* blk,
-                               uint64_t rows, uint64_t cols, const float* r, const float* xadd,
-                               float scale, float* out, hipStream_t s) {
+hipError_t launch_sel_backward(const Store& st, const BlockMajor& bm, bsgd_valtype vt,
+                               const uint8_t* blk, uint64_t rows, uint64_t cols, const float* r,
+                               const float* xadd, float scale, float* out, hipStream_t s) {
   const unsigned blocks = (unsigned)((st.nrows * kSelLanes + 255) / 256);
   if (!blocks) return hipSuccess;
   if (vt == BSGD_VAL_F16)
     k_sel_backward<__half, kSelLanes><<<blocks, 256, 0, s>>>(
-        st.ptr, st.seg, st.nseg, st.col, st.val16, blk, rows, cols, r, xadd, scale, out,
+        st.seg, st.nseg, bm.off, bm.col, bm.val16, blk, rows, cols, r, xadd, scale, out,
         st.nrows);
   else
     k_sel_backward<float, kSelLanes><<<blocks, 256, 0, s>>>(
-        st.ptr, st.seg, st.nseg, st.col, st.val, blk, rows, cols, r, xadd, scale, out,
+        st.seg, st.nseg, bm.off, bm.col, bm.val, blk, rows, cols, r, xadd, scale, out,
         st.nrows);
   return hipGetLastError();
 }

@@ -40,6 +40,9 @@ struct bsgd_state {
   float* zt = nullptr;                  // BSGD_STATE_BLOCK_SELECT: kept products, [N][r_int]
   uint8_t* blk_r = nullptr;             // ... row block of each internal ray (0xFF: hole)
   uint8_t* blk_c = nullptr;             // ... column block of each internal pixel
+  bsgd::BlockMajor bmf, bmb;            // ... block-major copies of A and A^T
+  int64_t* bm_scan = nullptr;           // ... scan scratch for building them
+  bool bm_built = false;
   int64_t epochs_done = 0;
   bool initialised = false;
   hipStream_t aux = nullptr;
@@ -156,6 +159,18 @@ static size_t state_layout(const bsgd_plan* p, int S, unsigned flags, void* ws, 
     st->zt = cv.take<float>((size_t)p->N * p->L.r_int);
     st->blk_r = cv.take<uint8_t>(p->L.r_int);
     st->blk_c = cv.take<uint8_t>(p->L.c_int);
+    const bool f16 = p->fwd.val16 != nullptr;
+    for (int d = 0; d < 2; ++d) {
+      const Store& so = d == 0 ? p->fwd : p->bwd;
+      BlockMajor& bm = d == 0 ? st->bmf : st->bmb;
+      const size_t cap = block_major_entries(so);
+      bm.off = cv.take<int64_t>((size_t)so.nrows * so.nseg + 1);
+      bm.col = cv.take<int32_t>(cap);
+      bm.val = cv.take<float>(cap);
+      bm.val16 = f16 ? cv.take<__half>(cap) : nullptr;
+    }
+    st->bm_scan = cv.take<int64_t>(
+        scan_tmp_count(std::max(p->fwd.nrows * p->fwd.nseg, p->bwd.nrows * p->bwd.nseg)));
   }
   return align_up(cv.off, kAlign);
 }
@@ -377,10 +392,15 @@ extern "C" bsgd_status bsgd_state_init(bsgd_state* st, const float* y, const flo
     BSGD_HIP(hipMemcpyAsync(st->r[0], st->y, sizeof(float) * r, hipMemcpyDeviceToDevice, stream));
   }
   if (st->zt) {
-    BSGD_HIP(launch_block_ids(p, st->blk_r, st->blk_c, stream));
+    if (!st->bm_built) {  // block ids and block-major copies: once per state
+      BSGD_HIP(launch_block_ids(p, st->blk_r, st->blk_c, stream));
+      BSGD_HIP(build_block_major(p->fwd, st->bmf, st->bm_scan, stream));
+      BSGD_HIP(build_block_major(p->bwd, st->bmb, st->bm_scan, stream));
+      st->bm_built = true;
+    }
     if (x0)  // kept products of x0 and their residual
-      BSGD_HIP(launch_sel_forward(p->fwd, st->vt, st->blk_r, ~0ull, ~0ull, st->x[0], st->y,
-                                  st->r[0], st->r[0], st->zt, stream));
+      BSGD_HIP(launch_sel_forward(p->fwd, st->bmf, st->vt, st->blk_r, ~0ull, ~0ull, st->x[0],
+                                  st->y, st->r[0], st->r[0], st->zt, stream));
     else
       BSGD_HIP(fill_f32(st->zt, (int64_t)p->N * p->L.r_int, 0.0f, stream));
   }
@@ -400,8 +420,8 @@ extern "C" bsgd_status bsgd_state_load(bsgd_state* st, const float* x, const flo
   BSGD_HIP(permute_in(p->L, kPixels, x, st->x[0], stream, st->nrhs));
   BSGD_HIP(permute_in(p->L, kRays, r, st->r[0], stream, st->nrhs));
   if (st->zt)  // kept products of the loaded x (their residual goes to scratch)
-    BSGD_HIP(launch_sel_forward(p->fwd, st->vt, st->blk_r, ~0ull, ~0ull, st->x[0], st->y,
-                                st->r[0], st->tmp_r, st->zt, stream));
+    BSGD_HIP(launch_sel_forward(p->fwd, st->bmf, st->vt, st->blk_r, ~0ull, ~0ull, st->x[0],
+                                st->y, st->r[0], st->tmp_r, st->zt, stream));
   st->epochs_done = epoch;
   return BSGD_OK;
 }
@@ -689,12 +709,12 @@ extern "C" bsgd_status bsgd_run_selected(bsgd_state* st, float mu, float lam, in
     hipEvent_t* tv = st->t_used < st->t_cap ? &st->tev[5 * (size_t)st->t_used++] : nullptr;
     // lines 4 + 6 with the current x; lines 3, 7, 8 with the kept residual
     if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
-    BSGD_HIP(launch_sel_forward(p->fwd, st->vt, st->blk_r, rows_sel[t], cols_sel[t], st->x[c],
-                                st->y, st->r[c], st->r[n], st->zt, stream));
+    BSGD_HIP(launch_sel_forward(p->fwd, st->bmf, st->vt, st->blk_r, rows_sel[t], cols_sel[t],
+                                st->x[c], st->y, st->r[c], st->r[n], st->zt, stream));
     if (tv) BSGD_HIP(hipEventRecord(tv[1], stream));
     if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
-    BSGD_HIP(launch_sel_backward(p->bwd, st->vt, st->blk_c, rows_sel[t], cols_sel[t], st->r[c],
-                                 st->x[c], 2.0f * mu, step_out, stream));
+    BSGD_HIP(launch_sel_backward(p->bwd, st->bmb, st->vt, st->blk_c, rows_sel[t], cols_sel[t],
+                                 st->r[c], st->x[c], 2.0f * mu, step_out, stream));
     if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
     if (theta != 0.f) BSGD_HIP(prox_step(st, mu, lam, false, prox_iters, st->x[n], stream));
     if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));

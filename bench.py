@@ -42,6 +42,10 @@ PMC_TRAFFIC = {
     ("fused", "c2_512", "f32", "gd"): {
         "sha256": "b5a82309c3100a2f93987e568eec2557ec7765113d054ebdcc3c3b07d18e20c4",
         "bytes": 1415093472},
+    # profiles/k_sel_c2_512_hbm_counters.md (mean over the 800 draws of the bench's run)
+    ("selected", "c2_512", "f32", 0.5, 0.5, 7, "fwd"): {
+        "sha256": "860e5417775ad0739ac4b171aafb144fb3321240362bd759314d7a29516de2bd",
+        "bytes": 903889374},
 }
 
 

@@ -8,9 +8,9 @@ Test infrastructure (runs the oracle on the CPU; too slow for the test suite):
       mu = 0.9 / (2 u_max) rounded to FP32.  Both sides use this mu.
 
   python bench.py --config c3_1024 --vt f32 --mu-file tests/golden/c3_1024_mu.json \
-      --dump-every 50 --dump gpurun_out/c3_f32.npz   (on the GPU; likewise --vt f16)
+      --dump-every 50 --dump c3_f32.npz   (on the GPU; likewise --vt f16)
 
-  python tests/precision_c3.py compare gpurun_out/c3_f32.npz gpurun_out/c3_f16.npz
+  python tests/precision_c3.py compare c3_f32.npz c3_f16.npz
       Runs 300 oracle epochs (FP64 values, the FP32-rounded y and mu) and
       prints the relative L2 error ||x_dev - x_orc|| / ||x_orc|| of each
       device run every 50 epochs.  With --dequantised, the oracle uses the

@@ -33,15 +33,15 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {
     # profiles/k_fused_c2_512_hbm_counters.md
     ("fused", "c2_512", "f32"): {
-        "sha256": "b5a82309c3100a2f93987e568eec2557ec7765113d054ebdcc3c3b07d18e20c4",
-        "bytes": 1421705622},
+        "sha256": "90e1851c8e3fcc208c01aa72f33af1c9bd96425568593eafeaff9432aa30d1ff",
+        "bytes": 1334577930},
     # profiles/k_fused_ista_c2_512_hbm_counters.md (the A x-only pass)
     ("fused", "c2_512", "f32", "ista"): {
-        "sha256": "b5a82309c3100a2f93987e568eec2557ec7765113d054ebdcc3c3b07d18e20c4",
-        "bytes": 1415093472},
+        "sha256": "90e1851c8e3fcc208c01aa72f33af1c9bd96425568593eafeaff9432aa30d1ff",
+        "bytes": 1310828314},
     ("fused", "c2_512", "f32", "gd"): {
-        "sha256": "b5a82309c3100a2f93987e568eec2557ec7765113d054ebdcc3c3b07d18e20c4",
-        "bytes": 1415093472},
+        "sha256": "90e1851c8e3fcc208c01aa72f33af1c9bd96425568593eafeaff9432aa30d1ff",
+        "bytes": 1310828314},
     # profiles/k_sel_c2_512_hbm_counters.md (mean over the 800 draws of the bench's run)
     ("selected", "c2_512", "f32", 0.5, 0.5, 7, "fwd"): {
         "sha256": "860e5417775ad0739ac4b171aafb144fb3321240362bd759314d7a29516de2bd",

@@ -491,7 +491,7 @@ void bsgd_graph_destroy(bsgd_graph* graph);
  * a = A[rho, p].  An epoch then reads the matrix once instead of once as A
  * and once as A^T.
  *
- * The tile-sliced store regroups the plan's forward store: pixels in 32 x 32
+ * The tile-sliced store regroups the plan's forward store: pixels in 64 x 64
  * tiles, rays in `chunks` chunks of whole ray groups (8 interleaved views when
  * the plan has view_len > 0); the part of one ray inside one tile (a
  * segment) is one lane's list of (16-bit tile-local column, value) entries.
@@ -507,14 +507,14 @@ void bsgd_graph_destroy(bsgd_graph* graph);
  * order by a second kernel, so results are bitwise reproducible for a given
  * store (and differ from the row kernels by summation order only).  FP16
  * values are available when the plan has BSGD_PLAN_F16.  Images wider than
- * 2048 pixels are not supported (BSGD_ERR_UNSUPPORTED).
+ * 4096 pixels are not supported (BSGD_ERR_UNSUPPORTED).
  *
  *   fused_workspace_size  counts the segments of `plan` (device pass over the
  *               forward store, uses the plan's scratch vectors: no other call
  *               on the plan may overlap it) and returns the workspace bytes
  *               for bsgd_fused_create with the same chunks and flags.  chunks = 0
- *               picks about 2048 (tile, chunk) units; chunks <= number of ray
- *               groups.  Synchronises `stream`.
+ *               picks at least about 1024 (tile, chunk) units and chunks of at
+ *               most 131072 rays; chunks <= number of ray groups.  Synchronises `stream`.
  *   fused_create  builds the store in `workspace` (device, 256-byte aligned,
  *               at least the size returned above) from the plan's forward
  *               store; the plan must outlive it.  Synchronises.

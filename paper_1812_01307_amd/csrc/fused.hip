@@ -7,7 +7,7 @@
 //     g[p]   += a * r_k[rho]    (line 3; summed over the row blocks:    line 7)
 // which reads the matrix once per epoch instead of once as A and once as A^T.
 //
-// Tile-sliced store.  Pixels are grouped into 32 x 32 tiles (4 x 4 of the
+// Tile-sliced store.  Pixels are grouped into 64 x 64 tiles (8 x 8 of the
 // internal 8 x 8 tiles, across slices for volumes); rays into Q chunks of
 // whole ray groups (8 interleaved views, see bsgd::Layout).  A segment is
 // the part of one ray inside one tile.  Unit u = (tile, chunk) holds the
@@ -19,9 +19,9 @@
 // lane-interleaved in groups of 4:
 //     entry j of lane l at soff[s] + (j / 4) * 256 + l * 4 + j % 4
 // as a column and an FP32 value (optional FP16 copy).  The column is the
-// pixel's address in the tile's LDS image (row stride 33); entries of a
+// pixel's address in the tile's LDS image (row stride 65); entries of a
 // segment are in ascending address order, and when every step from one
-// entry to the next is below 256 (always for rays: at most 65) the store
+// entry to the next is below 256 (for rays: about one row stride) the store
 // keeps 8-bit steps with a 16-bit start address per lane (5 bytes per entry
 // with FP32 values, 3 with FP16), else 16-bit addresses.  Lanes shorter than
 // the slice's longest are padded with zero values on an address they
@@ -60,15 +60,15 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kFT = 32;              // tile side in pixels
+constexpr int kFT = 64;              // tile side in pixels
 constexpr int kFTS = kFT + 1;        // LDS row stride (rows and columns hit distinct banks)
 constexpr int kFTA = kFT * kFTS;     // LDS floats per tile image
-constexpr int kKeyLen = 2048;        // key >> 32 = unit * 2048 + (2047 - segment length)
+constexpr int kKeyLen = 8192;        // key >> 32 = unit * 8192 + (8191 - segment length)
 constexpr int kMaxSeg = kFT * kFT;   // a segment holds at most one entry per pixel
 
 struct TileGeom {
   int Ht = 1, Wt = 1;        // 8 x 8 tiles per image column / row
-  int FTh = 1, FTw = 1;      // 32 x 32 tiles per image column / row
+  int FTh = 1, FTw = 1;      // 64 x 64 tiles per image column / row
   int D = 1;
   int Q = 1;                 // ray chunks
   int64_t slice_px = 0;      // internal pixels per slice (Ht * Wt * 64)
@@ -115,8 +115,8 @@ static TileGeom tile_geom(const Layout& L, int chunks) {
   TileGeom g;
   g.Ht = L.Ht;
   g.Wt = L.Wt;
-  g.FTh = (L.Ht + 3) / 4;
-  g.FTw = (L.Wt + 3) / 4;
+  g.FTh = (L.Ht + 7) / 8;
+  g.FTw = (L.Wt + 7) / 8;
   g.D = L.D;
   g.slice_px = (int64_t)L.Ht * L.Wt * 64;
   g.view_len = L.view_len;
@@ -130,11 +130,11 @@ static TileGeom tile_geom(const Layout& L, int chunks) {
   if (chunks > 0) {
     g.Q = chunks;
   } else {
-    // at least about 2048 unit workgroups, and chunks of at most 128 K rays
+    // at least about 1024 unit workgroups, and chunks of at most 128 K rays
     // (512 KB of r, so that a unit's residual gathers stay in L2; measured
-    // on gfx950: 8 chunks at 512^2 and 16 at 1024^2, 11% faster epochs
-    // there than 2), no more chunks than ray groups
-    const int64_t want = std::max<int64_t>((2048 + g.tiles() - 1) / g.tiles(),
+    // on gfx950: 16 chunks at 512^2 and at 1024^2, within 1% of the best
+    // of 8 to 32 at both), no more chunks than ray groups
+    const int64_t want = std::max<int64_t>((1024 + g.tiles() - 1) / g.tiles(),
                                            (L.r_int + 131071) / 131072);
     g.Q = (int)std::max<int64_t>(1, std::min<int64_t>(want, g.ngroups));
   }
@@ -153,9 +153,9 @@ __device__ __forceinline__ void decode_pixel(const TileGeom& g, int64_t cp, int&
   const int64_t rem = cp - d * g.slice_px;
   const int t8 = (int)(rem >> 6), w = (int)(rem & 63);
   const int tr8 = t8 / g.Wt, tc8 = t8 - tr8 * g.Wt;
-  G = (int)d * g.FTh + (tr8 >> 2);
-  f = tc8 >> 2;
-  a = (((tr8 & 3) << 3) + (w >> 3)) * kFTS + ((tc8 & 3) << 3) + (w & 7);
+  G = (int)d * g.FTh + (tr8 >> 3);
+  f = tc8 >> 3;
+  a = (((tr8 & 7) << 3) + (w >> 3)) * kFTS + ((tc8 & 7) << 3) + (w & 7);
 }
 
 // Walk one ray's entries (one wavefront; the entries are in ascending natural
@@ -629,9 +629,9 @@ __global__ __launch_bounds__(64 * W) void k_fused(
   if constexpr (MODE != kPassAt)
     for (int i = tid; i < kFT * kFT; i += NT) {
       const int b = i >> 6, w = i & 63;
-      const int tr8 = ftr * 4 + (b >> 2), tc8 = ftc * 4 + (b & 3);
+      const int tr8 = ftr * 8 + (b >> 3), tc8 = ftc * 8 + (b & 7);
       if (tr8 < g.Ht && tc8 < g.Wt)
-        xs[(((b >> 2) << 3) + (w >> 3)) * kFTS + ((b & 3) << 3) + (w & 7)] =
+        xs[(((b >> 3) << 3) + (w >> 3)) * kFTS + ((b & 7) << 3) + (w & 7)] =
             x[xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w];
     }
   const int e = MODE == kPassA ? 0 : fixed_exponent(smax, __uint_as_float(*rmax_in));
@@ -698,9 +698,9 @@ __global__ __launch_bounds__(64 * W) void k_fused(
   const double inv = ldexp(1.0, -e);
   for (int i = tid; i < kFT * kFT; i += NT) {
     const int b = i >> 6, w = i & 63;
-    const int tr8 = ftr * 4 + (b >> 2), tc8 = ftc * 4 + (b & 3);
+    const int tr8 = ftr * 8 + (b >> 3), tc8 = ftc * 8 + (b & 7);
     if (tr8 < g.Ht && tc8 < g.Wt) {
-      const int a = (((b >> 2) << 3) + (w >> 3)) * kFTS + ((b & 3) << 3) + (w & 7);
+      const int a = (((b >> 3) << 3) + (w >> 3)) * kFTS + ((b & 7) << 3) + (w & 7);
       gp[(int64_t)q * c_int + xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w] =
           (float)from_fixed(gs[a], inv);
     }
@@ -989,8 +989,8 @@ static bsgd_status fused_check(const bsgd_plan* p, int chunks, unsigned flags, T
   BSGD_REQUIRE((flags & ~BSGD_FUSED_WIDE) == 0, "unknown single-pass flags 0x%x", flags);
   BSGD_REQUIRE(chunks >= 0, "chunks must be >= 0 (0: automatic)");
   const Layout& L = p->L;
-  if ((L.Wt + 3) / 4 > 64) {
-    set_error("the single-pass form supports images up to 2048 pixels wide");
+  if ((L.Wt + 7) / 8 > 64) {
+    set_error("the single-pass form supports images up to 4096 pixels wide");
     return BSGD_ERR_UNSUPPORTED;
   }
   *g = tile_geom(L, chunks);

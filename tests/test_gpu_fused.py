@@ -22,11 +22,11 @@ def _host(t):
 def _cases():
     return {
         "c1": lambda: problem("c1_64"),
-        # many slices per (tile, chunk) unit, full and partial 32 x 32 tiles
-        "medium": lambda: problem(None, H=192, W=192, n_ang=180, bins=273, M=4, N=4, seed=7),
+        # many slices per (tile, chunk) unit, full and partial 64 x 64 tiles
+        "medium": lambda: problem(None, H=176, W=176, n_ang=180, bins=273, M=4, N=4, seed=7),
         # most rays miss the image (empty rows and empty chunks)
         "wide": lambda: problem(None, H=64, W=64, n_ang=16, bins=2500, M=2, N=2, seed=8),
-        # non-square, ragged 8 x 8 and 32 x 32 tiles, ragged view groups
+        # non-square, ragged 8 x 8 and 64 x 64 tiles, ragged view groups
         "ragged": ragged_problem,
         # a single pixel row and a single tile column
         "strip": lambda: problem(None, H=1, W=40, n_ang=12, bins=45, M=2, N=2, seed=9, lam=0.0),
@@ -34,12 +34,12 @@ def _cases():
 
 
 def _segments(p, view_len):
-    """Independent count of (ray, 32 x 32 tile) pairs with an entry, from the host CSR."""
+    """Independent count of (ray, 64 x 64 tile) pairs with an entry, from the host CSR."""
     rows = np.repeat(np.arange(p.nrows, dtype=np.int64), np.diff(p.row_ptr))
     col = np.asarray(p.col, np.int64)
     s, t = col // p.W, col % p.W
-    ftw = (p.W + 31) // 32
-    key = rows * (((p.H + 31) // 32) * ftw) + (s // 32) * ftw + t // 32
+    ftw = (p.W + 63) // 64
+    key = rows * (((p.H + 63) // 64) * ftw) + (s // 64) * ftw + t // 64
     return len(np.unique(key))
 
 
@@ -60,7 +60,7 @@ def test_fused_products_match_oracle(name, view_len):
     F = _fused(plan)
     tiles, chunks, segs, slices, entries, cbytes = bsgd.bsgd_fused_shape(F)
     assert cbytes == 1  # rays: steps between successive pixels of a tile are below 256
-    assert tiles == ((p.H + 31) // 32) * ((p.W + 31) // 32)
+    assert tiles == ((p.H + 63) // 64) * ((p.W + 63) // 64)
     assert segs == _segments(p, view_len)
     assert slices * 64 >= segs and entries >= p.nnz and entries % 256 == 0
     A, Aabs = matrix(p), abs_matrix(p)
@@ -243,7 +243,7 @@ def test_fused_full_size_sampled():
     plan = plan_for(p)
     F = _fused(plan)
     tiles, chunks, segs, slices, entries, cbytes = bsgd.bsgd_fused_shape(F)
-    assert tiles == 256 and segs > p.nrows and entries >= p.nnz and cbytes == 1
+    assert tiles == 64 and segs > p.nrows and entries >= p.nnz and cbytes == 1
     rng = np.random.default_rng(12)
     x = f32(rng.random(p.ncols))
     r = f32(rng.standard_normal(p.nrows))

@@ -44,8 +44,8 @@ PMC_TRAFFIC = {
         "bytes": 1310828314},
     # profiles/k_sel_c2_512_hbm_counters.md (mean over the 800 draws of the bench's run)
     ("selected", "c2_512", "f32", 0.5, 0.5, 7, "fwd"): {
-        "sha256": "860e5417775ad0739ac4b171aafb144fb3321240362bd759314d7a29516de2bd",
-        "bytes": 903889374},
+        "sha256": "012914dfb0429d0933058aa39fabe945e921c9c1c33ec648dcb109cb2c28384b",
+        "bytes": 614018393},
 }
 
 

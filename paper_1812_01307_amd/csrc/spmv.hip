@@ -596,14 +596,18 @@ extern "C" bsgd_status bsgd_backproject_block(const bsgd_plan* plan, bsgd_valtyp
 // ---------------------------------------------------------------------------
 // Several right-hand sides (slices of a volume, or a batch of reconstructions
 // sharing A): V is [ncols_int][S], Y / XADD / OUT are [nrows_int][S], the RHS
-// index fastest.  Each lane owns 4 consecutive RHS, so L = min(S/4, 64) lanes
+// index fastest.  Each lane owns 4 consecutive RHS, so L = min(S/4, 16) lanes
 // cover a chunk of 4L RHS (one 16-byte gather per lane and entry, 16L bytes
-// contiguous per entry).  When S is small the row's entries are split over G
+// contiguous per entry).  Chunks of at most 64 RHS keep the rows gathered by
+// one chunk (256 bytes per vector row: 67 MB for a 512 x 512 image) inside
+// the 256 MB last-level cache: 256 RHS at once (268 MB) made the 256-slice
+// volume's epochs 16% slower on gfx950, although A is read once per chunk.  When S is small the row's entries are split over G
 // groups of L lanes (G = 8 for L <= 8, else 64/L): group g takes the 4-entry
 // chunks g, g + G, ... (rows are padded to a multiple of 8 entries, so chunks
 // never straddle the row end), and the G partial sums are added with xor
 // shuffles in a fixed order.  A row uses L*G lanes; a wavefront holds 64/(L*G)
-// rows.  blockIdx.y selects the RHS chunk when S > 256.  No atomics; the
+// rows.  blockIdx.y selects the RHS chunk when S > 64 (the chunks run in
+// order: blockIdx.x varies fastest in the launch).  No atomics; the
 // summation order depends only on S.
 // ---------------------------------------------------------------------------
 namespace bsgd {
@@ -700,14 +704,12 @@ static hipError_t launch_spmm_mode(const Store& st, bsgd_valtype vt, const float
                                    const float* Y, const float* XADD, float scale, float* OUT,
                                    int S, hipStream_t s) {
   // S is 4 .. 1024 and a power of two (checked when the state is created)
-  switch (S >= 256 ? 64 : S / 4) {
+  switch (std::min(S / 4, 16)) {
     case 1: return launch_spmm_l<MODE, 1>(st, vt, V, Y, XADD, scale, OUT, S, s);
     case 2: return launch_spmm_l<MODE, 2>(st, vt, V, Y, XADD, scale, OUT, S, s);
     case 4: return launch_spmm_l<MODE, 4>(st, vt, V, Y, XADD, scale, OUT, S, s);
     case 8: return launch_spmm_l<MODE, 8>(st, vt, V, Y, XADD, scale, OUT, S, s);
     case 16: return launch_spmm_l<MODE, 16>(st, vt, V, Y, XADD, scale, OUT, S, s);
-    case 32: return launch_spmm_l<MODE, 32>(st, vt, V, Y, XADD, scale, OUT, S, s);
-    case 64: return launch_spmm_l<MODE, 64>(st, vt, V, Y, XADD, scale, OUT, S, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -754,87 +754,130 @@ hipError_t tv_prox_batch(const Layout& L, int S, const float* b, float mu, const
 
 // ---------------------------------------------------------------------------
 // 3-D FGP for a volume of S slices stored slice-minor in the internal pixel
-// order: voxel (d, s, t) at pix_st(s, t) * S + d.  One kernel per iteration:
-// a block owns one 8 x 8 memory tile of pixels times 32 slices, stages q on
-// the tile plus a one-voxel halo and u on the tile plus its lower-index halo
-// in LDS (the same recurrence as the 2-D kernels, with the difference across
-// slices added and step 1/(12 theta)).
+// order: voxel (d, s, t) at pix_st(s, t) * S + d.  One kernel per iteration
+// (the same recurrence as the 2-D kernels, with the difference across slices
+// added and step 1/(12 theta)).  A block owns one 8 x 8 memory tile of
+// pixels and walks down its slices in chunks of kVC = 32 (one 128-byte line
+// of a pixel's slices).  Chunk c0 loads q and b on slices c0 .. c0 + 31,
+// whole lines, for the tile plus a one-pixel halo; u on a slice needs q on
+// the next slice, so the chunk forms u and the new dual one slice behind,
+// on slices c0 - 1 .. c0 + 30, and carries the last q, u and b slices to the
+// next chunk.  Every line of the block's columns is read once (the halo
+// columns belong to neighbouring tiles).  LDS holds slices fastest (pitch
+// kVC + 1 floats), so a wavefront's lanes address consecutive words.
 // ---------------------------------------------------------------------------
-constexpr int kVS = 8, kVD = 32;
-constexpr int kVQ = (kVS + 2) * (kVS + 2) * (kVD + 2);
-constexpr int kVU = (kVS + 1) * (kVS + 1) * (kVD + 1);
+constexpr int kVS = 8;                       // pixel tile side
+constexpr int kVC = 32;                      // slices per chunk
+constexpr int kVQP = (kVS + 2) * (kVS + 2);  // q pixels: tile plus one-pixel halo
+constexpr int kVUP = (kVS + 1) * (kVS + 1);  // u pixels: tile plus upper/left halo
+constexpr int kVThreads = 512;
+static_assert(kVThreads % kVC == 0 && kVC == 32, "u phase: one pixel per 32 lanes");
 
-__global__ __launch_bounds__(256) void k_fgp_iter3v(
+__global__ __launch_bounds__(kVThreads) void k_fgp_iter3v(
     Layout L, int S, const float* __restrict__ b, float theta, float step, float coef, int qmode,
     const float* __restrict__ p1, const float* __restrict__ p2, float* __restrict__ po,
     int64_t n) {
-  __shared__ float sq[3][kVQ];
-  __shared__ float su[kVU];
+  // In chunk c0: sq[c][qp][j] = component c (depth, vertical, horizontal) of
+  // q on slice c0 - 1 + j of halo pixel qp = (s - s0 + 1) * 10 + (t - t0 + 1);
+  // su[up][j] = u on slice c0 - 2 + j of pixel up = (s - s0 + 1) * 9 + (t - t0 + 1);
+  // sb[c0 / kVC % 2][up] = b on slice c0 - 1.  Zero outside the volume.
+  __shared__ float sq[3][kVQP][kVC + 1];
+  __shared__ float su[kVUP][kVC + 1];
+  __shared__ float sb[2][kVUP];
   const int H = L.H, W = L.W;
   const int tile = blockIdx.x;
-  const int s0 = (tile / L.Wt) * kVS, t0 = (tile % L.Wt) * kVS, d0 = blockIdx.y * kVD;
+  const int s0 = (tile / L.Wt) * kVS, t0 = (tile % L.Wt) * kVS;
   const int tid = threadIdx.x;
-  // q on s0-1..s0+8, t0-1..t0+8, d0-1..d0+32
-  for (int q = tid; q < kVQ; q += 256) {
-    const int ld = q % (kVD + 2), rest = q / (kVD + 2);
-    const int lt = rest % (kVS + 2), ls = rest / (kVS + 2);
-    const int s = s0 - 1 + ls, t = t0 - 1 + lt, d = d0 - 1 + ld;
-    float qa = 0.f, qb = 0.f, qc = 0.f;
-    if (qmode != kQZero && s >= 0 && s < H && t >= 0 && t < W && d >= 0 && d < S) {
-      const int64_t i = L.pix_st(0, s, t) * S + d;
-      const float a1 = p1[i], b1 = p1[n + i], c1 = p1[2 * n + i];
-      if (qmode == kQCopy) {
-        qa = a1;
-        qb = b1;
-        qc = c1;
+  for (int k = tid; k < kVQP + kVUP; k += kVThreads) {
+    if (k < kVQP) {
+      sq[0][k][0] = 0.f;
+      sq[1][k][0] = 0.f;
+      sq[2][k][0] = 0.f;
+    } else {
+      su[k - kVQP][0] = 0.f;
+      sb[0][k - kVQP] = 0.f;
+    }
+  }
+  for (int c0 = 0, par = 0; c0 - 1 < S; c0 += kVC, par ^= 1) {
+    // q on slices c0 .. c0 + 31
+    for (int k = tid; k < kVQP * kVC; k += kVThreads) {
+      const int qp = k / kVC, j = k % kVC;
+      const int s = s0 - 1 + qp / (kVS + 2), t = t0 - 1 + qp % (kVS + 2), d = c0 + j;
+      float qa = 0.f, qb = 0.f, qc = 0.f;
+      if (qmode != kQZero && d < S && s >= 0 && s < H && t >= 0 && t < W) {
+        const int64_t i = L.pix_st(0, s, t) * S + d;
+        const float a1 = p1[i], b1 = p1[n + i], c1 = p1[2 * n + i];
+        if (qmode == kQCopy) {
+          qa = a1;
+          qb = b1;
+          qc = c1;
+        } else {
+          qa = fmaf(coef, a1 - p2[i], a1);
+          qb = fmaf(coef, b1 - p2[n + i], b1);
+          qc = fmaf(coef, c1 - p2[2 * n + i], c1);
+        }
+      }
+      sq[0][qp][j + 1] = qa;
+      sq[1][qp][j + 1] = qb;
+      sq[2][qp][j + 1] = qc;
+    }
+    __syncthreads();
+    // u = b - theta D^T q on slices e = c0 - 1 + j.  Each group of 32 lanes
+    // holds one pixel; lane j loads b on slice c0 + j and takes b on e from
+    // lane j - 1 (lane 0 from the previous chunk's slice c0 - 1).
+    for (int k = tid; k < kVUP * kVC; k += kVThreads) {
+      const int up = k / kVC, j = k % kVC;
+      const int ls = up / (kVS + 1), lt = up % (kVS + 1);
+      const int s = s0 - 1 + ls, t = t0 - 1 + lt, e = c0 - 1 + j;
+      const bool pix = s >= 0 && s < H && t >= 0 && t < W;
+      const float bn = (pix && e + 1 < S) ? b[L.pix_st(0, s, t) * S + e + 1] : 0.f;
+      float be = __shfl_up(bn, 1, kVC);
+      if (j == 0) be = sb[par][up];
+      if (j == kVC - 1) sb[par ^ 1][up] = bn;
+      float u = 0.f;
+      if (pix && e >= 0 && e < S) {
+        const int c = ls * (kVS + 2) + lt;
+        const float dtq = (sq[0][c][j] - sq[0][c][j + 1]) +
+                          (sq[1][c][j] - sq[1][c + kVS + 2][j]) +
+                          (sq[2][c][j] - sq[2][c + 1][j]);
+        u = be - theta * dtq;
+      }
+      su[up][j + 1] = u;
+    }
+    __syncthreads();
+    // p = P(q + step D u) on the tile, slices e = c0 - 1 + j
+    for (int k = tid; k < kVS * kVS * kVC; k += kVThreads) {
+      const int tp = k / kVC, j = k % kVC;
+      const int ls = tp / kVS, lt = tp % kVS;
+      const int s = s0 + ls, t = t0 + lt, e = c0 - 1 + j;
+      if (s >= H || t >= W || e < 0 || e >= S) continue;
+      const int uc = (ls + 1) * (kVS + 1) + lt + 1;
+      const float u0 = su[uc][j + 1];
+      const float gd = e >= 1 ? u0 - su[uc][j] : 0.f;
+      const float gv = s >= 1 ? u0 - su[uc - (kVS + 1)][j + 1] : 0.f;
+      const float gh = t >= 1 ? u0 - su[uc - 1][j + 1] : 0.f;
+      const int c = (ls + 1) * (kVS + 2) + lt + 1;
+      const float ad = fmaf(step, gd, sq[0][c][j]);
+      const float av = fmaf(step, gv, sq[1][c][j]);
+      const float ah = fmaf(step, gh, sq[2][c][j]);
+      const float nrm = fmaxf(1.f, sqrtf(ad * ad + av * av + ah * ah));
+      const int64_t i = L.pix_st(0, s, t) * S + e;
+      po[i] = ad / nrm;
+      po[n + i] = av / nrm;
+      po[2 * n + i] = ah / nrm;
+    }
+    __syncthreads();
+    // the chunk's last q and u slices become the next chunk's first
+    for (int k = tid; k < kVQP + kVUP; k += kVThreads) {
+      if (k < kVQP) {
+        sq[0][k][0] = sq[0][k][kVC];
+        sq[1][k][0] = sq[1][k][kVC];
+        sq[2][k][0] = sq[2][k][kVC];
       } else {
-        qa = fmaf(coef, a1 - p2[i], a1);
-        qb = fmaf(coef, b1 - p2[n + i], b1);
-        qc = fmaf(coef, c1 - p2[2 * n + i], c1);
+        su[k - kVQP][0] = su[k - kVQP][kVC];
       }
     }
-    sq[0][q] = qa;  // depth component
-    sq[1][q] = qb;  // vertical
-    sq[2][q] = qc;  // horizontal
-  }
-  __syncthreads();
-  auto qi = [](int ls, int lt, int ld) { return (ls * (kVS + 2) + lt) * (kVD + 2) + ld; };
-  auto ui = [](int ls, int lt, int ld) { return (ls * (kVS + 1) + lt) * (kVD + 1) + ld; };
-  // u on s0-1..s0+7, t0-1..t0+7, d0-1..d0+31
-  for (int q = tid; q < kVU; q += 256) {
-    const int ld = q % (kVD + 1), rest = q / (kVD + 1);
-    const int lt = rest % (kVS + 1), ls = rest / (kVS + 1);
-    const int s = s0 - 1 + ls, t = t0 - 1 + lt, d = d0 - 1 + ld;
-    float u = 0.f;
-    if (s >= 0 && s < H && t >= 0 && t < W && d >= 0 && d < S) {
-      const int c = qi(ls, lt, ld);
-      const float dtq = (sq[0][c] - sq[0][qi(ls, lt, ld + 1)]) +
-                        (sq[1][c] - sq[1][qi(ls + 1, lt, ld)]) +
-                        (sq[2][c] - sq[2][qi(ls, lt + 1, ld)]);
-      u = b[L.pix_st(0, s, t) * S + d] - theta * dtq;
-    }
-    su[q] = u;
-  }
-  __syncthreads();
-  for (int q = tid; q < kVS * kVS * kVD; q += 256) {
-    const int ld = q % kVD, rest = q / kVD;
-    const int lt = rest % kVS, ls = rest / kVS;
-    const int s = s0 + ls, t = t0 + lt, d = d0 + ld;
-    if (s >= H || t >= W || d >= S) continue;
-    const int uc = ui(ls + 1, lt + 1, ld + 1);
-    const float u0 = su[uc];
-    const float gd = d >= 1 ? u0 - su[ui(ls + 1, lt + 1, ld)] : 0.f;
-    const float gv = s >= 1 ? u0 - su[ui(ls, lt + 1, ld + 1)] : 0.f;
-    const float gh = t >= 1 ? u0 - su[ui(ls + 1, lt, ld + 1)] : 0.f;
-    const int c = qi(ls + 1, lt + 1, ld + 1);
-    const float ad = fmaf(step, gd, sq[0][c]);
-    const float av = fmaf(step, gv, sq[1][c]);
-    const float ah = fmaf(step, gh, sq[2][c]);
-    const float nrm = fmaxf(1.f, sqrtf(ad * ad + av * av + ah * ah));
-    const int64_t i = L.pix_st(0, s, t) * S + d;
-    po[i] = ad / nrm;
-    po[n + i] = av / nrm;
-    po[2 * n + i] = ah / nrm;
+    __syncthreads();
   }
 }
 
@@ -868,14 +911,14 @@ hipError_t tv_prox_volume(const Layout& L, int S, const float* b, float theta, i
   momentum(iters, c);
   float* buf[3] = {ws, ws + 3 * n, ws + 6 * n};  // (pd, pv, ph) triples
   const float step = 1.0f / (12.0f * theta);
-  dim3 grid((unsigned)(L.Ht * L.Wt), (unsigned)((S + kVD - 1) / kVD));
+  const unsigned grid = (unsigned)(L.Ht * L.Wt);
   int cur = 0;
   for (int k = 1; k <= iters; ++k) {
     float* o = buf[cur];
     const float* p1 = buf[(cur + 2) % 3];
     const float* p2 = buf[(cur + 1) % 3];
     const int qm = k == 1 ? kQZero : (k == 2 ? kQCopy : kQMomentum);
-    k_fgp_iter3v<<<grid, 256, 0, s>>>(L, S, b, theta, step, c[k], qm, p1, p2, o, n);
+    k_fgp_iter3v<<<grid, kVThreads, 0, s>>>(L, S, b, theta, step, c[k], qm, p1, p2, o, n);
     cur = (cur + 1) % 3;
   }
   k_fgp_out3v<<<grid_for((int64_t)L.H * L.W * S), 256, 0, s>>>(L, S, b, theta,

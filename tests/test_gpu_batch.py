@@ -80,6 +80,27 @@ def test_volume_state_matches_oracle():
         assert rel_l2(X, ref[k]) <= ITERATE_REL, k
 
 
+@pytest.mark.parametrize("name,S", [("ragged", 64), ("c1", 128), ("c1", 4), ("ragged", 32)])
+def test_volume_prox_chunks_match_oracle(name, S):
+    """Slice counts below, at and above the 32-slice chunks of the 3-D prox; ragged pixel tiles."""
+    import paper_1812_01307_amd as bsgd
+    from gpu_helpers import ragged_problem
+    p = ragged_problem() if name == "ragged" else problem("c1_64")
+    plan = plan_for(p)
+    mu = float(np.float32(mu_for(p)))
+    A = matrix(p)
+    X_true = np.stack([synth.ellipse_phantom(p.H, p.W, 6, 2000 + s).ravel() for s in range(S)])
+    Y = f32(np.asarray(A @ X_true.T).T).astype(np.float64)
+    lam, K, E = 30.0, 12, 3
+    st = bsgd.bsgd_state_create(plan, S, flags=bsgd.BSGD_STATE_VOLUME)
+    bsgd.bsgd_state_init(st, _dev(f32(_to_rows(Y)).ravel()))
+    _, _, ref = oracle.bsgd_tv_multi(A, Y, mu, lam, E, K, (p.H, p.W), volume=True, record=True)
+    for k in range(E):
+        bsgd.bsgd_run_epochs(st, mu, lam, 1, K)
+        X = _host(bsgd.bsgd_get_x(st)).reshape(p.ncols, S).T
+        assert rel_l2(X, ref[k]) <= ITERATE_REL, k
+
+
 def test_slot_restart_leaves_other_slots_bitwise_unchanged():
     import paper_1812_01307_amd as bsgd
     p = problem("c1_64")

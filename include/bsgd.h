@@ -433,9 +433,18 @@ bsgd_status bsgd_get_stats(const bsgd_state* state, hipStream_t stream, double* 
  * pass (lines 4 and 6), its backprojection pass (lines 3, 7, 8) and its prox
  * (line 9).  bsgd_state_timing synchronises, returns the summed durations in
  * milliseconds and the number of timed epochs, and rearms the timers.
- * max_epochs = 0 disables timing.
+ * max_epochs = 0 disables timing.  bsgd_state_enable_timing_sampled times
+ * one epoch in every `stride` (the first, then every stride-th), up to
+ * max_epochs timed epochs: each timed epoch records 5 events between its
+ * kernels, and every event leaves the GPU idle for a few microseconds, so a
+ * throughput measurement that also samples kernel durations should not time
+ * every epoch.  The events come from a per-device pool
+ * that the library keeps for the life of the process (destroying the state
+ * returns them to it), so timing a fresh state per job costs no event
+ * creation after the first.
  */
 bsgd_status bsgd_state_enable_timing(bsgd_state* state, int max_epochs);
+bsgd_status bsgd_state_enable_timing_sampled(bsgd_state* state, int max_epochs, int stride);
 bsgd_status bsgd_state_timing(bsgd_state* state, double* fwd_ms, double* bwd_ms, double* prox_ms,
                               int64_t* epochs_timed);
 

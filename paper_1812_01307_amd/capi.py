@@ -100,6 +100,7 @@ _PROTOS = {
     "bsgd_get_r": [_vp, _vp, _vp],
     "bsgd_get_stats": [_vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)],
     "bsgd_state_enable_timing": [_vp, _i32],
+    "bsgd_state_enable_timing_sampled": [_vp, _i32, _i32],
     "bsgd_state_set_overlap": [_vp, _i32],
     "bsgd_state_set_prox_schedule": [_vp, _i32],
     "bsgd_state_timing": [_vp] + [ctypes.POINTER(ctypes.c_double)] * 3 + [ctypes.POINTER(_i64)],
@@ -490,8 +491,14 @@ def bsgd_last_error() -> str:
     return _lib.bsgd_last_error().decode()
 
 
-def bsgd_state_enable_timing(state: State, max_epochs: int):
-    _check("bsgd_state_enable_timing", _lib.bsgd_state_enable_timing(state.handle, int(max_epochs)))
+def bsgd_state_enable_timing(state: State, max_epochs: int, stride: int = 1):
+    """Time up to max_epochs epochs: one in every `stride` (1: every epoch)."""
+    if stride == 1:
+        _check("bsgd_state_enable_timing",
+               _lib.bsgd_state_enable_timing(state.handle, int(max_epochs)))
+    else:
+        _check("bsgd_state_enable_timing_sampled",
+               _lib.bsgd_state_enable_timing_sampled(state.handle, int(max_epochs), int(stride)))
 
 
 def bsgd_state_timing(state: State):

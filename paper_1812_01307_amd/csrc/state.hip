@@ -11,6 +11,7 @@
 // double-buffered; events order the buffer reuse across epochs.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "bsgd_internal.h"
@@ -47,9 +48,13 @@ struct bsgd_state {
   bool initialised = false;
   hipStream_t aux = nullptr;
   hipEvent_t ev_main = nullptr, ev_aux = nullptr;
-  // optional kernel timers: 5 events per timed epoch
+  // optional kernel timers: 5 events per timed epoch, taken from the event
+  // pool of device tev_dev
   std::vector<hipEvent_t> tev;
+  int tev_dev = 0;
   int t_cap = 0, t_used = 0;
+  int t_stride = 1;         // time one epoch in every t_stride ...
+  int64_t t_seen = 0;       // ... counting epochs since the timers were armed
 };
 
 namespace bsgd {
@@ -350,10 +355,56 @@ extern "C" bsgd_status bsgd_state_create(const bsgd_plan* plan, int nrhs, bsgd_v
   return BSGD_OK;
 }
 
+// Timing events are pooled per device for the life of the process and
+// reused by later states: a state timing every epoch of a job needs
+// thousands, and creating and destroying them took milliseconds of host time
+// per job.  An event handed back may still be pending; recording it again
+// re-arms it.
+static std::mutex g_event_mu;
+static std::vector<std::vector<hipEvent_t>> g_event_pool;  // [device]
+
 static void destroy_timers(bsgd_state* st) {
-  for (hipEvent_t e : st->tev) (void)hipEventDestroy(e);
+  if (!st->tev.empty()) {
+    std::lock_guard<std::mutex> lk(g_event_mu);
+    if ((int)g_event_pool.size() <= st->tev_dev) g_event_pool.resize(st->tev_dev + 1);
+    auto& pool = g_event_pool[st->tev_dev];
+    pool.insert(pool.end(), st->tev.begin(), st->tev.end());
+  }
   st->tev.clear();
   st->t_cap = st->t_used = 0;
+}
+
+// Events of the epoch about to run, or NULL when it is not timed.
+static hipEvent_t* next_timers(bsgd_state* st) {
+  if (st->t_used >= st->t_cap) return nullptr;
+  if (st->t_seen++ % st->t_stride != 0) return nullptr;
+  return &st->tev[5 * (size_t)st->t_used++];
+}
+
+// n events on the current device into st->tev (pooled ones first).
+static hipError_t take_timers(bsgd_state* st, size_t n) {
+  int dev = 0;
+  hipError_t r = hipGetDevice(&dev);
+  if (r != hipSuccess) return r;
+  st->tev_dev = dev;
+  st->tev.reserve(n);
+  {
+    std::lock_guard<std::mutex> lk(g_event_mu);
+    if ((int)g_event_pool.size() > dev) {
+      auto& pool = g_event_pool[dev];
+      while (st->tev.size() < n && !pool.empty()) {
+        st->tev.push_back(pool.back());
+        pool.pop_back();
+      }
+    }
+  }
+  while (st->tev.size() < n) {
+    hipEvent_t e = nullptr;
+    r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    st->tev.push_back(e);
+  }
+  return hipSuccess;
 }
 
 extern "C" void bsgd_state_destroy(bsgd_state* st) {
@@ -481,7 +532,7 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
   const float theta = per_rhs ? -1.f : mu * lam;  // -1: per-RHS thetas from st->lam
   for (int e = 0; e < epochs; ++e) {
     const int c = st->cur, n = 1 - c;
-    hipEvent_t* tv = st->t_used < st->t_cap ? &st->tev[5 * (size_t)st->t_used++] : nullptr;
+    hipEvent_t* tv = next_timers(st);
     // S2 (+S4) on `stream`; S1 on the aux stream after everything queued on
     // `stream` before this epoch (overlap 0) or after S2 (overlap 1), or on
     // `stream` after the prox (overlap 2: no concurrency)
@@ -618,22 +669,26 @@ extern "C" bsgd_status bsgd_get_stats(const bsgd_state* st, hipStream_t stream, 
 }
 
 extern "C" bsgd_status bsgd_state_enable_timing(bsgd_state* st, int max_epochs) {
+  return bsgd_state_enable_timing_sampled(st, max_epochs, 1);
+}
+
+extern "C" bsgd_status bsgd_state_enable_timing_sampled(bsgd_state* st, int max_epochs,
+                                                        int stride) {
   clear_error();
   BSGD_REQUIRE(st != nullptr, "state is NULL");
   BSGD_REQUIRE(max_epochs >= 0, "max_epochs must be >= 0");
+  BSGD_REQUIRE(stride >= 1, "stride must be >= 1");
   destroy_timers(st);
-  st->tev.resize(5 * (size_t)max_epochs, nullptr);
-  for (auto& e : st->tev) {
-    hipError_t r = hipEventCreate(&e);
-    if (r != hipSuccess) {
-      e = nullptr;
-      destroy_timers(st);
-      set_error("timer event creation failed: %s", hipGetErrorString(r));
-      return BSGD_ERR_HIP;
-    }
+  hipError_t r = take_timers(st, 5 * (size_t)max_epochs);
+  if (r != hipSuccess) {
+    destroy_timers(st);
+    set_error("timer event creation failed: %s", hipGetErrorString(r));
+    return BSGD_ERR_HIP;
   }
   st->t_cap = max_epochs;
   st->t_used = 0;
+  st->t_stride = stride;
+  st->t_seen = 0;
   return BSGD_OK;
 }
 
@@ -659,6 +714,7 @@ extern "C" bsgd_status bsgd_state_timing(bsgd_state* st, double* fwd_ms, double*
   *prox_ms = x;
   *epochs_timed = st->t_used;
   st->t_used = 0;
+  st->t_seen = 0;
   return BSGD_OK;
 }
 
@@ -706,7 +762,7 @@ extern "C" bsgd_status bsgd_run_selected(bsgd_state* st, float mu, float lam, in
   for (int t = 0; t < iters; ++t) {
     const int c = st->cur, n = 1 - c;
     float* step_out = theta == 0.f ? st->x[n] : st->xhat;
-    hipEvent_t* tv = st->t_used < st->t_cap ? &st->tev[5 * (size_t)st->t_used++] : nullptr;
+    hipEvent_t* tv = next_timers(st);
     // lines 4 + 6 with the current x; lines 3, 7, 8 with the kept residual
     if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
     BSGD_HIP(launch_sel_forward(p->fwd, st->bmf, st->vt, st->blk_r, rows_sel[t], cols_sel[t],

@@ -249,18 +249,20 @@ def main(argv=None):
         if tuned is not None:
             bsgd.bsgd_plan_set_lanes(plan, *tuned[0])
             bsgd.bsgd_plan_set_staged(plan, *[max(v, 0) for v in tuned[1]])
+        F = None
+        if fused:
+            F = bsgd.bsgd_fused_create(plan, args.fused_chunks)
+            bsgd.bsgd_fused_set_waves(F, args.fused_waves)
         if fixed_mu is None:
             if args.umax == "lanczos":
-                u = bsgd.bsgd_lanczos_umax(plan, args.umax_steps, vt=vt)
+                # on the single-pass path the Lanczos products run on its store
+                u = (bsgd.bsgd_lanczos_umax_fused(F, args.umax_steps, vt=vt) if F is not None
+                     else bsgd.bsgd_lanczos_umax(plan, args.umax_steps, vt=vt))
             else:
                 u = bsgd.bsgd_power_umax(plan, args.power_iters, vt=vt)
             mu = 0.9 / (2.0 * u)
         else:
             mu = fixed_mu
-        F = None
-        if fused:
-            F = bsgd.bsgd_fused_create(plan, args.fused_chunks)
-            bsgd.bsgd_fused_set_waves(F, args.fused_waves)
         st = make_state(plan, F)
         if record and timing:
             # one epoch in TIMING_STRIDE carries the events (each leaves the GPU
@@ -520,7 +522,8 @@ def main(argv=None):
                    "lanes_per_row": list(bsgd.bsgd_plan_lanes(plan)), "overlap": args.overlap,
                    "staged": args.staged,
                    "mu": "fixed from " + args.mu_file if fixed_mu is not None
-                   else (f"Lanczos bidiagonalisation ({args.umax_steps} steps)"
+                   else (f"Lanczos bidiagonalisation ({args.umax_steps} steps"
+                         + (", products on the tile-sliced store)" if fused else ")")
                          if args.umax == "lanczos"
                          else f"power iteration ({args.power_iters} steps)")},
         "epoch_only_ms": round(epoch_ms, 4),

@@ -565,6 +565,21 @@ bsgd_status bsgd_fused_apply(const bsgd_fused* fused, bsgd_valtype vt, const flo
 bsgd_status bsgd_state_attach_fused(bsgd_state* state, const bsgd_fused* fused, void* partials,
                                     size_t partials_bytes);
 
+/*
+ * u_max (S0', the bound of Theorem 1 on the step) by the Lanczos steps of
+ * bsgd_lanczos_umax, with the products A v and A^T u taken from the
+ * tile-sliced store: one single-direction pass each (about 0.55 times the
+ * time of a row-kernel product at 512^2).  A^T u is summed in the store's
+ * fixed-point form, scaled from max |u|.  The result differs from the
+ * row-kernel form only by summation order.  Workspace (device, 256-byte
+ * aligned) from bsgd_lanczos_workspace_size_fused; the store's plan must not
+ * run other calls meanwhile (none of its scratch is used, but the store reads
+ * its arrays).  Synchronises; BSGD_ERR_DIVERGED if a value is not finite.
+ */
+bsgd_status bsgd_lanczos_workspace_size_fused(const bsgd_fused* fused, int steps, size_t* bytes);
+bsgd_status bsgd_lanczos_umax_fused(const bsgd_fused* fused, bsgd_valtype vt, int steps,
+                                    void* ws, size_t ws_bytes, hipStream_t stream, float* umax);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char* bsgd_last_error(void);
 

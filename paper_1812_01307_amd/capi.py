@@ -83,6 +83,8 @@ _PROTOS = {
     "bsgd_power_umax": [_vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_f32)],
     "bsgd_lanczos_workspace_size": [_vp, _i32, ctypes.POINTER(_sz)],
     "bsgd_lanczos_umax": [_vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_f32)],
+    "bsgd_lanczos_workspace_size_fused": [_vp, _i32, ctypes.POINTER(_sz)],
+    "bsgd_lanczos_umax_fused": [_vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_f32)],
     "bsgd_state_workspace_size": [_vp, _i32, ctypes.c_uint, ctypes.POINTER(_sz)],
     "bsgd_state_create": [_vp, _i32, _i32, ctypes.c_uint, _vp, _sz, ctypes.POINTER(_vp)],
     "bsgd_state_set_rhs": [_vp, _i32, _vp, _vp, _vp],
@@ -637,6 +639,25 @@ def bsgd_fused_create(plan: Plan, chunks=0, flags=0, stream=None) -> Fused:
                                                        _ptr(ws), nbytes, _stream(stream),
                                                        ctypes.byref(h)))
     return Fused(h, ws, plan)
+
+
+def bsgd_lanczos_workspace_size_fused(fused: Fused, steps: int) -> int:
+    out = _sz()
+    _check("bsgd_lanczos_workspace_size_fused",
+           _lib.bsgd_lanczos_workspace_size_fused(fused.handle, int(steps), ctypes.byref(out)))
+    return out.value
+
+
+def bsgd_lanczos_umax_fused(fused: Fused, steps, vt=BSGD_VAL_F32, ws=None, stream=None) -> float:
+    """u_max by Lanczos steps whose products run on the tile-sliced store."""
+    nbytes = bsgd_lanczos_workspace_size_fused(fused, steps)
+    if ws is None:
+        ws = _ws(nbytes, fused.workspace.device)
+    out = ctypes.c_float()
+    _check("bsgd_lanczos_umax_fused",
+           _lib.bsgd_lanczos_umax_fused(fused.handle, vt, int(steps), _ptr(ws), ws.numel(),
+                                        _stream(stream), ctypes.byref(out)))
+    return float(out.value)
 
 
 def bsgd_fused_shape(fused: Fused):

@@ -241,14 +241,12 @@ extern "C" bsgd_status bsgd_lanczos_workspace_size(const bsgd_plan* plan, int st
   return BSGD_OK;
 }
 
-extern "C" bsgd_status bsgd_lanczos_umax(const bsgd_plan* plan, bsgd_valtype vt, int steps,
-                                         void* ws, size_t ws_bytes, hipStream_t stream,
-                                         float* umax) {
-  clear_error();
-  BSGD_REQUIRE(plan && ws && umax, "NULL argument");
-  BSGD_REQUIRE(steps >= 1 && steps <= 4096, "steps must be in [1, 4096]");
-  BSGD_REQUIRE(vt == BSGD_VAL_F32 || (vt == BSGD_VAL_F16 && (plan->flags & BSGD_PLAN_F16)),
-               "value type not available in this plan");
+// Golub-Kahan-Lanczos recurrence with the two products given as callables:
+// fwd(v, out) = A v (r_int floats), bwd(u, out) = A^T u (c_int floats), both
+// in the internal orders on `stream`.
+template <class Fwd, class Bwd>
+static bsgd_status lanczos_run(const bsgd_plan* plan, int steps, void* ws, size_t ws_bytes,
+                               hipStream_t stream, float* umax, Fwd fwd, Bwd bwd) {
   float *v, *w, *u[2];
   double *part, *sc;
   const size_t need = lanczos_layout(plan, steps, ws, &v, &w, &u[0], &u[1], &part, &sc);
@@ -266,7 +264,7 @@ extern "C" bsgd_status bsgd_lanczos_umax(const bsgd_plan* plan, bsgd_valtype vt,
     float* un = u[j & 1];
     const float* up = u[(j + 1) & 1];
     // alpha_j u_j = A v_j - beta_{j-1} u_{j-1}
-    BSGD_HIP(launch_rows(plan->fwd, vt, kPlain, v, nullptr, nullptr, 1.0f, un, stream));
+    BSGD_HIP(fwd(v, un));
     if (j > 0) {
       k_sub_scaled<<<1024, 256, 0, stream>>>(un, up, r, sc + 2 * (j - 1) + 1);
       BSGD_LAUNCH_CHECK();
@@ -275,7 +273,7 @@ extern "C" bsgd_status bsgd_lanczos_umax(const bsgd_plan* plan, bsgd_valtype vt,
     k_scale_by_rsqrt<<<1024, 256, 0, stream>>>(un, un, r, sc + 2 * j);
     BSGD_LAUNCH_CHECK();
     // beta_j v_{j+1} = A^T u_j - alpha_j v_j
-    BSGD_HIP(launch_rows(plan->bwd, vt, kPlain, un, nullptr, nullptr, 1.0f, w, stream));
+    BSGD_HIP(bwd(un, w));
     k_sub_scaled<<<1024, 256, 0, stream>>>(w, v, c, sc + 2 * j);
     BSGD_LAUNCH_CHECK();
     BSGD_HIP(launch_sumsq(w, c, part, sc + 2 * j + 1, stream));
@@ -300,6 +298,78 @@ extern "C" bsgd_status bsgd_lanczos_umax(const bsgd_plan* plan, bsgd_valtype vt,
     }
   *umax = (float)tridiag_max_eig(d, e);
   return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_lanczos_umax(const bsgd_plan* plan, bsgd_valtype vt, int steps,
+                                         void* ws, size_t ws_bytes, hipStream_t stream,
+                                         float* umax) {
+  clear_error();
+  BSGD_REQUIRE(plan && ws && umax, "NULL argument");
+  BSGD_REQUIRE(steps >= 1 && steps <= 4096, "steps must be in [1, 4096]");
+  BSGD_REQUIRE(vt == BSGD_VAL_F32 || (vt == BSGD_VAL_F16 && (plan->flags & BSGD_PLAN_F16)),
+               "value type not available in this plan");
+  return lanczos_run(
+      plan, steps, ws, ws_bytes, stream, umax,
+      [&](const float* v, float* out) {
+        return launch_rows(plan->fwd, vt, kPlain, v, nullptr, nullptr, 1.0f, out, stream);
+      },
+      [&](const float* u, float* out) {
+        return launch_rows(plan->bwd, vt, kPlain, u, nullptr, nullptr, 1.0f, out, stream);
+      });
+}
+
+extern "C" bsgd_status bsgd_lanczos_workspace_size_fused(const bsgd_fused* F, int steps,
+                                                         size_t* bytes) {
+  clear_error();
+  BSGD_REQUIRE(F && bytes, "NULL argument");
+  BSGD_REQUIRE(steps >= 1 && steps <= 4096, "steps must be in [1, 4096]");
+  float *v, *w, *u0, *u1;
+  double *part, *sc;
+  const size_t a = lanczos_layout(fused_plan(F), steps, nullptr, &v, &w, &u0, &u1, &part, &sc);
+  *bytes = a + align_up(fused_partials(F, nullptr, nullptr), kAlign);
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_lanczos_umax_fused(const bsgd_fused* F, bsgd_valtype vt, int steps,
+                                               void* ws, size_t ws_bytes, hipStream_t stream,
+                                               float* umax) {
+  clear_error();
+  BSGD_REQUIRE(F && ws && umax, "NULL argument");
+  BSGD_REQUIRE(steps >= 1 && steps <= 4096, "steps must be in [1, 4096]");
+  BSGD_REQUIRE(vt == BSGD_VAL_F32 || (vt == BSGD_VAL_F16 && fused_has_f16(F)),
+               "value type not available in this store");
+  const bsgd_plan* plan = fused_plan(F);
+  float *v, *w, *u0, *u1;
+  double *part, *sc;
+  const size_t a = lanczos_layout(plan, steps, nullptr, &v, &w, &u0, &u1, &part, &sc);
+  const size_t b = align_up(fused_partials(F, nullptr, nullptr), kAlign);
+  if (ws_bytes < a + b) {
+    set_error("lanczos workspace has %zu bytes, needs %zu", ws_bytes, a + b);
+    return BSGD_ERR_WORKSPACE;
+  }
+  FusedPartials fp;
+  fused_partials(F, &fp, static_cast<char*>(ws) + a);
+  const int64_t r = plan->L.r_int;
+  return lanczos_run(
+      plan, steps, ws, a, stream, umax,
+      [&](const float* x, float* out) -> hipError_t {
+        // A x: the pass's row sums, then the ray half of the reduce (no y)
+        hipError_t e =
+            launch_fused_pass(F, vt, x, nullptr, nullptr, nullptr, fp.zp, fp.gp, stream, kPassA);
+        if (e != hipSuccess) return e;
+        return launch_fused_reduce(F, fp.zp, fp.gp, nullptr, out, nullptr, nullptr, 1.0f,
+                                   nullptr, stream, kReduceRays);
+      },
+      [&](const float* u, float* out) -> hipError_t {
+        // A^T u: max |u| sets the fixed-point scale of the pass's LDS sums
+        hipError_t e = launch_fused_absmax(u, r, fp.rmax, stream);
+        if (e != hipSuccess) return e;
+        e = launch_fused_pass(F, vt, nullptr, u, fp.rmax, nullptr, fp.zp, fp.gp, stream,
+                              kPassAt);
+        if (e != hipSuccess) return e;
+        return launch_fused_reduce(F, fp.zp, fp.gp, nullptr, nullptr, nullptr, nullptr, 1.0f,
+                                   out, stream, kReducePixels);
+      });
 }
 
 extern "C" bsgd_status bsgd_state_workspace_size(const bsgd_plan* plan, int nrhs, unsigned flags,

@@ -185,6 +185,23 @@ def test_lanczos_umax(name):
         bsgd.bsgd_lanczos_umax(plan, 0)
 
 
+@pytest.mark.parametrize("name", CASES)
+def test_lanczos_umax_on_the_single_pass_store(name):
+    """Same recurrence with the products from the tile-sliced store; same bar."""
+    import paper_1812_01307_amd as bsgd
+    p = _case(name)
+    plan = _plan(name)
+    F = bsgd.bsgd_fused_create(plan, 0)
+    ref = oracle.power_umax(matrix(p))
+    for steps in (6, 10, 24):
+        u = bsgd.bsgd_lanczos_umax_fused(F, steps)
+        assert abs(u - ref) <= 1e-5 * ref, (steps, u, ref)
+        assert abs(u - bsgd.bsgd_lanczos_umax(plan, steps)) <= 1e-5 * ref
+    assert bsgd.bsgd_lanczos_umax_fused(F, 1) <= ref * (1 + 1e-6)
+    with pytest.raises(bsgd.BsgdError):
+        bsgd.bsgd_lanczos_umax_fused(F, 0)
+
+
 # --------------------------------------------------------------------------
 # Whole epochs (Algorithm 1)
 # --------------------------------------------------------------------------

@@ -167,6 +167,18 @@ struct Staged {
 
 }  // namespace bsgd
 
+// Result of the single-pass store's segment count pass for one chunk count
+// and column width; while valid, scratch64 holds the rays' segment offsets
+// it produced (every other writer of scratch64 clears it).
+struct FusedCountCache {
+  bool valid = false;
+  int Q = 0;
+  bool wide = false;
+  bool narrow = true;
+  int64_t pairs = 0, slices = 0, bound = 0;
+  int maxrank = 0, maxlen = 0, maxstep = 0;
+};
+
 struct bsgd_plan {
   int M = 0, N = 0, H = 0, W = 0, D = 0;
   unsigned flags = 0;
@@ -178,6 +190,8 @@ struct bsgd_plan {
   float* stage_z = nullptr;       // stage partials for the autotuner
   std::vector<int64_t> row_off, col_off;
   int64_t* scratch64 = nullptr;   // max(r_int, c_int) + 1 entries (build, export)
+  mutable FusedCountCache fz_count;  // lets bsgd_fused_create reuse the count of
+                                     // bsgd_fused_workspace_size
   int64_t* scan_tmp = nullptr;    // block sums for scans
   int* err = nullptr;             // validation flags
   int64_t* seg_dev = nullptr;     // segment bounds staged for the fill kernel

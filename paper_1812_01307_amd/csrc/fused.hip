@@ -883,6 +883,20 @@ struct FusedCounts {
 // 64 * (maxlen + 3) + 192 * slices.  Synchronises.
 static bsgd_status fused_count(const bsgd_plan* p, const TileGeom& g, bool wide, hipStream_t s,
                                FusedCounts& fc) {
+  FusedCountCache& cc = p->fz_count;
+  if (cc.valid && cc.Q == g.Q && cc.wide == wide) {
+    // bsgd_fused_workspace_size counted this geometry and synchronised;
+    // scratch64 still holds the offsets
+    fc.narrow = cc.narrow;
+    fc.pairs = cc.pairs;
+    fc.slices = cc.slices;
+    fc.bound = cc.bound;
+    fc.maxrank = cc.maxrank;
+    fc.maxlen = cc.maxlen;
+    fc.maxstep = cc.maxstep;
+    return BSGD_OK;
+  }
+  cc.valid = false;
   const Layout& L = p->L;
   const int64_t units = g.units();
   int32_t* words = reinterpret_cast<int32_t*>(p->vin);  // maxc, maxlen, maxstep
@@ -910,6 +924,16 @@ static bsgd_status fused_count(const bsgd_plan* p, const TileGeom& g, bool wide,
   fc.bound = p->fwd.nnz + units * 64 * ((int64_t)fc.maxlen + 3) + 192 * fc.slices;
   BSGD_REQUIRE(fc.slices * 64 < ((int64_t)1 << 31), "too many slices (%lld)",
                (long long)fc.slices);
+  cc.Q = g.Q;
+  cc.wide = wide;
+  cc.narrow = fc.narrow;
+  cc.pairs = fc.pairs;
+  cc.slices = fc.slices;
+  cc.bound = fc.bound;
+  cc.maxrank = fc.maxrank;
+  cc.maxlen = fc.maxlen;
+  cc.maxstep = fc.maxstep;
+  cc.valid = true;
   return BSGD_OK;
 }
 

@@ -671,6 +671,7 @@ extern "C" bsgd_status bsgd_tile_nnz(const bsgd_plan* plan, int i, int j, hipStr
   BSGD_REQUIRE(nnz != nullptr, "nnz is NULL");
   const Store& st = plan->fwd;
   const unsigned blocks = (unsigned)std::min<int64_t>((nrows + 255) / 256, 65535);
+  plan->fz_count.valid = false;  // scratch64 is overwritten
   k_tile_len<true><<<blocks, 256, 0, stream>>>(st.seg, st.nseg, plan->L, row0, nrows, segk,
                                                plan->scratch64);
   BSGD_LAUNCH_CHECK();
@@ -697,6 +698,7 @@ extern "C" bsgd_status bsgd_tile_export(const bsgd_plan* plan, int i, int j, int
   const Store& st = transposed ? plan->bwd : plan->fwd;
   const unsigned blocks = (unsigned)std::min<int64_t>((nrows + 255) / 256, 65535);
   const unsigned cblocks = (unsigned)((nrows * 64 + 255) / 256);
+  plan->fz_count.valid = false;  // scratch64 is overwritten
   if (!transposed)
     k_tile_len<true><<<blocks, 256, 0, stream>>>(st.seg, st.nseg, plan->L, row0, nrows, segk,
                                                  plan->scratch64);

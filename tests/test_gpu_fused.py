@@ -320,3 +320,41 @@ def test_fused_overlap_modes_agree_bitwise(name):
         outs.append((_host(bsgd.bsgd_get_x(st)), _host(bsgd.bsgd_get_r(st))))
     for x, r in outs[1:]:
         assert np.array_equal(x, outs[0][0]) and np.array_equal(r, outs[0][1])
+
+
+def test_count_reuse_and_invalidation_give_identical_stores():
+    """bsgd_fused_create reuses the segment count of bsgd_fused_workspace_size;
+    a block export in between (which overwrites the plan's scratch) and a
+    different chunk count force a recount.  Every store must be the same."""
+    import ctypes
+    import paper_1812_01307_amd as bsgd
+    from paper_1812_01307_amd import capi
+    p = _cases()["medium"]()
+    plan = plan_for(p)
+    rng = np.random.default_rng(5)
+    x = f32(rng.random(p.ncols))
+    r = f32(rng.standard_normal(p.nrows))
+
+    def raw_create(chunks, between=None):
+        n = bsgd.bsgd_fused_workspace_size(plan, chunks)
+        if between:
+            between()
+        ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+        h = capi._vp()
+        capi._check("bsgd_fused_create", capi._lib.bsgd_fused_create(
+            plan.handle, chunks, 0, capi._ptr(ws), n, capi._stream(), ctypes.byref(h)))
+        return capi.Fused(h, ws, plan)
+
+    def products(F):
+        ax, g = bsgd.bsgd_fused_apply(F, _dev(x), _dev(r))
+        return _host(ax), _host(g), bsgd.bsgd_fused_shape(F)
+
+    ref = products(bsgd.bsgd_fused_create(plan, 0))
+    for F in (raw_create(0), raw_create(0, lambda: bsgd.bsgd_tile_export(plan, 1, 1)),
+              raw_create(2), raw_create(0)):
+        got = products(F)
+        if got[2][1] == ref[2][1]:  # same chunk count: bitwise the same store
+            assert got[2] == ref[2]
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+        else:
+            assert np.allclose(got[0], ref[0], rtol=1e-5, atol=1e-6)

@@ -36,19 +36,19 @@ TIMING_STRIDE = 8
 PMC_TRAFFIC = {
     # profiles/k_fused_c2_512_hbm_counters.md
     ("fused", "c2_512", "f32"): {
-        "sha256": "90e1851c8e3fcc208c01aa72f33af1c9bd96425568593eafeaff9432aa30d1ff",
-        "bytes": 1334577930},
+        "sha256": "f14070448bebd565fe1283bbebca8b25c8e3a859daedf49d284aaace0421b3be",
+        "bytes": 1335194399},
     # profiles/k_fused_ista_c2_512_hbm_counters.md (the A x-only pass)
     ("fused", "c2_512", "f32", "ista"): {
-        "sha256": "90e1851c8e3fcc208c01aa72f33af1c9bd96425568593eafeaff9432aa30d1ff",
-        "bytes": 1310828314},
+        "sha256": "f14070448bebd565fe1283bbebca8b25c8e3a859daedf49d284aaace0421b3be",
+        "bytes": 1310619171},
     ("fused", "c2_512", "f32", "gd"): {
-        "sha256": "90e1851c8e3fcc208c01aa72f33af1c9bd96425568593eafeaff9432aa30d1ff",
-        "bytes": 1310828314},
+        "sha256": "f14070448bebd565fe1283bbebca8b25c8e3a859daedf49d284aaace0421b3be",
+        "bytes": 1310619171},
     # profiles/k_sel_c2_512_hbm_counters.md (mean over the 800 draws of the bench's run)
     ("selected", "c2_512", "f32", 0.5, 0.5, 7, "fwd"): {
-        "sha256": "4614323e3fa8b4bf0cadbd52edfc1d38ba073d5b9d2eec858a57e32e147bcd60",
-        "bytes": 613988527},
+        "sha256": "a376794b8b41a6e02cc276c3678028389ff13f88962ba4495c42f086f7820c41",
+        "bytes": 613983496},
 }
 
 

@@ -36,15 +36,15 @@ TIMING_STRIDE = 8
 PMC_TRAFFIC = {
     # profiles/k_fused_c2_512_hbm_counters.md
     ("fused", "c2_512", "f32"): {
-        "sha256": "f14070448bebd565fe1283bbebca8b25c8e3a859daedf49d284aaace0421b3be",
-        "bytes": 1335194399},
+        "sha256": "3a52f63bc03ab1e800083d93d5b3cf0d66c79af3593c544536876f802c3ae6a7",
+        "bytes": 1335151517},
     # profiles/k_fused_ista_c2_512_hbm_counters.md (the A x-only pass)
     ("fused", "c2_512", "f32", "ista"): {
-        "sha256": "f14070448bebd565fe1283bbebca8b25c8e3a859daedf49d284aaace0421b3be",
-        "bytes": 1310619171},
+        "sha256": "3a52f63bc03ab1e800083d93d5b3cf0d66c79af3593c544536876f802c3ae6a7",
+        "bytes": 1310615639},
     ("fused", "c2_512", "f32", "gd"): {
-        "sha256": "f14070448bebd565fe1283bbebca8b25c8e3a859daedf49d284aaace0421b3be",
-        "bytes": 1310619171},
+        "sha256": "3a52f63bc03ab1e800083d93d5b3cf0d66c79af3593c544536876f802c3ae6a7",
+        "bytes": 1310615639},
     # profiles/k_sel_c2_512_hbm_counters.md (mean over the 800 draws of the bench's run)
     ("selected", "c2_512", "f32", 0.5, 0.5, 7, "fwd"): {
         "sha256": "a376794b8b41a6e02cc276c3678028389ff13f88962ba4495c42f086f7820c41",

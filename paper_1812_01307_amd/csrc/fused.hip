@@ -755,8 +755,19 @@ __global__ __launch_bounds__(256) void k_fz_reduce(
       bad = bad || (o != o);
     } else {
       const int64_t p = i - r_int;
+      // chunk order, 8 loads in flight (a loop of dependent single loads
+      // left this half of the reduce latency-bound)
+      const float* g = gp + p;
       float a = 0.f;
-      for (int k = 0; k < Q; ++k) a += gp[(int64_t)k * c_int + p];
+      int k = 0;
+      for (; k + 7 < Q; k += 8) {
+        float v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = g[(int64_t)(k + t) * c_int];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) a += v[t];
+      }
+      for (; k < Q; ++k) a += g[(int64_t)k * c_int];
       out_x[p] = xadd ? fmaf(scale, a, xadd[p]) : scale * a;
     }
   }

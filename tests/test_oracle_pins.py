@@ -329,6 +329,23 @@ def test_prox3_duality_gap():
     assert -1e-14 <= primal - dual < 1e-9
 
 
+def test_fgp3_hand_values():
+    """Finite-K iterates of the 3-D FGP against hand-derived values: the dual
+    step 1/(12 theta) and the momentum (two voxels along each axis, K = 1..3)
+    and the R^3 ball projection with the adjoint stencil (2 x 2 x 2, K = 1, 2)."""
+    g = json.load(open(os.path.join(GOLDEN, "fgp3_hand.json")))
+    c0 = g["cases"][0]
+    for axis, b in c0["b_by_axis"].items():
+        b = np.array(b)
+        for k, exp in c0["expected_by_iters"].items():
+            out = oracle.fgp_prox3(b, c0["theta"], int(k))
+            assert np.max(np.abs(out.ravel() - np.array(exp))) < 1e-15, (axis, k)
+    c1 = g["cases"][1]
+    for k, exp in c1["expected_by_iters"].items():
+        out = oracle.fgp_prox3(np.array(c1["b"]), c1["theta"], int(k))
+        assert np.max(np.abs(out - np.array(exp))) < 1e-15, k
+
+
 # --------------------------------------------------------------------------
 # Blocking (Section 2.1): changes rounding only
 # --------------------------------------------------------------------------
@@ -383,6 +400,30 @@ def test_theorem2_margin_diagnostic_runs():
     _, _, hist = oracle.bsgd_tv(A, p.y, mu, 30.0, 6, 20, (p.H, p.W), record=True)
     m = [oracle.thm2_margin(A, p.y, hist[k - 1], hist[k], hist[k + 1], mu) for k in range(1, 5)]
     assert all(np.isfinite(m))
+
+
+def test_theorem2_margin_hand_value_and_quadratic_identity():
+    """Eq. 8's margin f(x^k) + <d, grad f(x^{k-1})> + ||d||^2/(2 mu) - f(x^{k+1}).
+
+    Hand value: A = [1], y = 0, so f(v) = v^2 and grad f(v) = 2v; with
+    x^{k-1} = 0, x^k = 1, x^{k+1} = 2, mu = 1/4: 1 + 0 + 2 - 4 = -1.
+    Identity: f is quadratic, so f(x^{k+1}) = f(x^k) + <d, grad f(x^k)> + ||A d||^2
+    and grad f(u) - grad f(v) = 2 A^T A (u - v); the margin is therefore
+    2 <A d, A (x^{k-1} - x^k)> + ||d||^2/(2 mu) - ||A d||^2 for any vectors.
+    """
+    A1 = sp.csr_matrix(np.array([[1.0]]))
+    m = oracle.thm2_margin(A1, np.zeros(1), np.zeros(1), np.ones(1), np.full(1, 2.0), 0.25)
+    assert abs(m + 1.0) < 1e-15
+    p, A = _tiny(n=6, n_ang=8, bins=9)
+    rng = np.random.default_rng(21)
+    Ad = A.toarray()
+    for _ in range(3):
+        xp, xc, xn = (rng.standard_normal(A.shape[1]) for _ in range(3))
+        mu = 10.0 ** rng.uniform(-3, -1)
+        d = xn - xc
+        want = 2.0 * (Ad @ d) @ (Ad @ (xp - xc)) + d @ d / (2.0 * mu) - (Ad @ d) @ (Ad @ d)
+        got = oracle.thm2_margin(A, p.y, xp, xc, xn, mu)
+        assert abs(got - want) <= 1e-10 * (abs(want) + d @ d / mu)
 
 
 def test_c1_reconstruction_improves():

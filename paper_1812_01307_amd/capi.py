@@ -191,11 +191,13 @@ class Plan:
         self.nrows, self.ncols = nrows, ncols
         self.flags = flags
 
-    def __del__(self):
+    # the destroy function is bound at class creation: at interpreter exit the
+    # module's globals may already be gone when the last objects are collected
+    def __del__(self, _destroy=_lib.bsgd_plan_destroy):
         h = getattr(self, "handle", None)
         if h:
-            _lib.bsgd_plan_destroy(h)
             self.handle = None
+            _destroy(h)
 
 
 def bsgd_plan_workspace_size(nrows, ncols, nnz, M, N, H, W, D=1, view_len=0, flags=0) -> int:
@@ -419,11 +421,13 @@ class State:
         self.nrhs = nrhs
         self.flags = flags
 
-    def __del__(self):
+    # the destroy function is bound at class creation: at interpreter exit the
+    # module's globals may already be gone when the last objects are collected
+    def __del__(self, _destroy=_lib.bsgd_state_destroy):
         h = getattr(self, "handle", None)
         if h:
-            _lib.bsgd_state_destroy(h)
             self.handle = None
+            _destroy(h)
 
 
 def bsgd_state_workspace_size(plan: Plan, nrhs=1, flags=0) -> int:
@@ -576,12 +580,17 @@ class Graph:
     def __init__(self, handle, state):
         self.handle = handle
         self.state = state
+        # the captured kernels read the attached store and its partial sums
+        self.fused = getattr(state, "fused", None)
+        self.fused_partials = getattr(state, "fused_partials", None)
 
-    def __del__(self):
+    # the destroy function is bound at class creation: at interpreter exit the
+    # module's globals may already be gone when the last objects are collected
+    def __del__(self, _destroy=_lib.bsgd_graph_destroy):
         h = getattr(self, "handle", None)
         if h:
-            _lib.bsgd_graph_destroy(h)
             self.handle = None
+            _destroy(h)
 
 
 def bsgd_graph_create(state: State, mu, lam, epochs, prox_iters, stream=None) -> Graph:
@@ -617,11 +626,13 @@ class Fused:
         self.workspace = workspace
         self.plan = plan  # keeps the plan alive
 
-    def __del__(self):
+    # the destroy function is bound at class creation: at interpreter exit the
+    # module's globals may already be gone when the last objects are collected
+    def __del__(self, _destroy=_lib.bsgd_fused_destroy):
         h = getattr(self, "handle", None)
         if h:
-            _lib.bsgd_fused_destroy(h)
             self.handle = None
+            _destroy(h)
 
 
 def bsgd_fused_workspace_size(plan: Plan, chunks=0, flags=0, stream=None) -> int:

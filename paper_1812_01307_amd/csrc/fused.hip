@@ -634,7 +634,8 @@ __global__ __launch_bounds__(64 * W) void k_fused(
         xs[(((b >> 3) << 3) + (w >> 3)) * kFTS + ((b & 7) << 3) + (w & 7)] =
             x[xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w];
     }
-  const int e = MODE == kPassA ? 0 : fixed_exponent(smax, __uint_as_float(*rmax_in));
+  const float rmax = MODE == kPassA ? 0.f : __uint_as_float(*rmax_in);
+  const int e = fixed_exponent(smax, rmax);
   const double scale = ldexp(1.0, e);
   __syncthreads();
   // the next slice's table entries and its r value load while a slice streams
@@ -696,13 +697,17 @@ __global__ __launch_bounds__(64 * W) void k_fused(
   __syncthreads();
   if constexpr (MODE == kPassA) return;
   const double inv = ldexp(1.0, -e);
+  // a residual with an infinite or NaN entry has no fixed-point scale: its
+  // terms would drop out of the sums, so the partials carry a NaN instead and
+  // the divergence reaches x and the next residual
+  const bool rbad = !(rmax <= 3.40282347e38f);
   for (int i = tid; i < kFT * kFT; i += NT) {
     const int b = i >> 6, w = i & 63;
     const int tr8 = ftr * 8 + (b >> 3), tc8 = ftc * 8 + (b & 7);
     if (tr8 < g.Ht && tc8 < g.Wt) {
       const int a = (((b >> 3) << 3) + (w >> 3)) * kFTS + ((b & 7) << 3) + (w & 7);
       gp[(int64_t)q * c_int + xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w] =
-          (float)from_fixed(gs[a], inv);
+          rbad ? __uint_as_float(0x7fc00000u) : (float)from_fixed(gs[a], inv);
     }
   }
 }

@@ -975,11 +975,49 @@ extern "C" bsgd_status bsgd_get_res_change_rhs(const bsgd_state* st, hipStream_t
 // ---------------------------------------------------------------------------
 // HIP graph of a fixed number of epochs
 // ---------------------------------------------------------------------------
+// What a captured graph has baked into its kernels' arguments: the iterate
+// and residual buffers of the state's current parity, the attached
+// single-pass store and its partial sums, the update rule and the kernel
+// choices of the epoch schedule.  A replay is valid only while all of them
+// are unchanged.
+struct GraphKey {
+  int cur = 0, method = 0, overlap = 0, schedule = 0;
+  const bsgd_fused* fz = nullptr;
+  const float* zp = nullptr;
+  const float* gp = nullptr;
+  const unsigned* rmax = nullptr;
+  int lanes_fwd = 0, lanes_bwd = 0, staged_fwd = 0, staged_bwd = 0;
+  bool operator==(const GraphKey& o) const {
+    return cur == o.cur && method == o.method && overlap == o.overlap &&
+           schedule == o.schedule && fz == o.fz && zp == o.zp && gp == o.gp && rmax == o.rmax &&
+           lanes_fwd == o.lanes_fwd && lanes_bwd == o.lanes_bwd && staged_fwd == o.staged_fwd &&
+           staged_bwd == o.staged_bwd;
+  }
+};
+
+static GraphKey graph_key(const bsgd_state* st) {
+  GraphKey k;
+  k.cur = st->cur;
+  k.method = st->method;
+  k.overlap = st->overlap;
+  k.schedule = st->prox_schedule;
+  k.fz = st->fz;
+  k.zp = st->fzp.zp;
+  k.gp = st->fzp.gp;
+  k.rmax = st->fzp.rmax;
+  k.lanes_fwd = st->plan->fwd.lanes_per_row;
+  k.lanes_bwd = st->plan->bwd.lanes_per_row;
+  k.staged_fwd = st->plan->sfwd.lanes;
+  k.staged_bwd = st->plan->sbwd.lanes;
+  return k;
+}
+
 struct bsgd_graph {
   bsgd_state* st = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int epochs = 0;
+  GraphKey key;  // the state's configuration at capture
 };
 
 extern "C" bsgd_status bsgd_graph_create(bsgd_state* st, float mu, float lam, int epochs,
@@ -993,6 +1031,7 @@ extern "C" bsgd_status bsgd_graph_create(bsgd_state* st, float mu, float lam, in
   st->t_cap = 0;  // no timing events inside the graph
   const int64_t done = st->epochs_done;
   const int cur = st->cur;
+  const GraphKey key = graph_key(st);
   BSGD_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
   bsgd_status s = bsgd_run_epochs(st, mu, lam, epochs, prox_iters, stream);
   hipGraph_t g = nullptr;
@@ -1021,6 +1060,7 @@ extern "C" bsgd_status bsgd_graph_create(bsgd_state* st, float mu, float lam, in
   gr->graph = g;
   gr->exec = ex;
   gr->epochs = epochs;
+  gr->key = key;
   *out = gr;
   return BSGD_OK;
 }
@@ -1028,6 +1068,13 @@ extern "C" bsgd_status bsgd_graph_create(bsgd_state* st, float mu, float lam, in
 extern "C" bsgd_status bsgd_graph_launch(bsgd_graph* gr, hipStream_t stream) {
   clear_error();
   BSGD_REQUIRE(gr != nullptr, "graph is NULL");
+  const GraphKey now = graph_key(gr->st);
+  BSGD_REQUIRE(now.cur == gr->key.cur,
+               "the state's iterate buffers changed parity since capture (an odd number of "
+               "epochs ran outside the graph); recapture");
+  BSGD_REQUIRE(now == gr->key,
+               "the state's configuration (single-pass store, partials, update rule, epoch "
+               "schedule or kernel choice) changed since capture; recapture");
   BSGD_HIP(hipGraphLaunch(gr->exec, stream));
   gr->st->epochs_done += gr->epochs;
   return BSGD_OK;

@@ -197,6 +197,45 @@ def test_fused_runs_are_bitwise_reproducible_and_graphs_replay_exactly():
             _ = torch.ones(1000, device="cuda").sum().item()
 
 
+def test_graph_refuses_replay_after_state_changes():
+    """A graph bakes in the iterate parity and the attached store: a replay after
+    an odd eager epoch, or after the store was detached or swapped, is refused,
+    and an even eager run in between keeps replays exact."""
+    import paper_1812_01307_amd as bsgd
+    p = problem("c1_64")
+    plan = plan_for(p)
+    mu = float(np.float32(mu_for(p)))
+    F = _fused(plan)
+    ref, _ = _run(p, plan, F, mu, 20.0, 8, 20)
+    s = torch.cuda.Stream()
+    st = bsgd.bsgd_state_create(plan)
+    bsgd.bsgd_state_attach_fused(st, F)
+    with torch.cuda.stream(s):
+        bsgd.bsgd_state_init(st, _dev(f32(p.y)), stream=s)
+        gr = bsgd.bsgd_graph_create(st, mu, 20.0, 2, 20, stream=s)
+        bsgd.bsgd_graph_launch(gr, stream=s)
+        bsgd.bsgd_run_epochs(st, mu, 20.0, 1, 20, stream=s)  # odd: buffers change parity
+        with pytest.raises(bsgd.BsgdError, match="parity"):
+            bsgd.bsgd_graph_launch(gr, stream=s)
+        bsgd.bsgd_run_epochs(st, mu, 20.0, 1, 20, stream=s)  # parity restored
+        bsgd.bsgd_graph_launch(gr, stream=s)  # epochs 5, 6
+        s.synchronize()
+        assert np.array_equal(_host(bsgd.bsgd_get_x(st, stream=s)), ref[5])
+        # the graph keeps the store it captured alive
+        assert gr.fused is F
+        bsgd.bsgd_state_attach_fused(st, None)
+        with pytest.raises(bsgd.BsgdError, match="configuration"):
+            bsgd.bsgd_graph_launch(gr, stream=s)
+        bsgd.bsgd_state_attach_fused(st, F)  # new partials buffer: still refused
+        with pytest.raises(bsgd.BsgdError, match="configuration"):
+            bsgd.bsgd_graph_launch(gr, stream=s)
+        bsgd.bsgd_state_set_overlap(st, 2)
+        gr2 = bsgd.bsgd_graph_create(st, mu, 20.0, 2, 20, stream=s)
+        bsgd.bsgd_graph_launch(gr2, stream=s)  # epochs 7, 8
+        s.synchronize()
+        assert np.array_equal(_host(bsgd.bsgd_get_x(st, stream=s)), ref[7])
+
+
 def test_fused_validation():
     import paper_1812_01307_amd as bsgd
     p = problem("c1_64")

@@ -298,6 +298,24 @@ def test_divergence_is_reported():
         bsgd.bsgd_get_stats(st)
 
 
+def test_divergence_is_reported_on_the_single_pass_path():
+    """Same run through the tile-sliced store: once max |r| overflows, the
+    fixed-point backprojection has no scale and must hand on a NaN rather
+    than drop the non-finite terms."""
+    import paper_1812_01307_amd as bsgd
+    p = problem("c1_64")
+    plan = plan_for(p)
+    u = oracle.power_umax(matrix(p))
+    st = bsgd.bsgd_state_create(plan)
+    bsgd.bsgd_state_attach_fused(st, bsgd.bsgd_fused_create(plan, 0, 0))
+    bsgd.bsgd_state_init(st, _dev(f32(p.y)))
+    bsgd.bsgd_run_epochs(st, 8.0 / (2.0 * u), 0.0, 400, 0)
+    rn, ep, diverged = bsgd.bsgd_get_stats(st, allow_diverged=True)
+    assert diverged and ep == 400
+    x = _host(bsgd.bsgd_get_x(st))
+    assert not np.all(np.isfinite(x))
+
+
 def test_invalid_inputs_are_rejected():
     import paper_1812_01307_amd as bsgd
     p = problem(None, n=8, n_ang=6, bins=13, M=2, N=2, seed=3)

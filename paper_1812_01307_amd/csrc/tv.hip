@@ -27,6 +27,31 @@ namespace bsgd {
 
 enum QMode { kQZero = 0, kQCopy = 1, kQMomentum = 2 };
 
+// Projection onto the unit disk (2-D) or ball (3-D), applied in place: a
+// dual vector longer than 1 is scaled by the hardware reciprocal square
+// root of its squared length (within about 1 ulp of the division by the
+// length; one transcendental instead of a square root and two or three
+// IEEE divisions).  Every prox kernel uses these, so all schedules keep
+// identical per-pixel arithmetic.
+__device__ __forceinline__ void project2(float& av, float& ah) {
+  const float s2 = fmaf(av, av, ah * ah);
+  if (s2 > 1.f) {
+    const float sc = __builtin_amdgcn_rsqf(s2);
+    av *= sc;
+    ah *= sc;
+  }
+}
+
+__device__ __forceinline__ void project3(float& ad, float& av, float& ah) {
+  const float s2 = fmaf(ad, ad, fmaf(av, av, ah * ah));
+  if (s2 > 1.f) {
+    const float sc = __builtin_amdgcn_rsqf(s2);
+    ad *= sc;
+    av *= sc;
+    ah *= sc;
+  }
+}
+
 template <bool TILED>
 __device__ __forceinline__ int64_t pidx(const Layout& L, int d, int s, int t) {
   if constexpr (TILED)
@@ -102,12 +127,12 @@ __global__ __launch_bounds__(kTW* kTH) void k_fgp_iter2(
     const float uc = su[ls][lt];
     const float gv = s >= 1 ? uc - su[ls - 1][lt] : 0.f;
     const float gh = t >= 1 ? uc - su[ls][lt - 1] : 0.f;
-    const float av = fmaf(step, gv, sqv[ls][lt]);
-    const float ah = fmaf(step, gh, sqh[ls][lt]);
-    const float nrm = fmaxf(1.f, sqrtf(av * av + ah * ah));
+    float av = fmaf(step, gv, sqv[ls][lt]);
+    float ah = fmaf(step, gh, sqh[ls][lt]);
+    project2(av, ah);
     const int64_t i = pidx<TILED>(L, 0, s, t) * S + img;
-    ov[i] = av / nrm;
-    oh[i] = ah / nrm;
+    ov[i] = av;
+    oh[i] = ah;
   }
 }
 
@@ -152,7 +177,7 @@ __global__ __launch_bounds__(256) void k_fgp_out2b(Layout L, int S, const float*
 // ---------------------------------------------------------------------------
 constexpr int kFT = 32;
 constexpr int kFuseMax = 20;    // most iterations one launch can hold (LDS sizing)
-constexpr int kFuseSplit = 12;  // launches take equal chunks of at most this many
+constexpr int kFuseSplit = 10;  // launches take equal chunks of at most this many
 static_assert(kFuseSplit <= kFuseMax, "chunks must fit the LDS regions");
 constexpr int kFR = kFT + 2 * (kFuseMax + 1);  // 74
 constexpr int kFThreads = 512;
@@ -263,11 +288,11 @@ __global__ __launch_bounds__(kFThreads) void k_fgp_fused2(
           const float uc = su[o];
           const float gv = s >= 1 ? uc - su[o - kFR] : 0.f;
           const float gh = t >= 1 ? uc - su[o - 1] : 0.f;
-          const float av = fmaf(step, gv, qv_at(o));
-          const float ah = fmaf(step, gh, qh_at(o));
-          const float nrm = fmaxf(1.f, sqrtf(av * av + ah * ah));
-          p2v[o] = av / nrm;
-          p2h[o] = ah / nrm;
+          float av = fmaf(step, gv, qv_at(o));
+          float ah = fmaf(step, gh, qh_at(o));
+          project2(av, ah);
+          p2v[o] = av;
+          p2h[o] = ah;
         }
       }
     }
@@ -312,11 +337,12 @@ __global__ __launch_bounds__(kFThreads) void k_fgp_fused2(
 // instead of about twenty.  Region-edge pixels read zeros for their missing
 // neighbours; like the LDS-resident kernel, errors from the edge move one
 // pixel per iteration and stay inside the halo.
-constexpr int kRNP = 6;                                  // rows per thread
+constexpr int kRNP = 3;                                  // rows per thread
 constexpr int kRThreads = 1024;
-constexpr int kRMax = kFT + 2 * (kFuseMax + 1);          // 74
+constexpr int kRMax = kFT + 2 * (kFuseSplit + 1);        // 54: launches hold at most kFuseSplit
 constexpr int kRP = kRMax + 2;                           // LDS pitch: a pad column each side
-constexpr int kRNS = (kRMax + kRNP - 1) / kRNP;          // 13 strips
+constexpr int kRNS = (kRMax + kRNP - 1) / kRNP;          // 18 strips
+static_assert(kRMax * kRNS <= kRThreads, "every strip of the largest region needs a thread");
 
 template <bool TILED>
 __global__ __launch_bounds__(kRThreads) void k_fgp_reg2(
@@ -432,13 +458,13 @@ __global__ __launch_bounds__(kRThreads) void k_fgp_reg2(
         const float left = su[ls * kRP + lc - 1];
         const float gv = s >= 1 ? uc - above : 0.f;
         const float gh = t >= 1 ? uc - left : 0.f;
-        const float av = fmaf(step, gv, qv[r]);
-        const float ah = fmaf(step, gh, qh[r]);
-        const float nrm = fmaxf(1.f, sqrtf(av * av + ah * ah));
+        float av = fmaf(step, gv, qv[r]);
+        float ah = fmaf(step, gh, qh[r]);
+        project2(av, ah);
         p2v[r] = p1v[r];
         p2h[r] = p1h[r];
-        p1v[r] = av / nrm;
-        p1h[r] = ah / nrm;
+        p1v[r] = av;
+        p1h[r] = ah;
       }
     }
   }
@@ -555,13 +581,13 @@ __global__ __launch_bounds__(256) void k_fgp_p3(Layout L, int64_t n, float step,
     const float gd = d >= 1 ? uc - u[pidx<TILED>(L, d - 1, s, t)] : 0.f;
     const float gv = s >= 1 ? uc - u[pidx<TILED>(L, d, s - 1, t)] : 0.f;
     const float gh = t >= 1 ? uc - u[pidx<TILED>(L, d, s, t - 1)] : 0.f;
-    const float ad = fmaf(step, gd, q[c]);
-    const float av = fmaf(step, gv, q[n + c]);
-    const float ah = fmaf(step, gh, q[2 * n + c]);
-    const float nrm = fmaxf(1.f, sqrtf(ad * ad + av * av + ah * ah));
-    p[c] = ad / nrm;
-    p[n + c] = av / nrm;
-    p[2 * n + c] = ah / nrm;
+    float ad = fmaf(step, gd, q[c]);
+    float av = fmaf(step, gv, q[n + c]);
+    float ah = fmaf(step, gh, q[2 * n + c]);
+    project3(ad, av, ah);
+    p[c] = ad;
+    p[n + c] = av;
+    p[2 * n + c] = ah;
   }
 }
 
@@ -617,17 +643,21 @@ static unsigned grid_for(int64_t n) {
   return (unsigned)b;
 }
 
-// Momentum coefficients c_k = (tau_{k-1} - 1) / tau_k for k = 1..iters
-// (c_1 = c_2 = 0), evaluated in double and rounded once to float.
-static void momentum(int iters, std::vector<float>& c) {
-  c.assign(iters + 1, 0.f);
-  double tau = 1.0;  // tau_1
-  for (int k = 2; k <= iters; ++k) {
+// Momentum coefficients c_k = (tau_{k-1} - 1) / tau_k for k = 1, 2, ...
+// (c_1 = c_2 = 0), evaluated in double and rounded once to float.  next()
+// returns c_1, c_2, ... in turn; kept on the stack so that the prox makes no
+// host allocation either.
+struct Momentum {
+  double tau = 1.0;  // tau_{k-1}
+  int k = 0;
+  float next() {
+    if (++k == 1) return 0.f;
     const double tau_next = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tau * tau));  // tau_k
-    c[k] = (float)((tau - 1.0) / tau_next);
+    const float c = (float)((tau - 1.0) / tau_next);
     tau = tau_next;
+    return c;
   }
-}
+};
 
 // 2-D FGP over S images ([n][S] with n the per-image vector length) in chunks
 // of up to kFuseMax iterations, one fused launch each.  A chunk reads p_{k0}
@@ -636,8 +666,8 @@ static void momentum(int iters, std::vector<float>& c) {
 // buffer pairs; the last chunk writes the result.
 template <bool TILED>
 static hipError_t fgp2_per_iteration(const Layout& L, int S, const float* b, float theta0,
-                                     const float* lam, float mu, int iters,
-                                     const std::vector<float>& c, float* out, float* ws,
+                                     const float* lam, float mu, int iters, Momentum& mom,
+                                     float* out, float* ws,
                                      int64_t n, hipStream_t s) {
   const int64_t m = n * S;
   float* buf[3] = {ws, ws + 2 * m, ws + 4 * m};  // rotating (pv, ph) pairs
@@ -649,8 +679,8 @@ static hipError_t fgp2_per_iteration(const Layout& L, int S, const float* b, flo
     const float* p1 = buf[(cur + 2) % 3];  // p_{k-1}
     const float* p2 = buf[(cur + 1) % 3];  // p_{k-2}
     const int qm = k == 1 ? kQZero : (k == 2 ? kQCopy : kQMomentum);
-    k_fgp_iter2<TILED><<<grid, block, 0, s>>>(L, S, lam, mu, theta0, b, c[k], qm, p1, p1 + m, p2,
-                                              p2 + m, o, o + m);
+    k_fgp_iter2<TILED><<<grid, block, 0, s>>>(L, S, lam, mu, theta0, b, mom.next(), qm, p1,
+                                              p1 + m, p2, p2 + m, o, o + m);
     cur = (cur + 1) % 3;
   }
   const float* pk = buf[(cur + 2) % 3];
@@ -665,10 +695,11 @@ static hipError_t fgp2_per_iteration(const Layout& L, int S, const float* b, flo
 // iteration.  All compute the same recurrence with the same arithmetic.
 template <bool TILED>
 static hipError_t fgp2_chunks(const Layout& L, int S, const float* b, float theta0,
-                              const float* lam, float mu, int iters, const std::vector<float>& c,
-                              float* out, float* ws, int64_t n, hipStream_t s, int schedule) {
+                              const float* lam, float mu, int iters, float* out, float* ws,
+                              int64_t n, hipStream_t s, int schedule) {
+  Momentum mom;
   if (schedule == kFgpPerIteration && iters >= 1)
-    return fgp2_per_iteration<TILED>(L, S, b, theta0, lam, mu, iters, c, out, ws, n, s);
+    return fgp2_per_iteration<TILED>(L, S, b, theta0, lam, mu, iters, mom, out, ws, n, s);
   const int64_t m = n * S;
   float* buf[4] = {ws, ws + 2 * m, ws + 4 * m, ws + 6 * m};
   dim3 grid((L.W + kFT - 1) / kFT, (L.H + kFT - 1) / kFT, S);
@@ -682,7 +713,7 @@ static hipError_t fgp2_chunks(const Layout& L, int S, const float* b, float thet
   for (int k0 = 0, li = 0; k0 < iters; ++li) {
     const int chunk = iters / nl + (li < iters % nl ? 1 : 0);
     FuseArgs ca{};
-    for (int q = 1; q <= chunk; ++q) ca.coef[q] = c[k0 + q];
+    for (int q = 1; q <= chunk; ++q) ca.coef[q] = mom.next();  // c_{k0+q}
     const float* i1 = buf[in];
     const float* i2 = buf[in + 1];
     float* o1 = buf[2 - in];
@@ -711,10 +742,9 @@ static hipError_t tv_prox_impl(const Layout& L, const float* b, float theta, int
     k_copy_img<TILED><<<grid_for(npix), 256, 0, s>>>(L, b, out);
     return hipGetLastError();
   }
-  std::vector<float> c;
-  momentum(iters, c);
   if (L.D == 1)
-    return fgp2_chunks<TILED>(L, 1, b, theta, nullptr, 1.f, iters, c, out, ws, n, s, schedule);
+    return fgp2_chunks<TILED>(L, 1, b, theta, nullptr, 1.f, iters, out, ws, n, s, schedule);
+  Momentum mom;
   float* buf[3] = {ws, ws + 3 * n, ws + 6 * n};  // (pd, pv, ph) triples
   float* q = ws + 9 * n;
   float* u = ws + 12 * n;
@@ -725,7 +755,7 @@ static hipError_t tv_prox_impl(const Layout& L, const float* b, float theta, int
     const float* p1 = buf[(cur + 2) % 3];
     const float* p2 = buf[(cur + 1) % 3];
     const int qm = k == 1 ? kQZero : (k == 2 ? kQCopy : kQMomentum);
-    k_fgp_q3<<<grid_for(3 * n), 256, 0, s>>>(3 * n, c[k], qm, p1, p2, q);
+    k_fgp_q3<<<grid_for(3 * n), 256, 0, s>>>(3 * n, mom.next(), qm, p1, p2, q);
     k_fgp_u3<TILED><<<grid_for(npix), 256, 0, s>>>(L, n, b, theta, q, u);
     k_fgp_p3<TILED><<<grid_for(npix), 256, 0, s>>>(L, n, step, q, u, o);
     cur = (cur + 1) % 3;
@@ -743,13 +773,11 @@ hipError_t tv_prox_run(const Layout& L, bool tiled, const float* b, float theta,
 hipError_t tv_prox_batch(const Layout& L, int S, const float* b, float mu, const float* lam,
                          float lam0, int iters, float* out, float* ws, hipStream_t s,
                          int schedule) {
-  std::vector<float> c;
-  momentum(std::max(iters, 1), c);
   if (iters == 0) {
     // identity for every image: one chunk-free copy through the theta = 0 path
-    return fgp2_chunks<true>(L, S, b, 0.f, nullptr, mu, 1, c, out, ws, L.c_int, s, kFgpFused);
+    return fgp2_chunks<true>(L, S, b, 0.f, nullptr, mu, 1, out, ws, L.c_int, s, kFgpFused);
   }
-  return fgp2_chunks<true>(L, S, b, mu * lam0, lam, mu, iters, c, out, ws, L.c_int, s, schedule);
+  return fgp2_chunks<true>(L, S, b, mu * lam0, lam, mu, iters, out, ws, L.c_int, s, schedule);
 }
 
 // ---------------------------------------------------------------------------
@@ -857,14 +885,14 @@ __global__ __launch_bounds__(kVThreads) void k_fgp_iter3v(
       const float gv = s >= 1 ? u0 - su[uc - (kVS + 1)][j + 1] : 0.f;
       const float gh = t >= 1 ? u0 - su[uc - 1][j + 1] : 0.f;
       const int c = (ls + 1) * (kVS + 2) + lt + 1;
-      const float ad = fmaf(step, gd, sq[0][c][j]);
-      const float av = fmaf(step, gv, sq[1][c][j]);
-      const float ah = fmaf(step, gh, sq[2][c][j]);
-      const float nrm = fmaxf(1.f, sqrtf(ad * ad + av * av + ah * ah));
+      float ad = fmaf(step, gd, sq[0][c][j]);
+      float av = fmaf(step, gv, sq[1][c][j]);
+      float ah = fmaf(step, gh, sq[2][c][j]);
+      project3(ad, av, ah);
       const int64_t i = L.pix_st(0, s, t) * S + e;
-      po[i] = ad / nrm;
-      po[n + i] = av / nrm;
-      po[2 * n + i] = ah / nrm;
+      po[i] = ad;
+      po[n + i] = av;
+      po[2 * n + i] = ah;
     }
     __syncthreads();
     // the chunk's last q and u slices become the next chunk's first
@@ -907,8 +935,7 @@ hipError_t tv_prox_volume(const Layout& L, int S, const float* b, float theta, i
     k_copy_f32v<<<grid_for(n), 256, 0, s>>>(b, out, n);
     return hipGetLastError();
   }
-  std::vector<float> c;
-  momentum(iters, c);
+  Momentum mom;
   float* buf[3] = {ws, ws + 3 * n, ws + 6 * n};  // (pd, pv, ph) triples
   const float step = 1.0f / (12.0f * theta);
   const unsigned grid = (unsigned)(L.Ht * L.Wt);
@@ -918,7 +945,8 @@ hipError_t tv_prox_volume(const Layout& L, int S, const float* b, float theta, i
     const float* p1 = buf[(cur + 2) % 3];
     const float* p2 = buf[(cur + 1) % 3];
     const int qm = k == 1 ? kQZero : (k == 2 ? kQCopy : kQMomentum);
-    k_fgp_iter3v<<<grid, kVThreads, 0, s>>>(L, S, b, theta, step, c[k], qm, p1, p2, o, n);
+    k_fgp_iter3v<<<grid, kVThreads, 0, s>>>(L, S, b, theta, step, mom.next(), qm, p1, p2, o,
+                                             n);
     cur = (cur + 1) % 3;
   }
   k_fgp_out3v<<<grid_for((int64_t)L.H * L.W * S), 256, 0, s>>>(L, S, b, theta,

@@ -242,6 +242,20 @@ bsgd_status bsgd_tv_workspace_size(int H, int W, int D, size_t* bytes);
 bsgd_status bsgd_tv_prox(int H, int W, int D, const float* b, float theta, int iters, float* out,
                          void* ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * bsgd_tv_prox without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, kernels and results (bitwise) as
+ * bsgd_tv_prox; the FGP duals live in a scratch array of 32 MiB that the
+ * library holds on every GPU it runs on until the process ends.  Images
+ * needing more (2-D above 1048576 pixels, volumes above 645277 voxels) are
+ * rejected with BSGD_ERR_WORKSPACE.  The stream must belong to the current
+ * device.  Makes no allocation (device or host).  Calls that overlap on one
+ * GPU share the array and race: serialise them (one stream, or events).
+ */
+bsgd_status bsgd_tv_prox_noalloc(int H, int W, int D, const float* b, float theta, int iters,
+                                 float* out, hipStream_t stream);
+
 /* TV(x) of Eq. 2 (3-D when D > 1), accumulated in FP64.  Synchronises. */
 bsgd_status bsgd_tv_value(int H, int W, int D, const float* x, void* ws, size_t ws_bytes,
                           hipStream_t stream, double* tv);

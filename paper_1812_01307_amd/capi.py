@@ -78,6 +78,7 @@ _PROTOS = {
     "bsgd_backproject_block": [_vp, _i32, _i32, _i32, _vp, _vp, _vp],
     "bsgd_tv_workspace_size": [_i32, _i32, _i32, ctypes.POINTER(_sz)],
     "bsgd_tv_prox": [_i32, _i32, _i32, _vp, _f32, _i32, _vp, _vp, _sz, _vp],
+    "bsgd_tv_prox_noalloc": [_i32, _i32, _i32, _vp, _f32, _i32, _vp, _vp],
     "bsgd_tv_value": [_i32, _i32, _i32, _vp, _vp, _sz, _vp, ctypes.POINTER(ctypes.c_double)],
     "bsgd_power_workspace_size": [_vp, ctypes.POINTER(_sz)],
     "bsgd_power_umax": [_vp, _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(_f32)],
@@ -355,6 +356,18 @@ def bsgd_tv_prox(b, theta, iters, out=None, ws=None, stream=None):
         ws = _ws(nbytes, b.device)
     _check("bsgd_tv_prox", _lib.bsgd_tv_prox(H, W, D, _ptr(b), float(theta), int(iters), _ptr(out),
                                              _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def bsgd_tv_prox_noalloc(b, theta, iters, out, stream=None):
+    """bsgd_tv_prox on the library's own scratch array: `out` is caller-provided
+    (same shape as b), nothing is allocated."""
+    shape = tuple(b.shape)
+    D, H, W = (1,) + shape if len(shape) == 2 else shape
+    _chk(b)
+    _chk(out, b.numel(), "out")
+    _check("bsgd_tv_prox_noalloc", _lib.bsgd_tv_prox_noalloc(
+        H, W, D, _ptr(b), float(theta), int(iters), _ptr(out), _stream(stream)))
     return out
 
 

@@ -19,6 +19,7 @@
 // row-major order or in the library's internal 8 x 8-tiled pixel order.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "bsgd_internal.h"
@@ -1035,6 +1036,74 @@ extern "C" bsgd_status bsgd_tv_prox(int H, int W, int D, const float* b, float t
   }
   BSGD_HIP(tv_prox_run(natural_layout(H, W, D), false, b, theta, iters, out,
                        static_cast<float*>(ws), stream, kFgpFused));
+  return BSGD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free prox, for callers that cannot allocate device memory (code
+// under HIP graph capture, tight serving loops).  The FGP duals live in a
+// file-scope device array instead of a caller workspace; every GPU the
+// library runs on holds its own copy of it until the process ends.  In host
+// code the array's name is not a device address: its address on each device
+// is taken once, with that device current, by hipGetSymbolAddress, and only
+// that pointer is passed to kernels.  The FGP reads no dual it has not
+// written in the same call (iteration 1 takes q = 0, iteration 2 q = p_1),
+// so the array needs no clearing between calls; calls that overlap on one
+// GPU share it and race.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = (size_t)32 << 20;  // 2-D up to 2^20 pixels, 3-D 645277 voxels
+constexpr int kNoAllocDevices = 64;
+static __device__ __align__(256) float scratch[kNoAllocBytes / sizeof(float)];
+
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[kNoAllocDevices] = {};
+
+// Device address of `scratch` on device `dev` (the current device).
+static bsgd_status scratch_on_device(int dev, float** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                hipGetErrorString(e));
+      return BSGD_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_tv_prox_noalloc(int H, int W, int D, const float* b, float theta,
+                                            int iters, float* out, hipStream_t stream) {
+  clear_error();
+  BSGD_REQUIRE(H >= 1 && W >= 1 && D >= 1, "bad image shape %d x %d x %d", H, W, D);
+  BSGD_REQUIRE(b && out, "NULL argument");
+  BSGD_REQUIRE(b != out, "out may not alias b");
+  BSGD_REQUIRE(std::isfinite(theta) && theta >= 0.f, "theta must be finite and >= 0");
+  BSGD_REQUIRE(iters >= 0, "iters must be >= 0");
+  const int64_t n = (int64_t)H * W * D;
+  const size_t need = tv_ws_floats(n, D) * sizeof(float);
+  if (need > kNoAllocBytes) {
+    set_error("bsgd_tv_prox_noalloc: a %d x %d x %d image needs %zu bytes of scratch, the "
+              "library holds %zu (2-D images up to 1048576 pixels, volumes up to 645277 voxels)",
+              H, W, D, need, kNoAllocBytes);
+    return BSGD_ERR_WORKSPACE;
+  }
+  int dev = -1;
+  BSGD_HIP(hipGetDevice(&dev));
+  BSGD_REQUIRE(dev >= 0 && dev < kNoAllocDevices, "device %d out of range", dev);
+  if (stream) {
+    int sdev = -1;
+    BSGD_HIP(hipStreamGetDevice(stream, &sdev));
+    BSGD_REQUIRE(sdev == dev, "stream belongs to device %d, current device is %d", sdev, dev);
+  }
+  float* ws = nullptr;
+  const bsgd_status st = scratch_on_device(dev, &ws);
+  if (st != BSGD_OK) return st;
+  BSGD_HIP(tv_prox_run(natural_layout(H, W, D), false, b, theta, iters, out, ws, stream,
+                       kFgpFused));
   return BSGD_OK;
 }
 

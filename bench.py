@@ -78,6 +78,68 @@ def _alg_bytes(nnz, r, c, val_bytes):
     return fwd, bwd
 
 
+def cpu_baseline_bsgd(args):
+    """The FP64 oracle of Algorithm 1 timed on the host: one thread, then one
+    independent reconstruction per core (worker processes forked after the
+    matrix is built, so they share it).  Returns the cpu_baseline record."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import oracle  # CPU baseline leg only
+    import synth
+
+    t = time.perf_counter()
+    prob = synth.make_problem(args.config, with_transpose=False)
+    rp = prob.row_ptr.astype(np.int32) if prob.nnz < 2**31 - 1 else prob.row_ptr
+    A64 = oracle.as_matrix(rp, prob.col, prob.val, prob.ncols)
+    # any stable step serves for timing: a few power iterations
+    mu = 0.9 / (2.0 * oracle.power_umax(A64, tol=1e-6, max_iter=5))
+    shape, K, y = (prob.H, prob.W), prob.prox_iters, prob.y
+    # about 10 s of one core at 512^2 (0.5 s per epoch); fewer epochs at 1024^2
+    e1 = args.cpu_epochs if args.config == "c2_512" else max(2, args.cpu_epochs // 8)
+    print(f"[bench] cpu baseline: oracle set-up {time.perf_counter() - t:.1f} s, "
+          f"{e1} epochs on one thread", file=sys.stderr, flush=True)
+    xc, rc = oracle.initial_state(A64, y)
+    t0 = time.perf_counter()
+    oracle.bsgd_tv(A64, y, mu, prob.lam, e1, K, shape, state=(xc, rc))
+    t1 = time.perf_counter() - t0
+    try:
+        ncores = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        ncores = os.cpu_count() or 1
+    nproc = max(1, min(ncores, 16))
+    ea = max(2, e1 // 2)
+    ctx = mp.get_context("fork")
+    gate = ctx.Barrier(nproc + 1)
+
+    def work():
+        x0, r0 = oracle.initial_state(A64, y)
+        gate.wait()
+        oracle.bsgd_tv(A64, y, mu, prob.lam, ea, K, shape, state=(x0, r0))
+
+    print(f"[bench] cpu baseline: {nproc} processes x {ea} epochs", file=sys.stderr, flush=True)
+    procs = [ctx.Process(target=work) for _ in range(nproc)]
+    for pr in procs:
+        pr.start()
+    gate.wait()
+    t0 = time.perf_counter()
+    for pr in procs:
+        pr.join()
+    ta = time.perf_counter() - t0
+    ok = all(pr.exitcode == 0 for pr in procs)
+    one = {"value": round(e1 / t1, 4), "unit": "epochs/s", "cores": 1,
+           "sample": f"{e1} epochs in {t1:.1f} s"}
+    if not ok:
+        return dict(one, kind="oracle", sample=one["sample"] + " (all-cores leg failed)")
+    return {"value": round(nproc * ea / ta, 4), "unit": "epochs/s", "cores": nproc,
+            "kind": "oracle",
+            "sample": f"{nproc} independent reconstructions of {args.config} on {nproc} of "
+                      f"{ncores} host cores, {ea} epochs each (FP64 numpy/scipy, one thread "
+                      f"per process, set-up excluded) in {ta:.1f} s",
+            "single_thread": one}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,8 +171,9 @@ def main(argv=None):
     ap.add_argument("--select-seed", type=int, default=7)
     ap.add_argument("--fused-chunks", type=int, default=0,
                     help="ray chunks of the tile-sliced store (0: automatic)")
-    ap.add_argument("--fused-waves", type=int, default=8, choices=[2, 4, 8],
-                    help="wavefronts per (tile, chunk) workgroup of the single pass")
+    ap.add_argument("--fused-waves", type=int, default=8, choices=[2, 4, 8, 16],
+                    help="wavefronts per (tile, chunk) workgroup of the single pass (16: the "
+                         "several-RHS pass only)")
     ap.add_argument("--staged", default=None, choices=["none", "fwd", "bwd", "both"],
                     help="directions built in the staged form (LDS-served gathers) and used by "
                          "the epochs of --path rows (default bwd; none with --path fused)")
@@ -148,6 +211,13 @@ def main(argv=None):
         print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on exactly one GPU "
               "(see the design notes for how the path would shard)", file=sys.stderr)
         return 2
+
+    # the oracle's all-cores leg forks worker processes: it runs before this
+    # process touches the GPU
+    pre_cpu = None
+    if (not args.no_cpu_baseline and args.cpu_epochs > 0 and args.method == "bsgd"
+            and args.config in ("c2_512", "c3_1024") and not args.copy_calibration):
+        pre_cpu = cpu_baseline_bsgd(args)
 
     import numpy as np
     import torch
@@ -468,8 +538,8 @@ def main(argv=None):
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "alg_bytes_per_launch": dom_bytes}
 
-    cpu = None
-    if not args.no_cpu_baseline and args.cpu_epochs > 0:
+    cpu = pre_cpu
+    if cpu is None and not args.no_cpu_baseline and args.cpu_epochs > 0:
         import oracle  # CPU baseline leg only
         rp64, col64, val64 = synth.projection_matrix(prob.H, prob.W, prob.n_ang, prob.bins)
         A64 = oracle.as_matrix(rp64, col64, val64, c)
@@ -575,12 +645,26 @@ def run_volume(args, np, torch, synth, bsgd):
     acc = {"fwd": 0.0, "bwd": 0.0, "prox": 0.0, "n": 0}
     stream = torch.cuda.Stream()  # graph capture needs a non-default stream
 
+    fused = args.path == "fused"
+    shape = {}
+
     def job(graph, n_epochs=epochs, timed=False):
         plan = bsgd.bsgd_plan_create(A, At, prob.M, prob.N, prob.row_off, prob.col_off, prob.H,
                                      prob.W, 1, prob.bins, flags)
-        u = bsgd.bsgd_power_umax(plan, args.power_iters, vt=vt)
+        F = None
+        if fused:
+            # the single pass for several RHS reads the tile-sliced store; the
+            # Lanczos products run on it too
+            F = bsgd.bsgd_fused_create(plan, args.fused_chunks)
+            bsgd.bsgd_fused_set_waves(F, args.fused_waves)
+            u = bsgd.bsgd_lanczos_umax_fused(F, args.umax_steps, vt=vt)
+            shape["fused"] = bsgd.bsgd_fused_shape(F)
+        else:
+            u = bsgd.bsgd_power_umax(plan, args.power_iters, vt=vt)
         mu = 0.9 / (2.0 * u)
         st = bsgd.bsgd_state_create(plan, S, vt, flags=bsgd.BSGD_STATE_VOLUME)
+        if F is not None:
+            bsgd.bsgd_state_attach_fused(st, F)
         if timed:
             bsgd.bsgd_state_enable_timing(st, n_epochs)
         bsgd.bsgd_state_init(st, Y)
@@ -623,9 +707,28 @@ def run_volume(args, np, torch, synth, bsgd):
 
     val_bytes = 2 if vt == bsgd.BSGD_VAL_F16 else 4
     nvox = c * S
-    b_fwd = (val_bytes + 4) * nnz + 8 * (r + 1) + 4 * S * (c + 2 * r)
-    b_bwd = (val_bytes + 4) * nnz + 8 * (c + 1) + 4 * S * (r + 2 * c)
-    b_prox = 40 * nvox * K  # per 3-D FGP iteration: b, two dual triples in, one out
+    # 3-D FGP in launches of up to 3 iterations (temporally blocked): per
+    # launch b and two dual triples in, two triples out; the output kernel
+    # reads b and one triple, writes x
+    nlaunch = -(-K // 3)
+    b_prox = (28 + 24) * nvox * nlaunch - 24 * nvox + 20 * nvox
+    if fused:
+        tiles, chunks, segs, slices, entries, cbytes = shape["fused"]
+        # the pass: the stored entries once (value + column byte, padding not
+        # counted), 8 B per segment slot and 12 B per slice of metadata; per
+        # RHS, x once per chunk (each unit loads its tile), r once per segment,
+        # the A x partial per segment and the A^T r partial per (chunk, pixel)
+        b_fwd = ((val_bytes + cbytes) * nnz + 8 * slices * 64 + 12 * slices
+                 + 4 * S * (chunks * c + segs + segs + chunks * c))
+        # the reduce: partials in, y and x in, r' and x^ out
+        b_bwd = 4 * S * (segs + chunks * c) + 4 * S * 2 * (r + c)
+        names = {"fwd": "k_fused_mr (A X and A^T R in one pass)",
+                 "bwd": "k_fz_reduce_mr (lines 6-8)", "prox": "k_fgp_tb3 (3-D FGP, K iterations)"}
+    else:
+        b_fwd = (val_bytes + 4) * nnz + 8 * (r + 1) + 4 * S * (c + 2 * r)
+        b_bwd = (val_bytes + 4) * nnz + 8 * (c + 1) + 4 * S * (r + 2 * c)
+        names = {"fwd": "k_spmm (A X)", "bwd": "k_spmm (A^T R)",
+                 "prox": "k_fgp_tb3 (3-D FGP, K iterations)"}
     kernel, roofline = {}, None
     if timing and acc["n"]:
         f_ms, b_ms, p_ms = (acc[k] / acc["n"] for k in ("fwd", "bwd", "prox"))
@@ -635,8 +738,7 @@ def run_volume(args, np, torch, synth, bsgd):
         dom = max((("fwd", b_fwd, f_ms), ("bwd", b_bwd, b_ms), ("prox", b_prox, p_ms)),
                   key=lambda t: t[2])
         achieved = dom[1] / dom[2] / 1e6
-        roofline = {"bound": "hbm", "kernel": {"fwd": "k_spmm (A X)", "bwd": "k_spmm (A^T R)",
-                                               "prox": "3-D FGP (K iterations)"}[dom[0]],
+        roofline = {"bound": "hbm", "kernel": names[dom[0]],
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                     "alg_bytes_per_launch": dom[1]}
@@ -654,7 +756,7 @@ def run_volume(args, np, torch, synth, bsgd):
                                f"lambda={prob.lam}, {epochs} epochs, {K} FGP iterations, "
                                f"setup S0+S0' included",
                    "nnz": nnz, "slices": S, "epochs_per_step": epochs,
-                   "graph": graph,
+                   "graph": graph, "path": args.path,
                    "kernel_timing": "events on one eager 20-epoch job after the timed region"},
         "alg_bytes_per_epoch": b_fwd + b_bwd + b_prox,
         "kernels": {k: round(v, 4) for k, v in kernel.items()},

@@ -544,8 +544,10 @@ void bsgd_graph_destroy(bsgd_graph* graph);
  *   fused_shape   tiles, chunks, segments, slices (64 segments each),
  *               stored entries (with padding) and bytes per stored column (1:
  *               8-bit steps, 2: 16-bit addresses).
- *   fused_set_waves  wavefronts per (tile, chunk) workgroup: 2, 4 (default)
- *               or 8; results change by summation order only.
+ *   fused_set_waves  wavefronts per (tile, chunk) workgroup: 2, 4, 8 (default)
+ *               or 16 (taken by the several-RHS pass; one-RHS passes run 8).
+ *               Results do not depend on it (per-segment row sums in a fixed
+ *               order, exact fixed-point column sums).
  *   fused_partials_size  bytes of the partial-sum buffer (device) that every
  *               pass needs: one float per segment slot and chunks x pixels.
  *   fused_apply   one pass in natural orders:
@@ -555,12 +557,20 @@ void bsgd_graph_destroy(bsgd_graph* graph);
  *               x, xadd, out_x: c floats; y, r, out_r: r floats (device).
  *               Uses the store's internal scratch vectors: calls on one store
  *               must not overlap.
- *   state_attach_fused  epochs of a one-RHS state on the same plan use the
+ *   state_attach_fused  epochs of a state on the same plan use the
  *               single-pass form (pass, then the reduce that writes r' and x^,
  *               then the prox, all on the caller's stream); `partials` (device,
- *               fused_partials_size bytes) belongs to the state while attached.
- *               fused == NULL detaches (the row kernels again).  The state's
- *               value type must be available in the store.
+ *               fused_partials_size_rhs bytes for the state's nrhs) belongs to
+ *               the state while attached.  fused == NULL detaches (the row
+ *               kernels again).  The state's value type must be available in
+ *               the store.  States with several RHS (batches, volumes; nrhs a
+ *               multiple of 4) take the pass four RHS per workgroup: the tile
+ *               of x for those RHS in LDS as 4-vectors, the terms of A^T r
+ *               added as 32-bit fixed-point integers per RHS (scale from that
+ *               RHS's max |r|, sums below 2^30), the four row sums of an entry
+ *               from one LDS read; results are bitwise reproducible and each
+ *               RHS's are independent of the others.  ISTA epochs of such
+ *               states, and block-select states, use the block store.
  */
 #define BSGD_FUSED_WIDE 1u /* 16-bit column addresses even where 8-bit steps would do */
 bsgd_status bsgd_fused_workspace_size(const bsgd_plan* plan, int chunks, unsigned flags,
@@ -572,6 +582,12 @@ bsgd_status bsgd_fused_shape(const bsgd_fused* fused, int* tiles, int* chunks, i
                              int64_t* slices, int64_t* entries, int* col_bytes);
 bsgd_status bsgd_fused_set_waves(bsgd_fused* fused, int waves);
 bsgd_status bsgd_fused_partials_size(const bsgd_fused* fused, size_t* bytes);
+/*
+ * Partial-sum buffer of a state with nrhs right-hand sides (1, or a multiple
+ * of 4): nrhs floats per segment slot and per (chunk, pixel), 2 nrhs words of
+ * max |r|.
+ */
+bsgd_status bsgd_fused_partials_size_rhs(const bsgd_fused* fused, int nrhs, size_t* bytes);
 bsgd_status bsgd_fused_apply(const bsgd_fused* fused, bsgd_valtype vt, const float* x,
                              const float* y, const float* r, const float* xadd, float mu,
                              float* out_r, float* out_x, void* partials, size_t partials_bytes,

@@ -113,6 +113,7 @@ _PROTOS = {
                          ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i32)],
     "bsgd_fused_set_waves": [_vp, _i32],
     "bsgd_fused_partials_size": [_vp, ctypes.POINTER(_sz)],
+    "bsgd_fused_partials_size_rhs": [_vp, _i32, ctypes.POINTER(_sz)],
     "bsgd_fused_apply": [_vp, _i32, _vp, _vp, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp],
     "bsgd_state_attach_fused": [_vp, _vp, _vp, _sz],
     "bsgd_state_set_method": [_vp, _i32],
@@ -704,6 +705,13 @@ def bsgd_fused_partials_size(fused: Fused) -> int:
     return out.value
 
 
+def bsgd_fused_partials_size_rhs(fused: Fused, nrhs: int) -> int:
+    out = _sz()
+    _check("bsgd_fused_partials_size_rhs", _lib.bsgd_fused_partials_size_rhs(
+        fused.handle, int(nrhs), ctypes.byref(out)))
+    return out.value
+
+
 def bsgd_fused_apply(fused: Fused, x, r, y=None, xadd=None, mu=0.0, out_r=None, out_x=None,
                      vt=BSGD_VAL_F32, partials=None, stream=None):
     """One single-pass product: (y - A x or A x, xadd + mu 2 A^T r or 2 A^T r)."""
@@ -736,7 +744,7 @@ def bsgd_state_attach_fused(state: State, fused, partials=None):
         state.fused = state.fused_partials = None
         return
     if partials is None:
-        partials = _ws(bsgd_fused_partials_size(fused), state.workspace.device)
+        partials = _ws(bsgd_fused_partials_size_rhs(fused, state.nrhs), state.workspace.device)
     _check("bsgd_state_attach_fused", _lib.bsgd_state_attach_fused(
         state.handle, fused.handle, _ptr(partials), partials.numel()))
     state.fused = fused

@@ -239,7 +239,20 @@ struct FusedPartials {
   float* gp = nullptr;
   unsigned* rmax = nullptr;  // 2 words: max |r| of the two residual buffers
 };
-size_t fused_partials(const bsgd_fused* F, FusedPartials* fp, void* ws);
+// zp: maxrank x r_int x S floats, gp: Q x c_int x S, rmax: 2 x S words
+size_t fused_partials(const bsgd_fused* F, int S, FusedPartials* fp, void* ws);
+// several RHS (S a multiple of 4, vectors [rows][S]): per-RHS max |v|, the
+// pass (both products, rmax_in: S words) and the reduce
+hipError_t launch_fused_absmax_mr(const float* v, int64_t n, int S, unsigned* out,
+                                  hipStream_t s);
+hipError_t launch_fused_zero(unsigned* p, int n, hipStream_t s);
+hipError_t launch_fused_pass_mr(const bsgd_fused* F, bsgd_valtype vt, int S, const float* x,
+                                const float* r, const unsigned* rmax_in, float* zp, float* gp,
+                                hipStream_t s);
+hipError_t launch_fused_reduce_mr(const bsgd_fused* F, int S, const float* zp, const float* gp,
+                                  const float* y, float* out_r, unsigned* rmax_out,
+                                  const float* xadd, float scale, float* out_x, hipStream_t s,
+                                  int parts);
 hipError_t launch_fused_absmax(const float* v, int64_t n, unsigned* out, hipStream_t s);
 // mode kPassBoth: both products; kPassA: only the A x partials (no r,
 // rmax_in may be NULL); kPassAt: only the A^T r partials (x unused).
@@ -340,7 +353,9 @@ hipError_t tv_prox_batch(const Layout& L, int S, const float* b, float mu, const
                          int schedule);
 // One volume of S slices in the internal order [c_int][S] (slice index
 // fastest), 3-D TV.  ws: tv_ws_floats(c_int * S, 2).
+// schedule kFgpPerIteration: one launch per iteration (k_fgp_iter3v);
+// otherwise launches of up to three iterations (k_fgp_tb3).  Same results.
 hipError_t tv_prox_volume(const Layout& L, int S, const float* b, float theta, int iters,
-                          float* out, float* ws, hipStream_t s);
+                          float* out, float* ws, hipStream_t s, int schedule);
 
 }  // namespace bsgd

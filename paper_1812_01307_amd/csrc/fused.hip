@@ -712,6 +712,171 @@ __global__ __launch_bounds__(64 * W) void k_fused(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Several right-hand sides (batches of images and the slices of a volume,
+// vectors [rows][S] with the RHS index fastest, S a multiple of 4).  The same
+// store and units; a workgroup takes one unit for one column of kMrC = 4
+// consecutive RHS.  The unit's tile of x for those RHS goes to LDS as
+// 4-vectors.  Each slice's 64 segments are taken a quarter at a time, four
+// lanes per segment (one RHS each): a lane forms its segment's row sum for its
+// RHS in registers and adds its terms a * r_k of A^T r into the tile in LDS
+// as 32-bit fixed-point integers: scale 2^e_k from max |r_k|
+// and the largest column sum of |A| so that every sum stays below 2^30 in
+// magnitude (a term's rounding is below 2^-31 of the largest possible sum;
+// integer additions make the result independent of the order of the
+// atomics).  Launch slots are mapped so that the columns of one unit run side
+// by side on one XCD (workgroups are dealt to the 8 XCDs in turn): the unit's
+// stored entries are read from HBM once per pass and from that XCD's L2 by
+// its other columns.  Partials: A x per (segment, RHS) at [rank][ray][S],
+// A^T r per (chunk, pixel, RHS) at [chunk][pixel][S].
+// ---------------------------------------------------------------------------
+constexpr int kMrC = 4;      // RHS per workgroup
+constexpr int kXcds = 8;     // workgroups are dealt to the XCDs round robin
+
+__device__ __forceinline__ int fixed_exponent32(double smax, float rmax) {
+  const double b = smax * (double)rmax;
+  if (!(b > 0.0) || !isfinite(b)) return 0;
+  int E;
+  (void)frexp(b, &E);  // b < 2^E
+  return min(max(30 - E, -200), 200);
+}
+
+template <typename VT, bool NARROW, int W>
+__global__ __launch_bounds__(64 * W) void k_fused_mr(
+    TileGeom g, const int32_t* __restrict__ uorder, const int32_t* __restrict__ sbeg,
+    const int32_t* __restrict__ sng, const int64_t* __restrict__ soff,
+    const int32_t* __restrict__ sray, const uint16_t* __restrict__ srank,
+    const uint16_t* __restrict__ sbase, const void* __restrict__ col,
+    const VT* __restrict__ val, const float* __restrict__ x, const float* __restrict__ r,
+    const unsigned* __restrict__ rmax_in, float* __restrict__ zp, float* __restrict__ gp,
+    int64_t r_int, int64_t c_int, int S, int64_t units, double smax) {
+  // tile of x and the A^T r sums, both [cell][RHS]: the 4 lanes of a segment
+  // address 4 consecutive words, so one instruction's 64 lanes touch 16 random
+  // 4-word groups (about 2-way bank conflicts, where lanes on random single
+  // words would conflict about 6-way)
+  __shared__ f32x4 xs[kFTA];
+  __shared__ int gs[kFTA * kMrC];
+  constexpr int NT = 64 * W;
+  const int RC = S / kMrC;
+  const int64_t nwg = units * RC;
+  const int64_t per_xcd = (nwg + kXcds - 1) / kXcds;
+  const int64_t slot = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+  if (slot >= nwg) return;  // padding of the grid to a multiple of the XCD count
+  const int u = uorder[slot / RC];  // largest units first
+  const int cc = (int)(slot % RC);  // RHS column: RHS cc * 4 .. cc * 4 + 3
+  const int tile = u / g.Q, q = u - tile * g.Q;
+  const int per = g.FTh * g.FTw;
+  const int d = tile / per;
+  const int tt = tile - d * per;
+  const int ftr = tt / g.FTw, ftc = tt - ftr * g.FTw;
+  const int64_t xbase = (int64_t)d * g.slice_px;
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6, lane = tid & 63;
+  const int sub = lane & 3, sg = lane >> 2;  // this lane's RHS and segment of a quarter
+  const int s0 = sbeg[u], s1 = sbeg[u + 1];
+  for (int i = tid; i < kFTA; i += NT) {
+    xs[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < kMrC; ++k) gs[i * kMrC + k] = 0;
+  }
+  __syncthreads();
+  for (int i = tid; i < kFT * kFT; i += NT) {
+    const int b = i >> 6, w = i & 63;
+    const int tr8 = ftr * 8 + (b >> 3), tc8 = ftc * 8 + (b & 7);
+    if (tr8 < g.Ht && tc8 < g.Wt)
+      xs[(((b >> 3) << 3) + (w >> 3)) * kFTS + ((b & 7) << 3) + (w & 7)] =
+          *reinterpret_cast<const f32x4*>(
+              x + (xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w) * S + cc * kMrC);
+  }
+  const int rhs = cc * kMrC + sub;
+  const int ek = fixed_exponent32(smax, __uint_as_float(rmax_in[rhs]));
+  const float* xsf = reinterpret_cast<const float*>(xs) + sub;
+  int* gsi = gs + sub;
+  __syncthreads();
+  // work item = (slice, quarter): the quarter's 16 segments, 4 RHS each; the
+  // next item's table entries and r load while an item streams
+  auto meta = [&](int s, int qt) {
+    SliceMeta m{-1, 0, 0, 0, 0};
+    if (s < s1) {
+      const int L = qt * 16 + sg;
+      m.rho = sray[(int64_t)s * 64 + L];
+      m.rk = srank[(int64_t)s * 64 + L];
+      m.a0 = sbase ? sbase[(int64_t)s * 64 + L] : 0;
+      m.ng = sng[s];
+      m.base = soff[s] + L * 4;
+    }
+    return m;
+  };
+  int kk = 0, qt = 0, s = snake<W>(s0, 0, wv);
+  SliceMeta cur = meta(s, 0);
+  float rcur = cur.rho >= 0 ? r[(int64_t)cur.rho * S + rhs] : 0.f;
+  while (s < s1) {
+    const int qn = (qt + 1) & 3;
+    const int sn = qn == 0 ? snake<W>(s0, kk + 1, wv) : s;
+    const SliceMeta nxt = meta(sn, qn);
+    const float rnext = nxt.rho >= 0 ? r[(int64_t)nxt.rho * S + rhs] : 0.f;
+    const float rs = ldexpf(rcur, ek);
+    const int64_t base = cur.base;
+    const int ng = cur.ng;
+    float z0 = 0.f, z1 = 0.f;
+    int ap = cur.a0;
+    auto step = [&](const ColRaw<NARROW>& raw, const float (&a)[4], float& z) {
+      int c[4];
+      if constexpr (NARROW) {
+        c[0] = ap + (int)(raw & 255u);
+        c[1] = c[0] + (int)((raw >> 8) & 255u);
+        c[2] = c[1] + (int)((raw >> 16) & 255u);
+        c[3] = c[2] + (int)(raw >> 24);
+        ap = c[3];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c[e] = raw[e];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        z = fmaf(a[e], xsf[c[e] * kMrC], z);
+        atomicAdd(gsi + c[e] * kMrC, __float2int_rn(a[e] * rs));
+      }
+    };
+    int j = 0;
+    for (; j + 1 < ng; j += 2) {
+      ColRaw<NARROW> c0, c1;
+      float a0[4], a1[4];
+      load_group<VT, NARROW>(col, val, base + (int64_t)j * 256, c0, a0);
+      load_group<VT, NARROW>(col, val, base + (int64_t)(j + 1) * 256, c1, a1);
+      step(c0, a0, z0);
+      step(c1, a1, z1);
+    }
+    if (j < ng) {
+      ColRaw<NARROW> c0;
+      float a0[4];
+      load_group<VT, NARROW>(col, val, base + (int64_t)j * 256, c0, a0);
+      step(c0, a0, z0);
+    }
+    if (cur.rho >= 0) zp[((int64_t)cur.rk * r_int + cur.rho) * S + rhs] = z0 + z1;
+    if (qn == 0) ++kk;
+    qt = qn;
+    s = sn;
+    cur = nxt;
+    rcur = rnext;
+  }
+  __syncthreads();
+  // NT is a multiple of 4, so every thread flushes its own RHS `sub`; a
+  // residual with a non-finite entry has no scale and its partials carry a NaN
+  const float rm = __uint_as_float(rmax_in[rhs]);
+  const bool rbad = !(rm <= 3.40282347e38f);
+  for (int i = tid; i < kFT * kFT * kMrC; i += NT) {
+    const int px = i >> 2;
+    const int b = px >> 6, w = px & 63;
+    const int tr8 = ftr * 8 + (b >> 3), tc8 = ftc * 8 + (b & 7);
+    if (tr8 < g.Ht && tc8 < g.Wt) {
+      const int a = (((b >> 3) << 3) + (w >> 3)) * kFTS + ((b & 7) << 3) + (w & 7);
+      gp[((int64_t)q * c_int + xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w) * S + rhs] =
+          rbad ? __uint_as_float(0x7fc00000u) : ldexpf((float)gsi[a * kMrC], -ek);
+    }
+  }
+}
+
 // Maximum of v over a 256-thread block into *out: one atomic per block at
 // most, and only while it raises the stored value (every block of a launch
 // reading and updating one word serialises on one L2 channel otherwise).
@@ -780,6 +945,106 @@ __global__ __launch_bounds__(256) void k_fz_reduce(
     block_max_to(bad ? 0x7fc00000u : __float_as_uint(m), rmax_out);  // NaN > +inf
 }
 
+// Several RHS ([rows][S], RHS fastest): rays out_r = y - sum of the segment
+// partials zp[rank][ray][k] in rank order, per-RHS max |out_r| into
+// rmax_out[k]; pixels out_x = xadd + scale * sum over chunks of
+// gp[q][pixel][k].  Index space [0, r_int S) rays then [r_int S, (r_int +
+// c_int) S) pixels; the grid stride is a multiple of S, so a thread keeps one
+// RHS k throughout.
+__global__ __launch_bounds__(256) void k_fz_reduce_mr(
+    const int32_t* __restrict__ poff, const float* __restrict__ zp,
+    const float* __restrict__ y, float* __restrict__ out_r, unsigned* rmax_out,
+    int64_t r_int, const float* __restrict__ gp, int Q, const float* __restrict__ xadd,
+    float scale, float* __restrict__ out_x, int64_t c_int, int S, int64_t lo, int64_t hi) {
+  __shared__ unsigned smx[256];
+  float m = 0.f;
+  bool bad = false;
+  const int64_t rS = r_int * S, cS = c_int * S;
+  const int64_t i0 = lo + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int64_t i = i0; i < hi; i += (int64_t)gridDim.x * 256) {
+    if (i < rS) {
+      const int64_t ray = i / S;
+      const int n = poff[ray + 1] - poff[ray];
+      const float* z = zp + i;
+      float a = 0.f;
+      int k = 0;
+      for (; k + 3 < n; k += 4) {
+        const float v0 = z[(int64_t)k * rS], v1 = z[(int64_t)(k + 1) * rS];
+        const float v2 = z[(int64_t)(k + 2) * rS], v3 = z[(int64_t)(k + 3) * rS];
+        a += v0;
+        a += v1;
+        a += v2;
+        a += v3;
+      }
+      for (; k < n; ++k) a += z[(int64_t)k * rS];
+      const float o = y ? y[i] - a : a;
+      out_r[i] = o;
+      m = fmaxf(m, fabsf(o));
+      bad = bad || (o != o);
+    } else {
+      const int64_t pk = i - rS;
+      const float* g = gp + pk;
+      float a = 0.f;
+      int k = 0;
+      for (; k + 7 < Q; k += 8) {
+        float v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = g[(int64_t)(k + t) * cS];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) a += v[t];
+      }
+      for (; k < Q; ++k) a += g[(int64_t)k * cS];
+      out_x[pk] = xadd ? fmaf(scale, a, xadd[pk]) : scale * a;
+    }
+  }
+  if (!rmax_out || lo >= rS) return;
+  const unsigned bits = bad ? 0x7fc00000u : __float_as_uint(m);  // NaN > +inf
+  const int kr = (int)(i0 % S);
+  if (S <= 256) {
+    // threads of the block with the same RHS meet in LDS first
+    smx[threadIdx.x] = 0u;
+    __syncthreads();
+    if (i0 < rS) atomicMax(&smx[kr], bits);
+    __syncthreads();
+    if ((int)threadIdx.x < S && smx[threadIdx.x] > __atomic_load_n(rmax_out + threadIdx.x,
+                                                                  __ATOMIC_RELAXED))
+      atomicMax(rmax_out + threadIdx.x, smx[threadIdx.x]);
+  } else if (i0 < rS && bits > __atomic_load_n(rmax_out + kr, __ATOMIC_RELAXED)) {
+    atomicMax(rmax_out + kr, bits);
+  }
+}
+
+__global__ void k_fz_zero_n(unsigned* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+// per-RHS max |v| of a [rows][S] array into out[S] (zeroed by the preceding launch)
+__global__ __launch_bounds__(256) void k_fz_absmax_mr(const float* __restrict__ v, int64_t n,
+                                                      int S, unsigned* out) {
+  __shared__ unsigned smx[256];
+  float m = 0.f;
+  bool bad = false;
+  const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int64_t i = i0; i < n * S; i += (int64_t)gridDim.x * 256) {
+    const float o = v[i];
+    m = fmaxf(m, fabsf(o));
+    bad = bad || (o != o);
+  }
+  const unsigned bits = bad ? 0x7fc00000u : __float_as_uint(m);
+  const int kr = (int)(i0 % S);
+  if (S <= 256) {
+    smx[threadIdx.x] = 0u;
+    __syncthreads();
+    atomicMax(&smx[kr], bits);
+    __syncthreads();
+    if ((int)threadIdx.x < S && smx[threadIdx.x] > __atomic_load_n(out + threadIdx.x,
+                                                                  __ATOMIC_RELAXED))
+      atomicMax(out + threadIdx.x, smx[threadIdx.x]);
+  } else if (bits > __atomic_load_n(out + kr, __ATOMIC_RELAXED)) {
+    atomicMax(out + kr, bits);
+  }
+}
+
 __global__ void k_fz_zero_u32(unsigned* p) { *p = 0u; }
 
 // max |v| over n floats into *out (zeroed by the preceding launch)
@@ -825,7 +1090,7 @@ template <typename VT>
 static void launch_fused_vt(const bsgd_fused& F, int mode, const VT* val, const float* x,
                             const float* r, const unsigned* rmax_in, unsigned* rmax_zero,
                             float* zp, float* gp, hipStream_t s) {
-  switch (F.waves) {
+  switch (F.waves) {  // 16 is for the several-RHS pass; one RHS takes 8
     case 2: launch_fused_w<VT, 2>(F, mode, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
     case 4: launch_fused_w<VT, 4>(F, mode, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
     default: launch_fused_w<VT, 8>(F, mode, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
@@ -835,11 +1100,11 @@ static void launch_fused_vt(const bsgd_fused& F, int mode, const VT* val, const 
 bool fused_has_f16(const bsgd_fused* F) { return F->val16 != nullptr; }
 const bsgd_plan* fused_plan(const bsgd_fused* F) { return F->plan; }
 
-size_t fused_partials(const bsgd_fused* F, FusedPartials* fp, void* ws) {
+size_t fused_partials(const bsgd_fused* F, int S, FusedPartials* fp, void* ws) {
   Carver cv(ws);
-  float* a = cv.take<float>((size_t)std::max(F->maxrank, 1) * F->plan->L.r_int);
-  float* b = cv.take<float>((size_t)F->g.Q * F->plan->L.c_int);
-  unsigned* m = cv.take<unsigned>(2);
+  float* a = cv.take<float>((size_t)std::max(F->maxrank, 1) * F->plan->L.r_int * S);
+  float* b = cv.take<float>((size_t)F->g.Q * F->plan->L.c_int * S);
+  unsigned* m = cv.take<unsigned>(2 * (size_t)S);
   if (fp) {
     fp->zp = a;
     fp->gp = b;
@@ -861,6 +1126,76 @@ hipError_t launch_fused_pass(const bsgd_fused* F, bsgd_valtype vt, const float* 
     launch_fused_vt<__half>(*F, mode, F->val16, x, r, rmax_in, rmax_zero, zp, gp, s);
   else
     launch_fused_vt<float>(*F, mode, F->val, x, r, rmax_in, rmax_zero, zp, gp, s);
+  return hipGetLastError();
+}
+
+// grid for the several-RHS reduce kernels: a multiple of S / 256 blocks, so that
+// the grid stride (blocks * 256) is a multiple of S
+static unsigned grid_mr(int64_t n, int S) {
+  const unsigned mult = (unsigned)std::max(1, S / 256);
+  unsigned b = std::min<unsigned>(grid_for(n), 1024);
+  return (b + mult - 1) / mult * mult;
+}
+
+hipError_t launch_fused_zero(unsigned* p, int n, hipStream_t s) {
+  k_fz_zero_n<<<1, 256, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_absmax_mr(const float* v, int64_t n, int S, unsigned* out,
+                                  hipStream_t s) {
+  k_fz_zero_n<<<1, 256, 0, s>>>(out, S);
+  k_fz_absmax_mr<<<grid_mr(n * S, S), 256, 0, s>>>(v, n, S, out);
+  return hipGetLastError();
+}
+
+template <typename VT, int W>
+static void launch_mr_w(const bsgd_fused& F, const VT* val, const float* x, const float* r,
+                        const unsigned* rmax_in, float* zp, float* gp, int64_t ri, int64_t ci,
+                        int S, int64_t units, unsigned grid, hipStream_t s) {
+  if (F.narrow)
+    k_fused_mr<VT, true, W><<<grid, 64 * W, 0, s>>>(F.g, F.uorder, F.sbeg, F.sng, F.soff, F.sray,
+                                                    F.srank, F.sbase, F.col8, val, x, r, rmax_in,
+                                                    zp, gp, ri, ci, S, units, F.smax);
+  else
+    k_fused_mr<VT, false, W><<<grid, 64 * W, 0, s>>>(F.g, F.uorder, F.sbeg, F.sng, F.soff,
+                                                     F.sray, F.srank, nullptr, F.col, val, x, r,
+                                                     rmax_in, zp, gp, ri, ci, S, units, F.smax);
+}
+
+hipError_t launch_fused_pass_mr(const bsgd_fused* F, bsgd_valtype vt, int S, const float* x,
+                                const float* r, const unsigned* rmax_in, float* zp, float* gp,
+                                hipStream_t s) {
+  const int64_t units = F->g.units();
+  const int64_t nwg = units * (S / kMrC);
+  const unsigned grid = (unsigned)((nwg + kXcds - 1) / kXcds * kXcds);
+  const int64_t ri = F->plan->L.r_int, ci = F->plan->L.c_int;
+  if (vt == BSGD_VAL_F16) {
+    if (F->waves == 16)
+      launch_mr_w<__half, 16>(*F, F->val16, x, r, rmax_in, zp, gp, ri, ci, S, units, grid, s);
+    else
+      launch_mr_w<__half, 8>(*F, F->val16, x, r, rmax_in, zp, gp, ri, ci, S, units, grid, s);
+  } else {
+    if (F->waves == 16)
+      launch_mr_w<float, 16>(*F, F->val, x, r, rmax_in, zp, gp, ri, ci, S, units, grid, s);
+    else
+      launch_mr_w<float, 8>(*F, F->val, x, r, rmax_in, zp, gp, ri, ci, S, units, grid, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_reduce_mr(const bsgd_fused* F, int S, const float* zp, const float* gp,
+                                  const float* y, float* out_r, unsigned* rmax_out,
+                                  const float* xadd, float scale, float* out_x, hipStream_t s,
+                                  int parts) {
+  const Layout& L = F->plan->L;
+  const int64_t rS = L.r_int * S, cS = L.c_int * S;
+  const int64_t lo = (parts & kReduceRays) ? 0 : rS;
+  const int64_t hi = (parts & kReducePixels) ? rS + cS : rS;
+  if (hi <= lo) return hipSuccess;
+  k_fz_reduce_mr<<<grid_mr(hi - lo, S), 256, 0, s>>>(F->poff, zp, y, out_r, rmax_out, L.r_int,
+                                                     gp, F->g.Q, xadd, scale, out_x, L.c_int, S,
+                                                     lo, hi);
   return hipGetLastError();
 }
 
@@ -1243,7 +1578,8 @@ extern "C" bsgd_status bsgd_fused_shape(const bsgd_fused* F, int* tiles, int* ch
 extern "C" bsgd_status bsgd_fused_set_waves(bsgd_fused* F, int waves) {
   clear_error();
   BSGD_REQUIRE(F != nullptr, "fused store is NULL");
-  BSGD_REQUIRE(waves == 2 || waves == 4 || waves == 8, "waves must be 2, 4 or 8");
+  BSGD_REQUIRE(waves == 2 || waves == 4 || waves == 8 || waves == 16,
+               "waves must be 2, 4, 8 or 16");
   F->waves = waves;
   return BSGD_OK;
 }
@@ -1251,7 +1587,17 @@ extern "C" bsgd_status bsgd_fused_set_waves(bsgd_fused* F, int waves) {
 extern "C" bsgd_status bsgd_fused_partials_size(const bsgd_fused* F, size_t* bytes) {
   clear_error();
   BSGD_REQUIRE(F && bytes, "NULL argument");
-  *bytes = fused_partials(F, nullptr, nullptr);
+  *bytes = fused_partials(F, 1, nullptr, nullptr);
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_fused_partials_size_rhs(const bsgd_fused* F, int nrhs,
+                                                    size_t* bytes) {
+  clear_error();
+  BSGD_REQUIRE(F && bytes, "NULL argument");
+  BSGD_REQUIRE(nrhs == 1 || (nrhs >= kMrC && nrhs % kMrC == 0),
+               "nrhs must be 1 or a multiple of %d", kMrC);
+  *bytes = fused_partials(F, nrhs, nullptr, nullptr);
   return BSGD_OK;
 }
 
@@ -1265,7 +1611,7 @@ extern "C" bsgd_status bsgd_fused_apply(const bsgd_fused* F, bsgd_valtype vt, co
                "value type not available in this store");
   BSGD_REQUIRE(std::isfinite(mu), "mu must be finite");
   FusedPartials fp;
-  const size_t need = fused_partials(F, &fp, partials);
+  const size_t need = fused_partials(F, 1, &fp, partials);
   if (partials_bytes < need) {
     set_error("partials workspace has %zu bytes, needs %zu", partials_bytes, need);
     return BSGD_ERR_WORKSPACE;

@@ -326,7 +326,7 @@ extern "C" bsgd_status bsgd_lanczos_workspace_size_fused(const bsgd_fused* F, in
   float *v, *w, *u0, *u1;
   double *part, *sc;
   const size_t a = lanczos_layout(fused_plan(F), steps, nullptr, &v, &w, &u0, &u1, &part, &sc);
-  *bytes = a + align_up(fused_partials(F, nullptr, nullptr), kAlign);
+  *bytes = a + align_up(fused_partials(F, 1, nullptr, nullptr), kAlign);
   return BSGD_OK;
 }
 
@@ -342,13 +342,13 @@ extern "C" bsgd_status bsgd_lanczos_umax_fused(const bsgd_fused* F, bsgd_valtype
   float *v, *w, *u0, *u1;
   double *part, *sc;
   const size_t a = lanczos_layout(plan, steps, nullptr, &v, &w, &u0, &u1, &part, &sc);
-  const size_t b = align_up(fused_partials(F, nullptr, nullptr), kAlign);
+  const size_t b = align_up(fused_partials(F, 1, nullptr, nullptr), kAlign);
   if (ws_bytes < a + b) {
     set_error("lanczos workspace has %zu bytes, needs %zu", ws_bytes, a + b);
     return BSGD_ERR_WORKSPACE;
   }
   FusedPartials fp;
-  fused_partials(F, &fp, static_cast<char*>(ws) + a);
+  fused_partials(F, 1, &fp, static_cast<char*>(ws) + a);
   const int64_t r = plan->L.r_int;
   return lanczos_run(
       plan, steps, ws, a, stream, umax,
@@ -580,7 +580,8 @@ static hipError_t prox_step(const bsgd_state* st, float mu, float lam, bool per_
     return tv_prox_run(p->L, true, st->xhat, mu * lam, prox_iters, out, st->tv_ws, s,
                        st->prox_schedule);
   if (st->flags & BSGD_STATE_VOLUME)
-    return tv_prox_volume(p->L, S, st->xhat, mu * lam, prox_iters, out, st->tv_ws, s);
+    return tv_prox_volume(p->L, S, st->xhat, mu * lam, prox_iters, out, st->tv_ws, s,
+                          st->prox_schedule);
   return tv_prox_batch(p->L, S, st->xhat, mu, per_rhs ? st->lam : nullptr, lam, prox_iters, out,
                        st->tv_ws, s, st->prox_schedule);
 }
@@ -613,7 +614,7 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
       // products are two passes over it (A x only, then A^T r' only: the
       // second needs the first's residual), each with its half of the reduce.
       if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
-      if (st->fz) {
+      if (st->fz && S == 1) {
         const FusedPartials& fp = st->fzp;
         BSGD_HIP(launch_fused_pass(st->fz, st->vt, st->x[c], nullptr, nullptr, fp.rmax + n,
                                    fp.zp, fp.gp, stream, kPassA));
@@ -634,6 +635,41 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
       if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
       if (theta != 0.f) BSGD_HIP(prox_step(st, mu, lam, per_rhs, prox_iters, st->x[n], stream));
       if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));
+      st->cur = n;
+      st->epochs_done++;
+      continue;
+    }
+    if (st->fz && S > 1) {
+      // several RHS: the same schedule as below with the several-RHS pass and
+      // reduce (per-RHS max |r| words at rmax + c * S and rmax + n * S), and
+      // the batch or volume prox
+      const FusedPartials& fp = st->fzp;
+      const bool split = st->overlap != 2;
+      if (e == 0)
+        BSGD_HIP(launch_fused_absmax_mr(st->r[c], p->L.r_int, S, fp.rmax + (size_t)c * S,
+                                        stream));
+      if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
+      BSGD_HIP(launch_fused_pass_mr(st->fz, st->vt, S, st->x[c], st->r[c],
+                                    fp.rmax + (size_t)c * S, fp.zp, fp.gp, stream));
+      if (tv) BSGD_HIP(hipEventRecord(tv[1], stream));
+      // the next residual's maxima start from zero (after the pass read this one's)
+      BSGD_HIP(launch_fused_zero(fp.rmax + (size_t)n * S, S, stream));
+      if (split) {
+        BSGD_HIP(hipEventRecord(st->ev_main, stream));
+        BSGD_HIP(hipStreamWaitEvent(st->aux, st->ev_main, 0));
+        BSGD_HIP(launch_fused_reduce_mr(st->fz, S, fp.zp, fp.gp, st->y, st->r[n],
+                                        fp.rmax + (size_t)n * S, nullptr, 0.f, nullptr, st->aux,
+                                        kReduceRays));
+        BSGD_HIP(hipEventRecord(st->ev_aux, st->aux));
+      }
+      if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));
+      BSGD_HIP(launch_fused_reduce_mr(st->fz, S, fp.zp, fp.gp, st->y, st->r[n],
+                                      fp.rmax + (size_t)n * S, st->x[c], 2.0f * mu, step_out,
+                                      stream, split ? kReducePixels : kReduceAll));
+      if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
+      if (theta != 0.f) BSGD_HIP(prox_step(st, mu, lam, per_rhs, prox_iters, st->x[n], stream));
+      if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));
+      if (split) BSGD_HIP(hipStreamWaitEvent(stream, st->ev_aux, 0));
       st->cur = n;
       st->epochs_done++;
       continue;
@@ -861,11 +897,14 @@ extern "C" bsgd_status bsgd_state_attach_fused(bsgd_state* st, const bsgd_fused*
   }
   BSGD_REQUIRE(partials != nullptr, "partials is NULL");
   BSGD_REQUIRE(fused_plan(fused) == st->plan, "the store belongs to another plan");
-  BSGD_REQUIRE(st->nrhs == 1, "single-pass epochs need a one-RHS state");
+  BSGD_REQUIRE(st->nrhs == 1 || st->nrhs % 4 == 0,
+               "single-pass epochs need one RHS or a multiple of 4");
+  BSGD_REQUIRE(!(st->flags & BSGD_STATE_BLOCK_SELECT) || st->nrhs == 1,
+               "block-select states use the block store");
   BSGD_REQUIRE(st->vt == BSGD_VAL_F32 || fused_has_f16(fused),
                "the store has no FP16 values (plan without BSGD_PLAN_F16)");
   FusedPartials fp;
-  const size_t need = fused_partials(fused, &fp, partials);
+  const size_t need = fused_partials(fused, st->nrhs, &fp, partials);
   if (partials_bytes < need) {
     set_error("partials workspace has %zu bytes, needs %zu", partials_bytes, need);
     return BSGD_ERR_WORKSPACE;

@@ -929,16 +929,236 @@ __global__ __launch_bounds__(256) void k_fgp_out3v(Layout L, int S, const float*
   }
 }
 
+// ---------------------------------------------------------------------------
+// Temporally blocked 3-D FGP (volumes; the default schedule).  One launch runs
+// KL consecutive iterations.  Block (bx, by, bz) owns the columns t in
+// [bx T, bx T + T), the slices d in [by T, by T + T) and the image rows s in
+// [bz R, bz R + R), T = 32 - 2 KL, on a region of 32 x 32 (t, d) cells times
+// R + 2 KL rows: the owned ones plus a halo of KL on each side, recomputed
+// rather than exchanged (a value from the region edge is wrong by one more
+// cell per iteration, so after KL iterations the owned cells are exact).
+// One thread per (t, d) cell; the 32 cells of a thread column are
+// consecutive slices of one pixel, consecutive in memory.  The block streams
+// down its rows: at step tau, level m (global iteration k0 + m) works on
+// local row tau - 2m, so what level m needs of
+// level m - 1 (its dual on the next row) was made one step earlier and the
+// levels of one step are independent.  A step has three phases separated by
+// two barriers: (A) every level forms q on its next row from the two
+// previous levels' duals (registers) and publishes its current row's slice
+// and column components of q to LDS; (B) u = b - theta D^T q, with the row
+// neighbour from registers and the t and d neighbours from LDS, published to
+// LDS; (C) p = P(q + step D u), with u of the previous row from registers.
+// Each level keeps its last four row outputs in registers (the next level
+// reads them one step later, the one after that three steps later); b and the
+// launch's input duals are read once per row at the leading edge.  The
+// per-voxel arithmetic is that of k_fgp_iter3v, so both schedules agree
+// bitwise.
+// ---------------------------------------------------------------------------
+constexpr int kBR = 32;                       // region cells along t and along d
+constexpr int kTB3Rows = 64;                  // owned image rows per block
+constexpr int kBRing = 8;                     // b ring: rows tau .. tau - 2 KL
+
+template <int KL>
+__global__ __launch_bounds__(kBR* kBR) void k_fgp_tb3(
+    Layout L, int S, const float* __restrict__ b, float theta, float step, int k0, FuseArgs ca,
+    const float* __restrict__ in1, const float* __restrict__ in2, float* __restrict__ o1,
+    float* __restrict__ o2, int64_t n, int R) {
+  static_assert(KL >= 1 && 2 * KL + 1 <= kBRing, "levels per launch");
+  constexpr int T = kBR - 2 * KL;
+  constexpr int LP = kBR + 2;  // LDS pitch: cell (x, z) at [x + 1][z + 1], pads read as zero
+  __shared__ float sqd[KL][LP][LP];
+  __shared__ float sqh[KL][LP][LP];
+  __shared__ float su[KL][LP][LP];
+  const int tid = threadIdx.x;
+  const int dz = tid % kBR, tx = tid / kBR;
+  const int t = (int)blockIdx.x * T - KL + tx, d = (int)blockIdx.y * T - KL + dz;
+  // rows [lo, hi) are streamed, [own0, own1) written; rows outside [lo, hi)
+  // read as zero (the image border where lo = 0 or hi = H)
+  const int own0 = (int)blockIdx.z * R, own1 = min(own0 + R, L.H);
+  const int lo = max(own0 - KL, 0), hi = min(own1 + KL, L.H);
+  const bool inside = t >= 0 && t < L.W && d >= 0 && d < S;
+  const bool owner = inside && tx >= KL && tx < KL + T && dz >= KL && dz < KL + T;
+  for (int q = tid; q < KL * LP * LP; q += kBR * kBR) {
+    (&sqd[0][0][0])[q] = 0.f;
+    (&sqh[0][0][0])[q] = 0.f;
+    (&su[0][0][0])[q] = 0.f;
+  }
+  float br[kBRing];
+  float pr[KL + 1][4][3];  // pr[m][row % 4]: level m's dual (m = 0: the input p_{k0})
+  float pm[2][3];          // the input p_{k0-1}, [row % 2]
+  float qc[KL][3], qn[KL][3], up[KL];
+#pragma unroll
+  for (int i = 0; i < kBRing; ++i) br[i] = 0.f;
+#pragma unroll
+  for (int m = 0; m <= KL; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pr[m][r][0] = pr[m][r][1] = pr[m][r][2] = 0.f;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) pm[r][0] = pm[r][1] = pm[r][2] = 0.f;
+#pragma unroll
+  for (int m = 0; m < KL; ++m) {
+    qc[m][0] = qc[m][1] = qc[m][2] = 0.f;
+    qn[m][0] = qn[m][1] = qn[m][2] = 0.f;
+    up[m] = 0.f;
+  }
+  __syncthreads();
+  const int steps = (hi - lo + 2 * KL + kBRing - 1) / kBRing * kBRing;
+  for (int tau0 = 0; tau0 < steps; tau0 += kBRing) {
+#pragma unroll
+    for (int u = 0; u < kBRing; ++u) {
+      const int tau = tau0 + u;
+      // leading edge: b and the input duals on row tau
+      {
+        float bv = 0.f, a[3] = {0.f, 0.f, 0.f}, c[3] = {0.f, 0.f, 0.f};
+        if (inside && lo + tau < hi) {
+          const int64_t i = L.pix_st(0, lo + tau, t) * S + d;
+          bv = b[i];
+          if (k0 >= 1) {
+            a[0] = in1[i];
+            a[1] = in1[n + i];
+            a[2] = in1[2 * n + i];
+          }
+          if (k0 >= 2) {
+            c[0] = in2[i];
+            c[1] = in2[n + i];
+            c[2] = in2[2 * n + i];
+          }
+        }
+        br[u] = bv;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          pr[0][u % 4][k] = a[k];
+          pm[u % 2][k] = c[k];
+        }
+      }
+      // (A) q of level m on row tau - 2m + 1; publish q on row tau - 2m
+#pragma unroll
+      for (int m = 1; m <= KL; ++m) {
+        const int j = k0 + m;
+        const float coef = ca.coef[m];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const float p1 = pr[m - 1][(u + 3) % 4][k];                       // made at tau - 1
+          const float p2 = m >= 2 ? pr[m - 2][(u + 1) % 4][k] : pm[(u + 1) % 2][k];  // tau - 3
+          qn[m - 1][k] = j == 1 ? 0.f : (j == 2 ? p1 : fmaf(coef, p1 - p2, p1));
+        }
+        sqd[m - 1][tx + 1][dz + 1] = qc[m - 1][0];
+        sqh[m - 1][tx + 1][dz + 1] = qc[m - 1][2];
+      }
+      __syncthreads();
+      // (B) u = b - theta D^T q on row tau - 2m
+      float uu[KL];
+#pragma unroll
+      for (int m = 1; m <= KL; ++m) {
+        const int s = lo + tau - 2 * m;
+        uu[m - 1] = 0.f;
+        if (inside && s >= lo && s < hi) {
+          const float dtq = (qc[m - 1][0] - sqd[m - 1][tx + 1][dz + 2]) +
+                            (qc[m - 1][1] - qn[m - 1][1]) +
+                            (qc[m - 1][2] - sqh[m - 1][tx + 2][dz + 1]);
+          uu[m - 1] = br[(u + kBRing - 2 * m) % kBRing] - theta * dtq;
+        }
+        su[m - 1][tx + 1][dz + 1] = uu[m - 1];
+      }
+      __syncthreads();
+      // (C) p = P(q + step D u) on row tau - 2m
+#pragma unroll
+      for (int m = 1; m <= KL; ++m) {
+        const int s = lo + tau - 2 * m;
+        float ad = 0.f, av = 0.f, ah = 0.f;
+        const bool live = inside && s >= lo && s < hi;
+        if (live) {
+          const float u0 = uu[m - 1];
+          const float gd = d >= 1 ? u0 - su[m - 1][tx + 1][dz] : 0.f;
+          const float gv = s >= 1 ? u0 - up[m - 1] : 0.f;
+          const float gh = t >= 1 ? u0 - su[m - 1][tx][dz + 1] : 0.f;
+          ad = fmaf(step, gd, qc[m - 1][0]);
+          av = fmaf(step, gv, qc[m - 1][1]);
+          ah = fmaf(step, gh, qc[m - 1][2]);
+          project3(ad, av, ah);
+        }
+        pr[m][u % 4][0] = ad;
+        pr[m][u % 4][1] = av;
+        pr[m][u % 4][2] = ah;
+        up[m - 1] = uu[m - 1];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) qc[m - 1][k] = qn[m - 1][k];
+        if (owner && s >= own0 && s < own1) {
+          const int64_t i = L.pix_st(0, s, t) * S + d;
+          if (m == KL) {
+            o1[i] = ad;
+            o1[n + i] = av;
+            o1[2 * n + i] = ah;
+          }
+          if (m == KL - 1) {
+            o2[i] = ad;
+            o2[n + i] = av;
+            o2[2 * n + i] = ah;
+          }
+        }
+      }
+      if constexpr (KL == 1) {
+        // the launch's second output is its input p_{k0} on the same row
+        const int s = lo + tau - 2;
+        if (owner && s >= own0 && s < own1) {
+          const int64_t i = L.pix_st(0, s, t) * S + d;
+          o2[i] = pr[0][(u + 2) % 4][0];
+          o2[n + i] = pr[0][(u + 2) % 4][1];
+          o2[2 * n + i] = pr[0][(u + 2) % 4][2];
+        }
+      }
+    }
+  }
+}
+
+template <int KL>
+static void launch_tb3(const Layout& L, int S, const float* b, float theta, float step, int k0,
+                       const FuseArgs& ca, const float* i1, const float* i2, float* o1,
+                       float* o2, int64_t n, hipStream_t s) {
+  constexpr int T = kBR - 2 * KL;
+  dim3 grid((L.W + T - 1) / T, (S + T - 1) / T, (L.H + kTB3Rows - 1) / kTB3Rows);
+  k_fgp_tb3<KL><<<grid, kBR * kBR, 0, s>>>(L, S, b, theta, step, k0, ca, i1, i2, o1, o2, n,
+                                            kTB3Rows);
+}
+
+constexpr int kTB3Levels = 3;  // most iterations one launch of k_fgp_tb3 runs
+
 hipError_t tv_prox_volume(const Layout& L, int S, const float* b, float theta, int iters,
-                          float* out, float* ws, hipStream_t s) {
+                          float* out, float* ws, hipStream_t s, int schedule) {
   const int64_t n = L.c_int * S;
   if (theta == 0.f || iters == 0) {
     k_copy_f32v<<<grid_for(n), 256, 0, s>>>(b, out, n);
     return hipGetLastError();
   }
   Momentum mom;
-  float* buf[3] = {ws, ws + 3 * n, ws + 6 * n};  // (pd, pv, ph) triples
   const float step = 1.0f / (12.0f * theta);
+  if (schedule != kFgpPerIteration) {
+    // equal launches of at most kTB3Levels iterations; p_{k0} in buf[in],
+    // p_{k0-1} in buf[in + 1], outputs to the other pair
+    float* buf[4] = {ws, ws + 3 * n, ws + 6 * n, ws + 9 * n};
+    const int nl = (iters + kTB3Levels - 1) / kTB3Levels;
+    int in = 0;
+    for (int k0 = 0, li = 0; k0 < iters; ++li) {
+      const int chunk = iters / nl + (li < iters % nl ? 1 : 0);
+      FuseArgs ca{};
+      for (int q = 1; q <= chunk; ++q) ca.coef[q] = mom.next();  // c_{k0+q}
+      const float* i1 = buf[in];
+      const float* i2 = buf[in + 1];
+      float* o1 = buf[2 - in];
+      float* o2 = buf[3 - in];
+      switch (chunk) {
+        case 1: launch_tb3<1>(L, S, b, theta, step, k0, ca, i1, i2, o1, o2, n, s); break;
+        case 2: launch_tb3<2>(L, S, b, theta, step, k0, ca, i1, i2, o1, o2, n, s); break;
+        default: launch_tb3<3>(L, S, b, theta, step, k0, ca, i1, i2, o1, o2, n, s); break;
+      }
+      in = 2 - in;
+      k0 += chunk;
+    }
+    k_fgp_out3v<<<grid_for((int64_t)L.H * L.W * S), 256, 0, s>>>(L, S, b, theta, buf[in], out,
+                                                                 n);
+    return hipGetLastError();
+  }
+  float* buf[3] = {ws, ws + 3 * n, ws + 6 * n};  // (pd, pv, ph) triples
   const unsigned grid = (unsigned)(L.Ht * L.Wt);
   int cur = 0;
   for (int k = 1; k <= iters; ++k) {

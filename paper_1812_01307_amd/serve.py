@@ -24,7 +24,13 @@ A request is admitted between rounds only, so its epochs count from a chunk
 boundary and the stop rule is evaluated after the same epochs whatever else
 is being served; the slots of a state do not interact (every product, norm
 and prox is per slot).  A request therefore gets the same result alone and in
-a mix (bitwise, for the same slot count and chunk).
+a mix (bitwise, for the same slot count and chunk).  `cancel(rid)` drops a
+queued request, or empties a running request's slot between rounds; the
+other slots are untouched.
+
+Each geometry can keep a tile-sliced store resident (the single-pass form of
+the epoch products): every batch state of that geometry then reads it once
+per epoch for both products of all its slots, four slots per workgroup.
 
 The device work is done by the C entry points (through `capi`); this module
 only decides what runs where.  `Server` takes a backend object so that the
@@ -52,7 +58,7 @@ class Request:
     admitted: Optional[float] = None
     finished: Optional[float] = None
     res_norm2: Optional[float] = None
-    stop: str = ""                       # "converged" or "max_epochs"
+    stop: str = ""                       # "converged", "max_epochs" or "cancelled"
 
     @property
     def latency(self) -> float:
@@ -99,6 +105,7 @@ class Server:
         self.batches: List[_Batch] = []
         self.queue: List[Request] = []
         self.done: List[Request] = []
+        self.cancelled: List[Request] = []
         self.rounds = 0
 
     # -- bookkeeping ------------------------------------------------------
@@ -125,6 +132,31 @@ class Server:
         if not (math.isfinite(req.lam) and req.lam >= 0.0):
             raise ValueError("lambda must be finite and >= 0")
         self.queue.append(req)
+
+    def cancel(self, rid) -> bool:
+        """Withdraw request `rid`: from the queue, or from its slot (which is
+        emptied; the state's other slots are not touched).  Call between
+        rounds.  False if the request is not queued or running."""
+        for i, req in enumerate(self.queue):
+            if req.rid == rid:
+                del self.queue[i]
+                self._cancelled(req)
+                return True
+        for b in self.batches:
+            for k, req in enumerate(b.slots):
+                if req is not None and req.rid == rid:
+                    self.backend.release(b.handle, k)
+                    b.slots[k] = None
+                    self.backend.set_lambdas(b.handle, [r.lam if r is not None else 0.0
+                                                        for r in b.slots])
+                    self._cancelled(req)
+                    return True
+        return False
+
+    def _cancelled(self, req: Request) -> None:
+        req.stop = "cancelled"
+        req.finished = self.now()
+        self.cancelled.append(req)
 
     @property
     def busy(self) -> bool:
@@ -248,11 +280,13 @@ def percentile(values, q: float) -> float:
 
 @dataclass
 class Geometry:
-    """A resident geometry on the device: its plan and step size."""
+    """A resident geometry on the device: its plan, its tile-sliced store (or
+    None: states then run the block store's products) and step size."""
     plan: Any
     mu: float
     prox_iters: int = 20
     vt: int = 0
+    fused: Any = None
 
 
 class DeviceBackend:
@@ -265,23 +299,34 @@ class DeviceBackend:
         self.capi = capi
 
     def geometry(self, plan, power_iters: int = 30, prox_iters: int = 20, mu=None,
-                 vt: int = 0) -> Geometry:
-        """Step size mu = 0.9 / (2 u_max) (Theorem 1) with u_max by power iteration."""
+                 vt: int = 0, fused: bool = True, lanczos_steps: int = 10) -> Geometry:
+        """Resident geometry.  fused: build its tile-sliced store.  Step size
+        mu = 0.9 / (2 u_max) (Theorem 1), u_max by Lanczos steps on the store
+        (power iteration on the block store without one), unless mu is given."""
+        capi = self.capi
+        F = capi.bsgd_fused_create(plan, 0) if fused else None
         if mu is None:
-            mu = 0.9 / (2.0 * self.capi.bsgd_power_umax(plan, power_iters, vt=vt))
-        return Geometry(plan, float(mu), prox_iters, vt)
+            u = (capi.bsgd_lanczos_umax_fused(F, lanczos_steps, vt=vt) if F is not None
+                 else capi.bsgd_power_umax(plan, power_iters, vt=vt))
+            mu = 0.9 / (2.0 * u)
+        return Geometry(plan, float(mu), prox_iters, vt, F)
 
     def geometry_bytes(self, g: Geometry) -> int:
-        return g.plan.workspace.numel()
+        return g.plan.workspace.numel() + (g.fused.workspace.numel() if g.fused else 0)
 
     def state_bytes(self, g: Geometry, slots: int) -> int:
-        return self.capi.bsgd_state_workspace_size(g.plan, slots)
+        n = self.capi.bsgd_state_workspace_size(g.plan, slots)
+        if g.fused is not None:
+            n += self.capi.bsgd_fused_partials_size_rhs(g.fused, slots)
+        return n
 
     def new_state(self, g: Geometry, slots: int):
         torch, capi = self.torch, self.capi
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
             st = capi.bsgd_state_create(g.plan, slots, g.vt)
+            if g.fused is not None:
+                capi.bsgd_state_attach_fused(st, g.fused)
             if slots > 1:
                 zeros = torch.zeros(g.plan.nrows * slots, dtype=torch.float32, device="cuda")
                 capi.bsgd_state_init(st, zeros, stream=stream)

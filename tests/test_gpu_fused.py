@@ -241,9 +241,6 @@ def test_fused_validation():
     p = problem("c1_64")
     plan = plan_for(p)
     F = _fused(plan)
-    batch = bsgd.bsgd_state_create(plan, 4)
-    with pytest.raises(bsgd.BsgdError, match="one-RHS"):
-        bsgd.bsgd_state_attach_fused(batch, F)
     other = plan_for(p)
     st = bsgd.bsgd_state_create(other)
     with pytest.raises(bsgd.BsgdError, match="another plan"):

@@ -188,6 +188,35 @@ def test_run_follows_arrival_times():
         assert r.admitted >= r.arrival and r.finished > r.admitted and r.latency > 0
 
 
+def test_cancel_queued_and_running_requests_leaves_the_others_unchanged():
+    def serve(cancel_at):
+        fb = FakeBackend()
+        srv = _server(fb, slots=2, chunk=10, tol=1e-4, max_epochs=300)
+        reqs = _requests(7)
+        for r in reqs:
+            srv.submit(r)
+        rounds = 0
+        while srv.busy:
+            for rnd, rid in cancel_at:
+                if rnd == rounds:
+                    assert srv.cancel(rid)
+            srv.step()
+            rounds += 1
+        return srv, {r.rid: r for r in reqs}
+
+    base_srv, base = serve([])
+    # round 0: request 6 is still queued (2 slots per geometry, 3 geometries);
+    # round 2: request 1 is running
+    srv, got = serve([(0, 6), (2, 1)])
+    assert not srv.cancel(6) and not srv.cancel(99)
+    assert {r.rid for r in srv.cancelled} == {1, 6}
+    assert got[1].stop == got[6].stop == "cancelled" and got[6].epochs == 0
+    assert got[1].epochs == 20 and got[1].x is None
+    for rid in (0, 2, 3, 4, 5):
+        assert got[rid].epochs == base[rid].epochs and got[rid].x == base[rid].x
+    assert {r.rid for r in srv.done} == {0, 2, 3, 4, 5}
+
+
 def test_invalid_requests_and_settings_are_rejected():
     fb = FakeBackend()
     srv = _server(fb)

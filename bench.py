@@ -171,9 +171,11 @@ def main(argv=None):
     ap.add_argument("--select-seed", type=int, default=7)
     ap.add_argument("--fused-chunks", type=int, default=0,
                     help="ray chunks of the tile-sliced store (0: automatic)")
-    ap.add_argument("--fused-waves", type=int, default=8, choices=[2, 4, 8, 16],
-                    help="wavefronts per (tile, chunk) workgroup of the single pass (16: the "
-                         "several-RHS pass only)")
+    ap.add_argument("--fused-waves", type=int, default=8, choices=[2, 4, 8],
+                    help="wavefronts per (tile, chunk) workgroup of the single pass")
+    ap.add_argument("--mr-waves", type=int, default=0, choices=[0, 8, 16],
+                    help="volume workload: wavefronts per workgroup of the several-RHS pass "
+                         "(0: the library's default, 16)")
     ap.add_argument("--staged", default=None, choices=["none", "fwd", "bwd", "both"],
                     help="directions built in the staged form (LDS-served gathers) and used by "
                          "the epochs of --path rows (default bwd; none with --path fused)")
@@ -656,7 +658,6 @@ def run_volume(args, np, torch, synth, bsgd):
             # the single pass for several RHS reads the tile-sliced store; the
             # Lanczos products run on it too
             F = bsgd.bsgd_fused_create(plan, args.fused_chunks)
-            bsgd.bsgd_fused_set_waves(F, args.fused_waves)
             u = bsgd.bsgd_lanczos_umax_fused(F, args.umax_steps, vt=vt)
             shape["fused"] = bsgd.bsgd_fused_shape(F)
         else:
@@ -665,6 +666,15 @@ def run_volume(args, np, torch, synth, bsgd):
         st = bsgd.bsgd_state_create(plan, S, vt, flags=bsgd.BSGD_STATE_VOLUME)
         if F is not None:
             bsgd.bsgd_state_attach_fused(st, F)
+        if args.autotune and "tuned" not in shape:
+            # launch shapes timed once, outside the timed jobs, and reused
+            shape["tuned"] = bsgd.bsgd_state_autotune(st, mu, prob.lam, K, reps=2)
+            print(f"[bench] autotuned launch (pass waves, prox split) {shape['tuned']}",
+                  file=sys.stderr, flush=True)
+        if "tuned" in shape:
+            bsgd.bsgd_state_set_launch(st, *shape["tuned"])
+        elif args.mr_waves:
+            bsgd.bsgd_state_set_launch(st, args.mr_waves, 0)
         if timed:
             bsgd.bsgd_state_enable_timing(st, n_epochs)
         bsgd.bsgd_state_init(st, Y)
@@ -757,6 +767,8 @@ def run_volume(args, np, torch, synth, bsgd):
                                f"setup S0+S0' included",
                    "nnz": nnz, "slices": S, "epochs_per_step": epochs,
                    "graph": graph, "path": args.path,
+                   "launch": (list(shape["tuned"]) if "tuned" in shape
+                              else [args.mr_waves, 0]),
                    "kernel_timing": "events on one eager 20-epoch job after the timed region"},
         "alg_bytes_per_epoch": b_fwd + b_bwd + b_prox,
         "kernels": {k: round(v, 4) for k, v in kernel.items()},

@@ -428,6 +428,29 @@ bsgd_status bsgd_state_set_overlap(bsgd_state* state, int mode);
  */
 bsgd_status bsgd_state_set_prox_schedule(bsgd_state* state, int schedule);
 
+/*
+ * Launch shapes of the state's epochs that do not change results:
+ *   pass_waves  wavefronts per workgroup of the single pass: 2, 4 or 8 for
+ *               one RHS, 8 or 16 for several (0: the store's choice, resp. 16).
+ *               Row sums are per segment in a fixed order and the column sums
+ *               exact fixed-point integers, so results are the same for all.
+ *   prox_split  most FGP iterations per launch of the prox (2-D: 1 to 10,
+ *               volumes: 1 to 3; 0 or more than that: the most).  Each pixel's
+ *               arithmetic is the same whatever the split.
+ * bsgd_state_autotune chooses both by timing them on this state (every epoch
+ * of Algorithm 1 runs the same kernels, so a few epochs measure a choice):
+ * `reps` epochs per candidate with the given mu, lam and prox_iters (pass wavefronts 4 or 8 for one RHS, 8 or 16 for several; prox
+ * split 5 or 10 in 2-D, 1, 2 or 3 for volumes).  It runs on zero data and
+ * must be called before bsgd_state_init (it overwrites the state's vectors
+ * and leaves the state uninitialised); choice (host, 2 ints, may be NULL)
+ * receives the pass wavefronts (0 without a store) and the split (0 when lam
+ * = 0).  Synchronises.
+ */
+bsgd_status bsgd_state_set_launch(bsgd_state* state, int pass_waves, int prox_split);
+bsgd_status bsgd_state_launch(const bsgd_state* state, int* pass_waves, int* prox_split);
+bsgd_status bsgd_state_autotune(bsgd_state* state, float mu, float lam, int prox_iters, int reps,
+                                hipStream_t stream, int* choice);
+
 /* Copy the current iterate x (c floats) / residual r (r floats) to device memory. */
 bsgd_status bsgd_get_x(const bsgd_state* state, float* x, hipStream_t stream);
 bsgd_status bsgd_get_r(const bsgd_state* state, float* r, hipStream_t stream);
@@ -544,10 +567,11 @@ void bsgd_graph_destroy(bsgd_graph* graph);
  *   fused_shape   tiles, chunks, segments, slices (64 segments each),
  *               stored entries (with padding) and bytes per stored column (1:
  *               8-bit steps, 2: 16-bit addresses).
- *   fused_set_waves  wavefronts per (tile, chunk) workgroup: 2, 4, 8 (default)
- *               or 16 (taken by the several-RHS pass; one-RHS passes run 8).
- *               Results do not depend on it (per-segment row sums in a fixed
- *               order, exact fixed-point column sums).
+ *   fused_set_waves  wavefronts per (tile, chunk) workgroup of one-RHS
+ *               passes: 2, 4 or 8 (default); a state can override it
+ *               (bsgd_state_set_launch).  Results do not depend on it
+ *               (per-segment row sums in a fixed order, exact fixed-point
+ *               column sums).
  *   fused_partials_size  bytes of the partial-sum buffer (device) that every
  *               pass needs: one float per segment slot and chunks x pixels.
  *   fused_apply   one pass in natural orders:
@@ -565,11 +589,12 @@ void bsgd_graph_destroy(bsgd_graph* graph);
  *               kernels again).  The state's value type must be available in
  *               the store.  States with several RHS (batches, volumes; nrhs a
  *               multiple of 4) take the pass four RHS per workgroup: the tile
- *               of x for those RHS in LDS as 4-vectors, the terms of A^T r
- *               added as 32-bit fixed-point integers per RHS (scale from that
- *               RHS's max |r|, sums below 2^30), the four row sums of an entry
- *               from one LDS read; results are bitwise reproducible and each
- *               RHS's are independent of the others.  ISTA epochs of such
+ *               of x for those RHS in LDS as 4-vectors, two lanes per segment
+ *               with two RHS each, the terms of A^T r added as 32-bit
+ *               fixed-point integers per RHS (scale from that RHS's max |r|:
+ *               sums below 2^30, terms below 2^21), two RHS per 64-bit atomic;
+ *               results are bitwise reproducible and each RHS's are
+ *               independent of the others.  ISTA epochs of such
  *               states, and block-select states, use the block store.
  */
 #define BSGD_FUSED_WIDE 1u /* 16-bit column addresses even where 8-bit steps would do */

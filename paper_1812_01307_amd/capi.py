@@ -106,6 +106,9 @@ _PROTOS = {
     "bsgd_state_enable_timing_sampled": [_vp, _i32, _i32],
     "bsgd_state_set_overlap": [_vp, _i32],
     "bsgd_state_set_prox_schedule": [_vp, _i32],
+    "bsgd_state_set_launch": [_vp, _i32, _i32],
+    "bsgd_state_launch": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+    "bsgd_state_autotune": [_vp, _f32, _f32, _i32, _i32, _vp, ctypes.POINTER(_i32)],
     "bsgd_state_timing": [_vp] + [ctypes.POINTER(ctypes.c_double)] * 3 + [ctypes.POINTER(_i64)],
     "bsgd_fused_workspace_size": [_vp, _i32, ctypes.c_uint, _vp, ctypes.POINTER(_sz)],
     "bsgd_fused_create": [_vp, _i32, ctypes.c_uint, _vp, _sz, _vp, ctypes.POINTER(_vp)],
@@ -621,6 +624,27 @@ def bsgd_graph_create(state: State, mu, lam, epochs, prox_iters, stream=None) ->
 
 def bsgd_graph_launch(graph: Graph, stream=None):
     _check("bsgd_graph_launch", _lib.bsgd_graph_launch(graph.handle, _stream(stream)))
+
+
+def bsgd_state_set_launch(state: State, pass_waves: int = 0, prox_split: int = 0):
+    _check("bsgd_state_set_launch", _lib.bsgd_state_set_launch(state.handle, int(pass_waves),
+                                                               int(prox_split)))
+
+
+def bsgd_state_launch(state: State):
+    """(pass wavefronts, prox split) of the state's epochs (0: defaults)."""
+    w, sp = _i32(), _i32()
+    _check("bsgd_state_launch", _lib.bsgd_state_launch(state.handle, ctypes.byref(w),
+                                                       ctypes.byref(sp)))
+    return w.value, sp.value
+
+
+def bsgd_state_autotune(state: State, mu, lam, prox_iters, reps=3, stream=None):
+    """Time the launch shapes on this (not yet initialised) state; returns the choice."""
+    ch = (_i32 * 2)()
+    _check("bsgd_state_autotune", _lib.bsgd_state_autotune(
+        state.handle, float(mu), float(lam), int(prox_iters), int(reps), _stream(stream), ch))
+    return ch[0], ch[1]
 
 
 def bsgd_state_set_prox_schedule(state: State, schedule: int):

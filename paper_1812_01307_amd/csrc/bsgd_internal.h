@@ -246,9 +246,10 @@ size_t fused_partials(const bsgd_fused* F, int S, FusedPartials* fp, void* ws);
 hipError_t launch_fused_absmax_mr(const float* v, int64_t n, int S, unsigned* out,
                                   hipStream_t s);
 hipError_t launch_fused_zero(unsigned* p, int n, hipStream_t s);
+// waves: wavefronts per workgroup (8 or 16; 0: 16)
 hipError_t launch_fused_pass_mr(const bsgd_fused* F, bsgd_valtype vt, int S, const float* x,
                                 const float* r, const unsigned* rmax_in, float* zp, float* gp,
-                                hipStream_t s);
+                                hipStream_t s, int waves = 0);
 hipError_t launch_fused_reduce_mr(const bsgd_fused* F, int S, const float* zp, const float* gp,
                                   const float* y, float* out_r, unsigned* rmax_out,
                                   const float* xadd, float scale, float* out_x, hipStream_t s,
@@ -259,7 +260,8 @@ hipError_t launch_fused_absmax(const float* v, int64_t n, unsigned* out, hipStre
 enum { kPassBoth = 0, kPassA = 1, kPassAt = 2 };
 hipError_t launch_fused_pass(const bsgd_fused* F, bsgd_valtype vt, const float* x,
                              const float* r, const unsigned* rmax_in, unsigned* rmax_zero,
-                             float* zp, float* gp, hipStream_t s, int mode = kPassBoth);
+                             float* zp, float* gp, hipStream_t s, int mode = kPassBoth,
+                             int waves = 0);  // waves 0: the store's
 // parts: kReduceRays (out_r, *rmax_out), kReducePixels (out_x), or both.
 enum { kReduceRays = 1, kReducePixels = 2, kReduceAll = 3 };
 hipError_t launch_fused_reduce(const bsgd_fused* F, const float* zp, const float* gp,
@@ -343,19 +345,21 @@ hipError_t fill_f32(float* x, int64_t n, float v, hipStream_t s);
 // tv_ws_floats(n) floats with n the vector length.
 size_t tv_ws_floats(int64_t n, int D);
 enum FgpSchedule { kFgpFused = 0, kFgpPerIteration = 1, kFgpFusedLds = 2 };
+// split: most FGP iterations per launch of the chunked schedules (2-D: 1 to
+// 10, volumes: 1 to 3; 0 or larger: the most)
 hipError_t tv_prox_run(const Layout& L, bool tiled, const float* b, float theta, int iters,
-                       float* out, float* ws, hipStream_t s, int schedule);
+                       float* out, float* ws, hipStream_t s, int schedule, int split = 0);
 // S images in the internal 2-D pixel order, [c_int][S] (image index fastest),
 // each with its own theta_j = mu * lam[j] (lam: device array of S floats, or
 // nullptr for theta_j = mu * lam0 for all j).  ws: tv_ws_floats(c_int * S, 1).
 hipError_t tv_prox_batch(const Layout& L, int S, const float* b, float mu, const float* lam,
                          float lam0, int iters, float* out, float* ws, hipStream_t s,
-                         int schedule);
+                         int schedule, int split = 0);
 // One volume of S slices in the internal order [c_int][S] (slice index
 // fastest), 3-D TV.  ws: tv_ws_floats(c_int * S, 2).
 // schedule kFgpPerIteration: one launch per iteration (k_fgp_iter3v);
 // otherwise launches of up to three iterations (k_fgp_tb3).  Same results.
 hipError_t tv_prox_volume(const Layout& L, int S, const float* b, float theta, int iters,
-                          float* out, float* ws, hipStream_t s, int schedule);
+                          float* out, float* ws, hipStream_t s, int schedule, int split = 0);
 
 }  // namespace bsgd

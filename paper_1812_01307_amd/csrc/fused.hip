@@ -88,6 +88,7 @@ struct bsgd_fused {
   int64_t pairs = 0, slices = 0, entries = 0, cap = 0;
   int maxrank = 0;           // most segments of one ray
   double smax = 0.0;         // largest column sum of |A| (bounds the sums of A^T r)
+  double amax = 0.0;         // largest |a| (bounds one term of A^T r)
   int32_t* sbeg = nullptr;   // units + 1: first slice of each unit
   int32_t* uorder = nullptr; // units: launch order (most slices first)
   int32_t* sng = nullptr;    // slices: 4-entry groups per lane
@@ -445,8 +446,9 @@ __global__ void k_fz_pad(const int32_t* __restrict__ slen, const int32_t* __rest
   }
 }
 
-// Largest column sum of |A| (rows of the transposed store), FP64, as the bit
-// pattern of a non-negative double (which orders like the value).
+// Largest column sum of |A| (rows of the transposed store) into out[0] and the
+// largest |a| into out[1], FP64, as bit patterns of non-negative doubles
+// (which order like the values).
 __global__ __launch_bounds__(256) void k_fz_colsum(const int64_t* __restrict__ ptr,
                                                    const int32_t* __restrict__ seg, int nseg,
                                                    const float* __restrict__ val, int64_t n,
@@ -455,12 +457,21 @@ __global__ __launch_bounds__(256) void k_fz_colsum(const int64_t* __restrict__ p
   const int lane = threadIdx.x & 63;
   if (k >= n) return;  // uniform per wavefront
   const int64_t beg = ptr[k], len = seg[k * (nseg + 1) + nseg];
-  double acc = 0.0;
-  for (int64_t e = lane; e < len; e += 64) acc += fabs((double)val[beg + e]);
+  double acc = 0.0, amax = 0.0;
+  for (int64_t e = lane; e < len; e += 64) {
+    const double a = fabs((double)val[beg + e]);
+    acc += a;
+    amax = fmax(amax, a);
+  }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  for (int off = 32; off > 0; off >>= 1) {
+    acc += __shfl_xor(acc, off);
+    amax = fmax(amax, __shfl_xor(amax, off));
+  }
   const unsigned long long bits = (unsigned long long)__double_as_longlong(acc);
+  const unsigned long long abits = (unsigned long long)__double_as_longlong(amax);
   if (lane == 0 && bits > __atomic_load_n(out, __ATOMIC_RELAXED)) atomicMax(out, bits);
+  if (lane == 0 && abits > __atomic_load_n(out + 1, __ATOMIC_RELAXED)) atomicMax(out + 1, abits);
 }
 
 __global__ void k_i64_to_i32(const int64_t* __restrict__ in, int32_t* __restrict__ out,
@@ -717,14 +728,16 @@ __global__ __launch_bounds__(64 * W) void k_fused(
 // vectors [rows][S] with the RHS index fastest, S a multiple of 4).  The same
 // store and units; a workgroup takes one unit for one column of kMrC = 4
 // consecutive RHS.  The unit's tile of x for those RHS goes to LDS as
-// 4-vectors.  Each slice's 64 segments are taken a quarter at a time, four
-// lanes per segment (one RHS each): a lane forms its segment's row sum for its
-// RHS in registers and adds its terms a * r_k of A^T r into the tile in LDS
-// as 32-bit fixed-point integers: scale 2^e_k from max |r_k|
-// and the largest column sum of |A| so that every sum stays below 2^30 in
-// magnitude (a term's rounding is below 2^-31 of the largest possible sum;
-// integer additions make the result independent of the order of the
-// atomics).  Launch slots are mapped so that the columns of one unit run side
+// 4-vectors.  Each slice's 64 segments are taken a half at a time, two lanes
+// per segment (two RHS each): a lane forms its segment's row sums for its two
+// RHS in registers and adds its terms a * r_k of A^T r into the tile in LDS as
+// 32-bit fixed-point integers, the pair packed into one 64-bit integer atomic
+// (the high word absorbs the low word's borrow, so the two sums separate
+// exactly at the end).  Scale 2^e_k from max |r_k|, the largest column sum of
+// |A| and the largest |a|: every sum stays below 2^30 in magnitude and every
+// term below 2^21, so one FMA with 1.5 * 2^23 rounds a term to an integer (a
+// term's rounding is below 2^-31 of the largest possible sum; integer
+// additions make the result independent of the order of the atomics).  Launch slots are mapped so that the columns of one unit run side
 // by side on one XCD (workgroups are dealt to the 8 XCDs in turn): the unit's
 // stored entries are read from HBM once per pass and from that XCD's L2 by
 // its other columns.  Partials: A x per (segment, RHS) at [rank][ray][S],
@@ -732,13 +745,24 @@ __global__ __launch_bounds__(64 * W) void k_fused(
 // ---------------------------------------------------------------------------
 constexpr int kMrC = 4;      // RHS per workgroup
 constexpr int kXcds = 8;     // workgroups are dealt to the XCDs round robin
+constexpr float kMagic32 = 12582912.0f;  // 1.5 * 2^23
+constexpr int kMagic32Bits = 0x4B400000;
 
-__device__ __forceinline__ int fixed_exponent32(double smax, float rmax) {
-  const double b = smax * (double)rmax;
+// Scale exponent of the 32-bit fixed-point sums: every sum below 2^30
+// (smax |r| 2^e < 2^30) and every term below 2^21 (amax |r| 2^e < 2^21), so
+// that t = rint(a r 2^e) comes out of one FMA with 1.5 * 2^23 as the low bits
+// of the float's pattern.
+__device__ __forceinline__ int fixed_exponent32(double smax, double amax, float rmax) {
+  const double b = smax * (double)rmax, t = amax * (double)rmax;
   if (!(b > 0.0) || !isfinite(b)) return 0;
-  int E;
-  (void)frexp(b, &E);  // b < 2^E
-  return min(max(30 - E, -200), 200);
+  int Es, Et;
+  (void)frexp(b, &Es);  // b < 2^Es
+  (void)frexp(t, &Et);
+  return min(max(min(30 - Es, 21 - Et), -200), 200);
+}
+
+__device__ __forceinline__ int term32(float a, float rs) {
+  return __float_as_int(fmaf(a, rs, kMagic32)) - kMagic32Bits;
 }
 
 template <typename VT, bool NARROW, int W>
@@ -749,13 +773,13 @@ __global__ __launch_bounds__(64 * W) void k_fused_mr(
     const uint16_t* __restrict__ sbase, const void* __restrict__ col,
     const VT* __restrict__ val, const float* __restrict__ x, const float* __restrict__ r,
     const unsigned* __restrict__ rmax_in, float* __restrict__ zp, float* __restrict__ gp,
-    int64_t r_int, int64_t c_int, int S, int64_t units, double smax) {
-  // tile of x and the A^T r sums, both [cell][RHS]: the 4 lanes of a segment
-  // address 4 consecutive words, so one instruction's 64 lanes touch 16 random
-  // 4-word groups (about 2-way bank conflicts, where lanes on random single
-  // words would conflict about 6-way)
+    int64_t r_int, int64_t c_int, int S, int64_t units, double smax, double amax) {
+  // tile of x as [cell][4 RHS] and the A^T r sums as [cell][2 pairs] of
+  // packed 64-bit integers (low word: the pair's first RHS, high word: the
+  // second plus the first's borrow): lane pairs of a segment address 16
+  // consecutive bytes of one cell
   __shared__ f32x4 xs[kFTA];
-  __shared__ int gs[kFTA * kMrC];
+  __shared__ unsigned long long gs[kFTA * 2];
   constexpr int NT = 64 * W;
   const int RC = S / kMrC;
   const int64_t nwg = units * RC;
@@ -772,12 +796,12 @@ __global__ __launch_bounds__(64 * W) void k_fused_mr(
   const int64_t xbase = (int64_t)d * g.slice_px;
   const int tid = threadIdx.x;
   const int wv = tid >> 6, lane = tid & 63;
-  const int sub = lane & 3, sg = lane >> 2;  // this lane's RHS and segment of a quarter
+  const int hp = lane & 1, sg = lane >> 1;  // this lane's RHS pair and segment of a half
   const int s0 = sbeg[u], s1 = sbeg[u + 1];
   for (int i = tid; i < kFTA; i += NT) {
     xs[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < kMrC; ++k) gs[i * kMrC + k] = 0;
+    gs[2 * i] = 0ull;
+    gs[2 * i + 1] = 0ull;
   }
   __syncthreads();
   for (int i = tid; i < kFT * kFT; i += NT) {
@@ -788,17 +812,24 @@ __global__ __launch_bounds__(64 * W) void k_fused_mr(
           *reinterpret_cast<const f32x4*>(
               x + (xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w) * S + cc * kMrC);
   }
-  const int rhs = cc * kMrC + sub;
-  const int ek = fixed_exponent32(smax, __uint_as_float(rmax_in[rhs]));
-  const float* xsf = reinterpret_cast<const float*>(xs) + sub;
-  int* gsi = gs + sub;
+  const int rhs0 = cc * kMrC + 2 * hp;  // this lane's RHS: rhs0, rhs0 + 1
+  const float rm0 = __uint_as_float(rmax_in[rhs0]), rm1 = __uint_as_float(rmax_in[rhs0 + 1]);
+  const int e0 = fixed_exponent32(smax, amax, rm0);
+  const int e1 = fixed_exponent32(smax, amax, rm1);
+  // a residual with a non-finite entry has no scale: its terms are left out
+  // (they would spill into the other word of the pair) and its partials carry
+  // a NaN
+  const bool bad0 = !(rm0 <= 3.40282347e38f), bad1 = !(rm1 <= 3.40282347e38f);
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  const f32x2* xsp = reinterpret_cast<const f32x2*>(xs) + hp;
+  unsigned long long* gsp = gs + hp;
   __syncthreads();
-  // work item = (slice, quarter): the quarter's 16 segments, 4 RHS each; the
-  // next item's table entries and r load while an item streams
-  auto meta = [&](int s, int qt) {
+  // work item = (slice, half): the half's 32 segments, 2 lanes each; the next
+  // item's table entries and r load while an item streams
+  auto meta = [&](int s, int hf) {
     SliceMeta m{-1, 0, 0, 0, 0};
     if (s < s1) {
-      const int L = qt * 16 + sg;
+      const int L = hf * 32 + sg;
       m.rho = sray[(int64_t)s * 64 + L];
       m.rk = srank[(int64_t)s * 64 + L];
       m.a0 = sbase ? sbase[(int64_t)s * 64 + L] : 0;
@@ -807,20 +838,24 @@ __global__ __launch_bounds__(64 * W) void k_fused_mr(
     }
     return m;
   };
-  int kk = 0, qt = 0, s = snake<W>(s0, 0, wv);
+  auto rpair = [&](int rho) {
+    return rho >= 0 ? *reinterpret_cast<const f32x2*>(r + (int64_t)rho * S + rhs0)
+                    : f32x2{0.f, 0.f};
+  };
+  int kk = 0, hf = 0, s = snake<W>(s0, 0, wv);
   SliceMeta cur = meta(s, 0);
-  float rcur = cur.rho >= 0 ? r[(int64_t)cur.rho * S + rhs] : 0.f;
+  f32x2 rcur = rpair(cur.rho);
   while (s < s1) {
-    const int qn = (qt + 1) & 3;
-    const int sn = qn == 0 ? snake<W>(s0, kk + 1, wv) : s;
-    const SliceMeta nxt = meta(sn, qn);
-    const float rnext = nxt.rho >= 0 ? r[(int64_t)nxt.rho * S + rhs] : 0.f;
-    const float rs = ldexpf(rcur, ek);
+    const int hn = hf ^ 1;
+    const int sn = hn == 0 ? snake<W>(s0, kk + 1, wv) : s;
+    const SliceMeta nxt = meta(sn, hn);
+    const f32x2 rnext = rpair(nxt.rho);
+    const float rs0 = bad0 ? 0.f : ldexpf(rcur[0], e0), rs1 = bad1 ? 0.f : ldexpf(rcur[1], e1);
     const int64_t base = cur.base;
     const int ng = cur.ng;
-    float z0 = 0.f, z1 = 0.f;
+    float za = 0.f, zb = 0.f, zc = 0.f, zd = 0.f;
     int ap = cur.a0;
-    auto step = [&](const ColRaw<NARROW>& raw, const float (&a)[4], float& z) {
+    auto step = [&](const ColRaw<NARROW>& raw, const float (&a)[4], float& z0, float& z1) {
       int c[4];
       if constexpr (NARROW) {
         c[0] = ap + (int)(raw & 255u);
@@ -834,8 +869,13 @@ __global__ __launch_bounds__(64 * W) void k_fused_mr(
       }
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        z = fmaf(a[e], xsf[c[e] * kMrC], z);
-        atomicAdd(gsi + c[e] * kMrC, __float2int_rn(a[e] * rs));
+        const f32x2 xv = xsp[c[e] * 2];
+        z0 = fmaf(a[e], xv[0], z0);
+        z1 = fmaf(a[e], xv[1], z1);
+        const int t0 = term32(a[e], rs0), t1 = term32(a[e], rs1);
+        const unsigned long long pk =
+            ((unsigned long long)(unsigned)(t1 + (t0 >> 31)) << 32) | (unsigned)t0;
+        atomicAdd(gsp + c[e] * 2, pk);
       }
     };
     int j = 0;
@@ -844,35 +884,40 @@ __global__ __launch_bounds__(64 * W) void k_fused_mr(
       float a0[4], a1[4];
       load_group<VT, NARROW>(col, val, base + (int64_t)j * 256, c0, a0);
       load_group<VT, NARROW>(col, val, base + (int64_t)(j + 1) * 256, c1, a1);
-      step(c0, a0, z0);
-      step(c1, a1, z1);
+      step(c0, a0, za, zb);
+      step(c1, a1, zc, zd);
     }
     if (j < ng) {
       ColRaw<NARROW> c0;
       float a0[4];
       load_group<VT, NARROW>(col, val, base + (int64_t)j * 256, c0, a0);
-      step(c0, a0, z0);
+      step(c0, a0, za, zb);
     }
-    if (cur.rho >= 0) zp[((int64_t)cur.rk * r_int + cur.rho) * S + rhs] = z0 + z1;
-    if (qn == 0) ++kk;
-    qt = qn;
+    if (cur.rho >= 0)
+      *reinterpret_cast<f32x2*>(zp + ((int64_t)cur.rk * r_int + cur.rho) * S + rhs0) =
+          f32x2{za + zc, zb + zd};
+    if (hn == 0) ++kk;
+    hf = hn;
     s = sn;
     cur = nxt;
     rcur = rnext;
   }
   __syncthreads();
-  // NT is a multiple of 4, so every thread flushes its own RHS `sub`; a
-  // residual with a non-finite entry has no scale and its partials carry a NaN
-  const float rm = __uint_as_float(rmax_in[rhs]);
-  const bool rbad = !(rm <= 3.40282347e38f);
-  for (int i = tid; i < kFT * kFT * kMrC; i += NT) {
-    const int px = i >> 2;
+  // NT is even, so every thread flushes its own pair hp
+  for (int i = tid; i < kFT * kFT * 2; i += NT) {
+    const int px = i >> 1;
     const int b = px >> 6, w = px & 63;
     const int tr8 = ftr * 8 + (b >> 3), tc8 = ftc * 8 + (b & 7);
     if (tr8 < g.Ht && tc8 < g.Wt) {
       const int a = (((b >> 3) << 3) + (w >> 3)) * kFTS + ((b & 7) << 3) + (w & 7);
-      gp[((int64_t)q * c_int + xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w) * S + rhs] =
-          rbad ? __uint_as_float(0x7fc00000u) : ldexpf((float)gsi[a * kMrC], -ek);
+      const unsigned long long tot = gsp[a * 2];
+      const int lo = (int)(unsigned)(tot & 0xffffffffull);
+      const int hi = (int)(unsigned)((tot - (unsigned long long)(long long)lo) >> 32);
+      const f32x2 o{bad0 ? __uint_as_float(0x7fc00000u) : ldexpf((float)lo, -e0),
+                    bad1 ? __uint_as_float(0x7fc00000u) : ldexpf((float)hi, -e1)};
+      *reinterpret_cast<f32x2*>(
+          gp + ((int64_t)q * c_int + xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w) * S +
+          rhs0) = o;
     }
   }
 }
@@ -1090,7 +1135,7 @@ template <typename VT>
 static void launch_fused_vt(const bsgd_fused& F, int mode, const VT* val, const float* x,
                             const float* r, const unsigned* rmax_in, unsigned* rmax_zero,
                             float* zp, float* gp, hipStream_t s) {
-  switch (F.waves) {  // 16 is for the several-RHS pass; one RHS takes 8
+  switch (F.waves) {
     case 2: launch_fused_w<VT, 2>(F, mode, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
     case 4: launch_fused_w<VT, 4>(F, mode, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
     default: launch_fused_w<VT, 8>(F, mode, val, x, r, rmax_in, rmax_zero, zp, gp, s); break;
@@ -1121,11 +1166,13 @@ hipError_t launch_fused_absmax(const float* v, int64_t n, unsigned* out, hipStre
 
 hipError_t launch_fused_pass(const bsgd_fused* F, bsgd_valtype vt, const float* x,
                              const float* r, const unsigned* rmax_in, unsigned* rmax_zero,
-                             float* zp, float* gp, hipStream_t s, int mode) {
+                             float* zp, float* gp, hipStream_t s, int mode, int waves) {
+  bsgd_fused G = *F;  // the launch's wave count: the caller's, else the store's
+  G.waves = waves > 0 ? waves : F->waves;
   if (vt == BSGD_VAL_F16)
-    launch_fused_vt<__half>(*F, mode, F->val16, x, r, rmax_in, rmax_zero, zp, gp, s);
+    launch_fused_vt<__half>(G, mode, F->val16, x, r, rmax_in, rmax_zero, zp, gp, s);
   else
-    launch_fused_vt<float>(*F, mode, F->val, x, r, rmax_in, rmax_zero, zp, gp, s);
+    launch_fused_vt<float>(G, mode, F->val, x, r, rmax_in, rmax_zero, zp, gp, s);
   return hipGetLastError();
 }
 
@@ -1156,27 +1203,30 @@ static void launch_mr_w(const bsgd_fused& F, const VT* val, const float* x, cons
   if (F.narrow)
     k_fused_mr<VT, true, W><<<grid, 64 * W, 0, s>>>(F.g, F.uorder, F.sbeg, F.sng, F.soff, F.sray,
                                                     F.srank, F.sbase, F.col8, val, x, r, rmax_in,
-                                                    zp, gp, ri, ci, S, units, F.smax);
+                                                    zp, gp, ri, ci, S, units, F.smax, F.amax);
   else
     k_fused_mr<VT, false, W><<<grid, 64 * W, 0, s>>>(F.g, F.uorder, F.sbeg, F.sng, F.soff,
                                                      F.sray, F.srank, nullptr, F.col, val, x, r,
-                                                     rmax_in, zp, gp, ri, ci, S, units, F.smax);
+                                                     rmax_in, zp, gp, ri, ci, S, units, F.smax,
+                                                     F.amax);
 }
 
 hipError_t launch_fused_pass_mr(const bsgd_fused* F, bsgd_valtype vt, int S, const float* x,
                                 const float* r, const unsigned* rmax_in, float* zp, float* gp,
-                                hipStream_t s) {
+                                hipStream_t s, int waves) {
   const int64_t units = F->g.units();
   const int64_t nwg = units * (S / kMrC);
   const unsigned grid = (unsigned)((nwg + kXcds - 1) / kXcds * kXcds);
   const int64_t ri = F->plan->L.r_int, ci = F->plan->L.c_int;
+  // one workgroup per CU (its LDS): 16 wavefronts unless 8 are asked for
+  const bool w16 = waves != 8;
   if (vt == BSGD_VAL_F16) {
-    if (F->waves == 16)
+    if (w16)
       launch_mr_w<__half, 16>(*F, F->val16, x, r, rmax_in, zp, gp, ri, ci, S, units, grid, s);
     else
       launch_mr_w<__half, 8>(*F, F->val16, x, r, rmax_in, zp, gp, ri, ci, S, units, grid, s);
   } else {
-    if (F->waves == 16)
+    if (w16)
       launch_mr_w<float, 16>(*F, F->val, x, r, rmax_in, zp, gp, ri, ci, S, units, grid, s);
     else
       launch_mr_w<float, 8>(*F, F->val, x, r, rmax_in, zp, gp, ri, ci, S, units, grid, s);
@@ -1349,7 +1399,7 @@ static size_t fused_layout(const bsgd_plan* p, const TileGeom& g, const FusedCou
   T->sng256 = cv.take<int64_t>(fc.slices + 1);
   T->scan_tmp = cv.take<int64_t>(scan_tmp_count(fc.slices) + 1);
   T->err = cv.take<int>(64);
-  T->smax = cv.take<unsigned long long>(1);
+  T->smax = cv.take<unsigned long long>(2);
   size_t cub_bytes = 0;
   (void)hipcub::DeviceRadixSort::SortPairs(nullptr, cub_bytes, (const uint64_t*)nullptr,
                                            (uint64_t*)nullptr, (const int32_t*)nullptr,
@@ -1436,7 +1486,7 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, unsi
   };
   hipError_t e;
   e = hipMemsetAsync(T.err, 0, sizeof(int), stream);
-  if (e == hipSuccess) e = hipMemsetAsync(T.smax, 0, sizeof(unsigned long long), stream);
+  if (e == hipSuccess) e = hipMemsetAsync(T.smax, 0, 2 * sizeof(unsigned long long), stream);
   if (e != hipSuccess) return hip_fail(e, "single-pass build set-up");
   {
     const Store& B = plan->bwd;
@@ -1508,10 +1558,10 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, unsi
   if (e != hipSuccess) return hip_fail(e, "slice offsets");
   int64_t total = 0;
   int h_err = 0;
-  unsigned long long smax_bits = 0;
+  unsigned long long smax_bits[2] = {0, 0};
   e = hipMemcpyAsync(&total, F->soff + fc.slices, sizeof(int64_t), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(&smax_bits, T.smax, sizeof(smax_bits), hipMemcpyDeviceToHost, stream);
+    e = hipMemcpyAsync(smax_bits, T.smax, sizeof(smax_bits), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(&h_err, T.err, sizeof(int), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -1545,8 +1595,10 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, unsi
   F->pairs = fc.pairs;
   F->maxrank = fc.maxrank;
   {
-    double sm;
-    std::memcpy(&sm, &smax_bits, sizeof(sm));
+    double sm, am;
+    std::memcpy(&sm, &smax_bits[0], sizeof(sm));
+    std::memcpy(&am, &smax_bits[1], sizeof(am));
+    F->amax = am;
     // FP16 values round |a| up by at most 2^-11 relative: sums stay below
     // 2^46 * (1 + 2^-11), inside the 2^47 that the 48-bit window allows
     F->smax = sm;
@@ -1578,8 +1630,7 @@ extern "C" bsgd_status bsgd_fused_shape(const bsgd_fused* F, int* tiles, int* ch
 extern "C" bsgd_status bsgd_fused_set_waves(bsgd_fused* F, int waves) {
   clear_error();
   BSGD_REQUIRE(F != nullptr, "fused store is NULL");
-  BSGD_REQUIRE(waves == 2 || waves == 4 || waves == 8 || waves == 16,
-               "waves must be 2, 4, 8 or 16");
+  BSGD_REQUIRE(waves == 2 || waves == 4 || waves == 8, "waves must be 2, 4 or 8");
   F->waves = waves;
   return BSGD_OK;
 }

@@ -38,6 +38,8 @@ struct bsgd_state {
   int overlap = 1;  // 0: forward pass concurrent with backprojection + prox; 1: with the prox only
   int prox_schedule = bsgd::kFgpFused;  // 2-D prox: fused chunks or one launch per iteration
   int method = BSGD_METHOD_BSGD;        // update rule of bsgd_run_epochs
+  int pass_waves = 0;   // wavefronts per single-pass workgroup (0: the default)
+  int prox_split = 0;   // most FGP iterations per prox launch (0: the most)
   float* zt = nullptr;                  // BSGD_STATE_BLOCK_SELECT: kept products, [N][r_int]
   uint8_t* blk_r = nullptr;             // ... row block of each internal ray (0xFF: hole)
   uint8_t* blk_c = nullptr;             // ... column block of each internal pixel
@@ -578,12 +580,12 @@ static hipError_t prox_step(const bsgd_state* st, float mu, float lam, bool per_
   const int S = st->nrhs;
   if (S == 1)
     return tv_prox_run(p->L, true, st->xhat, mu * lam, prox_iters, out, st->tv_ws, s,
-                       st->prox_schedule);
+                       st->prox_schedule, st->prox_split);
   if (st->flags & BSGD_STATE_VOLUME)
     return tv_prox_volume(p->L, S, st->xhat, mu * lam, prox_iters, out, st->tv_ws, s,
-                          st->prox_schedule);
+                          st->prox_schedule, st->prox_split);
   return tv_prox_batch(p->L, S, st->xhat, mu, per_rhs ? st->lam : nullptr, lam, prox_iters, out,
-                       st->tv_ws, s, st->prox_schedule);
+                       st->tv_ws, s, st->prox_schedule, st->prox_split);
 }
 
 extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int epochs,
@@ -650,7 +652,8 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
                                         stream));
       if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
       BSGD_HIP(launch_fused_pass_mr(st->fz, st->vt, S, st->x[c], st->r[c],
-                                    fp.rmax + (size_t)c * S, fp.zp, fp.gp, stream));
+                                    fp.rmax + (size_t)c * S, fp.zp, fp.gp, stream,
+                                    st->pass_waves));
       if (tv) BSGD_HIP(hipEventRecord(tv[1], stream));
       // the next residual's maxima start from zero (after the pass read this one's)
       BSGD_HIP(launch_fused_zero(fp.rmax + (size_t)n * S, S, stream));
@@ -687,7 +690,7 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
       if (e == 0) BSGD_HIP(launch_fused_absmax(st->r[c], p->L.r_int, fp.rmax + c, stream));
       if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
       BSGD_HIP(launch_fused_pass(st->fz, st->vt, st->x[c], st->r[c], fp.rmax + c, fp.rmax + n,
-                                 fp.zp, fp.gp, stream));
+                                 fp.zp, fp.gp, stream, kPassBoth, st->pass_waves));
       if (tv) BSGD_HIP(hipEventRecord(tv[1], stream));
       if (split) {
         BSGD_HIP(hipEventRecord(st->ev_main, stream));
@@ -703,7 +706,7 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
       if (tv) BSGD_HIP(hipEventRecord(tv[3], stream));
       if (theta != 0.f)
         BSGD_HIP(tv_prox_run(p->L, true, st->xhat, theta, prox_iters, st->x[n], st->tv_ws,
-                             stream, st->prox_schedule));
+                             stream, st->prox_schedule, st->prox_split));
       if (tv) BSGD_HIP(hipEventRecord(tv[4], stream));
       if (split) BSGD_HIP(hipStreamWaitEvent(stream, st->ev_aux, 0));
       st->cur = n;
@@ -914,6 +917,132 @@ extern "C" bsgd_status bsgd_state_attach_fused(bsgd_state* st, const bsgd_fused*
   return BSGD_OK;
 }
 
+extern "C" bsgd_status bsgd_state_set_launch(bsgd_state* st, int pass_waves, int prox_split) {
+  clear_error();
+  BSGD_REQUIRE(st != nullptr, "state is NULL");
+  BSGD_REQUIRE(pass_waves == 0 || pass_waves == 2 || pass_waves == 4 || pass_waves == 8 ||
+                   pass_waves == 16,
+               "pass_waves must be 0, 2, 4, 8 or 16");
+  BSGD_REQUIRE(pass_waves != 16 || st->nrhs > 1, "16 wavefronts: several-RHS passes only");
+  BSGD_REQUIRE(st->nrhs == 1 || pass_waves == 0 || pass_waves >= 8,
+               "several-RHS passes run 8 or 16 wavefronts");
+  BSGD_REQUIRE(prox_split >= 0, "prox_split must be >= 0");
+  st->pass_waves = pass_waves;
+  st->prox_split = prox_split;
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_state_launch(const bsgd_state* st, int* pass_waves, int* prox_split) {
+  clear_error();
+  BSGD_REQUIRE(st && pass_waves && prox_split, "NULL argument");
+  *pass_waves = st->pass_waves;
+  *prox_split = st->prox_split;
+  return BSGD_OK;
+}
+
+// Time `reps` epochs (after one untimed) of the state on zero data; seconds.
+static bsgd_status time_epochs(bsgd_state* st, float mu, float lam, int prox_iters, int reps,
+                               hipStream_t stream, hipEvent_t e0, hipEvent_t e1, double* ms) {
+  bsgd_status r = bsgd_run_epochs(st, mu, lam, 1, prox_iters, stream);
+  if (r != BSGD_OK) return r;
+  BSGD_HIP(hipEventRecord(e0, stream));
+  r = bsgd_run_epochs(st, mu, lam, reps, prox_iters, stream);
+  if (r != BSGD_OK) return r;
+  BSGD_HIP(hipEventRecord(e1, stream));
+  BSGD_HIP(hipEventSynchronize(e1));
+  float t = 0.f;
+  BSGD_HIP(hipEventElapsedTime(&t, e0, e1));
+  *ms = t;
+  return BSGD_OK;
+}
+
+static bsgd_status zero_state(bsgd_state* st, hipStream_t stream) {
+  const bsgd_plan* p = st->plan;
+  const size_t rb = sizeof(float) * p->L.r_int * st->nrhs, cb = sizeof(float) * p->L.c_int * st->nrhs;
+  BSGD_HIP(hipMemsetAsync(st->y, 0, rb, stream));
+  BSGD_HIP(hipMemsetAsync(st->r[0], 0, rb, stream));
+  BSGD_HIP(hipMemsetAsync(st->r[1], 0, rb, stream));
+  BSGD_HIP(hipMemsetAsync(st->x[0], 0, cb, stream));
+  BSGD_HIP(hipMemsetAsync(st->x[1], 0, cb, stream));
+  BSGD_HIP(hipMemsetAsync(st->lam, 0, sizeof(float) * st->nrhs, stream));
+  st->cur = 0;
+  st->epochs_done = 0;
+  return BSGD_OK;
+}
+
+extern "C" bsgd_status bsgd_state_autotune(bsgd_state* st, float mu, float lam, int prox_iters,
+                                           int reps, hipStream_t stream, int* choice) {
+  clear_error();
+  BSGD_REQUIRE(st != nullptr, "state is NULL");
+  BSGD_REQUIRE(!st->initialised, "autotune runs before bsgd_state_init (it overwrites the state)");
+  BSGD_REQUIRE(std::isfinite(mu) && mu > 0.f, "mu must be finite and > 0");
+  BSGD_REQUIRE(std::isfinite(lam) && lam >= 0.f, "lam must be finite and >= 0");
+  BSGD_REQUIRE(lam == 0.f || prox_iters >= 1, "prox_iters must be >= 1 when lam != 0");
+  BSGD_REQUIRE(reps >= 1 && reps <= 1000, "reps must be in [1, 1000]");
+  bsgd_status r = zero_state(st, stream);
+  if (r != BSGD_OK) return r;
+  st->initialised = true;
+  const int t_cap = st->t_cap;
+  st->t_cap = 0;  // no kernel timers while tuning
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto done = [&](bsgd_status s) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    st->t_cap = t_cap;
+    st->initialised = false;
+    const bsgd_status z = zero_state(st, stream);
+    (void)hipStreamSynchronize(stream);
+    return s != BSGD_OK ? s : z;
+  };
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    set_error("event creation failed");
+    return done(BSGD_ERR_HIP);
+  }
+  const bool volume = (st->flags & BSGD_STATE_VOLUME) != 0;
+  // the pass: wavefronts per workgroup (one RHS: the store's 4 or 8; several: 8 or 16)
+  int best_w = 0;
+  if (st->fz && st->method == BSGD_METHOD_BSGD) {
+    const int one[2] = {4, 8}, many[2] = {8, 16};
+    const int* cand = st->nrhs == 1 ? one : many;
+    double best = 1e300;
+    for (int i = 0; i < 2; ++i) {
+      st->pass_waves = cand[i];
+      double ms = 0.0;
+      r = time_epochs(st, mu, 0.f, 0, reps, stream, e0, e1, &ms);
+      if (r != BSGD_OK) return done(r);
+      if (ms < best) {
+        best = ms;
+        best_w = cand[i];
+      }
+    }
+  }
+  st->pass_waves = best_w;
+  // the prox: most FGP iterations per launch (2-D: 5 or 10; volumes: 1, 2 or 3)
+  int best_s = 0;
+  if (lam > 0.f && st->prox_schedule != kFgpPerIteration) {
+    const int two[2] = {5, 10}, three[3] = {1, 2, 3};
+    const int* cand = volume ? three : two;
+    const int nc = volume ? 3 : 2;
+    double best = 1e300;
+    for (int i = 0; i < nc; ++i) {
+      st->prox_split = cand[i];
+      double ms = 0.0;
+      r = time_epochs(st, mu, lam, prox_iters, reps, stream, e0, e1, &ms);
+      if (r != BSGD_OK) return done(r);
+      if (ms < best) {
+        best = ms;
+        best_s = cand[i];
+      }
+    }
+  }
+  st->prox_split = best_s;
+  if (choice) {
+    choice[0] = best_w;
+    choice[1] = best_s;
+  }
+  return done(BSGD_OK);
+}
+
 extern "C" bsgd_status bsgd_state_set_prox_schedule(bsgd_state* st, int schedule) {
   clear_error();
   BSGD_REQUIRE(st != nullptr, "state is NULL");
@@ -1020,7 +1149,7 @@ extern "C" bsgd_status bsgd_get_res_change_rhs(const bsgd_state* st, hipStream_t
 // choices of the epoch schedule.  A replay is valid only while all of them
 // are unchanged.
 struct GraphKey {
-  int cur = 0, method = 0, overlap = 0, schedule = 0;
+  int cur = 0, method = 0, overlap = 0, schedule = 0, pass_waves = 0, prox_split = 0;
   const bsgd_fused* fz = nullptr;
   const float* zp = nullptr;
   const float* gp = nullptr;
@@ -1028,7 +1157,8 @@ struct GraphKey {
   int lanes_fwd = 0, lanes_bwd = 0, staged_fwd = 0, staged_bwd = 0;
   bool operator==(const GraphKey& o) const {
     return cur == o.cur && method == o.method && overlap == o.overlap &&
-           schedule == o.schedule && fz == o.fz && zp == o.zp && gp == o.gp && rmax == o.rmax &&
+           schedule == o.schedule && pass_waves == o.pass_waves &&
+           prox_split == o.prox_split && fz == o.fz && zp == o.zp && gp == o.gp && rmax == o.rmax &&
            lanes_fwd == o.lanes_fwd && lanes_bwd == o.lanes_bwd && staged_fwd == o.staged_fwd &&
            staged_bwd == o.staged_bwd;
   }
@@ -1040,6 +1170,8 @@ static GraphKey graph_key(const bsgd_state* st) {
   k.method = st->method;
   k.overlap = st->overlap;
   k.schedule = st->prox_schedule;
+  k.pass_waves = st->pass_waves;
+  k.prox_split = st->prox_split;
   k.fz = st->fz;
   k.zp = st->fzp.zp;
   k.gp = st->fzp.gp;

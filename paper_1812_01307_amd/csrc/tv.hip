@@ -697,7 +697,7 @@ static hipError_t fgp2_per_iteration(const Layout& L, int S, const float* b, flo
 template <bool TILED>
 static hipError_t fgp2_chunks(const Layout& L, int S, const float* b, float theta0,
                               const float* lam, float mu, int iters, float* out, float* ws,
-                              int64_t n, hipStream_t s, int schedule) {
+                              int64_t n, hipStream_t s, int schedule, int split = 0) {
   Momentum mom;
   if (schedule == kFgpPerIteration && iters >= 1)
     return fgp2_per_iteration<TILED>(L, S, b, theta0, lam, mu, iters, mom, out, ws, n, s);
@@ -710,7 +710,8 @@ static hipError_t fgp2_chunks(const Layout& L, int S, const float* b, float thet
   // one of 20 (measured on gfx950: 63 vs 84 us at 512^2, 337 vs 388 us for
   // 30 iterations at 1024^2).  The per-pixel arithmetic does not depend on
   // the split.
-  const int nl = (iters + kFuseSplit - 1) / kFuseSplit;
+  const int most = split >= 1 && split < kFuseSplit ? split : kFuseSplit;
+  const int nl = (iters + most - 1) / most;
   for (int k0 = 0, li = 0; k0 < iters; ++li) {
     const int chunk = iters / nl + (li < iters % nl ? 1 : 0);
     FuseArgs ca{};
@@ -736,7 +737,7 @@ static hipError_t fgp2_chunks(const Layout& L, int S, const float* b, float thet
 
 template <bool TILED>
 static hipError_t tv_prox_impl(const Layout& L, const float* b, float theta, int iters,
-                               float* out, float* ws, hipStream_t s, int schedule) {
+                               float* out, float* ws, hipStream_t s, int schedule, int split) {
   const int64_t n = TILED ? L.c_int : (int64_t)L.H * L.W * L.D;
   const int64_t npix = (int64_t)L.H * L.W * L.D;
   if (theta == 0.f || iters == 0) {
@@ -744,7 +745,8 @@ static hipError_t tv_prox_impl(const Layout& L, const float* b, float theta, int
     return hipGetLastError();
   }
   if (L.D == 1)
-    return fgp2_chunks<TILED>(L, 1, b, theta, nullptr, 1.f, iters, out, ws, n, s, schedule);
+    return fgp2_chunks<TILED>(L, 1, b, theta, nullptr, 1.f, iters, out, ws, n, s, schedule,
+                              split);
   Momentum mom;
   float* buf[3] = {ws, ws + 3 * n, ws + 6 * n};  // (pd, pv, ph) triples
   float* q = ws + 9 * n;
@@ -766,19 +768,20 @@ static hipError_t tv_prox_impl(const Layout& L, const float* b, float theta, int
 }
 
 hipError_t tv_prox_run(const Layout& L, bool tiled, const float* b, float theta, int iters,
-                       float* out, float* ws, hipStream_t s, int schedule) {
-  return tiled ? tv_prox_impl<true>(L, b, theta, iters, out, ws, s, schedule)
-               : tv_prox_impl<false>(L, b, theta, iters, out, ws, s, schedule);
+                       float* out, float* ws, hipStream_t s, int schedule, int split) {
+  return tiled ? tv_prox_impl<true>(L, b, theta, iters, out, ws, s, schedule, split)
+               : tv_prox_impl<false>(L, b, theta, iters, out, ws, s, schedule, split);
 }
 
 hipError_t tv_prox_batch(const Layout& L, int S, const float* b, float mu, const float* lam,
                          float lam0, int iters, float* out, float* ws, hipStream_t s,
-                         int schedule) {
+                         int schedule, int split) {
   if (iters == 0) {
     // identity for every image: one chunk-free copy through the theta = 0 path
     return fgp2_chunks<true>(L, S, b, 0.f, nullptr, mu, 1, out, ws, L.c_int, s, kFgpFused);
   }
-  return fgp2_chunks<true>(L, S, b, mu * lam0, lam, mu, iters, out, ws, L.c_int, s, schedule);
+  return fgp2_chunks<true>(L, S, b, mu * lam0, lam, mu, iters, out, ws, L.c_int, s, schedule,
+                          split);
 }
 
 // ---------------------------------------------------------------------------
@@ -1124,7 +1127,7 @@ static void launch_tb3(const Layout& L, int S, const float* b, float theta, floa
 constexpr int kTB3Levels = 3;  // most iterations one launch of k_fgp_tb3 runs
 
 hipError_t tv_prox_volume(const Layout& L, int S, const float* b, float theta, int iters,
-                          float* out, float* ws, hipStream_t s, int schedule) {
+                          float* out, float* ws, hipStream_t s, int schedule, int split) {
   const int64_t n = L.c_int * S;
   if (theta == 0.f || iters == 0) {
     k_copy_f32v<<<grid_for(n), 256, 0, s>>>(b, out, n);
@@ -1136,7 +1139,8 @@ hipError_t tv_prox_volume(const Layout& L, int S, const float* b, float theta, i
     // equal launches of at most kTB3Levels iterations; p_{k0} in buf[in],
     // p_{k0-1} in buf[in + 1], outputs to the other pair
     float* buf[4] = {ws, ws + 3 * n, ws + 6 * n, ws + 9 * n};
-    const int nl = (iters + kTB3Levels - 1) / kTB3Levels;
+    const int most = split >= 1 && split < kTB3Levels ? split : kTB3Levels;
+    const int nl = (iters + most - 1) / most;
     int in = 0;
     for (int k0 = 0, li = 0; k0 < iters; ++li) {
       const int chunk = iters / nl + (li < iters % nl ? 1 : 0);

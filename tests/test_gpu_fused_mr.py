@@ -188,3 +188,59 @@ def test_attach_rules_for_several_rhs():
         bsgd.bsgd_state_attach_fused(st, F, small)
     assert e.value.status == bsgd.BSGD_ERR_WORKSPACE
     bsgd.bsgd_state_attach_fused(st, F)
+
+
+@pytest.mark.parametrize("kind", ["one", "batch", "volume"])
+def test_autotuned_launch_shapes_leave_results_unchanged(kind):
+    """The autotuner picks wavefront counts and prox splits by timing them; none
+    of them changes a result, so tuned epochs equal default ones bitwise."""
+    import paper_1812_01307_amd as bsgd
+    p = problem("c1_64")
+    plan = plan_for(p)
+    F = bsgd.bsgd_fused_create(plan, 0)
+    mu = float(np.float32(mu_for(p)))
+    S, flags = {"one": (1, 0), "batch": (8, 0), "volume": (8, bsgd.BSGD_STATE_VOLUME)}[kind]
+    Y = _sinograms(p, S, zero_last=False) if S > 1 else f32(p.y)[None, :].astype(np.float64)
+    lam = 20.0
+
+    def run(tune):
+        st = bsgd.bsgd_state_create(plan, S, flags=flags)
+        bsgd.bsgd_state_attach_fused(st, F)
+        choice = None
+        if tune:
+            choice = bsgd.bsgd_state_autotune(st, mu, lam, 20, reps=2)
+            assert bsgd.bsgd_state_launch(st) == choice
+        bsgd.bsgd_state_init(st, _dev(f32(_rows(Y)).ravel()))
+        bsgd.bsgd_run_epochs(st, mu, lam, 6, 20)
+        return _host(bsgd.bsgd_get_x(st)), choice
+
+    x0, _ = run(False)
+    x1, choice = run(True)
+    assert np.array_equal(x0, x1)
+    waves, split = choice
+    assert waves in ((4, 8) if S == 1 else (8, 16))
+    assert split in ((1, 2, 3) if kind == "volume" else (5, 10))
+    # every shape by hand gives the same result too
+    for w in ((2, 4, 8) if S == 1 else (8, 16)):
+        for sp in ((1, 2, 3) if kind == "volume" else (1, 4, 10)):
+            st = bsgd.bsgd_state_create(plan, S, flags=flags)
+            bsgd.bsgd_state_attach_fused(st, F)
+            bsgd.bsgd_state_set_launch(st, w, sp)
+            bsgd.bsgd_state_init(st, _dev(f32(_rows(Y)).ravel()))
+            bsgd.bsgd_run_epochs(st, mu, lam, 6, 20)
+            assert np.array_equal(_host(bsgd.bsgd_get_x(st)), x0), (w, sp)
+
+
+def test_launch_shape_argument_checks():
+    import paper_1812_01307_amd as bsgd
+    p = problem("c1_64")
+    plan = plan_for(p)
+    one = bsgd.bsgd_state_create(plan, 1)
+    with pytest.raises(bsgd.BsgdError):
+        bsgd.bsgd_state_set_launch(one, 16, 0)
+    many = bsgd.bsgd_state_create(plan, 4)
+    with pytest.raises(bsgd.BsgdError):
+        bsgd.bsgd_state_set_launch(many, 4, 0)
+    bsgd.bsgd_state_init(many, _dev(np.zeros(p.nrows * 4, np.float32)))
+    with pytest.raises(bsgd.BsgdError, match="before"):
+        bsgd.bsgd_state_autotune(many, 1e-4, 1.0, 20)

@@ -269,7 +269,8 @@ def main(argv=None):
     fused = args.path == "fused"
 
     tuned = None
-    if args.autotune:
+    launch = {}
+    if args.autotune and not fused:
         # one autotuned plan outside the timed region; its launch choice is
         # reused by every timed job (the tuner's cache)
         p0 = bsgd.bsgd_plan_create(A, At, prob.M, prob.N, prob.row_off, prob.col_off, prob.H,
@@ -336,6 +337,14 @@ def main(argv=None):
         else:
             mu = fixed_mu
         st = make_state(plan, F)
+        if args.autotune and fused:
+            # the state's launch shapes (pass wavefronts, prox iterations per
+            # launch) timed once, on the first job's state, and reused
+            if "shape" not in launch:
+                launch["shape"] = bsgd.bsgd_state_autotune(st, mu, lam_run, K, reps=5)
+                print(f"[bench] autotuned launch (pass waves, prox split) {launch['shape']}",
+                      file=sys.stderr, flush=True)
+            bsgd.bsgd_state_set_launch(st, *launch["shape"])
         if record and timing:
             # one epoch in TIMING_STRIDE carries the events (each leaves the GPU
             # idle for microseconds between kernels)
@@ -593,6 +602,7 @@ def main(argv=None):
                    "path": args.path,
                    "lanes_per_row": list(bsgd.bsgd_plan_lanes(plan)), "overlap": args.overlap,
                    "staged": args.staged,
+                   "launch": list(bsgd.bsgd_state_launch(st)),
                    "mu": "fixed from " + args.mu_file if fixed_mu is not None
                    else (f"Lanczos bidiagonalisation ({args.umax_steps} steps"
                          + (", products on the tile-sliced store)" if fused else ")")

@@ -440,7 +440,7 @@ bsgd_status bsgd_state_set_prox_schedule(bsgd_state* state, int schedule);
  * bsgd_state_autotune chooses both by timing them on this state (every epoch
  * of Algorithm 1 runs the same kernels, so a few epochs measure a choice):
  * `reps` epochs per candidate with the given mu, lam and prox_iters (pass wavefronts 4 or 8 for one RHS, 8 or 16 for several; prox
- * split 5 or 10 in 2-D, 1, 2 or 3 for volumes).  It runs on zero data and
+ * split 5, 7 or 10 in 2-D, 1, 2 or 3 for volumes).  It runs on zero data and
  * must be called before bsgd_state_init (it overwrites the state's vectors
  * and leaves the state uninitialised); choice (host, 2 ints, may be NULL)
  * receives the pass wavefronts (0 without a store) and the split (0 when lam

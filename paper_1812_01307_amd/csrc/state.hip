@@ -1017,12 +1017,12 @@ extern "C" bsgd_status bsgd_state_autotune(bsgd_state* st, float mu, float lam, 
     }
   }
   st->pass_waves = best_w;
-  // the prox: most FGP iterations per launch (2-D: 5 or 10; volumes: 1, 2 or 3)
+  // the prox: most FGP iterations per launch (2-D: 5, 7 or 10; volumes: 1, 2 or 3)
   int best_s = 0;
   if (lam > 0.f && st->prox_schedule != kFgpPerIteration) {
-    const int two[2] = {5, 10}, three[3] = {1, 2, 3};
+    const int two[3] = {5, 7, 10}, three[3] = {1, 2, 3};
     const int* cand = volume ? three : two;
-    const int nc = volume ? 3 : 2;
+    const int nc = 3;
     double best = 1e300;
     for (int i = 0; i < nc; ++i) {
       st->prox_split = cand[i];

@@ -546,9 +546,11 @@ void bsgd_graph_destroy(bsgd_graph* graph);
  * which holds for rays (5 bytes per entry with FP32 values, 3 with FP16),
  * else 16-bit addresses (flag BSGD_FUSED_WIDE forces them).  One workgroup
  * per (tile, chunk) keeps the tile of x in LDS for the row sums of A x and
- * adds the terms of A^T r into the tile in LDS as 64-bit fixed-point numbers
- * (integer additions, exact in any order; the scale is set from max |r| so
- * that a term's rounding is below 2^-46 of the largest possible sum);
+ * adds the terms of A^T r into the tile in LDS as 32-bit fixed-point numbers
+ * (integer additions, exact in any order; the scale is set from max |r|, the
+ * largest column sum of |A| and the largest |a| so that sums stay below 2^30
+ * and terms below 2^21: a term's rounding is below 2^-31 of the largest
+ * possible sum);
  * per-segment sums of A x and per-chunk sums of A^T r are added in a fixed
  * order by a second kernel, so results are bitwise reproducible for a given
  * store (and differ from the row kernels by summation order only).  FP16

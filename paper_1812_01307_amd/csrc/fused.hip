@@ -31,8 +31,8 @@
 // wavefronts takes every W-th slice of the unit, gathers x from LDS for the
 // row sums (one partial per segment, stored at [rank][ray], rank = the
 // segment's place among the ray's segments) and adds a * r[rho] into the
-// tile's g in LDS.  Those adds are 64-bit integer LDS atomics on fixed-point
-// terms (see to_fixed): exact and order-free, so the lanes and wavefronts
+// tile's g in LDS.  Those adds are 32-bit integer LDS atomics on fixed-point
+// terms (see term32): exact and order-free, so the lanes and wavefronts
 // that meet on a pixel need no ordering (FP32 LDS atomics measured about 4x
 // slower than the whole pass on gfx950).  The unit's partial of g is
 // converted back to FP32 once.  A second kernel adds each ray's segment
@@ -494,34 +494,29 @@ static unsigned grid_for(int64_t n) {
 // ---------------------------------------------------------------------------
 // The pass
 // ---------------------------------------------------------------------------
-// Fixed-point terms for the LDS sums of A^T r.  Scale 2^e, e from the largest
-// |r| (rmax, computed by the kernel that wrote r) and the largest column sum
-// of |A| (smax), so that every partial sum of a pixel stays below 2^46 in
-// magnitude.  A term t = rint(a * r * 2^e) is formed with one FP64 fma:
-// d = a * (r 2^e) + 1.5 * 2^52 is exact up to that rounding and its bit
-// pattern is bits(1.5 * 2^52) + t.  The bit patterns are added as 64-bit
-// integers with LDS atomics: bits(1.5 * 2^52) is a multiple of 2^48, so the
-// low 48 bits of the total are those of sum(t), which the flush sign-extends.
-// Integer addition is exact and associative, so the order of the atomics
-// does not change the result; the rounding of a term is below 2^-46 of the
-// largest possible sum.
-constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
+// Fixed-point terms for the LDS sums of A^T r.  A term t = rint(a r 2^e) is
+// added as a 32-bit integer; the scale 2^e comes from the largest |r| (rmax,
+// gathered by the kernel that wrote r), the largest column sum of |A|
+// (smax) and the largest |a| (amax): every sum of a pixel stays below 2^30 in
+// magnitude and every term below 2^21.  The latter lets one FP32 FMA round a
+// term: f = a (r 2^e) + 1.5 * 2^23 is rounded once, and its bit pattern minus
+// that of 1.5 * 2^23 is t.  Integer addition is exact and associative, so the
+// order of the atomics does not change the result; the rounding of a term is
+// below 2^-31 of the largest possible sum.
+constexpr float kMagic32 = 12582912.0f;  // 1.5 * 2^23
+constexpr int kMagic32Bits = 0x4B400000;
 
-__device__ __forceinline__ int fixed_exponent(double smax, float rmax) {
-  const double b = smax * (double)rmax;
+__device__ __forceinline__ int fixed_exponent32(double smax, double amax, float rmax) {
+  const double b = smax * (double)rmax, t = amax * (double)rmax;
   if (!(b > 0.0) || !isfinite(b)) return 0;
-  int E;
-  (void)frexp(b, &E);  // b < 2^E
-  return min(max(46 - E, -1000), 1000);
+  int Es, Et;
+  (void)frexp(b, &Es);  // b < 2^Es
+  (void)frexp(t, &Et);
+  return min(max(min(30 - Es, 21 - Et), -200), 200);
 }
 
-__device__ __forceinline__ unsigned long long to_fixed(float a, double rs) {
-  return (unsigned long long)__double_as_longlong(fma((double)a, rs, kMagic));
-}
-
-__device__ __forceinline__ double from_fixed(unsigned long long acc, double inv) {
-  const long long t = (long long)(acc << 16) >> 16;  // sign-extend the low 48 bits
-  return (double)t * inv;
+__device__ __forceinline__ int term32(float a, float rs) {
+  return __float_as_int(fmaf(a, rs, kMagic32)) - kMagic32Bits;
 }
 
 struct SliceMeta {
@@ -579,9 +574,8 @@ __device__ __forceinline__ void load_group(const void* __restrict__ col,
 // narrow columns are decoded from the lane's running address ap (groups of
 // a lane are decoded in order)
 template <bool NARROW, int MODE>
-__device__ __forceinline__ void group_step(const float* xs, unsigned long long* gs,
-                                           const ColRaw<NARROW>& raw, const float (&a)[4],
-                                           double rs, float& z, int& ap) {
+__device__ __forceinline__ void group_step(const float* xs, int* gs, const ColRaw<NARROW>& raw,
+                                           const float (&a)[4], float rs, float& z, int& ap) {
   int c[4];
   if constexpr (NARROW) {
     c[0] = ap + (int)(raw & 255u);
@@ -596,7 +590,7 @@ __device__ __forceinline__ void group_step(const float* xs, unsigned long long* 
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     if constexpr (MODE != kPassAt) z = fmaf(a[t], xs[c[t]], z);
-    if constexpr (MODE != kPassA) atomicAdd(&gs[c[t]], to_fixed(a[t], rs));
+    if constexpr (MODE != kPassA) atomicAdd(&gs[c[t]], term32(a[t], rs));
   }
 }
 
@@ -616,9 +610,10 @@ __global__ __launch_bounds__(64 * W) void k_fused(
     const uint16_t* __restrict__ sbase, const void* __restrict__ col,
     const VT* __restrict__ val, const float* __restrict__ x,
     const float* __restrict__ r, const unsigned* __restrict__ rmax_in, unsigned* rmax_zero,
-    float* __restrict__ zp, float* __restrict__ gp, int64_t r_int, int64_t c_int, double smax) {
+    float* __restrict__ zp, float* __restrict__ gp, int64_t r_int, int64_t c_int, double smax,
+    double amax) {
   __shared__ float xs[kFTA];
-  __shared__ unsigned long long gs[kFTA];
+  __shared__ int gs[kFTA];
   constexpr int NT = 64 * W;
   const int u = uorder[blockIdx.x];  // largest units first
   const int tile = u / g.Q, q = u - tile * g.Q;
@@ -634,7 +629,7 @@ __global__ __launch_bounds__(64 * W) void k_fused(
   if (rmax_zero && blockIdx.x == 0 && tid == 0) *rmax_zero = 0u;
   for (int i = tid; i < kFTA; i += NT) {
     if constexpr (MODE != kPassAt) xs[i] = 0.f;
-    if constexpr (MODE != kPassA) gs[i] = 0ull;
+    if constexpr (MODE != kPassA) gs[i] = 0;
   }
   __syncthreads();
   if constexpr (MODE != kPassAt)
@@ -646,8 +641,11 @@ __global__ __launch_bounds__(64 * W) void k_fused(
             x[xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w];
     }
   const float rmax = MODE == kPassA ? 0.f : __uint_as_float(*rmax_in);
-  const int e = fixed_exponent(smax, rmax);
-  const double scale = ldexp(1.0, e);
+  const int e = fixed_exponent32(smax, amax, rmax);
+  // a residual with an infinite or NaN entry has no fixed-point scale: its
+  // terms are left out and the partials carry a NaN instead, so the
+  // divergence reaches x and the next residual
+  const bool rbad = !(rmax <= 3.40282347e38f);
   __syncthreads();
   // the next slice's table entries and its r value load while a slice streams
   int k = 0, s = snake<W>(s0, 0, wv);
@@ -656,7 +654,7 @@ __global__ __launch_bounds__(64 * W) void k_fused(
   while (s < s1) {
     const int sn = snake<W>(s0, k + 1, wv);
     const SliceMeta nxt = slice_meta(sray, srank, sbase, sng, soff, sn, s1, lane);
-    const double rs = (double)rcur * scale;
+    const float rs = rbad ? 0.f : ldexpf(rcur, e);
     const int64_t base = cur.base;
     const int ng = cur.ng;
     float z0 = 0.f, z1 = 0.f;
@@ -707,18 +705,13 @@ __global__ __launch_bounds__(64 * W) void k_fused(
   }
   __syncthreads();
   if constexpr (MODE == kPassA) return;
-  const double inv = ldexp(1.0, -e);
-  // a residual with an infinite or NaN entry has no fixed-point scale: its
-  // terms would drop out of the sums, so the partials carry a NaN instead and
-  // the divergence reaches x and the next residual
-  const bool rbad = !(rmax <= 3.40282347e38f);
   for (int i = tid; i < kFT * kFT; i += NT) {
     const int b = i >> 6, w = i & 63;
     const int tr8 = ftr * 8 + (b >> 3), tc8 = ftc * 8 + (b & 7);
     if (tr8 < g.Ht && tc8 < g.Wt) {
       const int a = (((b >> 3) << 3) + (w >> 3)) * kFTS + ((b & 7) << 3) + (w & 7);
       gp[(int64_t)q * c_int + xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w] =
-          rbad ? __uint_as_float(0x7fc00000u) : (float)from_fixed(gs[a], inv);
+          rbad ? __uint_as_float(0x7fc00000u) : ldexpf((float)gs[a], -e);
     }
   }
 }
@@ -745,25 +738,6 @@ __global__ __launch_bounds__(64 * W) void k_fused(
 // ---------------------------------------------------------------------------
 constexpr int kMrC = 4;      // RHS per workgroup
 constexpr int kXcds = 8;     // workgroups are dealt to the XCDs round robin
-constexpr float kMagic32 = 12582912.0f;  // 1.5 * 2^23
-constexpr int kMagic32Bits = 0x4B400000;
-
-// Scale exponent of the 32-bit fixed-point sums: every sum below 2^30
-// (smax |r| 2^e < 2^30) and every term below 2^21 (amax |r| 2^e < 2^21), so
-// that t = rint(a r 2^e) comes out of one FMA with 1.5 * 2^23 as the low bits
-// of the float's pattern.
-__device__ __forceinline__ int fixed_exponent32(double smax, double amax, float rmax) {
-  const double b = smax * (double)rmax, t = amax * (double)rmax;
-  if (!(b > 0.0) || !isfinite(b)) return 0;
-  int Es, Et;
-  (void)frexp(b, &Es);  // b < 2^Es
-  (void)frexp(t, &Et);
-  return min(max(min(30 - Es, 21 - Et), -200), 200);
-}
-
-__device__ __forceinline__ int term32(float a, float rs) {
-  return __float_as_int(fmaf(a, rs, kMagic32)) - kMagic32Bits;
-}
 
 template <typename VT, bool NARROW, int W>
 __global__ __launch_bounds__(64 * W) void k_fused_mr(
@@ -1113,11 +1087,11 @@ static void launch_fused_m(const bsgd_fused& F, const VT* val, const float* x, c
   if (F.narrow)
     k_fused<VT, true, W, MODE><<<(unsigned)F.g.units(), 64 * W, 0, s>>>(
         F.g, F.uorder, F.sbeg, F.sng, F.soff, F.sray, F.srank, F.sbase, F.col8, val, x, r,
-        rmax_in, rmax_zero, zp, gp, F.plan->L.r_int, F.plan->L.c_int, F.smax);
+        rmax_in, rmax_zero, zp, gp, F.plan->L.r_int, F.plan->L.c_int, F.smax, F.amax);
   else
     k_fused<VT, false, W, MODE><<<(unsigned)F.g.units(), 64 * W, 0, s>>>(
         F.g, F.uorder, F.sbeg, F.sng, F.soff, F.sray, F.srank, nullptr, F.col, val, x, r,
-        rmax_in, rmax_zero, zp, gp, F.plan->L.r_int, F.plan->L.c_int, F.smax);
+        rmax_in, rmax_zero, zp, gp, F.plan->L.r_int, F.plan->L.c_int, F.smax, F.amax);
 }
 
 template <typename VT, int W>
@@ -1600,7 +1574,8 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, unsi
     std::memcpy(&am, &smax_bits[1], sizeof(am));
     F->amax = am;
     // FP16 values round |a| up by at most 2^-11 relative: sums stay below
-    // 2^46 * (1 + 2^-11), inside the 2^47 that the 48-bit window allows
+    // 2^30 (1 + 2^-11) < 2^31 and terms below 2^21 (1 + 2^-11) < 2^22, where
+    // the FMA rounding of a term still holds
     F->smax = sm;
   }
   F->slices = fc.slices;

@@ -150,7 +150,7 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=None, help="override the workload's epoch count")
     ap.add_argument("--umax", default="lanczos", choices=["lanczos", "power"],
                     help="u_max for the step size: Lanczos bidiagonalisation or power iteration")
-    ap.add_argument("--umax-steps", type=int, default=10,
+    ap.add_argument("--umax-steps", type=int, default=6,
                     help="Lanczos steps (each one product with A and one with A^T)")
     ap.add_argument("--power-iters", type=int, default=30)
     ap.add_argument("--cpu-epochs", type=int, default=20,
@@ -280,6 +280,10 @@ def main(argv=None):
         print(f"[bench] autotuned launch {tuned}", file=sys.stderr, flush=True)
 
     selected = args.method == "selected"
+    if fused and args.umax == "lanczos" and not selected and args.staged in ("none", "fwd"):
+        # the tile-sliced store serves both products (and the Lanczos ones):
+        # the plan keeps no block store of A^T
+        flags |= bsgd.BSGD_PLAN_FWD_ONLY
     lam_run = 0.0 if args.method == "gd" else prob.lam
     n_updates = epochs
     if selected:
@@ -600,6 +604,7 @@ def main(argv=None):
                    "method": args.method,
                    "nnz": nnz, "epochs_per_step": epochs,
                    "path": args.path,
+                   "block_stores": "A" if flags & bsgd.BSGD_PLAN_FWD_ONLY else "A and A^T",
                    "lanes_per_row": list(bsgd.bsgd_plan_lanes(plan)), "overlap": args.overlap,
                    "staged": args.staged,
                    "launch": list(bsgd.bsgd_state_launch(st)),
@@ -659,6 +664,9 @@ def run_volume(args, np, torch, synth, bsgd):
 
     fused = args.path == "fused"
     shape = {}
+
+    if fused:
+        flags |= bsgd.BSGD_PLAN_FWD_ONLY  # the tile-sliced store serves both products
 
     def job(graph, n_epochs=epochs, timed=False):
         plan = bsgd.bsgd_plan_create(A, At, prob.M, prob.N, prob.row_off, prob.col_off, prob.H,
@@ -777,6 +785,7 @@ def run_volume(args, np, torch, synth, bsgd):
                                f"setup S0+S0' included",
                    "nnz": nnz, "slices": S, "epochs_per_step": epochs,
                    "graph": graph, "path": args.path,
+                   "block_stores": "A" if flags & bsgd.BSGD_PLAN_FWD_ONLY else "A and A^T",
                    "launch": (list(shape["tuned"]) if "tuned" in shape
                               else [args.mr_waves, 0]),
                    "kernel_timing": "events on one eager 20-epoch job after the timed region"},

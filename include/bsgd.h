@@ -59,6 +59,17 @@ typedef enum { BSGD_VAL_F32 = 0, BSGD_VAL_F16 = 1 } bsgd_valtype;
 #define BSGD_PLAN_STAGED_FWD 4u /* also build the staged form of the forward store (A) */
 #define BSGD_PLAN_STAGED_BWD 8u /* also build the staged form of the backward store (A^T) */
 #define BSGD_PLAN_STAGED 12u    /* both staged forms */
+/*
+ * Build the block store of A only, not that of A^T: for plans whose epochs
+ * run on the tile-sliced store (bsgd_fused_create), which yields A x and
+ * A^T r from one read of A.  Calls that need the A^T store return
+ * BSGD_ERR_UNSUPPORTED (bsgd_backproject, bsgd_backproject_block,
+ * bsgd_tile_export with transposed = 1, bsgd_power_umax, bsgd_lanczos_umax,
+ * block-selection states, and bsgd_run_epochs unless the state has a
+ * tile-sliced store attached and is not an ISTA state with nrhs > 1).
+ * Excludes BSGD_PLAN_STAGED_BWD.
+ */
+#define BSGD_PLAN_FWD_ONLY 16u
 
 /*
  * A sparse matrix in CSR form, in device memory.  Columns must be strictly
@@ -110,13 +121,17 @@ bsgd_status bsgd_plan_workspace_size(int64_t nrows, int64_t ncols, int64_t nnz, 
  *           are interleaved bin by bin, pixels are stored in 8 x 8 tiles, so
  *           the gathers of the products stay within few cache lines); every
  *           vector crossing this interface is in natural order.
- *   flags   BSGD_PLAN_F16, BSGD_PLAN_AUTOTUNE, BSGD_PLAN_STAGED_FWD and/or
- *           BSGD_PLAN_STAGED_BWD.
+ *   flags   BSGD_PLAN_F16, BSGD_PLAN_AUTOTUNE, BSGD_PLAN_STAGED_FWD,
+ *           BSGD_PLAN_STAGED_BWD and/or BSGD_PLAN_FWD_ONLY.  With
+ *           BSGD_PLAN_FWD_ONLY only the row pointers and values of At are
+ *           read (row_ptr is validated; its columns are not).
  *
  * The store keeps every block A_{I_i}^{J_j} and its transpose addressable
  * (bsgd_tile_export) in a row-interleaved layout: the entries of ray rho for
  * column block j follow those for block j-1, and likewise for each pixel's
- * row of A^T over the row blocks.  The A/At arrays are only read during the
+ * row of A^T over the row blocks.  It also keeps the largest column sum of
+ * |A| and the largest |a| (FP64, from At), which bound the fixed-point sums
+ * of the tile-sliced store.  The A/At arrays are only read during the
  * call.  Synchronises `stream` at the end (to validate the input: sorted
  * columns, indices in range, row_ptr consistent with nnz).
  * *out is released with bsgd_plan_destroy; the workspace must outlive it.

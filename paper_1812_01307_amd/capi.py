@@ -32,6 +32,7 @@ BSGD_PLAN_AUTOTUNE = 2
 BSGD_PLAN_STAGED_FWD = 4
 BSGD_PLAN_STAGED_BWD = 8
 BSGD_PLAN_STAGED = 12
+BSGD_PLAN_FWD_ONLY = 16
 BSGD_LAUNCH_NT = 128
 BSGD_STATE_VOLUME = 1
 BSGD_STATE_BLOCK_SELECT = 2
@@ -217,16 +218,19 @@ def bsgd_plan_create(A, At, M, N, row_off, col_off, H, W, D=1, view_len=0, flags
                      stream=None) -> Plan:
     """A, At: (row_ptr int64, col int32, val float32) device tensor triples plus shapes.
 
-    A = (nrows, ncols, row_ptr, col, val); At likewise for the transpose.
+    A = (nrows, ncols, row_ptr, col, val); At likewise for the transpose.  With
+    BSGD_PLAN_FWD_ONLY the transpose's column array may be None (only its row
+    pointers and values are read).
     """
     nrows, ncols, rp, cl, vl = A
     tn, tc, trp, tcl, tvl = At
     for t, dt in ((rp, torch.int64), (cl, torch.int32), (vl, torch.float32),
                   (trp, torch.int64), (tcl, torch.int32), (tvl, torch.float32)):
-        if t.dtype != dt:
+        if t is not None and t.dtype != dt:
             raise ValueError(f"CSR array has dtype {t.dtype}, expected {dt}")
     a = bsgd_csr(nrows, ncols, cl.numel(), _ptr(rp), _ptr(cl), _ptr(vl))
-    at = bsgd_csr(tn, tc, tcl.numel(), _ptr(trp), _ptr(tcl), _ptr(tvl))
+    at = bsgd_csr(tn, tc, tvl.numel(), _ptr(trp), _ptr(tcl) if tcl is not None else None,
+                  _ptr(tvl))
     nbytes = bsgd_plan_workspace_size(nrows, ncols, cl.numel(), M, N, H, W, D, view_len, flags)
     ws = _ws(nbytes, rp.device)
     ro = (_i64 * (M + 1))(*[int(v) for v in row_off])

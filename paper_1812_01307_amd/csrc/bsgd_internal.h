@@ -40,6 +40,15 @@ void clear_error();
     }                                                                                  \
   } while (0)
 
+// The call needs the block store of A^T, which a BSGD_PLAN_FWD_ONLY plan lacks.
+#define BSGD_NEED_BWD(plan, what)                                                      \
+  do {                                                                                 \
+    if ((plan)->flags & BSGD_PLAN_FWD_ONLY) {                                          \
+      ::bsgd::set_error("%s needs the A^T block store (a FWD_ONLY plan)", what);     \
+      return BSGD_ERR_UNSUPPORTED;                                                     \
+    }                                                                                  \
+  } while (0)
+
 #define BSGD_LAUNCH_CHECK()                                                            \
   do {                                                                                 \
     hipError_t e_ = hipGetLastError();                                                 \
@@ -194,6 +203,9 @@ struct bsgd_plan {
                                      // bsgd_fused_workspace_size
   int64_t* scan_tmp = nullptr;    // block sums for scans
   int* err = nullptr;             // validation flags
+  unsigned long long* colmax = nullptr;  // 2 words: column-sum / max |a| bits while building
+  double smax = 0.0;              // largest column sum of |A| (FP64)
+  double amax = 0.0;              // largest |a|
   int64_t* seg_dev = nullptr;     // segment bounds staged for the fill kernel
   float* vin = nullptr;           // max(r_int, c_int): permuted inputs of step-level calls
   float* vaux = nullptr;          // max(r_int, c_int): second permuted input

@@ -163,6 +163,8 @@ __device__ __forceinline__ void decode_pixel(const TileGeom& g, int64_t cp, int&
 // pixel order, so the band key G never decreases along the row).  Lane f
 // keeps, for the current band, the rank and running length of the segment
 // in tile column f.  Segments are ranked in the order the ray enters them.
+//   vis.group(rank)                     before the entries of one segment in
+//                                      a batch (called by the whole wavefront)
 //   vis.entry(rank, j, lds_addr, e, prev)  entry e is the j-th of segment
 //                                      `rank`; prev = the segment's previous
 //                                      address (-1 for j = 0)
@@ -176,11 +178,15 @@ __device__ void walk_ray(const TileGeom& g, const int32_t* __restrict__ col, int
   const int lane = threadIdx.x & 63;
   const uint64_t below = (1ull << lane) - 1ull;
   int Gcur = -1, cnt = 0, rank = -1, nseen = 0, first = 0, last = 0;
+  int32_t cnext = lane < len ? col[beg + lane] : 0;
   for (int64_t c0 = 0; c0 < len; c0 += 64) {
     const int64_t e = c0 + lane;
     const bool valid = e < len;
+    const int32_t cp = cnext;
+    // the next batch's columns load while this one is walked
+    if (e + 64 < len) cnext = col[beg + e + 64];
     int G = 0x7fffffff, f = 0, a = 0;
-    if (valid) decode_pixel(g, col[beg + e], G, f, a);
+    if (valid) decode_pixel(g, cp, G, f, a);
     bool done = !valid;
     uint64_t live;
     while ((live = __ballot(!done)) != 0ull) {
@@ -210,6 +216,7 @@ __device__ void walk_ray(const TileGeom& g, const int32_t* __restrict__ col, int
         const int alast = __shfl(a, 63 - __builtin_clzll(mm));
         const int afirst = __shfl(a, l2);
         if (rk < 0) rk = nseen++;
+        vis.group(rk);  // rk is the same in every lane
         if (lane == fl) {
           if (base == 0) first = afirst;
           rank = rk;
@@ -239,6 +246,7 @@ struct VisCount {
   int64_t* ncross;
   int32_t *maxc, *maxlen, *maxstep;
   int mlen = 0, mstep = 0;
+  __device__ void group(int) {}
   __device__ void entry(int, int, int a, int64_t, int prev) {
     if (prev >= 0) mstep = max(mstep, a - prev);
   }
@@ -280,6 +288,7 @@ struct VisPairs {
   int32_t* idx;
   int32_t* pray;
   uint16_t* pbase;
+  __device__ void group(int) {}
   __device__ void entry(int, int, int, int64_t, int) {}
   __device__ void close(int G, int f, int len, int rank, int first) {
     if (rank < 0) return;
@@ -293,11 +302,23 @@ struct VisPairs {
   __device__ void finish(int) {}
 };
 
+// Entry j of the ray's segment `rank` goes to dst + (j / 4) * 256 + j % 4,
+// dst and the slice's group count from the segment's packed destination.
+// Lane i holds the packed destination of the ray's segment i (loaded once
+// per ray); a batch's segment takes it from that lane's register.
+constexpr int kDstShift = 11;  // a segment has at most 4096 entries: ng <= 1024
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
+  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 struct VisFill {
-  int64_t k;
-  const int64_t* poff;
-  const int32_t* pos;
-  const int64_t* soff;
+  int64_t pk;    // the ray's first segment index
+  int64_t dpre;  // this lane's segment's packed destination (lane < segments)
+  int64_t d;     // the current segment's
+  const int64_t* pdst;
   const float* vsrc;
   const __half* v16src;
   uint16_t* col;
@@ -305,15 +326,13 @@ struct VisFill {
   float* val;
   __half* val16;
   int* err;
-  __device__ void entry(int rk, int j, int a, int64_t e, int prev) {
-    const int32_t P = pos[poff[k] + rk];
-    const int64_t s = P >> 6;
-    const int l = P & 63;
-    const int64_t addr = soff[s] + (int64_t)(j >> 2) * 256 + l * 4 + (j & 3);
-    if (addr >= soff[s + 1]) {
+  __device__ void group(int rk) { d = rk < 64 ? readlane64(dpre, rk) : pdst[pk + rk]; }
+  __device__ void entry(int, int j, int a, int64_t e, int prev) {
+    if (j >= 4 * (int)(d & ((1 << kDstShift) - 1))) {
       atomicOr(err, 1);
       return;
     }
+    const int64_t addr = (d >> kDstShift) + (int64_t)(j >> 2) * 256 + (j & 3);
     if (col8)
       col8[addr] = (uint8_t)(j == 0 ? 0 : a - prev);
     else
@@ -332,9 +351,18 @@ __global__ __launch_bounds__(256) void k_fz_walk(
     const int32_t* __restrict__ col, const float* __restrict__ vsrc,
     const __half* __restrict__ v16src, int64_t r_int, int64_t* ncross, int32_t* maxc,
     int32_t* maxlen, int32_t* maxstep, const int64_t* poff, uint64_t* key, int32_t* idx,
-    int32_t* pray, uint16_t* pbase, const int32_t* pos, const int64_t* soff, uint16_t* ocol,
-    uint8_t* ocol8, float* oval, __half* oval16, int* err) {
-  const int64_t k = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    int32_t* pray, uint16_t* pbase, const int64_t* pdst, uint16_t* ocol, uint8_t* ocol8,
+    float* oval, __half* oval16, int* err) {
+  int64_t b = blockIdx.x;
+  if constexpr (MODE == 2) {
+    // workgroups are dealt to the 8 XCDs in turn; the fill gives each XCD a
+    // contiguous range of rays instead (the grid is a multiple of 8), so the
+    // few rays whose segments share a line of the store (neighbouring bins
+    // of one view) write it through one L2, which merges their partial writes
+    const int64_t per = gridDim.x / 8;
+    b = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  }
+  const int64_t k = (b * 256 + threadIdx.x) >> 6;
   if (k >= r_int) return;  // uniform per wavefront
   const int64_t beg = ptr[k];
   const int64_t len = seg[k * (nseg + 1) + nseg];
@@ -346,7 +374,10 @@ __global__ __launch_bounds__(256) void k_fz_walk(
     VisPairs v{g, k, q, poff, key, idx, pray, pbase};
     walk_ray(g, col, beg, len, v);
   } else {
-    VisFill v{k, poff, pos, soff, vsrc, v16src, ocol, ocol8, oval, oval16, err};
+    const int64_t pk = poff[k], nr = poff[k + 1] - pk;
+    const int lane = threadIdx.x & 63;
+    const int64_t dpre = lane < nr ? pdst[pk + lane] : 0;
+    VisFill v{pk, dpre, 0, pdst, vsrc, v16src, ocol, ocol8, oval, oval16, err};
     walk_ray(g, col, beg, len, v);
   }
 }
@@ -408,6 +439,19 @@ __global__ void k_fz_place(const uint64_t* __restrict__ keys, const int32_t* __r
   }
 }
 
+// Packed destination of each segment once the slice offsets are known: the
+// first word of its lane, shifted, or-ed with the slice's group count.
+__global__ void k_fz_dst(const int32_t* __restrict__ pos, int64_t npairs,
+                         const int64_t* __restrict__ soff, const int32_t* __restrict__ sng,
+                         int64_t* __restrict__ pdst) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npairs;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t P = pos[p];
+    const int64_t s = P >> 6;
+    pdst[p] = ((soff[s] + (P & 63) * 4) << kDstShift) | sng[s];
+  }
+}
+
 __global__ void k_fz_init_slots(int32_t* __restrict__ sray, int32_t* __restrict__ slen,
                                 uint16_t* __restrict__ sbase, int64_t nslots) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nslots;
@@ -444,34 +488,6 @@ __global__ void k_fz_pad(const int32_t* __restrict__ slen, const int32_t* __rest
       if (val16) val16[a] = __float2half_rn(0.f);
     }
   }
-}
-
-// Largest column sum of |A| (rows of the transposed store) into out[0] and the
-// largest |a| into out[1], FP64, as bit patterns of non-negative doubles
-// (which order like the values).
-__global__ __launch_bounds__(256) void k_fz_colsum(const int64_t* __restrict__ ptr,
-                                                   const int32_t* __restrict__ seg, int nseg,
-                                                   const float* __restrict__ val, int64_t n,
-                                                   unsigned long long* __restrict__ out) {
-  const int64_t k = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (k >= n) return;  // uniform per wavefront
-  const int64_t beg = ptr[k], len = seg[k * (nseg + 1) + nseg];
-  double acc = 0.0, amax = 0.0;
-  for (int64_t e = lane; e < len; e += 64) {
-    const double a = fabs((double)val[beg + e]);
-    acc += a;
-    amax = fmax(amax, a);
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    acc += __shfl_xor(acc, off);
-    amax = fmax(amax, __shfl_xor(amax, off));
-  }
-  const unsigned long long bits = (unsigned long long)__double_as_longlong(acc);
-  const unsigned long long abits = (unsigned long long)__double_as_longlong(amax);
-  if (lane == 0 && bits > __atomic_load_n(out, __ATOMIC_RELAXED)) atomicMax(out, bits);
-  if (lane == 0 && abits > __atomic_load_n(out + 1, __ATOMIC_RELAXED)) atomicMax(out + 1, abits);
 }
 
 __global__ void k_i64_to_i32(const int64_t* __restrict__ in, int32_t* __restrict__ out,
@@ -1281,8 +1297,7 @@ static bsgd_status fused_count(const bsgd_plan* p, const TileGeom& g, bool wide,
   k_fz_walk<0><<<blocks, 256, 0, s>>>(g, p->fwd.ptr, p->fwd.seg, p->fwd.nseg, p->fwd.col,
                                       nullptr, nullptr, L.r_int, p->scratch64, words, words + 1,
                                       words + 2, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                      nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                      nullptr);
+                                      nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
   BSGD_LAUNCH_CHECK();
   BSGD_HIP(exclusive_scan_i64(p->scratch64, p->scratch64, L.r_int, p->scan_tmp, s));
   int32_t hw[3] = {0, 0, 0};
@@ -1317,8 +1332,8 @@ struct FusedTemps {
   int32_t *idx = nullptr, *idx2 = nullptr, *pray = nullptr, *slen = nullptr, *pos = nullptr;
   uint16_t* pbase = nullptr;
   int64_t *first = nullptr, *last = nullptr, *sng256 = nullptr, *scan_tmp = nullptr;
+  int64_t* pdst = nullptr;
   int* err = nullptr;
-  unsigned long long* smax = nullptr;
   void* cub = nullptr;
   size_t cub_bytes = 0;
 };
@@ -1363,6 +1378,7 @@ static size_t fused_layout(const bsgd_plan* p, const TileGeom& g, const FusedCou
   T->key = cv.take<uint64_t>(np);
   T->key2 = cv.take<uint64_t>(np);
   T->pos = cv.take<int32_t>(np);
+  T->pdst = cv.take<int64_t>(np);
   T->idx = cv.take<int32_t>(np);
   T->idx2 = cv.take<int32_t>(np);
   T->pray = cv.take<int32_t>(np);
@@ -1373,7 +1389,6 @@ static size_t fused_layout(const bsgd_plan* p, const TileGeom& g, const FusedCou
   T->sng256 = cv.take<int64_t>(fc.slices + 1);
   T->scan_tmp = cv.take<int64_t>(scan_tmp_count(fc.slices) + 1);
   T->err = cv.take<int>(64);
-  T->smax = cv.take<unsigned long long>(2);
   size_t cub_bytes = 0;
   (void)hipcub::DeviceRadixSort::SortPairs(nullptr, cub_bytes, (const uint64_t*)nullptr,
                                            (uint64_t*)nullptr, (const int32_t*)nullptr,
@@ -1460,13 +1475,7 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, unsi
   };
   hipError_t e;
   e = hipMemsetAsync(T.err, 0, sizeof(int), stream);
-  if (e == hipSuccess) e = hipMemsetAsync(T.smax, 0, 2 * sizeof(unsigned long long), stream);
   if (e != hipSuccess) return hip_fail(e, "single-pass build set-up");
-  {
-    const Store& B = plan->bwd;
-    k_fz_colsum<<<(unsigned)((B.nrows * 64 + 255) / 256), 256, 0, stream>>>(
-        B.ptr, B.seg, B.nseg, B.val, B.nrows, T.smax);
-  }
   // per-ray segment offsets (plan->scratch64 holds their exclusive scan)
   k_i64_to_i32<<<grid_for(L.r_int + 1), 256, 0, stream>>>(plan->scratch64, F->poff, L.r_int + 1);
   k_fz_unit_init<<<grid_for(units), 256, 0, stream>>>(T.first, T.last, units);
@@ -1474,7 +1483,7 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, unsi
     k_fz_walk<1><<<wblocks, 256, 0, stream>>>(
         g, A.ptr, A.seg, A.nseg, A.col, nullptr, nullptr, L.r_int, nullptr, nullptr, nullptr,
         nullptr, plan->scratch64, T.key, T.idx, T.pray, T.pbase, nullptr, nullptr, nullptr,
-        nullptr, nullptr, nullptr, nullptr);
+        nullptr, nullptr, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "segment pass");
     size_t cb = T.cub_bytes;
@@ -1532,10 +1541,7 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, unsi
   if (e != hipSuccess) return hip_fail(e, "slice offsets");
   int64_t total = 0;
   int h_err = 0;
-  unsigned long long smax_bits[2] = {0, 0};
   e = hipMemcpyAsync(&total, F->soff + fc.slices, sizeof(int64_t), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(smax_bits, T.smax, sizeof(smax_bits), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(&h_err, T.err, sizeof(int), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -1550,10 +1556,11 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, unsi
     return fail(BSGD_ERR_INVALID);
   }
   if (fc.pairs > 0) {
-    k_fz_walk<2><<<wblocks, 256, 0, stream>>>(
+    k_fz_dst<<<grid_for(fc.pairs), 256, 0, stream>>>(T.pos, fc.pairs, F->soff, F->sng, T.pdst);
+    k_fz_walk<2><<<(wblocks + 7) / 8 * 8, 256, 0, stream>>>(
         g, A.ptr, A.seg, A.nseg, A.col, A.val, A.val16, L.r_int, nullptr, nullptr, nullptr,
-        nullptr, plan->scratch64, nullptr, nullptr, nullptr, nullptr, T.pos, F->soff, F->col,
-        F->col8, F->val, F->val16, T.err);
+        nullptr, plan->scratch64, nullptr, nullptr, nullptr, nullptr, T.pdst, F->col, F->col8,
+        F->val, F->val16, T.err);
     k_fz_pad<<<grid_for(nslots), 256, 0, stream>>>(T.slen, F->sng, F->soff, nslots, F->col,
                                                    F->col8, F->val, F->val16);
     e = hipGetLastError();
@@ -1568,16 +1575,12 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, unsi
   }
   F->pairs = fc.pairs;
   F->maxrank = fc.maxrank;
-  {
-    double sm, am;
-    std::memcpy(&sm, &smax_bits[0], sizeof(sm));
-    std::memcpy(&am, &smax_bits[1], sizeof(am));
-    F->amax = am;
-    // FP16 values round |a| up by at most 2^-11 relative: sums stay below
-    // 2^30 (1 + 2^-11) < 2^31 and terms below 2^21 (1 + 2^-11) < 2^22, where
-    // the FMA rounding of a term still holds
-    F->smax = sm;
-  }
+  // the plan's FP64 column sums of |A| and max |a|.  FP16 values round |a|
+  // up by at most 2^-11 relative: sums stay below 2^30 (1 + 2^-11) < 2^31
+  // and terms below 2^21 (1 + 2^-11) < 2^22, where the FMA rounding of a
+  // term still holds
+  F->smax = plan->smax;
+  F->amax = plan->amax;
   F->slices = fc.slices;
   F->entries = total;
   F->cap = fc.bound;

@@ -61,6 +61,35 @@ __global__ void k_check_rowptr(const int64_t* __restrict__ row_ptr, int64_t nrow
   }
 }
 
+// Largest sum of |a| over one row of At (a column sum of |A|) into out[0] and
+// the largest |a| into out[1], FP64, as bit patterns of non-negative doubles
+// (which order like the values).  One wavefront per row; lane-strided sums
+// combined by a butterfly, so the result does not depend on the launch.
+__global__ __launch_bounds__(256) void k_col_abs_sums(const int64_t* __restrict__ row_ptr,
+                                                      const float* __restrict__ val, int64_t n,
+                                                      unsigned long long* __restrict__ out) {
+  const int64_t k = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (k >= n) return;  // uniform per wavefront
+  const int64_t beg = row_ptr[k], len = row_ptr[k + 1] - beg;
+  double acc = 0.0, amax = 0.0;
+#pragma unroll 4
+  for (int64_t e = lane; e < len; e += 64) {
+    const double a = fabs((double)val[beg + e]);
+    acc += a;
+    amax = fmax(amax, a);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    acc += __shfl_xor(acc, off);
+    amax = fmax(amax, __shfl_xor(amax, off));
+  }
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(acc);
+  const unsigned long long abits = (unsigned long long)__double_as_longlong(amax);
+  if (lane == 0 && bits > __atomic_load_n(out, __ATOMIC_RELAXED)) atomicMax(out, bits);
+  if (lane == 0 && abits > __atomic_load_n(out + 1, __ATOMIC_RELAXED)) atomicMax(out + 1, abits);
+}
+
 template <bool FWD>
 __device__ __forceinline__ int64_t nat_row(const Layout& L, int64_t k) {
   return FWD ? L.ray_out(k) : L.pix_out(k);
@@ -117,6 +146,7 @@ __global__ __launch_bounds__(256) void k_fill(
   const int64_t dst = ptr[k];
   const int64_t plen = ptr[k + 1] - dst;
   int bad = 0;
+#pragma unroll 4
   for (int64_t q = lane; q < plen; q += 64) {
     int64_t c;
     float v;
@@ -192,7 +222,7 @@ static size_t plan_layout(bsgd_plan* p, void* ws, const Layout& L, int64_t nnz, 
   Carver cv(ws);
   const bool f16 = (flags & BSGD_PLAN_F16) != 0;
   carve_store(cv, p->fwd, L.r_int, nnz, N, f16);
-  carve_store(cv, p->bwd, L.c_int, nnz, M, f16);
+  if (!(flags & BSGD_PLAN_FWD_ONLY)) carve_store(cv, p->bwd, L.c_int, nnz, M, f16);
   if (flags & BSGD_PLAN_STAGED) {
     if (flags & BSGD_PLAN_STAGED_FWD) carve_staged(cv, p->sfwd, L, true, nnz, f16);
     if (flags & BSGD_PLAN_STAGED_BWD) carve_staged(cv, p->sbwd, L, false, nnz, f16);
@@ -204,11 +234,29 @@ static size_t plan_layout(bsgd_plan* p, void* ws, const Layout& L, int64_t nnz, 
   p->scratch64 = cv.take<int64_t>(mx + 1);
   p->scan_tmp = cv.take<int64_t>(scan_tmp_count(mx) + 1);
   p->err = cv.take<int>(64);
+  p->colmax = cv.take<unsigned long long>(2);
   p->seg_dev = cv.take<int64_t>((size_t)std::max(M, N) + 1);
   p->vin = cv.take<float>(mx);
   p->vaux = cv.take<float>(mx);
   p->vout = cv.take<float>(mx);
   return align_up(cv.off, kAlign);
+}
+
+// Validates row_ptr (ascending within [0, nnz], from 0 to nnz) before any
+// kernel indexes the entries through it.  Synchronises.
+static bsgd_status check_row_ptr(const bsgd_csr& src, int* err, hipStream_t s, const char* what) {
+  BSGD_HIP(hipMemsetAsync(err, 0, sizeof(int), s));
+  {
+    const int64_t blocks = std::min<int64_t>((src.nrows + 255) / 256, 65535);
+    k_check_rowptr<<<(unsigned)blocks, 256, 0, s>>>(src.row_ptr, src.nrows, src.nnz, err);
+    BSGD_LAUNCH_CHECK();
+  }
+  int h_err = 0;
+  BSGD_HIP(hipMemcpyAsync(&h_err, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  BSGD_HIP(hipStreamSynchronize(s));
+  BSGD_REQUIRE(!(h_err & kErrRowPtr),
+               "%s: row_ptr is not ascending within [0, nnz] or row_ptr[nrows] != nnz", what);
+  return BSGD_OK;
 }
 
 template <bool FWD>
@@ -221,17 +269,10 @@ static bsgd_status build_store(Store& st, const bsgd_csr& src, const Layout& L,
   st.lanes_per_row = heuristic_lanes(st.nnz, src.nrows);
   BSGD_HIP(hipMemcpyAsync(seg_dev, seg_off.data(), sizeof(int64_t) * seg_off.size(),
                           hipMemcpyHostToDevice, s));
-  BSGD_HIP(hipMemsetAsync(err, 0, sizeof(int), s));
   {
-    const int64_t blocks = std::min<int64_t>((src.nrows + 255) / 256, 65535);
-    k_check_rowptr<<<(unsigned)blocks, 256, 0, s>>>(src.row_ptr, src.nrows, src.nnz, err);
-    BSGD_LAUNCH_CHECK();
+    const bsgd_status rs = check_row_ptr(src, err, s, what);
+    if (rs != BSGD_OK) return rs;
   }
-  int h_err = 0;
-  BSGD_HIP(hipMemcpyAsync(&h_err, err, sizeof(int), hipMemcpyDeviceToHost, s));
-  BSGD_HIP(hipStreamSynchronize(s));
-  BSGD_REQUIRE(!(h_err & kErrRowPtr),
-               "%s: row_ptr is not ascending within [0, nnz] or row_ptr[nrows] != nnz", what);
   {
     const int64_t blocks = std::min<int64_t>((st.nrows + 255) / 256, 65535);
     k_padlen<FWD><<<(unsigned)blocks, 256, 0, s>>>(src.row_ptr, L, st.nrows, scratch);
@@ -245,6 +286,7 @@ static bsgd_status build_store(Store& st, const bsgd_csr& src, const Layout& L,
                                        st.nseg, err);
     BSGD_LAUNCH_CHECK();
   }
+  int h_err = 0;
   BSGD_HIP(hipMemcpyAsync(&h_err, err, sizeof(int), hipMemcpyDeviceToHost, s));
   BSGD_HIP(hipStreamSynchronize(s));
   BSGD_REQUIRE(!(h_err & kErrColRange), "%s: column index out of range", what);
@@ -492,8 +534,11 @@ extern "C" bsgd_status bsgd_plan_workspace_size(int64_t nrows, int64_t ncols, in
                                                 unsigned flags, size_t* bytes) {
   clear_error();
   BSGD_REQUIRE(bytes != nullptr, "bytes is NULL");
-  BSGD_REQUIRE((flags & ~(BSGD_PLAN_F16 | BSGD_PLAN_AUTOTUNE | BSGD_PLAN_STAGED)) == 0,
+  BSGD_REQUIRE((flags & ~(BSGD_PLAN_F16 | BSGD_PLAN_AUTOTUNE | BSGD_PLAN_STAGED |
+                          BSGD_PLAN_FWD_ONLY)) == 0,
                "unknown plan flags 0x%x", flags);
+  BSGD_REQUIRE(!((flags & BSGD_PLAN_FWD_ONLY) && (flags & BSGD_PLAN_STAGED_BWD)),
+               "BSGD_PLAN_FWD_ONLY excludes BSGD_PLAN_STAGED_BWD");
   bsgd_status st = check_sizes(nrows, ncols, nnz, M, N, H, W, D, view_len);
   if (st != BSGD_OK) return st;
   bsgd_plan tmp;
@@ -508,10 +553,15 @@ extern "C" bsgd_status bsgd_plan_create(const bsgd_csr* A, const bsgd_csr* At, i
                                         hipStream_t stream, bsgd_plan** out) {
   clear_error();
   BSGD_REQUIRE(A && At && row_off && col_off && workspace && out, "NULL argument");
-  BSGD_REQUIRE((flags & ~(BSGD_PLAN_F16 | BSGD_PLAN_AUTOTUNE | BSGD_PLAN_STAGED)) == 0,
+  BSGD_REQUIRE((flags & ~(BSGD_PLAN_F16 | BSGD_PLAN_AUTOTUNE | BSGD_PLAN_STAGED |
+                          BSGD_PLAN_FWD_ONLY)) == 0,
                "unknown plan flags 0x%x", flags);
+  BSGD_REQUIRE(!((flags & BSGD_PLAN_FWD_ONLY) && (flags & BSGD_PLAN_STAGED_BWD)),
+               "BSGD_PLAN_FWD_ONLY excludes BSGD_PLAN_STAGED_BWD");
   BSGD_REQUIRE(((uintptr_t)workspace % kAlign) == 0, "workspace must be 256-byte aligned");
-  BSGD_REQUIRE(A->row_ptr && A->col && A->val && At->row_ptr && At->col && At->val,
+  const bool fwd_only = (flags & BSGD_PLAN_FWD_ONLY) != 0;
+  BSGD_REQUIRE(A->row_ptr && A->col && A->val && At->row_ptr && (At->col || fwd_only) &&
+                   At->val,
                "NULL CSR array");
   BSGD_REQUIRE(At->nrows == A->ncols && At->ncols == A->nrows, "At is not shaped as A^T");
   BSGD_REQUIRE(At->nnz == A->nnz, "At has %lld entries, A has %lld", (long long)At->nnz,
@@ -544,9 +594,23 @@ extern "C" bsgd_status bsgd_plan_create(const bsgd_csr* A, const bsgd_csr* At, i
   plan_layout(p, workspace, p->L, A->nnz, M, N, flags);
   st = build_store<true>(p->fwd, *A, p->L, p->col_off, p->seg_dev, p->scratch64, p->scan_tmp,
                          p->err, stream, "A");
-  if (st == BSGD_OK)
+  if (st == BSGD_OK && !fwd_only)
     st = build_store<false>(p->bwd, *At, p->L, p->row_off, p->seg_dev, p->scratch64, p->scan_tmp,
                             p->err, stream, "At");
+  if (st == BSGD_OK && fwd_only) st = check_row_ptr(*At, p->err, stream, "At");
+  if (st == BSGD_OK) {
+    // column sums of |A| and max |a| from the (validated) rows of At
+    hipError_t e = hipMemsetAsync(p->colmax, 0, 2 * sizeof(unsigned long long), stream);
+    if (e == hipSuccess && At->nrows > 0) {
+      k_col_abs_sums<<<(unsigned)((At->nrows * 64 + 255) / 256), 256, 0, stream>>>(
+          At->row_ptr, At->val, At->nrows, p->colmax);
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+      set_error("column sums: %s", hipGetErrorString(e));
+      st = BSGD_ERR_HIP;
+    }
+  }
   if (st == BSGD_OK && p->sfwd.P > 0)
     st = build_staged<true>(p->sfwd, *A, p->L, p->stage_cnt, stream);
   if (st == BSGD_OK && p->sbwd.P > 0)
@@ -560,18 +624,22 @@ extern "C" bsgd_status bsgd_plan_create(const bsgd_csr* A, const bsgd_csr* At, i
     }
     float tf = 0.f, tb = 0.f;
     if (st == BSGD_OK) st = autotune_store(p->fwd, p->vin, p->vout, stream, &tf);
-    if (st == BSGD_OK) st = autotune_store(p->bwd, p->vaux, p->vout, stream, &tb);
+    if (st == BSGD_OK && !fwd_only) st = autotune_store(p->bwd, p->vaux, p->vout, stream, &tb);
     if (st == BSGD_OK && p->sfwd.built)
       st = autotune_staged(p->sfwd, p->vin, p->L.c_int, p->vout, p->stage_z, stream, tf);
     if (st == BSGD_OK && p->sbwd.built)
       st = autotune_staged(p->sbwd, p->vaux, p->L.r_int, p->vout, p->stage_z, stream, tb);
   }
   if (st == BSGD_OK) {
-    hipError_t e = hipStreamSynchronize(stream);
+    unsigned long long bits[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(bits, p->colmax, sizeof(bits), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
       set_error("plan build failed: %s", hipGetErrorString(e));
       st = BSGD_ERR_HIP;
     }
+    std::memcpy(&p->smax, &bits[0], sizeof(double));
+    std::memcpy(&p->amax, &bits[1], sizeof(double));
   }
   if (st != BSGD_OK) {
     delete p;
@@ -695,6 +763,7 @@ extern "C" bsgd_status bsgd_tile_export(const bsgd_plan* plan, int i, int j, int
   bsgd_status s = tile_rows(plan, i, j, transposed, &row0, &nrows, &segk, &col_base);
   if (s != BSGD_OK) return s;
   BSGD_REQUIRE(ptr && col && val, "NULL output");
+  if (transposed) BSGD_NEED_BWD(plan, "bsgd_tile_export (transposed)");
   const Store& st = transposed ? plan->bwd : plan->fwd;
   const unsigned blocks = (unsigned)std::min<int64_t>((nrows + 255) / 256, 65535);
   const unsigned cblocks = (unsigned)((nrows * 64 + 255) / 256);

@@ -550,6 +550,7 @@ extern "C" bsgd_status bsgd_backproject(const bsgd_plan* plan, bsgd_valtype vt, 
   bsgd_status st = check_vt(plan, vt);
   if (st != BSGD_OK) return st;
   BSGD_REQUIRE(r != nullptr && out != nullptr, "r and out must be non-NULL");
+  BSGD_NEED_BWD(plan, "bsgd_backproject");
   const Layout& L = plan->L;
   BSGD_HIP(permute_in(L, kRays, r, plan->vin, stream));
   if (x) {
@@ -587,6 +588,7 @@ extern "C" bsgd_status bsgd_backproject_block(const bsgd_plan* plan, bsgd_valtyp
   BSGD_REQUIRE(i >= 0 && i < plan->M && j >= 0 && j < plan->N, "block (%d, %d) out of range", i,
                j);
   BSGD_REQUIRE(ri != nullptr && g != nullptr, "ri and g must be non-NULL");
+  BSGD_NEED_BWD(plan, "bsgd_backproject_block");
   const int64_t c0 = plan->col_off[j], c1 = plan->col_off[j + 1];
   BSGD_HIP(launch_segment_rows(plan, false, vt, c0, c1 - c0, i, plan->row_off[i], ri, 2.0f, g,
                                stream));

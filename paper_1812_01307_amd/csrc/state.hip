@@ -205,6 +205,7 @@ extern "C" bsgd_status bsgd_power_umax(const bsgd_plan* plan, bsgd_valtype vt, i
   clear_error();
   BSGD_REQUIRE(plan && ws && umax, "NULL argument");
   BSGD_REQUIRE(iters >= 1, "iters must be >= 1");
+  BSGD_NEED_BWD(plan, "bsgd_power_umax");
   BSGD_REQUIRE(vt == BSGD_VAL_F32 || (vt == BSGD_VAL_F16 && (plan->flags & BSGD_PLAN_F16)),
                "value type not available in this plan");
   float *v, *z, *w, *res;
@@ -310,6 +311,7 @@ extern "C" bsgd_status bsgd_lanczos_umax(const bsgd_plan* plan, bsgd_valtype vt,
   BSGD_REQUIRE(steps >= 1 && steps <= 4096, "steps must be in [1, 4096]");
   BSGD_REQUIRE(vt == BSGD_VAL_F32 || (vt == BSGD_VAL_F16 && (plan->flags & BSGD_PLAN_F16)),
                "value type not available in this plan");
+  BSGD_NEED_BWD(plan, "bsgd_lanczos_umax");
   return lanczos_run(
       plan, steps, ws, ws_bytes, stream, umax,
       [&](const float* v, float* out) {
@@ -387,6 +389,7 @@ extern "C" bsgd_status bsgd_state_workspace_size(const bsgd_plan* plan, int nrhs
                    (nrhs == 1 && plan->M <= kMaxSelBlocks && plan->N <= kMaxSelBlocks),
                "block selection needs nrhs = 1 and at most %d row and column blocks",
                kMaxSelBlocks);
+  if (flags & BSGD_STATE_BLOCK_SELECT) BSGD_NEED_BWD(plan, "a block-selection state");
   bsgd_state tmp;
   *bytes = state_layout(plan, nrhs, flags, nullptr, &tmp);
   return BSGD_OK;
@@ -602,6 +605,10 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
   BSGD_REQUIRE(lam == 0.f || prox_iters >= 1, "prox_iters must be >= 1 when lam != 0");
   const bsgd_plan* p = st->plan;
   const int S = st->nrhs;
+  // every epoch below reads A^T from the block store unless a tile-sliced
+  // store serves both products (ISTA with several RHS excepted)
+  if (!st->fz || (st->method == BSGD_METHOD_ISTA && S > 1))
+    BSGD_NEED_BWD(p, "bsgd_run_epochs without a tile-sliced store");
   const float theta = per_rhs ? -1.f : mu * lam;  // -1: per-RHS thetas from st->lam
   for (int e = 0; e < epochs; ++e) {
     const int c = st->cur, n = 1 - c;

@@ -44,6 +44,13 @@ def test_size_queries_and_argument_errors():
     assert bst > b32 + 6 * 477832
     with pytest.raises(capi.BsgdError, match="flags"):
         capi.bsgd_plan_workspace_size(8190, 4096, 477832, 2, 2, 64, 64, 1, 91, 64)
+    # without the A^T store: about one store's 8 bytes per entry less
+    bfo = capi.bsgd_plan_workspace_size(8190, 4096, 477832, 2, 2, 64, 64, 1, 91,
+                                        capi.BSGD_PLAN_FWD_ONLY)
+    assert b32 - bfo >= 8 * 477832
+    with pytest.raises(capi.BsgdError, match="STAGED_BWD"):
+        capi.bsgd_plan_workspace_size(8190, 4096, 477832, 2, 2, 64, 64, 1, 91,
+                                      capi.BSGD_PLAN_FWD_ONLY | capi.BSGD_PLAN_STAGED_BWD)
     assert capi.bsgd_tv_workspace_size(16, 16, 4) >= 13 * 16 * 16 * 4
     with pytest.raises(capi.BsgdError):
         capi.bsgd_tv_workspace_size(0, 5, 1)

@@ -394,3 +394,73 @@ def test_count_reuse_and_invalidation_give_identical_stores():
             assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
         else:
             assert np.allclose(got[0], ref[0], rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("name", ["c1", "ragged"])
+def test_fwd_only_plan_gives_the_same_single_pass_results(name):
+    """A plan without the A^T block store builds the same tile-sliced store: the
+    column-sum bounds come from At's rows either way, so one-RHS, batch and
+    ISTA epochs and the Lanczos estimate equal the full plan's bitwise."""
+    import paper_1812_01307_amd as bsgd
+    p = _cases()[name]()
+    full, lean = plan_for(p), plan_for(p, fwd_only=True)
+    F_full, F_lean = _fused(full), _fused(lean)
+    assert bsgd.bsgd_fused_shape(F_full) == bsgd.bsgd_fused_shape(F_lean)
+    u_full = bsgd.bsgd_lanczos_umax_fused(F_full, 6)
+    assert bsgd.bsgd_lanczos_umax_fused(F_lean, 6) == u_full
+    mu = float(np.float32(mu_for(p)))
+    y4 = np.stack([f32(p.y) * s for s in (1.0, 0.5, 2.0, 0.0)])
+
+    def run(plan, F, S, ista=False):
+        st = bsgd.bsgd_state_create(plan, S)
+        bsgd.bsgd_state_attach_fused(st, F)
+        if ista:
+            bsgd.bsgd_state_set_method(st, bsgd.BSGD_METHOD_ISTA)
+        y = f32(p.y) if S == 1 else np.ascontiguousarray(y4[:S].T).ravel()
+        bsgd.bsgd_state_init(st, _dev(f32(y)))
+        bsgd.bsgd_run_epochs(st, mu, 20.0, 5, 20)
+        return _host(bsgd.bsgd_get_x(st))
+
+    for S, ista in ((1, False), (4, False), (1, True)):
+        assert np.array_equal(run(full, F_full, S, ista), run(lean, F_lean, S, ista)), (S, ista)
+
+
+def test_fwd_only_plan_refuses_calls_that_need_the_transpose():
+    import paper_1812_01307_amd as bsgd
+    p = problem("c1_64")
+    plan = plan_for(p, fwd_only=True)
+    r = _dev(f32(p.y))
+
+    def unsupported(fn, *a, **k):
+        with pytest.raises(bsgd.BsgdError) as e:
+            fn(*a, **k)
+        assert e.value.status == bsgd.BSGD_ERR_UNSUPPORTED, fn
+
+    unsupported(bsgd.bsgd_backproject, plan, r)
+    unsupported(bsgd.bsgd_backproject_block, plan, 0, 0,
+                _dev(f32(p.y[p.row_off[0]:p.row_off[1]])))
+    unsupported(bsgd.bsgd_tile_export, plan, 0, 0, transposed=True)
+    unsupported(bsgd.bsgd_power_umax, plan, 3)
+    unsupported(bsgd.bsgd_lanczos_umax, plan, 3)
+    unsupported(bsgd.bsgd_state_create, plan, 1, flags=bsgd.BSGD_STATE_BLOCK_SELECT)
+    mu = float(np.float32(mu_for(p)))
+    st = bsgd.bsgd_state_create(plan, 1)   # no tile-sliced store attached
+    bsgd.bsgd_state_init(st, r)
+    unsupported(bsgd.bsgd_run_epochs, st, mu, 20.0, 1, 20)
+    F = _fused(plan)
+    st4 = bsgd.bsgd_state_create(plan, 4)
+    bsgd.bsgd_state_attach_fused(st4, F)
+    bsgd.bsgd_state_set_method(st4, bsgd.BSGD_METHOD_ISTA)
+    bsgd.bsgd_state_init(st4, _dev(np.zeros(p.nrows * 4, np.float32)))
+    unsupported(bsgd.bsgd_run_epochs, st4, mu, 20.0, 1, 20)
+    # the forward direction and the single pass stay available
+    x = _dev(f32(np.ones(p.ncols)))
+    ref = oracle.forward(matrix(p), np.ones(p.ncols))
+    assert rel_l2(_host(bsgd.bsgd_forward(plan, x)), ref) <= 1e-6
+    bsgd.bsgd_state_attach_fused(st, F)
+    bsgd.bsgd_run_epochs(st, mu, 20.0, 1, 20)
+    with pytest.raises(bsgd.BsgdError) as e:
+        bsgd.plan_from_host(p.nrows, p.ncols, p.row_ptr, p.col, p.val, *p.ensure_transpose(),
+                            p.M, p.N, p.row_off, p.col_off, p.H, p.W, 1, view_len=p.bins,
+                            staged="bwd", fwd_only=True)
+    assert e.value.status == bsgd.BSGD_ERR_INVALID

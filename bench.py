@@ -150,7 +150,7 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=None, help="override the workload's epoch count")
     ap.add_argument("--umax", default="lanczos", choices=["lanczos", "power"],
                     help="u_max for the step size: Lanczos bidiagonalisation or power iteration")
-    ap.add_argument("--umax-steps", type=int, default=6,
+    ap.add_argument("--umax-steps", type=int, default=4,
                     help="Lanczos steps (each one product with A and one with A^T)")
     ap.add_argument("--power-iters", type=int, default=30)
     ap.add_argument("--cpu-epochs", type=int, default=20,

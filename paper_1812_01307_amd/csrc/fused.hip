@@ -68,6 +68,7 @@ constexpr int kMaxSeg = kFT * kFT;   // a segment holds at most one entry per pi
 
 struct TileGeom {
   int Ht = 1, Wt = 1;        // 8 x 8 tiles per image column / row
+  float rWt = 1.f;           // 1 / Wt rounded to FP32 (division by Wt in the build)
   int FTh = 1, FTw = 1;      // 64 x 64 tiles per image column / row
   int D = 1;
   int Q = 1;                 // ray chunks
@@ -116,6 +117,7 @@ static TileGeom tile_geom(const Layout& L, int chunks) {
   TileGeom g;
   g.Ht = L.Ht;
   g.Wt = L.Wt;
+  g.rWt = 1.0f / (float)L.Wt;
   g.FTh = (L.Ht + 7) / 8;
   g.FTw = (L.Wt + 7) / 8;
   g.D = L.D;
@@ -150,10 +152,20 @@ __device__ __forceinline__ int chunk_of(const TileGeom& g, int64_t k) {
 // address in the tile's LDS image.
 __device__ __forceinline__ void decode_pixel(const TileGeom& g, int64_t cp, int& G, int& f,
                                              int& a) {
-  const int64_t d = cp / g.slice_px;
+  const int64_t d = g.D == 1 ? 0 : cp / g.slice_px;
   const int64_t rem = cp - d * g.slice_px;
   const int t8 = (int)(rem >> 6), w = (int)(rem & 63);
-  const int tr8 = t8 / g.Wt, tc8 = t8 - tr8 * g.Wt;
+  // t8 / Wt from the FP32 reciprocal: t8 < 2^24 is exact in FP32 and the
+  // product is within 1 of the quotient, so one correction step makes it exact
+  int tr8 = (int)((float)t8 * g.rWt);
+  int tc8 = t8 - tr8 * g.Wt;
+  if (tc8 < 0) {
+    --tr8;
+    tc8 += g.Wt;
+  } else if (tc8 >= g.Wt) {
+    ++tr8;
+    tc8 -= g.Wt;
+  }
   G = (int)d * g.FTh + (tr8 >> 3);
   f = tc8 >> 3;
   a = (((tr8 & 7) << 3) + (w >> 3)) * kFTS + ((tc8 & 7) << 3) + (w & 7);
@@ -163,6 +175,8 @@ __device__ __forceinline__ void decode_pixel(const TileGeom& g, int64_t cp, int&
 // pixel order, so the band key G never decreases along the row).  Lane f
 // keeps, for the current band, the rank and running length of the segment
 // in tile column f.  Segments are ranked in the order the ray enters them.
+//   vis.prefetch(e, ok) / vis.advance()  per-entry data of the next batch
+//                                      (entry e of this lane) / make it current
 //   vis.group(rank)                     before the entries of one segment in
 //                                      a batch (called by the whole wavefront)
 //   vis.entry(rank, j, lds_addr, e, prev)  entry e is the j-th of segment
@@ -179,12 +193,16 @@ __device__ void walk_ray(const TileGeom& g, const int32_t* __restrict__ col, int
   const uint64_t below = (1ull << lane) - 1ull;
   int Gcur = -1, cnt = 0, rank = -1, nseen = 0, first = 0, last = 0;
   int32_t cnext = lane < len ? col[beg + lane] : 0;
+  vis.prefetch(beg + lane, lane < len);
   for (int64_t c0 = 0; c0 < len; c0 += 64) {
     const int64_t e = c0 + lane;
     const bool valid = e < len;
     const int32_t cp = cnext;
-    // the next batch's columns load while this one is walked
+    vis.advance();
+    // the next batch's columns (and the visitor's data) load while this one
+    // is walked
     if (e + 64 < len) cnext = col[beg + e + 64];
+    vis.prefetch(beg + e + 64, e + 64 < len);
     int G = 0x7fffffff, f = 0, a = 0;
     if (valid) decode_pixel(g, cp, G, f, a);
     bool done = !valid;
@@ -246,6 +264,8 @@ struct VisCount {
   int64_t* ncross;
   int32_t *maxc, *maxlen, *maxstep;
   int mlen = 0, mstep = 0;
+  __device__ void prefetch(int64_t, bool) {}
+  __device__ void advance() {}
   __device__ void group(int) {}
   __device__ void entry(int, int, int a, int64_t, int prev) {
     if (prev >= 0) mstep = max(mstep, a - prev);
@@ -283,16 +303,18 @@ struct VisPairs {
   TileGeom g;
   int64_t k;
   int q;
-  const int64_t* poff;
+  int64_t pk;  // the ray's first segment index
   uint64_t* key;
   int32_t* idx;
   int32_t* pray;
   uint16_t* pbase;
+  __device__ void prefetch(int64_t, bool) {}
+  __device__ void advance() {}
   __device__ void group(int) {}
   __device__ void entry(int, int, int, int64_t, int) {}
   __device__ void close(int G, int f, int len, int rank, int first) {
     if (rank < 0) return;
-    const int64_t p = poff[k] + rank;
+    const int64_t p = pk + rank;
     const int64_t u = ((int64_t)G * g.FTw + f) * g.Q + q;
     key[p] = ((uint64_t)(u * kKeyLen + (kKeyLen - 1 - len)) << 32) | tie_of(g, k);
     idx[p] = (int32_t)p;
@@ -326,8 +348,19 @@ struct VisFill {
   float* val;
   __half* val16;
   int* err;
+  float vnext = 0.f, vcur = 0.f;  // this lane's entry of the next / current batch
+  __half hnext = 0.f, hcur = 0.f; // its FP16 copy (plans with one)
+  __device__ void prefetch(int64_t e, bool ok) {
+    if (!ok) return;
+    vnext = vsrc[e];
+    if (v16src) hnext = v16src[e];
+  }
+  __device__ void advance() {
+    vcur = vnext;
+    hcur = hnext;
+  }
   __device__ void group(int rk) { d = rk < 64 ? readlane64(dpre, rk) : pdst[pk + rk]; }
-  __device__ void entry(int, int j, int a, int64_t e, int prev) {
+  __device__ void entry(int, int j, int a, int64_t, int prev) {
     if (j >= 4 * (int)(d & ((1 << kDstShift) - 1))) {
       atomicOr(err, 1);
       return;
@@ -337,8 +370,8 @@ struct VisFill {
       col8[addr] = (uint8_t)(j == 0 ? 0 : a - prev);
     else
       col[addr] = (uint16_t)a;
-    val[addr] = vsrc[e];
-    if (val16) val16[addr] = v16src ? v16src[e] : __float2half_rn(vsrc[e]);
+    val[addr] = vcur;
+    if (val16) val16[addr] = v16src ? hcur : __float2half_rn(vcur);
   }
   __device__ void close(int, int, int, int, int) {}
   __device__ void finish(int) {}
@@ -371,7 +404,7 @@ __global__ __launch_bounds__(256) void k_fz_walk(
     VisCount v{k, ncross, maxc, maxlen, maxstep};
     walk_ray(g, col, beg, len, v);
   } else if constexpr (MODE == 1) {
-    VisPairs v{g, k, q, poff, key, idx, pray, pbase};
+    VisPairs v{g, k, q, poff[k], key, idx, pray, pbase};
     walk_ray(g, col, beg, len, v);
   } else {
     const int64_t pk = poff[k], nr = poff[k + 1] - pk;

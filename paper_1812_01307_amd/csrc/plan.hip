@@ -145,6 +145,18 @@ __global__ __launch_bounds__(256) void k_fill(
   const int64_t len = row_ptr[n + 1] - a;
   const int64_t dst = ptr[k];
   const int64_t plen = ptr[k + 1] - dst;
+  // seg[b] = number of entries whose natural column is < seg_off[b].  With
+  // fewer than 64 blocks, lane b holds the inner bound seg_off[b] (below
+  // ncols < 2^31), each entry finds its block by comparing with them, and the
+  // first entry of each block writes the table; otherwise a binary search
+  // per bound follows the copy.
+  const bool few = nseg < 64;
+  const int32_t bnd = few && lane < nseg ? (int32_t)seg_off[lane] : 0;
+  auto block_of = [&](int64_t c) {
+    int blk = 0;
+    for (int b = 1; b < nseg; ++b) blk += c >= (int64_t)__builtin_amdgcn_readlane(bnd, b);
+    return blk;
+  };
   int bad = 0;
 #pragma unroll 4
   for (int64_t q = lane; q < plen; q += 64) {
@@ -157,7 +169,13 @@ __global__ __launch_bounds__(256) void k_fill(
         bad |= kErrColRange;
         c = 0;
       }
-      if (q > 0 && col_src[a + q - 1] >= col_src[a + q]) bad |= kErrColOrder;
+      const int64_t cp = q > 0 ? (int64_t)col_src[a + q - 1] : 0;
+      if (q > 0 && cp >= c) bad |= kErrColOrder;
+      if (few) {
+        // blocks (block of the previous entry, this entry's] start here
+        const int hi = block_of(c);
+        for (int b = q > 0 ? block_of(cp) + 1 : 1; b <= hi; ++b) sg[b] = (int32_t)q;
+      }
     } else {
       // padding: repeat the last real column (already touched by the row)
       c = col_src[a + len - 1];
@@ -168,7 +186,14 @@ __global__ __launch_bounds__(256) void k_fill(
     val[dst + q] = v;
     if (val16) val16[dst + q] = __float2half_rn(v);
   }
-  // seg[q] = number of entries whose natural column is < seg_off[q]
+  if (few) {
+    // blocks after the last entry's start at len (all of them when empty)
+    const int last = len > 0 ? block_of(col_src[a + len - 1]) : 0;
+    for (int b = lane; b <= nseg; b += 64)
+      if (b == 0 || b > last) sg[b] = b == 0 ? 0 : (int32_t)len;
+    if (bad) atomicOr(err, bad);
+    return;
+  }
   for (int q = lane; q <= nseg; q += 64) {
     const int64_t bound = seg_off[q];
     int64_t lo = 0, hi = len;

@@ -54,6 +54,7 @@ struct bsgd_state {
   // pool of device tev_dev
   std::vector<hipEvent_t> tev;
   int tev_dev = 0;
+  int aux_dev = 0;                      // device of the pooled aux stream and events
   int t_cap = 0, t_used = 0;
   int t_stride = 1;         // time one epoch in every t_stride ...
   int64_t t_seen = 0;       // ... counting epochs since the timers were armed
@@ -395,6 +396,59 @@ extern "C" bsgd_status bsgd_state_workspace_size(const bsgd_plan* plan, int nrhs
   return BSGD_OK;
 }
 
+// The second stream and the two ordering events of a state are pooled per
+// device for the life of the process, like the timing events below: a job
+// that creates a state per reconstruction spent hundreds of microseconds of
+// host time creating a stream.  A state returns them after its stream has
+// drained.
+struct AuxSet {
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_main = nullptr, ev_aux = nullptr;
+};
+static std::mutex g_aux_mu;
+static std::vector<std::vector<AuxSet>> g_aux_pool;  // [device]
+
+static hipError_t take_aux(bsgd_state* st) {
+  int dev = 0;
+  hipError_t r = hipGetDevice(&dev);
+  if (r != hipSuccess) return r;
+  st->aux_dev = dev;
+  {
+    std::lock_guard<std::mutex> lk(g_aux_mu);
+    if ((int)g_aux_pool.size() > dev && !g_aux_pool[dev].empty()) {
+      const AuxSet a = g_aux_pool[dev].back();
+      g_aux_pool[dev].pop_back();
+      st->aux = a.aux;
+      st->ev_main = a.ev_main;
+      st->ev_aux = a.ev_aux;
+      return hipSuccess;
+    }
+  }
+  AuxSet a;
+  r = hipStreamCreateWithFlags(&a.aux, hipStreamNonBlocking);
+  if (r == hipSuccess) r = hipEventCreateWithFlags(&a.ev_main, hipEventDisableTiming);
+  if (r == hipSuccess) r = hipEventCreateWithFlags(&a.ev_aux, hipEventDisableTiming);
+  if (r != hipSuccess) {
+    if (a.ev_main) (void)hipEventDestroy(a.ev_main);
+    if (a.aux) (void)hipStreamDestroy(a.aux);
+    return r;
+  }
+  st->aux = a.aux;
+  st->ev_main = a.ev_main;
+  st->ev_aux = a.ev_aux;
+  return hipSuccess;
+}
+
+static void give_aux(bsgd_state* st) {
+  if (!st->aux) return;
+  (void)hipStreamSynchronize(st->aux);
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  if ((int)g_aux_pool.size() <= st->aux_dev) g_aux_pool.resize(st->aux_dev + 1);
+  g_aux_pool[st->aux_dev].push_back(AuxSet{st->aux, st->ev_main, st->ev_aux});
+  st->aux = nullptr;
+  st->ev_main = st->ev_aux = nullptr;
+}
+
 extern "C" bsgd_status bsgd_state_create(const bsgd_plan* plan, int nrhs, bsgd_valtype vt,
                                          unsigned flags, void* workspace, size_t workspace_bytes,
                                          bsgd_state** out) {
@@ -416,13 +470,9 @@ extern "C" bsgd_status bsgd_state_create(const bsgd_plan* plan, int nrhs, bsgd_v
   st->flags = flags;
   st->vt = vt;
   state_layout(plan, nrhs, flags, workspace, st);
-  hipError_t e = hipStreamCreateWithFlags(&st->aux, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_main, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&st->ev_aux, hipEventDisableTiming);
+  const hipError_t e = take_aux(st);
   if (e != hipSuccess) {
     set_error("state stream/event creation failed: %s", hipGetErrorString(e));
-    if (st->ev_main) (void)hipEventDestroy(st->ev_main);
-    if (st->aux) (void)hipStreamDestroy(st->aux);
     delete st;
     return BSGD_ERR_HIP;
   }
@@ -484,11 +534,8 @@ static hipError_t take_timers(bsgd_state* st, size_t n) {
 
 extern "C" void bsgd_state_destroy(bsgd_state* st) {
   if (!st) return;
-  if (st->aux) (void)hipStreamSynchronize(st->aux);
+  give_aux(st);
   destroy_timers(st);
-  if (st->ev_aux) (void)hipEventDestroy(st->ev_aux);
-  if (st->ev_main) (void)hipEventDestroy(st->ev_main);
-  if (st->aux) (void)hipStreamDestroy(st->aux);
   delete st;
 }
 

@@ -25,8 +25,9 @@ import time
 
 HBM_PEAK_GBS = 8000.0
 
-# Kernel durations inside the timed jobs are sampled on one epoch in 8.
-TIMING_STRIDE = 8
+# Kernel durations inside the timed jobs are sampled on one epoch in 20 (10 of
+# a 200-epoch job; the events cost about 1% of a job at one epoch in 8).
+TIMING_STRIDE = 20
 
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE runs (scaled by what the counters read for a plain copy), keyed

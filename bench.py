@@ -25,6 +25,10 @@ import time
 
 HBM_PEAK_GBS = 8000.0
 
+# Ray chunks of the volume workload's tile-sliced store (0 = the library's
+# one-RHS choice, 16 at 512^2).
+VOLUME_CHUNKS = 4
+
 # Kernel durations inside the timed jobs are sampled on one epoch in 20 (10 of
 # a 200-epoch job; the events cost about 1% of a job at one epoch in 8).
 TIMING_STRIDE = 20
@@ -37,19 +41,23 @@ TIMING_STRIDE = 20
 PMC_TRAFFIC = {
     # profiles/k_fused_c2_512_hbm_counters.md
     ("fused", "c2_512", "f32"): {
-        "sha256": "3a52f63bc03ab1e800083d93d5b3cf0d66c79af3593c544536876f802c3ae6a7",
-        "bytes": 1335151517},
+        "sha256": "eb65c79b6996c6a19ce3f6645d6b700dd0920b91fe85cd07d434b4f12042f130",
+        "bytes": 1335204259},
+    # profiles/k_fused_f16_c2_512_counters.md
+    ("fused", "c2_512", "f16"): {
+        "sha256": "eb65c79b6996c6a19ce3f6645d6b700dd0920b91fe85cd07d434b4f12042f130",
+        "bytes": 832943110},
     # profiles/k_fused_ista_c2_512_hbm_counters.md (the A x-only pass)
     ("fused", "c2_512", "f32", "ista"): {
-        "sha256": "3a52f63bc03ab1e800083d93d5b3cf0d66c79af3593c544536876f802c3ae6a7",
-        "bytes": 1310615639},
+        "sha256": "eb65c79b6996c6a19ce3f6645d6b700dd0920b91fe85cd07d434b4f12042f130",
+        "bytes": 1310727062},
     ("fused", "c2_512", "f32", "gd"): {
-        "sha256": "3a52f63bc03ab1e800083d93d5b3cf0d66c79af3593c544536876f802c3ae6a7",
-        "bytes": 1310615639},
-    # profiles/k_sel_c2_512_hbm_counters.md (mean over the 800 draws of the bench's run)
+        "sha256": "eb65c79b6996c6a19ce3f6645d6b700dd0920b91fe85cd07d434b4f12042f130",
+        "bytes": 1310727062},
+    # profiles/k_sel_c2_512_hbm_counters.md (mean over the 1600 draws of the profiled run)
     ("selected", "c2_512", "f32", 0.5, 0.5, 7, "fwd"): {
-        "sha256": "a376794b8b41a6e02cc276c3678028389ff13f88962ba4495c42f086f7820c41",
-        "bytes": 613983496},
+        "sha256": "0042c05c367575aa47a0e2725c16df3b9585bdf6b007b36c201bf6c18005155d",
+        "bytes": 613975405},
 }
 
 
@@ -171,7 +179,8 @@ def main(argv=None):
     ap.add_argument("--gamma", type=float, default=0.5)
     ap.add_argument("--select-seed", type=int, default=7)
     ap.add_argument("--fused-chunks", type=int, default=0,
-                    help="ray chunks of the tile-sliced store (0: automatic)")
+                    help="ray chunks of the tile-sliced store (0: automatic; volumes: %d)"
+                    % VOLUME_CHUNKS)
     ap.add_argument("--fused-waves", type=int, default=8, choices=[2, 4, 8],
                     help="wavefronts per (tile, chunk) workgroup of the single pass")
     ap.add_argument("--mr-waves", type=int, default=0, choices=[0, 8, 16],
@@ -675,8 +684,11 @@ def run_volume(args, np, torch, synth, bsgd):
         F = None
         if fused:
             # the single pass for several RHS reads the tile-sliced store; the
-            # Lanczos products run on it too
-            F = bsgd.bsgd_fused_create(plan, args.fused_chunks)
+            # Lanczos products run on it too.  4 ray chunks: with 64 RHS columns
+            # per unit there are workgroups enough, and fewer chunks mean fewer
+            # A^T R partials to write and reduce (measured at 256 slices: 8.3 k
+            # slice-epochs/s at 2 or 4 chunks, 7.7 k at 6 and 8, 6.5 k at 16)
+            F = bsgd.bsgd_fused_create(plan, args.fused_chunks or VOLUME_CHUNKS)
             u = bsgd.bsgd_lanczos_umax_fused(F, args.umax_steps, vt=vt)
             shape["fused"] = bsgd.bsgd_fused_shape(F)
         else:

@@ -11,8 +11,14 @@ Scheduling, one round of `step()`:
   1. admission: queued requests (arrival order) take a free slot of a batch
      state of their geometry; when every slot is taken, a new batch state is
      created if it fits the HBM budget (plans + states, by their workspace
-     sizes), after releasing idle states if needed.  A request that does not
-     fit waits; requests of other geometries are not held behind it.
+     sizes), after releasing idle states if needed.  A new state has one slot
+     when its request is the only one of its geometry running or waiting
+     (the one-RHS pass then runs no idle columns), else as many as that
+     geometry's running and waiting requests doubled, rounded up to 4, 8, ...
+     and capped at the server's width; an idle state of the geometry narrower
+     than that is dropped rather than reused.
+     A request that does not fit waits; requests of other geometries are not
+     held behind it.
   2. every batch state with an occupied slot runs `chunk` epochs on its own
      stream; the launches of all states are queued before any is waited on,
      so the work of different geometries overlaps on the device.
@@ -24,7 +30,8 @@ A request is admitted between rounds only, so its epochs count from a chunk
 boundary and the stop rule is evaluated after the same epochs whatever else
 is being served; the slots of a state do not interact (every product, norm
 and prox is per slot).  A request therefore gets the same result alone and in
-a mix (bitwise, for the same slot count and chunk).  `cancel(rid)` drops a
+a mix (bitwise, for the same chunk: a one-slot state and a slot of a wider
+state sum in the same order).  `cancel(rid)` drops a
 queued request, or empties a running request's slot between rounds; the
 other slots are untouched.
 
@@ -163,16 +170,33 @@ class Server:
         return bool(self.queue) or any(b.active for b in self.batches)
 
     # -- admission ---------------------------------------------------------
-    def _new_batch(self, key) -> Optional[_Batch]:
+    def _width(self, demand: int) -> int:
+        """Slots of a new state for a geometry with `demand` requests running or
+        waiting: one for a lone request, else the smallest power of two from 4
+        that holds twice as many (room for the arrivals a loaded geometry
+        keeps receiving), at most the server's width (states hold 1 or a power
+        of two from 4 RHS).  A wide state's pass costs about as much as its
+        slots would alone only when about half of them are occupied (at 512^2:
+        0.24 ms one RHS, 0.44 ms four, 0.83 ms eight), so widths follow the
+        geometry's load rather than the maximum."""
+        if demand <= 1 or self.slots < 4:
+            return 1
+        w = 4
+        while w < 2 * demand and w * 2 <= self.slots:
+            w *= 2
+        return w
+
+    def _new_batch(self, key, width: Optional[int] = None) -> Optional[_Batch]:
         geom = self.geometries[key]
-        nbytes = self.backend.state_bytes(geom, self.slots)
+        width = self.slots if width is None else width
+        nbytes = self.backend.state_bytes(geom, width)
         if self.max_states is not None and len(self.batches) >= self.max_states:
             if not self._release_idle(0, force_count=True):
                 return None
         if self.hbm_bytes is not None:
             if not self._release_idle(self.resident_bytes() + nbytes - self.hbm_bytes):
                 return None
-        b = _Batch(key, self.backend.new_state(geom, self.slots), nbytes, [None] * self.slots)
+        b = _Batch(key, self.backend.new_state(geom, width), nbytes, [None] * width)
         self.batches.append(b)
         return b
 
@@ -193,16 +217,26 @@ class Server:
     def _admit(self) -> None:
         waiting = []
         changed = set()
-        for req in self.queue:
+        for i, req in enumerate(self.queue):
+            # requests of this geometry running, and waiting from here on
+            demand = (sum(b.active for b in self.batches if b.geometry == req.geometry)
+                      + sum(r.geometry == req.geometry for r in self.queue[i:]))
+            want = self._width(demand)
             target, k = None, -1
             for b in self.batches:
-                if b.geometry == req.geometry:
+                # a free slot of a running state, or of an idle one wide enough
+                if b.geometry == req.geometry and (b.active or len(b.slots) >= want):
                     k = b.free_slot()
                     if k >= 0:
                         target = b
                         break
             if target is None:
-                target = self._new_batch(req.geometry)
+                # idle states of this geometry narrower than its load make room
+                for b in [b for b in self.batches
+                          if b.geometry == req.geometry and not b.active]:
+                    self.batches.remove(b)
+                    self.backend.drop_state(b.handle)
+                target = self._new_batch(req.geometry, want)
                 k = 0 if target is not None else -1
             if target is None:
                 waiting.append(req)

@@ -252,3 +252,26 @@ def test_launch_shape_argument_checks():
     bsgd.bsgd_state_init(many, _dev(np.zeros(p.nrows * 4, np.float32)))
     with pytest.raises(bsgd.BsgdError, match="before"):
         bsgd.bsgd_state_autotune(many, 1e-4, 1.0, 20)
+
+
+@pytest.mark.parametrize("name", ["c1", "ragged"])
+def test_one_rhs_state_equals_a_batch_slot_bitwise(name):
+    """The one-RHS single pass and a slot of the several-RHS pass sum in the same
+    order (row sums by group parity, A^T r in exact fixed point, chunk planes in
+    chunk order) and run the same prox arithmetic, so a reconstruction gives
+    bitwise the same iterate alone in a one-RHS state and in a batch slot."""
+    import paper_1812_01307_amd as bsgd
+    p = _cases()[name]()
+    plan = plan_for(p)
+    F = bsgd.bsgd_fused_create(plan, 0)
+    mu = float(np.float32(mu_for(p)))
+    Y = _sinograms(p, 4, seed0=700, zero_last=False)
+    lam = np.array([20.0, 0.0, 5.0, 200.0])
+    st = _state(plan, F, 4, Y)
+    bsgd.bsgd_state_set_lambda(st, lam)
+    bsgd.bsgd_run_epochs(st, mu, -1.0, 7, 20)
+    X = _host(bsgd.bsgd_get_x(st)).reshape(p.ncols, 4).T
+    for j in range(4):
+        one = _state(plan, F, 1, Y[j:j + 1])
+        bsgd.bsgd_run_epochs(one, mu, float(np.float32(lam[j])), 7, 20)
+        assert np.array_equal(_host(bsgd.bsgd_get_x(one)), X[j]), j

@@ -237,3 +237,62 @@ def test_percentile_nearest_rank():
     v = list(range(1, 101))
     assert percentile(v, 50) == 50 and percentile(v, 99) == 99 and percentile(v, 100) == 100
     assert percentile([7.0], 99) == 7.0
+
+
+def test_state_width_follows_demand():
+    """A lone request of a geometry gets a one-slot state; requests that share a
+    geometry (waiting together, or arriving while one runs) get full-width
+    states; the widths are 1 or powers of two from 4 up to the server's."""
+    be = FakeBackend()
+    srv = Server(be, slots=8, chunk=10, tol=1e-4, max_epochs=300)
+    for g in ("a", "b", "c"):
+        srv.add_geometry(g, g)
+    srv.submit(Request(rid=0, geometry="a", y=50.0, lam=1.0))
+    srv.submit(Request(rid=1, geometry="b", y=50.0, lam=1.0))
+    srv.submit(Request(rid=2, geometry="b", y=50.0, lam=1.0))
+    srv.step()
+    widths = {b.geometry: len(b.slots) for b in srv.batches}
+    assert widths == {"a": 1, "b": 4}  # two of "b": room for four
+    assert sum(b.active for b in srv.batches) == 3
+    # a second request of "a" while the first runs: a new state of 4 slots
+    srv.submit(Request(rid=3, geometry="a", y=50.0, lam=2.0))
+    srv.submit(Request(rid=4, geometry="c", y=50.0, lam=1.0))
+    srv.step()
+    assert sorted(len(b.slots) for b in srv.batches if b.geometry == "a") == [1, 4]
+    assert [len(b.slots) for b in srv.batches if b.geometry == "c"] == [1]
+    # six more of "c" at once (one running): the new state holds 8
+    for i in range(6):
+        srv.submit(Request(rid=10 + i, geometry="c", y=50.0, lam=1.0))
+    srv.step()
+    assert sorted(len(b.slots) for b in srv.batches if b.geometry == "c") == [1, 8]
+    while srv.busy:
+        srv.step()
+    assert sorted(r.rid for r in srv.done) == [0, 1, 2, 3, 4] + list(range(10, 16))
+    for r in srv.done:
+        assert r.epochs == expected_epochs(50.0, 10, 1e-4, 300)
+    # a narrow server: 4 slots; slot counts below 4 other than 1 do not exist
+    assert Server(be, slots=4)._width(3) == 4 and Server(be, slots=2)._width(2) == 1
+    assert Server(be, slots=16)._width(2) == 4 and Server(be, slots=16)._width(3) == 8
+    assert Server(be, slots=16)._width(5) == 16 and Server(be, slots=12)._width(30) == 8
+
+
+def test_idle_narrow_state_gives_way_to_a_wider_one():
+    be = FakeBackend()
+    srv = Server(be, slots=8, chunk=10, tol=1e-4, max_epochs=20)
+    srv.add_geometry("a", "a")
+    srv.submit(Request(rid=0, geometry="a", y=50.0, lam=1.0))
+    while srv.busy:
+        srv.step()
+    assert [len(b.slots) for b in srv.batches] == [1] and be.dropped == 0
+    # the one-slot state is idle: a lone request reuses it ...
+    srv.submit(Request(rid=1, geometry="a", y=50.0, lam=1.0))
+    srv.step()
+    assert [len(b.slots) for b in srv.batches] == [1] and be.dropped == 0
+    while srv.busy:
+        srv.step()
+    # ... three at once replace it with a state of 8 (room for twice the load)
+    for i in range(3):
+        srv.submit(Request(rid=2 + i, geometry="a", y=50.0, lam=1.0))
+    srv.step()
+    assert [len(b.slots) for b in srv.batches] == [8] and be.dropped == 1
+    assert srv.batches[0].active == 3

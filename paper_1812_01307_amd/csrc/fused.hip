@@ -554,6 +554,7 @@ static unsigned grid_for(int64_t n) {
 // below 2^-31 of the largest possible sum.
 constexpr float kMagic32 = 12582912.0f;  // 1.5 * 2^23
 constexpr int kMagic32Bits = 0x4B400000;
+constexpr unsigned long long kMagicPair = 0x4B4000004B400000ull;  // the magic in both words
 
 __device__ __forceinline__ int fixed_exponent32(double smax, double amax, float rmax) {
   const double b = smax * (double)rmax, t = amax * (double)rmax;
@@ -895,9 +896,12 @@ __global__ __launch_bounds__(64 * W) void k_fused_mr(
         const f32x2 xv = xsp[c[e] * 2];
         z0 = fmaf(a[e], xv[0], z0);
         z1 = fmaf(a[e], xv[1], z1);
-        const int t0 = term32(a[e], rs0), t1 = term32(a[e], rs1);
-        const unsigned long long pk =
-            ((unsigned long long)(unsigned)(t1 + (t0 >> 31)) << 32) | (unsigned)t0;
+        // the two rounded terms' bit patterns side by side, minus the magic
+        // constant in each word: a 64-bit subtraction leaves t0 + 2^32 t1 in
+        // two's complement (the high word takes the low word's borrow)
+        const unsigned b0 = __float_as_uint(fmaf(a[e], rs0, kMagic32));
+        const unsigned b1 = __float_as_uint(fmaf(a[e], rs1, kMagic32));
+        const unsigned long long pk = (((unsigned long long)b1 << 32) | b0) - kMagicPair;
         atomicAdd(gsp + c[e] * 2, pk);
       }
     };

@@ -41,19 +41,23 @@ TIMING_STRIDE = 20
 PMC_TRAFFIC = {
     # profiles/k_fused_c2_512_hbm_counters.md
     ("fused", "c2_512", "f32"): {
-        "sha256": "eb65c79b6996c6a19ce3f6645d6b700dd0920b91fe85cd07d434b4f12042f130",
-        "bytes": 1335204259},
+        "sha256": "e45f669262920ce0279a11f58a77ceb46989a33acaab42a18449c9305de8bd8e",
+        "bytes": 1335219423},
     # profiles/k_fused_f16_c2_512_counters.md
     ("fused", "c2_512", "f16"): {
-        "sha256": "eb65c79b6996c6a19ce3f6645d6b700dd0920b91fe85cd07d434b4f12042f130",
-        "bytes": 832943110},
+        "sha256": "e45f669262920ce0279a11f58a77ceb46989a33acaab42a18449c9305de8bd8e",
+        "bytes": 832946201},
     # profiles/k_fused_ista_c2_512_hbm_counters.md (the A x-only pass)
     ("fused", "c2_512", "f32", "ista"): {
-        "sha256": "eb65c79b6996c6a19ce3f6645d6b700dd0920b91fe85cd07d434b4f12042f130",
-        "bytes": 1310727062},
+        "sha256": "e45f669262920ce0279a11f58a77ceb46989a33acaab42a18449c9305de8bd8e",
+        "bytes": 1310718301},
     ("fused", "c2_512", "f32", "gd"): {
-        "sha256": "eb65c79b6996c6a19ce3f6645d6b700dd0920b91fe85cd07d434b4f12042f130",
-        "bytes": 1310727062},
+        "sha256": "e45f669262920ce0279a11f58a77ceb46989a33acaab42a18449c9305de8bd8e",
+        "bytes": 1310718301},
+    # profiles/k_vol_c4_hbm_counters.md (256 slices, 4 ray chunks)
+    ("fused_mr", "c4_vol", "f32", 256, 4, "fwd"): {
+        "sha256": "e45f669262920ce0279a11f58a77ceb46989a33acaab42a18449c9305de8bd8e",
+        "bytes": 25352154612},
     # profiles/k_sel_c2_512_hbm_counters.md (mean over the 1600 draws of the profiled run)
     ("selected", "c2_512", "f32", 0.5, 0.5, 7, "fwd"): {
         "sha256": "0042c05c367575aa47a0e2725c16df3b9585bdf6b007b36c201bf6c18005155d",
@@ -779,9 +783,13 @@ def run_volume(args, np, torch, synth, bsgd):
         dom = max((("fwd", b_fwd, f_ms), ("bwd", b_bwd, b_ms), ("prox", b_prox, p_ms)),
                   key=lambda t: t[2])
         achieved = dom[1] / dom[2] / 1e6
+        traffic = None
+        key = ("fused_mr", args.config, args.vt, S, shape["fused"][1] if fused else 0, dom[0])
+        if key in PMC_TRAFFIC and _kernel_source_hash("fused") == PMC_TRAFFIC[key]["sha256"]:
+            traffic = PMC_TRAFFIC[key]["bytes"]
         roofline = {"bound": "hbm", "kernel": names[dom[0]],
                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "alg_bytes_per_launch": dom[1]}
     out = {
         "metric": "BSGD-TV epochs/s + HBM GB/s vs peak; served recon p50/p99 latency",

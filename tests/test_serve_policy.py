@@ -205,8 +205,8 @@ def test_cancel_queued_and_running_requests_leaves_the_others_unchanged():
         return srv, {r.rid: r for r in reqs}
 
     base_srv, base = serve([])
-    # round 0: request 6 is still queued (2 slots per geometry, 3 geometries);
-    # round 2: request 1 is running
+    # before the first scheduling step request 6 is still queued (2 slots per
+    # geometry, 3 geometries); before the third, request 1 is running
     srv, got = serve([(0, 6), (2, 1)])
     assert not srv.cancel(6) and not srv.cancel(99)
     assert {r.rid for r in srv.cancelled} == {1, 6}

@@ -333,12 +333,14 @@ bsgd_status bsgd_state_workspace_size(const bsgd_plan* plan, int nrhs, unsigned 
 
 /*
  * Create a state in `workspace` (device).  The state borrows the plan.  It
- * owns one extra HIP stream and two events (default priority) that let the
- * forward product overlap the prox inside an epoch.
+ * holds one extra HIP stream and two events (default priority) that let the
+ * forward product overlap the prox inside an epoch; they come from a pool
+ * the library keeps per device for the life of the process.
  */
 bsgd_status bsgd_state_create(const bsgd_plan* plan, int nrhs, bsgd_valtype vt, unsigned flags,
                               void* workspace, size_t workspace_bytes, bsgd_state** out);
 
+/* Waits for the state's extra stream, returns it and the events to the pool. */
 void bsgd_state_destroy(bsgd_state* state);
 
 /*

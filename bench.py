@@ -4,8 +4,10 @@
 One step = one whole reconstruction job of the 512 x 512 workload
 (720 angles x 729 bins, M = N = 8 blocks, lambda = 0.01, 200 epochs, 20 FGP
 iterations), starting from A, A^T (FP32 CSR) and y already resident in HBM:
-    S0   build the block store            (bsgd_plan_create)
-         and the tile-sliced store         (bsgd_fused_create; --path fused)
+    S0   the plan                         (bsgd_plan_create: no block store with
+                                           --path fused, block stores of A and A^T
+                                           with --path rows)
+         and the tile-sliced store         (bsgd_fused_create, from A's CSR; --path fused)
     S0'  u_max by Lanczos bidiagonalisation (or --umax power), mu = 0.9 / (2 u_max)
     S1-S5 x 200 epochs                     (bsgd_run_epochs)
 With --path fused (default) every epoch reads the matrix once (both
@@ -82,6 +84,14 @@ def _kernel_source_hash(path):
         with open(os.path.join(base, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def _block_stores(flags):
+    """Which block stores a plan with these flags builds."""
+    import paper_1812_01307_amd as bsgd
+    if flags & bsgd.BSGD_PLAN_SINGLE_PASS_ONLY:
+        return "none (tile-sliced store from A's CSR)"
+    return "A" if flags & bsgd.BSGD_PLAN_FWD_ONLY else "A and A^T"
 
 
 def _alg_bytes(nnz, r, c, val_bytes):
@@ -296,8 +306,12 @@ def main(argv=None):
     selected = args.method == "selected"
     if fused and args.umax == "lanczos" and not selected and args.staged in ("none", "fwd"):
         # the tile-sliced store serves both products (and the Lanczos ones):
-        # the plan keeps no block store of A^T
+        # the plan keeps no block store of A^T, and none of A unless its
+        # staged form is asked for (the tile-sliced store is then built
+        # straight from A's CSR)
         flags |= bsgd.BSGD_PLAN_FWD_ONLY
+        if args.staged == "none":
+            flags |= bsgd.BSGD_PLAN_SINGLE_PASS_ONLY
     lam_run = 0.0 if args.method == "gd" else prob.lam
     n_updates = epochs
     if selected:
@@ -618,8 +632,10 @@ def main(argv=None):
                    "method": args.method,
                    "nnz": nnz, "epochs_per_step": epochs,
                    "path": args.path,
-                   "block_stores": "A" if flags & bsgd.BSGD_PLAN_FWD_ONLY else "A and A^T",
-                   "lanes_per_row": list(bsgd.bsgd_plan_lanes(plan)), "overlap": args.overlap,
+                   "block_stores": _block_stores(flags),
+                   "lanes_per_row": (None if flags & bsgd.BSGD_PLAN_SINGLE_PASS_ONLY
+                                     else list(bsgd.bsgd_plan_lanes(plan))),
+                   "overlap": args.overlap,
                    "staged": args.staged,
                    "launch": list(bsgd.bsgd_state_launch(st)),
                    "mu": "fixed from " + args.mu_file if fixed_mu is not None
@@ -680,7 +696,8 @@ def run_volume(args, np, torch, synth, bsgd):
     shape = {}
 
     if fused:
-        flags |= bsgd.BSGD_PLAN_FWD_ONLY  # the tile-sliced store serves both products
+        # the tile-sliced store serves both products and is built from A's CSR
+        flags |= bsgd.BSGD_PLAN_FWD_ONLY | bsgd.BSGD_PLAN_SINGLE_PASS_ONLY
 
     def job(graph, n_epochs=epochs, timed=False):
         plan = bsgd.bsgd_plan_create(A, At, prob.M, prob.N, prob.row_off, prob.col_off, prob.H,
@@ -806,7 +823,7 @@ def run_volume(args, np, torch, synth, bsgd):
                                f"setup S0+S0' included",
                    "nnz": nnz, "slices": S, "epochs_per_step": epochs,
                    "graph": graph, "path": args.path,
-                   "block_stores": "A" if flags & bsgd.BSGD_PLAN_FWD_ONLY else "A and A^T",
+                   "block_stores": _block_stores(flags),
                    "launch": (list(shape["tuned"]) if "tuned" in shape
                               else [args.mr_waves, 0]),
                    "kernel_timing": "events on one eager 20-epoch job after the timed region"},

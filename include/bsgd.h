@@ -70,6 +70,20 @@ typedef enum { BSGD_VAL_F32 = 0, BSGD_VAL_F16 = 1 } bsgd_valtype;
  * Excludes BSGD_PLAN_STAGED_BWD.
  */
 #define BSGD_PLAN_FWD_ONLY 16u
+/*
+ * Build no block store at all: for plans whose epochs run only on the
+ * tile-sliced store, which bsgd_fused_create then builds straight from A's
+ * CSR.  The plan keeps the device pointers of A's row_ptr, col and val (not
+ * copies): the caller keeps those arrays alive and unchanged while the plan
+ * exists.  A's columns are validated (in range, strictly ascending) when the
+ * tile-sliced store is built.  Implies BSGD_PLAN_FWD_ONLY; also refused
+ * (BSGD_ERR_UNSUPPORTED): bsgd_forward, bsgd_forward_block, bsgd_tile_nnz,
+ * bsgd_tile_export, bsgd_state_init with x0 and bsgd_state_set_rhs with x0.
+ * Excludes the staged forms and BSGD_PLAN_AUTOTUNE; with BSGD_PLAN_F16 the
+ * tile-sliced store's FP16 copy is rounded from A's FP32 values, as the block
+ * store's would be.
+ */
+#define BSGD_PLAN_SINGLE_PASS_ONLY 32u
 
 /*
  * A sparse matrix in CSR form, in device memory.  Columns must be strictly
@@ -575,14 +589,21 @@ void bsgd_graph_destroy(bsgd_graph* graph);
  * 4096 pixels are not supported (BSGD_ERR_UNSUPPORTED).
  *
  *   fused_workspace_size  counts the segments of `plan` (device pass over the
- *               forward store, uses the plan's scratch vectors: no other call
- *               on the plan may overlap it) and returns the workspace bytes
- *               for bsgd_fused_create with the same chunks and flags.  chunks = 0
- *               picks at least about 1024 (tile, chunk) units and chunks of at
- *               most 131072 rays; chunks <= number of ray groups.  Synchronises `stream`.
+ *               forward store, or over A's CSR for a BSGD_PLAN_SINGLE_PASS_ONLY
+ *               plan, which is also where A's columns are checked:
+ *               BSGD_ERR_INVALID for a column out of range or out of order;
+ *               such plans also need slices of at most 2^24 pixels, else
+ *               BSGD_ERR_UNSUPPORTED; uses the plan's scratch vectors: no
+ *               other call on the plan may overlap it) and returns the
+ *               workspace bytes for bsgd_fused_create with the same chunks and
+ *               flags.  chunks = 0 picks at least about 1024 (tile, chunk)
+ *               units and chunks of at most 131072 rays; chunks <= number of
+ *               ray groups.  Synchronises `stream`.
  *   fused_create  builds the store in `workspace` (device, 256-byte aligned,
  *               at least the size returned above) from the plan's forward
- *               store; the plan must outlive it.  Synchronises.
+ *               store (from A's CSR for a BSGD_PLAN_SINGLE_PASS_ONLY plan:
+ *               the same store, bitwise); the plan must outlive it.  The same
+ *               errors as above.  Synchronises.
  *   fused_shape   tiles, chunks, segments, slices (64 segments each),
  *               stored entries (with padding) and bytes per stored column (1:
  *               8-bit steps, 2: 16-bit addresses).

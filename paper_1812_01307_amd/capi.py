@@ -33,6 +33,7 @@ BSGD_PLAN_STAGED_FWD = 4
 BSGD_PLAN_STAGED_BWD = 8
 BSGD_PLAN_STAGED = 12
 BSGD_PLAN_FWD_ONLY = 16
+BSGD_PLAN_SINGLE_PASS_ONLY = 32
 BSGD_LAUNCH_NT = 128
 BSGD_STATE_VOLUME = 1
 BSGD_STATE_BLOCK_SELECT = 2
@@ -196,6 +197,7 @@ class Plan:
         self.H, self.W, self.D = H, W, D
         self.nrows, self.ncols = nrows, ncols
         self.flags = flags
+        self.source = None  # A's device arrays, kept alive by BSGD_PLAN_SINGLE_PASS_ONLY plans
 
     # the destroy function is bound at class creation: at interpreter exit the
     # module's globals may already be gone when the last objects are collected
@@ -220,7 +222,8 @@ def bsgd_plan_create(A, At, M, N, row_off, col_off, H, W, D=1, view_len=0, flags
 
     A = (nrows, ncols, row_ptr, col, val); At likewise for the transpose.  With
     BSGD_PLAN_FWD_ONLY the transpose's column array may be None (only its row
-    pointers and values are read).
+    pointers and values are read).  A BSGD_PLAN_SINGLE_PASS_ONLY plan reads A's
+    arrays again when its tile-sliced store is built: the Plan holds them.
     """
     nrows, ncols, rp, cl, vl = A
     tn, tc, trp, tcl, tvl = At
@@ -239,7 +242,10 @@ def bsgd_plan_create(A, At, M, N, row_off, col_off, H, W, D=1, view_len=0, flags
     _check("bsgd_plan_create", _lib.bsgd_plan_create(
         ctypes.byref(a), ctypes.byref(at), M, N, ro, co, H, W, D, view_len, flags, _ptr(ws),
         nbytes, _stream(stream), ctypes.byref(h)))
-    return Plan(h, ws, M, N, row_off, col_off, H, W, D, nrows, ncols, flags)
+    plan = Plan(h, ws, M, N, row_off, col_off, H, W, D, nrows, ncols, flags)
+    if flags & BSGD_PLAN_SINGLE_PASS_ONLY:
+        plan.source = (rp, cl, vl)
+    return plan
 
 
 def bsgd_plan_lanes(plan: Plan):

@@ -40,6 +40,16 @@ void clear_error();
     }                                                                                  \
   } while (0)
 
+// The call needs the block store of A, which a BSGD_PLAN_SINGLE_PASS_ONLY plan
+// lacks.
+#define BSGD_NEED_FWD(plan, what)                                                      \
+  do {                                                                                 \
+    if ((plan)->flags & BSGD_PLAN_SINGLE_PASS_ONLY) {                                  \
+      ::bsgd::set_error("%s needs the block store of A (a SINGLE_PASS_ONLY plan)", what); \
+      return BSGD_ERR_UNSUPPORTED;                                                     \
+    }                                                                                  \
+  } while (0)
+
 // The call needs the block store of A^T, which a BSGD_PLAN_FWD_ONLY plan lacks.
 #define BSGD_NEED_BWD(plan, what)                                                      \
   do {                                                                                 \
@@ -204,6 +214,11 @@ struct bsgd_plan {
   int64_t* scan_tmp = nullptr;    // block sums for scans
   int* err = nullptr;             // validation flags
   unsigned long long* colmax = nullptr;  // 2 words: column-sum / max |a| bits while building
+  // A's CSR as given (BSGD_PLAN_SINGLE_PASS_ONLY: the caller's arrays, natural order)
+  const int64_t* src_ptr = nullptr;
+  const int32_t* src_col = nullptr;
+  const float* src_val = nullptr;
+  int64_t src_nnz = 0;
   double smax = 0.0;              // largest column sum of |A| (FP64)
   double amax = 0.0;              // largest |a|
   int64_t* seg_dev = nullptr;     // segment bounds staged for the fill kernel

@@ -76,6 +76,10 @@ struct TileGeom {
   int64_t group_len = 64;    // internal rays per ray group
   int64_t ngroups = 1;
   int64_t view_len = 0;      // rays per view (0: rows without view structure)
+  int W = 1;                 // image width (natural pixel p = d H W + s W + t)
+  float rW = 1.f;            // 1 / W rounded to FP32
+  int64_t hw = 1;            // H W
+  int64_t ncols = 0;         // D H W
   int64_t tiles() const { return (int64_t)D * FTh * FTw; }
   int64_t units() const { return tiles() * Q; }
 };
@@ -118,6 +122,10 @@ static TileGeom tile_geom(const Layout& L, int chunks) {
   g.Ht = L.Ht;
   g.Wt = L.Wt;
   g.rWt = 1.0f / (float)L.Wt;
+  g.W = L.W;
+  g.rW = 1.0f / (float)L.W;
+  g.hw = (int64_t)L.H * L.W;
+  g.ncols = (int64_t)L.D * L.H * L.W;
   g.FTh = (L.Ht + 7) / 8;
   g.FTw = (L.Wt + 7) / 8;
   g.D = L.D;
@@ -171,6 +179,26 @@ __device__ __forceinline__ void decode_pixel(const TileGeom& g, int64_t cp, int&
   a = (((tr8 & 7) << 3) + (w >> 3)) * kFTS + ((tc8 & 7) << 3) + (w & 7);
 }
 
+// The same for a natural pixel index (d H W + s W + t: the columns of A as
+// given), s = rem / W from the FP32 reciprocal as above (rem < H W <= 2^24).
+__device__ __forceinline__ void decode_nat(const TileGeom& g, int64_t cp, int& G, int& f,
+                                           int& a) {
+  const int64_t d = g.D == 1 ? 0 : cp / g.hw;
+  const int rem = (int)(cp - d * g.hw);
+  int s = (int)((float)rem * g.rW);
+  int t = rem - s * g.W;
+  if (t < 0) {
+    --s;
+    t += g.W;
+  } else if (t >= g.W) {
+    ++s;
+    t -= g.W;
+  }
+  G = (int)d * g.FTh + (s >> 6);
+  f = t >> 6;
+  a = (s & 63) * kFTS + (t & 63);
+}
+
 // Walk one ray's entries (one wavefront; the entries are in ascending natural
 // pixel order, so the band key G never decreases along the row).  Lane f
 // keeps, for the current band, the rank and running length of the segment
@@ -186,12 +214,17 @@ __device__ __forceinline__ void decode_pixel(const TileGeom& g, int64_t cp, int&
 //                                      (rank < 0: no segment in column f;
 //                                      first = the segment's first address)
 //   vis.finish(nseg)
-template <class V>
-__device__ void walk_ray(const TileGeom& g, const int32_t* __restrict__ col, int64_t beg,
+// NAT: the columns are natural pixel indices (A as given) rather than the
+// block store's internal ones.  CHECK: also returns whether every column is
+// in range and the columns strictly ascend.
+template <bool NAT, bool CHECK, class V>
+__device__ bool walk_ray(const TileGeom& g, const int32_t* __restrict__ col, int64_t beg,
                          int64_t len, V& vis) {
   const int lane = threadIdx.x & 63;
   const uint64_t below = (1ull << lane) - 1ull;
   int Gcur = -1, cnt = 0, rank = -1, nseen = 0, first = 0, last = 0;
+  bool ok = true;
+  int32_t lastc = 0;  // the previous batch's last column (CHECK)
   int32_t cnext = lane < len ? col[beg + lane] : 0;
   vis.prefetch(beg + lane, lane < len);
   for (int64_t c0 = 0; c0 < len; c0 += 64) {
@@ -203,8 +236,19 @@ __device__ void walk_ray(const TileGeom& g, const int32_t* __restrict__ col, int
     // is walked
     if (e + 64 < len) cnext = col[beg + e + 64];
     vis.prefetch(beg + e + 64, e + 64 < len);
+    if constexpr (CHECK) {
+      const int32_t up = __shfl_up(cp, 1);
+      const int32_t prev = lane == 0 ? lastc : up;
+      if (valid && (cp < 0 || cp >= g.ncols || (e > 0 && cp <= prev))) ok = false;
+      lastc = __shfl(cp, 63);
+    }
     int G = 0x7fffffff, f = 0, a = 0;
-    if (valid) decode_pixel(g, cp, G, f, a);
+    if (valid) {
+      if constexpr (NAT)
+        decode_nat(g, cp, G, f, a);
+      else
+        decode_pixel(g, cp, G, f, a);
+    }
     bool done = !valid;
     uint64_t live;
     while ((live = __ballot(!done)) != 0ull) {
@@ -249,6 +293,7 @@ __device__ void walk_ray(const TileGeom& g, const int32_t* __restrict__ col, int
   }
   if (Gcur >= 0) vis.close(Gcur, lane, cnt, rank, first);
   vis.finish(nseen);
+  return __ballot(!ok) == 0ull;
 }
 
 // Raise *word to v (one word shared by the whole grid: read first, so that
@@ -377,10 +422,15 @@ struct VisFill {
   __device__ void finish(int) {}
 };
 
-// MODE 0: count, 1: segments, 2: fill.  One wavefront per internal ray.
-template <int MODE>
+// MODE 0: count, 1: segments, 2: fill.  One wavefront per internal ray.  The
+// rows come from the block store of A (ptr, seg: internal order and columns)
+// or, NAT, from A as given (ptr = row_ptr of the natural rows, internal ray
+// k being natural row L.ray_out(k)); the NAT count also checks the columns
+// and sets *err on a bad one.
+template <int MODE, bool NAT>
 __global__ __launch_bounds__(256) void k_fz_walk(
-    TileGeom g, const int64_t* __restrict__ ptr, const int32_t* __restrict__ seg, int nseg,
+    TileGeom g, Layout L, const int64_t* __restrict__ ptr, const int32_t* __restrict__ seg,
+    int nseg,
     const int32_t* __restrict__ col, const float* __restrict__ vsrc,
     const __half* __restrict__ v16src, int64_t r_int, int64_t* ncross, int32_t* maxc,
     int32_t* maxlen, int32_t* maxstep, const int64_t* poff, uint64_t* key, int32_t* idx,
@@ -397,22 +447,74 @@ __global__ __launch_bounds__(256) void k_fz_walk(
   }
   const int64_t k = (b * 256 + threadIdx.x) >> 6;
   if (k >= r_int) return;  // uniform per wavefront
-  const int64_t beg = ptr[k];
-  const int64_t len = seg[k * (nseg + 1) + nseg];
+  int64_t beg = 0, len = 0;
+  if constexpr (NAT) {
+    const int64_t n = L.ray_out(k);  // -1: a hole of the internal order (no entries)
+    if (n >= 0) {
+      beg = ptr[n];
+      len = ptr[n + 1] - beg;
+    }
+  } else {
+    beg = ptr[k];
+    len = seg[k * (nseg + 1) + nseg];
+  }
   const int q = chunk_of(g, k);
   if constexpr (MODE == 0) {
     VisCount v{k, ncross, maxc, maxlen, maxstep};
-    walk_ray(g, col, beg, len, v);
+    const bool ok = walk_ray<NAT, NAT>(g, col, beg, len, v);
+    if (NAT && !ok && (threadIdx.x & 63) == 0) atomicOr(err, 1);
   } else if constexpr (MODE == 1) {
     VisPairs v{g, k, q, poff[k], key, idx, pray, pbase};
-    walk_ray(g, col, beg, len, v);
+    walk_ray<NAT, false>(g, col, beg, len, v);
   } else {
     const int64_t pk = poff[k], nr = poff[k + 1] - pk;
     const int lane = threadIdx.x & 63;
     const int64_t dpre = lane < nr ? pdst[pk + lane] : 0;
     VisFill v{pk, dpre, 0, pdst, vsrc, v16src, ocol, ocol8, oval, oval16, err};
-    walk_ray(g, col, beg, len, v);
+    walk_ray<NAT, false>(g, col, beg, len, v);
   }
+}
+
+// A's rows for the walks: the block store of A, or A as given
+// (BSGD_PLAN_SINGLE_PASS_ONLY).
+struct WalkSrc {
+  bool nat = false;
+  const int64_t* ptr = nullptr;
+  const int32_t* seg = nullptr;
+  int nseg = 0;
+  const int32_t* col = nullptr;
+  const float* val = nullptr;
+  const __half* val16 = nullptr;
+  int64_t nnz = 0;
+};
+
+static WalkSrc walk_src(const bsgd_plan* p) {
+  WalkSrc w;
+  if (p->flags & BSGD_PLAN_SINGLE_PASS_ONLY) {
+    w.nat = true;
+    w.ptr = p->src_ptr;
+    w.col = p->src_col;
+    w.val = p->src_val;
+    w.nnz = p->src_nnz;
+  } else {
+    w.ptr = p->fwd.ptr;
+    w.seg = p->fwd.seg;
+    w.nseg = p->fwd.nseg;
+    w.col = p->fwd.col;
+    w.val = p->fwd.val;
+    w.val16 = p->fwd.val16;
+    w.nnz = p->fwd.nnz;
+  }
+  return w;
+}
+
+template <int MODE, typename... Args>
+static void launch_walk(const WalkSrc& w, const TileGeom& g, const Layout& L, unsigned blocks,
+                        hipStream_t s, Args... args) {
+  if (w.nat)
+    k_fz_walk<MODE, true><<<blocks, 256, 0, s>>>(g, L, w.ptr, w.seg, w.nseg, w.col, args...);
+  else
+    k_fz_walk<MODE, false><<<blocks, 256, 0, s>>>(g, L, w.ptr, w.seg, w.nseg, w.col, args...);
 }
 
 // First and last sorted position of each unit (keys sorted by unit first);
@@ -1328,27 +1430,32 @@ static bsgd_status fused_count(const bsgd_plan* p, const TileGeom& g, bool wide,
   const Layout& L = p->L;
   const int64_t units = g.units();
   int32_t* words = reinterpret_cast<int32_t*>(p->vin);  // maxc, maxlen, maxstep
-  k_fill_i32<<<1, 256, 0, s>>>(words, 3);
+  int* err = reinterpret_cast<int*>(words + 4);
+  k_fill_i32<<<1, 256, 0, s>>>(words, 5);
   BSGD_LAUNCH_CHECK();
   const unsigned blocks = (unsigned)((L.r_int * 64 + 255) / 256);
-  k_fz_walk<0><<<blocks, 256, 0, s>>>(g, p->fwd.ptr, p->fwd.seg, p->fwd.nseg, p->fwd.col,
-                                      nullptr, nullptr, L.r_int, p->scratch64, words, words + 1,
-                                      words + 2, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                      nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+  const WalkSrc w = walk_src(p);
+  launch_walk<0>(w, g, L, blocks, s, nullptr, nullptr, L.r_int, p->scratch64, words, words + 1,
+                 words + 2, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                 nullptr, nullptr, nullptr, err);
   BSGD_LAUNCH_CHECK();
   BSGD_HIP(exclusive_scan_i64(p->scratch64, p->scratch64, L.r_int, p->scan_tmp, s));
-  int32_t hw[3] = {0, 0, 0};
+  int32_t hw[5] = {0, 0, 0, 0, 0};
   BSGD_HIP(hipMemcpyAsync(&fc.pairs, p->scratch64 + L.r_int, sizeof(int64_t),
                           hipMemcpyDeviceToHost, s));
   BSGD_HIP(hipMemcpyAsync(hw, words, sizeof(hw), hipMemcpyDeviceToHost, s));
   BSGD_HIP(hipStreamSynchronize(s));
+  if (hw[4] != 0) {
+    set_error("A's column indices are out of range or not ascending within a row");
+    return BSGD_ERR_INVALID;
+  }
   fc.maxrank = hw[0];
   fc.maxlen = hw[1];
   fc.maxstep = hw[2];
   fc.narrow = !wide && fc.maxstep < 256;
   BSGD_REQUIRE(fc.maxrank < 65536, "a ray crosses %d tiles (at most 65535)", fc.maxrank);
   fc.slices = (fc.pairs + 63) / 64 + units;
-  fc.bound = p->fwd.nnz + units * 64 * ((int64_t)fc.maxlen + 3) + 192 * fc.slices;
+  fc.bound = w.nnz + units * 64 * ((int64_t)fc.maxlen + 3) + 192 * fc.slices;
   BSGD_REQUIRE(fc.slices * 64 < ((int64_t)1 << 31), "too many slices (%lld)",
                (long long)fc.slices);
   cc.Q = g.Q;
@@ -1388,7 +1495,7 @@ static size_t fused_layout(const bsgd_plan* p, const TileGeom& g, const FusedCou
   const int64_t units = g.units();
   const int64_t nslots = std::max<int64_t>(fc.slices, 1) * 64;
   const int64_t np = std::max<int64_t>(fc.pairs, 1);
-  const bool f16 = p->fwd.val16 != nullptr;
+  const bool f16 = (p->flags & BSGD_PLAN_F16) != 0;
   F->sbeg = cv.take<int32_t>(units + 1);
   F->uorder = cv.take<int32_t>(units);
   F->sng = cv.take<int32_t>(std::max<int64_t>(fc.slices, 1));
@@ -1450,7 +1557,12 @@ static bsgd_status fused_check(const bsgd_plan* p, int chunks, unsigned flags, T
   BSGD_REQUIRE(g->units() * kKeyLen < ((int64_t)1 << 32) &&
                    g->units() < std::max(L.r_int, L.c_int),
                "too many tiles x chunks (%lld)", (long long)g->units());
-  BSGD_REQUIRE(p->fwd.nnz < ((int64_t)1 << 31), "too many entries");
+  BSGD_REQUIRE(walk_src(p).nnz < ((int64_t)1 << 31), "too many entries");
+  if ((p->flags & BSGD_PLAN_SINGLE_PASS_ONLY) && (int64_t)L.H * L.W > ((int64_t)1 << 24)) {
+    // A's natural columns are split into (row, column) with an FP32 reciprocal
+    set_error("a plan without a block store supports slices of at most 2^24 pixels");
+    return BSGD_ERR_UNSUPPORTED;
+  }
   return BSGD_OK;
 }
 
@@ -1498,7 +1610,7 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, unsi
     return BSGD_ERR_WORKSPACE;
   }
   const Layout& L = plan->L;
-  const Store& A = plan->fwd;
+  const WalkSrc A = walk_src(plan);
   const int64_t units = g.units();
   const unsigned wblocks = (unsigned)((L.r_int * 64 + 255) / 256);
   auto fail = [&](bsgd_status s) {
@@ -1517,10 +1629,9 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, unsi
   k_i64_to_i32<<<grid_for(L.r_int + 1), 256, 0, stream>>>(plan->scratch64, F->poff, L.r_int + 1);
   k_fz_unit_init<<<grid_for(units), 256, 0, stream>>>(T.first, T.last, units);
   if (fc.pairs > 0) {
-    k_fz_walk<1><<<wblocks, 256, 0, stream>>>(
-        g, A.ptr, A.seg, A.nseg, A.col, nullptr, nullptr, L.r_int, nullptr, nullptr, nullptr,
-        nullptr, plan->scratch64, T.key, T.idx, T.pray, T.pbase, nullptr, nullptr, nullptr,
-        nullptr, nullptr, nullptr);
+    launch_walk<1>(A, g, L, wblocks, stream, nullptr, nullptr, L.r_int, nullptr, nullptr,
+                   nullptr, nullptr, plan->scratch64, T.key, T.idx, T.pray, T.pbase, nullptr,
+                   nullptr, nullptr, nullptr, nullptr, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "segment pass");
     size_t cb = T.cub_bytes;
@@ -1594,10 +1705,9 @@ extern "C" bsgd_status bsgd_fused_create(const bsgd_plan* plan, int chunks, unsi
   }
   if (fc.pairs > 0) {
     k_fz_dst<<<grid_for(fc.pairs), 256, 0, stream>>>(T.pos, fc.pairs, F->soff, F->sng, T.pdst);
-    k_fz_walk<2><<<(wblocks + 7) / 8 * 8, 256, 0, stream>>>(
-        g, A.ptr, A.seg, A.nseg, A.col, A.val, A.val16, L.r_int, nullptr, nullptr, nullptr,
-        nullptr, plan->scratch64, nullptr, nullptr, nullptr, nullptr, T.pdst, F->col, F->col8,
-        F->val, F->val16, T.err);
+    launch_walk<2>(A, g, L, (wblocks + 7) / 8 * 8, stream, A.val, A.val16, L.r_int, nullptr,
+                   nullptr, nullptr, nullptr, plan->scratch64, nullptr, nullptr, nullptr,
+                   nullptr, T.pdst, F->col, F->col8, F->val, F->val16, T.err);
     k_fz_pad<<<grid_for(nslots), 256, 0, stream>>>(T.slen, F->sng, F->soff, nslots, F->col,
                                                    F->col8, F->val, F->val16);
     e = hipGetLastError();

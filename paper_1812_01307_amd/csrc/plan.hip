@@ -246,8 +246,9 @@ static size_t plan_layout(bsgd_plan* p, void* ws, const Layout& L, int64_t nnz, 
                           unsigned flags) {
   Carver cv(ws);
   const bool f16 = (flags & BSGD_PLAN_F16) != 0;
-  carve_store(cv, p->fwd, L.r_int, nnz, N, f16);
-  if (!(flags & BSGD_PLAN_FWD_ONLY)) carve_store(cv, p->bwd, L.c_int, nnz, M, f16);
+  if (!(flags & BSGD_PLAN_SINGLE_PASS_ONLY)) carve_store(cv, p->fwd, L.r_int, nnz, N, f16);
+  if (!(flags & (BSGD_PLAN_FWD_ONLY | BSGD_PLAN_SINGLE_PASS_ONLY)))
+    carve_store(cv, p->bwd, L.c_int, nnz, M, f16);
   if (flags & BSGD_PLAN_STAGED) {
     if (flags & BSGD_PLAN_STAGED_FWD) carve_staged(cv, p->sfwd, L, true, nnz, f16);
     if (flags & BSGD_PLAN_STAGED_BWD) carve_staged(cv, p->sbwd, L, false, nnz, f16);
@@ -560,10 +561,13 @@ extern "C" bsgd_status bsgd_plan_workspace_size(int64_t nrows, int64_t ncols, in
   clear_error();
   BSGD_REQUIRE(bytes != nullptr, "bytes is NULL");
   BSGD_REQUIRE((flags & ~(BSGD_PLAN_F16 | BSGD_PLAN_AUTOTUNE | BSGD_PLAN_STAGED |
-                          BSGD_PLAN_FWD_ONLY)) == 0,
+                          BSGD_PLAN_FWD_ONLY | BSGD_PLAN_SINGLE_PASS_ONLY)) == 0,
                "unknown plan flags 0x%x", flags);
   BSGD_REQUIRE(!((flags & BSGD_PLAN_FWD_ONLY) && (flags & BSGD_PLAN_STAGED_BWD)),
                "BSGD_PLAN_FWD_ONLY excludes BSGD_PLAN_STAGED_BWD");
+  BSGD_REQUIRE(!((flags & BSGD_PLAN_SINGLE_PASS_ONLY) &&
+                 (flags & (BSGD_PLAN_STAGED | BSGD_PLAN_AUTOTUNE))),
+               "BSGD_PLAN_SINGLE_PASS_ONLY excludes the staged forms and BSGD_PLAN_AUTOTUNE");
   bsgd_status st = check_sizes(nrows, ncols, nnz, M, N, H, W, D, view_len);
   if (st != BSGD_OK) return st;
   bsgd_plan tmp;
@@ -579,11 +583,16 @@ extern "C" bsgd_status bsgd_plan_create(const bsgd_csr* A, const bsgd_csr* At, i
   clear_error();
   BSGD_REQUIRE(A && At && row_off && col_off && workspace && out, "NULL argument");
   BSGD_REQUIRE((flags & ~(BSGD_PLAN_F16 | BSGD_PLAN_AUTOTUNE | BSGD_PLAN_STAGED |
-                          BSGD_PLAN_FWD_ONLY)) == 0,
+                          BSGD_PLAN_FWD_ONLY | BSGD_PLAN_SINGLE_PASS_ONLY)) == 0,
                "unknown plan flags 0x%x", flags);
   BSGD_REQUIRE(!((flags & BSGD_PLAN_FWD_ONLY) && (flags & BSGD_PLAN_STAGED_BWD)),
                "BSGD_PLAN_FWD_ONLY excludes BSGD_PLAN_STAGED_BWD");
+  BSGD_REQUIRE(!((flags & BSGD_PLAN_SINGLE_PASS_ONLY) &&
+                 (flags & (BSGD_PLAN_STAGED | BSGD_PLAN_AUTOTUNE))),
+               "BSGD_PLAN_SINGLE_PASS_ONLY excludes the staged forms and BSGD_PLAN_AUTOTUNE");
   BSGD_REQUIRE(((uintptr_t)workspace % kAlign) == 0, "workspace must be 256-byte aligned");
+  const bool no_store = (flags & BSGD_PLAN_SINGLE_PASS_ONLY) != 0;
+  if (no_store) flags |= BSGD_PLAN_FWD_ONLY;  // refuses every call that needs A^T's store
   const bool fwd_only = (flags & BSGD_PLAN_FWD_ONLY) != 0;
   BSGD_REQUIRE(A->row_ptr && A->col && A->val && At->row_ptr && (At->col || fwd_only) &&
                    At->val,
@@ -617,8 +626,18 @@ extern "C" bsgd_status bsgd_plan_create(const bsgd_csr* A, const bsgd_csr* At, i
   p->row_off.assign(row_off, row_off + M + 1);
   p->col_off.assign(col_off, col_off + N + 1);
   plan_layout(p, workspace, p->L, A->nnz, M, N, flags);
-  st = build_store<true>(p->fwd, *A, p->L, p->col_off, p->seg_dev, p->scratch64, p->scan_tmp,
-                         p->err, stream, "A");
+  if (no_store) {
+    // the tile-sliced store is built straight from A (its columns are
+    // checked then); the row pointers are checked here
+    st = check_row_ptr(*A, p->err, stream, "A");
+    p->src_ptr = A->row_ptr;
+    p->src_col = A->col;
+    p->src_val = A->val;
+    p->src_nnz = A->nnz;
+  } else {
+    st = build_store<true>(p->fwd, *A, p->L, p->col_off, p->seg_dev, p->scratch64, p->scan_tmp,
+                           p->err, stream, "A");
+  }
   if (st == BSGD_OK && !fwd_only)
     st = build_store<false>(p->bwd, *At, p->L, p->row_off, p->seg_dev, p->scratch64, p->scan_tmp,
                             p->err, stream, "At");
@@ -762,6 +781,7 @@ extern "C" bsgd_status bsgd_tile_nnz(const bsgd_plan* plan, int i, int j, hipStr
   bsgd_status s = tile_rows(plan, i, j, 0, &row0, &nrows, &segk, &col_base);
   if (s != BSGD_OK) return s;
   BSGD_REQUIRE(nnz != nullptr, "nnz is NULL");
+  BSGD_NEED_FWD(plan, "bsgd_tile_nnz");
   const Store& st = plan->fwd;
   const unsigned blocks = (unsigned)std::min<int64_t>((nrows + 255) / 256, 65535);
   plan->fz_count.valid = false;  // scratch64 is overwritten
@@ -788,6 +808,7 @@ extern "C" bsgd_status bsgd_tile_export(const bsgd_plan* plan, int i, int j, int
   bsgd_status s = tile_rows(plan, i, j, transposed, &row0, &nrows, &segk, &col_base);
   if (s != BSGD_OK) return s;
   BSGD_REQUIRE(ptr && col && val, "NULL output");
+  BSGD_NEED_FWD(plan, "bsgd_tile_export");
   if (transposed) BSGD_NEED_BWD(plan, "bsgd_tile_export (transposed)");
   const Store& st = transposed ? plan->bwd : plan->fwd;
   const unsigned blocks = (unsigned)std::min<int64_t>((nrows + 255) / 256, 65535);

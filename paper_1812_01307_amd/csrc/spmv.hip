@@ -534,6 +534,7 @@ extern "C" bsgd_status bsgd_forward(const bsgd_plan* plan, bsgd_valtype vt, cons
   bsgd_status st = check_vt(plan, vt);
   if (st != BSGD_OK) return st;
   BSGD_REQUIRE(x != nullptr && out != nullptr, "x and out must be non-NULL");
+  BSGD_NEED_FWD(plan, "bsgd_forward");
   const Layout& L = plan->L;
   BSGD_HIP(permute_in(L, kPixels, x, plan->vin, stream));
   if (y) BSGD_HIP(permute_in(L, kRays, y, plan->vaux, stream));
@@ -573,6 +574,7 @@ extern "C" bsgd_status bsgd_forward_block(const bsgd_plan* plan, bsgd_valtype vt
   BSGD_REQUIRE(i >= 0 && i < plan->M && j >= 0 && j < plan->N, "block (%d, %d) out of range", i,
                j);
   BSGD_REQUIRE(xj != nullptr && z != nullptr, "xj and z must be non-NULL");
+  BSGD_NEED_FWD(plan, "bsgd_forward_block");
   const int64_t r0 = plan->row_off[i], r1 = plan->row_off[i + 1];
   BSGD_HIP(launch_segment_rows(plan, true, vt, r0, r1 - r0, j, plan->col_off[j], xj, 1.0f, z,
                                stream));

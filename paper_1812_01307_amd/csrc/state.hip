@@ -544,6 +544,7 @@ extern "C" bsgd_status bsgd_state_init(bsgd_state* st, const float* y, const flo
   clear_error();
   BSGD_REQUIRE(st && y, "NULL argument");
   const bsgd_plan* p = st->plan;
+  if (x0) BSGD_NEED_FWD(p, "bsgd_state_init with x0");
   const int S = st->nrhs;
   const int64_t r = p->L.r_int * S, c = p->L.c_int * S;
   BSGD_HIP(permute_in(p->L, kRays, y, st->y, stream, S));
@@ -1117,6 +1118,7 @@ extern "C" bsgd_status bsgd_state_set_rhs(bsgd_state* st, int k, const float* y,
   BSGD_REQUIRE(st->initialised, "state_init must be called first");
   BSGD_REQUIRE(k >= 0 && k < st->nrhs, "slot %d out of range", k);
   const bsgd_plan* p = st->plan;
+  if (y && x0) BSGD_NEED_FWD(p, "bsgd_state_set_rhs with x0");
   const Layout& L = p->L;
   const int S = st->nrhs, c = st->cur;
   // y == NULL empties the slot (all its vectors zero: it stays zero)

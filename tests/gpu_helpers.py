@@ -33,14 +33,16 @@ def f32(a):
     return np.asarray(a, np.float32)
 
 
-def plan_for(p, f16=False, view_len=None, autotune=False, staged=False, fwd_only=False):
+def plan_for(p, f16=False, view_len=None, autotune=False, staged=False, fwd_only=False,
+             single_pass=False):
     """Plan with the view structure of the generator's rays (view_len = bins) by default."""
     import paper_1812_01307_amd as bsgd
     tp, tc, tv = p.ensure_transpose()
     vl = p.bins if view_len is None else view_len
     return bsgd.plan_from_host(p.nrows, p.ncols, p.row_ptr, p.col, p.val, tp, tc, tv, p.M, p.N,
                                p.row_off, p.col_off, p.H, p.W, 1, view_len=vl, f16=f16,
-                               autotune=autotune, staged=staged, fwd_only=fwd_only)
+                               autotune=autotune, staged=staged, fwd_only=fwd_only,
+                               single_pass=single_pass)
 
 
 def matrix(p):

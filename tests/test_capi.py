@@ -51,6 +51,18 @@ def test_size_queries_and_argument_errors():
     with pytest.raises(capi.BsgdError, match="STAGED_BWD"):
         capi.bsgd_plan_workspace_size(8190, 4096, 477832, 2, 2, 64, 64, 1, 91,
                                       capi.BSGD_PLAN_FWD_ONLY | capi.BSGD_PLAN_STAGED_BWD)
+    # without any block store: vectors and scratch only (no bytes per entry)
+    bsp = capi.bsgd_plan_workspace_size(8190, 4096, 477832, 2, 2, 64, 64, 1, 91,
+                                        capi.BSGD_PLAN_SINGLE_PASS_ONLY)
+    assert bsp < bfo - 4 * 477832
+    assert bsp == capi.bsgd_plan_workspace_size(
+        8190, 4096, 477832, 2, 2, 64, 64, 1, 91,
+        capi.BSGD_PLAN_SINGLE_PASS_ONLY | capi.BSGD_PLAN_FWD_ONLY | capi.BSGD_PLAN_F16)
+    for extra in (capi.BSGD_PLAN_STAGED_FWD, capi.BSGD_PLAN_AUTOTUNE):
+        with pytest.raises(capi.BsgdError) as e:
+            capi.bsgd_plan_workspace_size(8190, 4096, 477832, 2, 2, 64, 64, 1, 91,
+                                          capi.BSGD_PLAN_SINGLE_PASS_ONLY | extra)
+        assert e.value.status == capi.BSGD_ERR_INVALID
     assert capi.bsgd_tv_workspace_size(16, 16, 4) >= 13 * 16 * 16 * 4
     with pytest.raises(capi.BsgdError):
         capi.bsgd_tv_workspace_size(0, 5, 1)

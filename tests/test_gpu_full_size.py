@@ -35,11 +35,13 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def _plan(p, f16=False):
+def _plan(p, f16=False, single_pass=True):
+    """The bench's plan: no block stores (the tile-sliced store is built from A's CSR)."""
     import paper_1812_01307_amd as bsgd
     tp, tc, tv = p.ensure_transpose()
     return bsgd.plan_from_host(p.nrows, p.ncols, p.row_ptr, p.col, p.val, tp, tc, tv, p.M, p.N,
-                               p.row_off, p.col_off, p.H, p.W, 1, view_len=p.bins, f16=f16)
+                               p.row_off, p.col_off, p.H, p.W, 1, view_len=p.bins, f16=f16,
+                               fwd_only=True, single_pass=single_pass)
 
 
 def _store(plan):
@@ -92,6 +94,16 @@ def test_c2_512_single_pass_trajectory_matches_oracle():
             # the prox changed the iterate by far more than the tolerance
             xhat_only, _ = oracle.bsgd_tv(A, y64, mu, 0.0, 1, 1, (p.H, p.W))
             assert rel_l2(ref[0], xhat_only) > 100 * ITERATE_REL
+    # the store built from the block store of A is the same store
+    print("c2_512: store from the block store of A", flush=True)
+    x_bare = _epochs(plan, F, y32, mu, 2000.0, 3, p.prox_iters)
+    del F, plan
+    plan_a = _plan(p, single_pass=False)
+    F_a = _store(plan_a)
+    assert bsgd.bsgd_fused_shape(F_a) == (tiles, chunks, segs, slices, entries, cbytes)
+    assert bsgd.bsgd_lanczos_umax_fused(F_a, 10) == u
+    x_a = _epochs(plan_a, F_a, y32, mu, 2000.0, 3, p.prox_iters)
+    assert all(np.array_equal(a, b) for a, b in zip(x_bare, x_a))
 
 
 @pytest.mark.timeout(600)

@@ -464,3 +464,132 @@ def test_fwd_only_plan_refuses_calls_that_need_the_transpose():
                             p.M, p.N, p.row_off, p.col_off, p.H, p.W, 1, view_len=p.bins,
                             staged="bwd", fwd_only=True)
     assert e.value.status == bsgd.BSGD_ERR_INVALID
+
+
+@pytest.mark.parametrize("name,f16", [("c1", False), ("medium", False), ("ragged", False),
+                                      ("strip", False), ("medium", True)])
+def test_single_pass_only_plan_builds_the_same_store_from_a(name, f16):
+    """A plan without block stores builds the tile-sliced store from A's CSR:
+    the block store keeps A's entries in row order, so both builds walk the
+    same entries in the same order and give the same store; the Lanczos
+    estimate and one-RHS, batch and ISTA epochs equal the full plan's bitwise."""
+    import paper_1812_01307_amd as bsgd
+    p = _cases()[name]()
+    full, bare = plan_for(p, f16=f16), plan_for(p, f16=f16, single_pass=True)
+    F_full, F_bare = _fused(full), _fused(bare)
+    assert bsgd.bsgd_fused_shape(F_full) == bsgd.bsgd_fused_shape(F_bare)
+    vt = bsgd.BSGD_VAL_F16 if f16 else bsgd.BSGD_VAL_F32
+    assert (bsgd.bsgd_lanczos_umax_fused(F_bare, 6, vt=vt)
+            == bsgd.bsgd_lanczos_umax_fused(F_full, 6, vt=vt))
+    rng = np.random.default_rng(11)
+    x = _dev(f32(rng.random(p.ncols)))
+    r = _dev(f32(rng.standard_normal(p.nrows)))
+    for a, b in zip(bsgd.bsgd_fused_apply(F_full, x, r, vt=vt),
+                    bsgd.bsgd_fused_apply(F_bare, x, r, vt=vt)):
+        assert np.array_equal(_host(a), _host(b))
+    mu = float(np.float32(mu_for(p)))
+    y4 = np.stack([f32(p.y) * s for s in (1.0, 0.5, 2.0, 0.0)])
+
+    def run(plan, F, S, ista=False):
+        st = bsgd.bsgd_state_create(plan, S, vt)
+        bsgd.bsgd_state_attach_fused(st, F)
+        if ista:
+            bsgd.bsgd_state_set_method(st, bsgd.BSGD_METHOD_ISTA)
+        y = f32(p.y) if S == 1 else np.ascontiguousarray(y4[:S].T).ravel()
+        bsgd.bsgd_state_init(st, _dev(f32(y)))
+        bsgd.bsgd_run_epochs(st, mu, 20.0, 5, 20)
+        return _host(bsgd.bsgd_get_x(st))
+
+    for S, ista in ((1, False), (4, False), (1, True)):
+        assert np.array_equal(run(full, F_full, S, ista), run(bare, F_bare, S, ista)), (S, ista)
+
+
+def test_single_pass_only_plan_matches_oracle():
+    """The store built from A's CSR against the FP64 oracle directly (products
+    and a 12-epoch trajectory on the ragged geometry)."""
+    import paper_1812_01307_amd as bsgd
+    p = _cases()["ragged"]()
+    plan = plan_for(p, single_pass=True)
+    F = _fused(plan)
+    rng = np.random.default_rng(5)
+    x = f32(rng.random(p.ncols))
+    r = f32(rng.standard_normal(p.nrows))
+    ax, g = bsgd.bsgd_fused_apply(F, _dev(x), _dev(r))
+    A, Aabs = matrix(p), abs_matrix(p)
+    assert np.all(np.abs(_host(ax) - A @ x) <= PRODUCT_REL * (Aabs @ np.abs(x)) + 1e-30)
+    assert np.all(np.abs(_host(g) - 2 * (A.T @ r)) <= PRODUCT_REL * 2 * (Aabs.T @ np.abs(r))
+                  + 1e-30)
+    mu = float(np.float32(mu_for(p)))
+    _, _, ref = oracle.bsgd_tv(A, f32(p.y).astype(np.float64), mu, 5.0, 12, 20, (p.H, p.W),
+                               record=True)
+    xs, _ = _run(p, plan, F, mu, 5.0, 12, 20)
+    assert max(rel_l2(a, b) for a, b in zip(xs, ref)) <= ITERATE_REL
+
+
+def test_single_pass_only_plan_refuses_calls_that_need_a_block_store():
+    import paper_1812_01307_amd as bsgd
+    p = problem("c1_64")
+    plan = plan_for(p, single_pass=True)
+    assert plan.source is not None  # the plan holds A's device arrays
+    y = _dev(f32(p.y))
+    x = _dev(f32(np.ones(p.ncols)))
+
+    def unsupported(fn, *a, **k):
+        with pytest.raises(bsgd.BsgdError) as e:
+            fn(*a, **k)
+        assert e.value.status == bsgd.BSGD_ERR_UNSUPPORTED, fn
+
+    unsupported(bsgd.bsgd_forward, plan, x)
+    unsupported(bsgd.bsgd_forward_block, plan, 0, 0,
+                _dev(f32(np.ones(p.col_off[1] - p.col_off[0]))))
+    unsupported(bsgd.bsgd_tile_nnz, plan, 0, 0)
+    unsupported(bsgd.bsgd_tile_export, plan, 0, 0)
+    unsupported(bsgd.bsgd_backproject, plan, y)
+    unsupported(bsgd.bsgd_power_umax, plan, 3)
+    unsupported(bsgd.bsgd_state_create, plan, 1, flags=bsgd.BSGD_STATE_BLOCK_SELECT)
+    st = bsgd.bsgd_state_create(plan, 1)
+    unsupported(bsgd.bsgd_state_init, st, y, x)
+    st4 = bsgd.bsgd_state_create(plan, 4)
+    bsgd.bsgd_state_init(st4, _dev(np.zeros(p.nrows * 4, np.float32)))
+    unsupported(bsgd.bsgd_state_set_rhs, st4, 0, y, x)
+    # without x0 the states start (r = y) and run on the tile-sliced store
+    F = _fused(plan)
+    mu = float(np.float32(mu_for(p)))
+    bsgd.bsgd_state_init(st, y)
+    bsgd.bsgd_state_attach_fused(st, F)
+    bsgd.bsgd_run_epochs(st, mu, 20.0, 1, 20)
+    bsgd.bsgd_state_set_rhs(st4, 0, y)
+    bsgd.bsgd_state_attach_fused(st4, F)
+    bsgd.bsgd_run_epochs(st4, mu, 20.0, 1, 20)
+    for staged in (True, "fwd"):
+        with pytest.raises(bsgd.BsgdError) as e:
+            plan_for(p, single_pass=True, staged=staged)
+        assert e.value.status == bsgd.BSGD_ERR_INVALID
+    with pytest.raises(bsgd.BsgdError) as e:
+        plan_for(p, single_pass=True, autotune=True)
+    assert e.value.status == bsgd.BSGD_ERR_INVALID
+
+
+@pytest.mark.parametrize("fault", ["order", "duplicate", "range"])
+def test_single_pass_only_plan_checks_a_columns_at_store_build(fault):
+    """Without a block store, A's columns are first read by the store build's
+    count pass, which rejects a column out of range or out of order (the
+    count pass only compares columns; nothing is addressed with them)."""
+    import paper_1812_01307_amd as bsgd
+    p = problem("c1_64")
+    col = p.col.copy()
+    k = int(np.argmax(np.diff(p.row_ptr) >= 3))  # a row with 3 entries or more
+    a = int(p.row_ptr[k])
+    if fault == "order":
+        col[a], col[a + 1] = col[a + 1], col[a]
+    elif fault == "duplicate":
+        col[a + 1] = col[a]
+    else:
+        col[int(p.row_ptr[k + 1]) - 1] = p.ncols
+    plan = bsgd.plan_from_host(p.nrows, p.ncols, p.row_ptr, col, p.val, *p.ensure_transpose(),
+                               p.M, p.N, p.row_off, p.col_off, p.H, p.W, 1, view_len=p.bins,
+                               single_pass=True)
+    for fn in (bsgd.bsgd_fused_workspace_size, bsgd.bsgd_fused_create):
+        with pytest.raises(bsgd.BsgdError, match="column") as e:
+            fn(plan, 0)
+        assert e.value.status == bsgd.BSGD_ERR_INVALID

@@ -43,27 +43,27 @@ TIMING_STRIDE = 20
 PMC_TRAFFIC = {
     # profiles/k_fused_c2_512_hbm_counters.md
     ("fused", "c2_512", "f32"): {
-        "sha256": "e45f669262920ce0279a11f58a77ceb46989a33acaab42a18449c9305de8bd8e",
-        "bytes": 1335219423},
+        "sha256": "531e026cd92f25e1b3c117a7a16ae42112894ee27d2b27c1ea5868c3b0ce23f4",
+        "bytes": 1334830934},
     # profiles/k_fused_f16_c2_512_counters.md
     ("fused", "c2_512", "f16"): {
-        "sha256": "e45f669262920ce0279a11f58a77ceb46989a33acaab42a18449c9305de8bd8e",
-        "bytes": 832946201},
+        "sha256": "531e026cd92f25e1b3c117a7a16ae42112894ee27d2b27c1ea5868c3b0ce23f4",
+        "bytes": 833035240},
     # profiles/k_fused_ista_c2_512_hbm_counters.md (the A x-only pass)
     ("fused", "c2_512", "f32", "ista"): {
-        "sha256": "e45f669262920ce0279a11f58a77ceb46989a33acaab42a18449c9305de8bd8e",
-        "bytes": 1310718301},
+        "sha256": "531e026cd92f25e1b3c117a7a16ae42112894ee27d2b27c1ea5868c3b0ce23f4",
+        "bytes": 1310701130},
     ("fused", "c2_512", "f32", "gd"): {
-        "sha256": "e45f669262920ce0279a11f58a77ceb46989a33acaab42a18449c9305de8bd8e",
-        "bytes": 1310718301},
+        "sha256": "531e026cd92f25e1b3c117a7a16ae42112894ee27d2b27c1ea5868c3b0ce23f4",
+        "bytes": 1310701130},
     # profiles/k_vol_c4_hbm_counters.md (256 slices, 4 ray chunks)
     ("fused_mr", "c4_vol", "f32", 256, 4, "fwd"): {
-        "sha256": "e45f669262920ce0279a11f58a77ceb46989a33acaab42a18449c9305de8bd8e",
-        "bytes": 25352154612},
+        "sha256": "531e026cd92f25e1b3c117a7a16ae42112894ee27d2b27c1ea5868c3b0ce23f4",
+        "bytes": 24373336461},
     # profiles/k_sel_c2_512_hbm_counters.md (mean over the 1600 draws of the profiled run)
     ("selected", "c2_512", "f32", 0.5, 0.5, 7, "fwd"): {
-        "sha256": "0042c05c367575aa47a0e2725c16df3b9585bdf6b007b36c201bf6c18005155d",
-        "bytes": 613975405},
+        "sha256": "c728dbcea262256a957619bee4d5312fec92291854392e78ec8675b75a806624",
+        "bytes": 614003335},
 }
 
 

@@ -43,27 +43,27 @@ TIMING_STRIDE = 20
 PMC_TRAFFIC = {
     # profiles/k_fused_c2_512_hbm_counters.md
     ("fused", "c2_512", "f32"): {
-        "sha256": "531e026cd92f25e1b3c117a7a16ae42112894ee27d2b27c1ea5868c3b0ce23f4",
-        "bytes": 1334830934},
+        "sha256": "2426b6151519501da591ad5a6f3ccd6d985d5810f260cc57acfdf426b839946e",
+        "bytes": 1328375637},
     # profiles/k_fused_f16_c2_512_counters.md
     ("fused", "c2_512", "f16"): {
-        "sha256": "531e026cd92f25e1b3c117a7a16ae42112894ee27d2b27c1ea5868c3b0ce23f4",
-        "bytes": 833035240},
+        "sha256": "2426b6151519501da591ad5a6f3ccd6d985d5810f260cc57acfdf426b839946e",
+        "bytes": 828237061},
     # profiles/k_fused_ista_c2_512_hbm_counters.md (the A x-only pass)
     ("fused", "c2_512", "f32", "ista"): {
-        "sha256": "531e026cd92f25e1b3c117a7a16ae42112894ee27d2b27c1ea5868c3b0ce23f4",
-        "bytes": 1310701130},
+        "sha256": "2426b6151519501da591ad5a6f3ccd6d985d5810f260cc57acfdf426b839946e",
+        "bytes": 1310876045},
     ("fused", "c2_512", "f32", "gd"): {
-        "sha256": "531e026cd92f25e1b3c117a7a16ae42112894ee27d2b27c1ea5868c3b0ce23f4",
-        "bytes": 1310701130},
+        "sha256": "2426b6151519501da591ad5a6f3ccd6d985d5810f260cc57acfdf426b839946e",
+        "bytes": 1310876045},
     # profiles/k_vol_c4_hbm_counters.md (256 slices, 4 ray chunks)
     ("fused_mr", "c4_vol", "f32", 256, 4, "fwd"): {
-        "sha256": "531e026cd92f25e1b3c117a7a16ae42112894ee27d2b27c1ea5868c3b0ce23f4",
-        "bytes": 24373336461},
+        "sha256": "2426b6151519501da591ad5a6f3ccd6d985d5810f260cc57acfdf426b839946e",
+        "bytes": 26431666536},
     # profiles/k_sel_c2_512_hbm_counters.md (mean over the 1600 draws of the profiled run)
     ("selected", "c2_512", "f32", 0.5, 0.5, 7, "fwd"): {
-        "sha256": "c728dbcea262256a957619bee4d5312fec92291854392e78ec8675b75a806624",
-        "bytes": 614003335},
+        "sha256": "8551ef8e81f3daebab52a76bffa99b4c508a58dcbfc1c5600055f14b1367f852",
+        "bytes": 613961498},
 }
 
 

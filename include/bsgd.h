@@ -613,7 +613,9 @@ void bsgd_graph_destroy(bsgd_graph* graph);
  *               (per-segment row sums in a fixed order, exact fixed-point
  *               column sums).
  *   fused_partials_size  bytes of the partial-sum buffer (device) that every
- *               pass needs: one float per segment slot and chunks x pixels.
+ *               pass needs: the row sums of the segments (one float per
+ *               slot, or per ray and rank, whichever needs more) and
+ *               chunks x pixels.
  *   fused_apply   one pass in natural orders:
  *                   out_r = y - A x      (A x when y == NULL)      (lines 4, 6)
  *                   out_x = xadd + mu * 2 A^T r   (2 A^T r when xadd == NULL)

@@ -266,7 +266,8 @@ struct FusedPartials {
   float* gp = nullptr;
   unsigned* rmax = nullptr;  // 2 words: max |r| of the two residual buffers
 };
-// zp: maxrank x r_int x S floats, gp: Q x c_int x S, rmax: 2 x S words
+// zp: maxrank x r_int x S floats (one RHS: also at least one per slot), gp:
+// Q x c_int x S, rmax: 2 x S words
 size_t fused_partials(const bsgd_fused* F, int S, FusedPartials* fp, void* ws);
 // several RHS (S a multiple of 4, vectors [rows][S]): per-RHS max |v|, the
 // pass (both products, rmax_in: S words) and the reduce
@@ -288,13 +289,17 @@ enum { kPassBoth = 0, kPassA = 1, kPassAt = 2 };
 hipError_t launch_fused_pass(const bsgd_fused* F, bsgd_valtype vt, const float* x,
                              const float* r, const unsigned* rmax_in, unsigned* rmax_zero,
                              float* zp, float* gp, hipStream_t s, int mode = kPassBoth,
-                             int waves = 0);  // waves 0: the store's
+                             int waves = 0,        // waves 0: the store's
+                             bool slotz = false);  // one row-sum partial per slot (kPassBoth)
 // parts: kReduceRays (out_r, *rmax_out), kReducePixels (out_x), or both.
 enum { kReduceRays = 1, kReducePixels = 2, kReduceAll = 3 };
 hipError_t launch_fused_reduce(const bsgd_fused* F, const float* zp, const float* gp,
                                const float* y, float* out_r, unsigned* rmax_out,
                                const float* xadd, float scale, float* out_x, hipStream_t s,
-                               int parts = kReduceAll);
+                               int parts = kReduceAll, bool slotz = false);
+// Whether one-RHS epochs whose ray reduce overlaps the prox keep the row-sum
+// partials in slot order (see the definition).
+bool fused_slot_partials(const bsgd_fused* F);
 bool fused_has_f16(const bsgd_fused* F);
 const bsgd_plan* fused_plan(const bsgd_fused* F);
 

@@ -65,6 +65,11 @@ constexpr int kFTS = kFT + 1;        // LDS row stride (rows and columns hit dis
 constexpr int kFTA = kFT * kFTS;     // LDS floats per tile image
 constexpr int kKeyLen = 8192;        // key >> 32 = unit * 8192 + (8191 - segment length)
 constexpr int kMaxSeg = kFT * kFT;   // a segment holds at most one entry per pixel
+// One-RHS epochs keep the row sums in slot order up to this many slots
+// (measured on gfx950: 3.8 M slots at 512^2, epochs 1.5% faster; 30 M at
+// 1024^2, 3.5% slower: the ray reduce's gathers leave the caches and slow
+// the pixel half and the prox beside it).
+constexpr int64_t kSlotPartialsMax = int64_t{1} << 23;
 
 struct TileGeom {
   int Ht = 1, Wt = 1;        // 8 x 8 tiles per image column / row
@@ -90,6 +95,7 @@ struct bsgd_fused {
   const bsgd_plan* plan = nullptr;
   bsgd::TileGeom g;
   int waves = 8;             // wavefronts per unit workgroup (2, 4 or 8)
+  bool slotz = false;        // per launch: one-RHS row-sum partials in slot order
   int64_t pairs = 0, slices = 0, entries = 0, cap = 0;
   int maxrank = 0;           // most segments of one ray
   double smax = 0.0;         // largest column sum of |A| (bounds the sums of A^T r)
@@ -100,6 +106,7 @@ struct bsgd_fused {
   int64_t* soff = nullptr;   // slices + 1: first entry of each slice
   int32_t* sray = nullptr;   // slices * 64: internal ray of each lane (-1: none)
   int32_t* poff = nullptr;   // r_int + 1: first segment of each ray
+  int32_t* pslot = nullptr;  // pairs: slot of each segment (ray order: poff[ray] + rank)
   uint16_t* srank = nullptr; // slices * 64: the lane's segment's rank within its ray
   bool narrow = true;        // 8-bit address steps (col8, sbase) or 16-bit addresses (col)
   uint8_t* col8 = nullptr;   // cap
@@ -763,7 +770,7 @@ __global__ __launch_bounds__(64 * W) void k_fused(
     const VT* __restrict__ val, const float* __restrict__ x,
     const float* __restrict__ r, const unsigned* __restrict__ rmax_in, unsigned* rmax_zero,
     float* __restrict__ zp, float* __restrict__ gp, int64_t r_int, int64_t c_int, double smax,
-    double amax) {
+    double amax, bool slotz) {
   __shared__ float xs[kFTA];
   __shared__ int gs[kFTA];
   constexpr int NT = 64 * W;
@@ -849,7 +856,15 @@ __global__ __launch_bounds__(64 * W) void k_fused(
       group_step<NARROW, MODE>(xs, gs, c0, a0, rs, z0, ap);
     }
     if (MODE != kPassA && !fetched && nxt.rho >= 0) rnext = r[nxt.rho];
-    if (MODE != kPassAt && cur.rho >= 0) zp[(int64_t)cur.rk * r_int + cur.rho] = z0 + z1;
+    // row sum of the lane's segment: at its slot (one 256-byte store per
+    // slice; the reduce gathers a ray's segments through pslot) or at
+    // [rank][ray] (the reduce reads rank planes with unit stride)
+    if constexpr (MODE != kPassAt) {
+      if (slotz)
+        zp[(int64_t)s * 64 + lane] = z0 + z1;
+      else if (cur.rho >= 0)
+        zp[(int64_t)cur.rk * r_int + cur.rho] = z0 + z1;
+    }
     ++k;
     s = sn;
     cur = nxt;
@@ -1071,28 +1086,42 @@ __device__ __forceinline__ void block_max_to(unsigned v, unsigned* out) {
 // the bit pattern of a non-negative float, which orders like the value).  Pixels: out_x = xadd + scale * (sum of the Q chunk
 // partials, in chunk order), or scale * sum when xadd is NULL.
 __global__ __launch_bounds__(256) void k_fz_reduce(
-    const int32_t* __restrict__ poff, const float* __restrict__ zp,
-    const float* __restrict__ y, float* __restrict__ out_r, unsigned* rmax_out,
-    int64_t r_int, const float* __restrict__ gp, int Q, const float* __restrict__ xadd,
-    float scale, float* __restrict__ out_x, int64_t c_int, int64_t lo, int64_t hi) {
+    const int32_t* __restrict__ poff, const int32_t* __restrict__ pslot,
+    const float* __restrict__ zp, const float* __restrict__ y, float* __restrict__ out_r,
+    unsigned* rmax_out, int64_t r_int, const float* __restrict__ gp, int Q,
+    const float* __restrict__ xadd, float scale, float* __restrict__ out_x, int64_t c_int,
+    int64_t lo, int64_t hi) {
   float m = 0.f;
   bool bad = false;  // a NaN residual (fmaxf would drop it)
   for (int64_t i = lo + (int64_t)blockIdx.x * 256 + threadIdx.x; i < hi;
        i += (int64_t)gridDim.x * 256) {
     if (i < r_int) {
-      const int n = poff[i + 1] - poff[i];
-      const float* z = zp + i;
+      const int b = poff[i], n = poff[i + 1] - b;
       float a = 0.f;
       int k = 0;
-      for (; k + 3 < n; k += 4) {
-        const float v0 = z[(int64_t)k * r_int], v1 = z[(int64_t)(k + 1) * r_int];
-        const float v2 = z[(int64_t)(k + 2) * r_int], v3 = z[(int64_t)(k + 3) * r_int];
-        a += v0;
-        a += v1;
-        a += v2;
-        a += v3;
+      if (pslot) {
+        // the segments' row sums at their slots, gathered in rank order
+        const int32_t* ps = pslot + b;
+        for (; k + 3 < n; k += 4) {
+          const float v0 = zp[ps[k]], v1 = zp[ps[k + 1]], v2 = zp[ps[k + 2]], v3 = zp[ps[k + 3]];
+          a += v0;
+          a += v1;
+          a += v2;
+          a += v3;
+        }
+        for (; k < n; ++k) a += zp[ps[k]];
+      } else {
+        const float* z = zp + i;
+        for (; k + 3 < n; k += 4) {
+          const float v0 = z[(int64_t)k * r_int], v1 = z[(int64_t)(k + 1) * r_int];
+          const float v2 = z[(int64_t)(k + 2) * r_int], v3 = z[(int64_t)(k + 3) * r_int];
+          a += v0;
+          a += v1;
+          a += v2;
+          a += v3;
+        }
+        for (; k < n; ++k) a += z[(int64_t)k * r_int];
       }
-      for (; k < n; ++k) a += z[(int64_t)k * r_int];
       const float o = y ? y[i] - a : a;
       out_r[i] = o;
       m = fmaxf(m, fabsf(o));
@@ -1242,11 +1271,11 @@ static void launch_fused_m(const bsgd_fused& F, const VT* val, const float* x, c
   if (F.narrow)
     k_fused<VT, true, W, MODE><<<(unsigned)F.g.units(), 64 * W, 0, s>>>(
         F.g, F.uorder, F.sbeg, F.sng, F.soff, F.sray, F.srank, F.sbase, F.col8, val, x, r,
-        rmax_in, rmax_zero, zp, gp, F.plan->L.r_int, F.plan->L.c_int, F.smax, F.amax);
+        rmax_in, rmax_zero, zp, gp, F.plan->L.r_int, F.plan->L.c_int, F.smax, F.amax, F.slotz);
   else
     k_fused<VT, false, W, MODE><<<(unsigned)F.g.units(), 64 * W, 0, s>>>(
         F.g, F.uorder, F.sbeg, F.sng, F.soff, F.sray, F.srank, nullptr, F.col, val, x, r,
-        rmax_in, rmax_zero, zp, gp, F.plan->L.r_int, F.plan->L.c_int, F.smax, F.amax);
+        rmax_in, rmax_zero, zp, gp, F.plan->L.r_int, F.plan->L.c_int, F.smax, F.amax, F.slotz);
 }
 
 template <typename VT, int W>
@@ -1272,11 +1301,20 @@ static void launch_fused_vt(const bsgd_fused& F, int mode, const VT* val, const 
 }
 
 bool fused_has_f16(const bsgd_fused* F) { return F->val16 != nullptr; }
+
+// Slot-order row sums save the pass its scattered per-segment stores (one
+// coalesced store per slice instead of 64 lines touched), and cost the ray
+// reduce one gather per segment; that reduce runs beside the pixel half and
+// the prox, which hide it while the partials stay cache-sized.
+bool fused_slot_partials(const bsgd_fused* F) { return F->slices * 64 <= kSlotPartialsMax; }
 const bsgd_plan* fused_plan(const bsgd_fused* F) { return F->plan; }
 
 size_t fused_partials(const bsgd_fused* F, int S, FusedPartials* fp, void* ws) {
   Carver cv(ws);
-  float* a = cv.take<float>((size_t)std::max(F->maxrank, 1) * F->plan->L.r_int * S);
+  // row-sum partials: [rank][ray] planes, or (one RHS) one per slot
+  size_t za = (size_t)std::max(F->maxrank, 1) * F->plan->L.r_int * S;
+  if (S == 1) za = std::max<size_t>(za, (size_t)std::max<int64_t>(F->slices, 1) * 64);
+  float* a = cv.take<float>(za);
   float* b = cv.take<float>((size_t)F->g.Q * F->plan->L.c_int * S);
   unsigned* m = cv.take<unsigned>(2 * (size_t)S);
   if (fp) {
@@ -1295,9 +1333,11 @@ hipError_t launch_fused_absmax(const float* v, int64_t n, unsigned* out, hipStre
 
 hipError_t launch_fused_pass(const bsgd_fused* F, bsgd_valtype vt, const float* x,
                              const float* r, const unsigned* rmax_in, unsigned* rmax_zero,
-                             float* zp, float* gp, hipStream_t s, int mode, int waves) {
+                             float* zp, float* gp, hipStream_t s, int mode, int waves,
+                             bool slotz) {
   bsgd_fused G = *F;  // the launch's wave count: the caller's, else the store's
   G.waves = waves > 0 ? waves : F->waves;
+  G.slotz = slotz;
   if (vt == BSGD_VAL_F16)
     launch_fused_vt<__half>(G, mode, F->val16, x, r, rmax_in, rmax_zero, zp, gp, s);
   else
@@ -1381,14 +1421,15 @@ hipError_t launch_fused_reduce_mr(const bsgd_fused* F, int S, const float* zp, c
 hipError_t launch_fused_reduce(const bsgd_fused* F, const float* zp, const float* gp,
                                const float* y, float* out_r, unsigned* rmax_out,
                                const float* xadd, float scale, float* out_x, hipStream_t s,
-                               int parts) {
+                               int parts, bool slotz) {
   const Layout& L = F->plan->L;
   const int64_t lo = (parts & kReduceRays) ? 0 : L.r_int;
   const int64_t hi = (parts & kReducePixels) ? L.r_int + L.c_int : L.r_int;
   if (hi <= lo) return hipSuccess;
   const unsigned blocks = std::min<unsigned>(grid_for(hi - lo), 1024);
-  k_fz_reduce<<<blocks, 256, 0, s>>>(F->poff, zp, y, out_r, rmax_out, L.r_int, gp, F->g.Q, xadd,
-                                     scale, out_x, L.c_int, lo, hi);
+  k_fz_reduce<<<blocks, 256, 0, s>>>(F->poff, slotz ? F->pslot : nullptr, zp, y, out_r,
+                                     rmax_out, L.r_int, gp, F->g.Q, xadd, scale, out_x, L.c_int,
+                                     lo, hi);
   return hipGetLastError();
 }
 
@@ -1502,6 +1543,8 @@ static size_t fused_layout(const bsgd_plan* p, const TileGeom& g, const FusedCou
   F->soff = cv.take<int64_t>(fc.slices + 1);
   F->sray = cv.take<int32_t>(nslots);
   F->poff = cv.take<int32_t>(L.r_int + 1);
+  F->pslot = cv.take<int32_t>(np);
+  T->pos = F->pslot;  // the build's placement fills it
   F->srank = cv.take<uint16_t>(nslots);
   F->narrow = fc.narrow;
   if (fc.narrow) {
@@ -1521,7 +1564,6 @@ static size_t fused_layout(const bsgd_plan* p, const TileGeom& g, const FusedCou
   // build-only temporaries
   T->key = cv.take<uint64_t>(np);
   T->key2 = cv.take<uint64_t>(np);
-  T->pos = cv.take<int32_t>(np);
   T->pdst = cv.take<int64_t>(np);
   T->idx = cv.take<int32_t>(np);
   T->idx2 = cv.take<int32_t>(np);

@@ -737,21 +737,26 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
       // reduce (lines 6-8), then the prox (line 9) on `stream`.  The ray half
       // of the reduce (line 6: the next residual and its max |r|) is needed
       // only by the next pass, so with overlap modes 0 and 1 it runs on the
-      // state's second stream, concurrently with the pixel half and the prox.
-      // max |r| of the residual the pass reads: computed at the start of each
-      // call, then carried by the reduce (which writes the next residual)
+      // state's second stream, concurrently with the pixel half and the prox
+      // (starting it after the pixel half, beside the prox only, measured
+      // slower: the prox lost more than the pixel half gained).  max |r| of
+      // the residual the pass reads: computed at the start of each call, then
+      // carried by the reduce (which writes the next residual)
       const FusedPartials& fp = st->fzp;
       const bool split = st->overlap != 2;
+      // with the ray half of the reduce off the critical path, the pass stores
+      // its row sums in slot order (coalesced) and that half gathers them
+      const bool slotz = split && fused_slot_partials(st->fz);
       if (e == 0) BSGD_HIP(launch_fused_absmax(st->r[c], p->L.r_int, fp.rmax + c, stream));
       if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
       BSGD_HIP(launch_fused_pass(st->fz, st->vt, st->x[c], st->r[c], fp.rmax + c, fp.rmax + n,
-                                 fp.zp, fp.gp, stream, kPassBoth, st->pass_waves));
+                                 fp.zp, fp.gp, stream, kPassBoth, st->pass_waves, slotz));
       if (tv) BSGD_HIP(hipEventRecord(tv[1], stream));
       if (split) {
         BSGD_HIP(hipEventRecord(st->ev_main, stream));
         BSGD_HIP(hipStreamWaitEvent(st->aux, st->ev_main, 0));
         BSGD_HIP(launch_fused_reduce(st->fz, fp.zp, fp.gp, st->y, st->r[n], fp.rmax + n,
-                                     nullptr, 0.f, nullptr, st->aux, kReduceRays));
+                                     nullptr, 0.f, nullptr, st->aux, kReduceRays, slotz));
         BSGD_HIP(hipEventRecord(st->ev_aux, st->aux));
       }
       if (tv) BSGD_HIP(hipEventRecord(tv[2], stream));

@@ -43,27 +43,27 @@ TIMING_STRIDE = 20
 PMC_TRAFFIC = {
     # profiles/k_fused_c2_512_hbm_counters.md
     ("fused", "c2_512", "f32"): {
-        "sha256": "2426b6151519501da591ad5a6f3ccd6d985d5810f260cc57acfdf426b839946e",
-        "bytes": 1328375637},
+        "sha256": "00c5003bb8783caf1beab33930b96b4848b13307af30fade649ab9630869a8c6",
+        "bytes": 1325699013},
     # profiles/k_fused_f16_c2_512_counters.md
     ("fused", "c2_512", "f16"): {
-        "sha256": "2426b6151519501da591ad5a6f3ccd6d985d5810f260cc57acfdf426b839946e",
-        "bytes": 828237061},
+        "sha256": "00c5003bb8783caf1beab33930b96b4848b13307af30fade649ab9630869a8c6",
+        "bytes": 826102561},
     # profiles/k_fused_ista_c2_512_hbm_counters.md (the A x-only pass)
     ("fused", "c2_512", "f32", "ista"): {
-        "sha256": "2426b6151519501da591ad5a6f3ccd6d985d5810f260cc57acfdf426b839946e",
-        "bytes": 1310876045},
+        "sha256": "00c5003bb8783caf1beab33930b96b4848b13307af30fade649ab9630869a8c6",
+        "bytes": 1311094190},
     ("fused", "c2_512", "f32", "gd"): {
-        "sha256": "2426b6151519501da591ad5a6f3ccd6d985d5810f260cc57acfdf426b839946e",
-        "bytes": 1310876045},
+        "sha256": "00c5003bb8783caf1beab33930b96b4848b13307af30fade649ab9630869a8c6",
+        "bytes": 1311094190},
     # profiles/k_vol_c4_hbm_counters.md (256 slices, 4 ray chunks)
     ("fused_mr", "c4_vol", "f32", 256, 4, "fwd"): {
-        "sha256": "2426b6151519501da591ad5a6f3ccd6d985d5810f260cc57acfdf426b839946e",
-        "bytes": 26431666536},
+        "sha256": "00c5003bb8783caf1beab33930b96b4848b13307af30fade649ab9630869a8c6",
+        "bytes": 25847345338},
     # profiles/k_sel_c2_512_hbm_counters.md (mean over the 1600 draws of the profiled run)
     ("selected", "c2_512", "f32", 0.5, 0.5, 7, "fwd"): {
         "sha256": "8551ef8e81f3daebab52a76bffa99b4c508a58dcbfc1c5600055f14b1367f852",
-        "bytes": 613961498},
+        "bytes": 613987949},
 }
 
 

@@ -731,10 +731,15 @@ __device__ __forceinline__ void load_group(const void* __restrict__ col,
 
 // z += a . x[c] (LDS gathers) and g[c] += a * r (fixed-point LDS atomics);
 // narrow columns are decoded from the lane's running address ap (groups of
-// a lane are decoded in order)
-template <bool NARROW, int MODE>
-__device__ __forceinline__ void group_step(const float* xs, int* gs, const ColRaw<NARROW>& raw,
-                                           const float (&a)[4], float rs, float& z, int& ap) {
+// a lane are decoded in order).  MERGED: x[c] and g[c] share one 64-bit LDS
+// cell (x's bits low, the fixed-point sum high), and one 64-bit atomic add of
+// the term shifted into the high word returns x with the old value: one LDS
+// instruction per entry instead of two.  The high word wraps like a 32-bit
+// add and the low word never changes, so the results are the same bits.
+template <bool NARROW, int MODE, bool MERGED>
+__device__ __forceinline__ void group_step(const float* xs, int* gs, unsigned long long* xg,
+                                           const ColRaw<NARROW>& raw, const float (&a)[4],
+                                           float rs, float& z, int& ap) {
   int c[4];
   if constexpr (NARROW) {
     c[0] = ap + (int)(raw & 255u);
@@ -748,8 +753,14 @@ __device__ __forceinline__ void group_step(const float* xs, int* gs, const ColRa
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    if constexpr (MODE != kPassAt) z = fmaf(a[t], xs[c[t]], z);
-    if constexpr (MODE != kPassA) atomicAdd(&gs[c[t]], term32(a[t], rs));
+    if constexpr (MERGED) {
+      const unsigned long long old =
+          atomicAdd(&xg[c[t]], (unsigned long long)(unsigned)term32(a[t], rs) << 32);
+      z = fmaf(a[t], __uint_as_float((unsigned)old), z);
+    } else {
+      if constexpr (MODE != kPassAt) z = fmaf(a[t], xs[c[t]], z);
+      if constexpr (MODE != kPassA) atomicAdd(&gs[c[t]], term32(a[t], rs));
+    }
   }
 }
 
@@ -761,8 +772,18 @@ __device__ __forceinline__ int snake(int s0, int k, int wv) {
   return s0 + k * W + ((k & 1) ? (W - 1 - wv) : wv);
 }
 
+// FP16 values: at most 64 VGPRs (eight wavefronts per SIMD), so that with
+// 33 KB of LDS four 8-wavefront workgroups share a CU and all 1024 units of a
+// 512^2 pass run at once (left to itself the compiler takes 80-88 VGPRs,
+// which holds a CU to two workgroups); 2% faster at 512^2 and 1024^2, where
+// the LDS work bounds the pass.  With FP32 values the cap left the 512^2
+// pass unchanged and made the 1024^2 one 4% slower, so they keep the
+// compiler's choice.
+template <typename VT>
+constexpr int kFusedWavesPerSimd = sizeof(VT) == 2 ? 8 : 1;
+
 template <typename VT, bool NARROW, int W, int MODE>
-__global__ __launch_bounds__(64 * W) void k_fused(
+__global__ __launch_bounds__(64 * W, kFusedWavesPerSimd<VT>) void k_fused(
     TileGeom g, const int32_t* __restrict__ uorder, const int32_t* __restrict__ sbeg,
     const int32_t* __restrict__ sng, const int64_t* __restrict__ soff,
     const int32_t* __restrict__ sray, const uint16_t* __restrict__ srank,
@@ -771,8 +792,16 @@ __global__ __launch_bounds__(64 * W) void k_fused(
     const float* __restrict__ r, const unsigned* __restrict__ rmax_in, unsigned* rmax_zero,
     float* __restrict__ zp, float* __restrict__ gp, int64_t r_int, int64_t c_int, double smax,
     double amax, bool slotz) {
-  __shared__ float xs[kFTA];
-  __shared__ int gs[kFTA];
+  // the tile of x and the fixed-point A^T r image: two arrays, or (FP16
+  // values, both products: there the LDS work bounds the pass, and halving
+  // its instructions took it from 0.1825 to 0.175 ms at 512^2; with FP32
+  // values it made the pass slower, 0.233 to 0.238 ms) one array of 64-bit
+  // cells
+  constexpr bool MERGED = MODE == kPassBoth && sizeof(VT) == 2;
+  __shared__ unsigned long long lds[kFTA];
+  float* xs = reinterpret_cast<float*>(lds);
+  int* gs = reinterpret_cast<int*>(lds) + kFTA;
+  unsigned long long* xg = lds;
   constexpr int NT = 64 * W;
   const int u = uorder[blockIdx.x];  // largest units first
   const int tile = u / g.Q, q = u - tile * g.Q;
@@ -787,17 +816,26 @@ __global__ __launch_bounds__(64 * W) void k_fused(
   // the next kernel of the epoch gathers the next residual's |r| maximum here
   if (rmax_zero && blockIdx.x == 0 && tid == 0) *rmax_zero = 0u;
   for (int i = tid; i < kFTA; i += NT) {
-    if constexpr (MODE != kPassAt) xs[i] = 0.f;
-    if constexpr (MODE != kPassA) gs[i] = 0;
+    if constexpr (MERGED) {
+      xg[i] = 0ull;
+    } else {
+      if constexpr (MODE != kPassAt) xs[i] = 0.f;
+      if constexpr (MODE != kPassA) gs[i] = 0;
+    }
   }
   __syncthreads();
   if constexpr (MODE != kPassAt)
     for (int i = tid; i < kFT * kFT; i += NT) {
       const int b = i >> 6, w = i & 63;
       const int tr8 = ftr * 8 + (b >> 3), tc8 = ftc * 8 + (b & 7);
-      if (tr8 < g.Ht && tc8 < g.Wt)
-        xs[(((b >> 3) << 3) + (w >> 3)) * kFTS + ((b & 7) << 3) + (w & 7)] =
-            x[xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w];
+      if (tr8 < g.Ht && tc8 < g.Wt) {
+        const float xv = x[xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w];
+        const int ai = (((b >> 3) << 3) + (w >> 3)) * kFTS + ((b & 7) << 3) + (w & 7);
+        if constexpr (MERGED)
+          xg[ai] = (unsigned long long)__float_as_uint(xv);
+        else
+          xs[ai] = xv;
+      }
     }
   const float rmax = MODE == kPassA ? 0.f : __uint_as_float(*rmax_in);
   const int e = fixed_exponent32(smax, amax, rmax);
@@ -832,10 +870,10 @@ __global__ __launch_bounds__(64 * W) void k_fused(
         fetched = true;
         if (MODE != kPassA && nxt.rho >= 0) rnext = r[nxt.rho];
       }
-      group_step<NARROW, MODE>(xs, gs, c0, a0, rs, z0, ap);
-      group_step<NARROW, MODE>(xs, gs, c1, a1, rs, z1, ap);
-      group_step<NARROW, MODE>(xs, gs, c2, a2, rs, z0, ap);
-      group_step<NARROW, MODE>(xs, gs, c3, a3, rs, z1, ap);
+      group_step<NARROW, MODE, MERGED>(xs, gs, xg, c0, a0, rs, z0, ap);
+      group_step<NARROW, MODE, MERGED>(xs, gs, xg, c1, a1, rs, z1, ap);
+      group_step<NARROW, MODE, MERGED>(xs, gs, xg, c2, a2, rs, z0, ap);
+      group_step<NARROW, MODE, MERGED>(xs, gs, xg, c3, a3, rs, z1, ap);
     }
     for (; j + 1 < ng; j += 2) {
       ColRaw<NARROW> c0, c1;
@@ -846,14 +884,14 @@ __global__ __launch_bounds__(64 * W) void k_fused(
         fetched = true;
         if (MODE != kPassA && nxt.rho >= 0) rnext = r[nxt.rho];
       }
-      group_step<NARROW, MODE>(xs, gs, c0, a0, rs, z0, ap);
-      group_step<NARROW, MODE>(xs, gs, c1, a1, rs, z1, ap);
+      group_step<NARROW, MODE, MERGED>(xs, gs, xg, c0, a0, rs, z0, ap);
+      group_step<NARROW, MODE, MERGED>(xs, gs, xg, c1, a1, rs, z1, ap);
     }
     if (j < ng) {
       ColRaw<NARROW> c0;
       float a0[4];
       load_group<VT, NARROW>(col, val, base + (int64_t)j * 256, c0, a0);
-      group_step<NARROW, MODE>(xs, gs, c0, a0, rs, z0, ap);
+      group_step<NARROW, MODE, MERGED>(xs, gs, xg, c0, a0, rs, z0, ap);
     }
     if (MODE != kPassA && !fetched && nxt.rho >= 0) rnext = r[nxt.rho];
     // row sum of the lane's segment: at its slot (one 256-byte store per
@@ -878,7 +916,8 @@ __global__ __launch_bounds__(64 * W) void k_fused(
     if (tr8 < g.Ht && tc8 < g.Wt) {
       const int a = (((b >> 3) << 3) + (w >> 3)) * kFTS + ((b & 7) << 3) + (w & 7);
       gp[(int64_t)q * c_int + xbase + ((int64_t)(tr8 * g.Wt + tc8) << 6) + w] =
-          rbad ? __uint_as_float(0x7fc00000u) : ldexpf((float)gs[a], -e);
+          rbad ? __uint_as_float(0x7fc00000u)
+               : ldexpf((float)(MERGED ? (int)(xg[a] >> 32) : gs[a]), -e);
     }
   }
 }

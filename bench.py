@@ -43,27 +43,27 @@ TIMING_STRIDE = 20
 PMC_TRAFFIC = {
     # profiles/k_fused_c2_512_hbm_counters.md
     ("fused", "c2_512", "f32"): {
-        "sha256": "00c5003bb8783caf1beab33930b96b4848b13307af30fade649ab9630869a8c6",
-        "bytes": 1325699013},
+        "sha256": "1dfbe6ee062d33d1cbf5dd11745366d5b430fe7f152c377d39646ed6dc78f97b",
+        "bytes": 1328371187},
     # profiles/k_fused_f16_c2_512_counters.md
     ("fused", "c2_512", "f16"): {
-        "sha256": "00c5003bb8783caf1beab33930b96b4848b13307af30fade649ab9630869a8c6",
-        "bytes": 826102561},
+        "sha256": "1dfbe6ee062d33d1cbf5dd11745366d5b430fe7f152c377d39646ed6dc78f97b",
+        "bytes": 826097760},
     # profiles/k_fused_ista_c2_512_hbm_counters.md (the A x-only pass)
     ("fused", "c2_512", "f32", "ista"): {
-        "sha256": "00c5003bb8783caf1beab33930b96b4848b13307af30fade649ab9630869a8c6",
-        "bytes": 1311094190},
+        "sha256": "1dfbe6ee062d33d1cbf5dd11745366d5b430fe7f152c377d39646ed6dc78f97b",
+        "bytes": 1310861175},
     ("fused", "c2_512", "f32", "gd"): {
-        "sha256": "00c5003bb8783caf1beab33930b96b4848b13307af30fade649ab9630869a8c6",
-        "bytes": 1311094190},
+        "sha256": "1dfbe6ee062d33d1cbf5dd11745366d5b430fe7f152c377d39646ed6dc78f97b",
+        "bytes": 1310861175},
     # profiles/k_vol_c4_hbm_counters.md (256 slices, 4 ray chunks)
     ("fused_mr", "c4_vol", "f32", 256, 4, "fwd"): {
-        "sha256": "00c5003bb8783caf1beab33930b96b4848b13307af30fade649ab9630869a8c6",
-        "bytes": 25847345338},
+        "sha256": "1dfbe6ee062d33d1cbf5dd11745366d5b430fe7f152c377d39646ed6dc78f97b",
+        "bytes": 24547917882},
     # profiles/k_sel_c2_512_hbm_counters.md (mean over the 1600 draws of the profiled run)
     ("selected", "c2_512", "f32", 0.5, 0.5, 7, "fwd"): {
         "sha256": "8551ef8e81f3daebab52a76bffa99b4c508a58dcbfc1c5600055f14b1367f852",
-        "bytes": 613987949},
+        "bytes": 613982205},
 }
 
 

@@ -581,7 +581,8 @@ void bsgd_graph_destroy(bsgd_graph* graph);
  * (integer additions, exact in any order; the scale is set from max |r|, the
  * largest column sum of |A| and the largest |a| so that sums stay below 2^30
  * and terms below 2^21: a term's rounding is below 2^-31 of the largest
- * possible sum);
+ * possible sum, or 2^-22 of the largest possible term when the second bound
+ * is the tighter one);
  * per-segment sums of A x and per-chunk sums of A^T r are added in a fixed
  * order by a second kernel, so results are bitwise reproducible for a given
  * store (and differ from the row kernels by summation order only).  FP16

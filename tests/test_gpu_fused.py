@@ -593,3 +593,122 @@ def test_single_pass_only_plan_checks_a_columns_at_store_build(fault):
         with pytest.raises(bsgd.BsgdError, match="column") as e:
             fn(plan, 0)
         assert e.value.status == bsgd.BSGD_ERR_INVALID
+
+
+def _fixed_point_step(A, r):
+    """Absolute rounding of one term of the single pass's fixed-point A^T r: the
+    exponent e is the largest with every column sum of |A| times max |r| below
+    2^30 and every |a| max |r| below 2^21 (the FP32 rounding of a term is exact
+    below 2^22); a term is rounded to a multiple of 2^-e, off by 2^-(e+1) at
+    most."""
+    Aabs = abs(A)
+    rmax = float(np.max(np.abs(np.asarray(r, np.float32))))
+    smax = float(np.max(np.asarray(Aabs.sum(axis=0)).ravel()))
+    amax = float(Aabs.max())
+    es = np.frexp(smax * rmax)[1]
+    et = np.frexp(amax * rmax)[1]
+    e = min(max(min(30 - es, 21 - et), -200), 200)
+    return 2.0 ** -(e + 1)
+
+
+def _volume_stack(D, H, W, n_ang, bins):
+    """D slices of one 2-D parallel-beam matrix, block-diagonal: rows of slice d
+    (angle-major within the slice) see only the pixels of slice d."""
+    import synth
+    rp, col, val = synth.projection_matrix(H, W, n_ang, bins)
+    nr, npx = n_ang * bins, H * W
+    row_ptr = np.concatenate([[0]] + [rp[1:] + d * rp[-1] for d in range(D)]).astype(np.int64)
+    cols = np.concatenate([col.astype(np.int64) + d * npx for d in range(D)]).astype(np.int32)
+    vals = np.tile(val, D)
+    return D * nr, D * npx, row_ptr, cols, vals
+
+
+def _general_volume(rng, D, H, W, nrows):
+    ncols = D * H * W
+    lens = rng.integers(0, 90, nrows)
+    lens[::37] = 0
+    cols = [np.sort(rng.choice(ncols, n, replace=False)).astype(np.int32) for n in lens]
+    row_ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    return nrows, ncols, row_ptr, np.concatenate(cols).astype(np.int32), rng.random(lens.sum()) * 1.5
+
+
+@pytest.mark.parametrize("kind,f16", [("rays", False), ("rays", True), ("general", False)])
+def test_three_dimensional_plan_matches_oracle(kind, f16):
+    """Plans over a D x H x W volume (D = 3; ragged 8 x 8 and 64 x 64 tiles): a
+    stack of parallel-beam matrices (block-diagonal over the slices) and a
+    general sparse A.  The block-store products, the single-pass products and
+    epochs with the 3-D TV prox against the oracle, from a full plan and from
+    a plan without block stores (the same store, bitwise).  For the general
+    matrix, whose columns hold few entries, the single pass's A^T r is also
+    allowed the rounding of its fixed-point terms (for ray matrices a column
+    sum is far above its largest entry and that rounding is far below the
+    FP32 bound)."""
+    import paper_1812_01307_amd as bsgd
+    import synth
+    rng = np.random.default_rng(21)
+    D, H, W = 3, 40, 70
+    if kind == "rays":
+        bins = 81  # covers the diagonal of a 40 x 70 slice
+        nrows, ncols, row_ptr, col, val = _volume_stack(D, H, W, 24, bins)
+        view_len = bins
+    else:
+        H = 20
+        nrows, ncols, row_ptr, col, val = _general_volume(rng, D, H, W, 900)
+        view_len = 0
+    tp, tc, tv = synth.transpose_csr(nrows, ncols, row_ptr, col, val)
+    vt = bsgd.BSGD_VAL_F16 if f16 else bsgd.BSGD_VAL_F32
+    vals = f32(val).astype(np.float64)
+    if f16:
+        vals = vals.astype(np.float32).astype(np.float16).astype(np.float64)
+    A = oracle.as_matrix(row_ptr, col, vals, ncols)
+    Aabs = oracle.as_matrix(row_ptr, col, np.abs(vals), ncols)
+
+    def make(single_pass):
+        return bsgd.plan_from_host(nrows, ncols, row_ptr, col, val, tp, tc, tv, 2, 2,
+                                   [0, nrows // 2, nrows], [0, ncols // 2, ncols], H, W, D,
+                                   view_len=view_len, f16=f16, single_pass=single_pass)
+
+    full, bare = make(False), make(True)
+    F_full, F_bare = _fused(full), _fused(bare)
+    assert bsgd.bsgd_fused_shape(F_full) == bsgd.bsgd_fused_shape(F_bare)
+    assert bsgd.bsgd_fused_shape(F_full)[0] == D * ((H + 63) // 64) * 2  # tiles
+    x = f32(rng.random(ncols))
+    r = f32(rng.standard_normal(nrows))
+    bound_f = PRODUCT_REL * (Aabs @ np.abs(x)) + 1e-30
+    bound_b = PRODUCT_REL * 2 * (Aabs.T @ np.abs(r)) + 1e-30
+    if not f16:
+        assert np.all(np.abs(_host(bsgd.bsgd_forward(full, _dev(x))) - A @ x) <= bound_f)
+        assert np.all(np.abs(_host(bsgd.bsgd_backproject(full, _dev(r))) - 2 * (A.T @ r))
+                      <= bound_b)
+    nz = np.diff(A.tocsc().indptr)  # entries per column
+    bound_fixed = bound_b + (2 * nz * _fixed_point_step(A, r) if kind == "general" else 0.0)
+    for F in (F_full, F_bare):
+        ax, g = bsgd.bsgd_fused_apply(F, _dev(x), _dev(r), vt=vt)
+        assert np.all(np.abs(_host(ax) - A @ x) <= bound_f)
+        assert np.all(np.abs(_host(g) - 2 * (A.T @ r)) <= bound_fixed)
+    mu = float(np.float32(oracle.step_size(oracle.power_umax(A))))
+    y = f32(A @ rng.random(ncols) + 0.01 * rng.standard_normal(nrows))
+    lam, E, K = 2.0, 5, 10
+    _, _, ref = oracle.bsgd_tv(A, y.astype(np.float64), mu, lam, E, K, (D, H, W), record=True)
+
+    def run(plan, F):
+        st = bsgd.bsgd_state_create(plan, 1, vt)
+        if F is not None:
+            bsgd.bsgd_state_attach_fused(st, F)
+        bsgd.bsgd_state_init(st, _dev(y))
+        xs = []
+        for _ in range(E):
+            bsgd.bsgd_run_epochs(st, mu, lam, 1, K)
+            xs.append(_host(bsgd.bsgd_get_x(st)))
+        return xs
+
+    runs = {"fused": run(full, F_full), "bare": run(bare, F_bare)}
+    if not f16:
+        runs["rows"] = run(full, None)
+    for name, xs in runs.items():
+        errs = [rel_l2(a, b) for a, b in zip(xs, ref)]
+        assert max(errs) <= ITERATE_REL, (name, errs)
+    # the prox moved the iterate by far more than the tolerance
+    xhat_only, _ = oracle.bsgd_tv(A, y.astype(np.float64), mu, 0.0, 1, 1, (D, H, W))
+    assert rel_l2(ref[0], xhat_only) > 100 * ITERATE_REL
+    assert all(np.array_equal(a, b) for a, b in zip(runs["fused"], runs["bare"]))

@@ -6,12 +6,12 @@
  * minimises ||y - A x||^2 + (TV term) for a sparse X-ray projection matrix A
  * (r rays x c pixels) split into M row blocks I_i and N column blocks J_j
  * (Section 2.1).  Each epoch of Algorithm 1 computes, for every block pair,
- *     g^i_{J_j} = 2 (A_{I_i}^{J_j})^T r_{I_i}      (line 3)
- *     z^j_{I_i} = A_{I_i}^{J_j} x_{J_j}             (line 4)
- * then r = y - sum_j z^j (line 6), g = sum_i g^i (line 7), x = x + mu g
- * (line 8) and x = argmin_t ||t - x||^2 + 2 mu lam TV(t) (line 9), the last
+ *     g^i_{J_j} = 2 (A_{I_i}^{J_j})^T r_{I_i}      (the block backprojection)
+ *     z^j_{I_i} = A_{I_i}^{J_j} x_{J_j}             (the block forward projection)
+ * then r = y - sum_j z^j (the residual update), g = sum_i g^i (the gradient sum), x = x + mu g
+ * (the gradient step) and x = argmin_t ||t - x||^2 + 2 mu lam TV(t) (the TV prox step), the last
  * solved by fast gradient projection (FGP) on the dual (the method the
- * paper cites for line 9).
+ * paper cites for the TV prox step).
  *
  * Conventions for every call:
  *   - Pointers documented as "device" point to HIP device memory owned by
@@ -173,7 +173,7 @@ bsgd_status bsgd_plan_set_lanes(bsgd_plan* plan, int fwd_launch, int bwd_launch)
 
 /*
  * Staged form (plans created with BSGD_PLAN_STAGED_FWD / _BWD).  The same fused sums of
- * Algorithm 1 lines 3-8 as the row kernels, reorganised for the epochs of
+ * The block products, block sums and gradient step of Algorithm 1 as the row kernels, reorganised for the epochs of
  * one-RHS states: the internal column space is cut into stages of at most
  * 32768 columns (whole 8-pixel tile rows, or whole groups of 8 views), each
  * row's entries are regrouped by stage with 16-bit stage-local column
@@ -215,45 +215,45 @@ bsgd_status bsgd_tile_export(const bsgd_plan* plan, int i, int j, int transposed
                              int32_t* col, float* val, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * Step-level products (Algorithm 1 lines 3, 4, 6, 7, 8).  The whole-matrix
+ * Step-level products of Algorithm 1 (block products, block sums, gradient step).  The whole-matrix
  * calls stage their operands in the plan's scratch vectors, so calls on one
  * plan must not overlap (serialise them on one stream).
  * ---------------------------------------------------------------------- */
 
 /*
- * Forward projection over all blocks (lines 4 and 6):
+ * Forward projection over all blocks (forward projection and residual):
  *   y == NULL:  out = A x             (sum over j of z^j = A_{I_i}^{J_j} x_{J_j})
- *   y != NULL:  out = y - A x         (the residual of line 6)
+ *   y != NULL:  out = y - A x         (the residual update)
  * x: device, c floats; y, out: device, r floats.  vt selects the value copy.
  */
 bsgd_status bsgd_forward(const bsgd_plan* plan, bsgd_valtype vt, const float* x, const float* y,
                          float* out, hipStream_t stream);
 
 /*
- * Backprojection over all blocks (lines 3, 7 and 8):
+ * Backprojection over all blocks (backprojection, gradient sum and step):
  *   x == NULL:  out = 2 A^T r                    (g = sum_i 2 (A_{I_i}^{J_j})^T r_{I_i})
- *   x != NULL:  out = x + mu * 2 A^T r           (the gradient step of line 8)
+ *   x != NULL:  out = x + mu * 2 A^T r           (the gradient step)
  * r: device, r floats; x, out: device, c floats.
  */
 bsgd_status bsgd_backproject(const bsgd_plan* plan, bsgd_valtype vt, const float* r,
                              const float* x, float mu, float* out, hipStream_t stream);
 
 /*
- * One block's forward product z^j_{I_i} = A_{I_i}^{J_j} x_{J_j} (line 4).
+ * One block's forward product z^j_{I_i} = A_{I_i}^{J_j} x_{J_j} (the block forward projection).
  * xj: device, |J_j| floats; z: device, |I_i| floats.
  */
 bsgd_status bsgd_forward_block(const bsgd_plan* plan, bsgd_valtype vt, int i, int j,
                                const float* xj, float* z, hipStream_t stream);
 
 /*
- * One block's backprojection g^i_{J_j} = 2 (A_{I_i}^{J_j})^T r_{I_i} (line 3).
+ * One block's backprojection g^i_{J_j} = 2 (A_{I_i}^{J_j})^T r_{I_i} (the block backprojection).
  * ri: device, |I_i| floats; g: device, |J_j| floats.
  */
 bsgd_status bsgd_backproject_block(const bsgd_plan* plan, bsgd_valtype vt, int i, int j,
                                    const float* ri, float* g, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * TV proximal step (line 9) and TV value (Eq. 2)
+ * TV proximal step of Algorithm 1 and TV value (Eq. 2)
  * ---------------------------------------------------------------------- */
 
 /* Workspace bytes for bsgd_tv_prox / bsgd_tv_value on an H x W x D image. */
@@ -261,7 +261,7 @@ bsgd_status bsgd_tv_workspace_size(int H, int W, int D, size_t* bytes);
 
 /*
  * out = argmin_t 1/2 ||t - b||^2 + theta TV(t) approximated by `iters` FGP
- * iterations started from a zero dual (line 9 with theta = mu * lam).  TV is
+ * iterations started from a zero dual (the TV prox step with theta = mu * lam).  TV is
  * the isotropic TV of Eq. 2 with backward differences (zero where a
  * difference would leave the image); D > 1 adds the difference across
  * slices (3-D TV, dual step 1/(12 theta) instead of 1/(8 theta)).
@@ -323,13 +323,14 @@ bsgd_status bsgd_lanczos_umax(const bsgd_plan* plan, bsgd_valtype vt, int steps,
 
 /*
  * State flags.  A state holds nrhs right-hand sides that share the plan's A:
- * nrhs = 1, or a power of two from 4 to 1024.  With several RHS every vector
+ * nrhs = 1, or a power of two from 4 to 1024 (several RHS need a 2-D plan,
+ * D = 1: BSGD_ERR_INVALID otherwise).  With several RHS every vector
  * crossing this interface is a row-major matrix [rows][nrhs] (the RHS index
  * fastest), the products become sparse-times-dense products that read A once
  * for all RHS, and the prox is either
  *   - per RHS (default): independent 2-D reconstructions, each with its own
  *     lambda (bsgd_state_set_lambda) -- batches of requests on one geometry;
- *   - BSGD_STATE_VOLUME: the RHS are the slices of one volume and line 9 uses
+ *   - BSGD_STATE_VOLUME: the RHS are the slices of one volume and the TV prox step uses
  *     the isotropic 3-D TV across them (needs a 2-D plan, D = 1).
  */
 #define BSGD_STATE_VOLUME 1u
@@ -393,7 +394,7 @@ bsgd_status bsgd_run_epochs(bsgd_state* state, float mu, float lam, int epochs, 
 /*
  * Update rule of bsgd_run_epochs (the Simulations section compares
  * BSGD-TV with ISTA and with gradient descent, Fig. 2):
- *   BSGD_METHOD_BSGD (default): Algorithm 1 as above; line 3 uses the
+ *   BSGD_METHOD_BSGD (default): Algorithm 1 as above; the block backprojection uses the
  *     residual of the previous iterate (Eq. 3), so both products read x and
  *     r of the epoch's start.
  *   BSGD_METHOD_ISTA: r = y - A x, then x = FGP(x + 2 mu A^T r): the
@@ -415,12 +416,12 @@ bsgd_status bsgd_state_set_method(bsgd_state* state, int method);
  * {x_{J_j}} per iteration).  Iteration t runs the pairs (i, j) with bit i
  * of rows_sel[t] and bit j of cols_sel[t] set (host arrays of iters masks,
  * each non-zero and within M resp. N bits; the caller draws them):
- *   lines 3, 7, 8: x_{J_j} += 2 mu sum over drawn i of (A_{I_i}^{J_j})^T
+ *   backprojection, gradient sum and step: x_{J_j} += 2 mu sum over drawn i of (A_{I_i}^{J_j})^T
  *     r_{I_i} for drawn j (kept r, no rescaling); other blocks of x stay;
- *   line 4: z^j_{I_i} = A_{I_i}^{J_j} x_{J_j} for drawn pairs, kept;
- *   line 6: r_{I_i} = y_{I_i} - sum over all j of the kept z^j_{I_i}
+ *   the block forward projection: z^j_{I_i} = A_{I_i}^{J_j} x_{J_j} for drawn pairs, kept;
+ *   the residual update: r_{I_i} = y_{I_i} - sum over all j of the kept z^j_{I_i}
  *     (ascending j) for drawn i; other rows keep r;
- *   line 9: the prox of the whole image with theta = mu * lam.
+ *   the TV prox step: the prox of the whole image with theta = mu * lam.
  * With every bit set an iteration is an epoch of Algorithm 1 (up to
  * rounding).  Needs a state created with BSGD_STATE_BLOCK_SELECT; counts
  * iterations in bsgd_get_stats.  The epoch of the Simulations section is
@@ -432,15 +433,15 @@ bsgd_status bsgd_run_selected(bsgd_state* state, float mu, float lam, int iters,
                               hipStream_t stream);
 
 /*
- * Epoch schedule.  The forward pass (lines 4, 6) does not depend on the
- * backprojection (lines 3, 7, 8) or the prox (line 9) of the same epoch
- * (Eq. 3: line 3 uses the previous epoch's residual), so it runs on the
+ * Epoch schedule.  The forward pass (forward projection, residual) does not depend on the
+ * backprojection (backprojection, gradient sum and step) or the prox of the same epoch
+ * (Eq. 3: the block backprojection uses the previous epoch's residual), so it runs on the
  * state's second stream: mode 0 starts it together with the backprojection,
  * mode 1 after the backprojection (it then overlaps the prox only; faster on
  * MI355X since both passes are bandwidth-bound); mode 2 runs everything on
  * the caller's stream in order (backprojection, prox, forward pass), which
  * gives each kernel the whole GPU.  With an attached single-pass store,
- * modes 0 and 1 run the ray half of the reduce (line 6: the next residual,
+ * modes 0 and 1 run the ray half of the reduce (the residual update: the next residual,
  * needed only by the next pass) on the second stream, concurrently with the
  * pixel half and the prox; mode 2 keeps it on the caller's stream.  Results
  * do not depend on the mode.  Default 1.
@@ -448,7 +449,7 @@ bsgd_status bsgd_run_selected(bsgd_state* state, float mu, float lam, int iters,
 bsgd_status bsgd_state_set_overlap(bsgd_state* state, int mode);
 
 /*
- * Schedule of the 2-D prox (line 9) kernels: 0 splits the FGP iterations
+ * Schedule of the 2-D prox kernels: 0 splits the FGP iterations
  * into equal launches of at most 12 on 32 x 32 tiles, recomputing a halo as
  * wide as the launch's iteration count (few launches, redundant work), with
  * each thread keeping a strip of
@@ -498,8 +499,8 @@ bsgd_status bsgd_get_stats(const bsgd_state* state, hipStream_t stream, double* 
  * Kernel timers (measurement).  After bsgd_state_enable_timing(state,
  * max_epochs), each of the next max_epochs epochs run by bsgd_run_epochs
  * (or iterations run by bsgd_run_selected) records HIP events (on the stream each kernel runs on) around its forward
- * pass (lines 4 and 6), its backprojection pass (lines 3, 7, 8) and its prox
- * (line 9).  bsgd_state_timing synchronises, returns the summed durations in
+ * pass (forward projection and residual), its backprojection pass (backprojection, gradient sum and step) and its prox
+ * (the TV prox step).  bsgd_state_timing synchronises, returns the summed durations in
  * milliseconds and the number of timed epochs, and rearms the timers.
  * max_epochs = 0 disables timing.  bsgd_state_enable_timing_sampled times
  * one epoch in every `stride` (the first, then every stride-th), up to
@@ -533,7 +534,7 @@ bsgd_status bsgd_state_timing(bsgd_state* state, double* fwd_ms, double* bwd_ms,
  *               slot: now[j] = ||r_{k+1}||^2 (the residual that the next
  *               epoch's backprojection uses) and prev[j] = ||r_k||^2 (the one
  *               the last epoch used), read from the two residual buffers
- *               (Algorithm 1 lines 3-4 keep both).  prev is meaningful once
+ *               (the two block products of Algorithm 1 keep both).  prev is meaningful once
  *               an epoch has run since init, load or the slot's set_rhs.
  *               Any state, also nrhs = 1.  Synchronises; BSGD_ERR_DIVERGED if
  *               a value is not finite.  This is what a stopping rule on the
@@ -560,9 +561,9 @@ bsgd_status bsgd_graph_launch(bsgd_graph* graph, hipStream_t stream);
 void bsgd_graph_destroy(bsgd_graph* graph);
 
 /* ------------------------------------------------------------------------
- * Single-pass epochs (Algorithm 1 lines 3-8 with the delay of Eq. 3)
+ * Single-pass epochs (the block products, block sums and gradient step of Algorithm 1, with the delay of Eq. 3)
  *
- * Line 3 of an epoch uses the previous epoch's residual r_k and line 4 the
+ * The block backprojection of an epoch uses the previous epoch's residual r_k and the block forward projection the
  * current iterate x_k, so both products can be taken in one pass over the
  * stored entries: z[rho] += a x_k[p] and g[p] += a r_k[rho] for every entry
  * a = A[rho, p].  An epoch then reads the matrix once instead of once as A
@@ -618,9 +619,9 @@ void bsgd_graph_destroy(bsgd_graph* graph);
  *               slot, or per ray and rank, whichever needs more) and
  *               chunks x pixels.
  *   fused_apply   one pass in natural orders:
- *                   out_r = y - A x      (A x when y == NULL)      (lines 4, 6)
+ *                   out_r = y - A x      (A x when y == NULL)      (forward projection, residual)
  *                   out_x = xadd + mu * 2 A^T r   (2 A^T r when xadd == NULL)
- *                                                               (lines 3, 7, 8)
+ *                                                               (backprojection, gradient sum and step)
  *               x, xadd, out_x: c floats; y, r, out_r: r floats (device).
  *               Uses the store's internal scratch vectors: calls on one store
  *               must not overlap.

@@ -15,19 +15,19 @@ What it computes, and where the paper defines it:
   term of Eq. 2 is read as x[s,t] - x[s,t-1]; a difference that would reach
   outside the image (s = 0 or t = 0) is zero.
 * One epoch of Algorithm 1 with every block pair active:
-      g  = sum_i 2 (A_{I_i}^{J_j})^T r_{I_i}      (lines 3 and 7)
-      r' = y - sum_j A_{I_i}^{J_j} x_{J_j}         (lines 4 and 6)
-      x^ = x + mu g                                (line 8)
-      x  = argmin_t ||t - x^||^2 + 2 mu lam TV(t)  (line 9)
+      g  = sum_i 2 (A_{I_i}^{J_j})^T r_{I_i}      (backprojection and gradient sum)
+      r' = y - sum_j A_{I_i}^{J_j} x_{J_j}         (forward projection and residual)
+      x^ = x + mu g                                (the gradient step)
+      x  = argmin_t ||t - x^||^2 + 2 mu lam TV(t)  (the TV prox step)
       r  = r'
-  The residual used in line 3 is one epoch old, which is Eq. 3:
+  The residual used in the block backprojection is one epoch old, which is Eq. 3:
   x^{k+1} = prox(x^k + 2 mu A^T (y - A x^{k-1})).  Initialisation (the
   paper ignores it): x = x0 (default 0) and r = y - A x0.
-* Line 9 is solved by the fast gradient projection (FGP) method that the
+* The TV prox step is solved by the fast gradient projection (FGP) method that the
   paper cites for it (Beck & Teboulle, IEEE TIP 18(11), 2009): projected
   gradient steps with FISTA momentum on the dual of
       min_t 1/2 ||t - b||^2 + theta TV(t),   theta = mu * lam,
-  which has the same minimiser as line 9.  The dual step is 1/(8 theta)
+  which has the same minimiser as the TV prox step.  The dual step is 1/(8 theta)
   because ||D||^2 <= 8 for the 2-D difference operator (12 in 3-D).
   No constraint set is applied (no clamp), and every call starts the dual
   at zero.
@@ -36,7 +36,7 @@ What it computes, and where the paper defines it:
 * The M x N block partition of Section 2.1 and a blocked epoch that sums
   the block products in ascending block order (used to show that blocking
   changes rounding only).
-* The Simulations section's comparison methods: ISTA (the same line 8-9
+* The Simulations section's comparison methods: ISTA (the same gradient and prox steps
   step with the current iterate's gradient, A taken whole) and gradient
   descent on f alone (ISTA with lam = 0).
 * Algorithm 1 on drawn subsets of the row and column blocks (Simulations
@@ -52,7 +52,7 @@ import numpy as np
 import scipy.sparse as sp
 
 # ---------------------------------------------------------------------------
-# Sparse products (Alg. 1 lines 3-4, summed over blocks)
+# Sparse products (both block products of Alg. 1, summed over blocks)
 # ---------------------------------------------------------------------------
 
 
@@ -64,12 +64,12 @@ def as_matrix(row_ptr, col, val, ncols: int) -> sp.csr_matrix:
 
 
 def forward(A: sp.csr_matrix, x: np.ndarray) -> np.ndarray:
-    """A x: all block forward projections z^j_{I_i} summed over j (Alg. 1 line 4)."""
+    """A x: all block forward projections z^j_{I_i} summed over j (the block forward projection of Alg. 1)."""
     return A @ np.asarray(x, np.float64)
 
 
 def backproject(A: sp.csr_matrix, r: np.ndarray) -> np.ndarray:
-    """2 A^T r: all block backprojections g^i_{J_j} summed over i (Alg. 1 line 3)."""
+    """2 A^T r: all block backprojections g^i_{J_j} summed over i (the block backprojection of Alg. 1)."""
     return 2.0 * (A.T @ np.asarray(r, np.float64))
 
 
@@ -135,7 +135,7 @@ def tv3(x: np.ndarray) -> float:
 
 
 # ---------------------------------------------------------------------------
-# TV proximal step (Alg. 1 line 9) by FGP on the dual
+# TV proximal step of Alg. 1 by FGP on the dual
 # ---------------------------------------------------------------------------
 
 
@@ -244,7 +244,7 @@ def step_size(u_max: float, factor: float = 0.9) -> float:
 
 
 def prox(xhat: np.ndarray, theta: float, prox_iters: int, shape) -> np.ndarray:
-    """Alg. 1 line 9 on the image of `shape` (2-D or 3-D)."""
+    """The TV prox step of Alg. 1 on the image of `shape` (2-D or 3-D)."""
     if theta == 0.0:
         return xhat.copy()
     img = xhat.reshape(shape)
@@ -255,10 +255,10 @@ def prox(xhat: np.ndarray, theta: float, prox_iters: int, shape) -> np.ndarray:
 
 def bsgd_epoch(A, y, x, r, mu: float, lam: float, prox_iters: int, shape):
     """One epoch of Algorithm 1 (all block pairs); returns (x_new, r_new)."""
-    g = backproject(A, r)                 # lines 3 + 7, stale residual
-    r_new = y - forward(A, x)             # lines 4 + 6, current x
-    xhat = x + mu * g                     # line 8
-    x_new = prox(xhat, mu * lam, prox_iters, shape)   # line 9
+    g = backproject(A, r)                 # backprojection and gradient sum, stale residual
+    r_new = y - forward(A, x)             # forward projection and residual, current x
+    xhat = x + mu * g                     # the gradient step
+    x_new = prox(xhat, mu * lam, prox_iters, shape)   # the TV prox step
     return x_new, r_new
 
 
@@ -289,7 +289,7 @@ def bsgd_tv(A, y, mu: float, lam: float, epochs: int, prox_iters: int, shape,
 
 
 def objective(A, y, x, lam: float, shape) -> float:
-    """F(x) = ||y - A x||^2 + lam TV(x) (the problem that Alg. 1 line 9 targets)."""
+    """F(x) = ||y - A x||^2 + lam TV(x) (the problem that the TV prox step of Alg. 1 targets)."""
     res = y - forward(A, x)
     tv = tv2(x.reshape(shape)) if len(shape) == 2 else tv3(x.reshape(shape))
     return float(res @ res) + lam * tv
@@ -352,7 +352,7 @@ def tiles(row_ptr, col, val, row_off, col_off):
 
 def bsgd_epoch_blocked(blocks, row_off, col_off, y, x, r, mu: float, lam: float,
                        prox_iters: int, shape):
-    """Algorithm 1 epoch written block by block (lines 2-9).
+    """Algorithm 1 epoch written block by block.
 
     z^j_{I_i} = A_{I_i}^{J_j} x_{J_j};  g^i_{J_j} = 2 (A_{I_i}^{J_j})^T r_{I_i};
     r_{I_i} = y_{I_i} - sum_j z^j (ascending j);  g_{J_j} = sum_i g^i (ascending i).
@@ -387,7 +387,7 @@ def bsgd_epoch_blocked(blocks, row_off, col_off, y, x, r, mu: float, lam: float,
 
 
 def block_forward(blocks, row_off, col_off, i: int, j: int, x_block):
-    """z^j_{I_i} = A_{I_i}^{J_j} x_{J_j} for one block (Alg. 1 line 4)."""
+    """z^j_{I_i} = A_{I_i}^{J_j} x_{J_j} for one block (the block forward projection of Alg. 1)."""
     r0, r1 = int(row_off[i]), int(row_off[i + 1])
     c0, c1 = int(col_off[j]), int(col_off[j + 1])
     ptr, lcol, lval = blocks[(i, j)]
@@ -395,7 +395,7 @@ def block_forward(blocks, row_off, col_off, i: int, j: int, x_block):
 
 
 def block_backproject(blocks, row_off, col_off, i: int, j: int, r_block):
-    """g^i_{J_j} = 2 (A_{I_i}^{J_j})^T r_{I_i} for one block (Alg. 1 line 3)."""
+    """g^i_{J_j} = 2 (A_{I_i}^{J_j})^T r_{I_i} for one block (the block backprojection of Alg. 1)."""
     r0, r1 = int(row_off[i]), int(row_off[i + 1])
     c0, c1 = int(col_off[j]), int(col_off[j + 1])
     ptr, lcol, lval = blocks[(i, j)]
@@ -412,15 +412,15 @@ def bsgd_epoch_multi(A, Y, X, R, mu: float, lam, prox_iters: int, shape2d, volum
     """One epoch of Algorithm 1 applied to S right-hand sides at once.
 
     Y, R: (S, r) arrays and X: (S, c) arrays, one row per RHS.  The products
-    are those of bsgd_epoch for every RHS.  Line 9 is either the 3-D TV prox
+    are those of bsgd_epoch for every RHS.  The TV prox step is either the 3-D TV prox
     of the volume whose slices are the RHS (volume=True, one lam), or the 2-D
     prox of each RHS with its own lam[j] (volume=False).
     """
     S = X.shape[0]
     H, W = shape2d
-    G = 2.0 * np.asarray(A.T @ R.T).T           # lines 3 + 7, stale residuals
-    R_new = Y - np.asarray(A @ X.T).T           # lines 4 + 6
-    Xhat = X + mu * G                           # line 8
+    G = 2.0 * np.asarray(A.T @ R.T).T           # backprojection and gradient sum, stale residuals
+    R_new = Y - np.asarray(A @ X.T).T           # forward projection and residual
+    Xhat = X + mu * G                           # the gradient step
     if volume:
         theta = mu * float(lam)
         X_new = (fgp_prox3(Xhat.reshape(S, H, W), theta, prox_iters).reshape(S, H * W)
@@ -455,7 +455,7 @@ def bsgd_tv_multi(A, Y, mu: float, lam, epochs: int, prox_iters: int, shape2d, v
 def ista_epoch(A, y, x, mu: float, lam: float, prox_iters: int, shape):
     """One ISTA iteration on F (the proximal gradient method the paper compares with).
 
-    The step of Algorithm 1 lines 8-9 with the gradient of the current
+    The gradient and prox steps of Algorithm 1 with the gradient of the current
     iterate (no delay; A taken as a whole, Fig. 2 caption):
         r  = y - A x
         x' = argmin_t ||t - (x + 2 mu A^T r)||^2 + 2 mu lam TV(t).
@@ -514,13 +514,13 @@ def selected_iteration(blocks, row_off, col_off, y, x, r, Z, mu: float, lam: flo
     with such subsets):
       * every pair keeps the last product z^j_{I_i} it computed, in Z[j]
         (a full-length ray vector per column block);
-      * lines 3-4 run for the selected pairs: g^i_{J_j} from the kept
+      * both block products run for the selected pairs: g^i_{J_j} from the kept
         residual r_{I_i}, and z^j_{I_i} from the current x_{J_j} (stored in Z);
-      * line 6 refreshes r_{I_i} for i in I from y and the kept products of
+      * the residual update refreshes r_{I_i} for i in I from y and the kept products of
         all column blocks, ascending j; other rows keep their residual;
-      * line 7 sums g^i over i in I only (no rescaling); line 8 moves the
+      * the gradient sum sums g^i over i in I only (no rescaling); the gradient step moves the
         selected column blocks; the other blocks of x stay as they are;
-      * line 9 runs on the whole image with theta = mu * lam, as written.
+      * the TV prox step runs on the whole image with theta = mu * lam, as written.
     With every bit set this is bsgd_epoch_blocked.  Returns (x, r, Z) as new
     arrays.
     """
@@ -529,14 +529,14 @@ def selected_iteration(blocks, row_off, col_off, y, x, r, Z, mu: float, lam: flo
     Z = Z.copy()
     r_new = r.copy()
     g = np.zeros_like(x)
-    for j in J:                                   # lines 3 + 7 over i in I
+    for j in J:                                   # backprojection and gradient sum over i in I
         c0, c1 = int(col_off[j]), int(col_off[j + 1])
         acc = np.zeros(c1 - c0)
         for i in I:
             r0, r1 = int(row_off[i]), int(row_off[i + 1])
             acc = acc + block_backproject(blocks, row_off, col_off, i, j, r[r0:r1])
         g[c0:c1] = acc
-    for i in I:                                   # line 4, then line 6 for I_i
+    for i in I:                                   # the block forward projection, then the residual update for I_i
         r0, r1 = int(row_off[i]), int(row_off[i + 1])
         for j in J:
             c0, c1 = int(col_off[j]), int(col_off[j + 1])
@@ -545,7 +545,7 @@ def selected_iteration(blocks, row_off, col_off, y, x, r, Z, mu: float, lam: flo
         for j in range(N):
             acc = acc + Z[j, r0:r1]
         r_new[r0:r1] = y[r0:r1] - acc
-    xhat = x + mu * g                             # line 8 (zero outside J)
+    xhat = x + mu * g                             # the gradient step (zero outside J)
     return prox(xhat, mu * lam, prox_iters, shape), r_new, Z
 
 

@@ -1,10 +1,10 @@
-// Single-pass epoch products (Algorithm 1 lines 3-8, with the delay of Eq. 3).
+// Single-pass epoch products (the block products, block sums and gradient step of Algorithm 1, with the delay of Eq. 3).
 //
-// Line 3 of an epoch uses the residual r_k of the previous epoch and line 4
+// The block backprojection of an epoch uses the residual r_k of the previous epoch and the block forward projection
 // the current iterate x_k.  Both are known when the epoch starts, so one
 // pass over the stored entries a = A[rho, p] can produce both sums:
-//     z[rho] += a * x_k[p]      (line 4; summed over the column blocks: line 6)
-//     g[p]   += a * r_k[rho]    (line 3; summed over the row blocks:    line 7)
+//     z[rho] += a * x_k[p]      (the block forward projection; summed over the column blocks: the residual update)
+//     g[p]   += a * r_k[rho]    (the block backprojection; summed over the row blocks:    the gradient sum)
 // which reads the matrix once per epoch instead of once as A and once as A^T.
 //
 // Tile-sliced store.  Pixels are grouped into 64 x 64 tiles (8 x 8 of the

@@ -1,9 +1,9 @@
-// Sparse products over the block store (Algorithm 1 lines 3-8).
+// Sparse products over the block store (the block products, block sums and gradient step of Algorithm 1).
 //
 // A row of the store (a ray of A, or a pixel of A^T) lists the row's entries
 // of all its blocks back to back, so one pass over the row computes the sum
-// over blocks of the block products: sum_j z^j for a ray (lines 4 and 6) and
-// sum_i g^i for a pixel (lines 3 and 7).  A group of LPR lanes of one
+// over blocks of the block products: sum_j z^j for a ray (forward projection and residual) and
+// sum_i g^i for a pixel (backprojection and gradient sum).  A group of LPR lanes of one
 // wavefront walks a row with 16-byte loads of column indices and values
 // (rows are padded to a multiple of 8 entries, so loads are aligned), gathers
 // the vector entries (x or r, in the internal tiled orders, L2-resident), and
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(256) void k_bm_copy(const int64_t* __restrict__ ptr
   }
 }
 
-// Lines 4 and 6 for the drawn pairs.  A ray of a drawn row block computes
+// Forward projection and residual for the drawn pairs.  A ray of a drawn row block computes
 // z^j (its segment j) for every drawn column block j and keeps it in
 // Z[j * nrows + ray]; its residual becomes y - sum_j Z[j] over all column
 // blocks, ascending j (kept products for the others).  Other rays copy
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(256) void k_sel_forward(
   if (lane == 0) r_out[row] = y[row] - tot;
 }
 
-// Lines 3, 7 and 8 for the drawn pairs.  A pixel of a drawn column block
+// Backprojection, gradient sum and step for the drawn pairs.  A pixel of a drawn column block
 // sums its segments i (rows of A^T restricted to I_i) over the drawn row
 // blocks: out = xadd + scale * sum; other pixels copy xadd.
 template <typename VT, int LPR>

@@ -1,4 +1,4 @@
-// Staged form of the fused products (Algorithm 1 lines 3-8 over the whole
+// Staged form of the fused products (the block products, block sums and gradient step of Algorithm 1 over the whole
 // block store): the same sums as the row kernels, with every gather served
 // from LDS.
 //

@@ -1,10 +1,10 @@
 // Step size (Theorem 1) and whole epochs of Algorithm 1.
 //
-// Epoch schedule.  Line 3 uses the residual r_k of the previous epoch and
-// line 4 the current iterate x_k, so within one epoch
-//     S2: x^ = x_k + mu * 2 A^T r_k     (lines 3, 7, 8; one fused pass over A^T)
-//     S1: r_{k+1} = y - A x_k           (lines 4, 6;    one fused pass over A)
-//     S5: x_{k+1} = FGP(x^)             (line 9)
+// Epoch schedule.  The block backprojection uses the residual r_k of the previous epoch and
+// the block forward projection the current iterate x_k, so within one epoch
+//     S2: x^ = x_k + mu * 2 A^T r_k     (backprojection, gradient sum and step; one fused pass over A^T)
+//     S1: r_{k+1} = y - A x_k           (forward projection, residual;    one fused pass over A)
+//     S5: x_{k+1} = FGP(x^)             (the TV prox step)
 // S1 depends on nothing produced in the epoch, so it runs on the state's
 // second stream while S2 and then the prox run on the caller's stream; the
 // prox (many short launches) hides under the forward pass.  x and r are
@@ -386,6 +386,8 @@ extern "C" bsgd_status bsgd_state_workspace_size(const bsgd_plan* plan, int nrhs
                "unknown state flags 0x%x", flags);
   BSGD_REQUIRE(!(flags & BSGD_STATE_VOLUME) || (nrhs > 1 && plan->D == 1),
                "a volume state needs nrhs > 1 slices and a 2-D plan");
+  // the batch prox is the 2-D one, image by image
+  BSGD_REQUIRE(nrhs == 1 || plan->D == 1, "states with several RHS need a 2-D plan (D = 1)");
   BSGD_REQUIRE(!(flags & BSGD_STATE_BLOCK_SELECT) ||
                    (nrhs == 1 && plan->M <= kMaxSelBlocks && plan->N <= kMaxSelBlocks),
                "block selection needs nrhs = 1 and at most %d row and column blocks",
@@ -600,9 +602,9 @@ extern "C" bsgd_status bsgd_state_load(bsgd_state* st, const float* x, const flo
   return BSGD_OK;
 }
 
-// Lines 4 + 6 (out = y - A x) and lines 3 + 7 + 8 (out = xadd + scale A^T r)
+// Forward projection and residual (out = y - A x) and backprojection, gradient sum and step (out = xadd + scale A^T r)
 // over the block store, in the state's launch form (staged, row kernel, or
-// the several-RHS product), and line 9 into `out`.
+// the several-RHS product), and the TV prox step into `out`.
 static hipError_t forward_residual(const bsgd_state* st, const float* x, float* out,
                                    hipStream_t s) {
   const bsgd_plan* p = st->plan;
@@ -667,7 +669,7 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
     float* step_out = theta == 0.f ? st->x[n] : st->xhat;
     if (st->method == BSGD_METHOD_ISTA) {
       // r' = y - A x, then x^ = x + 2 mu A^T r' (current gradient), then
-      // line 9; in order on `stream`.  With a single-pass store the two
+      // the TV prox step; in order on `stream`.  With a single-pass store the two
       // products are two passes over it (A x only, then A^T r' only: the
       // second needs the first's residual), each with its half of the reduce.
       if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
@@ -733,9 +735,9 @@ extern "C" bsgd_status bsgd_run_epochs(bsgd_state* st, float mu, float lam, int 
       continue;
     }
     if (st->fz) {
-      // single pass over the tile-sliced store (lines 3-4 together), then the
-      // reduce (lines 6-8), then the prox (line 9) on `stream`.  The ray half
-      // of the reduce (line 6: the next residual and its max |r|) is needed
+      // single pass over the tile-sliced store (both block products together), then the
+      // reduce (block sums and gradient step), then the prox (the TV prox step) on `stream`.  The ray half
+      // of the reduce (the residual update: the next residual and its max |r|) is needed
       // only by the next pass, so with overlap modes 0 and 1 it runs on the
       // state's second stream, concurrently with the pixel half and the prox
       // (starting it after the pixel half, beside the prox only, measured
@@ -932,7 +934,7 @@ extern "C" bsgd_status bsgd_run_selected(bsgd_state* st, float mu, float lam, in
     const int c = st->cur, n = 1 - c;
     float* step_out = theta == 0.f ? st->x[n] : st->xhat;
     hipEvent_t* tv = next_timers(st);
-    // lines 4 + 6 with the current x; lines 3, 7, 8 with the kept residual
+    // forward projection and residual with the current x; backprojection, gradient sum and step with the kept residual
     if (tv) BSGD_HIP(hipEventRecord(tv[0], stream));
     BSGD_HIP(launch_sel_forward(p->fwd, st->bmf, st->vt, st->blk_r, rows_sel[t], cols_sel[t],
                                 st->x[c], st->y, st->r[c], st->r[n], st->zt, stream));

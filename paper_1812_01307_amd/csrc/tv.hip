@@ -1,7 +1,7 @@
-// TV proximal step (Algorithm 1 line 9) by fast gradient projection on the
+// TV proximal step of Algorithm 1 by fast gradient projection on the
 // dual, and the TV value of Eq. 2.
 //
-// The prox argmin_t 1/2 ||t - b||^2 + theta TV(t) (line 9 with theta = mu lam)
+// The prox argmin_t 1/2 ||t - b||^2 + theta TV(t) (the TV prox step with theta = mu lam)
 // is solved on the dual variable p (one 2-vector per pixel, in the unit
 // disk).  With D the backward-difference operator of Eq. 2 (zero where a
 // difference would leave the image) and D^T its adjoint, iteration k is

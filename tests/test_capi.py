@@ -76,3 +76,21 @@ def test_product_path_has_no_cpu_fallback():
             text = open(os.path.join(pkg, f)).read()
             assert "import oracle" not in text and "from oracle" not in text, f
             assert "import synth" not in text and "from synth" not in text, f
+
+
+def test_counter_hash_ignores_comments_only():
+    """The recorded HBM counters stay attached to a kernel while only its comments
+    change, and drop as soon as the code does."""
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    src = "int f(int a) {\n  // sum\n  return a + 1; /* one */\n}\n"
+    reworded = "// header\nint f(int a) {\n\n  // the sum\n  return a + 1; /* plus one\n  */\n}\n"
+    changed = "int f(int a) {\n  // sum\n  return a + 2; /* one */\n}\n"
+    assert bench._code_text(src) == bench._code_text(reworded)
+    assert bench._code_text(src) != bench._code_text(changed)
+    # every path's hash reads its sources
+    for path in ("fused", "selected"):
+        assert len(bench._kernel_source_hash(path)) == 64

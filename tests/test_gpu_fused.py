@@ -672,6 +672,10 @@ def test_three_dimensional_plan_matches_oracle(kind, f16):
     F_full, F_bare = _fused(full), _fused(bare)
     assert bsgd.bsgd_fused_shape(F_full) == bsgd.bsgd_fused_shape(F_bare)
     assert bsgd.bsgd_fused_shape(F_full)[0] == D * ((H + 63) // 64) * 2  # tiles
+    # several RHS take the 2-D prox image by image: refused for a volume plan
+    with pytest.raises(bsgd.BsgdError) as e:
+        bsgd.bsgd_state_create(full, 4)
+    assert e.value.status == bsgd.BSGD_ERR_INVALID
     x = f32(rng.random(ncols))
     r = f32(rng.standard_normal(nrows))
     bound_f = PRODUCT_REL * (Aabs @ np.abs(x)) + 1e-30

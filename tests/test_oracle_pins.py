@@ -52,7 +52,7 @@ def _tv_from_matrix(K, x, H, W):
 
 
 # --------------------------------------------------------------------------
-# Products (Alg. 1 lines 3-4)
+# Products (both block products of Alg. 1)
 # --------------------------------------------------------------------------
 
 def test_adjoint_identity_and_dense_products():
@@ -216,7 +216,7 @@ def test_difference_operator_and_adjoint():
 
 
 # --------------------------------------------------------------------------
-# TV prox (Alg. 1 line 9) by FGP
+# TV prox step of Alg. 1 by FGP
 # --------------------------------------------------------------------------
 
 def test_fgp_hand_values():

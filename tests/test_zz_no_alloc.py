@@ -1,7 +1,7 @@
 """The allocation-free prox entry point against the workspace one, through the C ABI.
 
-bsgd_tv_prox_noalloc runs the same kernels as bsgd_tv_prox (Algorithm 1
-line 9, FGP on the dual) with the duals in the library's own device array,
+bsgd_tv_prox_noalloc runs the same kernels as bsgd_tv_prox (the TV prox step of
+Algorithm 1, FGP on the dual) with the duals in the library's own device array,
 so its results must equal bsgd_tv_prox's bitwise; they are also checked
 against the FP64 oracle to the prox bar of the parity tests.  Consecutive
 calls shrink the input, so a kernel that read a dual it had not written in

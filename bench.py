@@ -14,7 +14,7 @@ With --path fused (default) every epoch reads the matrix once (both
 products in one pass); --path rows runs one pass over A and one over A^T.
 The reported value is epochs per second over whole jobs (setup included).
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -244,7 +244,7 @@ def main(argv=None):
     if args.staged is None:
         args.staged = "none" if args.path == "fused" or args.method == "selected" else "bwd"
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} is not supported; this build runs on exactly one GPU "
+        print(f"bench.py: --gpus {args.gpus} is not supported; the library runs on exactly one GPU "
               "(see the design notes for how the path would shard)", file=sys.stderr)
         return 2
 

@@ -46,7 +46,7 @@ typedef enum {
   BSGD_ERR_INVALID = -1,     /* bad argument or inconsistent input data     */
   BSGD_ERR_WORKSPACE = -2,   /* workspace smaller than the size query gave  */
   BSGD_ERR_HIP = -3,         /* a HIP runtime call failed                   */
-  BSGD_ERR_UNSUPPORTED = -4, /* valid request this build does not implement */
+  BSGD_ERR_UNSUPPORTED = -4, /* valid request the library does not implement */
   BSGD_ERR_DIVERGED = -5     /* residual norm is not finite                 */
 } bsgd_status;
 

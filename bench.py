@@ -49,6 +49,13 @@ PMC_TRAFFIC = {
     ("fused", "c2_512", "f16"): {
         "sha256": "b1031d260261612f55747aebdfd13da5c405b84b08459f6671cb4adb02f44269",
         "bytes": 826097760},
+    # profiles/k_fused_c3_1024_counters_and_trace.md
+    ("fused", "c3_1024", "f32"): {
+        "sha256": "b1031d260261612f55747aebdfd13da5c405b84b08459f6671cb4adb02f44269",
+        "bytes": 10604834425},
+    ("fused", "c3_1024", "f16"): {
+        "sha256": "b1031d260261612f55747aebdfd13da5c405b84b08459f6671cb4adb02f44269",
+        "bytes": 6820311354},
     # profiles/k_fused_ista_c2_512_hbm_counters.md (the A x-only pass)
     ("fused", "c2_512", "f32", "ista"): {
         "sha256": "b1031d260261612f55747aebdfd13da5c405b84b08459f6671cb4adb02f44269",
